@@ -1,0 +1,136 @@
+"""Benchmark of the Relax step (Algorithm 2) on one MI355X.
+
+A "step" is one Relax iteration (probes, preconditioner, two PCG solves,
+H_p product, gradient, mirror-descent update) over the configuration-2
+workload: n = 50,000 pool points + 10 labeled, d = 100, c = 10, s = 20
+probes, PCG tol 1e-6, b = 100, synthetic Gaussian-mixture features (10
+clusters, whitened) and softmax probabilities with mean max-prob 0.7.
+
+    python bench.py [--steps K] [--warmup W] [--prec f32|f64] [--literal]
+
+Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Relax iter time + HVP TFLOP/s, FP32 vs bf16x3 at ≤1e-4 rel grad error"
+PEAK = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0}   # TFLOP/s, MI355X dense MFMA
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--literal", action="store_true", help="PCG without the null-space projection")
+    ap.add_argument("--hvp-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, beta0, project):
+    """Time the FP64 oracle on one Relax iteration of the same workload (full size)."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import relax as orc
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    w = np.full(p.n_pool, 1.0 / p.n_pool)
+    t0 = time.perf_counter()
+    orc.relax_iteration(p.X, p.H, p.n_pool, w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, p.tol,
+                        1000, project=project)
+    dt = time.perf_counter() - t0
+    return {"value": 1.0 / dt, "unit": "relax_iter/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one full-size Relax iteration (t=1) of the same workload in FP64 NumPy, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Relax path "
+              "of this build is single-GPU.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, default_beta0
+    from synthdata import make_problem
+
+    p = make_problem(2)
+    project = not args.literal
+    dt = torch.float64 if args.prec == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(p.X, dtype=dt, device=dev)
+    H = torch.as_tensor(p.H, dtype=dt, device=dev)
+    ctx = RelaxContext(X, H, p.n_pool, p.s, args.prec)
+    beta0 = default_beta0(p.n_pool, p.T)
+    max_iter = 1000
+
+    # warmup on a scratch weight vector
+    wtmp = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
+    for t in range(1, args.warmup + 1):
+        ctx.relax_step(wtmp, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, max_iter, project)
+
+    # timed: K Relax iterations from w = 1/n
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, max_iter, project)
+             for t in range(1, args.steps + 1)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = 1e3 * elapsed / args.steps
+    cg = [i["cg_iters"][0] + i["cg_iters"][1] for i in infos]
+
+    # HVP: the dominant operation (about 2 per CG iteration are not needed; one per iteration)
+    B = ctx.probes(p.probe_seed, 1, p.s)
+    out = torch.empty_like(B)
+    for _ in range(3):
+        ctx.hvp(B, shift=p.lam, out=out)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.hvp_reps):
+        ctx.hvp(B, shift=p.lam, out=out)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_hvp = ev0.elapsed_time(ev1) / 1e3 / args.hvp_reps
+    flops = 4.0 * p.N * p.c * p.d * p.s
+    tflops = flops / t_hvp / 1e12
+
+    res = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "relax_iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": "relax cfg2: n=50000+10 labeled, d=100, c=10, s=20, tol=1e-6, b=100",
+                   "pcg": "projected" if project else "literal",
+                   "mean_cg_iters_per_step": float(np.mean(cg)),
+                   "hvp_ms": t_hvp * 1e3, "hvp_tflops": tflops,
+                   "f_hat_last": infos[-1]["f_hat"]},
+        "roofline": {"bound": "mfma", "kernel": "hvp (Lemma 1 product, all its kernels)",
+                     "achieved": tflops, "peak": PEAK[args.prec], "unit": "TFLOP/s",
+                     "frac": tflops / PEAK[args.prec], "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(p, beta0, project)
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,154 @@
+/*
+ * firal.h -- C ABI of the MI355X (gfx950) Relax step of Approx-FIRAL
+ * (Chen, Wen & Biros, "A Scalable Algorithm for Active Learning", SC24).
+ *
+ * The library computes, on one GPU, every step of the fast Relax solve
+ * (Algorithm 2): Rademacher probes, the block-diagonal preconditioner of
+ * Definition 1 / eq. 12, block-Jacobi preconditioned CG with the matrix-free
+ * Hessian product of Lemma 1, the Hutchinson gradient of eq. 11 and the
+ * entropic mirror-descent update.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Pointers marked "device" are HIP device addresses on the context's device;
+ * "host" pointers are ordinary CPU memory.  Every device buffer belongs to
+ * the caller unless stated otherwise; the library never frees caller memory.
+ * `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *
+ * Rows: X is (n_pool + n_lab) x d row-major, pool rows first, then the
+ * labeled rows; H (the class probabilities h_i of eq. 1, one row per point)
+ * is (n_pool + n_lab) x c row-major in the same row order.
+ *
+ * Blocks: s vectors of length d*c are stored as a d x s x c row-major array
+ * B, element (a, j, k) at a*s*c + j*c + k.  It is entry k*d + a of the
+ * paper's j-th vector v_j = vec(V_j) (vec stacks the columns of the d x c
+ * matrix V_j; notation table and Lemma 1).
+ *
+ * Element type: FP64 for FIRAL_F64; FP32 for FIRAL_F32 and FIRAL_BF16X3
+ * (X, H, blocks).  Row weights omega, z, w, gradients and the
+ * preconditioner factors are always FP64.
+ *
+ * Return codes: 0 = success, > 0 = warning, < 0 = error (see FIRAL_E*).
+ * Argument errors are detected before any device work; conditions found on
+ * the device (non-SPD preconditioner block, CG breakdown, no convergence)
+ * are reported through firal_info by the calls that take one.  The
+ * detail of the last failure on the calling thread is firal_last_error().
+ * A context must not be used from two host threads or two streams at once.
+ */
+#ifndef FIRAL_H
+#define FIRAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct firal_ctx_s* firal_ctx;
+
+typedef enum {
+  FIRAL_F64 = 0,     /* FP64 storage, FP64 MFMA */
+  FIRAL_F32 = 1,     /* FP32 storage, FP32 MFMA */
+  FIRAL_BF16X3 = 2   /* FP32 storage, products as three bf16 MFMA passes (hi*hi + hi*lo + lo*hi) */
+} firal_prec;
+
+enum {
+  FIRAL_OK = 0,
+  FIRAL_WARN_NOT_CONVERGED = 1, /* a PCG column did not reach tol within max_iter */
+  FIRAL_EINVAL = -1,            /* bad argument: null pointer, size out of range, s > s_max ... */
+  FIRAL_EHIP = -2,              /* HIP runtime failure or no usable device */
+  FIRAL_ENOMEM = -3,            /* device allocation failed */
+  FIRAL_ENOTSUP = -4,           /* combination not supported */
+  FIRAL_EBREAKDOWN = -5,        /* PCG: p_j^T q_j <= 0 on an active column (operator not SPD) */
+  FIRAL_ENOTSPD = -6            /* a preconditioner block failed its Cholesky factorisation */
+};
+
+/* pcg_solve / relax_step flag: solve in the complement of {1_c (x) u}.
+ * With a full softmax h every H_i annihilates that d-dimensional space, so
+ * Sigma_z has the eigenvalue lambda there and block-Jacobi cannot reach it;
+ * projecting the right-hand sides and the preconditioner (P M^-1 P) removes
+ * it without changing H_p Sigma^-1 V, f_hat or the gradient of eq. 11. */
+#define FIRAL_PCG_PROJECT 1u
+
+typedef struct {
+  int32_t cg_iters[2];  /* iterations of the first / second PCG solve (pcg_solve fills [0]) */
+  int32_t converged;    /* 1 if every column of every solve met tol */
+  int32_t bad_block;    /* -1, or the first class k whose preconditioner block is not SPD */
+  double relres_max;    /* max_j ||r_j|| / ||b_j|| of the recurrence residual at exit */
+  double f_hat;         /* (1/s) sum_j <v_j, H_p Sigma_z^-1 v_j>: Hutchinson estimate of f(z) */
+  double g_absmax;      /* max_i |g_i| of the gradient estimate */
+  double beta;          /* step used: beta0 / g_absmax */
+} firal_info;
+
+/* Create a context for one problem.  X and H (device, element type of prec)
+ * are borrowed: they must stay valid and unchanged while the context lives.
+ * All workspace for blocks of up to s_max probes is allocated here.
+ * Errors: EINVAL (n_pool < 1, n_lab < 0, d < 1, c < 2, s_max < 1, null X/H/out,
+ * prec unknown), EHIP (no device), ENOMEM. */
+int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32_t c,
+                 int32_t s_max, int32_t prec, const void* X, const void* H, void* stream);
+
+/* Release the context's workspace (synchronises the device first).  NULL is a no-op. */
+int firal_destroy(firal_ctx ctx);
+
+/* Matrix-free Hessian product (Lemma 1; aggregated over rows as in the H_p v formula
+ * that follows it):
+ *   out_j = sum_{i < n_rows} omega_i H_i v_j + shift * v_j,   H_i = Gamma_i (x) x_i x_i^T,
+ * for the s blocks of B (eq. 2).  omega: device FP64 [n_rows] or NULL for all ones.
+ * n_rows <= n_pool + n_lab selects rows 0..n_rows-1 (n_pool gives H_p).
+ * B, out: device blocks d x s x c; out must not alias B.  Asynchronous. */
+int firal_hvp(firal_ctx ctx, const double* omega, int64_t n_rows, double shift,
+              const void* B, void* out, int32_t s, void* stream);
+
+/* Block-diagonal preconditioner (Definition 1, eq. 12):
+ *   P_k = shift * I_d + sum_i omega_i h_ik (1 - h_ik) x_i x_i^T,  k = 0..c-1, all rows,
+ * factorised in FP64 as P_k = L_k L_k^T.  L (lower, upper part zero) and Pinv = P_k^-1
+ * are device FP64 arrays c x d x d; either may be NULL.  omega: device FP64
+ * [n_pool + n_lab] or NULL for all ones.  Synchronous; info (host, may be NULL)
+ * gets bad_block.  Returns ENOTSPD when a block fails. */
+int firal_build_precond(firal_ctx ctx, const double* omega, double shift, double* L,
+                        double* Pinv, firal_info* info, void* stream);
+
+/* Block-Jacobi preconditioned CG for (sum_i omega_i H_i + shift I) Xsol_j = B_j, all s
+ * columns in lock-step from x0 = 0 (Algorithm 2, solve lines).  Pinv: device FP64
+ * c x d x d from firal_build_precond.  Column j stops once ||r_j|| <= tol ||b_j||; the
+ * loop ends when all have stopped or after max_iter iterations (tol = 0: exactly
+ * max_iter).  flags: FIRAL_PCG_PROJECT.  Synchronous; returns WARN_NOT_CONVERGED or
+ * EBREAKDOWN; info (host, may be NULL) gets cg_iters[0], converged, relres_max. */
+int firal_pcg_solve(firal_ctx ctx, const double* omega, double shift, const double* Pinv,
+                    const void* B, void* Xsol, int32_t s, double tol, int32_t max_iter,
+                    uint32_t flags, firal_info* info, void* stream);
+
+/* Per-point contraction of eq. 11 for every pool row i:
+ *   g_i = -(1/s) sum_j u_j^T H_i w_j = -(1/s) sum_j (U_j^T x_i)^T Gamma_i (W_j^T x_i)
+ * U, W: device blocks d x s x c; g: device FP64 [n_pool].  Asynchronous. */
+int firal_grad_z(firal_ctx ctx, const void* U, const void* W, int32_t s, double* g,
+                 void* stream);
+
+/* Rademacher probes of iteration t >= 1 (Algorithm 2, probe line): entry (a, j, k) is -1
+ * when the top bit of SplitMix64 output number ((t-1)*s + j)*(d*c) + k*d + a of the
+ * stream seeded with `seed` is set, else +1.  V: device block d x s x c.  Asynchronous. */
+int firal_probes(firal_ctx ctx, uint64_t seed, int32_t t, int32_t s, void* V, void* stream);
+
+/* One iteration t >= 1 of the fast Relax solve (Algorithm 2) on the simplex weights w:
+ *   z = b w; omega = [z; 1]; V = probes(seed, t); P_k = blocks of Sigma_z + lambda I;
+ *   W1 = Sigma^-1 V; Y = H_p W1; W2 = Sigma^-1 Y; g = grad_z(V, W2);
+ *   beta = beta0 / max|g|;  w_i <- w_i exp(-beta g_i) / sum_l w_l exp(-beta g_l).
+ * w: device FP64 [n_pool], in/out (positive, summing to 1).  g_out: device FP64 [n_pool]
+ * or NULL.  On a device-side failure (ENOTSPD, EBREAKDOWN) w is left unchanged.
+ * Synchronous; info (host, may be NULL) gets every field. */
+int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double beta0,
+                     uint64_t seed, int32_t t, int32_t s, double tol, int32_t max_iter,
+                     uint32_t flags, double* g_out, firal_info* info, void* stream);
+
+/* Static description of a return code. */
+const char* firal_strerror(int code);
+
+/* Detail of the last failing call on this host thread ("" if none). */
+const char* firal_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIRAL_H */

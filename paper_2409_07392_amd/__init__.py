@@ -1,0 +1,167 @@
+"""MI355X (gfx950) Relax step of Approx-FIRAL (Chen, Wen & Biros, SC24).
+
+Every step of the path runs in the hand-written HIP kernels of libfiral.so
+(see include/firal.h); this module only marshals arguments: torch tensors
+supply device memory and the current stream.  There is no CPU fallback:
+constructing a context without the built library or without a GPU raises.
+"""
+from __future__ import annotations
+
+import math
+
+import torch
+
+from . import _lib
+from ._lib import (BF16X3, F32, F64, PCG_PROJECT, FiralError, Info, WARN_NOT_CONVERGED, check,
+                   load)
+
+__all__ = ["RelaxContext", "FiralError", "default_beta0", "F64", "F32", "BF16X3", "load"]
+
+_DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32}
+
+
+def default_beta0(n: int, T: int) -> float:
+    """sqrt(2 ln n / T), the standard entropic mirror-descent step for T iterations."""
+    return math.sqrt(2.0 * math.log(n) / max(T, 1))
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+class RelaxContext:
+    """One Relax problem on the current GPU.
+
+    X: (n_pool + n_lab, d) and H: (n_pool + n_lab, c) CUDA tensors, pool rows
+    first, float64 for prec 'f64' and float32 otherwise.  The context borrows
+    them (keeps references) and owns all workspace for up to s_max probes.
+    """
+
+    def __init__(self, X: torch.Tensor, H: torch.Tensor, n_pool: int, s_max: int,
+                 prec: str = "f32"):
+        self.lib = load()
+        self.prec = _lib.PREC[prec]
+        self.dtype = _DTYPE[self.prec]
+        if not (X.is_cuda and H.is_cuda):
+            raise ValueError("X and H must be CUDA tensors")
+        if X.dtype != self.dtype or H.dtype != self.dtype:
+            raise ValueError(f"X and H must be {self.dtype} for prec={prec}")
+        if X.dim() != 2 or H.dim() != 2 or X.shape[0] != H.shape[0]:
+            raise ValueError("X must be (N, d) and H (N, c) with the same N")
+        self.X = X.contiguous()
+        self.H = H.contiguous()
+        self.N, self.d = self.X.shape
+        self.c = self.H.shape[1]
+        self.n_pool = int(n_pool)
+        self.n_lab = self.N - self.n_pool
+        self.s_max = int(s_max)
+        self._ctx = _lib.ctypes.c_void_p()
+        check(self.lib.firal_create(_lib.ctypes.byref(self._ctx), self.n_pool, self.n_lab,
+                                    self.d, self.c, self.s_max, self.prec, _ptr(self.X),
+                                    _ptr(self.H), _stream()))
+
+    # ------------------------------------------------------------ helpers
+    def block(self, s: int) -> torch.Tensor:
+        return torch.empty((self.d, s, self.c), dtype=self.dtype, device=self.X.device)
+
+    def _blk(self, B: torch.Tensor) -> torch.Tensor:
+        if B.dtype != self.dtype or not B.is_cuda or B.dim() != 3 or \
+                B.shape[0] != self.d or B.shape[2] != self.c:
+            raise ValueError(f"block must be a CUDA {self.dtype} tensor of shape (d, s, c)")
+        return B.contiguous()
+
+    @staticmethod
+    def _f64(t, n):
+        if t is None:
+            return None
+        if t.dtype != torch.float64 or not t.is_cuda or t.numel() != n:
+            raise ValueError(f"expected a CUDA float64 tensor with {n} elements")
+        return t.contiguous()
+
+    # -------------------------------------------------------------- calls
+    def hvp(self, B, omega=None, shift=0.0, n_rows=None, out=None):
+        B = self._blk(B)
+        n_rows = self.N if n_rows is None else int(n_rows)
+        omega = self._f64(omega, n_rows)
+        out = torch.empty_like(B) if out is None else out
+        check(self.lib.firal_hvp(self._ctx, _ptr(omega), n_rows, float(shift), _ptr(B),
+                                 _ptr(out), B.shape[1], _stream()))
+        return out
+
+    def build_precond(self, omega=None, shift=0.0, want_L=True):
+        omega = self._f64(omega, self.N)
+        shape = (self.c, self.d, self.d)
+        L = torch.empty(shape, dtype=torch.float64, device=self.X.device) if want_L else None
+        Pinv = torch.empty(shape, dtype=torch.float64, device=self.X.device)
+        info = Info()
+        rc = self.lib.firal_build_precond(self._ctx, _ptr(omega), float(shift), _ptr(L),
+                                          _ptr(Pinv), _lib.ctypes.byref(info), _stream())
+        check(rc)
+        return L, Pinv, info.as_dict()
+
+    def pcg_solve(self, B, Pinv, omega=None, shift=0.0, tol=1e-6, max_iter=1000, project=False):
+        B = self._blk(B)
+        omega = self._f64(omega, self.N)
+        Xsol = torch.empty_like(B)
+        info = Info()
+        rc = self.lib.firal_pcg_solve(self._ctx, _ptr(omega), float(shift), _ptr(Pinv), _ptr(B),
+                                      _ptr(Xsol), B.shape[1], float(tol), int(max_iter),
+                                      PCG_PROJECT if project else 0, _lib.ctypes.byref(info),
+                                      _stream())
+        check(rc)
+        d = info.as_dict()
+        d["rc"] = rc
+        return Xsol, d
+
+    def grad_z(self, U, W, g=None):
+        U = self._blk(U)
+        W = self._blk(W)
+        g = torch.empty(self.n_pool, dtype=torch.float64, device=self.X.device) if g is None else g
+        check(self.lib.firal_grad_z(self._ctx, _ptr(U), _ptr(W), U.shape[1], _ptr(g), _stream()))
+        return g
+
+    def probes(self, seed: int, t: int, s: int):
+        V = self.block(s)
+        check(self.lib.firal_probes(self._ctx, int(seed) & (2**64 - 1), int(t), int(s), _ptr(V),
+                                    _stream()))
+        return V
+
+    def relax_step(self, w, b, lam, beta0, seed, t, s=None, tol=1e-6, max_iter=1000,
+                   project=False, g_out=None):
+        """One Algorithm 2 iteration on w (in place).  Returns the info dict (with 'rc')."""
+        s = self.s_max if s is None else int(s)
+        w = self._f64(w, self.n_pool)
+        g_out = self._f64(g_out, self.n_pool)
+        info = Info()
+        rc = self.lib.firal_relax_step(self._ctx, _ptr(w), float(b), float(lam), float(beta0),
+                                       int(seed) & (2**64 - 1), int(t), s, float(tol),
+                                       int(max_iter), PCG_PROJECT if project else 0, _ptr(g_out),
+                                       _lib.ctypes.byref(info), _stream())
+        check(rc)
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
+
+    def relax(self, b, lam, beta0, seed, T, s=None, tol=1e-6, max_iter=1000, project=False,
+              w0=None):
+        """T iterations from w = 1/n; returns (z = b w, list of per-iteration info)."""
+        w = (torch.full((self.n_pool,), 1.0 / self.n_pool, dtype=torch.float64,
+                        device=self.X.device) if w0 is None else w0.clone())
+        hist = [self.relax_step(w, b, lam, beta0, seed, t, s, tol, max_iter, project)
+                for t in range(1, T + 1)]
+        return b * w, hist
+
+    def close(self):
+        if getattr(self, "_ctx", None) is not None and self._ctx.value:
+            self.lib.firal_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,86 @@
+"""ctypes declarations of the C ABI in include/firal.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfiral.so")
+
+F64, F32, BF16X3 = 0, 1, 2
+PREC = {"f64": F64, "f32": F32, "bf16x3": BF16X3}
+
+OK = 0
+WARN_NOT_CONVERGED = 1
+EINVAL, EHIP, ENOMEM, ENOTSUP, EBREAKDOWN, ENOTSPD = -1, -2, -3, -4, -5, -6
+PCG_PROJECT = 1
+
+# every symbol include/firal.h declares
+EXPORTS = ("firal_create", "firal_destroy", "firal_hvp", "firal_build_precond",
+           "firal_pcg_solve", "firal_grad_z", "firal_probes", "firal_relax_step",
+           "firal_strerror", "firal_last_error")
+
+
+class Info(ctypes.Structure):
+    """firal_info."""
+    _fields_ = [("cg_iters", ctypes.c_int32 * 2), ("converged", ctypes.c_int32),
+                ("bad_block", ctypes.c_int32), ("relres_max", ctypes.c_double),
+                ("f_hat", ctypes.c_double), ("g_absmax", ctypes.c_double),
+                ("beta", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return dict(cg_iters=(int(self.cg_iters[0]), int(self.cg_iters[1])),
+                    converged=bool(self.converged), bad_block=int(self.bad_block),
+                    relres_max=float(self.relres_max), f_hat=float(self.f_hat),
+                    g_absmax=float(self.g_absmax), beta=float(self.beta))
+
+
+class FiralError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(what)
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libfiral.so (built in-tree); raises ImportError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2409_07392_amd.build` (needs hipcc)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64, dbl = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double)
+    pinfo = ctypes.POINTER(Info)
+    sig = {
+        "firal_create": [ctypes.POINTER(vp), i64, i64, i32, i32, i32, i32, vp, vp, vp],
+        "firal_destroy": [vp],
+        "firal_hvp": [vp, vp, i64, dbl, vp, vp, i32, vp],
+        "firal_build_precond": [vp, vp, dbl, vp, vp, pinfo, vp],
+        "firal_pcg_solve": [vp, vp, dbl, vp, vp, vp, i32, dbl, i32, u32, pinfo, vp],
+        "firal_grad_z": [vp, vp, vp, i32, vp, vp],
+        "firal_probes": [vp, u64, i32, i32, vp, vp],
+        "firal_relax_step": [vp, vp, dbl, dbl, dbl, u64, i32, i32, dbl, i32, u32, vp, pinfo, vp],
+        "firal_strerror": [ctypes.c_int],
+        "firal_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.firal_strerror.restype = ctypes.c_char_p
+    lib.firal_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> int:
+    """Raise FiralError for negative return codes; pass warnings through."""
+    if rc < 0:
+        lib = load()
+        raise FiralError(rc, f"{lib.firal_strerror(rc).decode()} ({rc}): "
+                             f"{lib.firal_last_error().decode()}")
+    return rc

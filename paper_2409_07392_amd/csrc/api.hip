@@ -1,0 +1,339 @@
+// Exported C ABI: argument validation, context and workspace management, and
+// the synchronous calls that report device-side status through firal_info.
+#include <algorithm>
+#include <climits>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace firal {
+
+static thread_local char g_last_error[512] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+  va_end(ap);
+}
+
+int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, uint64_t seed,
+                      int t, int s, double tol, int max_iter, uint32_t flags, double* g_out,
+                      hipStream_t st);
+
+#define FIRAL_REQ(cond, ...)                                                    \
+  do {                                                                          \
+    if (!(cond)) {                                                              \
+      ::firal::set_error(__VA_ARGS__);                                          \
+      return FIRAL_EINVAL;                                                      \
+    }                                                                           \
+  } while (0)
+
+static void free_ctx(Ctx* x) {
+  void* bufs[] = {x->G, x->part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->V, x->W1, x->Y,
+                  x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
+                  x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
+                  x->redpart, x->status};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (x->status_host) (void)hipHostFree(x->status_host);
+  delete x;
+}
+
+static int dmalloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    return FIRAL_ENOMEM;
+  }
+  return FIRAL_OK;
+}
+
+static int check_common(firal_ctx ctx, int32_t s) {
+  FIRAL_REQ(ctx != nullptr, "null context");
+  FIRAL_REQ(s >= 1 && s <= C(ctx)->s_max, "s = %d outside [1, s_max = %d]", s, C(ctx)->s_max);
+  return FIRAL_OK;
+}
+
+static int finish_sync(Ctx* x, hipStream_t st) {
+  FIRAL_HIP(hipMemcpyAsync(x->status_host, x->status, sizeof(Status), hipMemcpyDeviceToHost, st));
+  FIRAL_HIP(hipStreamSynchronize(st));
+  return FIRAL_OK;
+}
+
+}  // namespace firal
+
+using namespace firal;
+
+extern "C" {
+
+const char* firal_strerror(int code) {
+  switch (code) {
+    case FIRAL_OK: return "success";
+    case FIRAL_WARN_NOT_CONVERGED: return "PCG did not converge within max_iter";
+    case FIRAL_EINVAL: return "invalid argument";
+    case FIRAL_EHIP: return "HIP runtime failure or no usable device";
+    case FIRAL_ENOMEM: return "device allocation failed";
+    case FIRAL_ENOTSUP: return "not supported";
+    case FIRAL_EBREAKDOWN: return "PCG breakdown: operator not positive definite on a column";
+    case FIRAL_ENOTSPD: return "preconditioner block not positive definite";
+    default: return "unknown return code";
+  }
+}
+
+const char* firal_last_error(void) { return g_last_error; }
+
+int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32_t c,
+                 int32_t s_max, int32_t prec, const void* X, const void* H, void* stream) {
+  FIRAL_REQ(out != nullptr, "null output pointer");
+  *out = nullptr;
+  FIRAL_REQ(n_pool >= 1, "n_pool = %lld < 1", (long long)n_pool);
+  FIRAL_REQ(n_lab >= 0, "n_lab = %lld < 0", (long long)n_lab);
+  FIRAL_REQ(d >= 1 && d <= 4096, "d = %d outside [1, 4096]", d);
+  FIRAL_REQ(c >= 2 && c <= 65536, "c = %d outside [2, 65536]", c);
+  FIRAL_REQ(s_max >= 1 && s_max <= 4096, "s_max = %d outside [1, 4096]", s_max);
+  FIRAL_REQ(prec == FIRAL_F64 || prec == FIRAL_F32 || prec == FIRAL_BF16X3, "unknown precision %d",
+            prec);
+  FIRAL_REQ(X != nullptr && H != nullptr, "null X or H");
+  if (prec == FIRAL_BF16X3) {
+    set_error("BF16X3 contexts are not built yet");
+    return FIRAL_ENOTSUP;
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    set_error("no HIP device available (%s)", e != hipSuccess ? hipGetErrorString(e) : "0 devices");
+    return FIRAL_EHIP;
+  }
+  Ctx* x = new (std::nothrow) Ctx();
+  if (!x) {
+    set_error("host allocation failed");
+    return FIRAL_ENOMEM;
+  }
+  std::memset(x, 0, sizeof(Ctx));
+  x->n_pool = n_pool;
+  x->n_lab = n_lab;
+  x->N = n_pool + n_lab;
+  x->d = d;
+  x->c = c;
+  x->s_max = s_max;
+  x->prec = prec;
+  x->esize = prec == FIRAL_F64 ? 8 : 4;
+  x->X = X;
+  x->H = H;
+  if (hipGetDevice(&x->device) != hipSuccess) {
+    delete x;
+    set_error("hipGetDevice failed");
+    return FIRAL_EHIP;
+  }
+  const int64_t blk = (int64_t)d * s_max * c;        // elements per block
+  const int64_t sc = (int64_t)s_max * c;
+  // row-chunked intermediates: two (rows x s*c) buffers within ~2 GiB
+  const int64_t budget = (int64_t)2 << 30;
+  int64_t rows = budget / (2 * sc * (int64_t)x->esize);
+  rows = std::max<int64_t>(64, std::min<int64_t>(rows, x->N));
+  rows = std::min<int64_t>(rows, (int64_t)65535 * 64);   // grid.y of the row-tiled GEMM
+  if (const char* env = getenv("FIRAL_CHUNK_ROWS")) {   // smaller chunks, for tests of the chunked path
+    const long long v = atoll(env);
+    if (v >= 1 && v < rows) rows = v;
+  }
+  x->chunk_rows = rows;
+  const int64_t tiles = cdiv(d, 64) * cdiv(sc, 64);
+  x->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, tiles), 64));
+  const int nb = (int)cdiv(d, 16);
+  const int npairs = nb * (nb + 1) / 2;
+  const int64_t syrk_wgs = (int64_t)npairs * cdiv(c, 16);
+  x->syrk_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, syrk_wgs), 64));
+  x->col_parts = (int)std::max<int64_t>(1, std::min<int64_t>(d, cdiv(256, s_max)));
+  x->red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n_pool, 256), 1024));
+
+  const size_t es = x->esize;
+  int rc = FIRAL_OK;
+#define ALLOC(ptr, bytes)                                          \
+  if (rc == FIRAL_OK) rc = dmalloc((void**)&(ptr), (size_t)(bytes))
+  ALLOC(x->G, 2 * rows * sc * es);
+  ALLOC(x->part, (int64_t)x->max_splits * blk * es);
+  ALLOC(x->P, (int64_t)c * d * d * 8);
+  ALLOC(x->Pinv, (int64_t)c * d * d * 8);
+  ALLOC(x->syrk_part, (int64_t)x->syrk_splits * c * npairs * 256 * es);
+  ALLOC(x->V, blk * es);
+  ALLOC(x->W1, blk * es);
+  ALLOC(x->Y, blk * es);
+  ALLOC(x->W2, blk * es);
+  ALLOC(x->cx, blk * es);
+  ALLOC(x->cr, blk * es);
+  ALLOC(x->cz, blk * es);
+  ALLOC(x->cp, blk * es);
+  ALLOC(x->cq, blk * es);
+  ALLOC(x->mean, (int64_t)d * s_max * 8);
+  ALLOC(x->omega, x->N * 8);
+  ALLOC(x->gbuf, n_pool * 8);
+  ALLOC(x->ebuf, n_pool * 8);
+  ALLOC(x->colpart, (int64_t)4 * s_max * x->col_parts * 8);
+  ALLOC(x->rho, s_max * 8);
+  ALLOC(x->bnorm, s_max * 8);
+  ALLOC(x->alpha, s_max * 8);
+  ALLOC(x->beta, s_max * 8);
+  ALLOC(x->relres, s_max * 8);
+  ALLOC(x->done, s_max * 4);
+  ALLOC(x->redpart, (3 * (int64_t)x->red_blocks + 1) * 8);
+  ALLOC(x->status, sizeof(Status));
+#undef ALLOC
+  if (rc == FIRAL_OK) {
+    hipError_t he = hipHostMalloc((void**)&x->status_host, sizeof(Status), hipHostMallocDefault);
+    if (he != hipSuccess) {
+      set_error("hipHostMalloc failed: %s", hipGetErrorString(he));
+      rc = FIRAL_ENOMEM;
+    }
+  }
+  if (rc == FIRAL_OK) {
+    hipStream_t st = (hipStream_t)stream;
+    if (hipMemsetAsync(x->status, 0, sizeof(Status), st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("status initialisation failed");
+      rc = FIRAL_EHIP;
+    }
+  }
+  if (rc != FIRAL_OK) {
+    free_ctx(x);
+    return rc;
+  }
+  *out = reinterpret_cast<firal_ctx>(x);
+  return FIRAL_OK;
+}
+
+int firal_destroy(firal_ctx ctx) {
+  if (!ctx) return FIRAL_OK;
+  (void)hipDeviceSynchronize();
+  free_ctx(C(ctx));
+  return FIRAL_OK;
+}
+
+int firal_hvp(firal_ctx ctx, const double* omega, int64_t n_rows, double shift, const void* B,
+              void* out, int32_t s, void* stream) {
+  FIRAL_CHECK(check_common(ctx, s));
+  Ctx* x = C(ctx);
+  FIRAL_REQ(B != nullptr && out != nullptr, "null B or out");
+  FIRAL_REQ(B != out, "out must not alias B");
+  FIRAL_REQ(n_rows >= 0 && n_rows <= x->N, "n_rows = %lld outside [0, %lld]", (long long)n_rows,
+            (long long)x->N);
+  return hvp_launch(x, omega, n_rows, shift, B, out, s, nullptr, (hipStream_t)stream);
+}
+
+int firal_build_precond(firal_ctx ctx, const double* omega, double shift, double* L, double* Pinv,
+                        firal_info* info, void* stream) {
+  FIRAL_REQ(ctx != nullptr, "null context");
+  Ctx* x = C(ctx);
+  hipStream_t st = (hipStream_t)stream;
+  FIRAL_CHECK(precond_launch(x, omega, shift, st));
+  const size_t bytes = (size_t)x->c * x->d * x->d * 8;
+  if (L) FIRAL_HIP(hipMemcpyAsync(L, x->P, bytes, hipMemcpyDeviceToDevice, st));
+  if (Pinv) FIRAL_HIP(hipMemcpyAsync(Pinv, x->Pinv, bytes, hipMemcpyDeviceToDevice, st));
+  FIRAL_CHECK(finish_sync(x, st));
+  const int bad = x->status_host->bad_block == INT_MAX ? -1 : x->status_host->bad_block;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->bad_block = bad;
+  }
+  if (bad >= 0) {
+    set_error("preconditioner block %d is not positive definite", bad);
+    return FIRAL_ENOTSPD;
+  }
+  return FIRAL_OK;
+}
+
+__global__ void k_pcg_reset(Status* st) {
+  st->converged = 1;
+  st->breakdown = 0;
+  st->bad_block = INT_MAX;
+}
+
+int firal_pcg_solve(firal_ctx ctx, const double* omega, double shift, const double* Pinv,
+                    const void* B, void* Xsol, int32_t s, double tol, int32_t max_iter,
+                    uint32_t flags, firal_info* info, void* stream) {
+  FIRAL_CHECK(check_common(ctx, s));
+  Ctx* x = C(ctx);
+  FIRAL_REQ(Pinv != nullptr && B != nullptr && Xsol != nullptr, "null Pinv, B or Xsol");
+  FIRAL_REQ(tol >= 0.0, "tol < 0");
+  FIRAL_REQ(max_iter >= 0, "max_iter < 0");
+  FIRAL_REQ((flags & ~FIRAL_PCG_PROJECT) == 0, "unknown flags 0x%x", flags);
+  hipStream_t st = (hipStream_t)stream;
+  k_pcg_reset<<<1, 1, 0, st>>>(x->status);
+  FIRAL_LAUNCHED();
+  FIRAL_CHECK(pcg_launch(x, omega, shift, Pinv, B, Xsol, s, tol, max_iter, flags, 0, st));
+  FIRAL_CHECK(finish_sync(x, st));
+  const Status& h = *x->status_host;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->cg_iters[0] = h.cg_iters[0];
+    info->converged = h.converged;
+    info->bad_block = -1;
+    info->relres_max = h.relres_max;
+  }
+  if (h.breakdown) {
+    set_error("PCG breakdown (p^T q <= 0)");
+    return FIRAL_EBREAKDOWN;
+  }
+  return h.converged ? FIRAL_OK : FIRAL_WARN_NOT_CONVERGED;
+}
+
+int firal_grad_z(firal_ctx ctx, const void* U, const void* W, int32_t s, double* g, void* stream) {
+  FIRAL_CHECK(check_common(ctx, s));
+  FIRAL_REQ(U != nullptr && W != nullptr && g != nullptr, "null U, W or g");
+  return grad_launch(C(ctx), U, W, s, g, (hipStream_t)stream);
+}
+
+int firal_probes(firal_ctx ctx, uint64_t seed, int32_t t, int32_t s, void* V, void* stream) {
+  FIRAL_CHECK(check_common(ctx, s));
+  FIRAL_REQ(V != nullptr, "null V");
+  FIRAL_REQ(t >= 1, "t = %d < 1", t);
+  return probes_launch(C(ctx), seed, t, s, V, (hipStream_t)stream);
+}
+
+int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double beta0,
+                     uint64_t seed, int32_t t, int32_t s, double tol, int32_t max_iter,
+                     uint32_t flags, double* g_out, firal_info* info, void* stream) {
+  FIRAL_CHECK(check_common(ctx, s));
+  Ctx* x = C(ctx);
+  FIRAL_REQ(w != nullptr, "null w");
+  FIRAL_REQ(b > 0.0, "b must be > 0");
+  FIRAL_REQ(lambda >= 0.0, "lambda < 0");
+  FIRAL_REQ(beta0 >= 0.0, "beta0 < 0");
+  FIRAL_REQ(t >= 1, "t = %d < 1", t);
+  FIRAL_REQ(tol >= 0.0, "tol < 0");
+  FIRAL_REQ(max_iter >= 0, "max_iter < 0");
+  FIRAL_REQ((flags & ~FIRAL_PCG_PROJECT) == 0, "unknown flags 0x%x", flags);
+  hipStream_t st = (hipStream_t)stream;
+  FIRAL_CHECK(relax_step_launch(x, w, b, lambda, beta0, seed, t, s, tol, max_iter, flags, g_out, st));
+  FIRAL_CHECK(finish_sync(x, st));
+  const Status& h = *x->status_host;
+  const int bad = h.bad_block == INT_MAX ? -1 : h.bad_block;
+  if (info) {
+    info->cg_iters[0] = h.cg_iters[0];
+    info->cg_iters[1] = h.cg_iters[1];
+    info->converged = h.converged;
+    info->bad_block = bad;
+    info->relres_max = h.relres_max;
+    info->f_hat = h.f_hat;
+    info->g_absmax = h.g_absmax;
+    info->beta = h.beta;
+  }
+  if (bad >= 0) {
+    set_error("preconditioner block %d is not positive definite", bad);
+    return FIRAL_ENOTSPD;
+  }
+  if (h.breakdown) {
+    set_error("PCG breakdown (p^T q <= 0)");
+    return FIRAL_EBREAKDOWN;
+  }
+  return h.converged ? FIRAL_OK : FIRAL_WARN_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -1,0 +1,191 @@
+// Internal declarations of the gfx950 Relax library: context layout, MFMA
+// wrappers, reductions and the host-side launchers shared between sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "firal.h"
+
+namespace firal {
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+
+#define FIRAL_HIP(x)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (x);                                                        \
+    if (e_ != hipSuccess) {                                                     \
+      ::firal::set_error("%s failed: %s", #x, hipGetErrorString(e_));           \
+      return FIRAL_EHIP;                                                        \
+    }                                                                           \
+  } while (0)
+
+#define FIRAL_LAUNCHED()                                                        \
+  do {                                                                          \
+    hipError_t e_ = hipGetLastError();                                          \
+    if (e_ != hipSuccess) {                                                     \
+      ::firal::set_error("kernel launch failed at %s:%d: %s", __FILE__, __LINE__, \
+                         hipGetErrorString(e_));                                \
+      return FIRAL_EHIP;                                                        \
+    }                                                                           \
+  } while (0)
+
+#define FIRAL_CHECK(x)                                                          \
+  do {                                                                          \
+    int rc_ = (x);                                                              \
+    if (rc_ < 0) return rc_;                                                    \
+  } while (0)
+
+// ------------------------------------------------------- device status
+// One per context, in device memory.  Written only by the library's kernels.
+struct Status {
+  int32_t all_done;     // PCG loop: nothing left to do (all columns converged, or an error)
+  int32_t iters;        // PCG iterations performed by the current solve
+  int32_t breakdown;    // PCG: p^T q <= 0 on an active column
+  int32_t bad_block;    // Cholesky: smallest failing class index, INT32_MAX when none
+  int32_t cg_iters[2];  // iterations of the two solves of a Relax iteration
+  int32_t converged;    // 1 while every finished solve converged
+  int32_t pad;
+  double relres_max;
+  double f_hat;
+  double g_absmax;
+  double beta;
+};
+
+// ------------------------------------------------------------- context
+struct Ctx {
+  int64_t n_pool, n_lab, N;
+  int d, c, s_max;
+  int prec;             // firal_prec
+  size_t esize;         // bytes per element of X, H and blocks
+  const void* X;
+  const void* H;
+  int device;
+
+  // hvp / grad row-chunk intermediates
+  int64_t chunk_rows;   // rows per chunk of the (rows x s*c) intermediate
+  void* G;              // 2 * chunk_rows * s_max * c elements
+  int max_splits;       // split-K partial buffers for the X^T G contraction
+  void* part;           // max_splits * d * s_max * c elements
+
+  // bf16x3 operands: hi/lo bf16 split of X (FP32 storage contexts only)
+  void* Xhi;
+  void* Xlo;
+
+  // preconditioner
+  double* P;            // c * d * d: blocks, factorised in place
+  double* Pinv;         // c * d * d
+  void* syrk_part;      // syrk_splits * c * npairs * 256 elements
+  int syrk_splits;
+
+  // Relax / PCG blocks (d * s_max * c elements each)
+  void *V, *W1, *Y, *W2;
+  void *cx, *cr, *cz, *cp, *cq;
+  double* mean;         // d * s_max: class means for the projection
+  double* omega;        // N
+  double* gbuf;         // n_pool: gradient
+  double* ebuf;         // n_pool: exponents of the mirror step
+
+  // per-column scalars and reduction partials
+  int col_parts;        // partial sums per column
+  double* colpart;      // 4 * s_max * col_parts
+  double* rho;          // s_max
+  double* bnorm;        // s_max
+  double* alpha;        // s_max
+  double* beta;         // s_max
+  double* relres;       // s_max
+  int32_t* done;        // s_max
+  int red_blocks;       // blocks of the n_pool reductions
+  double* redpart;      // 3 * red_blocks
+
+  Status* status;       // device
+  Status* status_host;  // pinned host mirror
+};
+
+inline Ctx* C(firal_ctx p) { return reinterpret_cast<Ctx*>(p); }
+
+// ------------------------------------------------------------ constants
+constexpr int kBlock = 256;
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------- MFMA
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// 16x16x4 MFMA: lane l supplies A[l%16][l/16] and B[l/16][l%16] and receives
+// D[row(l/16, v)][l%16], v = 0..3, where row(q, v) = 4q + v for FP32 and q + 4v for
+// FP64 (the two instructions place their four results differently).
+template <typename T> struct Mfma16;
+template <> struct Mfma16<float> {
+  typedef f32x4 acc;
+  static __device__ __forceinline__ int row(int q, int v) { return 4 * q + v; }
+  static __device__ __forceinline__ acc zero() { return acc{0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ acc run(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma16<double> {
+  typedef f64x4 acc;
+  static __device__ __forceinline__ int row(int q, int v) { return q + 4 * v; }
+  static __device__ __forceinline__ acc zero() { return acc{0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ acc run(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+// ------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+  return v;
+}
+// Block-wide sum/max in a fixed order; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[NT / 64];
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) r += red[i];
+  __syncthreads();
+  return r;
+}
+template <int NT>
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double red[NT / 64];
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double r = -INFINITY;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < NT / 64; ++i) r = fmax(r, red[i]);
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------- host-side launchers
+// All enqueue on `st`; `skip` (device, may be null) makes every kernel return
+// at once when *skip != 0, so a PCG loop can run ahead of its convergence test.
+int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
+               void* out, int s, const int32_t* skip, hipStream_t st);
+int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st);
+int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,
+               void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
+               hipStream_t st);
+int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st);
+int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st);
+int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part,
+                  const int32_t* skip, hipStream_t st);
+int bf16_split_launch(Ctx* x, hipStream_t st);
+
+}  // namespace firal

@@ -1,0 +1,335 @@
+// Block-Jacobi preconditioned CG over s right-hand sides in lock-step
+// (Algorithm 2, the two solves), from x0 = 0.
+//
+// Every per-column scalar (rho, alpha, beta, the residual test) lives on the
+// device and is produced by one-block kernels from partial sums written in a
+// fixed order, so the loop needs no host round trip per iteration: the host
+// only reads the status every few iterations.  Once all columns have met the
+// tolerance (or an error stopped the loop) every kernel of the loop returns at
+// once, so iterations queued past convergence cost a launch each.
+//
+// Column j freezes (x_j, r_j, p_j no longer change) when
+// ||r_j|| <= tol ||b_j|| on the recurrence residual.
+#include <algorithm>
+#include <climits>
+
+#include "common.h"
+
+namespace firal {
+
+// part[j * P + p] = sum over a in slice p of sum_k A[a,j,k] B[a,j,k].
+template <typename T>
+__global__ __launch_bounds__(256) void k_coldot(const T* __restrict__ A, const T* __restrict__ B,
+                                                int d, int s, int c, int P,
+                                                double* __restrict__ part, const int32_t* skip) {
+  if (skip && *skip) return;
+  const int j = blockIdx.x, p = blockIdx.y;
+  const int per = (d + P - 1) / P;
+  const int a0 = p * per;
+  const int a1 = min(d, a0 + per);
+  const int64_t n = a1 > a0 ? (int64_t)(a1 - a0) * c : 0;
+  double acc = 0.0;
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+    const int a = a0 + (int)(e / c), k = (int)(e % c);
+    const int64_t i = ((int64_t)a * s + j) * c + k;
+    acc += (double)A[i] * (double)B[i];
+  }
+  acc = block_sum<256>(acc);
+  if (threadIdx.x == 0) part[j * P + p] = acc;
+}
+
+int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, const int32_t* skip,
+                  hipStream_t st) {
+  dim3 grid(s, x->col_parts);
+  if (x->prec == FIRAL_F64)
+    k_coldot<double><<<grid, 256, 0, st>>>((const double*)A, (const double*)B, x->d, s, x->c,
+                                           x->col_parts, part, skip);
+  else
+    k_coldot<float><<<grid, 256, 0, st>>>((const float*)A, (const float*)B, x->d, s, x->c,
+                                          x->col_parts, part, skip);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
+// Y[a,j,:] = R[a,j,:] - mean_k R[a,j,k]  (projection onto the complement of 1_c (x) u).
+// Y may alias R.
+template <typename T>
+__global__ __launch_bounds__(256) void k_project(const T* R, T* Y, int d, int s, int c,
+                                                 const int32_t* skip) {
+  if (skip && *skip) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d * s) return;
+  const T* r = R + idx * c;
+  T* y = Y + idx * c;
+  double m = 0.0;
+  for (int k = 0; k < c; ++k) m += (double)r[k];
+  m /= c;
+  for (int k = 0; k < c; ++k) y[k] = (T)((double)r[k] - m);
+}
+
+// mean[a*s + j] = mean_k R[a,j,k]
+template <typename T>
+__global__ __launch_bounds__(256) void k_classmean(const T* __restrict__ R, double* __restrict__ mean,
+                                                   int d, int s, int c, const int32_t* skip) {
+  if (skip && *skip) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d * s) return;
+  const T* r = R + idx * c;
+  double m = 0.0;
+  for (int k = 0; k < c; ++k) m += (double)r[k];
+  mean[idx] = m / c;
+}
+
+// Z[a,j,k] = sum_b Pinv_k[b][a] (R[b,j,k] - mean[b,j]); Pinv_k is symmetric, so reading
+// its column makes consecutive lanes (consecutive a) read consecutive addresses.
+template <typename T>
+__global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
+                                                const T* __restrict__ R,
+                                                const double* __restrict__ mean,
+                                                T* __restrict__ Z, int d, int s, int c,
+                                                const int32_t* skip) {
+  if (skip && *skip) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d * s * c) return;
+  const int a = (int)(idx % d);
+  const int64_t kj = idx / d;
+  const int j = (int)(kj % s);
+  const int k = (int)(kj / s);
+  const double* Pk = Pinv + (int64_t)k * d * d;
+  const int64_t sc = (int64_t)s * c;
+  double acc = 0.0;
+  for (int b = 0; b < d; ++b) {
+    double rv = (double)R[b * sc + (int64_t)j * c + k];
+    if (mean) rv -= mean[(int64_t)b * s + j];
+    acc += Pk[(int64_t)b * d + a] * rv;
+  }
+  Z[a * sc + (int64_t)j * c + k] = (T)acc;
+}
+
+// ------------------------------------------------------------ scalars
+
+__device__ __forceinline__ double sum_parts(const double* part, int j, int P) {
+  double v = 0.0;
+  for (int p = 0; p < P; ++p) v += part[j * P + p];
+  return v;
+}
+
+__global__ __launch_bounds__(64) void k_cg_init(const double* part_bb, const double* part_rz, int s,
+                                                int P, Status* st, double* rho, double* bnorm,
+                                                double* relres, int32_t* done) {
+  __shared__ int alldone;
+  if (threadIdx.x == 0) alldone = 1;
+  __syncthreads();
+  for (int j = threadIdx.x; j < s; j += blockDim.x) {
+    const double bb = sum_parts(part_bb, j, P);
+    bnorm[j] = sqrt(bb);
+    rho[j] = sum_parts(part_rz, j, P);
+    done[j] = bb == 0.0;
+    relres[j] = bb > 0.0 ? 1.0 : 0.0;
+    if (bb != 0.0) atomicAnd(&alldone, 0);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->iters = 0;
+    // an earlier failure (non-SPD block, breakdown in a previous solve) stops this one too
+    st->all_done = alldone || st->breakdown != 0 || st->bad_block != INT_MAX;
+    double m = 0.0;
+    for (int j = 0; j < s; ++j) m = fmax(m, relres[j]);
+    st->relres_max = m;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_cg_alpha(const double* part_pq, int s, int P, Status* st,
+                                                 const double* rho, const int32_t* done,
+                                                 double* alpha) {
+  if (st->all_done) return;
+  __shared__ int brk;
+  if (threadIdx.x == 0) brk = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < s; j += blockDim.x) {
+    const double pq = sum_parts(part_pq, j, P);
+    double a = 0.0;
+    if (!done[j]) {
+      if (!(pq > 0.0)) atomicOr(&brk, 1);
+      else a = rho[j] / pq;
+    }
+    alpha[j] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && brk) {
+    st->breakdown = 1;
+    st->all_done = 1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_update(T* __restrict__ xv, T* __restrict__ r,
+                                                   const T* __restrict__ p,
+                                                   const T* __restrict__ q,
+                                                   const double* __restrict__ alpha, int64_t n,
+                                                   int s, int c, const int32_t* skip) {
+  if (*skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = (int)((i / c) % s);
+  const T a = (T)alpha[j];
+  xv[i] += a * p[i];
+  r[i] -= a * q[i];
+}
+
+__global__ __launch_bounds__(64) void k_cg_done(const double* part_rr, int s, int P, Status* st,
+                                                const double* bnorm, double* relres,
+                                                int32_t* done, double tol) {
+  if (st->all_done) return;
+  __shared__ int alldone;
+  if (threadIdx.x == 0) alldone = 1;
+  __syncthreads();
+  for (int j = threadIdx.x; j < s; j += blockDim.x) {
+    const double rn = sqrt(sum_parts(part_rr, j, P));
+    if (!done[j] && rn <= tol * bnorm[j]) done[j] = 1;
+    relres[j] = bnorm[j] > 0.0 ? rn / bnorm[j] : 0.0;
+    if (!done[j]) atomicAnd(&alldone, 0);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st->iters += 1;
+    double m = 0.0;
+    for (int j = 0; j < s; ++j) m = fmax(m, relres[j]);
+    st->relres_max = m;
+    st->all_done = alldone;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_cg_beta(const double* part_rz, int s, int P, Status* st,
+                                                double* rho, const int32_t* done, double* beta) {
+  if (st->all_done) return;
+  for (int j = threadIdx.x; j < s; j += blockDim.x) {
+    const double rz = sum_parts(part_rz, j, P);
+    if (!done[j]) {
+      beta[j] = rz / (rho[j] != 0.0 ? rho[j] : 1.0);
+      rho[j] = rz;
+    } else {
+      beta[j] = 0.0;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_cg_pupdate(T* __restrict__ p, const T* __restrict__ z,
+                                                    const double* __restrict__ beta,
+                                                    const int32_t* __restrict__ done, int64_t n,
+                                                    int s, int c, const int32_t* skip) {
+  if (*skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int j = (int)((i / c) % s);
+  if (done[j]) return;
+  p[i] = z[i] + (T)beta[j] * p[i];
+}
+
+__global__ void k_cg_finish(Status* st, int slot) {
+  st->cg_iters[slot] = st->iters;
+  if (st->breakdown || !st->all_done) st->converged = 0;
+}
+
+// z = M^-1 r with M = blockdiag(P_k); projected: z = Pp M^-1 Pp r.
+template <typename T>
+static int apply_t(Ctx* x, const double* Pinv, const T* r, T* z, int s, bool project,
+                   const int32_t* skip, hipStream_t st) {
+  const int d = x->d, c = x->c;
+  const int64_t nds = (int64_t)d * s;
+  if (project) {
+    k_classmean<T><<<(unsigned)cdiv(nds, 256), 256, 0, st>>>(r, x->mean, d, s, c, skip);
+    FIRAL_LAUNCHED();
+  }
+  k_papply<T><<<(unsigned)cdiv(nds * c, 256), 256, 0, st>>>(Pinv, r, project ? x->mean : nullptr,
+                                                             z, d, s, c, skip);
+  FIRAL_LAUNCHED();
+  if (project) {
+    k_project<T><<<(unsigned)cdiv(nds, 256), 256, 0, st>>>(z, z, d, s, c, skip);
+    FIRAL_LAUNCHED();
+  }
+  return FIRAL_OK;
+}
+
+static int read_status(Ctx* x, hipStream_t st) {
+  FIRAL_HIP(hipMemcpyAsync(x->status_host, x->status, sizeof(Status), hipMemcpyDeviceToHost, st));
+  FIRAL_HIP(hipStreamSynchronize(st));
+  return FIRAL_OK;
+}
+
+template <typename T>
+static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, const T* B,
+                 T* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
+                 hipStream_t st) {
+  const int d = x->d, c = x->c, P = x->col_parts;
+  const int64_t n = (int64_t)d * s * c;
+  const bool project = (flags & FIRAL_PCG_PROJECT) != 0;
+  T* xv = (T*)x->cx;
+  T* r = (T*)x->cr;
+  T* z = (T*)x->cz;
+  T* p = (T*)x->cp;
+  T* q = (T*)x->cq;
+  double* part0 = x->colpart;
+  double* part1 = x->colpart + (int64_t)x->s_max * P;
+  const int32_t* skip = &x->status->all_done;
+  const unsigned nb = (unsigned)cdiv(n, 256);
+
+  FIRAL_HIP(hipMemsetAsync(xv, 0, n * sizeof(T), st));
+  if (project) {
+    k_project<T><<<(unsigned)cdiv((int64_t)d * s, 256), 256, 0, st>>>(B, r, d, s, c, nullptr);
+    FIRAL_LAUNCHED();
+  } else {
+    FIRAL_HIP(hipMemcpyAsync(r, B, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+  }
+  FIRAL_CHECK(apply_t<T>(x, Pinv, r, z, s, project, nullptr, st));
+  FIRAL_HIP(hipMemcpyAsync(p, z, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+  FIRAL_CHECK(coldot_launch(x, r, r, s, part0, nullptr, st));
+  FIRAL_CHECK(coldot_launch(x, r, z, s, part1, nullptr, st));
+  k_cg_init<<<1, 64, 0, st>>>(part0, part1, s, P, x->status, x->rho, x->bnorm, x->relres, x->done);
+  FIRAL_LAUNCHED();
+
+  const int check_every = tol > 0.0 ? 4 : (max_iter > 0 ? max_iter : 1);
+  int launched = 0;
+  while (launched < max_iter) {
+    const int batch = std::min(check_every, max_iter - launched);
+    for (int it = 0; it < batch; ++it) {
+      FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip, st));
+      FIRAL_CHECK(coldot_launch(x, p, q, s, part0, skip, st));
+      k_cg_alpha<<<1, 64, 0, st>>>(part0, s, P, x->status, x->rho, x->done, x->alpha);
+      FIRAL_LAUNCHED();
+      k_cg_update<T><<<nb, 256, 0, st>>>(xv, r, p, q, x->alpha, n, s, c, skip);
+      FIRAL_LAUNCHED();
+      FIRAL_CHECK(coldot_launch(x, r, r, s, part1, skip, st));
+      k_cg_done<<<1, 64, 0, st>>>(part1, s, P, x->status, x->bnorm, x->relres, x->done, tol);
+      FIRAL_LAUNCHED();
+      FIRAL_CHECK(apply_t<T>(x, Pinv, r, z, s, project, skip, st));
+      FIRAL_CHECK(coldot_launch(x, r, z, s, part0, skip, st));
+      k_cg_beta<<<1, 64, 0, st>>>(part0, s, P, x->status, x->rho, x->done, x->beta);
+      FIRAL_LAUNCHED();
+      k_cg_pupdate<T><<<nb, 256, 0, st>>>(p, z, x->beta, x->done, n, s, c, skip);
+      FIRAL_LAUNCHED();
+    }
+    launched += batch;
+    if (launched < max_iter) {
+      FIRAL_CHECK(read_status(x, st));
+      if (x->status_host->all_done) break;
+    }
+  }
+  k_cg_finish<<<1, 1, 0, st>>>(x->status, slot);
+  FIRAL_LAUNCHED();
+  if (Xsol != xv) FIRAL_HIP(hipMemcpyAsync(Xsol, xv, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+  return FIRAL_OK;
+}
+
+int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,
+               void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
+               hipStream_t st) {
+  if (x->prec == FIRAL_F64)
+    return pcg_t<double>(x, omega, shift, Pinv, (const double*)B, (double*)Xsol, s, tol, max_iter,
+                         flags, slot, st);
+  return pcg_t<float>(x, omega, shift, Pinv, (const float*)B, (float*)Xsol, s, tol, max_iter,
+                      flags, slot, st);
+}
+
+}  // namespace firal

@@ -1,0 +1,247 @@
+// Rademacher probes, the eq. 11 per-point gradient contraction, the entropic
+// mirror-descent update, and one full iteration of the fast Relax solve
+// (Algorithm 2).
+#include <algorithm>
+#include <climits>
+#include <cmath>
+
+#include "common.h"
+
+namespace firal {
+
+int gemm_xb_launch(Ctx* x, const void* Xrows, const void* Bm, int SC, void* G, int64_t R,
+                   const int32_t* skip, hipStream_t st);
+
+// ------------------------------------------------------------- probes
+// SplitMix64 (Steele, Lea & Flood 2014): output m of the stream seeded with `seed` is the
+// finaliser applied to seed + (m + 1) * 0x9E3779B97F4A7C15.
+__device__ __forceinline__ uint64_t splitmix_final(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_probes(T* __restrict__ V, uint64_t seed, int t, int d,
+                                                int s, int c) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t sc = (int64_t)s * c;
+  if (idx >= (int64_t)d * sc) return;
+  const int a = (int)(idx / sc);
+  const int j = (int)((idx / c) % s);
+  const int k = (int)(idx % c);
+  const uint64_t ctr = ((uint64_t)(t - 1) * (uint64_t)s + (uint64_t)j) * ((uint64_t)d * c) +
+                       (uint64_t)k * d + (uint64_t)a;
+  const uint64_t z = splitmix_final(seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull);
+  V[idx] = (z >> 63) ? T(-1) : T(1);
+}
+
+int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st) {
+  const int64_t n = (int64_t)x->d * s * x->c;
+  if (x->prec == FIRAL_F64)
+    k_probes<double><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((double*)V, seed, t, x->d, s, x->c);
+  else
+    k_probes<float><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((float*)V, seed, t, x->d, s, x->c);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
+// ----------------------------------------------------------- gradient
+// g[r] = -(1/s) sum_j [ sum_k A h B - (A.h)(B.h) ]  with A = X U, B = X W row r
+// (Lemma 1: u^T H_i w = (U^T x_i)^T Gamma_i (W^T x_i)).  FP64 accumulation.
+template <typename T>
+__global__ __launch_bounds__(256) void k_grad_rows(const T* __restrict__ A, const T* __restrict__ B,
+                                                   const T* __restrict__ H, int64_t R, int s,
+                                                   int c, double* __restrict__ g) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int64_t sc = (int64_t)s * c;
+  const T* a = A + r * sc;
+  const T* b = B + r * sc;
+  const T* h = H + r * c;
+  double q = 0.0;
+  for (int j = 0; j < s; ++j) {
+    double sab = 0.0, sa = 0.0, sb = 0.0;
+    for (int k = 0; k < c; ++k) {
+      const double hk = (double)h[k];
+      const double ak = (double)a[j * c + k] * hk;
+      const double bk = (double)b[j * c + k];
+      sab += ak * bk;
+      sa += ak;
+      sb += bk * hk;
+    }
+    q += sab - sa * sb;
+  }
+  g[r] = -q / s;
+}
+
+int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st) {
+  const int d = x->d, c = x->c, SC = s * c;
+  const int64_t half = x->chunk_rows * (int64_t)x->s_max * c;
+  for (int64_t r0 = 0; r0 < x->n_pool; r0 += x->chunk_rows) {
+    const int64_t R = std::min<int64_t>(x->chunk_rows, x->n_pool - r0);
+    const char* Xr = (const char*)x->X + r0 * d * x->esize;
+    const char* Hr = (const char*)x->H + r0 * c * x->esize;
+    void* G0 = x->G;
+    void* G1 = (char*)x->G + half * x->esize;
+    FIRAL_CHECK(gemm_xb_launch(x, Xr, U, SC, G0, R, nullptr, st));
+    FIRAL_CHECK(gemm_xb_launch(x, Xr, W, SC, G1, R, nullptr, st));
+    if (x->prec == FIRAL_F64)
+      k_grad_rows<double><<<(unsigned)cdiv(R, 256), 256, 0, st>>>(
+          (const double*)G0, (const double*)G1, (const double*)Hr, R, s, c, g + r0);
+    else
+      k_grad_rows<float><<<(unsigned)cdiv(R, 256), 256, 0, st>>>(
+          (const float*)G0, (const float*)G1, (const float*)Hr, R, s, c, g + r0);
+    FIRAL_LAUNCHED();
+  }
+  return FIRAL_OK;
+}
+
+// ----------------------------------------------------- mirror descent
+// Four passes with per-block partials re-reduced in a fixed order by every block:
+//   (1) max|g|   (2) beta = beta0/max|g|, e = log w - beta g, max e
+//   (3) u = exp(e - max e), sum u   (4) w = u / sum u
+// A failed step (non-SPD block or CG breakdown) leaves w unchanged.
+
+__device__ __forceinline__ bool step_failed(const Status* st) {
+  return st->breakdown != 0 || st->bad_block != INT_MAX;
+}
+
+__device__ __forceinline__ double reduce_parts_max(const double* part, int nb) {
+  double m = -INFINITY;
+  for (int i = 0; i < nb; ++i) m = fmax(m, part[i]);
+  return m;
+}
+
+__global__ __launch_bounds__(256) void k_md1(const double* __restrict__ g, int64_t n,
+                                             double* __restrict__ part) {
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, fabs(g[i]));
+  m = block_max<256>(m);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_md2(const double* __restrict__ w,
+                                             const double* __restrict__ g, int64_t n,
+                                             double beta0, const double* __restrict__ part_g,
+                                             double* __restrict__ e, double* __restrict__ part_e,
+                                             Status* st) {
+  const double gmax = reduce_parts_max(part_g, gridDim.x);
+  const double beta = gmax > 0.0 ? beta0 / gmax : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->g_absmax = gmax;
+    st->beta = beta;
+  }
+  double m = -INFINITY;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = log(w[i]) - beta * g[i];
+    e[i] = v;
+    m = fmax(m, v);
+  }
+  m = block_max<256>(m);
+  if (threadIdx.x == 0) part_e[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_md3(double* __restrict__ e, int64_t n,
+                                             const double* __restrict__ part_e,
+                                             double* __restrict__ part_s) {
+  const double m = reduce_parts_max(part_e, gridDim.x);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double u = exp(e[i] - m);
+    e[i] = u;
+    acc += u;
+  }
+  acc = block_sum<256>(acc);
+  if (threadIdx.x == 0) part_s[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_md4(double* __restrict__ w, const double* __restrict__ u,
+                                             int64_t n, const double* __restrict__ part_s,
+                                             const Status* st) {
+  if (step_failed(st)) return;
+  double S = 0.0;
+  for (int i = 0; i < (int)gridDim.x; ++i) S += part_s[i];
+  const double inv = 1.0 / S;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    w[i] = u[i] * inv;
+}
+
+// omega = [b w ; 1]
+__global__ __launch_bounds__(256) void k_omega(const double* __restrict__ w, double b,
+                                               int64_t n_pool, int64_t N,
+                                               double* __restrict__ omega) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) omega[i] = i < n_pool ? b * w[i] : 1.0;
+}
+
+__global__ void k_fhat(const double* part, int s, int P, Status* st) {
+  double f = 0.0;
+  for (int j = 0; j < s; ++j)
+    for (int p = 0; p < P; ++p) f += part[j * P + p];
+  st->f_hat = f / s;
+}
+
+__global__ void k_step_reset(Status* st) {
+  st->converged = 1;
+  st->breakdown = 0;
+  st->bad_block = INT_MAX;
+  st->cg_iters[0] = 0;
+  st->cg_iters[1] = 0;
+  st->relres_max = 0.0;
+  st->f_hat = 0.0;
+  st->g_absmax = 0.0;
+  st->beta = 0.0;
+}
+
+__global__ void k_relres_merge(Status* st, double* keep) {
+  // keeps the max recurrence residual over both solves
+  *keep = fmax(*keep, st->relres_max);
+  st->relres_max = *keep;
+}
+
+int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, uint64_t seed,
+                      int t, int s, double tol, int max_iter, uint32_t flags, double* g_out,
+                      hipStream_t st) {
+  const int64_t n = x->n_pool, N = x->N;
+  k_step_reset<<<1, 1, 0, st>>>(x->status);
+  FIRAL_LAUNCHED();
+  k_omega<<<(unsigned)cdiv(N, 256), 256, 0, st>>>(w, b, n, N, x->omega);
+  FIRAL_LAUNCHED();
+  FIRAL_CHECK(probes_launch(x, seed, t, s, x->V, st));
+  FIRAL_CHECK(precond_launch(x, x->omega, lambda, st));
+  double* keep = x->redpart + 3 * x->red_blocks;   // one spare slot
+  FIRAL_HIP(hipMemsetAsync(keep, 0, sizeof(double), st));
+  FIRAL_CHECK(pcg_launch(x, x->omega, lambda, x->Pinv, x->V, x->W1, s, tol, max_iter, flags, 0, st));
+  k_relres_merge<<<1, 1, 0, st>>>(x->status, keep);
+  FIRAL_LAUNCHED();
+  FIRAL_CHECK(hvp_launch(x, nullptr, n, 0.0, x->W1, x->Y, s, nullptr, st));
+  FIRAL_CHECK(coldot_launch(x, x->V, x->Y, s, x->colpart, nullptr, st));
+  k_fhat<<<1, 1, 0, st>>>(x->colpart, s, x->col_parts, x->status);
+  FIRAL_LAUNCHED();
+  FIRAL_CHECK(pcg_launch(x, x->omega, lambda, x->Pinv, x->Y, x->W2, s, tol, max_iter, flags, 1, st));
+  k_relres_merge<<<1, 1, 0, st>>>(x->status, keep);
+  FIRAL_LAUNCHED();
+  double* g = g_out ? g_out : x->gbuf;
+  FIRAL_CHECK(grad_launch(x, x->V, x->W2, s, g, st));
+  const int nb = x->red_blocks;
+  double* pg = x->redpart;
+  double* pe = x->redpart + nb;
+  double* ps = x->redpart + 2 * nb;
+  k_md1<<<nb, 256, 0, st>>>(g, n, pg);
+  FIRAL_LAUNCHED();
+  k_md2<<<nb, 256, 0, st>>>(w, g, n, beta0, pg, x->ebuf, pe, x->status);
+  FIRAL_LAUNCHED();
+  k_md3<<<nb, 256, 0, st>>>(x->ebuf, n, pe, ps);
+  FIRAL_LAUNCHED();
+  k_md4<<<nb, 256, 0, st>>>(w, x->ebuf, n, ps, x->status);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
+}  // namespace firal

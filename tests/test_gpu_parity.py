@@ -1,0 +1,305 @@
+"""GPU parity: every C-ABI entry point against the FP64 oracle on the same inputs.
+
+Tolerances (normwise relative error ||gpu - oracle|| / ||oracle||, plus an
+elementwise bound scaled by the largest oracle entry):
+* FP64 mode: 1e-10.  Both sides compute in FP64; they differ only in the
+  order of the sums (tiles, split-K partials), so the error is a small
+  multiple of eps * sqrt(terms) ~ 1e-13.
+* FP32 mode: 1e-5.  The oracle runs on the FP32-rounded inputs, so the gap is
+  FP32 arithmetic alone: products accumulated over d or n terms in FP32.
+Iterative results (PCG, Relax) are compared with the same probes and either
+the same stopping rule (iteration counts must match) or a fixed number of
+iterations on both sides.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import relax as orc
+from paper_2409_07392_amd import FiralError, RelaxContext, _lib
+from synthdata import make_problem, make_small
+
+pytestmark = pytest.mark.gpu
+
+DT = {"f64": torch.float64, "f32": torch.float32}
+NPDT = {"f64": np.float64, "f32": np.float32}
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+def dev(a, dtype):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def rounded(a, prec):
+    return np.asarray(a, dtype=NPDT[prec]).astype(np.float64)
+
+
+def relerr(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def assert_close(got, ref, tol, what=""):
+    e = relerr(got, ref)
+    assert e <= tol, f"{what}: normwise relative error {e:.3e} > {tol:.1e}"
+    scale = np.abs(ref).max() if ref.size else 1.0
+    worst = np.abs(got - ref).max() if ref.size else 0.0
+    assert worst <= 10 * tol * max(scale, 1e-300), f"{what}: max abs error {worst:.3e}"
+
+
+def context(p, prec, s_max):
+    X = rounded(p.X, prec)
+    H = rounded(p.H, prec)
+    ctx = RelaxContext(dev(X, DT[prec]), dev(H, DT[prec]), p.n_pool, s_max, prec)
+    return ctx, X, H
+
+
+SHAPES = [  # n_pool, n_lab, d, c, s
+    (2000, 50, 20, 5, 10),     # configuration 1 shape
+    (3001, 7, 100, 10, 20),    # configuration 2 shape, ragged n
+    (517, 3, 37, 13, 3),       # nothing a multiple of a tile
+    (300, 0, 1, 2, 1),         # degenerate d = 1, c = 2, s = 1, no labeled rows
+    (1000, 10, 130, 33, 2),    # d over two 64-tiles
+]
+
+
+# --------------------------------------------------------------------- probes
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_probes_bit_exact(prec):
+    p = make_small(n=50, n_lab=1, d=13, c=7, s=5)
+    ctx, _, _ = context(p, prec, 9)
+    for seed, t, s in [(0, 1, 5), (2002, 3, 9), (2**64 - 5, 7, 1), (123456789, 100, 4)]:
+        V = host(ctx.probes(seed, t, s))
+        assert np.array_equal(V, orc.probes(seed, t, 13, s, 7)), (seed, t, s)
+
+
+# ------------------------------------------------------------------------ hvp
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_hvp_matches_oracle(prec, shape):
+    n, nl, d, c, s = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=5)
+    ctx, X, H = context(p, prec, s)
+    rng = np.random.default_rng(1)
+    B = rounded(rng.standard_normal((d, s, c)), prec)
+    om = rng.uniform(0.0, 2.0, p.N)
+    got = host(ctx.hvp(dev(B, DT[prec]), omega=dev(om, torch.float64), shift=0.25))
+    assert_close(got, orc.hvp(X, H, om, 0.25, B), TOL[prec], f"hvp {prec} {shape}")
+    # H_p: pool rows only, unit weights, no shift
+    got = host(ctx.hvp(dev(B, DT[prec]), n_rows=n))
+    assert_close(got, orc.hvp(X[:n], H[:n], None, 0.0, B), TOL[prec], f"H_p {prec} {shape}")
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_hvp_row_chunks(prec, monkeypatch):
+    monkeypatch.setenv("FIRAL_CHUNK_ROWS", "333")
+    p = make_small(n=2100, n_lab=17, d=29, c=6, s=4, seed=9)
+    ctx, X, H = context(p, prec, 4)
+    B = rounded(np.random.default_rng(2).standard_normal((29, 4, 6)), prec)
+    got = host(ctx.hvp(dev(B, DT[prec]), shift=0.5))
+    assert_close(got, orc.hvp(X, H, None, 0.5, B), TOL[prec], "chunked hvp")
+
+
+def test_hvp_no_rows_is_the_shift():
+    p = make_small(n=20, n_lab=2, d=5, c=3, s=2)
+    ctx, _, _ = context(p, "f64", 2)
+    B = np.random.default_rng(3).standard_normal((5, 2, 3))
+    got = host(ctx.hvp(dev(B, torch.float64), n_rows=0, shift=1.5))
+    assert np.array_equal(got, 1.5 * B)
+
+
+def test_hvp_is_deterministic():
+    p = make_small(n=3001, n_lab=7, d=100, c=10, s=20, seed=4)
+    ctx, _, _ = context(p, "f32", 20)
+    B = dev(np.random.default_rng(4).standard_normal((100, 20, 10)), torch.float32)
+    a = ctx.hvp(B, shift=0.1)
+    b = ctx.hvp(B, shift=0.1)
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------- preconditioner
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(2000, 50, 20, 5), (3001, 7, 100, 10), (517, 3, 37, 13),
+                                   (700, 4, 130, 3)])
+def test_precond_matches_oracle(prec, shape):
+    n, nl, d, c = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=6)
+    ctx, X, H = context(p, prec, 1)
+    om = np.random.default_rng(5).uniform(0.0, 1.0, p.N)
+    L, Pinv, info = ctx.build_precond(dev(om, torch.float64), shift=1e-3)
+    assert info["bad_block"] == -1
+    P = orc.precond_blocks(X, H, om, 1e-3)
+    Lr, bad = orc.precond_factor(P)
+    assert bad == -1
+    L = host(L)
+    assert np.all(np.triu(L, 1) == 0.0)
+    assert_close(L, Lr, TOL[prec], "Cholesky factor")
+    assert_close(host(Pinv), np.linalg.inv(P), 100 * TOL[prec], "block inverse")
+
+
+def test_precond_reports_non_spd_block():
+    p = make_small(n=200, n_lab=3, d=6, c=4, s=1, seed=7)
+    H = p.H.copy()
+    H[:, 2] = 0.0
+    ctx = RelaxContext(dev(p.X, torch.float64), dev(H, torch.float64), p.n_pool, 1, "f64")
+    with pytest.raises(FiralError) as ei:
+        ctx.build_precond(shift=0.0)
+    assert ei.value.code == _lib.ENOTSPD
+
+
+# ------------------------------------------------------------------------ pcg
+
+@pytest.mark.parametrize("project", [True, False])
+def test_pcg_f64_matches_oracle(project):
+    p = make_small(n=1500, n_lab=20, d=12, c=5, s=6, seed=8)
+    ctx, X, H = context(p, "f64", 6)
+    rng = np.random.default_rng(6)
+    om = np.concatenate([rng.uniform(0, 0.02, p.n_pool), np.ones(p.n_lab)])
+    B = rng.standard_normal((12, 6, 5))
+    _, Pinv, _ = ctx.build_precond(dev(om, torch.float64), shift=1e-3)
+    L, _ = orc.precond_factor(orc.precond_blocks(X, H, om, 1e-3))
+    # same number of iterations on both sides: the same arithmetic sequence
+    Xs, info = ctx.pcg_solve(dev(B, torch.float64), Pinv, omega=dev(om, torch.float64),
+                             shift=1e-3, tol=0.0, max_iter=40, project=project)
+    xr, it, _ = orc.pcg(X, H, om, 1e-3, L, B, 0.0, 40, project)
+    assert info["cg_iters"][0] == it == 40
+    assert_close(host(Xs), xr, 1e-8, "pcg iterate after 40 iterations")
+    # stopping rule: with the projection (kappa ~ 10) the counts agree exactly; without it
+    # (kappa ~ 1e4, the lambda eigenspace) rounding order can move the crossing of tol by an
+    # iteration or two, and the two solutions agree to about kappa * tol.
+    Xs, info = ctx.pcg_solve(dev(B, torch.float64), Pinv, omega=dev(om, torch.float64),
+                             shift=1e-3, tol=1e-9, max_iter=2000, project=project)
+    xr, it, rr = orc.pcg(X, H, om, 1e-3, L, B, 1e-9, 2000, project)
+    assert info["rc"] == 0 and info["converged"]
+    assert info["relres_max"] <= 1e-9
+    if project:
+        assert info["cg_iters"][0] == it
+        assert_close(host(Xs), xr, 1e-8, "pcg solution")
+    else:
+        assert abs(info["cg_iters"][0] - it) <= 3
+        assert relerr(host(Xs), xr) <= 1e-4
+
+
+def test_pcg_f32_fixed_iterations():
+    p = make_small(n=3001, n_lab=7, d=100, c=10, s=20, seed=10, whiten_x=True, probs="maxprob")
+    ctx, X, H = context(p, "f32", 20)
+    rng = np.random.default_rng(7)
+    om = np.concatenate([np.full(p.n_pool, 100.0 / p.n_pool), np.ones(p.n_lab)])
+    B = rounded(rng.choice([-1.0, 1.0], size=(100, 20, 10)), "f32")
+    _, Pinv, _ = ctx.build_precond(dev(om, torch.float64), shift=1e-3)
+    Xs, info = ctx.pcg_solve(dev(B, torch.float32), Pinv, omega=dev(om, torch.float64),
+                             shift=1e-3, tol=0.0, max_iter=12, project=True)
+    assert info["cg_iters"][0] == 12
+    L, _ = orc.precond_factor(orc.precond_blocks(X, H, om, 1e-3))
+    xr, _, _ = orc.pcg(X, H, om, 1e-3, L, B, 0.0, 12, True)
+    assert relerr(host(Xs), xr) <= 1e-4
+
+
+def test_pcg_breakdown_and_not_converged():
+    p = make_small(n=300, n_lab=3, d=4, c=3, s=2, seed=11)
+    ctx, _, _ = context(p, "f64", 2)
+    _, Pinv, _ = ctx.build_precond(shift=1.0)
+    B = dev(np.random.default_rng(8).standard_normal((4, 2, 3)), torch.float64)
+    with pytest.raises(FiralError) as ei:
+        ctx.pcg_solve(B, Pinv, shift=-1e4, tol=1e-8, max_iter=50)
+    assert ei.value.code == _lib.EBREAKDOWN
+    _, info = ctx.pcg_solve(B, Pinv, shift=1e-3, tol=1e-14, max_iter=1)
+    assert info["rc"] == _lib.WARN_NOT_CONVERGED and not info["converged"]
+    assert info["cg_iters"][0] == 1
+
+
+# ----------------------------------------------------------------------- grad
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_grad_matches_oracle(prec, shape):
+    n, nl, d, c, s = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=12)
+    ctx, X, H = context(p, prec, s)
+    rng = np.random.default_rng(9)
+    U = rounded(rng.choice([-1.0, 1.0], size=(d, s, c)), prec)
+    W = rounded(rng.standard_normal((d, s, c)), prec)
+    g = host(ctx.grad_z(dev(U, DT[prec]), dev(W, DT[prec])))
+    assert_close(g, orc.grad_contract(X[:n], H[:n], U, W), 10 * TOL[prec], f"grad {shape}")
+
+
+# ---------------------------------------------------------------------- relax
+
+def test_relax_f64_trajectory_matches_oracle():
+    p = make_problem(1)
+    ctx, X, H = context(p, "f64", p.s)
+    beta0 = orc.default_beta0(p.n_pool, p.T)
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(w)
+    wr = np.full(p.n_pool, 1.0 / p.n_pool)
+    for t in range(1, 4):
+        info = ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, 1000,
+                              project=True, g_out=g)
+        wr, ir = orc.relax_iteration(X, H, p.n_pool, wr, p.b, p.lam, beta0, p.probe_seed, t, p.s,
+                                     p.tol, 1000, project=True)
+        assert info["cg_iters"] == ir["cg_iters"], t
+        assert abs(info["f_hat"] - ir["f_hat"]) <= 1e-9 * abs(ir["f_hat"])
+        assert abs(info["g_absmax"] - ir["g_absmax"]) <= 1e-9 * ir["g_absmax"]
+        assert_close(host(g), ir["g"], 1e-9, f"gradient t={t}")
+        assert_close(host(w), wr, 1e-9, f"weights t={t}")
+    wh = host(w)
+    assert abs(wh.sum() - 1.0) < 1e-12 and np.all(wh > 0)
+
+
+def test_relax_literal_mode_f64():
+    p = make_small(n=400, n_lab=5, d=6, c=4, s=4, seed=13)
+    ctx, X, H = context(p, "f64", 4)
+    w0 = np.full(p.n_pool, 1.0 / p.n_pool)
+    # fixed CG count: identical sequence of operations on both sides
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    info = ctx.relax_step(w, 5.0, 1e-3, 0.3, 77, 1, 4, 0.0, 60, project=False)
+    wr, ir = orc.relax_iteration(X, H, p.n_pool, w0, 5.0, 1e-3, 0.3, 77, 1, 4, 0.0, 60,
+                                 project=False)
+    assert info["cg_iters"] == ir["cg_iters"] == (60, 60)
+    assert_close(host(w), wr, 1e-8, "weights (literal, 60 CG iterations)")
+    # tolerance-based stop (kappa ~ 1e4 here): counts within 3, weights close
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    info = ctx.relax_step(w, 5.0, 1e-3, 0.3, 77, 1, 4, 1e-8, 3000, project=False)
+    wr, ir = orc.relax_iteration(X, H, p.n_pool, w0, 5.0, 1e-3, 0.3, 77, 1, 4, 1e-8, 3000,
+                                 project=False)
+    assert all(abs(a - b) <= 3 for a, b in zip(info["cg_iters"], ir["cg_iters"]))
+    assert relerr(host(w), wr) <= 1e-6
+
+
+def test_relax_not_spd_leaves_weights():
+    p = make_small(n=200, n_lab=0, d=5, c=3, s=2, seed=14)
+    H = p.H.copy()
+    H[:, 1] = 0.0
+    ctx = RelaxContext(dev(p.X, torch.float64), dev(H, torch.float64), p.n_pool, 2, "f64")
+    w0 = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    w = w0.clone()
+    with pytest.raises(FiralError) as ei:
+        ctx.relax_step(w, 5.0, 0.0, 0.3, 1, 1, 2, 1e-8, 100)
+    assert ei.value.code == _lib.ENOTSPD
+    assert torch.equal(w, w0)
+
+
+def test_relax_f32_gradient_error_fixed_iterations():
+    # FP32 against the FP64 oracle with the same probes and the same fixed CG count
+    p = make_problem(2, n=5000)
+    ctx, X, H = context(p, "f32", p.s)
+    beta0 = orc.default_beta0(p.n_pool, p.T)
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(w)
+    info = ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, 0.0, 15, project=True,
+                          g_out=g)
+    wr, ir = orc.relax_iteration(X, H, p.n_pool, np.full(p.n_pool, 1.0 / p.n_pool), p.b, p.lam,
+                                 beta0, p.probe_seed, 1, p.s, 0.0, 15, project=True)
+    assert info["cg_iters"] == (15, 15)
+    e = relerr(host(g), ir["g"])
+    assert e <= 1e-4, e
+    assert abs(info["f_hat"] - ir["f_hat"]) <= 1e-5 * abs(ir["f_hat"])
