@@ -34,7 +34,7 @@ int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, 
   } while (0)
 
 static void free_ctx(Ctx* x) {
-  void* bufs[] = {x->G, x->part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->V, x->W1, x->Y,
+  void* bufs[] = {x->G, x->part, x->fused_part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->V, x->W1, x->Y,
                   x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
                   x->redpart, x->status};
@@ -154,12 +154,21 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   x->col_parts = (int)std::max<int64_t>(1, std::min<int64_t>(d, cdiv(256, s_max)));
   x->red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n_pool, 256), 1024));
 
+  const char* unf = getenv("FIRAL_UNFUSED");
+  x->force_unfused = unf && atoi(unf) != 0;
+  x->fused_part_elems = 0;
+  for (int s = 1; s <= s_max; ++s) {
+    FusedPlan fp;
+    if (fused_plan(x, s, x->N, &fp)) x->fused_part_elems = std::max(x->fused_part_elems, fp.part_elems);
+  }
+
   const size_t es = x->esize;
   int rc = FIRAL_OK;
 #define ALLOC(ptr, bytes)                                          \
   if (rc == FIRAL_OK) rc = dmalloc((void**)&(ptr), (size_t)(bytes))
   ALLOC(x->G, 2 * rows * sc * es);
   ALLOC(x->part, (int64_t)x->max_splits * blk * es);
+  ALLOC(x->fused_part, x->fused_part_elems * 4);
   ALLOC(x->P, (int64_t)c * d * d * 8);
   ALLOC(x->Pinv, (int64_t)c * d * d * 8);
   ALLOC(x->syrk_part, (int64_t)x->syrk_splits * c * npairs * 256 * es);

@@ -70,6 +70,11 @@ struct Ctx {
   int max_splits;       // split-K partial buffers for the X^T G contraction
   void* part;           // max_splits * d * s_max * c elements
 
+  // fused FP32 product: per-row-range partials of the output block
+  void* fused_part;
+  int64_t fused_part_elems;
+  int force_unfused;    // FIRAL_UNFUSED=1: always take the general three-pass product
+
   // bf16x3 operands: hi/lo bf16 split of X (FP32 storage contexts only)
   void* Xhi;
   void* Xlo;
@@ -172,6 +177,22 @@ __device__ __forceinline__ double block_max(double v) {
   __syncthreads();
   return r;
 }
+
+// Tile plan of the fused FP32 product (hvp_fused.hip).
+struct FusedPlan {
+  void* kernel;
+  int D16, ncb, probes_per_tile, n_ctiles, n_splits;
+  int64_t rows_per_split;
+  int XS, XT, GT, CP;
+  size_t lds_bytes;
+  int64_t part_elems;   // n_splits * d * s * c
+};
+bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p);
+template <typename T>
+int reduce_parts_launch(const T* part, int64_t n, int P, double shift, const T* B, T* out,
+                        const int32_t* skip, hipStream_t st);
+int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_rows, double shift,
+                     const float* B, float* out, int s, const int32_t* skip, hipStream_t st);
 
 // ------------------------------------------------- host-side launchers
 // All enqueue on `st`; `skip` (device, may be null) makes every kernel return

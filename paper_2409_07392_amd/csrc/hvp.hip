@@ -157,7 +157,9 @@ __global__ __launch_bounds__(256) void k_gemm_xtg(const T* __restrict__ X, int d
       }
 }
 
-// out[e] = sum_p part[p][e] + shift * B[e], partials summed in FP64 in a fixed order.
+// out[e] = sum_p part[p][e] + shift * B[e] in FP64 with a fixed summation tree: a block
+// covers 32 outputs; its 8 groups of 32 threads each sum every 8th partial, then group 0
+// adds the 8 group sums in order.
 template <typename T>
 __global__ __launch_bounds__(256) void k_reduce_parts(const T* __restrict__ part, int64_t n,
                                                       int P, double shift,
@@ -165,12 +167,40 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const T* __restrict__ part
                                                       T* __restrict__ out,
                                                       const int32_t* skip) {
   if (skip && *skip) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  __shared__ double red[8][33];
+  const int el = threadIdx.x & 31, q = threadIdx.x >> 5;
+  const int64_t i = (int64_t)blockIdx.x * 32 + el;
   double acc = 0.0;
-  for (int p = 0; p < P; ++p) acc += (double)part[(int64_t)p * n + i];
-  out[i] = (T)(acc + shift * (double)B[i]);
+  if (i < n) {
+    int p = q;
+    for (; p + 24 < P; p += 32) {
+      const double v0 = (double)part[(int64_t)p * n + i];
+      const double v1 = (double)part[(int64_t)(p + 8) * n + i];
+      const double v2 = (double)part[(int64_t)(p + 16) * n + i];
+      const double v3 = (double)part[(int64_t)(p + 24) * n + i];
+      acc += (v0 + v1) + (v2 + v3);
+    }
+    for (; p < P; p += 8) acc += (double)part[(int64_t)p * n + i];
+  }
+  red[q][el] = acc;
+  __syncthreads();
+  if (q == 0 && i < n) {
+    double s = 0.0;
+#pragma unroll
+    for (int g = 0; g < 8; ++g) s += red[g][el];
+    out[i] = (T)(s + shift * (double)B[i]);
+  }
 }
+
+template <typename T>
+int reduce_parts_launch(const T* part, int64_t n, int P, double shift, const T* B, T* out,
+                        const int32_t* skip, hipStream_t st) {
+  k_reduce_parts<T><<<(unsigned)cdiv(n, 32), 256, 0, st>>>(part, n, P, shift, B, out, skip);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+template int reduce_parts_launch<float>(const float*, int64_t, int, double, const float*, float*,
+                                        const int32_t*, hipStream_t);
 
 template <typename T>
 static int launch_gemm_xb(const T* X, int d, const T* Bm, int SC, T* G, int64_t R,
@@ -214,14 +244,16 @@ static int hvp_t(Ctx* x, const double* omega, int64_t n_rows, double shift, cons
     k_gemm_xtg<T><<<grid, 256, 0, st>>>(X + r0 * d, d, G, SC, R, rps, part, n_out, r0 > 0, skip);
     FIRAL_LAUNCHED();
   }
-  k_reduce_parts<T><<<(unsigned)cdiv(n_out, 256), 256, 0, st>>>(part, n_out, n_rows > 0 ? S : 0,
-                                                                 shift, B, out, skip);
-  FIRAL_LAUNCHED();
-  return FIRAL_OK;
+  return reduce_parts_launch<T>(part, n_out, n_rows > 0 ? S : 0, shift, B, out, skip, st);
 }
 
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
                void* out, int s, const int32_t* skip, hipStream_t st) {
+  FusedPlan plan;
+  if (x->prec == FIRAL_F32 && !x->force_unfused && fused_plan(x, s, n_rows, &plan) &&
+      plan.part_elems <= x->fused_part_elems)
+    return hvp_fused_launch(x, plan, omega, n_rows, shift, (const float*)B, (float*)out, s, skip,
+                            st);
   if (x->prec == FIRAL_F64)
     return hvp_t<double>(x, omega, n_rows, shift, (const double*)B, (double*)out, s, skip, st);
   return hvp_t<float>(x, omega, n_rows, shift, (const float*)B, (float*)out, s, skip, st);

@@ -1,0 +1,300 @@
+// Fused FP32 Hessian product (Lemma 1): one kernel computes, for a tile of
+// whole probes and a range of rows, X^T [omega * Gamma(X V)] into a per-range
+// partial; a second pass sums the ranges in a fixed order and adds shift*V.
+//
+// Per workgroup (8 waves) and per chunk of 32 rows:
+//   1. the chunk of X is staged in LDS twice (row-major for the first
+//      contraction, transposed for the second) with h and omega;
+//   2. G = X_chunk V_tile on MFMA 16x16x4; each wave owns up to NCB 16-column
+//      blocks of the tile and keeps its slice of V in registers for the whole
+//      kernel (V is reused by every chunk);
+//   3. G goes to LDS column-major; one thread per (row, probe) forms
+//      alpha = G.h and G' = omega (G - alpha) h (steps 2-3 of the lemma);
+//   4. Out_tile += X_chunk^T G' on MFMA, accumulated in registers across all
+//      chunks of the range.
+// The contraction index of every MFMA is permuted within groups of 16 so that
+// each lane's four operands are contiguous in LDS (one 128-bit read).
+#include <algorithm>
+
+#include "common.h"
+
+namespace firal {
+
+namespace {
+
+constexpr int kNW = 8;        // waves per workgroup
+constexpr int kRC = 32;       // rows per chunk
+constexpr int kThreads = kNW * 64;
+
+struct FusedGeom {
+  int XS, XT, GT;             // LDS strides (floats) of Xs[r][a], XsT[a][r], GsT[col][r]
+  int DP, CP;                 // padded d and padded tile width
+  size_t lds_floats;
+};
+
+inline FusedGeom fused_geom(int D16, int C16, int c) {
+  FusedGeom g;
+  g.DP = 16 * D16;
+  g.CP = 16 * C16;
+  g.XS = g.DP + 4;
+  g.XT = kRC + 4;
+  g.GT = kRC + 4;
+  g.lds_floats = (size_t)kRC * g.XS + (size_t)g.DP * g.XT + (size_t)g.CP * g.GT +
+                 (size_t)kRC * c + kRC;
+  return g;
+}
+
+}  // namespace
+
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+template <int D16, int NCB>
+__global__ __launch_bounds__(kThreads) void k_hvp_fused(
+    const float* __restrict__ X, const float* __restrict__ H, const double* __restrict__ omega,
+    int64_t n_rows, int d, int c, int SC, const float* __restrict__ B, int probes_per_tile, int s,
+    int n_ctiles, int64_t rows_per_split, int n_splits, int XS, int XT, int GT, int CP,
+    float* __restrict__ part, const int32_t* skip) {
+  if (skip && *skip) return;
+  // XCD-aware placement: workgroups are dealt round-robin to the 8 XCDs, so the
+  // logical id packs the column tiles of one row range onto one XCD (shared L2).
+  const int nwg = gridDim.x;
+  const int lid = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+  if (lid >= n_splits * n_ctiles) return;
+  const int ct = lid % n_ctiles;
+  const int split = lid / n_ctiles;
+  const int j0 = ct * probes_per_tile;
+  const int sp = min(probes_per_tile, s - j0);
+  const int col0 = j0 * c;
+  const int CT = sp * c;
+  const int C16 = (CT + 15) >> 4;
+  const int64_t rb = (int64_t)split * rows_per_split;
+  const int64_t re = rb + rows_per_split < n_rows ? rb + rows_per_split : n_rows;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int DP = 16 * D16;
+
+  extern __shared__ float lds[];
+  float* Xs = lds;                       // [kRC][XS]
+  float* XsT = Xs + kRC * XS;            // [DP][XT]
+  float* GsT = XsT + DP * XT;            // [CP][GT]
+  float* Hs = GsT + CP * GT;             // [kRC][c]
+  float* Om = Hs + kRC * c;              // [kRC]
+
+  // V slice in registers: k index 16g + 4lk + t for "step" 4g + t.
+  float breg[NCB][4 * D16];
+#pragma unroll
+  for (int i = 0; i < NCB; ++i) {
+    const int cb = wave + kNW * i;
+    const int col = cb * 16 + li;
+    const bool ok = cb < C16 && col < CT;
+#pragma unroll
+    for (int g = 0; g < D16; ++g)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = 16 * g + 4 * lk + t;
+        breg[i][4 * g + t] = (ok && k < d) ? B[(int64_t)k * SC + col0 + col] : 0.f;
+      }
+  }
+  f32x4 acc2[NCB][D16];
+#pragma unroll
+  for (int i = 0; i < NCB; ++i)
+#pragma unroll
+    for (int ab = 0; ab < D16; ++ab) acc2[i][ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t r0 = rb; r0 < re; r0 += kRC) {
+    const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+    // 1. stage X, h, omega (zero padding outside the chunk and beyond d)
+    for (int e = tid; e < kRC * DP; e += kThreads) {
+      const int r = e / DP, a = e - r * DP;
+      const float v = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
+      Xs[r * XS + a] = v;
+      XsT[a * XT + r] = v;
+    }
+    for (int e = tid; e < kRC * c; e += kThreads) {
+      const int r = e / c;
+      Hs[e] = r < R ? H[r0 * c + e] : 0.f;
+    }
+    if (tid < kRC) Om[tid] = tid < R ? (omega ? (float)omega[r0 + tid] : 1.f) : 0.f;
+    __syncthreads();
+
+    // 2. G = X_chunk V_tile for this wave's column blocks
+    f32x4 acc1[NCB][2];
+#pragma unroll
+    for (int i = 0; i < NCB; ++i) {
+      acc1[i][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+      acc1[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int g = 0; g < D16; ++g) {
+      const f32x4v a0 = *(const f32x4v*)(Xs + li * XS + 16 * g + 4 * lk);
+      const f32x4v a1 = *(const f32x4v*)(Xs + (16 + li) * XS + 16 * g + 4 * lk);
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < NCB; ++i) {
+          acc1[i][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[t], breg[i][4 * g + t], acc1[i][0], 0, 0, 0);
+          acc1[i][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[t], breg[i][4 * g + t], acc1[i][1], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < NCB; ++i) {
+      const int cb = wave + kNW * i;
+      if (cb < C16) {
+        // lane holds G[rb*16 + 4lk + v][cb*16 + li], v = 0..3: contiguous in the column-major tile
+        *(f32x4v*)(GsT + (cb * 16 + li) * GT + 4 * lk) =
+            f32x4v{acc1[i][0][0], acc1[i][0][1], acc1[i][0][2], acc1[i][0][3]};
+        *(f32x4v*)(GsT + (cb * 16 + li) * GT + 16 + 4 * lk) =
+            f32x4v{acc1[i][1][0], acc1[i][1][1], acc1[i][1][2], acc1[i][1][3]};
+      }
+    }
+    __syncthreads();
+
+    // 3. Gamma apply per (row, probe), rows fastest across threads
+    for (int e = tid; e < kRC * sp; e += kThreads) {
+      const int r = e % kRC, jj = e / kRC;
+      float* g = GsT + (jj * c) * GT + r;
+      const float* h = Hs + r * c;
+      float alpha = 0.f;
+      for (int k = 0; k < c; ++k) alpha += g[k * GT] * h[k];
+      const float w = Om[r];
+      for (int k = 0; k < c; ++k) g[k * GT] = w * ((g[k * GT] - alpha) * h[k]);
+    }
+    __syncthreads();
+
+    // 4. Out += X_chunk^T G'
+#pragma unroll
+    for (int g2 = 0; g2 < kRC / 16; ++g2) {
+      f32x4v bq[NCB];
+#pragma unroll
+      for (int i = 0; i < NCB; ++i) {
+        const int cb = wave + kNW * i;
+        bq[i] = cb < C16 ? *(const f32x4v*)(GsT + (cb * 16 + li) * GT + 16 * g2 + 4 * lk)
+                         : f32x4v{0.f, 0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int ab = 0; ab < D16; ++ab) {
+        const f32x4v aq = *(const f32x4v*)(XsT + (ab * 16 + li) * XT + 16 * g2 + 4 * lk);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+          for (int i = 0; i < NCB; ++i)
+            acc2[i][ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[t], bq[i][t], acc2[i][ab], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+
+  float* out = part + (int64_t)split * d * SC;
+#pragma unroll
+  for (int i = 0; i < NCB; ++i) {
+    const int cb = wave + kNW * i;
+    const int col = cb * 16 + li;
+    if (cb < C16 && col < CT) {
+#pragma unroll
+      for (int ab = 0; ab < D16; ++ab)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = ab * 16 + 4 * lk + v;
+          if (a < d) out[(int64_t)a * SC + col0 + col] = acc2[i][ab][v];
+        }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+
+typedef void (*FusedKernel)(const float*, const float*, const double*, int64_t, int, int, int,
+                            const float*, int, int, int, int64_t, int, int, int, int, int, float*,
+                            const int32_t*);
+
+template <int D16>
+static FusedKernel pick_ncb(int ncb) {
+  if (ncb == 1) return k_hvp_fused<D16, 1>;
+  if (ncb == 2) return k_hvp_fused<D16, 2>;
+  return nullptr;
+}
+
+static FusedKernel pick(int D16, int ncb) {
+  switch (D16) {
+    case 1: return pick_ncb<1>(ncb);
+    case 2: return pick_ncb<2>(ncb);
+    case 3: return pick_ncb<3>(ncb);
+    case 4: return pick_ncb<4>(ncb);
+    case 5: return pick_ncb<5>(ncb);
+    case 6: return pick_ncb<6>(ncb);
+    case 7: return pick_ncb<7>(ncb);
+    case 8: return pick_ncb<8>(ncb);
+    case 9: return ncb == 1 ? k_hvp_fused<9, 1> : nullptr;
+    case 10: return ncb == 1 ? k_hvp_fused<10, 1> : nullptr;
+    case 11: return ncb == 1 ? k_hvp_fused<11, 1> : nullptr;
+    case 12: return ncb == 1 ? k_hvp_fused<12, 1> : nullptr;
+    case 13: return ncb == 1 ? k_hvp_fused<13, 1> : nullptr;
+    case 14: return ncb == 1 ? k_hvp_fused<14, 1> : nullptr;
+    case 15: return ncb == 1 ? k_hvp_fused<15, 1> : nullptr;
+    case 16: return ncb == 1 ? k_hvp_fused<16, 1> : nullptr;
+    default: return nullptr;
+  }
+}
+
+// Tile plan of the fused product for a call with s probes (FP32 contexts only).
+// Returns false when the shape is outside what the fused kernel holds in registers/LDS.
+bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p) {
+  if (x->prec == FIRAL_F64 || n_rows <= 0) return false;
+  const int d = x->d, c = x->c;
+  const int D16 = (d + 15) / 16;
+  if (D16 > 16) return false;
+  const int max_ncb = D16 <= 8 ? 2 : 1;
+  // widest tile of whole probes whose 16-column blocks fit max_ncb per wave
+  const int max_cols = max_ncb * kNW * 16;
+  int pp = std::min(s, max_cols / c);
+  if (pp < 1) return false;
+  const int n_ct = (s + pp - 1) / pp;
+  pp = (s + n_ct - 1) / n_ct;            // balance the tiles
+  const int C16 = (pp * c + 15) / 16;
+  const int ncb = (C16 + kNW - 1) / kNW;
+  FusedGeom g = fused_geom(D16, C16, c);
+  if (g.lds_floats * 4 > 160 * 1024) return false;
+  const int64_t chunks = (n_rows + kRC - 1) / kRC;
+  const int target_wgs = 256;
+  int64_t splits = std::max<int64_t>(1, std::min<int64_t>(chunks, target_wgs / n_ct));
+  const int64_t rps = ((n_rows + splits - 1) / splits + kRC - 1) / kRC * kRC;
+  splits = (n_rows + rps - 1) / rps;
+  p->part_elems = splits * (int64_t)d * s * c;
+  p->kernel = (void*)pick(D16, ncb);
+  if (!p->kernel) return false;
+  p->D16 = D16;
+  p->ncb = ncb;
+  p->probes_per_tile = pp;
+  p->n_ctiles = n_ct;
+  p->rows_per_split = rps;
+  p->n_splits = (int)splits;
+  p->XS = g.XS;
+  p->XT = g.XT;
+  p->GT = g.GT;
+  p->CP = g.CP;
+  p->lds_bytes = g.lds_floats * 4;
+  return true;
+}
+
+int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_rows, double shift,
+                     const float* B, float* out, int s, const int32_t* skip, hipStream_t st) {
+  FusedKernel k = (FusedKernel)p.kernel;
+  static bool attr_set[17][3] = {};
+  if (!attr_set[p.D16][p.ncb]) {
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  160 * 1024));
+    attr_set[p.D16][p.ncb] = true;
+  }
+  const int SC = s * x->c;
+  const int nwg = (int)(((int64_t)p.n_splits * p.n_ctiles + 7) / 8 * 8);
+  float* part = (float*)x->fused_part;
+  k<<<nwg, kThreads, p.lds_bytes, st>>>((const float*)x->X, (const float*)x->H, omega, n_rows,
+                                        x->d, x->c, SC, B, p.probes_per_tile, s, p.n_ctiles,
+                                        p.rows_per_split, p.n_splits, p.XS, p.XT, p.GT, p.CP,
+                                        part, skip);
+  FIRAL_LAUNCHED();
+  return reduce_parts_launch<float>(part, (int64_t)x->d * SC, p.n_splits, shift, B, out, skip, st);
+}
+
+}  // namespace firal

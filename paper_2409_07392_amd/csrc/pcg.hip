@@ -80,8 +80,11 @@ __global__ __launch_bounds__(256) void k_classmean(const T* __restrict__ R, doub
   mean[idx] = m / c;
 }
 
-// Z[a,j,k] = sum_b Pinv_k[b][a] (R[b,j,k] - mean[b,j]); Pinv_k is symmetric, so reading
-// its column makes consecutive lanes (consecutive a) read consecutive addresses.
+// Z[a,j,k] = sum_b Pinv_k[b][a] (R[b,j,k] - mean[b,j]) for the probes j0..j0+JT-1 of one
+// class k per block.  The JT right-hand sides are staged in LDS; Pinv_k is symmetric, so its
+// column is read, and consecutive threads (consecutive a) read consecutive addresses.  The
+// dot product over b is split in four interleaved partial sums (fixed order).
+constexpr int kApplyJT = 4;
 template <typename T>
 __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
                                                 const T* __restrict__ R,
@@ -89,21 +92,33 @@ __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
                                                 T* __restrict__ Z, int d, int s, int c,
                                                 const int32_t* skip) {
   if (skip && *skip) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)d * s * c) return;
-  const int a = (int)(idx % d);
-  const int64_t kj = idx / d;
-  const int j = (int)(kj % s);
-  const int k = (int)(kj / s);
-  const double* Pk = Pinv + (int64_t)k * d * d;
+  extern __shared__ double rs[];   // [kApplyJT][d]
+  const int k = blockIdx.x;
+  const int j0 = blockIdx.y * kApplyJT;
+  const int jn = min(kApplyJT, s - j0);
   const int64_t sc = (int64_t)s * c;
-  double acc = 0.0;
-  for (int b = 0; b < d; ++b) {
-    double rv = (double)R[b * sc + (int64_t)j * c + k];
-    if (mean) rv -= mean[(int64_t)b * s + j];
-    acc += Pk[(int64_t)b * d + a] * rv;
+  for (int e = threadIdx.x; e < jn * d; e += blockDim.x) {
+    const int jj = e / d, b = e - jj * d;
+    double rv = (double)R[b * sc + (int64_t)(j0 + jj) * c + k];
+    if (mean) rv -= mean[(int64_t)b * s + j0 + jj];
+    rs[jj * d + b] = rv;
   }
-  Z[a * sc + (int64_t)j * c + k] = (T)acc;
+  __syncthreads();
+  const double* Pk = Pinv + (int64_t)k * d * d;
+  for (int e = threadIdx.x; e < jn * d; e += blockDim.x) {
+    const int jj = e / d, a = e - jj * d;
+    const double* r = rs + jj * d;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = 0;
+    for (; b + 3 < d; b += 4) {
+      s0 += Pk[(int64_t)b * d + a] * r[b];
+      s1 += Pk[(int64_t)(b + 1) * d + a] * r[b + 1];
+      s2 += Pk[(int64_t)(b + 2) * d + a] * r[b + 2];
+      s3 += Pk[(int64_t)(b + 3) * d + a] * r[b + 3];
+    }
+    for (; b < d; ++b) s0 += Pk[(int64_t)b * d + a] * r[b];
+    Z[a * sc + (int64_t)(j0 + jj) * c + k] = (T)((s0 + s1) + (s2 + s3));
+  }
 }
 
 // ------------------------------------------------------------ scalars
@@ -242,8 +257,8 @@ static int apply_t(Ctx* x, const double* Pinv, const T* r, T* z, int s, bool pro
     k_classmean<T><<<(unsigned)cdiv(nds, 256), 256, 0, st>>>(r, x->mean, d, s, c, skip);
     FIRAL_LAUNCHED();
   }
-  k_papply<T><<<(unsigned)cdiv(nds * c, 256), 256, 0, st>>>(Pinv, r, project ? x->mean : nullptr,
-                                                             z, d, s, c, skip);
+  k_papply<T><<<dim3(c, (unsigned)cdiv(s, kApplyJT)), 256, kApplyJT * d * sizeof(double), st>>>(
+      Pinv, r, project ? x->mean : nullptr, z, d, s, c, skip);
   FIRAL_LAUNCHED();
   if (project) {
     k_project<T><<<(unsigned)cdiv(nds, 256), 256, 0, st>>>(z, z, d, s, c, skip);

@@ -152,6 +152,111 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ L,
   }
 }
 
+// Cholesky factor and inverse of block k in one pass, the whole block held in registers.
+// The symmetric sweep operator on pivot j maps a -> a - a_{:j} a_{j:} / a_jj off row/column j,
+// a_{j:} / a_jj on them and -1/a_jj on the pivot; sweeping every pivot of an SPD matrix leaves
+// -P^-1.  Before pivot j is swept its unswept column is the Schur complement, so
+// L[i][j] = a_ij / sqrt(a_jj) (i >= j) is the Cholesky factor, and a_jj <= 0 means P is not SPD.
+// Thread (ty, tx) of a TT x TT grid owns rows ty + TT u and columns tx + TT v (u, v < TB).
+// L is written over P (P is read completely before the first pivot).
+template <int TT, int TB>
+__global__ __launch_bounds__(TT* TT) void k_sweep(double* __restrict__ P, double* __restrict__ Pinv,
+                                                  int d, int32_t* bad) {
+  const int kb = blockIdx.x;
+  double* A0 = P + (int64_t)kb * d * d;
+  double* Y = Pinv + (int64_t)kb * d * d;
+  const int ty = threadIdx.x / TT, tx = threadIdx.x % TT;
+  __shared__ double prow[TT * TB];
+  double a[TB][TB];
+#pragma unroll
+  for (int u = 0; u < TB; ++u)
+#pragma unroll
+    for (int v = 0; v < TB; ++v) {
+      const int i = ty + TT * u, q = tx + TT * v;
+      a[u][v] = (i < d && q < d) ? A0[(int64_t)i * d + q] : 0.0;
+    }
+  __syncthreads();
+  for (int j = 0; j < d; ++j) {
+    const int uj = j / TT;
+    if (ty == j % TT) {
+#pragma unroll
+      for (int u = 0; u < TB; ++u)
+        if (u == uj) {
+#pragma unroll
+          for (int v = 0; v < TB; ++v) prow[tx + TT * v] = a[u][v];
+        }
+    }
+    __syncthreads();
+    const double piv = prow[j];
+    if (!(piv > 0.0)) {
+      if (threadIdx.x == 0) atomicMin(bad, kb);
+      return;
+    }
+    const double ip = 1.0 / piv;
+    if (tx == 0) {
+      const double sq = sqrt(piv);
+#pragma unroll
+      for (int u = 0; u < TB; ++u) {
+        const int i = ty + TT * u;
+        if (i >= j && i < d) A0[(int64_t)i * d + j] = i == j ? sq : prow[i] / sq;
+      }
+    }
+    double pr[TB], pc[TB];
+#pragma unroll
+    for (int u = 0; u < TB; ++u) pr[u] = prow[ty + TT * u];
+#pragma unroll
+    for (int v = 0; v < TB; ++v) pc[v] = prow[tx + TT * v];
+#pragma unroll
+    for (int u = 0; u < TB; ++u)
+#pragma unroll
+      for (int v = 0; v < TB; ++v) {
+        const int i = ty + TT * u, q = tx + TT * v;
+        const double upd = a[u][v] - pr[u] * pc[v] * ip;
+        const double onrow = (i == j) ? pc[v] * ip : pr[u] * ip;
+        a[u][v] = (i == j && q == j) ? -ip : ((i == j || q == j) ? onrow : upd);
+      }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < TB; ++u)
+#pragma unroll
+    for (int v = 0; v < TB; ++v) {
+      const int i = ty + TT * u, q = tx + TT * v;
+      if (i < d && q < d) {
+        Y[(int64_t)i * d + q] = -a[u][v];
+        if (q > i) A0[(int64_t)i * d + q] = 0.0;
+      }
+    }
+}
+
+typedef void (*SweepKernel)(double*, double*, int, int32_t*);
+
+static SweepKernel pick_sweep(int d, int* threads) {
+  if (d <= 128) {
+    *threads = 256;
+    switch ((d + 15) / 16) {
+      case 1: return k_sweep<16, 1>;
+      case 2: return k_sweep<16, 2>;
+      case 3: return k_sweep<16, 3>;
+      case 4: return k_sweep<16, 4>;
+      case 5: return k_sweep<16, 5>;
+      case 6: return k_sweep<16, 6>;
+      case 7: return k_sweep<16, 7>;
+      default: return k_sweep<16, 8>;
+    }
+  }
+  if (d <= 256) {
+    *threads = 1024;
+    switch ((d + 31) / 32) {
+      case 5: return k_sweep<32, 5>;
+      case 6: return k_sweep<32, 6>;
+      case 7: return k_sweep<32, 7>;
+      default: return k_sweep<32, 8>;
+    }
+  }
+  return nullptr;
+}
+
 __global__ void k_bad_reset(Status* st) { st->bad_block = INT_MAX; }
 
 template <typename T>
@@ -171,10 +276,17 @@ static int precond_t(Ctx* x, const double* omega, double shift, hipStream_t st) 
   k_syrk_reduce<T><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((const T*)x->syrk_part, S, c, d,
                                                            npairs, shift, x->P);
   FIRAL_LAUNCHED();
-  k_chol<<<c, 256, 0, st>>>(x->P, d, &x->status->bad_block);
-  FIRAL_LAUNCHED();
-  k_chol_inv<<<c, 256, 0, st>>>(x->P, x->Pinv, d, &x->status->bad_block);
-  FIRAL_LAUNCHED();
+  int threads = 0;
+  SweepKernel sw = pick_sweep(d, &threads);
+  if (sw) {
+    sw<<<c, threads, 0, st>>>(x->P, x->Pinv, d, &x->status->bad_block);
+    FIRAL_LAUNCHED();
+  } else {
+    k_chol<<<c, 256, 0, st>>>(x->P, d, &x->status->bad_block);
+    FIRAL_LAUNCHED();
+    k_chol_inv<<<c, 256, 0, st>>>(x->P, x->Pinv, d, &x->status->bad_block);
+    FIRAL_LAUNCHED();
+  }
   return FIRAL_OK;
 }
 
