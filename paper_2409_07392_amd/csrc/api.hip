@@ -37,7 +37,7 @@ static void free_ctx(Ctx* x) {
   void* bufs[] = {x->G, x->part, x->fused_part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->V, x->W1, x->Y,
                   x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
-                  x->redpart, x->status};
+                  x->redpart, x->status, x->counter};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (x->status_host) (void)hipHostFree(x->status_host);
@@ -191,9 +191,10 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   ALLOC(x->alpha, s_max * 8);
   ALLOC(x->beta, s_max * 8);
   ALLOC(x->relres, s_max * 8);
-  ALLOC(x->done, s_max * 4);
+  ALLOC(x->done, 2 * s_max * 4);   // two flag buffers (column-local CG)
   ALLOC(x->redpart, (3 * (int64_t)x->red_blocks + 1) * 8);
   ALLOC(x->status, sizeof(Status));
+  ALLOC(x->counter, sizeof(int32_t));
 #undef ALLOC
   if (rc == FIRAL_OK) {
     hipError_t he = hipHostMalloc((void**)&x->status_host, sizeof(Status), hipHostMallocDefault);
@@ -205,6 +206,7 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   if (rc == FIRAL_OK) {
     hipStream_t st = (hipStream_t)stream;
     if (hipMemsetAsync(x->status, 0, sizeof(Status), st) != hipSuccess ||
+        hipMemsetAsync(x->counter, 0, sizeof(int32_t), st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       set_error("status initialisation failed");
       rc = FIRAL_EHIP;
@@ -233,7 +235,7 @@ int firal_hvp(firal_ctx ctx, const double* omega, int64_t n_rows, double shift, 
   FIRAL_REQ(B != out, "out must not alias B");
   FIRAL_REQ(n_rows >= 0 && n_rows <= x->N, "n_rows = %lld outside [0, %lld]", (long long)n_rows,
             (long long)x->N);
-  return hvp_launch(x, omega, n_rows, shift, B, out, s, nullptr, (hipStream_t)stream);
+  return hvp_launch(x, omega, n_rows, shift, B, out, s, skip_none(), (hipStream_t)stream);
 }
 
 int firal_build_precond(firal_ctx ctx, const double* omega, double shift, double* L, double* Pinv,

@@ -17,6 +17,7 @@ void set_error(const char* fmt, ...);
   do {                                                                          \
     hipError_t e_ = (x);                                                        \
     if (e_ != hipSuccess) {                                                     \
+      (void)hipGetLastError(); /* do not leave the error for a later check */   \
       ::firal::set_error("%s failed: %s", #x, hipGetErrorString(e_));           \
       return FIRAL_EHIP;                                                        \
     }                                                                           \
@@ -105,6 +106,7 @@ struct Ctx {
   int red_blocks;       // blocks of the n_pool reductions
   double* redpart;      // 3 * red_blocks
 
+  int32_t* counter;     // device: arrival counter of the column-local CG kernels (kept at 0)
   Status* status;       // device
   Status* status_host;  // pinned host mirror
 };
@@ -178,6 +180,29 @@ __device__ __forceinline__ double block_max(double v) {
   return r;
 }
 
+// ---------------------------------------------------------- skip rule
+// Kernels of a PCG loop return at once when there is nothing left to do, so the host can
+// queue iterations ahead of its convergence test.  `flag`: skip when *flag != 0;
+// `flags`: skip when flags[0..n) are all nonzero (the per-column convergence flags of the
+// previous iteration).  skip_now must be reached by every thread of the block.
+struct Skip {
+  const int32_t* flag;
+  const int32_t* flags;
+  int n;
+};
+__host__ __device__ inline Skip skip_none() { return Skip{nullptr, nullptr, 0}; }
+__host__ __device__ inline Skip skip_flag(const int32_t* f) { return Skip{f, nullptr, 0}; }
+__host__ __device__ inline Skip skip_all(const int32_t* f, int n) { return Skip{nullptr, f, n}; }
+__device__ __forceinline__ bool skip_now(const Skip& k) {
+  if (k.flag) return *k.flag != 0;
+  if (k.flags) {
+    int ok = 1;
+    for (int j = threadIdx.x; j < k.n; j += blockDim.x) ok &= k.flags[j] != 0;
+    return __syncthreads_and(ok) != 0;
+  }
+  return false;
+}
+
 // Tile plan of the fused FP32 product (hvp_fused.hip).
 struct FusedPlan {
   void* kernel;
@@ -190,23 +215,22 @@ struct FusedPlan {
 bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p);
 template <typename T>
 int reduce_parts_launch(const T* part, int64_t n, int P, double shift, const T* B, T* out,
-                        const int32_t* skip, hipStream_t st);
+                        Skip skip, hipStream_t st);
 int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_rows, double shift,
-                     const float* B, float* out, int s, const int32_t* skip, hipStream_t st);
+                     const float* B, float* out, int s, Skip skip, hipStream_t st);
 
 // ------------------------------------------------- host-side launchers
-// All enqueue on `st`; `skip` (device, may be null) makes every kernel return
-// at once when *skip != 0, so a PCG loop can run ahead of its convergence test.
+// All enqueue on `st`; `skip` (see Skip) makes every kernel of the call return at once.
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
-               void* out, int s, const int32_t* skip, hipStream_t st);
+               void* out, int s, Skip skip, hipStream_t st);
 int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st);
 int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,
                void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
                hipStream_t st);
 int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st);
 int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st);
-int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part,
-                  const int32_t* skip, hipStream_t st);
+int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, Skip skip,
+                  hipStream_t st);
 int bf16_split_launch(Ctx* x, hipStream_t st);
 
 }  // namespace firal

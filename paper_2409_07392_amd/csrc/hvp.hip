@@ -23,8 +23,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_xb(const T* __restrict__ X, int d,
                                                  const T* __restrict__ Bm, int SC,
                                                  T* __restrict__ G, int64_t R,
-                                                 const int32_t* skip) {
-  if (skip && *skip) return;
+                                                 Skip skip) {
+  if (skip_now(skip)) return;
   __shared__ T As[TK][TM + 4];
   __shared__ T Bs[TK][TN + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -81,8 +81,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_gamma(T* __restrict__ G, int64_t R, int s, int c,
                                                const T* __restrict__ H,
                                                const double* __restrict__ omega,
-                                               const int32_t* skip) {
-  if (skip && *skip) return;
+                                               Skip skip) {
+  if (skip_now(skip)) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= R * s) return;
   const int64_t r = idx / s;
@@ -101,8 +101,8 @@ __global__ __launch_bounds__(256) void k_gemm_xtg(const T* __restrict__ X, int d
                                                   const T* __restrict__ G, int SC, int64_t R,
                                                   int64_t rows_per_split, T* __restrict__ part,
                                                   int64_t part_stride, int accumulate,
-                                                  const int32_t* skip) {
-  if (skip && *skip) return;
+                                                  Skip skip) {
+  if (skip_now(skip)) return;
   __shared__ T As[TK][TM + 4];
   __shared__ T Bs[TK][TN + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -165,8 +165,8 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const T* __restrict__ part
                                                       int P, double shift,
                                                       const T* __restrict__ B,
                                                       T* __restrict__ out,
-                                                      const int32_t* skip) {
-  if (skip && *skip) return;
+                                                      Skip skip) {
+  if (skip_now(skip)) return;
   __shared__ double red[8][33];
   const int el = threadIdx.x & 31, q = threadIdx.x >> 5;
   const int64_t i = (int64_t)blockIdx.x * 32 + el;
@@ -194,17 +194,17 @@ __global__ __launch_bounds__(256) void k_reduce_parts(const T* __restrict__ part
 
 template <typename T>
 int reduce_parts_launch(const T* part, int64_t n, int P, double shift, const T* B, T* out,
-                        const int32_t* skip, hipStream_t st) {
+                        Skip skip, hipStream_t st) {
   k_reduce_parts<T><<<(unsigned)cdiv(n, 32), 256, 0, st>>>(part, n, P, shift, B, out, skip);
   FIRAL_LAUNCHED();
   return FIRAL_OK;
 }
 template int reduce_parts_launch<float>(const float*, int64_t, int, double, const float*, float*,
-                                        const int32_t*, hipStream_t);
+                                        Skip, hipStream_t);
 
 template <typename T>
 static int launch_gemm_xb(const T* X, int d, const T* Bm, int SC, T* G, int64_t R,
-                          const int32_t* skip, hipStream_t st) {
+                          Skip skip, hipStream_t st) {
   dim3 grid((unsigned)cdiv(SC, TN), (unsigned)cdiv(R, TM));
   k_gemm_xb<T><<<grid, 256, 0, st>>>(X, d, Bm, SC, G, R, skip);
   FIRAL_LAUNCHED();
@@ -212,7 +212,7 @@ static int launch_gemm_xb(const T* X, int d, const T* Bm, int SC, T* G, int64_t 
 }
 
 int gemm_xb_launch(Ctx* x, const void* Xrows, const void* Bm, int SC, void* G, int64_t R,
-                   const int32_t* skip, hipStream_t st) {
+                   Skip skip, hipStream_t st) {
   if (x->prec == FIRAL_F64)
     return launch_gemm_xb<double>((const double*)Xrows, x->d, (const double*)Bm, SC,
                                   (double*)G, R, skip, st);
@@ -222,7 +222,7 @@ int gemm_xb_launch(Ctx* x, const void* Xrows, const void* Bm, int SC, void* G, i
 
 template <typename T>
 static int hvp_t(Ctx* x, const double* omega, int64_t n_rows, double shift, const T* B, T* out,
-                 int s, const int32_t* skip, hipStream_t st) {
+                 int s, Skip skip, hipStream_t st) {
   const int d = x->d, c = x->c;
   const int SC = s * c;
   const T* X = (const T*)x->X;
@@ -248,7 +248,7 @@ static int hvp_t(Ctx* x, const double* omega, int64_t n_rows, double shift, cons
 }
 
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
-               void* out, int s, const int32_t* skip, hipStream_t st) {
+               void* out, int s, Skip skip, hipStream_t st) {
   FusedPlan plan;
   if (x->prec == FIRAL_F32 && !x->force_unfused && fused_plan(x, s, n_rows, &plan) &&
       plan.part_elems <= x->fused_part_elems)

@@ -53,8 +53,8 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
     const float* __restrict__ X, const float* __restrict__ H, const double* __restrict__ omega,
     int64_t n_rows, int d, int c, int SC, const float* __restrict__ B, int probes_per_tile, int s,
     int n_ctiles, int64_t rows_per_split, int n_splits, int XS, int XT, int GT, int CP,
-    float* __restrict__ part, const int32_t* skip) {
-  if (skip && *skip) return;
+    float* __restrict__ part, Skip skip) {
+  if (skip_now(skip)) return;
   // XCD-aware placement: workgroups are dealt round-robin to the 8 XCDs, so the
   // logical id packs the column tiles of one row range onto one XCD (shared L2).
   const int nwg = gridDim.x;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
 
 typedef void (*FusedKernel)(const float*, const float*, const double*, int64_t, int, int, int,
                             const float*, int, int, int, int64_t, int, int, int, int, int, float*,
-                            const int32_t*);
+                            Skip);
 
 template <int D16>
 static FusedKernel pick_ncb(int ncb) {
@@ -254,7 +254,7 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p) {
   const int C16 = (pp * c + 15) / 16;
   const int ncb = (C16 + kNW - 1) / kNW;
   FusedGeom g = fused_geom(D16, C16, c);
-  if (g.lds_floats * 4 > 160 * 1024) return false;
+  if (g.lds_floats * 4 > 156 * 1024) return false;   // static LDS of the kernel needs a little
   const int64_t chunks = (n_rows + kRC - 1) / kRC;
   const int target_wgs = 256;
   int64_t splits = std::max<int64_t>(1, std::min<int64_t>(chunks, target_wgs / n_ct));
@@ -278,13 +278,13 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p) {
 }
 
 int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_rows, double shift,
-                     const float* B, float* out, int s, const int32_t* skip, hipStream_t st) {
+                     const float* B, float* out, int s, Skip skip, hipStream_t st) {
   FusedKernel k = (FusedKernel)p.kernel;
-  static bool attr_set[17][3] = {};
-  if (!attr_set[p.D16][p.ncb]) {
+  static size_t attr_set[17][3] = {};   // largest dynamic LDS size granted per instantiation
+  if (p.lds_bytes > 64 * 1024 && attr_set[p.D16][p.ncb] < p.lds_bytes) {
     FIRAL_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  160 * 1024));
-    attr_set[p.D16][p.ncb] = true;
+                                  (int)p.lds_bytes));
+    attr_set[p.D16][p.ncb] = p.lds_bytes;
   }
   const int SC = s * x->c;
   const int nwg = (int)(((int64_t)p.n_splits * p.n_ctiles + 7) / 8 * 8);

@@ -21,8 +21,8 @@ namespace firal {
 template <typename T>
 __global__ __launch_bounds__(256) void k_coldot(const T* __restrict__ A, const T* __restrict__ B,
                                                 int d, int s, int c, int P,
-                                                double* __restrict__ part, const int32_t* skip) {
-  if (skip && *skip) return;
+                                                double* __restrict__ part, Skip skip) {
+  if (skip_now(skip)) return;
   const int j = blockIdx.x, p = blockIdx.y;
   const int per = (d + P - 1) / P;
   const int a0 = p * per;
@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void k_coldot(const T* __restrict__ A, const T
   if (threadIdx.x == 0) part[j * P + p] = acc;
 }
 
-int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, const int32_t* skip,
+int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, Skip skip,
                   hipStream_t st) {
   dim3 grid(s, x->col_parts);
   if (x->prec == FIRAL_F64)
@@ -55,8 +55,8 @@ int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, con
 // Y may alias R.
 template <typename T>
 __global__ __launch_bounds__(256) void k_project(const T* R, T* Y, int d, int s, int c,
-                                                 const int32_t* skip) {
-  if (skip && *skip) return;
+                                                 Skip skip) {
+  if (skip_now(skip)) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)d * s) return;
   const T* r = R + idx * c;
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(256) void k_project(const T* R, T* Y, int d, int s,
 // mean[a*s + j] = mean_k R[a,j,k]
 template <typename T>
 __global__ __launch_bounds__(256) void k_classmean(const T* __restrict__ R, double* __restrict__ mean,
-                                                   int d, int s, int c, const int32_t* skip) {
-  if (skip && *skip) return;
+                                                   int d, int s, int c, Skip skip) {
+  if (skip_now(skip)) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)d * s) return;
   const T* r = R + idx * c;
@@ -90,8 +90,8 @@ __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
                                                 const T* __restrict__ R,
                                                 const double* __restrict__ mean,
                                                 T* __restrict__ Z, int d, int s, int c,
-                                                const int32_t* skip) {
-  if (skip && *skip) return;
+                                                Skip skip) {
+  if (skip_now(skip)) return;
   extern __shared__ double rs[];   // [kApplyJT][d]
   const int k = blockIdx.x;
   const int j0 = blockIdx.y * kApplyJT;
@@ -124,9 +124,14 @@ __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
 // ------------------------------------------------------------ scalars
 
 __device__ __forceinline__ double sum_parts(const double* part, int j, int P) {
-  double v = 0.0;
-  for (int p = 0; p < P; ++p) v += part[j * P + p];
-  return v;
+  // independent loads first, then the fixed-order sum
+  double v[64];
+  const int m = P < 64 ? P : 64;
+  for (int p = 0; p < m; ++p) v[p] = part[j * P + p];
+  double acc = 0.0;
+  for (int p = 0; p < m; ++p) acc += v[p];
+  for (int p = m; p < P; ++p) acc += part[j * P + p];
+  return acc;
 }
 
 __global__ __launch_bounds__(64) void k_cg_init(const double* part_bb, const double* part_rz, int s,
@@ -182,8 +187,8 @@ __global__ __launch_bounds__(256) void k_cg_update(T* __restrict__ xv, T* __rest
                                                    const T* __restrict__ p,
                                                    const T* __restrict__ q,
                                                    const double* __restrict__ alpha, int64_t n,
-                                                   int s, int c, const int32_t* skip) {
-  if (*skip) return;
+                                                   int s, int c, Skip skip) {
+  if (skip_now(skip)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int j = (int)((i / c) % s);
@@ -233,8 +238,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cg_pupdate(T* __restrict__ p, const T* __restrict__ z,
                                                     const double* __restrict__ beta,
                                                     const int32_t* __restrict__ done, int64_t n,
-                                                    int s, int c, const int32_t* skip) {
-  if (*skip) return;
+                                                    int s, int c, Skip skip) {
+  if (skip_now(skip)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int j = (int)((i / c) % s);
@@ -247,10 +252,244 @@ __global__ void k_cg_finish(Status* st, int slot) {
   if (st->breakdown || !st->all_done) st->converged = 0;
 }
 
+// ---------------------------------------------------- column-local CG step
+// Every vector operation of a CG iteration except the Hessian product acts on one probe
+// column j alone: alpha_j needs <p_j, q_j>, the residual test, the projection (a mean over
+// the classes of each feature) and z_j = M^-1 r_j (one d x d product per class) stay inside
+// the column.  One block per column does the whole step with r_j and z_j in LDS (FP64), so a
+// CG iteration is the product plus this kernel.  The last block to finish (counter) folds
+// the per-column flags into the status.  Used when 2 d c doubles fit in LDS.
+
+constexpr int kColThreads = 1024;
+constexpr int kColSplit = 4;     // each output of the apply is summed in 4 pieces over b
+
+__device__ __forceinline__ double block_sum_col(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < kColThreads / 64; ++i) r += red[i];
+  return r;
+}
+
+// z = M^-1 rs (both [c][d] in LDS, FP64), optionally projected before and after.
+// zp: [kColSplit][c*d] LDS scratch for the partial dot products.
+__device__ void col_apply(const double* __restrict__ Pinv, double* rs, double* zs, double* zp,
+                          int d, int c, bool project) {
+  const int n = d * c;
+  if (project) {
+    for (int a = threadIdx.x; a < d; a += blockDim.x) {
+      double m = 0.0;
+      for (int k = 0; k < c; ++k) m += rs[k * d + a];
+      m /= c;
+      for (int k = 0; k < c; ++k) rs[k * d + a] -= m;
+    }
+    __syncthreads();
+  }
+  const int piece = (d + kColSplit - 1) / kColSplit;
+  for (int w = threadIdx.x; w < kColSplit * n; w += blockDim.x) {
+    const int q = w / n, e = w - q * n;
+    const int k = e / d, a = e - k * d;
+    const double* Pk = Pinv + (int64_t)k * d * d + a;
+    const double* rk = rs + k * d;
+    const int b0 = q * piece, b1 = min(d, b0 + piece);
+    double acc = 0.0;
+    for (int bb = b0; bb < b1; bb += 16) {
+      // sixteen independent loads in flight before the products
+      double pv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) pv[u] = bb + u < b1 ? Pk[(int64_t)(bb + u) * d] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (bb + u < b1) acc += pv[u] * rk[bb + u];
+    }
+    zp[w] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    double z = 0.0;
+#pragma unroll
+    for (int q = 0; q < kColSplit; ++q) z += zp[q * n + e];
+    zs[e] = z;
+  }
+  __syncthreads();
+  if (project) {
+    for (int a = threadIdx.x; a < d; a += blockDim.x) {
+      double m = 0.0;
+      for (int k = 0; k < c; ++k) m += zs[k * d + a];
+      m /= c;
+      for (int k = 0; k < c; ++k) zs[k * d + a] -= m;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kColThreads) void k_cg_col_init(const T* __restrict__ B, T* __restrict__ xv,
+                                                     T* __restrict__ r, T* __restrict__ p,
+                                                     const double* __restrict__ Pinv, int d, int s,
+                                                     int c, int project, double* rho,
+                                                     double* bnorm, double* relres, int32_t* done,
+                                                     Status* st) {
+  extern __shared__ double sh[];
+  __shared__ double red[kColThreads / 64];
+  double* rs = sh;               // [c][d]
+  double* zs = sh + d * c;       // [c][d]
+  double* zp = zs + d * c;       // [kColSplit][c][d]
+  const int j = blockIdx.x, n = d * c;
+  const int64_t sc = (int64_t)s * c;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int k = e / d, a = e - k * d;
+    rs[e] = (double)B[a * sc + (int64_t)j * c + k];
+  }
+  __syncthreads();
+  if (project) {
+    for (int a = threadIdx.x; a < d; a += blockDim.x) {
+      double m = 0.0;
+      for (int k = 0; k < c; ++k) m += rs[k * d + a];
+      m /= c;
+      for (int k = 0; k < c; ++k) rs[k * d + a] -= m;
+    }
+    __syncthreads();
+  }
+  // r = b (projected), rounded to the working type as stored; x = 0
+  double bb = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int k = e / d, a = e - k * d;
+    const int64_t gi = a * sc + (int64_t)j * c + k;
+    const T rv = (T)rs[e];
+    r[gi] = rv;
+    xv[gi] = T(0);
+    rs[e] = (double)rv;
+    bb += (double)rv * (double)rv;
+  }
+  bb = block_sum_col(bb, red);
+  col_apply(Pinv, rs, zs, zp, d, c, project);
+  double rz = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int k = e / d, a = e - k * d;
+    const int64_t gi = a * sc + (int64_t)j * c + k;
+    const T zv = (T)zs[e];
+    p[gi] = zv;
+    rz += (double)r[gi] * (double)zv;
+  }
+  rz = block_sum_col(rz, red);
+  if (threadIdx.x == 0) {
+    // an earlier failure (non-SPD block, breakdown in the previous solve) stops this solve
+    const bool failed = st->breakdown != 0 || st->bad_block != INT_MAX;
+    bnorm[j] = sqrt(bb);
+    rho[j] = rz;
+    done[j] = bb == 0.0 || failed;
+    relres[j] = bb > 0.0 ? 1.0 : 0.0;
+    if (j == 0) st->iters = 0;
+  }
+}
+
+// One CG iteration for column j.  done_prev holds every column's flag after the previous
+// iteration (read-only here); done_next receives this iteration's flags, so no block ever
+// reads a flag another block of the same launch writes.
+template <typename T>
+__global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv, T* __restrict__ r,
+                                                     T* __restrict__ p, const T* __restrict__ q,
+                                                     const double* __restrict__ Pinv, int d, int s,
+                                                     int c, int project, double tol, double* rho,
+                                                     const double* bnorm, double* relres,
+                                                     const int32_t* done_prev, int32_t* done_next,
+                                                     Status* st) {
+  if (skip_now(skip_all(done_prev, s))) {
+    // nothing left: carry the flags forward so the next launch reads a current set
+    if (threadIdx.x == 0) done_next[blockIdx.x] = 1;
+    return;
+  }
+  extern __shared__ double sh[];
+  __shared__ double red[kColThreads / 64];
+  double* rs = sh;
+  double* zs = sh + d * c;
+  double* zp = zs + d * c;
+  double* r0s = zp + kColSplit * d * c;
+  const int j = blockIdx.x, n = d * c;
+  const int64_t sc = (int64_t)s * c;
+  const bool was_done = done_prev[j] != 0;
+  if (j == 0 && threadIdx.x == 0) st->iters += 1;
+  if (was_done) {
+    if (threadIdx.x == 0) done_next[j] = 1;
+    return;
+  }
+  double pq = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int k = e / d, a = e - k * d;
+    const int64_t gi = a * sc + (int64_t)j * c + k;
+    pq += (double)p[gi] * (double)q[gi];
+  }
+  pq = block_sum_col(pq, red);
+  if (!(pq > 0.0)) {   // breakdown: report it and freeze the column
+    if (threadIdx.x == 0) {
+      st->breakdown = 1;
+      done_next[j] = 1;
+    }
+    return;
+  }
+  const T at = (T)(rho[j] / pq);
+  double rr = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int k = e / d, a = e - k * d;
+    const int64_t gi = a * sc + (int64_t)j * c + k;
+    const T pv = p[gi];
+    xv[gi] += at * pv;
+    const T rv = r[gi] - at * q[gi];
+    r[gi] = rv;
+    rs[e] = (double)rv;
+    r0s[e] = (double)rv;
+    rr += (double)rv * (double)rv;
+  }
+  rr = block_sum_col(rr, red);
+  const double rn = sqrt(rr);
+  const bool now_done = rn <= tol * bnorm[j];
+  if (threadIdx.x == 0) {
+    done_next[j] = now_done;
+    relres[j] = bnorm[j] > 0.0 ? rn / bnorm[j] : 0.0;
+  }
+  if (now_done) return;
+  // rz = <r, M^-1 r> with the stored (unprojected) r, kept in r0s; col_apply may project rs
+  col_apply(Pinv, rs, zs, zp, d, c, project);
+  double rz = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) rz += r0s[e] * (double)(T)zs[e];
+  rz = block_sum_col(rz, red);
+  const double beta = rz / (rho[j] != 0.0 ? rho[j] : 1.0);
+  const T bt = (T)beta;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int k = e / d, a = e - k * d;
+    const int64_t gi = a * sc + (int64_t)j * c + k;
+    p[gi] = (T)zs[e] + bt * p[gi];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) rho[j] = rz;
+}
+
+// Fold the per-column flags into the status (host check points and the end of a solve).
+__global__ __launch_bounds__(256) void k_col_status(const int32_t* done, const double* relres, int s,
+                                                    Status* st) {
+  int ok = 1;
+  double m = 0.0;
+  for (int j = threadIdx.x; j < s; j += blockDim.x) {
+    ok &= done[j] != 0;
+    m = fmax(m, relres[j]);
+  }
+  const int all = __syncthreads_and(ok);
+  m = block_max<256>(m);
+  if (threadIdx.x == 0) {
+    st->relres_max = m;
+    st->all_done = all;
+  }
+}
+
 // z = M^-1 r with M = blockdiag(P_k); projected: z = Pp M^-1 Pp r.
 template <typename T>
 static int apply_t(Ctx* x, const double* Pinv, const T* r, T* z, int s, bool project,
-                   const int32_t* skip, hipStream_t st) {
+                   Skip skip, hipStream_t st) {
   const int d = x->d, c = x->c;
   const int64_t nds = (int64_t)d * s;
   if (project) {
@@ -287,20 +526,66 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
   T* q = (T*)x->cq;
   double* part0 = x->colpart;
   double* part1 = x->colpart + (int64_t)x->s_max * P;
-  const int32_t* skip = &x->status->all_done;
+  const Skip skip = skip_flag(&x->status->all_done);
   const unsigned nb = (unsigned)cdiv(n, 256);
+
+  const size_t col_lds = (size_t)(3 + kColSplit) * d * c * sizeof(double);
+  if (col_lds <= 128 * 1024 && !x->force_unfused) {
+    // column-local CG: init, then per iteration the product and one step kernel
+    static bool attr[2] = {false, false};
+    if (!attr[sizeof(T) == 8]) {
+      FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_init<T>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+      FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_step<T>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+      attr[sizeof(T) == 8] = true;
+    }
+    int32_t* flags[2] = {x->done, x->done + x->s_max};
+    k_cg_col_init<T><<<s, kColThreads, col_lds, st>>>(B, xv, r, p, Pinv, d, s, c, project, x->rho,
+                                                      x->bnorm, x->relres, flags[0], x->status);
+    FIRAL_LAUNCHED();
+    const int check_every = tol > 0.0 ? 4 : (max_iter > 0 ? max_iter : 1);
+    int launched = 0;
+    while (launched < max_iter) {
+      const int batch = std::min(check_every, max_iter - launched);
+      for (int it = 0; it < batch; ++it) {
+        const int32_t* dp = flags[(launched + it) & 1];
+        int32_t* dn = flags[(launched + it + 1) & 1];
+        FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip_all(dp, s), st));
+        k_cg_col_step<T><<<s, kColThreads, col_lds, st>>>(xv, r, p, q, Pinv, d, s, c, project, tol,
+                                                          x->rho, x->bnorm, x->relres, dp, dn,
+                                                          x->status);
+        FIRAL_LAUNCHED();
+      }
+      launched += batch;
+      k_col_status<<<1, 256, 0, st>>>(flags[launched & 1], x->relres, s, x->status);
+      FIRAL_LAUNCHED();
+      if (launched < max_iter) {
+        FIRAL_CHECK(read_status(x, st));
+        if (x->status_host->all_done) break;
+      }
+    }
+    if (max_iter == 0) {
+      k_col_status<<<1, 256, 0, st>>>(flags[0], x->relres, s, x->status);
+      FIRAL_LAUNCHED();
+    }
+    k_cg_finish<<<1, 1, 0, st>>>(x->status, slot);
+    FIRAL_LAUNCHED();
+    if (Xsol != xv) FIRAL_HIP(hipMemcpyAsync(Xsol, xv, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    return FIRAL_OK;
+  }
 
   FIRAL_HIP(hipMemsetAsync(xv, 0, n * sizeof(T), st));
   if (project) {
-    k_project<T><<<(unsigned)cdiv((int64_t)d * s, 256), 256, 0, st>>>(B, r, d, s, c, nullptr);
+    k_project<T><<<(unsigned)cdiv((int64_t)d * s, 256), 256, 0, st>>>(B, r, d, s, c, skip_none());
     FIRAL_LAUNCHED();
   } else {
     FIRAL_HIP(hipMemcpyAsync(r, B, n * sizeof(T), hipMemcpyDeviceToDevice, st));
   }
-  FIRAL_CHECK(apply_t<T>(x, Pinv, r, z, s, project, nullptr, st));
+  FIRAL_CHECK(apply_t<T>(x, Pinv, r, z, s, project, skip_none(), st));
   FIRAL_HIP(hipMemcpyAsync(p, z, n * sizeof(T), hipMemcpyDeviceToDevice, st));
-  FIRAL_CHECK(coldot_launch(x, r, r, s, part0, nullptr, st));
-  FIRAL_CHECK(coldot_launch(x, r, z, s, part1, nullptr, st));
+  FIRAL_CHECK(coldot_launch(x, r, r, s, part0, skip_none(), st));
+  FIRAL_CHECK(coldot_launch(x, r, z, s, part1, skip_none(), st));
   k_cg_init<<<1, 64, 0, st>>>(part0, part1, s, P, x->status, x->rho, x->bnorm, x->relres, x->done);
   FIRAL_LAUNCHED();
 

@@ -10,7 +10,7 @@
 namespace firal {
 
 int gemm_xb_launch(Ctx* x, const void* Xrows, const void* Bm, int SC, void* G, int64_t R,
-                   const int32_t* skip, hipStream_t st);
+                   Skip skip, hipStream_t st);
 
 // ------------------------------------------------------------- probes
 // SplitMix64 (Steele, Lea & Flood 2014): output m of the stream seeded with `seed` is the
@@ -84,8 +84,8 @@ int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStrea
     const char* Hr = (const char*)x->H + r0 * c * x->esize;
     void* G0 = x->G;
     void* G1 = (char*)x->G + half * x->esize;
-    FIRAL_CHECK(gemm_xb_launch(x, Xr, U, SC, G0, R, nullptr, st));
-    FIRAL_CHECK(gemm_xb_launch(x, Xr, W, SC, G1, R, nullptr, st));
+    FIRAL_CHECK(gemm_xb_launch(x, Xr, U, SC, G0, R, skip_none(), st));
+    FIRAL_CHECK(gemm_xb_launch(x, Xr, W, SC, G1, R, skip_none(), st));
     if (x->prec == FIRAL_F64)
       k_grad_rows<double><<<(unsigned)cdiv(R, 256), 256, 0, st>>>(
           (const double*)G0, (const double*)G1, (const double*)Hr, R, s, c, g + r0);
@@ -107,10 +107,25 @@ __device__ __forceinline__ bool step_failed(const Status* st) {
   return st->breakdown != 0 || st->bad_block != INT_MAX;
 }
 
+// max / sum of nb per-block partials, every block computing the same value: each thread
+// takes every 256th partial, then a fixed block tree (one memory round trip, not nb).
 __device__ __forceinline__ double reduce_parts_max(const double* part, int nb) {
   double m = -INFINITY;
-  for (int i = 0; i < nb; ++i) m = fmax(m, part[i]);
-  return m;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) m = fmax(m, part[i]);
+  m = block_max<256>(m);
+  __shared__ double bc;
+  if (threadIdx.x == 0) bc = m;
+  __syncthreads();
+  return bc;
+}
+__device__ __forceinline__ double reduce_parts_sum(const double* part, int nb) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) v += part[i];
+  v = block_sum<256>(v);
+  __shared__ double bc;
+  if (threadIdx.x == 0) bc = v;
+  __syncthreads();
+  return bc;
 }
 
 __global__ __launch_bounds__(256) void k_md1(const double* __restrict__ g, int64_t n,
@@ -164,8 +179,7 @@ __global__ __launch_bounds__(256) void k_md4(double* __restrict__ w, const doubl
                                              int64_t n, const double* __restrict__ part_s,
                                              const Status* st) {
   if (step_failed(st)) return;
-  double S = 0.0;
-  for (int i = 0; i < (int)gridDim.x; ++i) S += part_s[i];
+  const double S = reduce_parts_sum(part_s, gridDim.x);
   const double inv = 1.0 / S;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -180,11 +194,11 @@ __global__ __launch_bounds__(256) void k_omega(const double* __restrict__ w, dou
   if (i < N) omega[i] = i < n_pool ? b * w[i] : 1.0;
 }
 
-__global__ void k_fhat(const double* part, int s, int P, Status* st) {
+__global__ __launch_bounds__(256) void k_fhat(const double* part, int s, int P, Status* st) {
   double f = 0.0;
-  for (int j = 0; j < s; ++j)
-    for (int p = 0; p < P; ++p) f += part[j * P + p];
-  st->f_hat = f / s;
+  for (int i = threadIdx.x; i < s * P; i += blockDim.x) f += part[i];
+  f = block_sum<256>(f);
+  if (threadIdx.x == 0) st->f_hat = f / s;
 }
 
 __global__ void k_step_reset(Status* st) {
@@ -220,9 +234,9 @@ int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, 
   FIRAL_CHECK(pcg_launch(x, x->omega, lambda, x->Pinv, x->V, x->W1, s, tol, max_iter, flags, 0, st));
   k_relres_merge<<<1, 1, 0, st>>>(x->status, keep);
   FIRAL_LAUNCHED();
-  FIRAL_CHECK(hvp_launch(x, nullptr, n, 0.0, x->W1, x->Y, s, nullptr, st));
-  FIRAL_CHECK(coldot_launch(x, x->V, x->Y, s, x->colpart, nullptr, st));
-  k_fhat<<<1, 1, 0, st>>>(x->colpart, s, x->col_parts, x->status);
+  FIRAL_CHECK(hvp_launch(x, nullptr, n, 0.0, x->W1, x->Y, s, skip_none(), st));
+  FIRAL_CHECK(coldot_launch(x, x->V, x->Y, s, x->colpart, skip_none(), st));
+  k_fhat<<<1, 256, 0, st>>>(x->colpart, s, x->col_parts, x->status);
   FIRAL_LAUNCHED();
   FIRAL_CHECK(pcg_launch(x, x->omega, lambda, x->Pinv, x->Y, x->W2, s, tol, max_iter, flags, 1, st));
   k_relres_merge<<<1, 1, 0, st>>>(x->status, keep);

@@ -191,8 +191,10 @@ def test_precond_reports_non_spd_block():
 
 # ------------------------------------------------------------------------ pcg
 
+@pytest.mark.parametrize("unfused", ["0", "1"])
 @pytest.mark.parametrize("project", [True, False])
-def test_pcg_f64_matches_oracle(project):
+def test_pcg_f64_matches_oracle(project, unfused, monkeypatch):
+    monkeypatch.setenv("FIRAL_UNFUSED", unfused)   # column-local CG step / separate kernels
     p = make_small(n=1500, n_lab=20, d=12, c=5, s=6, seed=8)
     ctx, X, H = context(p, "f64", 6)
     rng = np.random.default_rng(6)
@@ -222,7 +224,9 @@ def test_pcg_f64_matches_oracle(project):
         assert relerr(host(Xs), xr) <= 1e-4
 
 
-def test_pcg_f32_fixed_iterations():
+@pytest.mark.parametrize("unfused", ["0", "1"])
+def test_pcg_f32_fixed_iterations(unfused, monkeypatch):
+    monkeypatch.setenv("FIRAL_UNFUSED", unfused)
     p = make_small(n=3001, n_lab=7, d=100, c=10, s=20, seed=10, whiten_x=True, probs="maxprob")
     ctx, X, H = context(p, "f32", 20)
     rng = np.random.default_rng(7)
@@ -237,7 +241,9 @@ def test_pcg_f32_fixed_iterations():
     assert relerr(host(Xs), xr) <= 1e-4
 
 
-def test_pcg_breakdown_and_not_converged():
+@pytest.mark.parametrize("unfused", ["0", "1"])
+def test_pcg_breakdown_and_not_converged(unfused, monkeypatch):
+    monkeypatch.setenv("FIRAL_UNFUSED", unfused)
     p = make_small(n=300, n_lab=3, d=4, c=3, s=2, seed=11)
     ctx, _, _ = context(p, "f64", 2)
     _, Pinv, _ = ctx.build_precond(shift=1.0)
@@ -267,7 +273,9 @@ def test_grad_matches_oracle(prec, shape):
 
 # ---------------------------------------------------------------------- relax
 
-def test_relax_f64_trajectory_matches_oracle():
+@pytest.mark.parametrize("unfused", ["0", "1"])
+def test_relax_f64_trajectory_matches_oracle(unfused, monkeypatch):
+    monkeypatch.setenv("FIRAL_UNFUSED", unfused)
     p = make_problem(1)
     ctx, X, H = context(p, "f64", p.s)
     beta0 = orc.default_beta0(p.n_pool, p.T)
