@@ -30,7 +30,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16x3"])
+    ap.add_argument("--no-bf16x3", action="store_true", help="skip the bf16x3 leg")
     ap.add_argument("--literal", action="store_true", help="PCG without the null-space projection")
     ap.add_argument("--hvp-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -54,65 +55,97 @@ def cpu_baseline(p, beta0, project):
                       f"{dt:.1f} s"}
 
 
+def run_leg(p, prec, steps, warmup, project, hvp_reps):
+    """Time `steps` Relax iterations and the Hessian product in one precision."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, default_beta0
+    dt = torch.float64 if prec == "f64" else torch.float32
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(p.X, dtype=dt, device=dev)
+    H = torch.as_tensor(p.H, dtype=dt, device=dev)
+    ctx = RelaxContext(X, H, p.n_pool, p.s, prec)
+    beta0 = default_beta0(p.n_pool, p.T)
+    wtmp = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
+    for t in range(1, warmup + 1):
+        ctx.relax_step(wtmp, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, 1000, project)
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = [ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, 1000, project)
+             for t in range(1, steps + 1)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    B = ctx.probes(p.probe_seed, 1, p.s)
+    out = torch.empty_like(B)
+    om = torch.full((p.N,), 1.0, dtype=torch.float64, device=dev)
+    om[:p.n_pool] = p.b / p.n_pool
+    for _ in range(3):
+        ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(hvp_reps):
+        ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_hvp = ev0.elapsed_time(ev1) / 1e3 / hvp_reps
+    flops = 4.0 * p.N * p.c * p.d * p.s
+    ctx.close()
+    return dict(elapsed=elapsed, ms=1e3 * elapsed / steps, value=steps / elapsed,
+                cg=float(np.mean([i["cg_iters"][0] + i["cg_iters"][1] for i in infos])),
+                t_hvp=t_hvp, hvp_tflops=flops / t_hvp / 1e12, f_hat_last=infos[-1]["f_hat"])
+
+
+def grad_errors(p, project, n_cg=15):
+    """Relative gradient error of FP32 and bf16x3 against the GPU FP64 mode (same probes,
+    same fixed number of CG iterations, so only arithmetic precision differs)."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, default_beta0
+    dev = torch.device("cuda:0")
+    beta0 = default_beta0(p.n_pool, p.T)
+    Xf = np.asarray(p.X, dtype=np.float32)
+    Hf = np.asarray(p.H, dtype=np.float32)
+    g = {}
+    for prec in ("f64", "f32", "bf16x3"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        ctx = RelaxContext(torch.as_tensor(Xf, dtype=dt, device=dev),
+                           torch.as_tensor(Hf, dtype=dt, device=dev), p.n_pool, p.s, prec)
+        w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
+        gt = torch.empty_like(w)
+        ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, 0.0, n_cg, project, g_out=gt)
+        g[prec] = gt.cpu().numpy()
+        ctx.close()
+    ref = np.linalg.norm(g["f64"])
+    return {k: float(np.linalg.norm(g[k] - g["f64"]) / ref) for k in ("f32", "bf16x3")}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Relax path "
               "of this build is single-GPU.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
-    import torch
-
-    from paper_2409_07392_amd import RelaxContext, default_beta0
     from synthdata import make_problem
+    from paper_2409_07392_amd import default_beta0
 
     p = make_problem(2)
     project = not args.literal
-    dt = torch.float64 if args.prec == "f64" else torch.float32
-    dev = torch.device("cuda:0")
-    X = torch.as_tensor(p.X, dtype=dt, device=dev)
-    H = torch.as_tensor(p.H, dtype=dt, device=dev)
-    ctx = RelaxContext(X, H, p.n_pool, p.s, args.prec)
-    beta0 = default_beta0(p.n_pool, p.T)
-    max_iter = 1000
-
-    # warmup on a scratch weight vector
-    wtmp = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
-    for t in range(1, args.warmup + 1):
-        ctx.relax_step(wtmp, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, max_iter, project)
-
-    # timed: K Relax iterations from w = 1/n
-    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = [ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, max_iter, project)
-             for t in range(1, args.steps + 1)]
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    ms = 1e3 * elapsed / args.steps
-    cg = [i["cg_iters"][0] + i["cg_iters"][1] for i in infos]
-
-    # HVP: the dominant operation (about 2 per CG iteration are not needed; one per iteration)
-    B = ctx.probes(p.probe_seed, 1, p.s)
-    out = torch.empty_like(B)
-    for _ in range(3):
-        ctx.hvp(B, shift=p.lam, out=out)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.hvp_reps):
-        ctx.hvp(B, shift=p.lam, out=out)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_hvp = ev0.elapsed_time(ev1) / 1e3 / args.hvp_reps
-    flops = 4.0 * p.N * p.c * p.d * p.s
-    tflops = flops / t_hvp / 1e12
-
+    main_leg = run_leg(p, args.prec, args.steps, args.warmup, project, args.hvp_reps)
+    legs = {args.prec: main_leg}
+    if args.prec != "bf16x3" and not args.no_bf16x3:
+        legs["bf16x3"] = run_leg(p, "bf16x3", args.steps, args.warmup, project, args.hvp_reps)
+    errs = grad_errors(p, project)
+    peak = PEAK[args.prec]
     res = {
         "metric": METRIC,
-        "value": args.steps / elapsed,
+        "value": main_leg["value"],
         "unit": "relax_iter/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": main_leg["ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -120,15 +153,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": "relax cfg2: n=50000+10 labeled, d=100, c=10, s=20, tol=1e-6, b=100",
                    "pcg": "projected" if project else "literal",
-                   "mean_cg_iters_per_step": float(np.mean(cg)),
-                   "hvp_ms": t_hvp * 1e3, "hvp_tflops": tflops,
-                   "f_hat_last": infos[-1]["f_hat"]},
+                   "mean_cg_iters_per_step": main_leg["cg"],
+                   "hvp_ms": main_leg["t_hvp"] * 1e3, "hvp_tflops": main_leg["hvp_tflops"],
+                   "f_hat_last": main_leg["f_hat_last"]},
+        "precision_legs": {k: {"ms_per_step": v["ms"], "relax_iter_per_s": v["value"],
+                               "hvp_ms": v["t_hvp"] * 1e3, "hvp_tflops": v["hvp_tflops"],
+                               "mean_cg_iters_per_step": v["cg"],
+                               "rel_grad_err_vs_f64": errs.get(k)}
+                           for k, v in legs.items()},
         "roofline": {"bound": "mfma", "kernel": "hvp (Lemma 1 product, all its kernels)",
-                     "achieved": tflops, "peak": PEAK[args.prec], "unit": "TFLOP/s",
-                     "frac": tflops / PEAK[args.prec], "traffic": None},
+                     "achieved": main_leg["hvp_tflops"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": main_leg["hvp_tflops"] / peak, "traffic": None},
     }
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(p, beta0, project)
+        res["cpu_baseline"] = cpu_baseline(p, default_beta0(p.n_pool, p.T), project)
     print(json.dumps(res))
 
 

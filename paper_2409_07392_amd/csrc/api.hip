@@ -101,10 +101,6 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   FIRAL_REQ(prec == FIRAL_F64 || prec == FIRAL_F32 || prec == FIRAL_BF16X3, "unknown precision %d",
             prec);
   FIRAL_REQ(X != nullptr && H != nullptr, "null X or H");
-  if (prec == FIRAL_BF16X3) {
-    set_error("BF16X3 contexts are not built yet");
-    return FIRAL_ENOTSUP;
-  }
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev < 1) {

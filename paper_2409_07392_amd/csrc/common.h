@@ -206,6 +206,7 @@ __device__ __forceinline__ bool skip_now(const Skip& k) {
 // Tile plan of the fused FP32 product (hvp_fused.hip).
 struct FusedPlan {
   void* kernel;
+  int bf3;              // bf16x3 products
   int D16, ncb, probes_per_tile, n_ctiles, n_splits;
   int64_t rows_per_split;
   int XS, XT, GT, CP;

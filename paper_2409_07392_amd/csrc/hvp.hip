@@ -250,7 +250,7 @@ static int hvp_t(Ctx* x, const double* omega, int64_t n_rows, double shift, cons
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
                void* out, int s, Skip skip, hipStream_t st) {
   FusedPlan plan;
-  if (x->prec == FIRAL_F32 && !x->force_unfused && fused_plan(x, s, n_rows, &plan) &&
+  if (x->prec != FIRAL_F64 && !x->force_unfused && fused_plan(x, s, n_rows, &plan) &&
       plan.part_elems <= x->fused_part_elems)
     return hvp_fused_launch(x, plan, omega, n_rows, shift, (const float*)B, (float*)out, s, skip,
                             st);

@@ -150,15 +150,34 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
     }
     __syncthreads();
 
-    // 3. Gamma apply per (row, probe), rows fastest across threads
+    // 3. Gamma apply per (row, probe), rows fastest across threads; loads issued in groups
     for (int e = tid; e < kRC * sp; e += kThreads) {
       const int r = e % kRC, jj = e / kRC;
       float* g = GsT + (jj * c) * GT + r;
       const float* h = Hs + r * c;
       float alpha = 0.f;
-      for (int k = 0; k < c; ++k) alpha += g[k * GT] * h[k];
+      for (int k0 = 0; k0 < c; k0 += 4) {
+        float gv[4], hv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
+          hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) alpha += gv[u] * hv[u];
+      }
       const float w = Om[r];
-      for (int k = 0; k < c; ++k) g[k * GT] = w * ((g[k * GT] - alpha) * h[k]);
+      for (int k0 = 0; k0 < c; k0 += 4) {
+        float gv[4], hv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
+          hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + u < c) g[(k0 + u) * GT] = w * ((gv[u] - alpha) * hv[u]);
+      }
     }
     __syncthreads();
 
@@ -202,6 +221,218 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
   }
 }
 
+// ------------------------------------------------------------- bf16x3 variant
+// Same tiling with each FP32 product taken as three bf16 products on the
+// 16x16x32 bf16 MFMA (FP32 accumulation): x y ~ xh yh + xh yl + xl yh with
+// xh = bf16(x), xl = bf16(x - xh).  X is split once per chunk while it is
+// staged (hi and lo planes, both layouts), V once per kernel into registers,
+// and G' per use.  The contraction index is again permuted so a lane's eight
+// operands are adjacent: k = 32 g + 8 lk + u.
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const __bf16 h = (__bf16)v[u];
+    hi[u] = h;
+    lo[u] = (__bf16)(v[u] - (float)h);
+  }
+}
+
+__device__ __forceinline__ f32x4 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                       const bf16x8& bl, f32x4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+  return acc;
+}
+
+template <int D16, int NCB>
+__global__ __launch_bounds__(kThreads) void k_hvp_fused_bf3(
+    const float* __restrict__ X, const float* __restrict__ H, const double* __restrict__ omega,
+    int64_t n_rows, int d, int c, int SC, const float* __restrict__ B, int probes_per_tile, int s,
+    int n_ctiles, int64_t rows_per_split, int n_splits, int XS, int XT, int GT, int CP,
+    float* __restrict__ part, Skip skip) {
+  if (skip_now(skip)) return;
+  const int nwg = gridDim.x;
+  const int lid = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+  if (lid >= n_splits * n_ctiles) return;
+  const int ct = lid % n_ctiles;
+  const int split = lid / n_ctiles;
+  const int j0 = ct * probes_per_tile;
+  const int sp = min(probes_per_tile, s - j0);
+  const int col0 = j0 * c;
+  const int CT = sp * c;
+  const int C16 = (CT + 15) >> 4;
+  const int64_t rb = (int64_t)split * rows_per_split;
+  const int64_t re = rb + rows_per_split < n_rows ? rb + rows_per_split : n_rows;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int D32 = (D16 + 1) / 2;
+  constexpr int DP = 32 * D32;          // contraction padding of the first product
+
+  extern __shared__ float lds[];
+  __bf16* Xh = (__bf16*)lds;             // [kRC][XS]  hi plane, row-major
+  __bf16* Xl = Xh + kRC * XS;            // [kRC][XS]  lo plane
+  __bf16* XTh = Xl + kRC * XS;           // [DP][XT]   hi plane, transposed
+  __bf16* XTl = XTh + DP * XT;           // [DP][XT]
+  float* GsT = (float*)(XTl + DP * XT);  // [CP][GT]
+  float* Hs = GsT + CP * GT;             // [kRC][c]
+  float* Om = Hs + kRC * c;              // [kRC]
+
+  bf16x8 bh[NCB][D32], bl[NCB][D32];
+#pragma unroll
+  for (int i = 0; i < NCB; ++i) {
+    const int cb = wave + kNW * i;
+    const int col = cb * 16 + li;
+    const bool ok = cb < C16 && col < CT;
+#pragma unroll
+    for (int g = 0; g < D32; ++g) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = 32 * g + 8 * lk + u;
+        v[u] = (ok && k < d) ? B[(int64_t)k * SC + col0 + col] : 0.f;
+      }
+      split8(v, bh[i][g], bl[i][g]);
+    }
+  }
+  f32x4 acc2[NCB][D16];
+#pragma unroll
+  for (int i = 0; i < NCB; ++i)
+#pragma unroll
+    for (int ab = 0; ab < D16; ++ab) acc2[i][ab] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t r0 = rb; r0 < re; r0 += kRC) {
+    const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+    for (int e = tid; e < kRC * DP; e += kThreads) {
+      const int r = e / DP, a = e - r * DP;
+      const float v = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
+      const __bf16 h = (__bf16)v;
+      const __bf16 l = (__bf16)(v - (float)h);
+      Xh[r * XS + a] = h;
+      Xl[r * XS + a] = l;
+      XTh[a * XT + r] = h;
+      XTl[a * XT + r] = l;
+    }
+    for (int e = tid; e < kRC * c; e += kThreads) {
+      const int r = e / c;
+      Hs[e] = r < R ? H[r0 * c + e] : 0.f;
+    }
+    if (tid < kRC) Om[tid] = tid < R ? (omega ? (float)omega[r0 + tid] : 1.f) : 0.f;
+    __syncthreads();
+
+    // G = X_chunk V_tile
+    f32x4 acc1[NCB][2];
+#pragma unroll
+    for (int i = 0; i < NCB; ++i) {
+      acc1[i][0] = f32x4{0.f, 0.f, 0.f, 0.f};
+      acc1[i][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int g = 0; g < D32; ++g) {
+      const bf16x8 a0h = *(const bf16x8*)(Xh + li * XS + 32 * g + 8 * lk);
+      const bf16x8 a0l = *(const bf16x8*)(Xl + li * XS + 32 * g + 8 * lk);
+      const bf16x8 a1h = *(const bf16x8*)(Xh + (16 + li) * XS + 32 * g + 8 * lk);
+      const bf16x8 a1l = *(const bf16x8*)(Xl + (16 + li) * XS + 32 * g + 8 * lk);
+#pragma unroll
+      for (int i = 0; i < NCB; ++i) {
+        acc1[i][0] = mfma3(a0h, a0l, bh[i][g], bl[i][g], acc1[i][0]);
+        acc1[i][1] = mfma3(a1h, a1l, bh[i][g], bl[i][g], acc1[i][1]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NCB; ++i) {
+      const int cb = wave + kNW * i;
+      if (cb < C16) {
+        *(f32x4v*)(GsT + (cb * 16 + li) * GT + 4 * lk) =
+            f32x4v{acc1[i][0][0], acc1[i][0][1], acc1[i][0][2], acc1[i][0][3]};
+        *(f32x4v*)(GsT + (cb * 16 + li) * GT + 16 + 4 * lk) =
+            f32x4v{acc1[i][1][0], acc1[i][1][1], acc1[i][1][2], acc1[i][1][3]};
+      }
+    }
+    __syncthreads();
+
+    // Gamma apply (FP32)
+    for (int e = tid; e < kRC * sp; e += kThreads) {
+      const int r = e % kRC, jj = e / kRC;
+      float* g = GsT + (jj * c) * GT + r;
+      const float* h = Hs + r * c;
+      float alpha = 0.f;
+      for (int k0 = 0; k0 < c; k0 += 4) {
+        float gv[4], hv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
+          hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) alpha += gv[u] * hv[u];
+      }
+      const float w = Om[r];
+      for (int k0 = 0; k0 < c; k0 += 4) {
+        float gv[4], hv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
+          hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (k0 + u < c) g[(k0 + u) * GT] = w * ((gv[u] - alpha) * hv[u]);
+      }
+    }
+    __syncthreads();
+
+    // Out += X_chunk^T G' (one group of 32 rows)
+    bf16x8 gh[NCB], gl[NCB];
+#pragma unroll
+    for (int i = 0; i < NCB; ++i) {
+      const int cb = wave + kNW * i;
+      float v[8];
+      if (cb < C16) {
+        const f32x4v q0 = *(const f32x4v*)(GsT + (cb * 16 + li) * GT + 8 * lk);
+        const f32x4v q1 = *(const f32x4v*)(GsT + (cb * 16 + li) * GT + 8 * lk + 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          v[u] = q0[u];
+          v[4 + u] = q1[u];
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = 0.f;
+      }
+      split8(v, gh[i], gl[i]);
+    }
+#pragma unroll
+    for (int ab = 0; ab < D16; ++ab) {
+      const bf16x8 ah = *(const bf16x8*)(XTh + (ab * 16 + li) * XT + 8 * lk);
+      const bf16x8 al = *(const bf16x8*)(XTl + (ab * 16 + li) * XT + 8 * lk);
+#pragma unroll
+      for (int i = 0; i < NCB; ++i) acc2[i][ab] = mfma3(ah, al, gh[i], gl[i], acc2[i][ab]);
+    }
+    __syncthreads();
+  }
+
+  float* out = part + (int64_t)split * d * SC;
+#pragma unroll
+  for (int i = 0; i < NCB; ++i) {
+    const int cb = wave + kNW * i;
+    const int col = cb * 16 + li;
+    if (cb < C16 && col < CT) {
+#pragma unroll
+      for (int ab = 0; ab < D16; ++ab)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = ab * 16 + 4 * lk + v;
+          if (a < d) out[(int64_t)a * SC + col0 + col] = acc2[i][ab][v];
+        }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- dispatch
 
 typedef void (*FusedKernel)(const float*, const float*, const double*, int64_t, int, int, int,
@@ -213,6 +444,27 @@ static FusedKernel pick_ncb(int ncb) {
   if (ncb == 1) return k_hvp_fused<D16, 1>;
   if (ncb == 2) return k_hvp_fused<D16, 2>;
   return nullptr;
+}
+
+template <int D16>
+static FusedKernel pick_bf3_ncb(int ncb) {
+  if (ncb == 1) return k_hvp_fused_bf3<D16, 1>;
+  if (ncb == 2) return k_hvp_fused_bf3<D16, 2>;
+  return nullptr;
+}
+
+static FusedKernel pick_bf3(int D16, int ncb) {
+  switch (D16) {
+    case 1: return pick_bf3_ncb<1>(ncb);
+    case 2: return pick_bf3_ncb<2>(ncb);
+    case 3: return pick_bf3_ncb<3>(ncb);
+    case 4: return pick_bf3_ncb<4>(ncb);
+    case 5: return pick_bf3_ncb<5>(ncb);
+    case 6: return pick_bf3_ncb<6>(ncb);
+    case 7: return pick_bf3_ncb<7>(ncb);
+    case 8: return pick_bf3_ncb<8>(ncb);
+    default: return nullptr;
+  }
 }
 
 static FusedKernel pick(int D16, int ncb) {
@@ -243,7 +495,7 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p) {
   if (x->prec == FIRAL_F64 || n_rows <= 0) return false;
   const int d = x->d, c = x->c;
   const int D16 = (d + 15) / 16;
-  if (D16 > 16) return false;
+  if (D16 > 16 || (x->prec == FIRAL_BF16X3 && D16 > 8)) return false;
   const int max_ncb = D16 <= 8 ? 2 : 1;
   // widest tile of whole probes whose 16-column blocks fit max_ncb per wave
   const int max_cols = max_ncb * kNW * 16;
@@ -253,16 +505,27 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p) {
   pp = (s + n_ct - 1) / n_ct;            // balance the tiles
   const int C16 = (pp * c + 15) / 16;
   const int ncb = (C16 + kNW - 1) / kNW;
+  const bool bf3 = x->prec == FIRAL_BF16X3;
   FusedGeom g = fused_geom(D16, C16, c);
-  if (g.lds_floats * 4 > 156 * 1024) return false;   // static LDS of the kernel needs a little
+  size_t lds_bytes = g.lds_floats * 4;
+  if (bf3) {
+    // hi/lo bf16 planes of the X chunk in both layouts, then the FP32 G tile, h, omega
+    const int DP32 = 32 * ((D16 + 1) / 2);
+    g.XS = DP32 + 8;
+    g.XT = kRC + 8;
+    lds_bytes = (size_t)2 * 2 * kRC * g.XS + (size_t)2 * 2 * DP32 * g.XT +
+                4 * ((size_t)g.CP * g.GT + (size_t)kRC * c + kRC);
+  }
+  if (lds_bytes > 156 * 1024) return false;   // the kernel's own static LDS needs a little
   const int64_t chunks = (n_rows + kRC - 1) / kRC;
   const int target_wgs = 256;
   int64_t splits = std::max<int64_t>(1, std::min<int64_t>(chunks, target_wgs / n_ct));
   const int64_t rps = ((n_rows + splits - 1) / splits + kRC - 1) / kRC * kRC;
   splits = (n_rows + rps - 1) / rps;
   p->part_elems = splits * (int64_t)d * s * c;
-  p->kernel = (void*)pick(D16, ncb);
+  p->kernel = bf3 ? (void*)pick_bf3(D16, ncb) : (void*)pick(D16, ncb);
   if (!p->kernel) return false;
+  p->bf3 = bf3;
   p->D16 = D16;
   p->ncb = ncb;
   p->probes_per_tile = pp;
@@ -273,18 +536,18 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p) {
   p->XT = g.XT;
   p->GT = g.GT;
   p->CP = g.CP;
-  p->lds_bytes = g.lds_floats * 4;
+  p->lds_bytes = lds_bytes;
   return true;
 }
 
 int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_rows, double shift,
                      const float* B, float* out, int s, Skip skip, hipStream_t st) {
   FusedKernel k = (FusedKernel)p.kernel;
-  static size_t attr_set[17][3] = {};   // largest dynamic LDS size granted per instantiation
-  if (p.lds_bytes > 64 * 1024 && attr_set[p.D16][p.ncb] < p.lds_bytes) {
+  static size_t attr_set[2][17][3] = {};   // largest dynamic LDS size granted per instantiation
+  if (p.lds_bytes > 64 * 1024 && attr_set[p.bf3][p.D16][p.ncb] < p.lds_bytes) {
     FIRAL_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)p.lds_bytes));
-    attr_set[p.D16][p.ncb] = p.lds_bytes;
+    attr_set[p.bf3][p.D16][p.ncb] = p.lds_bytes;
   }
   const int SC = s * x->c;
   const int nwg = (int)(((int64_t)p.n_splits * p.n_ctiles + 7) / 8 * 8);

@@ -344,3 +344,44 @@ def test_relax_f32_gradient_error_fixed_iterations():
     e = relerr(host(g), ir["g"])
     assert e <= 1e-4, e
     assert abs(info["f_hat"] - ir["f_hat"]) <= 1e-5 * abs(ir["f_hat"])
+
+
+# -------------------------------------------------------------------- bf16x3
+# Each FP32 product is taken as hi*hi + hi*lo + lo*hi of bf16 halves (FP32 sums): the
+# dropped lo*lo term and the rounding of lo leave ~2^-16 relative error per product, so
+# the bar for these results is 1e-4 normwise (the gradient gate of the metric).
+
+BF3_TOL = 1e-4
+
+
+@pytest.mark.parametrize("shape", [(3001, 7, 100, 10, 20), (650, 2, 20, 5, 10), (900, 3, 37, 13, 3),
+                                   (300, 0, 1, 2, 1)])
+def test_hvp_bf16x3(shape):
+    n, nl, d, c, s = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=17, whiten_x=True, probs="maxprob")
+    X = rounded(p.X, "f32")
+    H = rounded(p.H, "f32")
+    ctx = RelaxContext(dev(X, torch.float32), dev(H, torch.float32), p.n_pool, s, "bf16x3")
+    rng = np.random.default_rng(19)
+    for B in (rng.choice([-1.0, 1.0], size=(d, s, c)), rounded(rng.standard_normal((d, s, c)), "f32")):
+        om = rng.uniform(0.0, 1.0, p.N)
+        got = host(ctx.hvp(dev(B, torch.float32), omega=dev(om, torch.float64), shift=1e-3))
+        ref = orc.hvp(X, H, om, 1e-3, B)
+        assert relerr(got, ref) <= BF3_TOL, relerr(got, ref)
+
+
+def test_relax_bf16x3_gradient_error_fixed_iterations():
+    p = make_problem(2, n=5000)
+    X = rounded(p.X, "f32")
+    H = rounded(p.H, "f32")
+    ctx = RelaxContext(dev(X, torch.float32), dev(H, torch.float32), p.n_pool, p.s, "bf16x3")
+    beta0 = orc.default_beta0(p.n_pool, p.T)
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(w)
+    info = ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, 0.0, 15, project=True,
+                          g_out=g)
+    _, ir = orc.relax_iteration(X, H, p.n_pool, np.full(p.n_pool, 1.0 / p.n_pool), p.b, p.lam,
+                                beta0, p.probe_seed, 1, p.s, 0.0, 15, project=True)
+    assert info["cg_iters"] == (15, 15)
+    e = relerr(host(g), ir["g"])
+    assert e <= BF3_TOL, e
