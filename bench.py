@@ -23,6 +23,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Relax iter time + HVP TFLOP/s, FP32 vs bf16x3 at ≤1e-4 rel grad error"
 PEAK = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0}   # TFLOP/s, MI355X dense MFMA
+KERNEL_NAME = {"f32": "k_hvp_fused<7,2> (fused Lemma 1 product, FP32)",
+               "bf16x3": "k_hvp_fused_bf3<7,2> (fused Lemma 1 product, bf16x3)",
+               "f64": "general product path (FP64 contraction kernels)"}
+# HBM bytes per launch of the main kernel from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
+# each scaled by the copy-kernel calibration factor (profiles/; None until measured for
+# the current kernel)
+TRAFFIC = {}
 
 
 def parse():
@@ -35,11 +42,14 @@ def parse():
     ap.add_argument("--literal", action="store_true", help="PCG without the null-space projection")
     ap.add_argument("--hvp-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (counter calibration)")
     return ap.parse_args()
 
 
-def cpu_baseline(p, beta0, project):
-    """Time the FP64 oracle on one Relax iteration of the same workload (full size)."""
+def cpu_baseline(p, beta0, project, budget_s=10.0, max_iters=8):
+    """Time the FP64 oracle on full-size Relax iterations of the same workload: iterations
+    t = 1, 2, ... until about budget_s seconds of CPU work (at most max_iters)."""
     import numpy as np
     from threadpoolctl import threadpool_info
 
@@ -47,12 +57,15 @@ def cpu_baseline(p, beta0, project):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     w = np.full(p.n_pool, 1.0 / p.n_pool)
     t0 = time.perf_counter()
-    orc.relax_iteration(p.X, p.H, p.n_pool, w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, p.tol,
-                        1000, project=project)
+    it = 0
+    while it < max_iters and (it == 0 or time.perf_counter() - t0 < budget_s):
+        it += 1
+        w, _ = orc.relax_iteration(p.X, p.H, p.n_pool, w, p.b, p.lam, beta0, p.probe_seed, it,
+                                   p.s, p.tol, 1000, project=project)
     dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "relax_iter/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one full-size Relax iteration (t=1) of the same workload in FP64 NumPy, "
-                      f"{dt:.1f} s"}
+    return {"value": it / dt, "unit": "relax_iter/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"Relax iterations t=1..{it} of the same full-size workload in FP64 NumPy "
+                      f"on the host, {dt:.1f} s"}
 
 
 def run_leg(p, prec, steps, warmup, project, hvp_reps):
@@ -83,6 +96,7 @@ def run_leg(p, prec, steps, warmup, project, hvp_reps):
     om[:p.n_pool] = p.b / p.n_pool
     for _ in range(3):
         ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    # whole product call (main kernel + split-sum reduction), events on the call's stream
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -91,11 +105,18 @@ def run_leg(p, prec, steps, warmup, project, hvp_reps):
     ev1.record(stream)
     torch.cuda.synchronize()
     t_hvp = ev0.elapsed_time(ev1) / 1e3 / hvp_reps
+    # the main product kernel alone: the library's event pairs around each launch
+    ctx.profile_begin()
+    for _ in range(hvp_reps):
+        ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    k_ms, k_n = ctx.profile_end()
+    t_kern = k_ms / 1e3 / max(k_n, 1)
     flops = 4.0 * p.N * p.c * p.d * p.s
     ctx.close()
     return dict(elapsed=elapsed, ms=1e3 * elapsed / steps, value=steps / elapsed,
                 cg=float(np.mean([i["cg_iters"][0] + i["cg_iters"][1] for i in infos])),
-                t_hvp=t_hvp, hvp_tflops=flops / t_hvp / 1e12, f_hat_last=infos[-1]["f_hat"])
+                t_hvp=t_hvp, hvp_tflops=flops / t_hvp / 1e12, t_kern=t_kern,
+                kern_tflops=flops / t_kern / 1e12, f_hat_last=infos[-1]["f_hat"])
 
 
 def grad_errors(p, project, n_cg=15):
@@ -123,8 +144,23 @@ def grad_errors(p, project, n_cg=15):
     return {k: float(np.linalg.norm(g[k] - g["f64"]) / ref) for k in ("f32", "bf16x3")}
 
 
+def calibrate_copy(mib):
+    """A plain device copy of `mib` MiB (for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4}))
+
+
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Relax path "
               "of this build is single-GPU.", file=sys.stderr)
@@ -158,12 +194,15 @@ def main():
                    "f_hat_last": main_leg["f_hat_last"]},
         "precision_legs": {k: {"ms_per_step": v["ms"], "relax_iter_per_s": v["value"],
                                "hvp_ms": v["t_hvp"] * 1e3, "hvp_tflops": v["hvp_tflops"],
+                               "kernel_us": v["t_kern"] * 1e6, "kernel_tflops": v["kern_tflops"],
                                "mean_cg_iters_per_step": v["cg"],
                                "rel_grad_err_vs_f64": errs.get(k)}
                            for k, v in legs.items()},
-        "roofline": {"bound": "mfma", "kernel": "hvp (Lemma 1 product, all its kernels)",
-                     "achieved": main_leg["hvp_tflops"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": main_leg["hvp_tflops"] / peak, "traffic": None},
+        "roofline": {"bound": "mfma", "kernel": KERNEL_NAME.get(args.prec),
+                     "achieved": main_leg["kern_tflops"], "peak": peak, "unit": "TFLOP/s",
+                     "frac": main_leg["kern_tflops"] / peak,
+                     "kernel_us": main_leg["t_kern"] * 1e6,
+                     "traffic": TRAFFIC.get(args.prec)},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(p, default_beta0(p.n_pool, p.T), project)

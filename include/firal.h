@@ -141,6 +141,16 @@ int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double b
                      uint64_t seed, int32_t t, int32_t s, double tol, int32_t max_iter,
                      uint32_t flags, double* g_out, firal_info* info, void* stream);
 
+/* Measurement of the main Hessian-product kernel (the fused product kernel; for the general
+ * path, the span of its per-chunk contraction and Gamma kernels before the final reduction of
+ * the split sums): between firal_profile_begin and
+ * firal_profile_end the library records a HIP event pair on the call's stream around every
+ * launch of that kernel.  firal_profile_end synchronises the device and returns the summed
+ * kernel time in milliseconds (host double) and the number of launches (host int64); either
+ * pointer may be NULL.  Recording adds no synchronisation to the timed calls. */
+int firal_profile_begin(firal_ctx ctx);
+int firal_profile_end(firal_ctx ctx, double* total_ms, int64_t* launches);
+
 /* Static description of a return code. */
 const char* firal_strerror(int code);
 

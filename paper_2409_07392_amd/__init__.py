@@ -155,6 +155,17 @@ class RelaxContext:
                 for t in range(1, T + 1)]
         return b * w, hist
 
+    def profile_begin(self):
+        """Start timing every launch of the main product kernel with events on its stream."""
+        check(self.lib.firal_profile_begin(self._ctx))
+
+    def profile_end(self):
+        """Stop timing; returns (total kernel milliseconds, number of launches)."""
+        ms = _lib.ctypes.c_double()
+        n = _lib.ctypes.c_int64()
+        check(self.lib.firal_profile_end(self._ctx, _lib.ctypes.byref(ms), _lib.ctypes.byref(n)))
+        return ms.value, n.value
+
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             self.lib.firal_destroy(self._ctx)

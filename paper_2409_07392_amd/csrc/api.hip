@@ -7,6 +7,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
+#include <vector>
 
 #include "common.h"
 
@@ -33,7 +35,32 @@ int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, 
     }                                                                           \
   } while (0)
 
+typedef std::vector<std::pair<hipEvent_t, hipEvent_t>> EventPairs;
+
+static void drop_events(Ctx* x) {
+  if (!x->prof_events) return;
+  EventPairs* ev = (EventPairs*)x->prof_events;
+  for (auto& e : *ev) {
+    if (e.first) (void)hipEventDestroy(e.first);
+    if (e.second) (void)hipEventDestroy(e.second);
+  }
+  delete ev;
+  x->prof_events = nullptr;
+}
+
+int prof_mark(Ctx* x, hipStream_t st, bool start) {
+  if (!x->profiling) return FIRAL_OK;
+  EventPairs* ev = (EventPairs*)x->prof_events;
+  hipEvent_t e;
+  FIRAL_HIP(hipEventCreate(&e));
+  FIRAL_HIP(hipEventRecord(e, st));
+  if (start) ev->push_back({e, nullptr});
+  else ev->back().second = e;
+  return FIRAL_OK;
+}
+
 static void free_ctx(Ctx* x) {
+  drop_events(x);
   void* bufs[] = {x->G, x->part, x->fused_part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->V, x->W1, x->Y,
                   x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
@@ -88,6 +115,37 @@ const char* firal_strerror(int code) {
 }
 
 const char* firal_last_error(void) { return g_last_error; }
+
+int firal_profile_begin(firal_ctx ctx) {
+  FIRAL_REQ(ctx != nullptr, "null context");
+  Ctx* x = C(ctx);
+  drop_events(x);
+  x->prof_events = new EventPairs();
+  x->profiling = 1;
+  return FIRAL_OK;
+}
+
+int firal_profile_end(firal_ctx ctx, double* total_ms, int64_t* launches) {
+  FIRAL_REQ(ctx != nullptr, "null context");
+  Ctx* x = C(ctx);
+  FIRAL_REQ(x->profiling && x->prof_events, "profiling was not begun");
+  x->profiling = 0;
+  FIRAL_HIP(hipDeviceSynchronize());
+  EventPairs* ev = (EventPairs*)x->prof_events;
+  double sum = 0.0;
+  int64_t n = 0;
+  for (auto& e : *ev) {
+    if (!e.first || !e.second) continue;
+    float ms = 0.f;
+    FIRAL_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+    sum += ms;
+    ++n;
+  }
+  drop_events(x);
+  if (total_ms) *total_ms = sum;
+  if (launches) *launches = n;
+  return FIRAL_OK;
+}
 
 int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32_t c,
                  int32_t s_max, int32_t prec, const void* X, const void* H, void* stream) {
@@ -152,10 +210,18 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
 
   const char* unf = getenv("FIRAL_UNFUSED");
   x->force_unfused = unf && atoi(unf) != 0;
+  // BF16X3 PCG: switch to FP32 products below this relative residual (0 = never).  With the
+  // residual kept in the projected space the split products converge like FP32 ones, so
+  // the switch is off unless asked for.
+  const char* sw = getenv("FIRAL_BF3_SWITCH");
+  x->bf3_switch = sw ? atof(sw) : 0.0;
   x->fused_part_elems = 0;
   for (int s = 1; s <= s_max; ++s) {
-    FusedPlan fp;
-    if (fused_plan(x, s, x->N, &fp)) x->fused_part_elems = std::max(x->fused_part_elems, fp.part_elems);
+    for (int precise = 0; precise < 2; ++precise) {
+      FusedPlan fp;
+      if (fused_plan(x, s, x->N, &fp, precise != 0))
+        x->fused_part_elems = std::max(x->fused_part_elems, fp.part_elems);
+    }
   }
 
   const size_t es = x->esize;

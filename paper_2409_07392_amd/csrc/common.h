@@ -75,6 +75,7 @@ struct Ctx {
   void* fused_part;
   int64_t fused_part_elems;
   int force_unfused;    // FIRAL_UNFUSED=1: always take the general three-pass product
+  double bf3_switch;    // BF16X3 PCG: FP32 products once max_j ||r_j||/||b_j|| < bf3_switch
 
   // bf16x3 operands: hi/lo bf16 split of X (FP32 storage contexts only)
   void* Xhi;
@@ -109,7 +110,14 @@ struct Ctx {
   int32_t* counter;     // device: arrival counter of the column-local CG kernels (kept at 0)
   Status* status;       // device
   Status* status_host;  // pinned host mirror
+
+  // firal_profile_begin/end: event pairs around each main product kernel
+  int profiling;
+  void* prof_events;    // std::vector<std::pair<hipEvent_t, hipEvent_t>>*
 };
+
+// record an event on `st` when profiling (start: true before the kernel, false after)
+int prof_mark(Ctx* x, hipStream_t st, bool start);
 
 inline Ctx* C(firal_ctx p) { return reinterpret_cast<Ctx*>(p); }
 
@@ -213,7 +221,7 @@ struct FusedPlan {
   size_t lds_bytes;
   int64_t part_elems;   // n_splits * d * s * c
 };
-bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p);
+bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p, bool precise = false);
 template <typename T>
 int reduce_parts_launch(const T* part, int64_t n, int P, double shift, const T* B, T* out,
                         Skip skip, hipStream_t st);
@@ -222,8 +230,9 @@ int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_
 
 // ------------------------------------------------- host-side launchers
 // All enqueue on `st`; `skip` (see Skip) makes every kernel of the call return at once.
+// precise: in a BF16X3 context, take the FP32 products for this call (mixed-precision PCG)
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
-               void* out, int s, Skip skip, hipStream_t st);
+               void* out, int s, Skip skip, hipStream_t st, bool precise = false);
 int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st);
 int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,
                void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,

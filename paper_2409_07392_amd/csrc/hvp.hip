@@ -233,6 +233,7 @@ static int hvp_t(Ctx* x, const double* omega, int64_t n_rows, double shift, cons
   const int64_t tiles = cdiv(d, TM) * cdiv(SC, TN);
   const int64_t cap = (int64_t)x->max_splits * x->s_max / s;
   int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, tiles), cap), 256));
+  FIRAL_CHECK(prof_mark(x, st, true));
   for (int64_t r0 = 0; r0 < n_rows; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, n_rows - r0);
     FIRAL_CHECK(launch_gemm_xb<T>(X + r0 * d, d, B, SC, G, R, skip, st));
@@ -244,13 +245,14 @@ static int hvp_t(Ctx* x, const double* omega, int64_t n_rows, double shift, cons
     k_gemm_xtg<T><<<grid, 256, 0, st>>>(X + r0 * d, d, G, SC, R, rps, part, n_out, r0 > 0, skip);
     FIRAL_LAUNCHED();
   }
+  FIRAL_CHECK(prof_mark(x, st, false));
   return reduce_parts_launch<T>(part, n_out, n_rows > 0 ? S : 0, shift, B, out, skip, st);
 }
 
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
-               void* out, int s, Skip skip, hipStream_t st) {
+               void* out, int s, Skip skip, hipStream_t st, bool precise) {
   FusedPlan plan;
-  if (x->prec != FIRAL_F64 && !x->force_unfused && fused_plan(x, s, n_rows, &plan) &&
+  if (x->prec != FIRAL_F64 && !x->force_unfused && fused_plan(x, s, n_rows, &plan, precise) &&
       plan.part_elems <= x->fused_part_elems)
     return hvp_fused_launch(x, plan, omega, n_rows, shift, (const float*)B, (float*)out, s, skip,
                             st);

@@ -491,11 +491,12 @@ static FusedKernel pick(int D16, int ncb) {
 
 // Tile plan of the fused product for a call with s probes (FP32 contexts only).
 // Returns false when the shape is outside what the fused kernel holds in registers/LDS.
-bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p) {
+bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p, bool precise) {
   if (x->prec == FIRAL_F64 || n_rows <= 0) return false;
   const int d = x->d, c = x->c;
   const int D16 = (d + 15) / 16;
-  if (D16 > 16 || (x->prec == FIRAL_BF16X3 && D16 > 8)) return false;
+  const bool bf3 = x->prec == FIRAL_BF16X3 && !precise;
+  if (D16 > 16 || (bf3 && D16 > 8)) return false;
   const int max_ncb = D16 <= 8 ? 2 : 1;
   // widest tile of whole probes whose 16-column blocks fit max_ncb per wave
   const int max_cols = max_ncb * kNW * 16;
@@ -505,7 +506,6 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p) {
   pp = (s + n_ct - 1) / n_ct;            // balance the tiles
   const int C16 = (pp * c + 15) / 16;
   const int ncb = (C16 + kNW - 1) / kNW;
-  const bool bf3 = x->prec == FIRAL_BF16X3;
   FusedGeom g = fused_geom(D16, C16, c);
   size_t lds_bytes = g.lds_floats * 4;
   if (bf3) {
@@ -552,11 +552,13 @@ int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_
   const int SC = s * x->c;
   const int nwg = (int)(((int64_t)p.n_splits * p.n_ctiles + 7) / 8 * 8);
   float* part = (float*)x->fused_part;
+  FIRAL_CHECK(prof_mark(x, st, true));
   k<<<nwg, kThreads, p.lds_bytes, st>>>((const float*)x->X, (const float*)x->H, omega, n_rows,
                                         x->d, x->c, SC, B, p.probes_per_tile, s, p.n_ctiles,
                                         p.rows_per_split, p.n_splits, p.XS, p.XT, p.GT, p.CP,
                                         part, skip);
   FIRAL_LAUNCHED();
+  FIRAL_CHECK(prof_mark(x, st, false));
   return reduce_parts_launch<float>(part, (int64_t)x->d * SC, p.n_splits, shift, B, out, skip, st);
 }
 

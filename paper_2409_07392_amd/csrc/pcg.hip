@@ -433,14 +433,31 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv,
     return;
   }
   const T at = (T)(rho[j] / pq);
-  double rr = 0.0;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int k = e / d, a = e - k * d;
     const int64_t gi = a * sc + (int64_t)j * c + k;
     const T pv = p[gi];
     xv[gi] += at * pv;
-    const T rv = r[gi] - at * q[gi];
-    r[gi] = rv;
+    r0s[e] = (double)(r[gi] - at * q[gi]);
+  }
+  __syncthreads();
+  if (project) {
+    // r stays in the complement of {1_c (x) u} in exact arithmetic; remove the rounding
+    // (the split products of BF16X3 leave ~1e-5 there, which the projected preconditioner
+    // never searches, so it would floor the residual)
+    for (int a = threadIdx.x; a < d; a += blockDim.x) {
+      double m = 0.0;
+      for (int k = 0; k < c; ++k) m += r0s[k * d + a];
+      m /= c;
+      for (int k = 0; k < c; ++k) r0s[k * d + a] -= m;
+    }
+    __syncthreads();
+  }
+  double rr = 0.0;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int k = e / d, a = e - k * d;
+    const T rv = (T)r0s[e];
+    r[a * sc + (int64_t)j * c + k] = rv;
     rs[e] = (double)rv;
     r0s[e] = (double)rv;
     rr += (double)rv * (double)rv;
@@ -544,6 +561,11 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
     k_cg_col_init<T><<<s, kColThreads, col_lds, st>>>(B, xv, r, p, Pinv, d, s, c, project, x->rho,
                                                       x->bnorm, x->relres, flags[0], x->status);
     FIRAL_LAUNCHED();
+    // Mixed precision (BF16X3): bf16x3 products while every column's relative residual is
+    // above bf3_switch, FP32 products from the first check point where none is.  The switch
+    // keeps the operator error of the split products from stalling the last iterations.
+    const bool mixed = x->prec == FIRAL_BF16X3 && tol > 0.0;
+    bool precise = false;
     const int check_every = tol > 0.0 ? 4 : (max_iter > 0 ? max_iter : 1);
     int launched = 0;
     while (launched < max_iter) {
@@ -551,7 +573,7 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
       for (int it = 0; it < batch; ++it) {
         const int32_t* dp = flags[(launched + it) & 1];
         int32_t* dn = flags[(launched + it + 1) & 1];
-        FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip_all(dp, s), st));
+        FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip_all(dp, s), st, precise));
         k_cg_col_step<T><<<s, kColThreads, col_lds, st>>>(xv, r, p, q, Pinv, d, s, c, project, tol,
                                                           x->rho, x->bnorm, x->relres, dp, dn,
                                                           x->status);
@@ -563,6 +585,7 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
       if (launched < max_iter) {
         FIRAL_CHECK(read_status(x, st));
         if (x->status_host->all_done) break;
+        if (mixed && x->status_host->relres_max < x->bf3_switch) precise = true;
       }
     }
     if (max_iter == 0) {
@@ -589,17 +612,23 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
   k_cg_init<<<1, 64, 0, st>>>(part0, part1, s, P, x->status, x->rho, x->bnorm, x->relres, x->done);
   FIRAL_LAUNCHED();
 
+  const bool mixed = x->prec == FIRAL_BF16X3 && tol > 0.0;
+  bool precise = false;
   const int check_every = tol > 0.0 ? 4 : (max_iter > 0 ? max_iter : 1);
   int launched = 0;
   while (launched < max_iter) {
     const int batch = std::min(check_every, max_iter - launched);
     for (int it = 0; it < batch; ++it) {
-      FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip, st));
+      FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip, st, precise));
       FIRAL_CHECK(coldot_launch(x, p, q, s, part0, skip, st));
       k_cg_alpha<<<1, 64, 0, st>>>(part0, s, P, x->status, x->rho, x->done, x->alpha);
       FIRAL_LAUNCHED();
       k_cg_update<T><<<nb, 256, 0, st>>>(xv, r, p, q, x->alpha, n, s, c, skip);
       FIRAL_LAUNCHED();
+      if (project) {   // keep r in the projected space (removes rounding only)
+        k_project<T><<<(unsigned)cdiv((int64_t)d * s, 256), 256, 0, st>>>(r, r, d, s, c, skip);
+        FIRAL_LAUNCHED();
+      }
       FIRAL_CHECK(coldot_launch(x, r, r, s, part1, skip, st));
       k_cg_done<<<1, 64, 0, st>>>(part1, s, P, x->status, x->bnorm, x->relres, x->done, tol);
       FIRAL_LAUNCHED();
@@ -614,6 +643,7 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
     if (launched < max_iter) {
       FIRAL_CHECK(read_status(x, st));
       if (x->status_host->all_done) break;
+      if (mixed && x->status_host->relres_max < x->bf3_switch) precise = true;
     }
   }
   k_cg_finish<<<1, 1, 0, st>>>(x->status, slot);
