@@ -29,7 +29,7 @@ KERNEL_NAME = {"f32": "k_hvp_fused<7,2> (fused Lemma 1 product, FP32)",
 # HBM bytes per launch of the main kernel from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # each scaled by the copy-kernel calibration factor (profiles/; None until measured for
 # the current kernel)
-TRAFFIC = {}
+TRAFFIC = {"f32": (23.27 + 17.93) * 1e6}   # k_hvp_fused<7,2>: fetched + written bytes per launch
 
 
 def parse():
