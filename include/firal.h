@@ -141,6 +141,20 @@ int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double b
                      uint64_t seed, int32_t t, int32_t s, double tol, int32_t max_iter,
                      uint32_t flags, double* g_out, firal_info* info, void* stream);
 
+/* Sampled objective and its gradient (the objective of eq. 4-5 with the trace replaced by
+ * the Hutchinson estimate of eq. 11 for a fixed probe block V):
+ *   f_V(z) = (1/s) sum_j v_j^T Sigma_z^-1 H_p v_j,   Sigma_z = H_o + H_z + lambda I (eq. 7),
+ *   df_V/dz_i = -(1/s) sum_j (Sigma_z^-1 v_j)^T H_i (Sigma_z^-1 H_p v_j)   (i in the pool),
+ * the exact derivative of f_V (dSigma_z/dz_i = H_i): preconditioner at z, U = Sigma^-1 V,
+ * Y = H_p V, f from <U, Y>; with g: Y' = Sigma^-1 Y and the eq. 11 contraction of U and Y'.
+ * z: device FP64 [n_pool] (any positive weights, not normalised); V: device block d x s x c;
+ * f: host double; g: device FP64 [n_pool] or NULL for the objective alone.  PCG as in
+ * firal_pcg_solve (tol, max_iter, flags).  Synchronous; info gets cg_iters (solve of V, solve
+ * of H_p V), converged, relres_max and f_hat. */
+int firal_sampled_objective(firal_ctx ctx, const double* z, double lambda, const void* V,
+                            int32_t s, double tol, int32_t max_iter, uint32_t flags, double* f,
+                            double* g, firal_info* info, void* stream);
+
 /* Measurement of the main Hessian-product kernel (the fused product kernel; for the general
  * path, the span of its per-chunk contraction and Gamma kernels before the final reduction of
  * the split sums): between firal_profile_begin and

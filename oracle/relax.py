@@ -348,7 +348,8 @@ def relax(X, H, n_pool, b, lam, beta0, seed, T, s, tol, max_iter, project=False,
 def sampled_objective(X, H, n_pool, z, lam, V, tol, max_iter, project=False):
     """f_V(z) = (1/s) sum_j v_j^T Sigma_z^-1 H_p v_j with Sigma_z = H_o + H_z + lam I.
 
-    Returns (f, U, Yp) with U = Sigma^-1 V and Yp = H_p V (reused by the adjoint).
+    Returns (f, U, Yp, L): U = Sigma^-1 V, Yp = H_p V and the preconditioner factor
+    (reused by the adjoint).
     """
     N, d = X.shape
     s = V.shape[1]

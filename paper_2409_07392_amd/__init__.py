@@ -15,7 +15,8 @@ from . import _lib
 from ._lib import (BF16X3, F32, F64, PCG_PROJECT, FiralError, Info, WARN_NOT_CONVERGED, check,
                    load)
 
-__all__ = ["RelaxContext", "FiralError", "default_beta0", "F64", "F32", "BF16X3", "load"]
+__all__ = ["RelaxContext", "RelaxObjective", "FiralError", "default_beta0", "F64", "F32",
+           "BF16X3", "load"]
 
 _DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32}
 
@@ -155,6 +156,23 @@ class RelaxContext:
                 for t in range(1, T + 1)]
         return b * w, hist
 
+    def sampled_objective(self, z, lam, V, tol=1e-10, max_iter=1000, project=True, grad=True):
+        """f_V(z) = (1/s) sum_j v_j^T Sigma_z^-1 H_p v_j and, if grad, df_V/dz (FP64 CUDA)."""
+        z = self._f64(z, self.n_pool)
+        V = self._blk(V)
+        g = torch.empty(self.n_pool, dtype=torch.float64, device=self.X.device) if grad else None
+        f = _lib.ctypes.c_double()
+        info = Info()
+        rc = self.lib.firal_sampled_objective(self._ctx, _ptr(z), float(lam), _ptr(V), V.shape[1],
+                                              float(tol), int(max_iter),
+                                              PCG_PROJECT if project else 0,
+                                              _lib.ctypes.byref(f), _ptr(g),
+                                              _lib.ctypes.byref(info), _stream())
+        check(rc)
+        d = info.as_dict()
+        d["rc"] = rc
+        return f.value, g, d
+
     def profile_begin(self):
         """Start timing every launch of the main product kernel with events on its stream."""
         check(self.lib.firal_profile_begin(self._ctx))
@@ -176,3 +194,29 @@ class RelaxContext:
             self.close()
         except Exception:
             pass
+
+
+class RelaxObjective(torch.autograd.Function):
+    """f_V(z) = (1/s) sum_j v_j^T Sigma_z^-1 H_p v_j as a differentiable function of z.
+
+    The backward pass is the adjoint of the sampled objective,
+    df_V/dz_i = -(1/s) sum_j (Sigma^-1 v_j)^T H_i (Sigma^-1 H_p v_j): two PCG solves and the
+    per-point contraction, all in the library (firal_sampled_objective).  The forward computes
+    the gradient along with f when z requires it (the solves it needs are shared).
+
+        f = RelaxObjective.apply(z, relax_ctx, V, lam, tol, max_iter, project)
+    """
+
+    @staticmethod
+    def forward(ctx, z, relax_ctx, V, lam, tol=1e-10, max_iter=1000, project=True):
+        need = ctx.needs_input_grad[0]
+        f, g, _ = relax_ctx.sampled_objective(z.detach(), lam, V, tol, max_iter, project,
+                                              grad=need)
+        if need:
+            ctx.save_for_backward(g)
+        return torch.tensor(f, dtype=torch.float64, device=z.device)
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        (g,) = ctx.saved_tensors
+        return grad_f * g, None, None, None, None, None, None

@@ -17,7 +17,8 @@ PCG_PROJECT = 1
 # every symbol include/firal.h declares
 EXPORTS = ("firal_create", "firal_destroy", "firal_hvp", "firal_build_precond",
            "firal_pcg_solve", "firal_grad_z", "firal_probes", "firal_relax_step",
-           "firal_profile_begin", "firal_profile_end", "firal_strerror", "firal_last_error")
+           "firal_sampled_objective", "firal_profile_begin", "firal_profile_end",
+           "firal_strerror", "firal_last_error")
 
 
 class Info(ctypes.Structure):
@@ -64,6 +65,8 @@ def load() -> ctypes.CDLL:
         "firal_grad_z": [vp, vp, vp, i32, vp, vp],
         "firal_probes": [vp, u64, i32, i32, vp, vp],
         "firal_relax_step": [vp, vp, dbl, dbl, dbl, u64, i32, i32, dbl, i32, u32, vp, pinfo, vp],
+        "firal_sampled_objective": [vp, vp, dbl, vp, i32, dbl, i32, u32, ctypes.POINTER(dbl), vp,
+                                    pinfo, vp],
         "firal_profile_begin": [vp],
         "firal_profile_end": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         "firal_strerror": [ctypes.c_int],

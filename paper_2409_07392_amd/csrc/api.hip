@@ -26,6 +26,8 @@ void set_error(const char* fmt, ...) {
 int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, uint64_t seed,
                       int t, int s, double tol, int max_iter, uint32_t flags, double* g_out,
                       hipStream_t st);
+int objective_launch(Ctx* x, const double* z, double lambda, const void* V, int s, double tol,
+                     int max_iter, uint32_t flags, double* g, hipStream_t st);
 
 #define FIRAL_REQ(cond, ...)                                                    \
   do {                                                                          \
@@ -368,6 +370,42 @@ int firal_probes(firal_ctx ctx, uint64_t seed, int32_t t, int32_t s, void* V, vo
   FIRAL_REQ(V != nullptr, "null V");
   FIRAL_REQ(t >= 1, "t = %d < 1", t);
   return probes_launch(C(ctx), seed, t, s, V, (hipStream_t)stream);
+}
+
+int firal_sampled_objective(firal_ctx ctx, const double* z, double lambda, const void* V,
+                            int32_t s, double tol, int32_t max_iter, uint32_t flags, double* f,
+                            double* g, firal_info* info, void* stream) {
+  FIRAL_CHECK(check_common(ctx, s));
+  Ctx* x = C(ctx);
+  FIRAL_REQ(z != nullptr && V != nullptr && f != nullptr, "null z, V or f");
+  FIRAL_REQ(lambda >= 0.0, "lambda < 0");
+  FIRAL_REQ(tol >= 0.0, "tol < 0");
+  FIRAL_REQ(max_iter >= 0, "max_iter < 0");
+  FIRAL_REQ((flags & ~FIRAL_PCG_PROJECT) == 0, "unknown flags 0x%x", flags);
+  hipStream_t st = (hipStream_t)stream;
+  FIRAL_CHECK(objective_launch(x, z, lambda, V, s, tol, max_iter, flags, g, st));
+  FIRAL_CHECK(finish_sync(x, st));
+  const Status& h = *x->status_host;
+  const int bad = h.bad_block == INT_MAX ? -1 : h.bad_block;
+  *f = h.f_hat;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->cg_iters[0] = h.cg_iters[0];
+    info->cg_iters[1] = h.cg_iters[1];
+    info->converged = h.converged;
+    info->bad_block = bad;
+    info->relres_max = h.relres_max;
+    info->f_hat = h.f_hat;
+  }
+  if (bad >= 0) {
+    set_error("preconditioner block %d is not positive definite", bad);
+    return FIRAL_ENOTSPD;
+  }
+  if (h.breakdown) {
+    set_error("PCG breakdown (p^T q <= 0)");
+    return FIRAL_EBREAKDOWN;
+  }
+  return h.converged ? FIRAL_OK : FIRAL_WARN_NOT_CONVERGED;
 }
 
 int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double beta0,

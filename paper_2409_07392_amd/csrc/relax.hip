@@ -219,6 +219,33 @@ __global__ void k_relres_merge(Status* st, double* keep) {
   st->relres_max = *keep;
 }
 
+int objective_launch(Ctx* x, const double* z, double lambda, const void* V, int s, double tol,
+                     int max_iter, uint32_t flags, double* g, hipStream_t st) {
+  const int64_t n = x->n_pool, N = x->N;
+  k_step_reset<<<1, 1, 0, st>>>(x->status);
+  FIRAL_LAUNCHED();
+  k_omega<<<(unsigned)cdiv(N, 256), 256, 0, st>>>(z, 1.0, n, N, x->omega);
+  FIRAL_LAUNCHED();
+  FIRAL_CHECK(precond_launch(x, x->omega, lambda, st));
+  double* keep = x->redpart + 3 * x->red_blocks;
+  FIRAL_HIP(hipMemsetAsync(keep, 0, sizeof(double), st));
+  FIRAL_CHECK(pcg_launch(x, x->omega, lambda, x->Pinv, V, x->W1, s, tol, max_iter, flags, 0, st));
+  k_relres_merge<<<1, 1, 0, st>>>(x->status, keep);
+  FIRAL_LAUNCHED();
+  FIRAL_CHECK(hvp_launch(x, nullptr, n, 0.0, V, x->Y, s, skip_none(), st));
+  FIRAL_CHECK(coldot_launch(x, x->W1, x->Y, s, x->colpart, skip_none(), st));
+  k_fhat<<<1, 256, 0, st>>>(x->colpart, s, x->col_parts, x->status);
+  FIRAL_LAUNCHED();
+  if (g) {
+    FIRAL_CHECK(pcg_launch(x, x->omega, lambda, x->Pinv, x->Y, x->W2, s, tol, max_iter, flags, 1,
+                           st));
+    k_relres_merge<<<1, 1, 0, st>>>(x->status, keep);
+    FIRAL_LAUNCHED();
+    FIRAL_CHECK(grad_launch(x, x->W1, x->W2, s, g, st));
+  }
+  return FIRAL_OK;
+}
+
 int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, uint64_t seed,
                       int t, int s, double tol, int max_iter, uint32_t flags, double* g_out,
                       hipStream_t st) {
