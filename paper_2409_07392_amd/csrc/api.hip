@@ -63,7 +63,7 @@ int prof_mark(Ctx* x, hipStream_t st, bool start) {
 
 static void free_ctx(Ctx* x) {
   drop_events(x);
-  void* bufs[] = {x->G, x->part, x->fused_part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->V, x->W1, x->Y,
+  void* bufs[] = {x->G, x->abuf, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->V, x->W1, x->Y,
                   x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
                   x->redpart, x->status, x->counter};
@@ -191,18 +191,18 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   }
   const int64_t blk = (int64_t)d * s_max * c;        // elements per block
   const int64_t sc = (int64_t)s_max * c;
-  // row-chunked intermediates: two (rows x s*c) buffers within ~2 GiB
+  // row-chunked intermediate: one (rows x s*c) buffer within ~2 GiB
   const int64_t budget = (int64_t)2 << 30;
-  int64_t rows = budget / (2 * sc * (int64_t)x->esize);
-  rows = std::max<int64_t>(64, std::min<int64_t>(rows, x->N));
-  rows = std::min<int64_t>(rows, (int64_t)65535 * 64);   // grid.y of the row-tiled GEMM
+  int64_t rows = budget / (sc * (int64_t)x->esize);
+  rows = std::max<int64_t>(128, std::min<int64_t>(rows, x->N));
   if (const char* env = getenv("FIRAL_CHUNK_ROWS")) {   // smaller chunks, for tests of the chunked path
     const long long v = atoll(env);
     if (v >= 1 && v < rows) rows = v;
   }
   x->chunk_rows = rows;
-  const int64_t tiles = cdiv(d, 64) * cdiv(sc, 64);
+  const int64_t tiles = tiled_out_tiles(prec, d, sc);
   x->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, tiles), 64));
+  const int64_t awin = tiled_alpha_windows(prec, c), gwin = tiled_grad_windows(prec, c);
   const int nb = (int)cdiv(d, 16);
   const int npairs = nb * (nb + 1) / 2;
   const int64_t syrk_wgs = (int64_t)npairs * cdiv(c, 16);
@@ -230,7 +230,9 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   int rc = FIRAL_OK;
 #define ALLOC(ptr, bytes)                                          \
   if (rc == FIRAL_OK) rc = dmalloc((void**)&(ptr), (size_t)(bytes))
-  ALLOC(x->G, 2 * rows * sc * es);
+  ALLOC(x->G, rows * sc * es);
+  ALLOC(x->abuf, rows * s_max * awin * es);
+  ALLOC(x->gpart, std::min<int64_t>(rows, n_pool) * s_max * gwin * 3 * 8);
   ALLOC(x->part, (int64_t)x->max_splits * blk * es);
   ALLOC(x->fused_part, x->fused_part_elems * 4);
   ALLOC(x->P, (int64_t)c * d * d * 8);

@@ -67,7 +67,9 @@ struct Ctx {
 
   // hvp / grad row-chunk intermediates
   int64_t chunk_rows;   // rows per chunk of the (rows x s*c) intermediate
-  void* G;              // 2 * chunk_rows * s_max * c elements
+  void* G;              // chunk_rows * s_max * c elements
+  void* abuf;           // chunk_rows * s_max * alpha_windows elements: per-window row sums
+  double* gpart;        // chunk_rows * s_max * grad_windows * 3: gradient partial sums
   int max_splits;       // split-K partial buffers for the X^T G contraction
   void* part;           // max_splits * d * s_max * c elements
 
@@ -238,9 +240,15 @@ int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, co
                void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
                hipStream_t st);
 int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st);
+// general (any d, c) product through the row-tiled kernels of tiled.hip
+int hvp_tiled_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
+                     void* out, int s, Skip skip, hipStream_t st);
+// buffer sizing of the row-tiled kernels
+int tiled_alpha_windows(int prec, int c);
+int tiled_grad_windows(int prec, int c);
+int64_t tiled_out_tiles(int prec, int d, int64_t sc);
 int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st);
 int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, Skip skip,
                   hipStream_t st);
-int bf16_split_launch(Ctx* x, hipStream_t st);
 
 }  // namespace firal

@@ -1,6 +1,6 @@
-// Rademacher probes, the eq. 11 per-point gradient contraction, the entropic
-// mirror-descent update, and one full iteration of the fast Relax solve
-// (Algorithm 2).
+// Rademacher probes, the entropic mirror-descent update, the sampled objective
+// and one full iteration of the fast Relax solve (Algorithm 2).  The eq. 11
+// per-point gradient contraction is in tiled.hip.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -8,9 +8,6 @@
 #include "common.h"
 
 namespace firal {
-
-int gemm_xb_launch(Ctx* x, const void* Xrows, const void* Bm, int SC, void* G, int64_t R,
-                   Skip skip, hipStream_t st);
 
 // ------------------------------------------------------------- probes
 // SplitMix64 (Steele, Lea & Flood 2014): output m of the stream seeded with `seed` is the
@@ -49,54 +46,6 @@ int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st) 
 // ----------------------------------------------------------- gradient
 // g[r] = -(1/s) sum_j [ sum_k A h B - (A.h)(B.h) ]  with A = X U, B = X W row r
 // (Lemma 1: u^T H_i w = (U^T x_i)^T Gamma_i (W^T x_i)).  FP64 accumulation.
-template <typename T>
-__global__ __launch_bounds__(256) void k_grad_rows(const T* __restrict__ A, const T* __restrict__ B,
-                                                   const T* __restrict__ H, int64_t R, int s,
-                                                   int c, double* __restrict__ g) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  const int64_t sc = (int64_t)s * c;
-  const T* a = A + r * sc;
-  const T* b = B + r * sc;
-  const T* h = H + r * c;
-  double q = 0.0;
-  for (int j = 0; j < s; ++j) {
-    double sab = 0.0, sa = 0.0, sb = 0.0;
-    for (int k = 0; k < c; ++k) {
-      const double hk = (double)h[k];
-      const double ak = (double)a[j * c + k] * hk;
-      const double bk = (double)b[j * c + k];
-      sab += ak * bk;
-      sa += ak;
-      sb += bk * hk;
-    }
-    q += sab - sa * sb;
-  }
-  g[r] = -q / s;
-}
-
-int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st) {
-  const int d = x->d, c = x->c, SC = s * c;
-  const int64_t half = x->chunk_rows * (int64_t)x->s_max * c;
-  for (int64_t r0 = 0; r0 < x->n_pool; r0 += x->chunk_rows) {
-    const int64_t R = std::min<int64_t>(x->chunk_rows, x->n_pool - r0);
-    const char* Xr = (const char*)x->X + r0 * d * x->esize;
-    const char* Hr = (const char*)x->H + r0 * c * x->esize;
-    void* G0 = x->G;
-    void* G1 = (char*)x->G + half * x->esize;
-    FIRAL_CHECK(gemm_xb_launch(x, Xr, U, SC, G0, R, skip_none(), st));
-    FIRAL_CHECK(gemm_xb_launch(x, Xr, W, SC, G1, R, skip_none(), st));
-    if (x->prec == FIRAL_F64)
-      k_grad_rows<double><<<(unsigned)cdiv(R, 256), 256, 0, st>>>(
-          (const double*)G0, (const double*)G1, (const double*)Hr, R, s, c, g + r0);
-    else
-      k_grad_rows<float><<<(unsigned)cdiv(R, 256), 256, 0, st>>>(
-          (const float*)G0, (const float*)G1, (const float*)Hr, R, s, c, g + r0);
-    FIRAL_LAUNCHED();
-  }
-  return FIRAL_OK;
-}
-
 // ----------------------------------------------------- mirror descent
 // Four passes with per-block partials re-reduced in a fixed order by every block:
 //   (1) max|g|   (2) beta = beta0/max|g|, e = log w - beta g, max e

@@ -116,6 +116,38 @@ def test_hvp_f32_fused_and_general_paths(shape, unfused, monkeypatch):
     assert_close(got, orc.hvp(X[:n], H[:n], None, 0.0, B[:, :1]), TOL["f32"], "s=1")
 
 
+# Column modes of the row-tiled kernels (any d, c): whole probes per tile with short (c <= 32)
+# or long segments, probes cut into column windows (c above the tile width), one-column last
+# windows, d over many pipeline stages, and configuration 4's d and c.
+TILED_SHAPES = [  # n_pool, n_lab, d, c, s
+    (700, 5, 40, 300, 2),       # c > 128: three product windows, five gradient windows
+    (400, 3, 70, 129, 3),       # a one-column last product window
+    (350, 1, 24, 64, 3),        # two probes per product tile, one per gradient tile
+    (520, 4, 33, 65, 2),        # a one-column last gradient window
+    (300, 2, 300, 7, 17),       # 16 short probes per tile plus a ragged tile; 19 k-stages
+    (1500, 10, 384, 1000, 2),   # configuration 4's d and c
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", TILED_SHAPES)
+def test_tiled_hvp_and_grad(prec, shape, monkeypatch):
+    monkeypatch.setenv("FIRAL_UNFUSED", "1")
+    n, nl, d, c, s = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=25)
+    ctx, X, H = context(p, prec, s)
+    rng = np.random.default_rng(21)
+    B = rounded(rng.standard_normal((d, s, c)), prec)
+    om = rng.uniform(0.0, 2.0, p.N)
+    got = host(ctx.hvp(dev(B, DT[prec]), omega=dev(om, torch.float64), shift=0.5))
+    assert_close(got, orc.hvp(X, H, om, 0.5, B), TOL[prec], f"hvp {prec} {shape}")
+    got = host(ctx.hvp(dev(B, DT[prec]), n_rows=n))
+    assert_close(got, orc.hvp(X[:n], H[:n], None, 0.0, B), TOL[prec], f"H_p {prec} {shape}")
+    U = rounded(rng.choice([-1.0, 1.0], size=(d, s, c)), prec)
+    g = host(ctx.grad_z(dev(U, DT[prec]), dev(B, DT[prec])))
+    assert_close(g, orc.grad_contract(X[:n], H[:n], U, B), 10 * TOL[prec], f"grad {shape}")
+
+
 def test_hvp_f32_full_configuration_2():
     # the bench workload at full size, in the launch configuration the bench times
     p = make_problem(2)
