@@ -63,7 +63,7 @@ int prof_mark(Ctx* x, hipStream_t st, bool start) {
 
 static void free_ctx(Ctx* x) {
   drop_events(x);
-  void* bufs[] = {x->G, x->abuf, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->V, x->W1, x->Y,
+  void* bufs[] = {x->G, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->syrk_tiles, x->V, x->W1, x->Y,
                   x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
                   x->redpart, x->status, x->counter};
@@ -202,11 +202,10 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   x->chunk_rows = rows;
   const int64_t tiles = tiled_out_tiles(prec, d, sc);
   x->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, tiles), 64));
-  const int64_t awin = tiled_alpha_windows(prec, c), gwin = tiled_grad_windows(prec, c);
-  const int nb = (int)cdiv(d, 16);
-  const int npairs = nb * (nb + 1) / 2;
-  const int64_t syrk_wgs = (int64_t)npairs * cdiv(c, 16);
-  x->syrk_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, syrk_wgs), 64));
+
+  std::vector<int32_t> syrk_tiles;
+  syrk_plan(prec, d, c, &syrk_tiles, &x->syrk_splits);
+  x->syrk_ntiles = (int)(syrk_tiles.size() / 2);
   x->col_parts = (int)std::max<int64_t>(1, std::min<int64_t>(d, cdiv(256, s_max)));
   x->red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n_pool, 256), 1024));
 
@@ -231,13 +230,13 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
 #define ALLOC(ptr, bytes)                                          \
   if (rc == FIRAL_OK) rc = dmalloc((void**)&(ptr), (size_t)(bytes))
   ALLOC(x->G, rows * sc * es);
-  ALLOC(x->abuf, rows * s_max * awin * es);
-  ALLOC(x->gpart, std::min<int64_t>(rows, n_pool) * s_max * gwin * 3 * 8);
+  ALLOC(x->gpart, std::min<int64_t>(rows, n_pool) * tiled_col_tiles(prec, c, s_max) * 8);
   ALLOC(x->part, (int64_t)x->max_splits * blk * es);
   ALLOC(x->fused_part, x->fused_part_elems * 4);
   ALLOC(x->P, (int64_t)c * d * d * 8);
   ALLOC(x->Pinv, (int64_t)c * d * d * 8);
-  ALLOC(x->syrk_part, (int64_t)x->syrk_splits * c * npairs * 256 * es);
+  ALLOC(x->syrk_part, (int64_t)x->syrk_splits * c * d * d * es);
+  ALLOC(x->syrk_tiles, syrk_tiles.size() * sizeof(int32_t));
   ALLOC(x->V, blk * es);
   ALLOC(x->W1, blk * es);
   ALLOC(x->Y, blk * es);
@@ -273,6 +272,8 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
     hipStream_t st = (hipStream_t)stream;
     if (hipMemsetAsync(x->status, 0, sizeof(Status), st) != hipSuccess ||
         hipMemsetAsync(x->counter, 0, sizeof(int32_t), st) != hipSuccess ||
+        hipMemcpyAsync(x->syrk_tiles, syrk_tiles.data(), syrk_tiles.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
       set_error("status initialisation failed");
       rc = FIRAL_EHIP;

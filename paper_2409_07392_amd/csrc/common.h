@@ -6,6 +6,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <vector>
+
 #include "firal.h"
 
 namespace firal {
@@ -68,8 +70,7 @@ struct Ctx {
   // hvp / grad row-chunk intermediates
   int64_t chunk_rows;   // rows per chunk of the (rows x s*c) intermediate
   void* G;              // chunk_rows * s_max * c elements
-  void* abuf;           // chunk_rows * s_max * alpha_windows elements: per-window row sums
-  double* gpart;        // chunk_rows * s_max * grad_windows * 3: gradient partial sums
+  double* gpart;        // column tiles * chunk_rows: per-tile row dot products (gradient)
   int max_splits;       // split-K partial buffers for the X^T G contraction
   void* part;           // max_splits * d * s_max * c elements
 
@@ -86,8 +87,10 @@ struct Ctx {
   // preconditioner
   double* P;            // c * d * d: blocks, factorised in place
   double* Pinv;         // c * d * d
-  void* syrk_part;      // syrk_splits * c * npairs * 256 elements
+  void* syrk_part;      // syrk_splits * c * d * d elements (lower triangles written)
   int syrk_splits;
+  int32_t* syrk_tiles;  // (a-block, b-block) of each pair tile of the Gram GEMM
+  int syrk_ntiles;
 
   // Relax / PCG blocks (d * s_max * c elements each)
   void *V, *W1, *Y, *W2;
@@ -152,6 +155,29 @@ template <> struct Mfma16<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
 };
+
+// bf16x3 products: x y ~ xh yh + xh yl + xl yh with xh = bf16(x) (round to nearest even) and
+// xl = bf16(x - xh), each on the 16x16x32 bf16 MFMA with FP32 accumulation.  Lane l supplies
+// A[l%16][8(l/16) + u] and B[8(l/16) + u][l%16], u = 0..7, and receives D as the FP32
+// 16x16x4 instruction does (row 4(l/16) + v).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const __bf16 h = (__bf16)v[u];
+    hi[u] = h;
+    lo[u] = (__bf16)(v[u] - (float)h);
+  }
+}
+
+__device__ __forceinline__ f32x4 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
+                                       const bf16x8& bl, f32x4 acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+  return acc;
+}
 
 // ------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
@@ -236,16 +262,16 @@ int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
                void* out, int s, Skip skip, hipStream_t st, bool precise = false);
 int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st);
+void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits);
 int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,
                void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
                hipStream_t st);
 int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st);
 // general (any d, c) product through the row-tiled kernels of tiled.hip
 int hvp_tiled_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
-                     void* out, int s, Skip skip, hipStream_t st);
+                     void* out, int s, Skip skip, hipStream_t st, bool precise);
 // buffer sizing of the row-tiled kernels
-int tiled_alpha_windows(int prec, int c);
-int tiled_grad_windows(int prec, int c);
+int64_t tiled_col_tiles(int prec, int c, int s);
 int64_t tiled_out_tiles(int prec, int d, int64_t sc);
 int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st);
 int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, Skip skip,

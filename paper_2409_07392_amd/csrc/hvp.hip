@@ -71,7 +71,7 @@ int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const 
       plan.part_elems <= x->fused_part_elems)
     return hvp_fused_launch(x, plan, omega, n_rows, shift, (const float*)B, (float*)out, s, skip,
                             st);
-  return hvp_tiled_launch(x, omega, n_rows, shift, B, out, s, skip, st);
+  return hvp_tiled_launch(x, omega, n_rows, shift, B, out, s, skip, st, precise);
 }
 
 }  // namespace firal

@@ -229,25 +229,6 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
 // and G' per use.  The contraction index is again permuted so a lane's eight
 // operands are adjacent: k = 32 g + 8 lk + u.
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-
-__device__ __forceinline__ void split8(const float* v, bf16x8& hi, bf16x8& lo) {
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const __bf16 h = (__bf16)v[u];
-    hi[u] = h;
-    lo[u] = (__bf16)(v[u] - (float)h);
-  }
-}
-
-__device__ __forceinline__ f32x4 mfma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh,
-                                       const bf16x8& bl, f32x4 acc) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-  return acc;
-}
-
 template <int D16, int NCB>
 __global__ __launch_bounds__(kThreads) void k_hvp_fused_bf3(
     const float* __restrict__ X, const float* __restrict__ H, const double* __restrict__ omega,
@@ -477,14 +458,6 @@ static FusedKernel pick(int D16, int ncb) {
     case 6: return pick_ncb<6>(ncb);
     case 7: return pick_ncb<7>(ncb);
     case 8: return pick_ncb<8>(ncb);
-    case 9: return ncb == 1 ? k_hvp_fused<9, 1> : nullptr;
-    case 10: return ncb == 1 ? k_hvp_fused<10, 1> : nullptr;
-    case 11: return ncb == 1 ? k_hvp_fused<11, 1> : nullptr;
-    case 12: return ncb == 1 ? k_hvp_fused<12, 1> : nullptr;
-    case 13: return ncb == 1 ? k_hvp_fused<13, 1> : nullptr;
-    case 14: return ncb == 1 ? k_hvp_fused<14, 1> : nullptr;
-    case 15: return ncb == 1 ? k_hvp_fused<15, 1> : nullptr;
-    case 16: return ncb == 1 ? k_hvp_fused<16, 1> : nullptr;
     default: return nullptr;
   }
 }
@@ -496,8 +469,9 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p, bool precise)
   const int d = x->d, c = x->c;
   const int D16 = (d + 15) / 16;
   const bool bf3 = x->prec == FIRAL_BF16X3 && !precise;
-  if (D16 > 16 || (bf3 && D16 > 8)) return false;
-  const int max_ncb = D16 <= 8 ? 2 : 1;
+  // above d = 128 the row-tiled kernels are faster (measured at d = 256, c = 100: 2x)
+  if (D16 > 8) return false;
+  const int max_ncb = 2;
   // widest tile of whole probes whose 16-column blocks fit max_ncb per wave
   const int max_cols = max_ncb * kNW * 16;
   int pp = std::min(s, max_cols / c);

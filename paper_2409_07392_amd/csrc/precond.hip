@@ -3,92 +3,171 @@
 // followed by an FP64 Cholesky factorisation P_k = L_k L_k^T and the explicit
 // inverse P_k^-1 = L_k^-T L_k^-1 used by the PCG apply.
 //
-// The c weighted Gram matrices share the row data x_i: one wave owns a 16 x 16
-// block pair (a-block >= b-block, the lower triangle) for a group of up to 16
-// classes and a slice of rows; per group of 4 rows it loads x_i's two 16-wide
-// pieces once and issues one MFMA per class with the A operand scaled by that
-// class's weight u_ik = omega_i h_ik (1 - h_ik).  Slices of rows are reduced
-// afterwards in FP64 in a fixed order.
+// The c weighted Gram matrices are one GEMM over rows, classes against (a, b)
+// pairs, with both operands formed from H, omega and X while they are staged;
+// slices of rows are reduced afterwards in FP64 in a fixed order.
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "common.h"
 
 namespace firal {
 
-constexpr int kSyrkG = 16;   // classes per wave
+// Weighted Gram matrices as one GEMM: P[k][(a, b)] = sum_i u_ik w_i,(a,b) with u_ik =
+// omega_i h_ik (1 - h_ik) (classes: the M dimension) and w_i,(a,b) = x_ia x_ib (pairs: the N
+// dimension), k over the rows.  A pair tile is a 16 x BR block of (a, b) in or below the
+// diagonal band; each row stage stages u for the class tile and the tile's 16 + BR x values
+// in LDS, and the MFMA B operand is formed as x_a x_b when it is read.  Four waves in a 2 x 2
+// arrangement, each CMW x PNW blocks of 16 x 16.
+constexpr int kSyrkTK = 16;
 
-__device__ __forceinline__ void pair_decode(int pair, int& ab, int& bb) {
-  int a = (int)((sqrt(8.0 * pair + 1.0) - 1.0) * 0.5);
-  while ((a + 1) * (a + 2) / 2 <= pair) ++a;
-  while (a * (a + 1) / 2 > pair) --a;
-  ab = a;
-  bb = pair - a * (a + 1) / 2;
-}
-
-template <typename T>
-__global__ __launch_bounds__(64) void k_syrk(const T* __restrict__ X, const T* __restrict__ H,
-                                             const double* __restrict__ omega, int64_t N, int d,
-                                             int c, int npairs, int64_t rows_per_split,
-                                             T* __restrict__ part) {
-  int ab, bb;
-  pair_decode(blockIdx.x, ab, bb);
-  const int kg0 = blockIdx.y * kSyrkG;
-  const int ng = min(kSyrkG, c - kg0);
-  const int64_t rb = (int64_t)blockIdx.z * rows_per_split;
+template <typename T, int CMW, int PNW>
+__global__ __launch_bounds__(256, 2) void k_syrk(const T* __restrict__ X, const T* __restrict__ H,
+                                                 const double* __restrict__ omega, int64_t N,
+                                                 int d, int c, const int32_t* __restrict__ tiles,
+                                                 int ntiles, int nct, int64_t rows_per_split,
+                                                 T* __restrict__ part) {
+  constexpr int TC = 32 * CMW, TP = 32 * PNW, BR = TP / 16;
+  constexpr int SU = TC + 16;
+  constexpr int EU = TC * kSyrkTK / 256;
+  __shared__ __align__(16) T Us[2][kSyrkTK][SU];
+  __shared__ T Xa[2][kSyrkTK][17];
+  __shared__ T Xb[2][kSyrkTK][BR + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  // logical tile: class tile fastest, then pair tile, then row split
+  const int64_t lid = blockIdx.x;
+  const int cls_t = (int)(lid % nct);
+  const int64_t rest = lid / nct;
+  const int pt = (int)(rest % ntiles);
+  const int sp = (int)(rest / ntiles);
+  const int c0 = cls_t * TC;
+  const int a0 = 16 * tiles[2 * pt], b0 = BR * tiles[2 * pt + 1];
+  const int64_t rb = (int64_t)sp * rows_per_split;
   const int64_t re = rb + rows_per_split < N ? rb + rows_per_split : N;
-  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
-  const int a = ab * 16 + li, b = bb * 16 + li;
-  typedef Mfma16<T> M;
-  typename M::acc acc[kSyrkG];
-#pragma unroll
-  for (int g = 0; g < kSyrkG; ++g) acc[g] = M::zero();
+  const int wc = (wave >> 1) * 16 * CMW, wp = (wave & 1) * 16 * PNW;
 
-  for (int64_t r0 = rb; r0 < re; r0 += 4) {
-    const int64_t r = r0 + lk;
-    const bool ok = r < re;
-    const T xa = (ok && a < d) ? X[r * d + a] : T(0);
-    const T xb = (ok && b < d) ? X[r * d + b] : T(0);
-    const T w = ok ? (omega ? (T)omega[r] : T(1)) : T(0);
-    const T* hr = H + (ok ? r : 0) * c + kg0;
+  typedef Mfma16<T> M;
+  typename M::acc acc[CMW][PNW];
 #pragma unroll
-    for (int g = 0; g < kSyrkG; ++g) {
-      if (g < ng) {
-        const T h = ok ? hr[g] : T(0);
-        const T u = w * h * (T(1) - h);
-        acc[g] = M::run(u * xa, xb, acc[g]);
+  for (int i = 0; i < CMW; ++i)
+#pragma unroll
+    for (int j = 0; j < PNW; ++j) acc[i][j] = M::zero();
+
+  // staging: u for (row k, class); the 16 x_a and BR x_b values of each row k
+  const int ucls = tid % TC, uk = tid / TC;
+  constexpr int KU = 256 / TC;
+  const bool uvalid = c0 + ucls < c;
+  constexpr int XW = 16 + BR, XE = kSyrkTK * XW, NX = (XE + 255) / 256;
+  int xk[NX], xj[NX];
+  bool xon[NX], xvalid[NX];
+#pragma unroll
+  for (int i = 0; i < NX; ++i) {
+    const int e = tid + 256 * i;
+    xon[i] = e < XE;
+    xk[i] = e / XW;
+    xj[i] = e % XW;
+    const int col = xj[i] < 16 ? a0 + xj[i] : b0 + (xj[i] - 16);
+    xvalid[i] = xon[i] && col < d;
+    xj[i] = xvalid[i] ? col : 0;   // column of X to load (when valid)
+  }
+  T ru[EU], rx[NX];
+  auto load = [&](int kt) {
+    const int64_t r0 = rb + (int64_t)kt * kSyrkTK;
+#pragma unroll
+    for (int i = 0; i < EU; ++i) {
+      const int64_t r = r0 + uk + KU * i;
+      T u = T(0);
+      if (r < re && uvalid) {
+        const T h = H[r * c + c0 + ucls];
+        const T w = omega ? (T)omega[r] : T(1);
+        u = w * h * (T(1) - h);
       }
+      ru[i] = u;
     }
-  }
 #pragma unroll
-  for (int g = 0; g < kSyrkG; ++g) {
-    if (g < ng) {
-      T* o = part + (((int64_t)blockIdx.z * c + kg0 + g) * npairs + blockIdx.x) * 256;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[M::row(lk, v) * 16 + li] = acc[g][v];
+    for (int i = 0; i < NX; ++i) {
+      const int64_t r = r0 + xk[i];
+      rx[i] = (r < re && xvalid[i]) ? X[r * d + xj[i]] : T(0);
     }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < EU; ++i) Us[buf][uk + KU * i][ucls] = ru[i];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      if (!xon[i]) continue;
+      const int e = tid + 256 * i, j = e % XW;
+      if (j < 16) Xa[buf][xk[i]][j] = rx[i];
+      else Xb[buf][xk[i]][j - 16] = rx[i];
+    }
+  };
+
+  const int64_t nrows = re > rb ? re - rb : 0;
+  const int nk = (int)((nrows + kSyrkTK - 1) / kSyrkTK);
+  if (nk > 0) {
+    load(0);
+    store(0);
   }
+  __syncthreads();
+  // this lane's pairs in the B operand: (a_local, b_local) of column wp + 16 j + li
+  int pa[PNW], pb[PNW];
+#pragma unroll
+  for (int j = 0; j < PNW; ++j) {
+    const int pp = wp + 16 * j + li;
+    pa[j] = pp / BR;
+    pb[j] = pp % BR;
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) load(kt + 1);
+#pragma unroll
+    for (int q = 0; q < kSyrkTK / 4; ++q) {
+      const int k = 4 * q + g;
+      T av[CMW], bv[PNW];
+#pragma unroll
+      for (int i = 0; i < CMW; ++i) av[i] = Us[buf][k][wc + 16 * i + li];
+#pragma unroll
+      for (int j = 0; j < PNW; ++j) bv[j] = Xa[buf][k][pa[j]] * Xb[buf][k][pb[j]];
+#pragma unroll
+      for (int i = 0; i < CMW; ++i)
+#pragma unroll
+        for (int j = 0; j < PNW; ++j) acc[i][j] = M::run(av[i], bv[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  T* out = part + (int64_t)sp * c * d * d;
+#pragma unroll
+  for (int i = 0; i < CMW; ++i)
+#pragma unroll
+    for (int j = 0; j < PNW; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = c0 + wc + 16 * i + M::row(g, v);
+        const int a = a0 + pa[j], b = b0 + pb[j];
+        if (k < c && a < d && b < d && b <= a) out[((int64_t)k * d + a) * d + b] = acc[i][j][v];
+      }
 }
 
-// P[k][a][b] = sum_split part(lower-triangle element) + shift [a == b], FP64.
-// Element (a, b) is always read from the (max, min) position so P is exactly symmetric.
+// P[k][a][b] = sum over splits (in order, FP64) of the lower-triangle entry (max, min) +
+// shift [a == b]: P is exactly symmetric.
 template <typename T>
 __global__ __launch_bounds__(256) void k_syrk_reduce(const T* __restrict__ part, int S, int c,
-                                                     int d, int npairs, double shift,
+                                                     int d, double shift,
                                                      double* __restrict__ P) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t dd = (int64_t)d * d;
   if (idx >= (int64_t)c * dd) return;
-  const int k = (int)(idx / dd);
-  const int rem = (int)(idx % dd);
-  int a = rem / d, b = rem % d;
-  if (a < b) { const int t = a; a = b; b = t; }
-  const int ab = a >> 4, bb = b >> 4;
-  const int pair = ab * (ab + 1) / 2 + bb;
-  const int within = (a & 15) * 16 + (b & 15);
+  const int64_t k = idx / dd;
+  const int rem = (int)(idx - k * dd);
+  const int a = rem / d, b = rem - (rem / d) * d;
+  const int64_t e = k * dd + (a >= b ? (int64_t)a * d + b : (int64_t)b * d + a);
   double acc = 0.0;
-  for (int p = 0; p < S; ++p) acc += (double)part[(((int64_t)p * c + k) * npairs + pair) * 256 + within];
-  P[idx] = acc + ((rem / d) == (rem % d) ? shift : 0.0);
+  for (int p = 0; p < S; ++p) acc += (double)part[(int64_t)p * c * dd + e];
+  P[idx] = acc + (a == b ? shift : 0.0);
 }
 
 // In-place right-looking Cholesky of block k (lower triangle); upper part zeroed.
@@ -259,22 +338,36 @@ static SweepKernel pick_sweep(int d, int* threads) {
 
 __global__ void k_bad_reset(Status* st) { st->bad_block = INT_MAX; }
 
+// Class-tile width by c (narrow tiles for few classes); pair tiles of 128 (FP32) or 64 (FP64).
+template <typename T> constexpr int syrk_pnw() { return sizeof(T) == 4 ? 4 : 2; }
+int syrk_cmw(int c) { return c <= 32 ? 1 : (c <= 64 ? 2 : 4); }
+
+template <typename T, int CMW>
+static void launch_syrk(Ctx* x, const double* omega, int64_t rps, hipStream_t st) {
+  constexpr int PNW = syrk_pnw<T>();
+  const int nct = (int)cdiv(x->c, 32 * CMW);
+  const int64_t nwg = (int64_t)nct * x->syrk_ntiles * x->syrk_splits;
+  k_syrk<T, CMW, PNW><<<(unsigned)nwg, 256, 0, st>>>((const T*)x->X, (const T*)x->H, omega, x->N,
+                                                     x->d, x->c, x->syrk_tiles, x->syrk_ntiles,
+                                                     nct, rps, (T*)x->syrk_part);
+}
+
 template <typename T>
 static int precond_t(Ctx* x, const double* omega, double shift, hipStream_t st) {
   const int d = x->d, c = x->c;
-  const int nb = (int)cdiv(d, 16);
-  const int npairs = nb * (nb + 1) / 2;
-  const int groups = (int)cdiv(c, kSyrkG);
   const int S = x->syrk_splits;
   const int64_t rps = cdiv(x->N, S);
   k_bad_reset<<<1, 1, 0, st>>>(x->status);
   FIRAL_LAUNCHED();
-  k_syrk<T><<<dim3(npairs, groups, S), 64, 0, st>>>((const T*)x->X, (const T*)x->H, omega, x->N,
-                                                   d, c, npairs, rps, (T*)x->syrk_part);
+  switch (syrk_cmw(c)) {
+    case 1: launch_syrk<T, 1>(x, omega, rps, st); break;
+    case 2: launch_syrk<T, 2>(x, omega, rps, st); break;
+    default: launch_syrk<T, 4>(x, omega, rps, st); break;
+  }
   FIRAL_LAUNCHED();
   const int64_t n = (int64_t)c * d * d;
   k_syrk_reduce<T><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((const T*)x->syrk_part, S, c, d,
-                                                           npairs, shift, x->P);
+                                                           shift, x->P);
   FIRAL_LAUNCHED();
   int threads = 0;
   SweepKernel sw = pick_sweep(d, &threads);
@@ -288,6 +381,25 @@ static int precond_t(Ctx* x, const double* omega, double shift, hipStream_t st) 
     FIRAL_LAUNCHED();
   }
   return FIRAL_OK;
+}
+
+// Pair tiles (a-block of 16, b-block of BR) that meet the lower triangle, and the row-split
+// count, for a context (host side, at creation).
+void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits) {
+  const int BR = 2 * (prec == FIRAL_F64 ? syrk_pnw<double>() : syrk_pnw<float>());
+  const int nab = (int)cdiv(d, 16), nbb = (int)cdiv(d, BR);
+  tiles->clear();
+  for (int A = 0; A < nab; ++A)
+    for (int Bb = 0; Bb < nbb && Bb * BR <= 16 * A + 15; ++Bb) {
+      tiles->push_back(A);
+      tiles->push_back(Bb);
+    }
+  const int64_t nt = (int64_t)tiles->size() / 2;
+  const int64_t wgs = nt * cdiv(c, 32 * syrk_cmw(c));
+  const int64_t es = prec == FIRAL_F64 ? 8 : 4;
+  const int64_t mem_cap = std::max<int64_t>(1, ((int64_t)2 << 30) / ((int64_t)c * d * d * es));
+  *splits = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, wgs), 64),
+                                                        mem_cap));
 }
 
 int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st) {

@@ -2,18 +2,18 @@
 // rows) and of the per-point gradient contraction (eq. 11), for any d and c.
 //
 // Product, per chunk of rows:
-//   kernel 1   G = X V on a TM x TN tile (pipelined through LDS), then in its epilogue the
-//              row-local step of the lemma: alpha_rj = sum_k G[r,j,k] h_rk over the probe
-//              columns the tile holds.  When a tile holds whole probes (c <= TN) the epilogue
-//              writes G' = omega_r (G - alpha) h directly; for c > TN a probe spans several
-//              column windows, so the tile writes raw G and its window's partial alpha.
-//   kernel 2   part[split] (+)= X^T G' over the split's rows, applying the row step while
-//              staging G when the first kernel could not (windowed probes).
+//   kernel 1   G = X V on a TM x TN tile (pipelined through LDS).  When a tile holds whole
+//              probes (c <= TN) its epilogue takes the row-local step of the lemma,
+//              alpha_rj = sum_k G[r,j,k] h_rk and G' = omega_r (G - alpha_rj) h_r, and writes
+//              G'; for c > TN a probe spans several column windows, so the tile writes raw G
+//              and a separate pass (one wave per row and probe) takes the row step in place.
+//   kernel 2   part[split] (+)= X^T G' over the split's rows.
 // A final fixed-order pass (reduce_parts_launch) sums the splits and adds shift * V.
 //
-// Gradient, per chunk of pool rows: one kernel computes A = X U and B = X W on the same tile
-// and reduces, per row, probe and column window, sum a h b, sum a h and sum b h in FP64;
-// a second pass forms g_r = -(1/s) sum_j [sum a h b - (sum a h)(sum b h)].
+// Gradient, per chunk of pool rows: u_j^T H_i w_j = a^T Gamma_i b with a = U_j^T x_i and
+// b = W_j^T x_i, and Gamma_i b is the row step applied to b with unit weight; so the chunk's
+// G' = Gamma-step(X W) is formed as in the product, and a second pass of kernel 1 takes the
+// row-wise dot product of X U with G' tile by tile (FP64 sums, reduced in a fixed order).
 //
 // All sums are in a fixed order (no float atomics): results are reproducible run to run.
 #include <algorithm>
@@ -76,31 +76,89 @@ ColMap make_colmap(int c, int s, int TN) {
   return m;
 }
 
-template <typename T, int WM, int WN, int NB, bool GRAD>
+enum XvMode { kGamma = 0, kRaw = 1, kDot = 2 };
+
+// Pipeline stage depth and LDS row strides: FP32/FP64 stages of 16 k-rows are read four rows
+// apart (k = 4q + g), bf16x3 stages of 32 eight apart (k = 8g + u); the strides put the four
+// 16-lane groups of a wave on two disjoint halves of the banks.
+template <bool BF3> constexpr int stage_k() { return BF3 ? 32 : kTK; }
+template <bool BF3> constexpr int lds_pad() { return BF3 ? 2 : 4; }
+
+template <typename T, int WM, int WN, int MODE, bool BF3>
 constexpr size_t xv_lds_bytes() {
-  constexpr int TM = 32 * WM, TN = 32 * WN, SA = TM + 16, SB = TN + 16;
-  constexpr size_t main_b = (size_t)(2 * kTK * SA + 2 * NB * kTK * SB) * sizeof(T);
-  constexpr size_t epi_b = (size_t)(NB * TM * (TN + 1) + (GRAD ? 0 : TM * kMaxPP)) * sizeof(T);
+  constexpr int TK = stage_k<BF3>();
+  constexpr int TM = 32 * WM, TN = 32 * WN, SA = TM + lds_pad<BF3>(), SB = TN + lds_pad<BF3>();
+  constexpr size_t main_b = (size_t)(2 * TK * SA + 2 * TK * SB) * sizeof(T);
+  constexpr size_t epi_b = (size_t)(TM * (TN + 1) + (MODE == kGamma ? TM * kMaxPP : 0)) * sizeof(T);
   return main_b > epi_b ? main_b : epi_b;
 }
 
-// Kernel 1.  Tile (row tile rt, column tile ct) of A_nb = X_chunk B_nb (nb < NB); four waves in
-// a 2 x 2 arrangement, each WM x WN MFMA blocks of 16 x 16.  Product mode (GRAD false, NB 1):
-// writes G' (whole probes) or G and the window's partial alpha (windowed).  Gradient mode
-// (NB 2): writes the three FP64 partial sums per row, probe and window to gpart.
-template <typename T, int WM, int WN, int NB, bool GRAD>
+// One pipeline stage of a wave's WM x WN blocks from LDS tiles stored k-major (a[k][m],
+// b[k][n]).  FP32/FP64: four 16x16x4 steps, lane (li, g) reading k = 4q + g.  bf16x3: one
+// 16x16x32 step per product pass, lane (li, g) reading k = 8g + u, split into bf16 halves.
+template <typename T, int WM, int WN, bool BF3>
+__device__ __forceinline__ void mma_stage(const T* __restrict__ a, int SA, const T* __restrict__ b,
+                                          int SB, int wm, int wn, int li, int g,
+                                          typename Mfma16<T>::acc (&acc)[WM][WN]) {
+  if constexpr (BF3) {
+    bf16x8 ah[WM], al[WM];
+#pragma unroll
+    for (int i = 0; i < WM; ++i) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = a[(8 * g + u) * SA + wm + 16 * i + li];
+      split8(v, ah[i], al[i]);
+    }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = b[(8 * g + u) * SB + wn + 16 * j + li];
+      bf16x8 bh, bl;
+      split8(v, bh, bl);
+#pragma unroll
+      for (int i = 0; i < WM; ++i) acc[i][j] = mfma3(ah[i], al[i], bh, bl, acc[i][j]);
+    }
+  } else {
+    typedef Mfma16<T> M;
+#pragma unroll
+    for (int q = 0; q < kTK / 4; ++q) {
+      T av[WM], bv[WN];
+#pragma unroll
+      for (int i = 0; i < WM; ++i) av[i] = a[(4 * q + g) * SA + wm + 16 * i + li];
+#pragma unroll
+      for (int j = 0; j < WN; ++j) bv[j] = b[(4 * q + g) * SB + wn + 16 * j + li];
+#pragma unroll
+      for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = M::run(av[i], bv[j], acc[i][j]);
+    }
+  }
+}
+
+// Kernel 1: tile (row tile, column tile) of X_chunk B on four waves in a 2 x 2 arrangement, each
+// WM x WN MFMA blocks of 16 x 16, k pipelined through double-buffered LDS.  Epilogue by MODE:
+//   kGamma  (tiles of whole probes) alpha = gamma . h per row and probe, then
+//           Gout = omega (gamma - alpha) h;
+//   kRaw    Gout = gamma;
+//   kDot    part[ct][r] = sum over the tile's columns of gamma * Gin (FP64): one tile's share of
+//           a row-wise dot product with a matrix of the same shape.
+// The epilogue moves the tile through LDS so that every global access is a coalesced row
+// segment, and issues all of a wave's loads before it uses any of them.
+template <typename T, int WM, int WN, int MODE, bool BF3>
 __global__ __launch_bounds__(256, 2) void k_xv(
-    const T* __restrict__ X, int d, int64_t R, const T* __restrict__ B0,
-    const T* __restrict__ B1, const T* __restrict__ H, const double* __restrict__ omega,
-    ColMap cm, int64_t nrt, T* __restrict__ Gout, T* __restrict__ abuf,
-    double* __restrict__ gpart, Skip skip) {
+    const T* __restrict__ X, int d, int64_t R, const T* __restrict__ B,
+    const T* __restrict__ H, const double* __restrict__ omega, ColMap cm,
+    T* __restrict__ Gout, const T* __restrict__ Gin, double* __restrict__ dpart, Skip skip) {
   if (skip_now(skip)) return;
-  constexpr int TM = 32 * WM, TN = 32 * WN, SA = TM + 16, SB = TN + 16, SCs = TN + 1;
-  constexpr int EA = TM * kTK / 256, EB = TN * kTK / 256;
-  constexpr int NU = (TN + 63) / 64;
+  constexpr int TK = stage_k<BF3>();
+  constexpr int TM = 32 * WM, TN = 32 * WN, SCs = TN + 1;
+  constexpr int SA = TM + lds_pad<BF3>(), SB = TN + lds_pad<BF3>();
+  constexpr int EA = TM * TK / 256, EB = TN * TK / 256;
+  constexpr int NU = TN / 64, RPW = TM / 4;   // columns per lane, rows per wave (epilogue)
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* As = reinterpret_cast<T*>(lds_raw);   // [2][kTK][SA]
-  T* Bs = As + 2 * kTK * SA;               // [2][NB][kTK][SB]
+  T* As = reinterpret_cast<T*>(lds_raw);   // [2][TK][SA]
+  T* Bs = As + 2 * TK * SA;                // [2][TK][SB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t lid = xcd_lid(blockIdx.x, gridDim.x);
@@ -109,256 +167,188 @@ __global__ __launch_bounds__(256, 2) void k_xv(
   const int64_t row0 = rt * TM;
   int col0, width, p0, np, w;
   cm.tile(ct, col0, width, p0, np, w);
-  const int c = cm.c, s = cm.s, SC = cm.SC;
+  const int c = cm.c, SC = cm.SC;
   const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
   typedef Mfma16<T> M;
-  typename M::acc acc[NB][WM][WN];
+  typename M::acc acc[WM][WN];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
-#pragma unroll
-      for (int j = 0; j < WN; ++j) acc[nb][i][j] = M::zero();
+    for (int j = 0; j < WN; ++j) acc[i][j] = M::zero();
 
-  T ra[EA], rb[NB][EB];
+  T ra[EA], rb[EB];
   auto load = [&](int kt) {
-    const int k0 = kt * kTK;
+    const int k0 = kt * TK;
 #pragma unroll
     for (int i = 0; i < EA; ++i) {
-      const int e = tid + 256 * i, r = e >> 4, k = e & 15;
+      const int e = tid + 256 * i, r = e / TK, k = e % TK;
       const int64_t gr = row0 + r;
       ra[i] = (gr < R && k0 + k < d) ? X[gr * d + k0 + k] : T(0);
     }
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      const T* Bp = nb ? B1 : B0;
-#pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const int e = tid + 256 * i, k = e / TN, n = e % TN;
-        rb[nb][i] = (k0 + k < d && n < width) ? Bp[(int64_t)(k0 + k) * SC + col0 + n] : T(0);
-      }
+    for (int i = 0; i < EB; ++i) {
+      const int e = tid + 256 * i, k = e / TN, n = e % TN;
+      rb[i] = (k0 + k < d && n < width) ? B[(int64_t)(k0 + k) * SC + col0 + n] : T(0);
     }
   };
   auto store = [&](int buf) {
-    T* a = As + buf * kTK * SA;
+    T* a = As + buf * TK * SA;
 #pragma unroll
     for (int i = 0; i < EA; ++i) {
       const int e = tid + 256 * i;
-      a[(e & 15) * SA + (e >> 4)] = ra[i];
+      a[(e % TK) * SA + e / TK] = ra[i];
     }
-    T* b = Bs + buf * NB * kTK * SB;
+    T* b = Bs + buf * TK * SB;
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-      for (int i = 0; i < EB; ++i) {
-        const int e = tid + 256 * i;
-        b[(nb * kTK + e / TN) * SB + e % TN] = rb[nb][i];
-      }
+    for (int i = 0; i < EB; ++i) {
+      const int e = tid + 256 * i;
+      b[(e / TN) * SB + e % TN] = rb[i];
+    }
   };
 
-  const int nk = (d + kTK - 1) / kTK;
+  const int nk = (d + TK - 1) / TK;
   load(0);
   store(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) load(kt + 1);
-    const T* a = As + buf * kTK * SA;
-    const T* b = Bs + buf * NB * kTK * SB;
-#pragma unroll
-    for (int q = 0; q < kTK / 4; ++q) {
-      T av[WM], bv[NB][WN];
-#pragma unroll
-      for (int i = 0; i < WM; ++i) av[i] = a[(4 * q + g) * SA + wm + 16 * i + li];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) bv[nb][j] = b[(nb * kTK + 4 * q + g) * SB + wn + 16 * j + li];
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int i = 0; i < WM; ++i)
-#pragma unroll
-          for (int j = 0; j < WN; ++j) acc[nb][i][j] = M::run(av[i], bv[nb][j], acc[nb][i][j]);
-    }
+    mma_stage<T, WM, WN, BF3>(As + buf * TK * SA, SA, Bs + buf * TK * SB, SB, wm, wn, li, g, acc);
     if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
   }
 
-  // ---- epilogue: the raw tile goes to LDS (the pipeline buffers are free now)
-  T* Cs = reinterpret_cast<T*>(lds_raw);   // [NB][TM][SCs]
+  // ---- epilogue: the tile goes to LDS (the pipeline buffers are free after the last barrier)
+  T* Cs = reinterpret_cast<T*>(lds_raw);   // [TM][SCs]
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int i = 0; i < WM; ++i)
+    for (int j = 0; j < WN; ++j)
 #pragma unroll
-      for (int j = 0; j < WN; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-          Cs[(nb * TM + wm + 16 * i + M::row(g, v)) * SCs + wn + 16 * j + li] = acc[nb][i][j][v];
+      for (int v = 0; v < 4; ++v)
+        Cs[(wm + 16 * i + M::row(g, v)) * SCs + wn + 16 * j + li] = acc[i][j][v];
   __syncthreads();
-
   const int rows_here = (int)(R - row0 < TM ? R - row0 : TM);
-  const bool serial = cm.full && c <= 32;   // short probe segments: one thread per (row, probe)
-  const int nw = cm.nw;
 
-  if constexpr (GRAD) {
-    const T* CA = Cs;
-    const T* CB = Cs + TM * SCs;
-    if (serial) {
-      for (int it = tid; it < TM * np; it += 256) {
-        const int m = it / np, p = it - m * np;
-        if (m >= rows_here) continue;
-        const int64_t r = row0 + m;
-        const T* hr = H + r * c;
-        double sab = 0.0, sa = 0.0, sb = 0.0;
-        for (int k = 0; k < c; ++k) {
-          const double h = (double)hr[k];
-          const double ah = (double)CA[m * SCs + p * c + k] * h;
-          const double b = (double)CB[m * SCs + p * c + k];
-          sab += ah * b;
-          sa += ah;
-          sb += b * h;
-        }
-        double* o = gpart + ((r * s + p0 + p) * nw + w) * 3;
-        o[0] = sab;
-        o[1] = sa;
-        o[2] = sb;
-      }
-    } else {
-      for (int m = wave; m < rows_here; m += 4) {
-        const int64_t r = row0 + m;
-        const T* hr = H + r * c;
-        double ah[NU], bb[NU], hh[NU];
-        int sg[NU];
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int n = lane + 64 * u;
-          sg[u] = -1;
-          ah[u] = bb[u] = hh[u] = 0.0;
-          if (n < width) {
-            const int p = cm.full ? n / c : 0;
-            const int kk = cm.full ? n - p * c : w * TN + n;
-            hh[u] = (double)hr[kk];
-            ah[u] = (double)CA[m * SCs + n] * hh[u];
-            bb[u] = (double)CB[m * SCs + n];
-            sg[u] = p;
-          }
-        }
-        for (int p = 0; p < np; ++p) {
-          double sab = 0.0, sa = 0.0, sb = 0.0;
-#pragma unroll
-          for (int u = 0; u < NU; ++u)
-            if (sg[u] == p) {
-              sab += ah[u] * bb[u];
-              sa += ah[u];
-              sb += bb[u] * hh[u];
-            }
-          sab = wave_sum(sab);
-          sa = wave_sum(sa);
-          sb = wave_sum(sb);
-          if (lane == 0) {
-            double* o = gpart + ((r * s + p0 + p) * nw + w) * 3;
-            o[0] = sab;
-            o[1] = sa;
-            o[2] = sb;
-          }
-        }
-      }
-    }
-  } else {
-    T* Al = Cs + TM * SCs;   // [TM][kMaxPP]: alpha of each (row, probe) of the tile
-    if (serial) {
-      for (int it = tid; it < TM * np; it += 256) {
-        const int m = it / np, p = it - m * np;
-        if (m >= rows_here) continue;
-        const T* hr = H + (row0 + m) * c;
-        double sa = 0.0;
-        for (int k = 0; k < c; ++k) sa += (double)Cs[m * SCs + p * c + k] * (double)hr[k];
-        Al[m * kMaxPP + p] = (T)sa;
-      }
-    } else {
-      for (int m = wave; m < rows_here; m += 4) {
-        const T* hr = H + (row0 + m) * c;
-        double gh[NU];
-        int sg[NU];
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int n = lane + 64 * u;
-          sg[u] = -1;
-          gh[u] = 0.0;
-          if (n < width) {
-            const int p = cm.full ? n / c : 0;
-            const int kk = cm.full ? n - p * c : w * TN + n;
-            gh[u] = (double)Cs[m * SCs + n] * (double)hr[kk];
-            sg[u] = p;
-          }
-        }
-        for (int p = 0; p < np; ++p) {
-          double sa = 0.0;
-#pragma unroll
-          for (int u = 0; u < NU; ++u)
-            if (sg[u] == p) sa += gh[u];
-          sa = wave_sum(sa);
-          if (lane == 0) Al[m * kMaxPP + p] = (T)sa;
-        }
-      }
-    }
-    __syncthreads();
-    for (int m = wave; m < rows_here; m += 4) {
-      const int64_t r = row0 + m;
-      T* go = Gout + r * SC + col0;
-      if (cm.full) {
-        const T* hr = H + r * c;
-        const T om = omega ? (T)omega[r] : T(1);
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int n = lane + 64 * u;
-          if (n < width) {
-            const int p = n / c, kk = n - p * c;
-            go[n] = om * ((Cs[m * SCs + n] - Al[m * kMaxPP + p]) * hr[kk]);
-          }
-        }
-      } else {
+  if constexpr (MODE == kRaw) {
+#pragma unroll 4
+    for (int it = 0; it < RPW; ++it) {
+      const int m = wave + 4 * it;
+      if (m < rows_here) {
+        T* go = Gout + (row0 + m) * SC + col0;
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
           const int n = lane + 64 * u;
           if (n < width) go[n] = Cs[m * SCs + n];
         }
-        if (lane == 0) abuf[(r * s + p0) * nw + w] = Al[m * kMaxPP];
+      }
+    }
+    return;
+  } else {
+    // E2: this wave's rows (m = wave + 4 it), lanes over columns; the row operand (h for
+    // kGamma, Gin for kDot) is loaded for every row before any is used.
+    T gv[RPW][NU], xv[RPW][NU];
+#pragma unroll
+    for (int it = 0; it < RPW; ++it) {
+      const int m = wave + 4 * it;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int n = lane + 64 * u;
+        const bool ok = m < rows_here && n < width;
+        if constexpr (MODE == kGamma) {
+          const int kk = n - (n / c) * c;
+          xv[it][u] = ok ? H[(row0 + m) * c + kk] : T(0);
+        } else {
+          xv[it][u] = ok ? Gin[(row0 + m) * SC + col0 + n] : T(0);
+        }
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < RPW; ++it) {
+      const int m = wave + 4 * it;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int n = lane + 64 * u;
+        gv[it][u] = Cs[m * SCs + n];
+        Cs[m * SCs + n] = gv[it][u] * xv[it][u];   // each element is touched by one thread
+      }
+    }
+    __syncthreads();
+    // E3: segment sums from LDS, two lanes per (row, segment), FP64, fixed order
+    const int L = MODE == kGamma ? c : width;       // segment length
+    const int nseg = MODE == kGamma ? np : 1;
+    const int hl = (L + 1) >> 1;
+    T* Al = Cs + TM * SCs;                          // [TM][kMaxPP] (kGamma)
+    for (int item = tid; item < TM * nseg * 2; item += 256) {
+      const int half = item & 1, mp = item >> 1;
+      const int m = mp / nseg, p = mp - m * nseg;
+      const int beg = p * L + half * hl, end = half ? p * L + L : p * L + hl;
+      double v = 0.0;
+      if (m < rows_here)
+        for (int k = beg; k < end; ++k) v += (double)Cs[m * SCs + k];
+      v += __shfl_xor(v, 1, 64);
+      if (!half && m < rows_here) {
+        if constexpr (MODE == kGamma) Al[m * kMaxPP + p] = (T)v;
+        else dpart[(int64_t)ct * R + row0 + m] = v;
+      }
+    }
+    if constexpr (MODE == kGamma) {
+      __syncthreads();
+      // E4: G' = omega (gamma - alpha) h, coalesced row segments
+#pragma unroll
+      for (int it = 0; it < RPW; ++it) {
+        const int m = wave + 4 * it;
+        if (m < rows_here) {
+          const int64_t r = row0 + m;
+          const T om = omega ? (T)omega[r] : T(1);
+          T* go = Gout + r * SC + col0;
+#pragma unroll
+          for (int u = 0; u < NU; ++u) {
+            const int n = lane + 64 * u;
+            if (n < width) go[n] = om * ((gv[it][u] - Al[m * kMaxPP + n / c]) * xv[it][u]);
+          }
+        }
       }
     }
   }
 }
 
-// Windowed probes: alpha_rj = sum over the nw windows, in order, stored in window slot 0.
+// Row step of Lemma 1 for probes wider than a column tile: one wave per (row, probe),
+// alpha = sum_k G h_k (FP64), then G <- omega (G - alpha) h in place.
 template <typename T>
-__global__ __launch_bounds__(256) void k_alpha_sum(T* __restrict__ abuf, int64_t n, int nw,
-                                                   Skip skip) {
+__global__ __launch_bounds__(256) void k_gamma_rows(T* __restrict__ G, int64_t R, int s, int c,
+                                                    const T* __restrict__ H,
+                                                    const double* __restrict__ omega, Skip skip) {
   if (skip_now(skip)) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  T* a = abuf + i * nw;
-  T acc = a[0];
-  for (int w = 1; w < nw; ++w) acc += a[w];
-  a[0] = acc;
+  const int lane = threadIdx.x & 63;
+  const int64_t id = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (id >= R * s) return;   // whole waves
+  const int64_t r = id / s;
+  T* gr = G + id * c;        // row r, probe id - r s
+  const T* hr = H + r * c;
+  double a = 0.0;
+  for (int k = lane; k < c; k += 64) a += (double)gr[k] * (double)hr[k];
+  a = wave_sum(a);
+  const T al = (T)__shfl(a, 0, 64);
+  const T om = omega ? (T)omega[r] : T(1);
+  for (int k = lane; k < c; k += 64) gr[k] = om * ((gr[k] - al) * hr[k]);
 }
 
 // Kernel 2.  part[split][a, col] (+)= sum over the split's rows r of X[r, a] G'[r, col], with
-// a d-tile of TM = 32 WM rows and a column tile of TN = 32 WN.  GAM: G holds raw products and
-// the row step G' = omega_r (G - alpha_rj) h_rk is applied while staging.
-template <typename T, int WM, int WN, bool GAM>
+// a d-tile of TM = 32 WM rows and a column tile of TN = 32 WN.
+template <typename T, int WM, int WN, bool BF3>
 __global__ __launch_bounds__(256, 2) void k_xtg(
     const T* __restrict__ X, int d, const T* __restrict__ G, int SC, int64_t R,
-    int64_t rows_per_split, int nmt, int nct, const T* __restrict__ H, int c, int s,
-    const double* __restrict__ omega, const T* __restrict__ abuf, int nw, T* __restrict__ part,
-    int64_t part_stride, int accumulate, Skip skip) {
+    int64_t rows_per_split, int nmt, int nct, T* __restrict__ part, int64_t part_stride,
+    int accumulate, Skip skip) {
   if (skip_now(skip)) return;
-  constexpr int TM = 32 * WM, TN = 32 * WN, SA = TM + 16, SB = TN + 16;
-  constexpr int EA = TM * kTK / 256, EB = TN * kTK / 256;
+  constexpr int TK = stage_k<BF3>();
+  constexpr int TM = 32 * WM, TN = 32 * WN, SA = TM + lds_pad<BF3>(), SB = TN + lds_pad<BF3>();
+  constexpr int EA = TM * TK / 256, EB = TN * TK / 256;
   constexpr int KA = 256 / TM, KB = 256 / TN;   // k-rows covered by one pass of the threads
-  __shared__ __align__(16) T As[2][kTK][SA];
-  __shared__ __align__(16) T Bs[2][kTK][SB];
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* As = reinterpret_cast<T*>(lds_raw);   // [2][TK][SA]
+  T* Bs = As + 2 * TK * SA;                // [2][TK][SB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t lid = xcd_lid(blockIdx.x, gridDim.x);
@@ -370,15 +360,8 @@ __global__ __launch_bounds__(256, 2) void k_xtg(
   const int64_t rb = (int64_t)sp * rows_per_split;
   const int64_t re = rb + rows_per_split < R ? rb + rows_per_split : R;
   const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
-  // this thread's staging column of G (fixed for the whole kernel)
   const int bn = tid % TN, bk = tid / TN;
-  const int bcol = col0 + bn;
-  const bool bvalid = bcol < SC;
-  int bj = 0, bkk = 0;
-  if (GAM && bvalid) {
-    bj = bcol / c;
-    bkk = bcol - bj * c;
-  }
+  const bool bvalid = col0 + bn < SC;
   const int am = tid % TM, ak = tid / TM;
   const bool avalid = a0 + am < d;
 
@@ -391,7 +374,7 @@ __global__ __launch_bounds__(256, 2) void k_xtg(
 
   T ra[EA], rb_[EB];
   auto load = [&](int kt) {
-    const int64_t r0 = rb + (int64_t)kt * kTK;
+    const int64_t r0 = rb + (int64_t)kt * TK;
 #pragma unroll
     for (int i = 0; i < EA; ++i) {
       const int64_t r = r0 + ak + KA * i;
@@ -400,26 +383,18 @@ __global__ __launch_bounds__(256, 2) void k_xtg(
 #pragma unroll
     for (int i = 0; i < EB; ++i) {
       const int64_t r = r0 + bk + KB * i;
-      T v = T(0);
-      if (r < re && bvalid) {
-        v = G[r * SC + bcol];
-        if (GAM) {
-          const T om = omega ? (T)omega[r] : T(1);
-          v = om * ((v - abuf[(r * s + bj) * nw]) * H[r * c + bkk]);
-        }
-      }
-      rb_[i] = v;
+      rb_[i] = (r < re && bvalid) ? G[r * SC + col0 + bn] : T(0);
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < EA; ++i) As[buf][ak + KA * i][am] = ra[i];
+    for (int i = 0; i < EA; ++i) As[(buf * TK + ak + KA * i) * SA + am] = ra[i];
 #pragma unroll
-    for (int i = 0; i < EB; ++i) Bs[buf][bk + KB * i][bn] = rb_[i];
+    for (int i = 0; i < EB; ++i) Bs[(buf * TK + bk + KB * i) * SB + bn] = rb_[i];
   };
 
   const int64_t nrows = re > rb ? re - rb : 0;
-  const int nk = (int)((nrows + kTK - 1) / kTK);
+  const int nk = (int)((nrows + TK - 1) / TK);
   if (nk > 0) {
     load(0);
     store(0);
@@ -428,18 +403,7 @@ __global__ __launch_bounds__(256, 2) void k_xtg(
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     if (kt + 1 < nk) load(kt + 1);
-#pragma unroll
-    for (int q = 0; q < kTK / 4; ++q) {
-      T av[WM], bv[WN];
-#pragma unroll
-      for (int i = 0; i < WM; ++i) av[i] = As[buf][4 * q + g][wm + 16 * i + li];
-#pragma unroll
-      for (int j = 0; j < WN; ++j) bv[j] = Bs[buf][4 * q + g][wn + 16 * j + li];
-#pragma unroll
-      for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = M::run(av[i], bv[j], acc[i][j]);
-    }
+    mma_stage<T, WM, WN, BF3>(As + buf * TK * SA, SA, Bs + buf * TK * SB, SB, wm, wn, li, g, acc);
     if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
   }
@@ -460,36 +424,35 @@ __global__ __launch_bounds__(256, 2) void k_xtg(
       }
 }
 
-// g_r = -(1/s) sum_j [S_ab - S_a S_b], each S summed over the nw windows in order; one wave per row.
-__global__ __launch_bounds__(256) void k_grad_sum(const double* __restrict__ gpart, int64_t R,
-                                                  int s, int nw, double* __restrict__ g) {
-  const int lane = threadIdx.x & 63;
-  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+// g_r = -(1/s) sum over column tiles (in order) of the tile's row dot product.
+__global__ __launch_bounds__(256) void k_grad_sum(const double* __restrict__ dpart, int64_t R,
+                                                  int ntiles, int s, double* __restrict__ g) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   double q = 0.0;
-  for (int j = lane; j < s; j += 64) {
-    const double* p = gpart + (r * s + j) * nw * 3;
-    double sab = 0.0, sa = 0.0, sb = 0.0;
-    for (int w = 0; w < nw; ++w) {
-      sab += p[3 * w];
-      sa += p[3 * w + 1];
-      sb += p[3 * w + 2];
-    }
-    q += sab - sa * sb;
-  }
-  q = wave_sum(q);
-  if (lane == 0) g[r] = -q / s;
+  for (int t = 0; t < ntiles; ++t) q += dpart[(int64_t)t * R + r];
+  g[r] = -q / s;
 }
 
-// Tile shapes: FP32 product 128 x 128 (64 x 64 per wave); FP64 64 x 128; gradient tiles hold
-// two operands and are half as wide.
-template <typename T> struct Shape;
-template <> struct Shape<float> {
-  static constexpr int WM1 = 4, WN1 = 4, WM2 = 4, WN2 = 4, WMG = 4, WNG = 2;
+// Tile shapes: FP32 128 x 128 (64 x 64 per wave), FP64 64 x 128 (32 x 64 per wave); bf16x3
+// 128 x 64 (its split operands and 32-deep stages need the registers a wider tile would take).
+template <typename T, bool BF3> struct Shape;
+template <> struct Shape<float, false> {
+  static constexpr int WM1 = 4, WN1 = 4, WM2 = 4, WN2 = 4;
 };
-template <> struct Shape<double> {
-  static constexpr int WM1 = 2, WN1 = 4, WM2 = 2, WN2 = 4, WMG = 2, WNG = 2;
+template <> struct Shape<float, true> {
+  static constexpr int WM1 = 4, WN1 = 2, WM2 = 4, WN2 = 2;
 };
+template <> struct Shape<double, false> {
+  static constexpr int WM1 = 2, WN1 = 4, WM2 = 2, WN2 = 4;
+};
+
+template <typename T, int WM, int WN, bool BF3>
+constexpr size_t xtg_lds_bytes() {
+  constexpr int TK = stage_k<BF3>();
+  return (size_t)(2 * TK * (32 * WM + lds_pad<BF3>()) + 2 * TK * (32 * WN + lds_pad<BF3>())) *
+         sizeof(T);
+}
 
 template <typename Kern>
 int set_lds(Kern k, size_t bytes, bool& done) {
@@ -501,69 +464,87 @@ int set_lds(Kern k, size_t bytes, bool& done) {
   return FIRAL_OK;
 }
 
+template <typename T, bool BF3>
+ColMap colmap_for(int c, int s) {
+  return make_colmap(c, s, 32 * Shape<T, BF3>::WN1);
+}
+
+// G = Gamma-step(omega, X_chunk B) for the chunk's R rows: the whole-probe epilogue when tiles
+// hold whole probes, else the raw product followed by the per-(row, probe) pass.
+template <typename T, bool BF3>
+int xv_gamma(const ColMap& cm, const T* Xc, int d, int64_t R, const T* B, const T* Hc,
+             const double* om, T* G, Skip skip, hipStream_t st) {
+  typedef Shape<T, BF3> S_;
+  constexpr int TM1 = 32 * S_::WM1;
+  const unsigned nwg = (unsigned)(cdiv(R, TM1) * cm.ntiles);
+  if (cm.full) {
+    auto k = k_xv<T, S_::WM1, S_::WN1, kGamma, BF3>;
+    constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kGamma, BF3>();
+    static bool attr = false;
+    FIRAL_CHECK(set_lds(k, lds, attr));
+    k<<<nwg, 256, lds, st>>>(Xc, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
+    FIRAL_LAUNCHED();
+  } else {
+    auto k = k_xv<T, S_::WM1, S_::WN1, kRaw, BF3>;
+    constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kRaw, BF3>();
+    static bool attr = false;
+    FIRAL_CHECK(set_lds(k, lds, attr));
+    k<<<nwg, 256, lds, st>>>(Xc, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
+    FIRAL_LAUNCHED();
+    k_gamma_rows<T><<<(unsigned)cdiv(R * cm.s, 4), 256, 0, st>>>(G, R, cm.s, cm.c, Hc, om, skip);
+    FIRAL_LAUNCHED();
+  }
+  return FIRAL_OK;
+}
+
 }  // namespace
 
-// Largest windows-per-probe count and split count the tiled kernels need (buffer sizing).
-int tiled_alpha_windows(int prec, int c) {
-  const int TN = 32 * (prec == FIRAL_F64 ? Shape<double>::WN1 : Shape<float>::WN1);
-  return c <= TN ? 1 : (int)cdiv(c, TN);
-}
-int tiled_grad_windows(int prec, int c) {
-  const int TN = 32 * (prec == FIRAL_F64 ? Shape<double>::WNG : Shape<float>::WNG);
-  return c <= TN ? 1 : (int)cdiv(c, TN);
+// Buffer sizing of the row-tiled kernels: column tiles of a block of s probes, and output
+// tiles of the X^T G' contraction.
+// (a BF16X3 context also takes the FP32 kernels, for its precise products)
+int64_t tiled_col_tiles(int prec, int c, int s) {
+  if (prec == FIRAL_F64) return colmap_for<double, false>(c, s).ntiles;
+  const int64_t n = colmap_for<float, false>(c, s).ntiles;
+  return prec == FIRAL_BF16X3 ? std::max<int64_t>(n, colmap_for<float, true>(c, s).ntiles) : n;
 }
 int64_t tiled_out_tiles(int prec, int d, int64_t sc) {
-  const int TM = 32 * (prec == FIRAL_F64 ? Shape<double>::WM2 : Shape<float>::WM2);
-  const int TN = 32 * (prec == FIRAL_F64 ? Shape<double>::WN2 : Shape<float>::WN2);
-  return cdiv(d, TM) * cdiv(sc, TN);
+  if (prec == FIRAL_F64)
+    return cdiv(d, 32 * Shape<double, false>::WM2) * cdiv(sc, 32 * Shape<double, false>::WN2);
+  const int64_t n = cdiv(d, 32 * Shape<float, false>::WM2) * cdiv(sc, 32 * Shape<float, false>::WN2);
+  if (prec != FIRAL_BF16X3) return n;
+  return std::max<int64_t>(
+      n, cdiv(d, 32 * Shape<float, true>::WM2) * cdiv(sc, 32 * Shape<float, true>::WN2));
 }
 
-template <typename T>
+template <typename T, bool BF3>
 static int hvp_tiled_t(Ctx* x, const double* omega, int64_t n_rows, double shift, const T* B,
                        T* out, int s, Skip skip, hipStream_t st) {
-  typedef Shape<T> S_;
-  constexpr int TM1 = 32 * S_::WM1, TN1 = 32 * S_::WN1;
+  typedef Shape<T, BF3> S_;
   constexpr int TM2 = 32 * S_::WM2, TN2 = 32 * S_::WN2;
   const int d = x->d, c = x->c, SC = s * c;
-  const ColMap cm = make_colmap(c, s, TN1);
+  const ColMap cm = colmap_for<T, BF3>(c, s);
   const T* X = (const T*)x->X;
   const T* H = (const T*)x->H;
   T* G = (T*)x->G;
-  T* ab = (T*)x->abuf;
   T* part = (T*)x->part;
   const int64_t n_out = (int64_t)d * SC;
   const int nmt = (int)cdiv(d, TM2), nct = (int)cdiv(SC, TN2);
   const int64_t tiles = (int64_t)nmt * nct;
   const int64_t cap = (int64_t)x->max_splits * x->s_max / s;
   const int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, tiles), cap), 256));
-
-  auto k1 = k_xv<T, S_::WM1, S_::WN1, 1, false>;
-  constexpr size_t lds1 = xv_lds_bytes<T, S_::WM1, S_::WN1, 1, false>();
-  static bool attr1 = false;
-  FIRAL_CHECK(set_lds(k1, lds1, attr1));
+  auto k2 = k_xtg<T, S_::WM2, S_::WN2, BF3>;
+  constexpr size_t lds2 = xtg_lds_bytes<T, S_::WM2, S_::WN2, BF3>();
+  static bool attr2 = false;
+  FIRAL_CHECK(set_lds(k2, lds2, attr2));
 
   FIRAL_CHECK(prof_mark(x, st, true));
   for (int64_t r0 = 0; r0 < n_rows; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, n_rows - r0);
-    const int64_t nrt = cdiv(R, TM1);
     const T* Xc = X + r0 * d;
-    const T* Hc = H + r0 * c;
-    const double* om = omega ? omega + r0 : nullptr;
-    k1<<<(unsigned)(nrt * cm.ntiles), 256, lds1, st>>>(Xc, d, R, B, nullptr, Hc, om, cm, nrt, G,
-                                                      ab, nullptr, skip);
-    FIRAL_LAUNCHED();
-    const int64_t rps = cdiv(R, S);
-    const unsigned nwg2 = (unsigned)(tiles * S);
-    if (cm.full) {
-      k_xtg<T, S_::WM2, S_::WN2, false><<<nwg2, 256, 0, st>>>(
-          Xc, d, G, SC, R, rps, nmt, nct, nullptr, c, s, nullptr, nullptr, 1, part, n_out,
-          r0 > 0, skip);
-    } else {
-      k_alpha_sum<T><<<(unsigned)cdiv(R * s, 256), 256, 0, st>>>(ab, R * s, cm.nw, skip);
-      FIRAL_LAUNCHED();
-      k_xtg<T, S_::WM2, S_::WN2, true><<<nwg2, 256, 0, st>>>(
-          Xc, d, G, SC, R, rps, nmt, nct, Hc, c, s, om, ab, cm.nw, part, n_out, r0 > 0, skip);
-    }
+    FIRAL_CHECK((xv_gamma<T, BF3>(cm, Xc, d, R, B, H + r0 * c, omega ? omega + r0 : nullptr, G,
+                                  skip, st)));
+    k2<<<(unsigned)(tiles * S), 256, lds2, st>>>(Xc, d, G, SC, R, cdiv(R, S), nmt, nct, part,
+                                                n_out, r0 > 0, skip);
     FIRAL_LAUNCHED();
   }
   FIRAL_CHECK(prof_mark(x, st, false));
@@ -571,31 +552,39 @@ static int hvp_tiled_t(Ctx* x, const double* omega, int64_t n_rows, double shift
 }
 
 int hvp_tiled_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
-                     void* out, int s, Skip skip, hipStream_t st) {
+                     void* out, int s, Skip skip, hipStream_t st, bool precise) {
   if (x->prec == FIRAL_F64)
-    return hvp_tiled_t<double>(x, omega, n_rows, shift, (const double*)B, (double*)out, s, skip,
-                               st);
-  return hvp_tiled_t<float>(x, omega, n_rows, shift, (const float*)B, (float*)out, s, skip, st);
+    return hvp_tiled_t<double, false>(x, omega, n_rows, shift, (const double*)B, (double*)out, s,
+                                      skip, st);
+  if (x->prec == FIRAL_BF16X3 && !precise)
+    return hvp_tiled_t<float, true>(x, omega, n_rows, shift, (const float*)B, (float*)out, s,
+                                    skip, st);
+  return hvp_tiled_t<float, false>(x, omega, n_rows, shift, (const float*)B, (float*)out, s, skip,
+                                   st);
 }
 
-template <typename T>
+// Gradient of eq. 11 per chunk of pool rows: u^T H_i w = (U^T x_i) . Gamma_i (W^T x_i), i.e.
+// G' = Gamma-step(1, X W) followed by the row-wise dot product of X U with G'.
+template <typename T, bool BF3>
 static int grad_tiled_t(Ctx* x, const T* U, const T* W, int s, double* g, hipStream_t st) {
-  typedef Shape<T> S_;
-  constexpr int TM = 32 * S_::WMG, TN = 32 * S_::WNG;
+  typedef Shape<T, BF3> S_;
+  constexpr int TM1 = 32 * S_::WM1;
   const int d = x->d, c = x->c;
-  const ColMap cm = make_colmap(c, s, TN);
-  auto k = k_xv<T, S_::WMG, S_::WNG, 2, true>;
-  constexpr size_t lds = xv_lds_bytes<T, S_::WMG, S_::WNG, 2, true>();
+  const ColMap cm = colmap_for<T, BF3>(c, s);
+  auto kd = k_xv<T, S_::WM1, S_::WN1, kDot, BF3>;
+  constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kDot, BF3>();
   static bool attr = false;
-  FIRAL_CHECK(set_lds(k, lds, attr));
+  FIRAL_CHECK(set_lds(kd, lds, attr));
+  T* G = (T*)x->G;
   for (int64_t r0 = 0; r0 < x->n_pool; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, x->n_pool - r0);
-    const int64_t nrt = cdiv(R, TM);
-    k<<<(unsigned)(nrt * cm.ntiles), 256, lds, st>>>((const T*)x->X + r0 * d, d, R, U, W,
-                                                    (const T*)x->H + r0 * c, nullptr, cm, nrt,
-                                                    nullptr, nullptr, x->gpart, skip_none());
+    const T* Xc = (const T*)x->X + r0 * d;
+    const T* Hc = (const T*)x->H + r0 * c;
+    FIRAL_CHECK((xv_gamma<T, BF3>(cm, Xc, d, R, W, Hc, nullptr, G, skip_none(), st)));
+    kd<<<(unsigned)(cdiv(R, TM1) * cm.ntiles), 256, lds, st>>>(Xc, d, R, U, Hc, nullptr, cm,
+                                                              nullptr, G, x->gpart, skip_none());
     FIRAL_LAUNCHED();
-    k_grad_sum<<<(unsigned)cdiv(R, 4), 256, 0, st>>>(x->gpart, R, s, cm.nw, g + r0);
+    k_grad_sum<<<(unsigned)cdiv(R, 256), 256, 0, st>>>(x->gpart, R, cm.ntiles, s, g + r0);
     FIRAL_LAUNCHED();
   }
   return FIRAL_OK;
@@ -603,8 +592,10 @@ static int grad_tiled_t(Ctx* x, const T* U, const T* W, int s, double* g, hipStr
 
 int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st) {
   if (x->prec == FIRAL_F64)
-    return grad_tiled_t<double>(x, (const double*)U, (const double*)W, s, g, st);
-  return grad_tiled_t<float>(x, (const float*)U, (const float*)W, s, g, st);
+    return grad_tiled_t<double, false>(x, (const double*)U, (const double*)W, s, g, st);
+  if (x->prec == FIRAL_BF16X3)
+    return grad_tiled_t<float, true>(x, (const float*)U, (const float*)W, s, g, st);
+  return grad_tiled_t<float, false>(x, (const float*)U, (const float*)W, s, g, st);
 }
 
 }  // namespace firal

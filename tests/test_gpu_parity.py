@@ -190,8 +190,10 @@ def test_hvp_is_deterministic():
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(2000, 50, 20, 5), (3001, 7, 100, 10), (517, 3, 37, 13),
-                                   (700, 4, 130, 3), (900, 2, 200, 2), (800, 1, 300, 2)])
+                                   (700, 4, 130, 3), (900, 2, 200, 2), (800, 1, 300, 2),
+                                   (600, 3, 45, 40), (500, 5, 24, 70), (400, 2, 27, 130)])
 def test_precond_matches_oracle(prec, shape):
+    # class tiles of 32, 64 and 128 (the last ones partial), pair tiles cut by d
     n, nl, d, c = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=6)
     ctx, X, H = context(p, prec, 1)
@@ -400,6 +402,28 @@ def test_hvp_bf16x3(shape):
         got = host(ctx.hvp(dev(B, torch.float32), omega=dev(om, torch.float64), shift=1e-3))
         ref = orc.hvp(X, H, om, 1e-3, B)
         assert relerr(got, ref) <= BF3_TOL, relerr(got, ref)
+
+
+@pytest.mark.parametrize("shape", TILED_SHAPES)
+def test_tiled_bf16x3_hvp_and_grad(shape, monkeypatch):
+    # the row-tiled kernels with split products (FIRAL_UNFUSED=1 keeps small shapes off the
+    # fused kernel): every column mode, against the FP64 oracle at the bf16x3 bar
+    monkeypatch.setenv("FIRAL_UNFUSED", "1")
+    n, nl, d, c, s = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=27, whiten_x=True, probs="maxprob")
+    X = rounded(p.X, "f32")
+    H = rounded(p.H, "f32")
+    ctx = RelaxContext(dev(X, torch.float32), dev(H, torch.float32), p.n_pool, s, "bf16x3")
+    rng = np.random.default_rng(23)
+    B = rounded(rng.standard_normal((d, s, c)), "f32")
+    om = rng.uniform(0.0, 1.0, p.N)
+    got = host(ctx.hvp(dev(B, torch.float32), omega=dev(om, torch.float64), shift=1e-3))
+    e = relerr(got, orc.hvp(X, H, om, 1e-3, B))
+    assert e <= BF3_TOL, ("hvp", e)
+    U = rng.choice([-1.0, 1.0], size=(d, s, c))
+    g = host(ctx.grad_z(dev(U, torch.float32), dev(B, torch.float32)))
+    e = relerr(g, orc.grad_contract(X[:n], H[:n], U, B))
+    assert e <= BF3_TOL, ("grad", e)
 
 
 def test_relax_bf16x3_gradient_error_fixed_iterations():
