@@ -63,7 +63,7 @@ int prof_mark(Ctx* x, hipStream_t st, bool start) {
 
 static void free_ctx(Ctx* x) {
   drop_events(x);
-  void* bufs[] = {x->G, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->P, x->Pinv, x->syrk_part, x->syrk_tiles, x->V, x->W1, x->Y,
+  void* bufs[] = {x->G, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->XThi, x->XTlo, x->P, x->Pinv, x->syrk_part, x->syrk_tiles, x->V, x->W1, x->Y,
                   x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
                   x->redpart, x->status, x->counter};
@@ -199,6 +199,8 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
     const long long v = atoll(env);
     if (v >= 1 && v < rows) rows = v;
   }
+  // bf16x3: chunks start on multiples of 32 rows (the X^T planes are read 8 rows at a time)
+  if (prec == FIRAL_BF16X3) rows = std::max<int64_t>(32, rows - rows % 32);
   x->chunk_rows = rows;
   const int64_t tiles = tiled_out_tiles(prec, d, sc);
   x->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, tiles), 64));
@@ -237,6 +239,13 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   ALLOC(x->Pinv, (int64_t)c * d * d * 8);
   ALLOC(x->syrk_part, (int64_t)x->syrk_splits * c * d * d * es);
   ALLOC(x->syrk_tiles, syrk_tiles.size() * sizeof(int32_t));
+  if (prec == FIRAL_BF16X3) {
+    x->ldt = cdiv(x->N, 8) * 8;
+    ALLOC(x->Xhi, x->N * d * 2);
+    ALLOC(x->Xlo, x->N * d * 2);
+    ALLOC(x->XThi, x->ldt * d * 2);
+    ALLOC(x->XTlo, x->ldt * d * 2);
+  }
   ALLOC(x->V, blk * es);
   ALLOC(x->W1, blk * es);
   ALLOC(x->Y, blk * es);
@@ -274,6 +283,7 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
         hipMemsetAsync(x->counter, 0, sizeof(int32_t), st) != hipSuccess ||
         hipMemcpyAsync(x->syrk_tiles, syrk_tiles.data(), syrk_tiles.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
+        (prec == FIRAL_BF16X3 && split_x_launch(x, st) != FIRAL_OK) ||
         hipStreamSynchronize(st) != hipSuccess) {
       set_error("status initialisation failed");
       rc = FIRAL_EHIP;

