@@ -203,7 +203,7 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   if (prec == FIRAL_BF16X3) rows = std::max<int64_t>(32, rows - rows % 32);
   x->chunk_rows = rows;
   const int64_t tiles = tiled_out_tiles(prec, d, sc);
-  x->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(1024, tiles), 64));
+  x->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(4096, tiles), 64));
 
   std::vector<int32_t> syrk_tiles;
   syrk_plan(prec, d, c, &syrk_tiles, &x->syrk_splits);

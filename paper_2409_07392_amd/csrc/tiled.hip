@@ -401,8 +401,9 @@ __global__ __launch_bounds__(256, 2) void k_xv(
 }
 
 // Row step of Lemma 1 for probes wider than a column tile: one wave per (row, probe),
-// alpha = sum_k G h_k (FP64), then G <- omega (G - alpha) h in place.
-template <typename T>
+// alpha = sum_k G h_k (FP64), then G <- omega (G - alpha) h in place.  VEC: c % 4 == 0 and
+// c <= 1024, the row held in registers as float4 (one read of G, one write).
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_gamma_rows(T* __restrict__ G, int64_t R, int s, int c,
                                                     const T* __restrict__ H,
                                                     const double* __restrict__ omega, Skip skip) {
@@ -413,12 +414,47 @@ __global__ __launch_bounds__(256) void k_gamma_rows(T* __restrict__ G, int64_t R
   const int64_t r = id / s;
   T* gr = G + id * c;        // row r, probe id - r s
   const T* hr = H + r * c;
-  double a = 0.0;
-  for (int k = lane; k < c; k += 64) a += (double)gr[k] * (double)hr[k];
-  a = wave_sum(a);
-  const T al = (T)__shfl(a, 0, 64);
   const T om = omega ? (T)omega[r] : T(1);
-  for (int k = lane; k < c; k += 64) gr[k] = om * ((gr[k] - al) * hr[k]);
+  if constexpr (VEC) {
+    const int n4 = c >> 2;
+    float4 gv[4], hv[4];
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k4 = lane + 64 * q;
+      if (k4 < n4) {
+        gv[q] = reinterpret_cast<const float4*>(gr)[k4];
+        hv[q] = reinterpret_cast<const float4*>(hr)[k4];
+      } else {
+        gv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        hv[q] = gv[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      a += (double)gv[q].x * hv[q].x + (double)gv[q].y * hv[q].y + (double)gv[q].z * hv[q].z +
+           (double)gv[q].w * hv[q].w;
+    a = wave_sum(a);
+    const float al = (float)__shfl(a, 0, 64);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k4 = lane + 64 * q;
+      if (k4 < n4) {
+        float4 o;
+        o.x = om * ((gv[q].x - al) * hv[q].x);
+        o.y = om * ((gv[q].y - al) * hv[q].y);
+        o.z = om * ((gv[q].z - al) * hv[q].z);
+        o.w = om * ((gv[q].w - al) * hv[q].w);
+        reinterpret_cast<float4*>(gr)[k4] = o;
+      }
+    }
+  } else {
+    double a = 0.0;
+    for (int k = lane; k < c; k += 64) a += (double)gr[k] * (double)hr[k];
+    a = wave_sum(a);
+    const T al = (T)__shfl(a, 0, 64);
+    for (int k = lane; k < c; k += 64) gr[k] = om * ((gr[k] - al) * hr[k]);
+  }
 }
 
 // Kernel 2.  part[split][a, col] (+)= sum over the split's rows r of X[r, a] G'[r, col], with
@@ -666,7 +702,11 @@ int xv_gamma(const ColMap& cm, const XRows<T>& xr, int d, int64_t R, const T* B,
     FIRAL_CHECK(set_lds(k, lds, attr));
     k<<<nwg, 256, lds, st>>>(xr.x, xr.xh, xr.xl, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
     FIRAL_LAUNCHED();
-    k_gamma_rows<T><<<(unsigned)cdiv(R * cm.s, 4), 256, 0, st>>>(G, R, cm.s, cm.c, Hc, om, skip);
+    const unsigned nb = (unsigned)cdiv(R * cm.s, 4);
+    if (sizeof(T) == 4 && cm.c % 4 == 0 && cm.c <= 1024)
+      k_gamma_rows<T, true><<<nb, 256, 0, st>>>(G, R, cm.s, cm.c, Hc, om, skip);
+    else
+      k_gamma_rows<T, false><<<nb, 256, 0, st>>>(G, R, cm.s, cm.c, Hc, om, skip);
     FIRAL_LAUNCHED();
   }
   return FIRAL_OK;
@@ -699,7 +739,8 @@ static int hvp_tiled_t(Ctx* x, const double* omega, int64_t n_rows, double shift
   const int nmt = (int)cdiv(d, TM2), nct = (int)cdiv(SC, TN2);
   const int64_t tiles = (int64_t)nmt * nct;
   const int64_t cap = (int64_t)x->max_splits * x->s_max / s;
-  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, tiles), cap), 256));
+  // enough row splits for several full rounds of two workgroups per CU
+  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(4096, tiles), cap), 256));
   auto k2 = k_xtg<T, S_::WM2, S_::WN2, BF3>;
   constexpr size_t lds2 = xtg_lds_bytes<T, S_::WM2, S_::WN2, BF3>();
   static bool attr2 = false;
