@@ -9,6 +9,14 @@ clusters, whitened) and softmax probabilities with mean max-prob 0.7.
     python bench.py [--steps K] [--warmup W] [--prec f32|f64] [--literal]
 
 Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+
+--workload 3 / 4 measures the larger configurations instead (their inputs drawn on
+the GPU with the same recipes): configuration 3 (n = 200,000, d = 256, c = 100,
+s = 32) times the sampled objective and its adjoint gradient at a Dirichlet z;
+configuration 4 (n = 1,280,000, d = 384, c = 1000, s = 16) times Relax iterations
+with a fixed number of CG iterations per solve (--fixed-cg).  Both report the
+product's TFLOP/s and the gradient error against the GPU FP64 mode for FP32 and
+bf16x3.  These are measurements of the other workloads, not the bench line.
 """
 from __future__ import annotations
 
@@ -22,10 +30,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Relax iter time + HVP TFLOP/s, FP32 vs bf16x3 at ≤1e-4 rel grad error"
-PEAK = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0}   # TFLOP/s, MI355X dense MFMA
+# TFLOP/s, MI355X dense MFMA; bf16x3 counts the FP32-equivalent products of three bf16 passes
+PEAK = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0 / 3}
 KERNEL_NAME = {"f32": "k_hvp_fused<7,2> (fused Lemma 1 product, FP32)",
                "bf16x3": "k_hvp_fused_bf3<7,2> (fused Lemma 1 product, bf16x3)",
-               "f64": "general product path (FP64 contraction kernels)"}
+               "f64": "row-tiled product kernels (FP64), per-chunk span"}
 # HBM bytes per launch of the main kernel from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # each scaled by the copy-kernel calibration factor (profiles/; None until measured for
 # the current kernel)
@@ -44,6 +53,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4])
+    ap.add_argument("--fixed-cg", type=int, default=50,
+                    help="configuration 4: CG iterations per solve of each timed Relax iteration")
     return ap.parse_args()
 
 
@@ -76,8 +88,8 @@ def run_leg(p, prec, steps, warmup, project, hvp_reps):
     from paper_2409_07392_amd import RelaxContext, default_beta0
     dt = torch.float64 if prec == "f64" else torch.float32
     dev = torch.device("cuda:0")
-    X = torch.as_tensor(p.X, dtype=dt, device=dev)
-    H = torch.as_tensor(p.H, dtype=dt, device=dev)
+    X = torch.as_tensor(p.X, dtype=dt, device=dev).contiguous()
+    H = torch.as_tensor(p.H, dtype=dt, device=dev).contiguous()
     ctx = RelaxContext(X, H, p.n_pool, p.s, prec)
     beta0 = default_beta0(p.n_pool, p.T)
     wtmp = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
@@ -144,6 +156,109 @@ def grad_errors(p, project, n_cg=15):
     return {k: float(np.linalg.norm(g[k] - g["f64"]) / ref) for k in ("f32", "bf16x3")}
 
 
+def log(msg):
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
+def hvp_timing(ctx, p, reps):
+    """(seconds per product call, seconds per main-kernel span) with omega = [b/n; 1]."""
+    import torch
+    B = ctx.probes(p.probe_seed, 1, p.s)
+    out = torch.empty_like(B)
+    om = torch.full((p.N,), 1.0, dtype=torch.float64, device="cuda:0")
+    om[:p.n_pool] = p.b / p.n_pool
+    ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t_call = ev0.elapsed_time(ev1) / 1e3 / reps
+    ctx.profile_begin()
+    for _ in range(reps):
+        ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    k_ms, k_n = ctx.profile_end()
+    return t_call, k_ms / 1e3 / max(k_n, 1)
+
+
+def large_workload(args):
+    """Configurations 3 and 4: FP32 and bf16x3 legs plus the FP64 reference gradient."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, default_beta0
+    from synthdata.device import make_problem_device
+    cfg = args.workload
+    log(f"drawing configuration {cfg} on the GPU")
+    p = make_problem_device(cfg, device="cuda:0")
+    flops = 4.0 * p.N * p.c * p.d * p.s
+    beta0 = default_beta0(p.n_pool, max(p.T, 1))
+    reps = 20 if cfg == 3 else 5
+    z = None
+    if cfg == 3:   # z = b * Dirichlet(1_n), drawn on the device
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(3003)
+        e = -torch.log(torch.rand(p.n_pool, generator=g, device="cuda:0", dtype=torch.float64))
+        z = p.b * e / e.sum()
+    V = None
+    legs, grads = {}, {}
+    n_cg_err = 10
+    for prec in ("f32", "bf16x3", "f64"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        ctx = RelaxContext(p.X.to(dt).contiguous(), p.H.to(dt).contiguous(), p.n_pool, p.s, prec)
+        w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda:0")
+        gt = torch.empty_like(w)
+        if prec != "f64":
+            log(f"{prec}: product timing")
+            t_call, t_kern = hvp_timing(ctx, p, reps)
+            leg = {"hvp_ms": t_call * 1e3, "hvp_tflops": flops / t_call / 1e12,
+                   "kernel_ms": t_kern * 1e3, "kernel_tflops": flops / t_kern / 1e12}
+            log(f"{prec}: timed step")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if cfg == 4:
+                info = ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, 0.0,
+                                      args.fixed_cg, True)
+                leg["relax_iter_ms_fixed_cg"] = (time.perf_counter() - t0) * 1e3
+                leg["cg_iters"] = list(info["cg_iters"])
+            else:
+                Vd = ctx.probes(p.probe_seed, 1, p.s)
+                f, _, info = ctx.sampled_objective(z, p.lam, Vd, tol=p.tol, max_iter=1000,
+                                                   project=True)
+                leg["objective_and_adjoint_ms"] = (time.perf_counter() - t0) * 1e3
+                leg["cg_iters"] = list(info["cg_iters"])
+                leg["f"] = f
+            legs[prec] = leg
+        log(f"{prec}: gradient at {n_cg_err} fixed CG iterations")
+        w.fill_(1.0 / p.n_pool)
+        ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, 0.0, n_cg_err, True, g_out=gt)
+        grads[prec] = gt.cpu().numpy()
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    ref = np.linalg.norm(grads["f64"])
+    for prec in ("f32", "bf16x3"):
+        legs[prec]["rel_grad_err_vs_f64"] = float(np.linalg.norm(grads[prec] - grads["f64"]) / ref)
+    main = legs["f32"]
+    res = {
+        "metric": METRIC,
+        "workload": f"configuration {cfg}",
+        "config": {"n_pool": p.n_pool, "n_lab": p.n_lab, "d": p.d, "c": p.c, "s": p.s,
+                   "b": p.b, "tol": p.tol, "inputs": "drawn on the GPU (synthdata.device)"},
+        "precision_legs": legs,
+        "roofline": {"bound": "mfma", "kernel": "row-tiled product (per-chunk span)",
+                     "f32": {"achieved": main["kernel_tflops"], "peak": PEAK["f32"],
+                             "frac": main["kernel_tflops"] / PEAK["f32"]},
+                     "bf16x3": {"achieved": legs["bf16x3"]["kernel_tflops"],
+                                "peak": PEAK["bf16x3"],
+                                "frac": legs["bf16x3"]["kernel_tflops"] / PEAK["bf16x3"]},
+                     "unit": "TFLOP/s"},
+    }
+    print(json.dumps(res))
+
+
 def calibrate_copy(mib):
     """A plain device copy of `mib` MiB (for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
     import torch
@@ -165,6 +280,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Relax path "
               "of this build is single-GPU.", file=sys.stderr)
         sys.exit(2)
+    if args.workload != 2:
+        large_workload(args)
+        return
     from synthdata import make_problem
     from paper_2409_07392_amd import default_beta0
 
