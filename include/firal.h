@@ -165,6 +165,54 @@ int firal_sampled_objective(firal_ctx ctx, const double* z, double lambda, const
 int firal_profile_begin(firal_ctx ctx);
 int firal_profile_end(firal_ctx ctx, double* total_ms, int64_t* launches);
 
+/* Kernel-variant tuner (the tile plan of extension (2); usable on any context).  Times on this
+ * context, for s probes, the product kernels (fused single pass where its plan fits, row-tiled)
+ * and the PCG step forms (column-local, separate kernels), keeps the faster of each for the
+ * context and remembers the choice for the process per bucket (precision, d, c, s, n_pool +
+ * n_lab rounded up to a power of two); a bucket already tuned is applied without timing.
+ * The context's work blocks and preconditioner are overwritten.  choice (host, may be NULL)
+ * gets bit 0 = row-tiled product, bit 1 = separate-kernel PCG.  Synchronous. */
+int firal_autotune(firal_ctx ctx, int32_t s, int32_t* choice, void* stream);
+
+/* Batch of independent Relax problems (extension (2)): one Relax iteration (Algorithm 2) of
+ * every problem captured into a single HIP graph, one branch per problem, replayed as a whole.
+ * Each problem keeps its own context (created as usual, one per problem, not shared) and its
+ * own simplex weights; the branches run concurrently.  In the captured step every PCG solve
+ * enqueues exactly max_iter iterations whose kernels return at once after all columns have
+ * met tol (the results equal those of firal_relax_step with the same arguments), and the
+ * iteration index is kept on the device: replay k runs iteration t0 + k of every problem. */
+typedef struct firal_batch_s* firal_batch;
+typedef struct {
+  firal_ctx ctx;        /* the problem's context */
+  double* w;            /* device FP64 [n_pool]: simplex weights, advanced in place */
+  double b;             /* budget: z = b w */
+  double lambda;        /* regulariser of Sigma_z */
+  double beta0;         /* mirror-descent step scale */
+  uint64_t seed;        /* probe stream seed */
+  int32_t t0;           /* iteration index of the first replay, >= 1 */
+  int32_t s;            /* probes, 1..s_max of the context */
+  double tol;           /* PCG relative-residual tolerance */
+  int32_t max_iter;     /* PCG iterations enqueued per solve */
+  uint32_t flags;       /* FIRAL_PCG_PROJECT */
+} firal_batch_problem;
+
+/* Tune each problem (firal_autotune), run one uncaptured pass of each problem's captured step
+ * (weights and iteration index restored afterwards), then capture and instantiate the graph.
+ * probs (host, n entries) is copied.  Errors: EINVAL (null argument, n < 1, a shared context,
+ * s outside the context's range, t0 < 1, max_iter < 0, b or lambda not positive), EHIP, ENOMEM.
+ * Synchronous. */
+int firal_batch_create(firal_batch* out, int32_t n, const firal_batch_problem* probs,
+                       void* stream);
+/* Replay the graph iters times on stream (asynchronous). */
+int firal_batch_run(firal_batch batch, int32_t iters, void* stream);
+/* Synchronise stream and report problem i's last iteration (as firal_relax_step's info; the
+ * return code carries ENOTSPD, EBREAKDOWN or WARN_NOT_CONVERGED of that iteration). */
+int firal_batch_info(firal_batch batch, int32_t i, firal_info* info, void* stream);
+/* The iteration index problem i's next replay will run (synchronises the device). */
+int firal_batch_next_t(firal_batch batch, int32_t i, int32_t* t);
+/* Release the graph, streams and events (the contexts stay with the caller).  NULL is a no-op. */
+int firal_batch_destroy(firal_batch batch);
+
 /* Static description of a return code. */
 const char* firal_strerror(int code);
 

@@ -15,8 +15,8 @@ from . import _lib
 from ._lib import (BF16X3, F32, F64, PCG_PROJECT, FiralError, Info, WARN_NOT_CONVERGED, check,
                    load)
 
-__all__ = ["RelaxContext", "RelaxObjective", "FiralError", "default_beta0", "F64", "F32",
-           "BF16X3", "load"]
+__all__ = ["RelaxContext", "RelaxBatch", "RelaxObjective", "FiralError", "default_beta0", "F64",
+           "F32", "BF16X3", "load"]
 
 _DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32}
 
@@ -173,6 +173,16 @@ class RelaxContext:
         d["rc"] = rc
         return f.value, g, d
 
+    def autotune(self, s=None):
+        """Time the kernel variants on this problem and keep the faster ones (firal_autotune).
+
+        Returns the choice bits: 1 = row-tiled product, 2 = separate-kernel PCG.  The work
+        blocks and preconditioner of the context are overwritten."""
+        s = self.s_max if s is None else int(s)
+        ch = _lib.ctypes.c_int32()
+        check(self.lib.firal_autotune(self._ctx, s, _lib.ctypes.byref(ch), _stream()))
+        return ch.value
+
     def profile_begin(self):
         """Start timing every launch of the main product kernel with events on its stream."""
         check(self.lib.firal_profile_begin(self._ctx))
@@ -188,6 +198,62 @@ class RelaxContext:
         if getattr(self, "_ctx", None) is not None and self._ctx.value:
             self.lib.firal_destroy(self._ctx)
             self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RelaxBatch:
+    """Independent Relax problems advanced together by one captured HIP graph (extension 2).
+
+    problems: list of dicts with keys ctx (a RelaxContext, one per problem), w (CUDA float64
+    simplex weights, advanced in place), b, lam, beta0, seed, and optionally t0 (1), s
+    (ctx.s_max), tol (1e-6), max_iter (100), project (True).  Every replay runs one Relax
+    iteration of every problem; each PCG solve enqueues exactly max_iter iterations whose
+    kernels return once all columns have converged.
+    """
+
+    def __init__(self, problems):
+        self.lib = load()
+        self.problems = list(problems)
+        arr = (_lib.BatchProblem * len(self.problems))()
+        for i, q in enumerate(self.problems):
+            ctx = q["ctx"]
+            w = RelaxContext._f64(q["w"], ctx.n_pool)
+            if w.data_ptr() != q["w"].data_ptr():
+                raise ValueError("w must be a contiguous CUDA float64 tensor (updated in place)")
+            arr[i] = _lib.BatchProblem(ctx._ctx.value, w.data_ptr(), float(q["b"]), float(q["lam"]),
+                                       float(q["beta0"]), int(q["seed"]) & (2**64 - 1),
+                                       int(q.get("t0", 1)), int(q.get("s", ctx.s_max)),
+                                       float(q.get("tol", 1e-6)), int(q.get("max_iter", 100)),
+                                       PCG_PROJECT if q.get("project", True) else 0)
+        self._b = _lib.ctypes.c_void_p()
+        check(self.lib.firal_batch_create(_lib.ctypes.byref(self._b), len(self.problems), arr,
+                                          _stream()))
+
+    def run(self, iters=1):
+        check(self.lib.firal_batch_run(self._b, int(iters), _stream()))
+
+    def info(self, i):
+        info = Info()
+        rc = self.lib.firal_batch_info(self._b, int(i), _lib.ctypes.byref(info), _stream())
+        check(rc)
+        d = info.as_dict()
+        d["rc"] = rc
+        return d
+
+    def next_t(self, i):
+        t = _lib.ctypes.c_int32()
+        check(self.lib.firal_batch_next_t(self._b, int(i), _lib.ctypes.byref(t)))
+        return t.value
+
+    def close(self):
+        if getattr(self, "_b", None) is not None and self._b.value:
+            self.lib.firal_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

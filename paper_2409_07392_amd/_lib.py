@@ -18,7 +18,8 @@ PCG_PROJECT = 1
 EXPORTS = ("firal_create", "firal_destroy", "firal_hvp", "firal_build_precond",
            "firal_pcg_solve", "firal_grad_z", "firal_probes", "firal_relax_step",
            "firal_sampled_objective", "firal_profile_begin", "firal_profile_end",
-           "firal_strerror", "firal_last_error")
+           "firal_autotune", "firal_batch_create", "firal_batch_run", "firal_batch_info",
+           "firal_batch_next_t", "firal_batch_destroy", "firal_strerror", "firal_last_error")
 
 
 class Info(ctypes.Structure):
@@ -33,6 +34,14 @@ class Info(ctypes.Structure):
                     converged=bool(self.converged), bad_block=int(self.bad_block),
                     relres_max=float(self.relres_max), f_hat=float(self.f_hat),
                     g_absmax=float(self.g_absmax), beta=float(self.beta))
+
+
+class BatchProblem(ctypes.Structure):
+    """firal_batch_problem."""
+    _fields_ = [("ctx", ctypes.c_void_p), ("w", ctypes.c_void_p), ("b", ctypes.c_double),
+                ("lam", ctypes.c_double), ("beta0", ctypes.c_double), ("seed", ctypes.c_uint64),
+                ("t0", ctypes.c_int32), ("s", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("flags", ctypes.c_uint32)]
 
 
 class FiralError(RuntimeError):
@@ -67,6 +76,12 @@ def load() -> ctypes.CDLL:
         "firal_relax_step": [vp, vp, dbl, dbl, dbl, u64, i32, i32, dbl, i32, u32, vp, pinfo, vp],
         "firal_sampled_objective": [vp, vp, dbl, vp, i32, dbl, i32, u32, ctypes.POINTER(dbl), vp,
                                     pinfo, vp],
+        "firal_autotune": [vp, i32, ctypes.POINTER(i32), vp],
+        "firal_batch_create": [ctypes.POINTER(vp), i32, ctypes.POINTER(BatchProblem), vp],
+        "firal_batch_run": [vp, i32, vp],
+        "firal_batch_info": [vp, i32, pinfo, vp],
+        "firal_batch_next_t": [vp, i32, ctypes.POINTER(i32)],
+        "firal_batch_destroy": [vp],
         "firal_profile_begin": [vp],
         "firal_profile_end": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         "firal_strerror": [ctypes.c_int],

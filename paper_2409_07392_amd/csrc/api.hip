@@ -66,7 +66,7 @@ static void free_ctx(Ctx* x) {
   void* bufs[] = {x->G, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->XThi, x->XTlo, x->P, x->Pinv, x->syrk_part, x->syrk_tiles, x->V, x->W1, x->Y,
                   x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
-                  x->redpart, x->status, x->counter};
+                  x->redpart, x->status, x->counter, x->t_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (x->status_host) (void)hipHostFree(x->status_host);
@@ -212,7 +212,7 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   x->red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n_pool, 256), 1024));
 
   const char* unf = getenv("FIRAL_UNFUSED");
-  x->force_unfused = unf && atoi(unf) != 0;
+  x->force_tiled = x->force_multik = unf && atoi(unf) != 0;
   // BF16X3 PCG: switch to FP32 products below this relative residual (0 = never).  With the
   // residual kept in the projected space the split products converge like FP32 ones, so
   // the switch is off unless asked for.
@@ -269,6 +269,7 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   ALLOC(x->redpart, (3 * (int64_t)x->red_blocks + 1) * 8);
   ALLOC(x->status, sizeof(Status));
   ALLOC(x->counter, sizeof(int32_t));
+  ALLOC(x->t_dev, sizeof(int32_t));
 #undef ALLOC
   if (rc == FIRAL_OK) {
     hipError_t he = hipHostMalloc((void**)&x->status_host, sizeof(Status), hipHostMallocDefault);

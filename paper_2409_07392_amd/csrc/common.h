@@ -77,7 +77,12 @@ struct Ctx {
   // fused FP32 product: per-row-range partials of the output block
   void* fused_part;
   int64_t fused_part_elems;
-  int force_unfused;    // FIRAL_UNFUSED=1: always take the general three-pass product
+  int force_tiled;      // product: the row-tiled kernels even where the fused plan fits
+  int force_multik;     // PCG: separate kernels even where the column-local step fits
+                        // (FIRAL_UNFUSED=1 sets both; firal_autotune chooses them)
+  int async;            // enqueue without host reads (graph capture): fixed-trip PCG whose
+                        // kernels return once every column has converged
+  int32_t* t_dev;       // device Relax-iteration counter of captured steps
   double bf3_switch;    // BF16X3 PCG: FP32 products once max_j ||r_j||/||b_j|| < bf3_switch
 
   // bf16x3 contexts: hi/lo bf16 planes of X (N x d) and of X^T (d x ldt, ldt = N rounded up
@@ -278,7 +283,11 @@ int hvp_tiled_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, 
 int64_t tiled_col_tiles(int prec, int c, int s);
 int split_x_launch(Ctx* x, hipStream_t st);
 int64_t tiled_out_tiles(int prec, int d, int64_t sc);
-int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st);
+int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st,
+                  const int32_t* t_dev = nullptr);
+int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, uint64_t seed,
+                      int t, int s, double tol, int max_iter, uint32_t flags, double* g_out,
+                      hipStream_t st);
 int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, Skip skip,
                   hipStream_t st);
 

@@ -67,7 +67,7 @@ template int reduce_parts_launch<double>(const double*, int64_t, int, double, co
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
                void* out, int s, Skip skip, hipStream_t st, bool precise) {
   FusedPlan plan;
-  if (x->prec != FIRAL_F64 && !x->force_unfused && fused_plan(x, s, n_rows, &plan, precise) &&
+  if (x->prec != FIRAL_F64 && !x->force_tiled && fused_plan(x, s, n_rows, &plan, precise) &&
       plan.part_elems <= x->fused_part_elems)
     return hvp_fused_launch(x, plan, omega, n_rows, shift, (const float*)B, (float*)out, s, skip,
                             st);

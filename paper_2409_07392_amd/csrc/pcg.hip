@@ -523,6 +523,12 @@ static int apply_t(Ctx* x, const double* Pinv, const T* r, T* z, int s, bool pro
   return FIRAL_OK;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ v, int64_t n, T value) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = value;
+}
+
 static int read_status(Ctx* x, hipStream_t st) {
   FIRAL_HIP(hipMemcpyAsync(x->status_host, x->status, sizeof(Status), hipMemcpyDeviceToHost, st));
   FIRAL_HIP(hipStreamSynchronize(st));
@@ -547,7 +553,7 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
   const unsigned nb = (unsigned)cdiv(n, 256);
 
   const size_t col_lds = (size_t)(3 + kColSplit) * d * c * sizeof(double);
-  if (col_lds <= 128 * 1024 && !x->force_unfused) {
+  if (col_lds <= 128 * 1024 && !x->force_multik) {
     // column-local CG: init, then per iteration the product and one step kernel
     static bool attr[2] = {false, false};
     if (!attr[sizeof(T) == 8]) {
@@ -564,9 +570,9 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
     // Mixed precision (BF16X3): bf16x3 products while every column's relative residual is
     // above bf3_switch, FP32 products from the first check point where none is.  The switch
     // keeps the operator error of the split products from stalling the last iterations.
-    const bool mixed = x->prec == FIRAL_BF16X3 && tol > 0.0;
+    const bool mixed = x->prec == FIRAL_BF16X3 && tol > 0.0 && !x->async;
     bool precise = false;
-    const int check_every = tol > 0.0 ? 4 : (max_iter > 0 ? max_iter : 1);
+    const int check_every = tol > 0.0 && !x->async ? 4 : (max_iter > 0 ? max_iter : 1);
     int launched = 0;
     while (launched < max_iter) {
       const int batch = std::min(check_every, max_iter - launched);
@@ -598,7 +604,8 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
     return FIRAL_OK;
   }
 
-  FIRAL_HIP(hipMemsetAsync(xv, 0, n * sizeof(T), st));
+  k_fill<T><<<nb, 256, 0, st>>>(xv, n, T(0));
+  FIRAL_LAUNCHED();
   if (project) {
     k_project<T><<<(unsigned)cdiv((int64_t)d * s, 256), 256, 0, st>>>(B, r, d, s, c, skip_none());
     FIRAL_LAUNCHED();
@@ -612,9 +619,9 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
   k_cg_init<<<1, 64, 0, st>>>(part0, part1, s, P, x->status, x->rho, x->bnorm, x->relres, x->done);
   FIRAL_LAUNCHED();
 
-  const bool mixed = x->prec == FIRAL_BF16X3 && tol > 0.0;
+  const bool mixed = x->prec == FIRAL_BF16X3 && tol > 0.0 && !x->async;
   bool precise = false;
-  const int check_every = tol > 0.0 ? 4 : (max_iter > 0 ? max_iter : 1);
+  const int check_every = tol > 0.0 && !x->async ? 4 : (max_iter > 0 ? max_iter : 1);
   int launched = 0;
   while (launched < max_iter) {
     const int batch = std::min(check_every, max_iter - launched);

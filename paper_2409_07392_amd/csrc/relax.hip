@@ -19,8 +19,10 @@ __device__ __forceinline__ uint64_t splitmix_final(uint64_t z) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_probes(T* __restrict__ V, uint64_t seed, int t, int d,
-                                                int s, int c) {
+__global__ __launch_bounds__(256) void k_probes(T* __restrict__ V, uint64_t seed, int t_host,
+                                                const int32_t* __restrict__ t_dev, int d, int s,
+                                                int c) {
+  const int t = t_dev ? *t_dev : t_host;   // captured steps read the iteration from the device
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t sc = (int64_t)s * c;
   if (idx >= (int64_t)d * sc) return;
@@ -33,19 +35,19 @@ __global__ __launch_bounds__(256) void k_probes(T* __restrict__ V, uint64_t seed
   V[idx] = (z >> 63) ? T(-1) : T(1);
 }
 
-int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st) {
+int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st,
+                  const int32_t* t_dev) {
   const int64_t n = (int64_t)x->d * s * x->c;
   if (x->prec == FIRAL_F64)
-    k_probes<double><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((double*)V, seed, t, x->d, s, x->c);
+    k_probes<double><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((double*)V, seed, t, t_dev, x->d, s,
+                                                             x->c);
   else
-    k_probes<float><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((float*)V, seed, t, x->d, s, x->c);
+    k_probes<float><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((float*)V, seed, t, t_dev, x->d, s,
+                                                            x->c);
   FIRAL_LAUNCHED();
   return FIRAL_OK;
 }
 
-// ----------------------------------------------------------- gradient
-// g[r] = -(1/s) sum_j [ sum_k A h B - (A.h)(B.h) ]  with A = X U, B = X W row r
-// (Lemma 1: u^T H_i w = (U^T x_i)^T Gamma_i (W^T x_i)).  FP64 accumulation.
 // ----------------------------------------------------- mirror descent
 // Four passes with per-block partials re-reduced in a fixed order by every block:
 //   (1) max|g|   (2) beta = beta0/max|g|, e = log w - beta g, max e
@@ -150,7 +152,8 @@ __global__ __launch_bounds__(256) void k_fhat(const double* part, int s, int P, 
   if (threadIdx.x == 0) st->f_hat = f / s;
 }
 
-__global__ void k_step_reset(Status* st) {
+__global__ void k_step_reset(Status* st, double* keep) {
+  *keep = 0.0;   // running max of the two solves' residuals
   st->converged = 1;
   st->breakdown = 0;
   st->bad_block = INT_MAX;
@@ -162,6 +165,8 @@ __global__ void k_step_reset(Status* st) {
   st->beta = 0.0;
 }
 
+__global__ void k_advance(int32_t* t) { *t += 1; }
+
 __global__ void k_relres_merge(Status* st, double* keep) {
   // keeps the max recurrence residual over both solves
   *keep = fmax(*keep, st->relres_max);
@@ -171,13 +176,12 @@ __global__ void k_relres_merge(Status* st, double* keep) {
 int objective_launch(Ctx* x, const double* z, double lambda, const void* V, int s, double tol,
                      int max_iter, uint32_t flags, double* g, hipStream_t st) {
   const int64_t n = x->n_pool, N = x->N;
-  k_step_reset<<<1, 1, 0, st>>>(x->status);
+  double* keep = x->redpart + 3 * x->red_blocks;
+  k_step_reset<<<1, 1, 0, st>>>(x->status, keep);
   FIRAL_LAUNCHED();
   k_omega<<<(unsigned)cdiv(N, 256), 256, 0, st>>>(z, 1.0, n, N, x->omega);
   FIRAL_LAUNCHED();
   FIRAL_CHECK(precond_launch(x, x->omega, lambda, st));
-  double* keep = x->redpart + 3 * x->red_blocks;
-  FIRAL_HIP(hipMemsetAsync(keep, 0, sizeof(double), st));
   FIRAL_CHECK(pcg_launch(x, x->omega, lambda, x->Pinv, V, x->W1, s, tol, max_iter, flags, 0, st));
   k_relres_merge<<<1, 1, 0, st>>>(x->status, keep);
   FIRAL_LAUNCHED();
@@ -199,14 +203,13 @@ int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, 
                       int t, int s, double tol, int max_iter, uint32_t flags, double* g_out,
                       hipStream_t st) {
   const int64_t n = x->n_pool, N = x->N;
-  k_step_reset<<<1, 1, 0, st>>>(x->status);
+  double* keep = x->redpart + 3 * x->red_blocks;   // one spare slot
+  k_step_reset<<<1, 1, 0, st>>>(x->status, keep);
   FIRAL_LAUNCHED();
   k_omega<<<(unsigned)cdiv(N, 256), 256, 0, st>>>(w, b, n, N, x->omega);
   FIRAL_LAUNCHED();
-  FIRAL_CHECK(probes_launch(x, seed, t, s, x->V, st));
+  FIRAL_CHECK(probes_launch(x, seed, t, s, x->V, st, x->async ? x->t_dev : nullptr));
   FIRAL_CHECK(precond_launch(x, x->omega, lambda, st));
-  double* keep = x->redpart + 3 * x->red_blocks;   // one spare slot
-  FIRAL_HIP(hipMemsetAsync(keep, 0, sizeof(double), st));
   FIRAL_CHECK(pcg_launch(x, x->omega, lambda, x->Pinv, x->V, x->W1, s, tol, max_iter, flags, 0, st));
   k_relres_merge<<<1, 1, 0, st>>>(x->status, keep);
   FIRAL_LAUNCHED();
@@ -231,6 +234,10 @@ int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, 
   FIRAL_LAUNCHED();
   k_md4<<<nb, 256, 0, st>>>(w, x->ebuf, n, ps, x->status);
   FIRAL_LAUNCHED();
+  if (x->async) {
+    k_advance<<<1, 1, 0, st>>>(x->t_dev);
+    FIRAL_LAUNCHED();
+  }
   return FIRAL_OK;
 }
 
