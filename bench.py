@@ -16,7 +16,9 @@ s = 32) times the sampled objective and its adjoint gradient at a Dirichlet z;
 configuration 4 (n = 1,280,000, d = 384, c = 1000, s = 16) times Relax iterations
 with a fixed number of CG iterations per solve (--fixed-cg).  Both report the
 product's TFLOP/s and the gradient error against the GPU FP64 mode for FP32 and
-bf16x3.  These are measurements of the other workloads, not the bench line.
+bf16x3.  --workload 5 runs the batch workload (64 uneven problems, 30 iterations) as one
+captured graph and one call at a time.  These are measurements of the other workloads, not
+the bench line.
 """
 from __future__ import annotations
 
@@ -53,7 +55,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4])
+    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5])
     ap.add_argument("--fixed-cg", type=int, default=50,
                     help="configuration 4: CG iterations per solve of each timed Relax iteration")
     return ap.parse_args()
@@ -259,6 +261,73 @@ def large_workload(args):
     print(json.dumps(res))
 
 
+def batch_workload(args):
+    """Configuration 5: 64 independent problems (uneven n, d, c) for 30 Relax iterations, as
+    one captured graph replayed 30 times and as the same iterations one call at a time."""
+    import torch
+
+    from paper_2409_07392_amd import RelaxBatch, RelaxContext, default_beta0
+    from synthdata.device import batch_problems_device
+    prec = args.prec if args.prec != "f64" else "f32"
+    log("drawing the 64 problems on the GPU")
+    plist = batch_problems_device(64, device="cuda:0")
+    iters = 30
+    max_iter = 100
+
+    def contexts():
+        out = []
+        for p in plist:
+            ctx = RelaxContext(p.X, p.H, p.n_pool, p.s, prec)
+            w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda:0")
+            out.append((p, ctx, w))
+        return out
+
+    log("batch: tune, warm up, capture")
+    A = contexts()
+    probs = [dict(ctx=ctx, w=w, b=p.b, lam=p.lam, beta0=default_beta0(p.n_pool, p.T),
+                  seed=p.probe_seed, t0=1, s=p.s, tol=p.tol, max_iter=max_iter, project=True)
+             for p, ctx, w in A]
+    t0 = time.perf_counter()
+    batch = RelaxBatch(probs)
+    t_create = time.perf_counter() - t0
+    log("batch: 30 replays")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.run(iters)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    cg = [batch.info(i)["cg_iters"] for i in range(len(A))]
+    log("one call at a time")
+    B = contexts()
+    for (p, ctx, w), (_, ca, _) in zip(B, A):
+        ctx.autotune(p.s)   # the batch's variants (same bucket)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, ctx, w in B:
+        beta0 = default_beta0(p.n_pool, p.T)
+        for t in range(1, iters + 1):
+            ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, max_iter, True)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    maxdiff = max(float((a[2] - b[2]).abs().max()) for a, b in zip(A, B))
+    flops = sum(4.0 * (p.n_pool + p.n_lab) * p.c * p.d * p.s for p in plist)
+    res = {
+        "metric": METRIC,
+        "workload": "configuration 5: 64 problems, n in [5k, 100k], d in {64,128,256}, "
+                    "c in {10,50,100}, s = 16, 30 iterations each",
+        "dtype": prec,
+        "problem_iters_per_s_batched": len(plist) * iters / t_batch,
+        "problem_iters_per_s_one_at_a_time": len(plist) * iters / t_seq,
+        "batched_s": t_batch, "one_at_a_time_s": t_seq, "speedup": t_seq / t_batch,
+        "capture_and_tune_s": t_create,
+        "max_abs_weight_difference_batched_vs_one_at_a_time": maxdiff,
+        "mean_cg_iters_last_iteration": float(sum(a + b for a, b in cg) / (2 * len(cg))),
+        "sum_product_gflop_per_iteration_all_problems": flops / 1e9,
+    }
+    batch.close()
+    print(json.dumps(res))
+
+
 def calibrate_copy(mib):
     """A plain device copy of `mib` MiB (for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
     import torch
@@ -280,6 +349,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Relax path "
               "of this build is single-GPU.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == 5:
+        batch_workload(args)
+        return
     if args.workload != 2:
         large_workload(args)
         return

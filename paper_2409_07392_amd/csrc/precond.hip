@@ -397,7 +397,7 @@ void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits)
   const int64_t nt = (int64_t)tiles->size() / 2;
   const int64_t wgs = nt * cdiv(c, 32 * syrk_cmw(c));
   const int64_t es = prec == FIRAL_F64 ? 8 : 4;
-  const int64_t mem_cap = std::max<int64_t>(1, ((int64_t)2 << 30) / ((int64_t)c * d * d * es));
+  const int64_t mem_cap = std::max<int64_t>(1, ((int64_t)1 << 28) / ((int64_t)c * d * d * es));
   *splits = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, wgs), 64),
                                                         mem_cap));
 }

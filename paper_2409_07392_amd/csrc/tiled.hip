@@ -65,9 +65,10 @@ ColMap make_colmap(int c, int s, int TN) {
   m.TN = TN;
   m.full = c <= TN;
   if (m.full) {
-    m.pp = std::min(TN / c, kMaxPP);
+    // as few tiles as whole probes allow, the probes spread evenly over them
+    m.ntiles = (int)cdiv(s, std::min(TN / c, kMaxPP));
+    m.pp = (int)cdiv(s, m.ntiles);
     m.nw = 1;
-    m.ntiles = (int)cdiv(s, m.pp);
   } else {
     m.pp = 1;
     m.nw = (int)cdiv(c, TN);

@@ -60,11 +60,35 @@ def make_problem_device(cfg: int, device="cuda", dtype=torch.float32, n: int | N
         p["n"] = n
     if n_lab is not None:
         p["n_lab"] = n_lab
+    return draw_device(f"cfg{cfg}", p, 1000 + cfg, 2000 + cfg, device, dtype, chunk)
+
+
+def batch_problems_device(count: int = 64, device="cuda", dtype=torch.float32, seed0: int = 5000,
+                          n_range=(5000, 100000), chunk: int = 131072) -> list:
+    """The batch workload: problem p (seed seed0 + p) has n ~ U{n_range}, d ~ U{64, 128, 256},
+    c ~ U{10, 50, 100}, n_lab = c labeled rows, s = 16, b = c, a mixture of c clusters,
+    whitened, with mean max-probability 0.7; tol 1e-6, 30 iterations."""
+    out = []
+    for q in range(count):
+        g = torch.Generator(device="cpu")
+        g.manual_seed(seed0 + q)
+        n = int(torch.randint(n_range[0], n_range[1] + 1, (1,), generator=g))
+        d = (64, 128, 256)[int(torch.randint(0, 3, (1,), generator=g))]
+        c = (10, 50, 100)[int(torch.randint(0, 3, (1,), generator=g))]
+        p = dict(n=n, n_lab=c, d=d, c=c, s=16, b=float(c), lam=1e-3, tol=1e-6, T=30, K=c,
+                 whiten=True, probs="maxprob")
+        out.append(draw_device(f"batch{q}", p, seed0 + q, seed0 + 1000 + q, device, dtype, chunk))
+    return out
+
+
+def draw_device(name: str, p: dict, seed: int, probe_seed: int, device, dtype,
+                chunk: int = 131072) -> DeviceProblem:
+    """One problem of recipe p (keys n, n_lab, d, c, s, b, lam, tol, T, K, whiten, probs)."""
     d, c = p["d"], p["c"]
     N = p["n"] + p["n_lab"]
     K = min(p["K"], c)
     gen = torch.Generator(device=device)
-    gen.manual_seed(1000 + cfg)
+    gen.manual_seed(seed)
     f32 = dict(device=device, dtype=torch.float32)
     means = torch.randn(K, d, generator=gen, **f32) * 2.0
     lab = torch.randint(0, K, (N,), generator=gen, device=device)
@@ -128,7 +152,7 @@ def make_problem_device(cfg: int, device="cuda", dtype=torch.float32, n: int | N
             H[r0:r0 + chunk] = _softmax_rows(X[r0:r0 + chunk] @ W, 1.0)
     else:
         raise ValueError(p["probs"])
-    return DeviceProblem(name=f"cfg{cfg}", X=X.to(dtype).contiguous(), H=H.to(dtype).contiguous(),
+    return DeviceProblem(name=name, X=X.to(dtype).contiguous(), H=H.to(dtype).contiguous(),
                          n_pool=p["n"], n_lab=p["n_lab"], d=d, c=c, s=p["s"], b=float(p["b"]),
                          lam=float(p["lam"]), tol=float(p["tol"]), T=int(p["T"]),
-                         probe_seed=2000 + cfg)
+                         probe_seed=probe_seed)
