@@ -34,13 +34,13 @@ sys.path.insert(0, ROOT)
 METRIC = "Relax iter time + HVP TFLOP/s, FP32 vs bf16x3 at ≤1e-4 rel grad error"
 # TFLOP/s, MI355X dense MFMA; bf16x3 counts the FP32-equivalent products of three bf16 passes
 PEAK = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0 / 3}
-KERNEL_NAME = {"f32": "k_hvp_fused<7,2> (fused Lemma 1 product, FP32)",
-               "bf16x3": "k_hvp_fused_bf3<7,2> (fused Lemma 1 product, bf16x3)",
+KERNEL_NAME = {"f32": "k_hvp_fused<7,1> (fused Lemma 1 product, FP32)",
+               "bf16x3": "k_hvp_fused_bf3<7,1> (fused Lemma 1 product, bf16x3)",
                "f64": "row-tiled product kernels (FP64), per-chunk span"}
 # HBM bytes per launch of the main kernel from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # each scaled by the copy-kernel calibration factor (profiles/; None until measured for
 # the current kernel)
-TRAFFIC = {"f32": (23.27 + 17.93) * 1e6}   # k_hvp_fused<7,2>: fetched + written bytes per launch
+TRAFFIC = {"f32": (24.01 + 9.69) * 1e6}   # k_hvp_fused<7,1>: fetched + written bytes per launch
 
 
 def parse():

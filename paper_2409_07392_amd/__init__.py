@@ -176,8 +176,9 @@ class RelaxContext:
     def autotune(self, s=None):
         """Time the kernel variants on this problem and keep the faster ones (firal_autotune).
 
-        Returns the choice bits: 1 = row-tiled product, 2 = separate-kernel PCG.  The work
-        blocks and preconditioner of the context are overwritten."""
+        Returns the choice bits: 1 = row-tiled product, 2 = separate-kernel PCG, 4 = fused
+        product with two column blocks per wave.  The work blocks and preconditioner of the
+        context are overwritten."""
         s = self.s_max if s is None else int(s)
         ch = _lib.ctypes.c_int32()
         check(self.lib.firal_autotune(self._ctx, s, _lib.ctypes.byref(ch), _stream()))

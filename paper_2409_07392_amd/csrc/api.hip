@@ -213,19 +213,28 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
 
   const char* unf = getenv("FIRAL_UNFUSED");
   x->force_tiled = x->force_multik = unf && atoi(unf) != 0;
+  // fused tile width in 16-column blocks per wave: 1 (default; the next row chunk is fetched
+  // ahead, measured faster at configuration 2) or 2 (wider tiles, X staged once per chunk)
+  const char* ncb = getenv("FIRAL_FUSED_MAX_NCB");
+  x->fused_max_ncb = ncb && atoi(ncb) == 2 ? 2 : 1;
   // BF16X3 PCG: switch to FP32 products below this relative residual (0 = never).  With the
   // residual kept in the projected space the split products converge like FP32 ones, so
   // the switch is off unless asked for.
   const char* sw = getenv("FIRAL_BF3_SWITCH");
   x->bf3_switch = sw ? atof(sw) : 0.0;
   x->fused_part_elems = 0;
-  for (int s = 1; s <= s_max; ++s) {
-    for (int precise = 0; precise < 2; ++precise) {
-      FusedPlan fp;
-      if (fused_plan(x, s, x->N, &fp, precise != 0))
-        x->fused_part_elems = std::max(x->fused_part_elems, fp.part_elems);
+  const int ncb_set = x->fused_max_ncb;
+  for (int ncb_try = 1; ncb_try <= 2; ++ncb_try) {   // room for either tile width (the tuner)
+    x->fused_max_ncb = ncb_try;
+    for (int s = 1; s <= s_max; ++s) {
+      for (int precise = 0; precise < 2; ++precise) {
+        FusedPlan fp;
+        if (fused_plan(x, s, x->N, &fp, precise != 0))
+          x->fused_part_elems = std::max(x->fused_part_elems, fp.part_elems);
+      }
     }
   }
+  x->fused_max_ncb = ncb_set;
 
   const size_t es = x->esize;
   int rc = FIRAL_OK;

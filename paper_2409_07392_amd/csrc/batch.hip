@@ -34,7 +34,8 @@ namespace {
 typedef std::tuple<int, int, int, int, int> TuneKey;   // prec, d, c, s, log2 N bucket
 
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;   // choice bits: 1 = row-tiled product, 2 = separate-kernel PCG
+std::map<TuneKey, int> g_tune;   // choice bits: 1 = row-tiled product, 2 = separate-kernel
+                                 // PCG, 4 = fused product with two column blocks per wave
 
 TuneKey tune_key(const Ctx* x, int s) {
   const int nb = (int)std::ceil(std::log2((double)std::max<int64_t>(x->N, 1)));
@@ -44,6 +45,7 @@ TuneKey tune_key(const Ctx* x, int s) {
 void apply_choice(Ctx* x, int choice) {
   x->force_tiled = (choice & 1) != 0;
   x->force_multik = (choice & 2) != 0;
+  x->fused_max_ncb = (choice & 4) ? 2 : 1;
 }
 
 // Milliseconds per call of fn (after one untimed call), events on st.
@@ -86,27 +88,33 @@ int autotune(Ctx* x, int s, hipStream_t st, int* choice_out) {
     }
   }
   FIRAL_CHECK(probes_launch(x, 1, 1, s, x->V, st));
-  // product: fused (where its plan fits) against row-tiled
-  double t_prod[2] = {0.0, 0.0};
-  for (int v = 0; v < 2; ++v) {
-    x->force_tiled = v;
+  // product: fused with one or two column blocks per wave (where its plan fits), row-tiled
+  const int prod_bits[3] = {0, 4, 1};
+  double best = 0.0;
+  int prod = 0;
+  for (int v = 0; v < 3; ++v) {
+    apply_choice(x, prod_bits[v]);
+    double t = 0.0;
     FIRAL_CHECK(time_ms([&] { return hvp_launch(x, nullptr, x->N, 1e-3, x->V, x->W1, s,
                                                 skip_none(), st); },
-                        3, st, &t_prod[v]));
+                        3, st, &t));
+    if (v == 0 || t < best) {
+      best = t;
+      prod = prod_bits[v];
+    }
   }
-  const int tiled = t_prod[1] < t_prod[0] ? 1 : 0;
-  x->force_tiled = tiled;
+  apply_choice(x, prod);
   // PCG step: column-local against separate kernels, 4 fixed iterations each
   FIRAL_CHECK(precond_launch(x, nullptr, 1e-3, st));
   double t_cg[2] = {0.0, 0.0};
   for (int v = 0; v < 2; ++v) {
-    x->force_multik = v;
+    apply_choice(x, prod | (v << 1));
     FIRAL_CHECK(time_ms([&] { return pcg_launch(x, nullptr, 1e-3, x->Pinv, x->V, x->W1, s, 0.0,
                                                 4, FIRAL_PCG_PROJECT, 0, st); },
                         2, st, &t_cg[v]));
   }
   const int multik = t_cg[1] < t_cg[0] ? 1 : 0;
-  const int choice = tiled | (multik << 1);
+  const int choice = prod | (multik << 1);
   apply_choice(x, choice);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);

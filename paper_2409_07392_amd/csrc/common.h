@@ -77,6 +77,8 @@ struct Ctx {
   // fused FP32 product: per-row-range partials of the output block
   void* fused_part;
   int64_t fused_part_elems;
+  int fused_max_ncb;    // fused product: column blocks per wave, 2 (wide tiles) or 1 (two
+                        // workgroups' registers per CU, next chunk fetched ahead)
   int force_tiled;      // product: the row-tiled kernels even where the fused plan fits
   int force_multik;     // PCG: separate kernels even where the column-local step fits
                         // (FIRAL_UNFUSED=1 sets both; firal_autotune chooses them)

@@ -25,6 +25,7 @@ namespace {
 constexpr int kNW = 8;        // waves per workgroup
 constexpr int kRC = 32;       // rows per chunk
 constexpr int kThreads = kNW * 64;
+constexpr int kHP = 2;        // h values per thread fetched ahead (all of h when c <= 32)
 
 struct FusedGeom {
   int XS, XT, GT;             // LDS strides (floats) of Xs[r][a], XsT[a][r], GsT[col][r]
@@ -102,21 +103,64 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
 #pragma unroll
     for (int ab = 0; ab < D16; ++ab) acc2[i][ab] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t r0 = rb; r0 < re; r0 += kRC) {
+  // 1. the next chunk's X, h and omega are fetched into registers while the current chunk's
+  //    products run, then staged in LDS (zero padding outside the chunk and beyond d)
+  // with two column blocks per wave the registers are taken by V and the accumulators: the
+  // chunk is then read just before it is staged
+  constexpr bool kAhead = NCB == 1;
+  constexpr int NX = kAhead ? kRC * DP / kThreads : 1;
+  const int nh = (kRC * c + kThreads - 1) / kThreads;   // c <= 256: at most 16
+  float xr[NX], hr[kHP], omr = 0.f;
+  auto fetch_h = [&](int64_t r0) {
     const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
-    // 1. stage X, h, omega (zero padding outside the chunk and beyond d)
-    for (int e = tid; e < kRC * DP; e += kThreads) {
-      const int r = e / DP, a = e - r * DP;
-      const float v = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
-      Xs[r * XS + a] = v;
-      XsT[a * XT + r] = v;
+#pragma unroll
+    for (int q = 0; q < kHP; ++q) {
+      const int e = tid + kThreads * q;
+      if (q < nh) hr[q] = (e < kRC * c && e / c < R) ? H[r0 * c + e] : 0.f;
     }
-    for (int e = tid; e < kRC * c; e += kThreads) {
-      const int r = e / c;
-      Hs[e] = r < R ? H[r0 * c + e] : 0.f;
+    omr = tid < R ? (omega ? (float)omega[r0 + tid] : 1.f) : 0.f;
+  };
+  auto fetch = [&](int64_t r0) {
+    const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int e = tid + kThreads * q, r = e / DP, a = e - r * DP;
+      xr[q] = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
     }
-    if (tid < kRC) Om[tid] = tid < R ? (omega ? (float)omega[r0 + tid] : 1.f) : 0.f;
+    fetch_h(r0);
+  };
+  if (kAhead && rb < re) fetch(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += kRC) {
+    if (kAhead) {
+#pragma unroll
+      for (int q = 0; q < NX; ++q) {
+        const int e = tid + kThreads * q, r = e / DP, a = e - r * DP;
+        Xs[r * XS + a] = xr[q];
+        XsT[a * XT + r] = xr[q];
+      }
+    } else {
+      fetch_h(r0);
+      const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+      for (int e = tid; e < kRC * DP; e += kThreads) {
+        const int r = e / DP, a = e - r * DP;
+        const float v = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
+        Xs[r * XS + a] = v;
+        XsT[a * XT + r] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kHP; ++q) {
+      const int e = tid + kThreads * q;
+      if (q < nh && e < kRC * c) Hs[e] = hr[q];
+    }
+    for (int q = kHP; q < nh; ++q) {   // beyond c = 32 the rest of h is read directly
+      const int e = tid + kThreads * q;
+      const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+      if (e < kRC * c) Hs[e] = e / c < R ? H[r0 * c + e] : 0.f;
+    }
+    if (tid < kRC) Om[tid] = omr;
     __syncthreads();
+    if (kAhead && r0 + kRC < re) fetch(r0 + kRC);
 
     // 2. G = X_chunk V_tile for this wave's column blocks
     f32x4 acc1[NCB][2];
@@ -286,24 +330,71 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused_bf3(
 #pragma unroll
     for (int ab = 0; ab < D16; ++ab) acc2[i][ab] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t r0 = rb; r0 < re; r0 += kRC) {
+  // the next chunk is fetched into registers while the current one's products run
+  // with two column blocks per wave the registers are taken by V and the accumulators: the
+  // chunk is then read just before it is staged
+  constexpr bool kAhead = NCB == 1;
+  constexpr int NX = kAhead ? kRC * DP / kThreads : 1;
+  const int nh = (kRC * c + kThreads - 1) / kThreads;   // c <= 256: at most 16
+  float xr[NX], hr[kHP], omr = 0.f;
+  auto fetch_h = [&](int64_t r0) {
     const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
-    for (int e = tid; e < kRC * DP; e += kThreads) {
-      const int r = e / DP, a = e - r * DP;
-      const float v = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
-      const __bf16 h = (__bf16)v;
-      const __bf16 l = (__bf16)(v - (float)h);
-      Xh[r * XS + a] = h;
-      Xl[r * XS + a] = l;
-      XTh[a * XT + r] = h;
-      XTl[a * XT + r] = l;
+#pragma unroll
+    for (int q = 0; q < kHP; ++q) {
+      const int e = tid + kThreads * q;
+      if (q < nh) hr[q] = (e < kRC * c && e / c < R) ? H[r0 * c + e] : 0.f;
     }
-    for (int e = tid; e < kRC * c; e += kThreads) {
-      const int r = e / c;
-      Hs[e] = r < R ? H[r0 * c + e] : 0.f;
+    omr = tid < R ? (omega ? (float)omega[r0 + tid] : 1.f) : 0.f;
+  };
+  auto fetch = [&](int64_t r0) {
+    const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int e = tid + kThreads * q, r = e / DP, a = e - r * DP;
+      xr[q] = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
     }
-    if (tid < kRC) Om[tid] = tid < R ? (omega ? (float)omega[r0 + tid] : 1.f) : 0.f;
+    fetch_h(r0);
+  };
+  if (kAhead && rb < re) fetch(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += kRC) {
+    if (kAhead) {
+#pragma unroll
+      for (int q = 0; q < NX; ++q) {
+        const int e = tid + kThreads * q, r = e / DP, a = e - r * DP;
+        const __bf16 h = (__bf16)xr[q];
+        const __bf16 l = (__bf16)(xr[q] - (float)h);
+        Xh[r * XS + a] = h;
+        Xl[r * XS + a] = l;
+        XTh[a * XT + r] = h;
+        XTl[a * XT + r] = l;
+      }
+    } else {
+      fetch_h(r0);
+      const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+      for (int e = tid; e < kRC * DP; e += kThreads) {
+        const int r = e / DP, a = e - r * DP;
+        const float v = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
+        const __bf16 h = (__bf16)v;
+        const __bf16 l = (__bf16)(v - (float)h);
+        Xh[r * XS + a] = h;
+        Xl[r * XS + a] = l;
+        XTh[a * XT + r] = h;
+        XTl[a * XT + r] = l;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kHP; ++q) {
+      const int e = tid + kThreads * q;
+      if (q < nh && e < kRC * c) Hs[e] = hr[q];
+    }
+    for (int q = kHP; q < nh; ++q) {   // beyond c = 32 the rest of h is read directly
+      const int e = tid + kThreads * q;
+      const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+      if (e < kRC * c) Hs[e] = e / c < R ? H[r0 * c + e] : 0.f;
+    }
+    if (tid < kRC) Om[tid] = omr;
     __syncthreads();
+    if (kAhead && r0 + kRC < re) fetch(r0 + kRC);
 
     // G = X_chunk V_tile
     f32x4 acc1[NCB][2];
@@ -471,7 +562,7 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p, bool precise)
   const bool bf3 = x->prec == FIRAL_BF16X3 && !precise;
   // above d = 128 the row-tiled kernels are faster (measured at d = 256, c = 100: 2x)
   if (D16 > 8) return false;
-  const int max_ncb = 2;
+  const int max_ncb = x->fused_max_ncb;
   // widest tile of whole probes whose 16-column blocks fit max_ncb per wave
   const int max_cols = max_ncb * kNW * 16;
   int pp = std::min(s, max_cols / c);

@@ -98,12 +98,14 @@ def test_hvp_matches_oracle(prec, shape):
     assert_close(got, orc.hvp(X[:n], H[:n], None, 0.0, B), TOL[prec], f"H_p {prec} {shape}")
 
 
-@pytest.mark.parametrize("unfused", ["0", "1"])
+@pytest.mark.parametrize("unfused", ["0", "1", "ncb1"])
 @pytest.mark.parametrize("shape", [(3001, 7, 100, 10, 20), (1200, 9, 256, 100, 5),
                                    (900, 3, 130, 33, 11), (650, 2, 20, 5, 10)])
 def test_hvp_f32_fused_and_general_paths(shape, unfused, monkeypatch):
-    # FIRAL_UNFUSED=1 forces the three-pass product; both must meet the FP32 bar
-    monkeypatch.setenv("FIRAL_UNFUSED", unfused)
+    # FIRAL_UNFUSED=1 forces the row-tiled product, ncb1 the fused kernel's one-block tiles
+    # (next chunk fetched ahead); all must meet the FP32 bar
+    monkeypatch.setenv("FIRAL_UNFUSED", "1" if unfused == "1" else "0")
+    monkeypatch.setenv("FIRAL_FUSED_MAX_NCB", "1" if unfused == "ncb1" else "2")
     n, nl, d, c, s = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=15)
     ctx, X, H = context(p, "f32", s)
@@ -389,9 +391,11 @@ def test_relax_f32_gradient_error_fixed_iterations():
 BF3_TOL = 1e-4
 
 
+@pytest.mark.parametrize("ncb", ["1", "2"])
 @pytest.mark.parametrize("shape", [(3001, 7, 100, 10, 20), (650, 2, 20, 5, 10), (900, 3, 37, 13, 3),
                                    (300, 0, 1, 2, 1)])
-def test_hvp_bf16x3(shape):
+def test_hvp_bf16x3(shape, ncb, monkeypatch):
+    monkeypatch.setenv("FIRAL_FUSED_MAX_NCB", ncb)
     n, nl, d, c, s = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=17, whiten_x=True, probs="maxprob")
     X = rounded(p.X, "f32")
