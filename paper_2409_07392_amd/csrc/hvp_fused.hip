@@ -49,6 +49,52 @@ inline FusedGeom fused_geom(int D16, int C16, int c) {
 
 typedef float f32x4v __attribute__((ext_vector_type(4)));
 
+// Row step of Lemma 1 for one (row, probe) of the LDS tile: g[k * GT], k < c, holds the
+// probe's c values of G for the row, h the row's probabilities, w its weight:
+// alpha = g . h, then g <- w (g - alpha) h.  Up to 16 classes the row is held in registers
+// (one pass over LDS, when the kernel has the registers: REG); beyond, it is streamed twice.
+template <bool REG>
+__device__ __forceinline__ void gamma_row(float* g, int GT, const float* h, float w, int c) {
+  constexpr int kGR = 16;
+  if (REG && c <= kGR) {
+    float gv[kGR], hv[kGR];
+    float alpha = 0.f;
+#pragma unroll
+    for (int k = 0; k < kGR; ++k) {
+      gv[k] = k < c ? g[k * GT] : 0.f;
+      hv[k] = k < c ? h[k] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < kGR; ++k) alpha += gv[k] * hv[k];
+#pragma unroll
+    for (int k = 0; k < kGR; ++k)
+      if (k < c) g[k * GT] = w * ((gv[k] - alpha) * hv[k]);
+    return;
+  }
+  float alpha = 0.f;
+  for (int k0 = 0; k0 < c; k0 += 4) {
+    float gv[4], hv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
+      hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) alpha += gv[u] * hv[u];
+  }
+  for (int k0 = 0; k0 < c; k0 += 4) {
+    float gv[4], hv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
+      hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (k0 + u < c) g[(k0 + u) * GT] = w * ((gv[u] - alpha) * hv[u]);
+  }
+}
+
 template <int D16, int NCB>
 __global__ __launch_bounds__(kThreads) void k_hvp_fused(
     const float* __restrict__ X, const float* __restrict__ H, const double* __restrict__ omega,
@@ -196,32 +242,8 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
 
     // 3. Gamma apply per (row, probe), rows fastest across threads; loads issued in groups
     for (int e = tid; e < kRC * sp; e += kThreads) {
-      const int r = e % kRC, jj = e / kRC;
-      float* g = GsT + (jj * c) * GT + r;
-      const float* h = Hs + r * c;
-      float alpha = 0.f;
-      for (int k0 = 0; k0 < c; k0 += 4) {
-        float gv[4], hv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
-          hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) alpha += gv[u] * hv[u];
-      }
-      const float w = Om[r];
-      for (int k0 = 0; k0 < c; k0 += 4) {
-        float gv[4], hv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
-          hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k0 + u < c) g[(k0 + u) * GT] = w * ((gv[u] - alpha) * hv[u]);
-      }
+      gamma_row<NCB == 1>(GsT + (e / kRC) * c * GT + e % kRC, GT, Hs + (e % kRC) * c, Om[e % kRC],
+                          c);
     }
     __syncthreads();
 
@@ -429,32 +451,8 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused_bf3(
 
     // Gamma apply (FP32)
     for (int e = tid; e < kRC * sp; e += kThreads) {
-      const int r = e % kRC, jj = e / kRC;
-      float* g = GsT + (jj * c) * GT + r;
-      const float* h = Hs + r * c;
-      float alpha = 0.f;
-      for (int k0 = 0; k0 < c; k0 += 4) {
-        float gv[4], hv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
-          hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) alpha += gv[u] * hv[u];
-      }
-      const float w = Om[r];
-      for (int k0 = 0; k0 < c; k0 += 4) {
-        float gv[4], hv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          gv[u] = k0 + u < c ? g[(k0 + u) * GT] : 0.f;
-          hv[u] = k0 + u < c ? h[k0 + u] : 0.f;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (k0 + u < c) g[(k0 + u) * GT] = w * ((gv[u] - alpha) * hv[u]);
-      }
+      gamma_row<NCB == 1>(GsT + (e / kRC) * c * GT + e % kRC, GT, Hs + (e % kRC) * c, Om[e % kRC],
+                          c);
     }
     __syncthreads();
 
