@@ -18,17 +18,19 @@ namespace firal {
 // omega_i h_ik (1 - h_ik) (classes: the M dimension) and w_i,(a,b) = x_ia x_ib (pairs: the N
 // dimension), k over the rows.  A pair tile is a 16 x BR block of (a, b) in or below the
 // diagonal band; each row stage stages u for the class tile and the tile's 16 + BR x values
-// in LDS, and the MFMA B operand is formed as x_a x_b when it is read.  Four waves in a 2 x 2
-// arrangement, each CMW x PNW blocks of 16 x 16.
+// in LDS, and the MFMA B operand is formed as x_a x_b when it is read.  Four waves in a
+// WC x (4 / WC) arrangement (classes x pairs), each CMW x PNW blocks of 16 x 16: with few
+// classes (c <= 16) all four waves sit along the pairs.
 constexpr int kSyrkTK = 16;
 
-template <typename T, int CMW, int PNW>
+template <typename T, int CMW, int PNW, int WC>
 __global__ __launch_bounds__(256, 2) void k_syrk(const T* __restrict__ X, const T* __restrict__ H,
                                                  const double* __restrict__ omega, int64_t N,
                                                  int d, int c, const int32_t* __restrict__ tiles,
                                                  int ntiles, int nct, int64_t rows_per_split,
                                                  T* __restrict__ part) {
-  constexpr int TC = 32 * CMW, TP = 32 * PNW, BR = TP / 16;
+  constexpr int WP = 4 / WC;
+  constexpr int TC = 16 * CMW * WC, TP = 16 * PNW * WP, BR = TP / 16;
   constexpr int SU = TC + 16;
   constexpr int EU = TC * kSyrkTK / 256;
   __shared__ __align__(16) T Us[2][kSyrkTK][SU];
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const T* __restrict__ X, const 
   const int a0 = 16 * tiles[2 * pt], b0 = BR * tiles[2 * pt + 1];
   const int64_t rb = (int64_t)sp * rows_per_split;
   const int64_t re = rb + rows_per_split < N ? rb + rows_per_split : N;
-  const int wc = (wave >> 1) * 16 * CMW, wp = (wave & 1) * 16 * PNW;
+  const int wc = (wave / WP) * 16 * CMW, wp = (wave % WP) * 16 * PNW;
 
   typedef Mfma16<T> M;
   typename M::acc acc[CMW][PNW];
@@ -338,18 +340,29 @@ static SweepKernel pick_sweep(int d, int* threads) {
 
 __global__ void k_bad_reset(Status* st) { st->bad_block = INT_MAX; }
 
-// Class-tile width by c (narrow tiles for few classes); pair tiles of 128 (FP32) or 64 (FP64).
-template <typename T> constexpr int syrk_pnw() { return sizeof(T) == 4 ? 4 : 2; }
-int syrk_cmw(int c) { return c <= 32 ? 1 : (c <= 64 ? 2 : 4); }
+// Tile shape by c: class blocks per wave (CMW) and waves along the classes (WC); pair tiles
+// of 16 x BR with BR = PNW (4 / WC), PNW = 4 (FP32) or 2 (FP64).
+struct SyrkShape {
+  int cmw, wc, pnw;
+  int tc() const { return 16 * cmw * wc; }
+  int br() const { return pnw * (4 / wc); }
+};
+SyrkShape syrk_shape(int prec, int c) {
+  const int pnw = prec == FIRAL_F64 ? 2 : 4;
+  if (c <= 16) return SyrkShape{1, 1, pnw};
+  if (c <= 32) return SyrkShape{1, 2, pnw};
+  if (c <= 64) return SyrkShape{2, 2, pnw};
+  return SyrkShape{4, 2, pnw};
+}
 
-template <typename T, int CMW>
+template <typename T, int CMW, int WC>
 static void launch_syrk(Ctx* x, const double* omega, int64_t rps, hipStream_t st) {
-  constexpr int PNW = syrk_pnw<T>();
-  const int nct = (int)cdiv(x->c, 32 * CMW);
+  constexpr int PNW = sizeof(T) == 4 ? 4 : 2;
+  const int nct = (int)cdiv(x->c, 16 * CMW * WC);
   const int64_t nwg = (int64_t)nct * x->syrk_ntiles * x->syrk_splits;
-  k_syrk<T, CMW, PNW><<<(unsigned)nwg, 256, 0, st>>>((const T*)x->X, (const T*)x->H, omega, x->N,
-                                                     x->d, x->c, x->syrk_tiles, x->syrk_ntiles,
-                                                     nct, rps, (T*)x->syrk_part);
+  k_syrk<T, CMW, PNW, WC><<<(unsigned)nwg, 256, 0, st>>>(
+      (const T*)x->X, (const T*)x->H, omega, x->N, x->d, x->c, x->syrk_tiles, x->syrk_ntiles, nct,
+      rps, (T*)x->syrk_part);
 }
 
 template <typename T>
@@ -359,11 +372,11 @@ static int precond_t(Ctx* x, const double* omega, double shift, hipStream_t st) 
   const int64_t rps = cdiv(x->N, S);
   k_bad_reset<<<1, 1, 0, st>>>(x->status);
   FIRAL_LAUNCHED();
-  switch (syrk_cmw(c)) {
-    case 1: launch_syrk<T, 1>(x, omega, rps, st); break;
-    case 2: launch_syrk<T, 2>(x, omega, rps, st); break;
-    default: launch_syrk<T, 4>(x, omega, rps, st); break;
-  }
+  const SyrkShape sh = syrk_shape(x->prec, c);
+  if (sh.wc == 1) launch_syrk<T, 1, 1>(x, omega, rps, st);
+  else if (sh.cmw == 1) launch_syrk<T, 1, 2>(x, omega, rps, st);
+  else if (sh.cmw == 2) launch_syrk<T, 2, 2>(x, omega, rps, st);
+  else launch_syrk<T, 4, 2>(x, omega, rps, st);
   FIRAL_LAUNCHED();
   const int64_t n = (int64_t)c * d * d;
   k_syrk_reduce<T><<<(unsigned)cdiv(n, 256), 256, 0, st>>>((const T*)x->syrk_part, S, c, d,
@@ -386,7 +399,8 @@ static int precond_t(Ctx* x, const double* omega, double shift, hipStream_t st) 
 // Pair tiles (a-block of 16, b-block of BR) that meet the lower triangle, and the row-split
 // count, for a context (host side, at creation).
 void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits) {
-  const int BR = 2 * (prec == FIRAL_F64 ? syrk_pnw<double>() : syrk_pnw<float>());
+  const SyrkShape sh = syrk_shape(prec, c);
+  const int BR = sh.br();
   const int nab = (int)cdiv(d, 16), nbb = (int)cdiv(d, BR);
   tiles->clear();
   for (int A = 0; A < nab; ++A)
@@ -395,7 +409,7 @@ void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits)
       tiles->push_back(Bb);
     }
   const int64_t nt = (int64_t)tiles->size() / 2;
-  const int64_t wgs = nt * cdiv(c, 32 * syrk_cmw(c));
+  const int64_t wgs = nt * cdiv(c, sh.tc());
   const int64_t es = prec == FIRAL_F64 ? 8 : 4;
   const int64_t mem_cap = std::max<int64_t>(1, ((int64_t)1 << 28) / ((int64_t)c * d * d * es));
   *splits = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, wgs), 64),
