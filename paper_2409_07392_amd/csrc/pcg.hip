@@ -341,9 +341,9 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_init(const T* __restrict
   double* zp = zs + d * c;       // [kColSplit][c][d]
   const int j = blockIdx.x, n = d * c;
   const int64_t sc = (int64_t)s * c;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int k = e / d, a = e - k * d;
-    rs[e] = (double)B[a * sc + (int64_t)j * c + k];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {   // (a, k), k fastest: coalesced rows
+    const int a = e / c, k = e - a * c;
+    rs[k * d + a] = (double)B[a * sc + (int64_t)j * c + k];
   }
   __syncthreads();
   if (project) {
@@ -358,21 +358,21 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_init(const T* __restrict
   // r = b (projected), rounded to the working type as stored; x = 0
   double bb = 0.0;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int k = e / d, a = e - k * d;
+    const int a = e / c, k = e - a * c;
     const int64_t gi = a * sc + (int64_t)j * c + k;
-    const T rv = (T)rs[e];
+    const T rv = (T)rs[k * d + a];
     r[gi] = rv;
     xv[gi] = T(0);
-    rs[e] = (double)rv;
+    rs[k * d + a] = (double)rv;
     bb += (double)rv * (double)rv;
   }
   bb = block_sum_col(bb, red);
   col_apply(Pinv, rs, zs, zp, d, c, project);
   double rz = 0.0;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int k = e / d, a = e - k * d;
+    const int a = e / c, k = e - a * c;
     const int64_t gi = a * sc + (int64_t)j * c + k;
-    const T zv = (T)zs[e];
+    const T zv = (T)zs[k * d + a];
     p[gi] = zv;
     rz += (double)r[gi] * (double)zv;
   }
@@ -418,9 +418,11 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv,
     if (threadIdx.x == 0) done_next[j] = 1;
     return;
   }
+  // global accesses walk (a, k) with k fastest: the c classes of a probe are contiguous in
+  // the block layout; the LDS vectors keep the vec order k d + a
   double pq = 0.0;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int k = e / d, a = e - k * d;
+    const int a = e / c, k = e - a * c;
     const int64_t gi = a * sc + (int64_t)j * c + k;
     pq += (double)p[gi] * (double)q[gi];
   }
@@ -434,11 +436,11 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv,
   }
   const T at = (T)(rho[j] / pq);
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int k = e / d, a = e - k * d;
+    const int a = e / c, k = e - a * c;
     const int64_t gi = a * sc + (int64_t)j * c + k;
     const T pv = p[gi];
     xv[gi] += at * pv;
-    r0s[e] = (double)(r[gi] - at * q[gi]);
+    r0s[k * d + a] = (double)(r[gi] - at * q[gi]);
   }
   __syncthreads();
   if (project) {
@@ -455,11 +457,12 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv,
   }
   double rr = 0.0;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int k = e / d, a = e - k * d;
-    const T rv = (T)r0s[e];
+    const int a = e / c, k = e - a * c;
+    const int l = k * d + a;
+    const T rv = (T)r0s[l];
     r[a * sc + (int64_t)j * c + k] = rv;
-    rs[e] = (double)rv;
-    r0s[e] = (double)rv;
+    rs[l] = (double)rv;
+    r0s[l] = (double)rv;
     rr += (double)rv * (double)rv;
   }
   rr = block_sum_col(rr, red);
@@ -478,9 +481,9 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv,
   const double beta = rz / (rho[j] != 0.0 ? rho[j] : 1.0);
   const T bt = (T)beta;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int k = e / d, a = e - k * d;
+    const int a = e / c, k = e - a * c;
     const int64_t gi = a * sc + (int64_t)j * c + k;
-    p[gi] = (T)zs[e] + bt * p[gi];
+    p[gi] = (T)zs[k * d + a] + bt * p[gi];
   }
   __syncthreads();
   if (threadIdx.x == 0) rho[j] = rz;
