@@ -1,0 +1,87 @@
+"""Parity at the larger workloads' own sizes, in the launch configuration bench.py --workload
+3 / 4 times (full-size contexts, default row chunks, all probes).
+
+Configuration 3 (n = 200,000 + 100, d = 256, c = 100, s = 32): the whole product against the
+oracle (6.6e11 flops, seconds in NumPy).  Configuration 4 (n = 1,280,000 + 2000, d = 384,
+c = 1000, s = 16): the oracle cannot form the whole product, so the GPU's product over the
+first 40,000 rows (two row chunks) is compared with the oracle on those rows, and at the full
+size the properties every H_i has are checked: class-constant probes are annihilated
+(Gamma_i 1 = 0) and <U, H V> = <H U, V> (each H_i symmetric).  Inputs are drawn on the GPU
+(synthdata.device) and copied to the host for the oracle.
+
+Bars: FP32 1e-5 and bf16x3 1e-4 normwise, as everywhere; the properties at 1e-5 (FP32) and
+1e-4 (bf16x3) of the scale they are measured against.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import relax as orc
+from paper_2409_07392_amd import RelaxContext
+from synthdata.device import make_problem_device
+
+pytestmark = pytest.mark.gpu
+
+BAR = {"f32": 1e-5, "bf16x3": 1e-4}
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    return make_problem_device(3, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    return make_problem_device(4, device="cuda")
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_configuration_3_full_product(cfg3, prec):
+    p = cfg3
+    ctx = RelaxContext(p.X, p.H, p.n_pool, p.s, prec)
+    V = ctx.probes(p.probe_seed, 1, p.s)
+    om = torch.full((p.N,), 1.0, dtype=torch.float64, device="cuda")
+    om[:p.n_pool] = p.b / p.n_pool
+    got = ctx.hvp(V, omega=om, shift=p.lam).cpu().numpy().astype(np.float64)
+    X = p.X.cpu().numpy().astype(np.float64)
+    H = p.H.cpu().numpy().astype(np.float64)
+    ref = orc.hvp(X, H, om.cpu().numpy(), p.lam, V.cpu().numpy().astype(np.float64))
+    e = relerr(got, ref)
+    assert e <= BAR[prec], e
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_configuration_4_rows_and_properties(cfg4, prec):
+    p = cfg4
+    ctx = RelaxContext(p.X, p.H, p.n_pool, p.s, prec)
+    V = ctx.probes(p.probe_seed, 1, p.s)
+    # (1) the first 40,000 rows (beyond one row chunk) against the oracle
+    rows = 40000
+    got = ctx.hvp(V, n_rows=rows).cpu().numpy().astype(np.float64)
+    X = p.X[:rows].cpu().numpy().astype(np.float64)
+    H = p.H[:rows].cpu().numpy().astype(np.float64)
+    ref = orc.hvp(X, H, None, 0.0, V.cpu().numpy().astype(np.float64))
+    e = relerr(got, ref)
+    assert e <= BAR[prec], ("rows", e)
+    # (2) full size: class-constant probes are annihilated, up to the shift
+    g = torch.Generator(device="cuda")
+    g.manual_seed(44)
+    u = torch.randn(p.d, p.s, 1, generator=g, device="cuda")
+    C = u.expand(p.d, p.s, p.c).contiguous()
+    B = torch.randn(p.d, p.s, p.c, generator=g, device="cuda")
+    HB = ctx.hvp(B)
+    HC = ctx.hvp(C)
+    assert float(HC.norm() / HB.norm()) <= BAR[prec], "class-constant probes"
+    # (3) full size: <U, H V> = <H U, V>
+    U = torch.randn(p.d, p.s, p.c, generator=g, device="cuda")
+    HU = ctx.hvp(U)
+    lhs = float((U.double() * HB.double()).sum())
+    rhs = float((HU.double() * B.double()).sum())
+    scale = float(U.double().norm() * HB.double().norm())
+    assert abs(lhs - rhs) <= BAR[prec] * scale, (lhs, rhs, scale)
+    ctx.close()
