@@ -282,19 +282,32 @@ __global__ __launch_bounds__(TT* TT) void k_sweep(double* __restrict__ P, double
         if (i >= j && i < d) A0[(int64_t)i * d + j] = i == j ? sq : prow[i] / sq;
       }
     }
-    double pr[TB], pc[TB];
+    // rank-1 update of every element, then row j, column j and the pivot rewritten (their
+    // owners are known: j = jt + TT vj in both the row and the column decomposition)
+    double pri[TB], pc[TB];
 #pragma unroll
-    for (int u = 0; u < TB; ++u) pr[u] = prow[ty + TT * u];
+    for (int u = 0; u < TB; ++u) pri[u] = prow[ty + TT * u] * ip;
 #pragma unroll
     for (int v = 0; v < TB; ++v) pc[v] = prow[tx + TT * v];
 #pragma unroll
     for (int u = 0; u < TB; ++u)
 #pragma unroll
-      for (int v = 0; v < TB; ++v) {
-        const int i = ty + TT * u, q = tx + TT * v;
-        const double upd = a[u][v] - pr[u] * pc[v] * ip;
-        const double onrow = (i == j) ? pc[v] * ip : pr[u] * ip;
-        a[u][v] = (i == j && q == j) ? -ip : ((i == j || q == j) ? onrow : upd);
+      for (int v = 0; v < TB; ++v) a[u][v] = fma(-pri[u], pc[v], a[u][v]);
+    const int jt = j % TT, vj = j / TT;
+#pragma unroll
+    for (int u = 0; u < TB; ++u)
+      if (u == vj && ty == jt) {
+#pragma unroll
+        for (int v = 0; v < TB; ++v) a[u][v] = pc[v] * ip;       // row j: a_jq / a_jj
+      }
+#pragma unroll
+    for (int v = 0; v < TB; ++v)
+      if (v == vj && tx == jt) {
+#pragma unroll
+        for (int u = 0; u < TB; ++u) a[u][v] = pri[u];           // column j: a_ij / a_jj
+#pragma unroll
+        for (int u = 0; u < TB; ++u)
+          if (u == vj && ty == jt) a[u][v] = -ip;                // pivot
       }
     __syncthreads();
   }
