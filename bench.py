@@ -35,7 +35,7 @@ METRIC = "Relax iter time + HVP TFLOP/s, FP32 vs bf16x3 at ≤1e-4 rel grad erro
 # TFLOP/s, MI355X dense MFMA; bf16x3 counts the FP32-equivalent products of three bf16 passes
 PEAK = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0 / 3}
 KERNEL_NAME = {"f32": "k_hvp_fused<7,1> (fused Lemma 1 product, FP32)",
-               "bf16x3": "k_hvp_fused_bf3<7,1> (fused Lemma 1 product, bf16x3)",
+               "bf16x3": "k_hvp_fused_bf3<7,2> (fused Lemma 1 product, bf16x3)",
                "f64": "row-tiled product kernels (FP64), per-chunk span"}
 # HBM bytes per launch of the main kernel from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # each scaled by the copy-kernel calibration factor (profiles/; None until measured for

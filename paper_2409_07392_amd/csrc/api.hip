@@ -213,10 +213,11 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
 
   const char* unf = getenv("FIRAL_UNFUSED");
   x->force_tiled = x->force_multik = unf && atoi(unf) != 0;
-  // fused tile width in 16-column blocks per wave: 1 (default; the next row chunk is fetched
-  // ahead, measured faster at configuration 2) or 2 (wider tiles, X staged once per chunk)
+  // fused tile width in 16-column blocks per wave: FP32 1 (the next row chunk fetched ahead),
+  // bf16x3 2 (its X planes are read once per chunk instead of once per column tile); the
+  // faster of the two measured at configuration 2 for each
   const char* ncb = getenv("FIRAL_FUSED_MAX_NCB");
-  x->fused_max_ncb = ncb && atoi(ncb) == 2 ? 2 : 1;
+  x->fused_max_ncb = ncb ? (atoi(ncb) == 2 ? 2 : 1) : (prec == FIRAL_BF16X3 ? 2 : 1);
   // BF16X3 PCG: switch to FP32 products below this relative residual (0 = never).  With the
   // residual kept in the projected space the split products converge like FP32 ones, so
   // the switch is off unless asked for.

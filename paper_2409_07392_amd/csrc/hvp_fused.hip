@@ -48,6 +48,17 @@ inline FusedGeom fused_geom(int D16, int C16, int c) {
 }  // namespace
 
 typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// The context's bf16 hi/lo planes of X (row-major) and of X^T (leading dimension ldt), made
+// once at creation in BF16X3 contexts; the FP32 kernel ignores them.
+struct XPlanes {
+  const __bf16* h;
+  const __bf16* l;
+  const __bf16* th;
+  const __bf16* tl;
+  int64_t ldt;
+};
 
 // Row step of Lemma 1 for one (row, probe) of the LDS tile: g[k * GT], k < c, holds the
 // probe's c values of G for the row, h the row's probabilities, w its weight:
@@ -100,7 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
     const float* __restrict__ X, const float* __restrict__ H, const double* __restrict__ omega,
     int64_t n_rows, int d, int c, int SC, const float* __restrict__ B, int probes_per_tile, int s,
     int n_ctiles, int64_t rows_per_split, int n_splits, int XS, int XT, int GT, int CP,
-    float* __restrict__ part, Skip skip) {
+    float* __restrict__ part, XPlanes xp, Skip skip) {
   if (skip_now(skip)) return;
   // XCD-aware placement: workgroups are dealt round-robin to the 8 XCDs, so the
   // logical id packs the column tiles of one row range onto one XCD (shared L2).
@@ -300,7 +311,7 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused_bf3(
     const float* __restrict__ X, const float* __restrict__ H, const double* __restrict__ omega,
     int64_t n_rows, int d, int c, int SC, const float* __restrict__ B, int probes_per_tile, int s,
     int n_ctiles, int64_t rows_per_split, int n_splits, int XS, int XT, int GT, int CP,
-    float* __restrict__ part, Skip skip) {
+    float* __restrict__ part, XPlanes xp, Skip skip) {
   if (skip_now(skip)) return;
   const int nwg = gridDim.x;
   const int lid = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
@@ -356,9 +367,8 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused_bf3(
   // with two column blocks per wave the registers are taken by V and the accumulators: the
   // chunk is then read just before it is staged
   constexpr bool kAhead = NCB == 1;
-  constexpr int NX = kAhead ? kRC * DP / kThreads : 1;
   const int nh = (kRC * c + kThreads - 1) / kThreads;   // c <= 256: at most 16
-  float xr[NX], hr[kHP], omr = 0.f;
+  float hr[kHP], omr = 0.f;
   auto fetch_h = [&](int64_t r0) {
     const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
 #pragma unroll
@@ -368,40 +378,78 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused_bf3(
     }
     omr = tid < R ? (omega ? (float)omega[r0 + tid] : 1.f) : 0.f;
   };
+  // X comes from the context's pre-split planes: row-major in 8-byte groups of 4, transposed
+  // in 16-byte groups of 8 rows (chunks start on multiples of 32 rows, ldt a multiple of 8)
+  constexpr int RG = DP / 4;                                    // 4-element groups per row
+  constexpr int NRM = (2 * kRC * RG + kThreads - 1) / kThreads; // row-major groups, both planes
+  constexpr int NTR = (2 * DP * 4 + kThreads - 1) / kThreads;   // transposed groups, both planes
+  const bool dvec = (d & 3) == 0;
+  bf16x4 prm[NRM];
+  bf16x8 ptr[NTR];
   auto fetch = [&](int64_t r0) {
     const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
 #pragma unroll
-    for (int q = 0; q < NX; ++q) {
-      const int e = tid + kThreads * q, r = e / DP, a = e - r * DP;
-      xr[q] = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
+    for (int q = 0; q < NRM; ++q) {
+      const int e = tid + kThreads * q;
+      bf16x4 v;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = (__bf16)0.0f;
+      if (e < 2 * kRC * RG) {
+        const int plane = e / (kRC * RG), rem = e - plane * (kRC * RG);
+        const int r = rem / RG, a = 4 * (rem - r * RG);
+        const __bf16* src = plane ? xp.l : xp.h;
+        if (r < R && a < d) {
+          const int64_t o = (r0 + r) * d + a;
+          if (dvec) {
+            v = *reinterpret_cast<const bf16x4*>(src + o);
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              if (a + u < d) v[u] = src[o + u];
+          }
+        }
+      }
+      prm[q] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < NTR; ++q) {
+      const int e = tid + kThreads * q;
+      bf16x8 v;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (__bf16)0.0f;
+      if (e < 2 * DP * 4) {
+        const int plane = e / (DP * 4), rem = e - plane * (DP * 4);
+        const int a = rem >> 2, rg = 8 * (rem & 3);
+        if (a < d && rg < R) {
+          v = *reinterpret_cast<const bf16x8*>((plane ? xp.tl : xp.th) + a * xp.ldt + r0 + rg);
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (rg + u >= R) v[u] = (__bf16)0.0f;
+        }
+      }
+      ptr[q] = v;
     }
     fetch_h(r0);
   };
   if (kAhead && rb < re) fetch(rb);
   for (int64_t r0 = rb; r0 < re; r0 += kRC) {
-    if (kAhead) {
+    if (!kAhead) fetch(r0);
 #pragma unroll
-      for (int q = 0; q < NX; ++q) {
-        const int e = tid + kThreads * q, r = e / DP, a = e - r * DP;
-        const __bf16 h = (__bf16)xr[q];
-        const __bf16 l = (__bf16)(xr[q] - (float)h);
-        Xh[r * XS + a] = h;
-        Xl[r * XS + a] = l;
-        XTh[a * XT + r] = h;
-        XTl[a * XT + r] = l;
+    for (int q = 0; q < NRM; ++q) {
+      const int e = tid + kThreads * q;
+      if (e < 2 * kRC * RG) {
+        const int plane = e / (kRC * RG), rem = e - plane * (kRC * RG);
+        const int r = rem / RG, a = 4 * (rem - r * RG);
+        *reinterpret_cast<bf16x4*>((plane ? Xl : Xh) + r * XS + a) = prm[q];
       }
-    } else {
-      fetch_h(r0);
-      const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
-      for (int e = tid; e < kRC * DP; e += kThreads) {
-        const int r = e / DP, a = e - r * DP;
-        const float v = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
-        const __bf16 h = (__bf16)v;
-        const __bf16 l = (__bf16)(v - (float)h);
-        Xh[r * XS + a] = h;
-        Xl[r * XS + a] = l;
-        XTh[a * XT + r] = h;
-        XTl[a * XT + r] = l;
+    }
+#pragma unroll
+    for (int q = 0; q < NTR; ++q) {
+      const int e = tid + kThreads * q;
+      if (e < 2 * DP * 4) {
+        const int plane = e / (DP * 4), rem = e - plane * (DP * 4);
+        const int a = rem >> 2, rg = 8 * (rem & 3);
+        *reinterpret_cast<bf16x8*>((plane ? XTl : XTh) + a * XT + rg) = ptr[q];
       }
     }
 #pragma unroll
@@ -507,7 +555,7 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused_bf3(
 
 typedef void (*FusedKernel)(const float*, const float*, const double*, int64_t, int, int, int,
                             const float*, int, int, int, int64_t, int, int, int, int, int, float*,
-                            Skip);
+                            XPlanes, Skip);
 
 template <int D16>
 static FusedKernel pick_ncb(int ncb) {
@@ -619,7 +667,11 @@ int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_
   k<<<nwg, kThreads, p.lds_bytes, st>>>((const float*)x->X, (const float*)x->H, omega, n_rows,
                                         x->d, x->c, SC, B, p.probes_per_tile, s, p.n_ctiles,
                                         p.rows_per_split, p.n_splits, p.XS, p.XT, p.GT, p.CP,
-                                        part, skip);
+                                        part,
+                                        XPlanes{(const __bf16*)x->Xhi, (const __bf16*)x->Xlo,
+                                                (const __bf16*)x->XThi, (const __bf16*)x->XTlo,
+                                                x->ldt},
+                                        skip);
   FIRAL_LAUNCHED();
   FIRAL_CHECK(prof_mark(x, st, false));
   return reduce_parts_launch<float>(part, (int64_t)x->d * SC, p.n_splits, shift, B, out, skip, st);
