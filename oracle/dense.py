@@ -69,3 +69,64 @@ def hadamard(m: int) -> np.ndarray:
     for _ in range(m):
         Hm = np.block([[Hm, Hm], [Hm, -Hm]])
     return Hm
+
+
+# ---------------------------------------------------------------- Round step
+
+def block_diag_part(S: np.ndarray, d: int, c: int) -> np.ndarray:
+    """S with every off-diagonal d x d block set to zero (the block-diagonal
+    assumption of the new Round step, Section 3.2)."""
+    M = np.zeros_like(S)
+    for k in range(c):
+        sl = slice(k * d, (k + 1) * d)
+        M[sl, sl] = S[sl, sl]
+    return M
+
+
+def round_exact_blockdiag(X, H, n_pool, z, lam, eta, b):
+    """Algorithm 1's Round step on dense dc x dc matrices, every Fisher matrix
+    reduced to its block diagonal: the transform H~ = Sigma^-1/2 H Sigma^-1/2
+    (Section 2.3) formed explicitly, the per-point objective
+    Tr[(A_t + (eta/b) H~_o + eta H~_i)^-1] by a dense inverse, the FTRL action
+    A_1 = sqrt(dc) I and A_{t+1} = V (nu I + Lambda) V^T from the
+    eigendecomposition of eta H~ (nu from Tr(A^-2) = 1, found by Brent's method).
+    A point is selected at most once; ties go to the lowest index.
+
+    Returns (selected rows, [nu_1 .. nu_{b+1}], per-round objective arrays).
+    """
+    from scipy.optimize import brentq
+
+    N, d = X.shape
+    c = H.shape[1]
+    dc = d * c
+    bd = lambda S: block_diag_part(S, d, c)
+    Hi = [bd(fisher(X[i], H[i])) for i in range(N)]
+    Sig = bd(sigma(X, H, n_pool, z, lam))
+    Ho = sum(Hi[n_pool:], np.zeros((dc, dc)))
+    ev, U = np.linalg.eigh(Sig)
+    Smh = (U / np.sqrt(ev)) @ U.T
+    tl = lambda M: Smh @ M @ Smh
+    Ho_t = tl(Ho)
+    Hi_t = [tl(Hi[i]) for i in range(n_pool)]
+    A = np.sqrt(dc) * np.eye(dc)
+    Ht = np.zeros((dc, dc))
+    sel, nus, objs = [], [float(np.sqrt(dc))], []
+    for _ in range(b):
+        r = np.full(n_pool, np.inf)
+        for i in range(n_pool):
+            if i not in sel:
+                r[i] = np.trace(np.linalg.inv(A + (eta / b) * Ho_t + eta * Hi_t[i]))
+        objs.append(r)
+        it = int(np.argmin(r))
+        Ht = Ht + Ho_t / b + Hi_t[it]
+        lam_, V = np.linalg.eigh(eta * Ht)
+        f = lambda nu: float(np.sum((nu + lam_) ** -2.0)) - 1.0
+        lo = 1.0 - lam_.min()
+        hi = np.sqrt(dc) - lam_.min()
+        nu = lo if f(lo) == 0.0 else (hi if f(hi) == 0.0 else
+                                      brentq(f, lo, hi, xtol=1e-15, rtol=4 * np.finfo(float).eps,
+                                             maxiter=500))
+        A = (V * (nu + lam_)) @ V.T
+        sel.append(it)
+        nus.append(float(nu))
+    return np.array(sel, dtype=np.int64), np.array(nus), objs
