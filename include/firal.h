@@ -1,12 +1,13 @@
 /*
- * firal.h -- C ABI of the MI355X (gfx950) Relax step of Approx-FIRAL
+ * firal.h -- C ABI of the MI355X (gfx950) Relax and Round steps of Approx-FIRAL
  * (Chen, Wen & Biros, "A Scalable Algorithm for Active Learning", SC24).
  *
  * The library computes, on one GPU, every step of the fast Relax solve
  * (Algorithm 2): Rademacher probes, the block-diagonal preconditioner of
  * Definition 1 / eq. 12, block-Jacobi preconditioned CG with the matrix-free
  * Hessian product of Lemma 1, the Hutchinson gradient of eq. 11 and the
- * entropic mirror-descent update.
+ * entropic mirror-descent update; and the diagonal Round step (Algorithm 3)
+ * that selects the b points from the relaxed weights.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -213,6 +214,47 @@ int firal_batch_info(firal_batch batch, int32_t i, firal_info* info, void* strea
 int firal_batch_next_t(firal_batch batch, int32_t i, int32_t* t);
 /* Release the graph, streams and events (the contexts stay with the caller).  NULL is a no-op. */
 int firal_batch_destroy(firal_batch batch);
+
+/* Diagonal Round step of Approx-FIRAL (Algorithm 3).  Every Fisher matrix keeps only its c
+ * diagonal d x d blocks (Section 3.2), so all state is c blocks of d x d.  Round t selects the
+ * unselected pool row i maximising the per-point objective of the Section 3.2 proposition,
+ *   sum_k g_ik x_i^T (B_t)_k^-1 (Sigma_o)_k (B_t)_k^-1 x_i / (1 + eta g_ik x_i^T (B_t)_k^-1 x_i),
+ * g_ik = h_ik (1 - h_ik) (ties: lowest row index; a row is selected at most once), then
+ *   (H)_k += (H_o)_k / b + g_ik x_i x_i^T,
+ *   nu_{t+1}: sum_kj (nu + eta lambda_kj)^-2 = 1 over the eigenvalues lambda_kj of
+ *             (Sigma_o)_k^-1/2 (H)_k (Sigma_o)_k^-1/2,
+ *   B_{t+1} = nu_{t+1} Sigma_o + eta H + (eta / b) H_o,   B_1 = sqrt(dc) Sigma_o + (eta / b) H_o.
+ * (Sigma_o)_k = lambda I + (H_o)_k + sum_i z_i g_ik x_i x_i^T over the pool rows (the blocks of
+ * Sigma_z at the relaxed weights z); (H_o)_k = sum over the labeled rows of g_ik x_i x_i^T.  The
+ * objective's numerator holds Sigma_o itself, as the proposition's proof derives it (the stated
+ * objective prints its inverse).  All arithmetic is FP64 (FP32 X and H are read exactly).
+ * Requires d <= 512.  The state borrows the context (X and H): destroy it first. */
+typedef struct firal_round_s* firal_round;
+
+/* Set up rounds of one Round solve on ctx's rows: z (device FP64 [n_pool]) the relaxed
+ * weights (read during the call only), lambda >= 0 the regulariser of Sigma_o, eta > 0 the
+ * learning rate, b in [1, n_pool] the number of rounds (points to select).  Forms Sigma_o's
+ * blocks and Cholesky factors, H_o's blocks and round 1's B^-1.  Synchronous.
+ * Errors: EINVAL, ENOTSPD (a Sigma_o block is not positive definite), EHIP, ENOMEM. */
+int firal_round_create(firal_round* out, firal_ctx ctx, const double* z, double lambda,
+                       double eta, int32_t b, void* stream);
+/* Enqueue the next `rounds` rounds (asynchronous; nothing is read back, so the calls may be
+ * captured).  EINVAL if fewer than `rounds` of the b rounds are left. */
+int firal_round_step(firal_round round, int32_t rounds, void* stream);
+/* The per-point objective of every pool row at the current round (device FP64 [n_pool];
+ * selected rows get -inf).  Asynchronous; changes no state. */
+int firal_round_scores(firal_round round, double* scores, void* stream);
+/* Synchronise and copy to host buffers (each may be NULL): the t rounds done so far,
+ * selected[0..t) (row indices into the pool), nu[0..t] (nu_1 .. nu_{t+1}), score_max[0..t)
+ * (the winning objective of each round).  EINVAL if a round found no unselected row with a
+ * finite objective. */
+int firal_round_result(firal_round round, int64_t* selected, double* nu, double* score_max,
+                       int32_t* t, void* stream);
+/* min over k of the smallest eigenvalue of (H)_k after the rounds done so far (host *out):
+ * the quantity the eta choice of the experiments section maximises.  Synchronous. */
+int firal_round_criterion(firal_round round, double* out, void* stream);
+/* Release the state (NULL is a no-op). */
+int firal_round_destroy(firal_round round);
 
 /* Static description of a return code. */
 const char* firal_strerror(int code);

@@ -1,4 +1,4 @@
-"""MI355X (gfx950) Relax step of Approx-FIRAL (Chen, Wen & Biros, SC24).
+"""MI355X (gfx950) Relax and Round steps of Approx-FIRAL (Chen, Wen & Biros, SC24).
 
 Every step of the path runs in the hand-written HIP kernels of libfiral.so
 (see include/firal.h); this module only marshals arguments: torch tensors
@@ -15,8 +15,8 @@ from . import _lib
 from ._lib import (BF16X3, F32, F64, PCG_PROJECT, FiralError, Info, WARN_NOT_CONVERGED, check,
                    load)
 
-__all__ = ["RelaxContext", "RelaxBatch", "RelaxObjective", "FiralError", "default_beta0", "F64",
-           "F32", "BF16X3", "load"]
+__all__ = ["RelaxContext", "RelaxBatch", "RelaxObjective", "RoundSolver", "round_eta_sweep",
+           "FiralError", "default_beta0", "F64", "F32", "BF16X3", "load"]
 
 _DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32}
 
@@ -261,6 +261,84 @@ class RelaxBatch:
             self.close()
         except Exception:
             pass
+
+
+class RoundSolver:
+    """Diagonal Round step (Algorithm 3) on a RelaxContext's rows.
+
+    z: CUDA float64 relaxed weights of the pool rows (read at construction); lam: regulariser of
+    Sigma_o's blocks; eta: learning rate; b: rounds (points to select).  Everything runs in
+    FP64 on the device; step() only enqueues.  Keep the context alive while the solver lives.
+    """
+
+    def __init__(self, ctx: RelaxContext, z: torch.Tensor, lam: float, eta: float, b: int):
+        self.lib = load()
+        self.ctx = ctx
+        self.b = int(b)
+        z = RelaxContext._f64(z, ctx.n_pool)
+        self._r = _lib.ctypes.c_void_p()
+        check(self.lib.firal_round_create(_lib.ctypes.byref(self._r), ctx._ctx, _ptr(z),
+                                          float(lam), float(eta), self.b, _stream()))
+
+    def step(self, rounds: int = 1):
+        check(self.lib.firal_round_step(self._r, int(rounds), _stream()))
+
+    def run(self):
+        """All remaining rounds; returns the selected pool rows (int64 numpy array)."""
+        t = self.result()["t"]
+        self.step(self.b - t)
+        return self.result()["selected"]
+
+    def scores(self, out=None):
+        """The per-point objective of every pool row at the current round (-inf if selected)."""
+        if out is None:
+            out = torch.empty(self.ctx.n_pool, dtype=torch.float64, device=self.ctx.X.device)
+        out = RelaxContext._f64(out, self.ctx.n_pool)
+        check(self.lib.firal_round_scores(self._r, _ptr(out), _stream()))
+        return out
+
+    def result(self):
+        import numpy as np
+        sel = np.zeros(self.b, dtype=np.int64)
+        nu = np.zeros(self.b + 1, dtype=np.float64)
+        smax = np.zeros(self.b, dtype=np.float64)
+        t = _lib.ctypes.c_int32()
+        check(self.lib.firal_round_result(
+            self._r, sel.ctypes.data_as(_lib.ctypes.c_void_p),
+            nu.ctypes.data_as(_lib.ctypes.c_void_p), smax.ctypes.data_as(_lib.ctypes.c_void_p),
+            _lib.ctypes.byref(t), _stream()))
+        n = t.value
+        return dict(t=n, selected=sel[:n], nu=nu[:n + 1], score_max=smax[:n])
+
+    def criterion(self) -> float:
+        """min_k lambda_min((H)_k) after the rounds done so far."""
+        out = _lib.ctypes.c_double()
+        check(self.lib.firal_round_criterion(self._r, _lib.ctypes.byref(out), _stream()))
+        return out.value
+
+    def close(self):
+        if getattr(self, "_r", None) is not None and self._r.value:
+            self.lib.firal_round_destroy(self._r)
+            self._r = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def round_eta_sweep(ctx: RelaxContext, z: torch.Tensor, lam: float, etas, b: int) -> dict:
+    """The eta choice of the experiments section: run the Round step for every eta and keep
+    the one whose selection maximises min_k lambda_min((H)_k)."""
+    crit, sels = [], []
+    for eta in etas:
+        rs = RoundSolver(ctx, z, lam, eta, b)
+        sels.append(rs.run())
+        crit.append(rs.criterion())
+        rs.close()
+    best = max(range(len(crit)), key=lambda i: (crit[i], -i))
+    return dict(etas=list(etas), criterion=crit, best=etas[best], selected=sels[best])
 
 
 class RelaxObjective(torch.autograd.Function):

@@ -19,7 +19,9 @@ EXPORTS = ("firal_create", "firal_destroy", "firal_hvp", "firal_build_precond",
            "firal_pcg_solve", "firal_grad_z", "firal_probes", "firal_relax_step",
            "firal_sampled_objective", "firal_profile_begin", "firal_profile_end",
            "firal_autotune", "firal_batch_create", "firal_batch_run", "firal_batch_info",
-           "firal_batch_next_t", "firal_batch_destroy", "firal_strerror", "firal_last_error")
+           "firal_batch_next_t", "firal_batch_destroy", "firal_round_create", "firal_round_step",
+           "firal_round_scores", "firal_round_result", "firal_round_criterion",
+           "firal_round_destroy", "firal_strerror", "firal_last_error")
 
 
 class Info(ctypes.Structure):
@@ -82,6 +84,12 @@ def load() -> ctypes.CDLL:
         "firal_batch_info": [vp, i32, pinfo, vp],
         "firal_batch_next_t": [vp, i32, ctypes.POINTER(i32)],
         "firal_batch_destroy": [vp],
+        "firal_round_create": [ctypes.POINTER(vp), vp, vp, dbl, dbl, i32, vp],
+        "firal_round_step": [vp, i32, vp],
+        "firal_round_scores": [vp, vp, vp],
+        "firal_round_result": [vp, vp, vp, vp, ctypes.POINTER(i32), vp],
+        "firal_round_criterion": [vp, ctypes.POINTER(dbl), vp],
+        "firal_round_destroy": [vp],
         "firal_profile_begin": [vp],
         "firal_profile_end": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         "firal_strerror": [ctypes.c_int],

@@ -274,6 +274,15 @@ int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const 
                void* out, int s, Skip skip, hipStream_t st, bool precise = false);
 int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st);
 void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits);
+// FP64 weighted Gram blocks sum_r omega_r h_rk (1 - h_rk) x_r x_r^T + shift I over rows [0, N)
+// of X and H (storage FP32 unless prec is FIRAL_F64; omega null: weight 1) into out
+// (c x d x d); tiles/S from syrk_plan(FIRAL_F64, ...), part holds S x c x d x d doubles.
+int gram64_launch(int prec, const void* X, const void* H, const double* omega, int64_t N, int d,
+                  int c, const int32_t* tiles, int ntiles, int S, double shift, double* part,
+                  double* out, hipStream_t st);
+// In-place Cholesky of c SPD blocks (lower factor, upper zeroed); for d <= 256 the blocks'
+// inverses go to Pinv.  *bad (preset to INT32_MAX) receives the smallest failing block.
+int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, hipStream_t st);
 int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,
                void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
                hipStream_t st);

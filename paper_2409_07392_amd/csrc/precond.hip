@@ -23,8 +23,9 @@ namespace firal {
 // classes (c <= 16) all four waves sit along the pairs.
 constexpr int kSyrkTK = 16;
 
-template <typename T, int CMW, int PNW, int WC>
-__global__ __launch_bounds__(256, 2) void k_syrk(const T* __restrict__ X, const T* __restrict__ H,
+// L is the storage type of X and H (FP32 rows feed the FP64 Gram of the Round step).
+template <typename T, typename L, int CMW, int PNW, int WC>
+__global__ __launch_bounds__(256, 2) void k_syrk(const L* __restrict__ X, const L* __restrict__ H,
                                                  const double* __restrict__ omega, int64_t N,
                                                  int d, int c, const int32_t* __restrict__ tiles,
                                                  int ntiles, int nct, int64_t rows_per_split,
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const T* __restrict__ X, const 
       const int64_t r = r0 + uk + KU * i;
       T u = T(0);
       if (r < re && uvalid) {
-        const T h = H[r * c + c0 + ucls];
+        const T h = (T)H[r * c + c0 + ucls];
         const T w = omega ? (T)omega[r] : T(1);
         u = w * h * (T(1) - h);
       }
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const T* __restrict__ X, const 
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
       const int64_t r = r0 + xk[i];
-      rx[i] = (r < re && xvalid[i]) ? X[r * d + xj[i]] : T(0);
+      rx[i] = (r < re && xvalid[i]) ? (T)X[r * d + xj[i]] : T(0);
     }
   };
   auto store = [&](int buf) {
@@ -373,7 +374,7 @@ static void launch_syrk(Ctx* x, const double* omega, int64_t rps, hipStream_t st
   constexpr int PNW = sizeof(T) == 4 ? 4 : 2;
   const int nct = (int)cdiv(x->c, 16 * CMW * WC);
   const int64_t nwg = (int64_t)nct * x->syrk_ntiles * x->syrk_splits;
-  k_syrk<T, CMW, PNW, WC><<<(unsigned)nwg, 256, 0, st>>>(
+  k_syrk<T, T, CMW, PNW, WC><<<(unsigned)nwg, 256, 0, st>>>(
       (const T*)x->X, (const T*)x->H, omega, x->N, x->d, x->c, x->syrk_tiles, x->syrk_ntiles, nct,
       rps, (T*)x->syrk_part);
 }
@@ -427,6 +428,56 @@ void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits)
   const int64_t mem_cap = std::max<int64_t>(1, ((int64_t)1 << 28) / ((int64_t)c * d * d * es));
   *splits = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, wgs), 64),
                                                         mem_cap));
+}
+
+int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, hipStream_t st) {
+  int threads = 0;
+  SweepKernel sw = pick_sweep(d, &threads);
+  if (sw) {
+    sw<<<c, threads, 0, st>>>(P, Pinv, d, bad);
+    FIRAL_LAUNCHED();
+  } else {
+    k_chol<<<c, 256, 0, st>>>(P, d, bad);
+    FIRAL_LAUNCHED();
+  }
+  return FIRAL_OK;
+}
+
+template <typename L, int CMW, int WC>
+static void launch_gram64(const L* X, const L* H, const double* omega, int64_t N, int d, int c,
+                          const int32_t* tiles, int ntiles, int S, double* part,
+                          hipStream_t st) {
+  const int nct = (int)cdiv(c, 16 * CMW * WC);
+  const int64_t nwg = (int64_t)nct * ntiles * S;
+  k_syrk<double, L, CMW, 2, WC><<<(unsigned)nwg, 256, 0, st>>>(X, H, omega, N, d, c, tiles, ntiles,
+                                                               nct, cdiv(std::max<int64_t>(N, 1), S),
+                                                               part);
+}
+
+template <typename L>
+static int gram64_t(const L* X, const L* H, const double* omega, int64_t N, int d, int c,
+                    const int32_t* tiles, int ntiles, int S, double shift, double* part,
+                    double* out, hipStream_t st) {
+  const SyrkShape sh = syrk_shape(FIRAL_F64, c);
+  if (sh.wc == 1) launch_gram64<L, 1, 1>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);
+  else if (sh.cmw == 1) launch_gram64<L, 1, 2>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);
+  else if (sh.cmw == 2) launch_gram64<L, 2, 2>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);
+  else launch_gram64<L, 4, 2>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);
+  FIRAL_LAUNCHED();
+  const int64_t n = (int64_t)c * d * d;
+  k_syrk_reduce<double><<<(unsigned)cdiv(n, 256), 256, 0, st>>>(part, S, c, d, shift, out);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
+int gram64_launch(int prec, const void* X, const void* H, const double* omega, int64_t N, int d,
+                  int c, const int32_t* tiles, int ntiles, int S, double shift, double* part,
+                  double* out, hipStream_t st) {
+  if (prec == FIRAL_F64)
+    return gram64_t<double>((const double*)X, (const double*)H, omega, N, d, c, tiles, ntiles, S,
+                            shift, part, out, st);
+  return gram64_t<float>((const float*)X, (const float*)H, omega, N, d, c, tiles, ntiles, S,
+                         shift, part, out, st);
 }
 
 int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st) {
