@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5])
+    ap.add_argument("--no-round", action="store_true", help="skip the Round-step leg")
+    ap.add_argument("--eta", type=float, default=None,
+                    help="Round-step learning rate (default 8 sqrt(dc), the theorem's value at "
+                         "epsilon = 1)")
     ap.add_argument("--fixed-cg", type=int, default=50,
                     help="configuration 4: CG iterations per solve of each timed Relax iteration")
     return ap.parse_args()
@@ -127,7 +131,7 @@ def run_leg(p, prec, steps, warmup, project, hvp_reps):
     t_kern = k_ms / 1e3 / max(k_n, 1)
     flops = 4.0 * p.N * p.c * p.d * p.s
     ctx.close()
-    return dict(elapsed=elapsed, ms=1e3 * elapsed / steps, value=steps / elapsed,
+    return dict(w=w, elapsed=elapsed, ms=1e3 * elapsed / steps, value=steps / elapsed,
                 cg=float(np.mean([i["cg_iters"][0] + i["cg_iters"][1] for i in infos])),
                 t_hvp=t_hvp, hvp_tflops=flops / t_hvp / 1e12, t_kern=t_kern,
                 kern_tflops=flops / t_kern / 1e12, f_hat_last=infos[-1]["f_hat"])
@@ -156,6 +160,63 @@ def grad_errors(p, project, n_cg=15):
         ctx.close()
     ref = np.linalg.norm(g["f64"])
     return {k: float(np.linalg.norm(g[k] - g["f64"]) / ref) for k in ("f32", "bf16x3")}
+
+
+def round_leg(p, w, eta, cpu_rounds=2):
+    """The Round step (Algorithm 3) at the same workload: all b rounds from z = b w (the
+    Relax leg's final weights), FP64 on the device.  Reports ms per selected point, the scoring
+    kernel's time and FP64 MFMA rate, and the FP64 oracle's time per round on the host."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, RoundSolver
+    dev = torch.device("cuda:0")
+    X = torch.as_tensor(p.X, dtype=torch.float32, device=dev).contiguous()
+    H = torch.as_tensor(p.H, dtype=torch.float32, device=dev).contiguous()
+    ctx = RelaxContext(X, H, p.n_pool, 1, "f32")
+    z = (p.b * w).contiguous()
+    b = int(p.b)
+    warm = RoundSolver(ctx, z, p.lam, eta, b)
+    warm.step(2)
+    warm.result()
+    warm.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = RoundSolver(ctx, z, p.lam, eta, b)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    ctx.profile_begin()
+    t0 = time.perf_counter()
+    rs.step(b)
+    res = rs.result()
+    elapsed = time.perf_counter() - t0
+    k_ms, k_n = ctx.profile_end()
+    ldw = -(-p.d // 16) * 16
+    flops = 2.0 * p.n_pool * p.c * p.d * p.d     # y = W_k^T x for every pool row and class
+    t_kern = k_ms / 1e3 / max(k_n, 1)
+    rs.close()
+    ctx.close()
+    # the oracle on the host: the first rounds of the same solve
+    from oracle import round as orr
+    Xo = X.cpu().numpy().astype(np.float64)
+    Ho = H.cpu().numpy().astype(np.float64)
+    zo = z.cpu().numpy()
+    tc = time.perf_counter()
+    st = orr.DiagonalRound(Xo, Ho, p.n_pool, zo, p.lam, eta, b)
+    for _ in range(cpu_rounds):
+        st.step()
+    t_cpu = (time.perf_counter() - tc) / cpu_rounds
+    same = [int(i) for i in st.selected] == [int(i) for i in res["selected"][:cpu_rounds]]
+    return {"rounds": res["t"], "eta": eta, "ms_per_point": 1e3 * elapsed / b,
+            "points_per_s": b / elapsed, "setup_ms": 1e3 * t_setup,
+            "first_selected": [int(i) for i in res["selected"][:8]],
+            "roofline": {"bound": "mfma", "kernel": "k_round_score<float> (eq.-13 scores, FP64 MFMA)",
+                         "achieved": flops / t_kern / 1e12, "peak": PEAK["f64"],
+                         "unit": "TFLOP/s", "frac": flops / t_kern / 1e12 / PEAK["f64"],
+                         "kernel_us": t_kern * 1e6, "traffic": None,
+                         "padded_columns": ldw},
+            "cpu_oracle": {"s_per_round": t_cpu, "rounds_timed": cpu_rounds,
+                           "same_first_selections": same}}
 
 
 def log(msg):
@@ -359,12 +420,15 @@ def main():
     from paper_2409_07392_amd import default_beta0
 
     p = make_problem(2)
+    if args.eta is None:
+        args.eta = 8.0 * (p.d * p.c) ** 0.5
     project = not args.literal
     main_leg = run_leg(p, args.prec, args.steps, args.warmup, project, args.hvp_reps)
     legs = {args.prec: main_leg}
     if args.prec != "bf16x3" and not args.no_bf16x3:
         legs["bf16x3"] = run_leg(p, "bf16x3", args.steps, args.warmup, project, args.hvp_reps)
     errs = grad_errors(p, project)
+    rnd = None if args.no_round else round_leg(p, main_leg["w"], args.eta)
     peak = PEAK[args.prec]
     res = {
         "metric": METRIC,
@@ -394,6 +458,8 @@ def main():
                      "kernel_us": main_leg["t_kern"] * 1e6,
                      "traffic": TRAFFIC.get(args.prec)},
     }
+    if rnd is not None:
+        res["round_step"] = rnd
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(p, default_beta0(p.n_pool, p.T), project)
     print(json.dumps(res))

@@ -228,7 +228,7 @@ int firal_batch_destroy(firal_batch batch);
  * Sigma_z at the relaxed weights z); (H_o)_k = sum over the labeled rows of g_ik x_i x_i^T.  The
  * objective's numerator holds Sigma_o itself, as the proposition's proof derives it (the stated
  * objective prints its inverse).  All arithmetic is FP64 (FP32 X and H are read exactly).
- * Requires d <= 512.  The state borrows the context (X and H): destroy it first. */
+ * Requires d <= 512 and c <= 30000.  The state borrows the context (X and H): destroy it first. */
 typedef struct firal_round_s* firal_round;
 
 /* Set up rounds of one Round solve on ctx's rows: z (device FP64 [n_pool]) the relaxed

@@ -87,6 +87,7 @@ struct BGemm {
   int64_t sC;
   int64_t ci, cj;
   int M, N, K;
+  int amod, bmod;   // batch k reads A block k % amod and B block k % bmod
 };
 
 __global__ __launch_bounds__(256) void k_bgemm(BGemm g) {
@@ -95,8 +96,8 @@ __global__ __launch_bounds__(256) void k_bgemm(BGemm g) {
   const int ti = blockIdx.x / tiles_n, tj = blockIdx.x % tiles_n;
   const int64_t k = blockIdx.y;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const double* A = g.A + k * g.sA;
-  const double* B = g.B + k * g.sB;
+  const double* A = g.A + (k % g.amod) * g.sA;
+  const double* B = g.B + (k % g.bmod) * g.sB;
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int p0 = 0; p0 < g.K; p0 += 32) {
     for (int e = threadIdx.x; e < 1024; e += 256) {
@@ -154,23 +155,28 @@ __global__ void k_pad_comb(const double* __restrict__ A, double sa, const double
 // sym.schur2: tau = (a_qq - a_pp) / 2 a_pq, t = sign(tau) / (|tau| + sqrt(1 + tau^2))), then
 // applies J^T A J block by block: each 2 x 2 block of rows of pair P and columns of pair R is
 // computed once and written together with its transpose, so A stays exactly symmetric.
-// Sweeps stop once ||offdiag(A)||_F <= tol ||diag(A)||_2 (checked before each sweep) or after
-// max_sweeps.  Blocks [0, n_vals) return eigenvalues only; later blocks also accumulate
+// Off-diagonal entries at or below 2.3e-16 ||A||_F (FP64 unit roundoff of the block's norm,
+// evaluated at the start of each sweep) are zeroed without a rotation.  Sweeps
+// stop once ||offdiag(A)||_F <= tol ||diag(A)||_2 (checked before each sweep), after a sweep
+// without rotations, or after max_sweeps.  Blocks [0, n_vals) return eigenvalues only; later blocks also accumulate
 // V <- V J (V starts at I; its columns are the eigenvectors).  SMEM: A (and V) are held in
 // LDS for the whole solve.
-template <bool SMEM>
-__global__ __launch_bounds__(256) void k_jacobi(double* __restrict__ A_all,
-                                                double* __restrict__ V_all,
-                                                double* __restrict__ lam_all, int m, int d,
-                                                int n_vals, int max_sweeps, double tol) {
+template <bool SMEM, int NT>
+__global__ __launch_bounds__(NT) void k_jacobi(double* __restrict__ A_all,
+                                               double* __restrict__ V_all,
+                                               double* __restrict__ lam_all, int m, int d,
+                                               int n_vals, int v_given, int max_sweeps,
+                                               double tol) {
   constexpr int kHalf = SMEM ? 64 : kMaxD / 2;
   extern __shared__ double dyn[];
   __shared__ double cs[kHalf], sn[kHalf], tn[kHalf];
-  __shared__ int pp[kHalf], qq[kHalf];
+  __shared__ int pp[kHalf], qq[kHalf], act[kHalf];
   __shared__ double stat[2];
+  __shared__ int any_rot;
+  int prev_rot = 1;
   const int blk = blockIdx.x, tid = threadIdx.x;
   const bool vecs = blk >= n_vals;
-  const int64_t mm = (int64_t)m * m;
+  const int mm = m * m;
   double* Ag = A_all + (int64_t)blk * mm;
   double* Vg = vecs ? V_all + (int64_t)(blk - n_vals) * mm : nullptr;
   double* A = Ag;
@@ -178,39 +184,60 @@ __global__ __launch_bounds__(256) void k_jacobi(double* __restrict__ A_all,
   if (SMEM) {
     A = dyn;
     V = vecs ? dyn + mm : nullptr;
-    for (int64_t e = tid; e < mm; e += blockDim.x) A[e] = Ag[e];
+    for (int e = tid; e < mm; e += NT) A[e] = Ag[e];
   }
-  if (vecs)
-    for (int64_t e = tid; e < mm; e += blockDim.x) V[e] = (e / m == e % m) ? 1.0 : 0.0;
+  if (vecs) {
+    if (v_given) {
+      if (SMEM)
+        for (int e = tid; e < mm; e += NT) V[e] = Vg[e];
+    } else {
+      for (int e = tid; e < mm; e += NT) V[e] = (e / m == e % m) ? 1.0 : 0.0;
+    }
+  }
   __syncthreads();
   const int nb = m / 2, M = m - 1, half = nb / 2;
-  const int ntask = nb * (half + 1);
+  // thread -> (pair myP, lane myq of stride nth): it updates the 2 x 2 blocks (myP, myP + dl)
+  // for dl = myq, myq + nth, ... <= half, and rows myq, myq + nth, ... of V's two columns of
+  // pair myP, loading the pair's rotation once
+  const int nth = NT / nb;
+  const int myP = tid % nb, myq = tid / nb;
+  const bool worker = myq < nth;
+  const int wave = tid >> 6, lane = tid & 63;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, dg = 0.0;
-    for (int64_t e = tid; e < mm; e += blockDim.x) {
-      const double v = A[e];
-      if (e / m == e % m) dg += v * v;
-      else off += v * v;
-    }
-    off = block_sum<256>(off);
-    dg = block_sum<256>(dg);
+    for (int i = wave; i < m; i += NT / 64)
+      for (int j = lane; j < m; j += 64) {
+        const double v = A[i * m + j];
+        if (i == j) dg += v * v;
+        else off += v * v;
+      }
+    off = block_sum<NT>(off);
+    dg = block_sum<NT>(dg);
     if (tid == 0) {
       stat[0] = off;
       stat[1] = dg;
+      any_rot = 0;
     }
     __syncthreads();
-    const bool conv = stat[0] <= tol * tol * stat[1];
+    const bool conv = stat[0] <= tol * tol * stat[1] || (sweep > 0 && prev_rot == 0);
+    // entries at the rounding level of the whole block are zeroed, not rotated: in a degenerate
+    // eigenspace (the zero eigenvalues of a rank-deficient block) rotations would only stir
+    // that noise and the sweeps would not settle
+    const double thr = 2.3e-16 * sqrt(stat[0] + stat[1]);
     __syncthreads();
     if (conv) break;
     for (int r = 0; r < M; ++r) {
-      for (int P = tid; P < nb; P += blockDim.x) {
+      if (tid < nb) {
+        const int P = tid;
         int p, q;
         if (P == 0) {
           p = r;
           q = M;
         } else {
-          p = (r + P) % M;
-          q = (r - P + M) % M;
+          p = r + P;
+          if (p >= M) p -= M;
+          q = r - P;
+          if (q < 0) q += M;
         }
         if (p > q) {
           const int tmp = p;
@@ -218,93 +245,108 @@ __global__ __launch_bounds__(256) void k_jacobi(double* __restrict__ A_all,
           q = tmp;
         }
         double c = 1.0, s = 0.0, t = 0.0;
-        const double apq = A[(int64_t)p * m + q];
-        if (q < d && apq != 0.0) {
-          const double tau = (A[(int64_t)q * m + q] - A[(int64_t)p * m + p]) / (2.0 * apq);
+        const double apq = A[p * m + q];
+        const double app = A[p * m + p], aqq = A[q * m + q];
+        int rot = 0;
+        if (q < d && fabs(apq) > thr) {
+          const double tau = (aqq - app) / (2.0 * apq);
           t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
+          any_rot = 1;
+          rot = 1;
         }
         pp[P] = p;
         qq[P] = q;
         cs[P] = c;
         sn[P] = s;
         tn[P] = t;
+        // 2: rotates; 1: only zeroes a_pq; 0: nothing to do
+        act[P] = rot ? 2 : (apq != 0.0 ? 1 : 0);
       }
       __syncthreads();
-      for (int e = tid; e < ntask; e += blockDim.x) {
-        const int dl = e / nb, P = e - dl * nb;
-        if ((nb & 1) == 0 && dl == half && P >= half) continue;
-        const int R = (P + dl) % nb;
-        const int p = pp[P], q = qq[P], r0 = pp[R], s0 = qq[R];
-        double* Ap = A + (int64_t)p * m;
-        double* Aq = A + (int64_t)q * m;
-        if (R == P) {
-          const double apq = Ap[q], t = tn[P];
-          Ap[p] = Ap[p] - t * apq;
-          Aq[q] = Aq[q] + t * apq;
-          Ap[q] = 0.0;
-          Aq[p] = 0.0;
-          continue;
+      if (worker) {
+        const int P = myP;
+        const int aP = act[P], p = pp[P], q = qq[P];
+        const double cP = cs[P], sP = sn[P];
+        double* Ap = A + p * m;
+        double* Aq = A + q * m;
+        for (int dl = myq; dl <= half; dl += nth) {
+          if ((nb & 1) == 0 && dl == half && P >= half) continue;
+          if (dl == 0) {
+            if (aP == 0) continue;
+            const double apq = Ap[q], t = tn[P];
+            Ap[p] = Ap[p] - t * apq;
+            Aq[q] = Aq[q] + t * apq;
+            Ap[q] = 0.0;
+            Aq[p] = 0.0;
+            continue;
+          }
+          int R = P + dl;
+          if (R >= nb) R -= nb;
+          if (aP < 2 && act[R] < 2) continue;   // both rotations are the identity
+          const int r0 = pp[R], s0 = qq[R];
+          const double cR = cs[R], sR = sn[R];
+          const double a00 = Ap[r0], a01 = Ap[s0], a10 = Aq[r0], a11 = Aq[s0];
+          const double b00 = cP * a00 - sP * a10, b01 = cP * a01 - sP * a11;
+          const double b10 = sP * a00 + cP * a10, b11 = sP * a01 + cP * a11;
+          const double e00 = cR * b00 - sR * b01, e01 = sR * b00 + cR * b01;
+          const double e10 = cR * b10 - sR * b11, e11 = sR * b10 + cR * b11;
+          Ap[r0] = e00;
+          Ap[s0] = e01;
+          Aq[r0] = e10;
+          Aq[s0] = e11;
+          A[r0 * m + p] = e00;
+          A[s0 * m + p] = e01;
+          A[r0 * m + q] = e10;
+          A[s0 * m + q] = e11;
         }
-        const double cP = cs[P], sP = sn[P], cR = cs[R], sR = sn[R];
-        const double a00 = Ap[r0], a01 = Ap[s0], a10 = Aq[r0], a11 = Aq[s0];
-        const double b00 = cP * a00 - sP * a10, b01 = cP * a01 - sP * a11;
-        const double b10 = sP * a00 + cP * a10, b11 = sP * a01 + cP * a11;
-        const double e00 = cR * b00 - sR * b01, e01 = sR * b00 + cR * b01;
-        const double e10 = cR * b10 - sR * b11, e11 = sR * b10 + cR * b11;
-        Ap[r0] = e00;
-        Ap[s0] = e01;
-        Aq[r0] = e10;
-        Aq[s0] = e11;
-        A[(int64_t)r0 * m + p] = e00;
-        A[(int64_t)s0 * m + p] = e01;
-        A[(int64_t)r0 * m + q] = e10;
-        A[(int64_t)s0 * m + q] = e11;
-      }
-      if (vecs) {
-        for (int e = tid; e < m * nb; e += blockDim.x) {
-          const int i = e / nb, R = e - (e / nb) * nb;
-          double* Vi = V + (int64_t)i * m;
-          const int p = pp[R], q = qq[R];
-          const double v0 = Vi[p], v1 = Vi[q];
-          Vi[p] = cs[R] * v0 - sn[R] * v1;
-          Vi[q] = sn[R] * v0 + cs[R] * v1;
+        if (vecs && aP == 2) {
+#pragma unroll 4
+          for (int i = myq; i < m; i += nth) {
+            double* Vi = V + i * m;
+            const double v0 = Vi[p], v1 = Vi[q];
+            Vi[p] = cP * v0 - sP * v1;
+            Vi[q] = sP * v0 + cP * v1;
+          }
         }
       }
       __syncthreads();
     }
+    prev_rot = any_rot;
   }
-  for (int i = tid; i < m; i += blockDim.x) lam_all[(int64_t)blk * m + i] = A[(int64_t)i * m + i];
+  for (int i = tid; i < m; i += NT) lam_all[(int64_t)blk * m + i] = A[i * m + i];
   if (SMEM && vecs)
-    for (int64_t e = tid; e < mm; e += blockDim.x) Vg[e] = V[e];
+    for (int e = tid; e < mm; e += NT) Vg[e] = V[e];
 }
 
 size_t jacobi_smem_bytes(int m, bool vecs) { return (size_t)(vecs ? 2 : 1) * m * m * sizeof(double); }
 // LDS per workgroup is 160 KiB; the kernel's static arrays (pair tables, reduction slots) take
-// 2096 bytes when the blocks are held in LDS.
-constexpr size_t kJacobiSmemMax = 160 * 1024 - 2304;
+// 2356 bytes when the blocks are held in LDS.
+constexpr size_t kJacobiSmemMax = 160 * 1024 - 2560;
 
 // Jacobi on n_vals value-only blocks followed by n_vec blocks with vectors (A_all holds them in
 // that order; V_all the n_vec vector blocks).
 int jacobi_launch(double* A_all, double* V_all, double* lam, int m, int d, int n_vals, int n_vec,
-                  hipStream_t st) {
+                  int v_given, hipStream_t st) {
   const int nblk = n_vals + n_vec;
   if (nblk == 0) return FIRAL_OK;
   const size_t smem = jacobi_smem_bytes(m, n_vec > 0);
   const int max_sweeps = 40;
-  const double tol = 1e-15;
+  const double tol = 1e-14;
   if (smem <= kJacobiSmemMax && m / 2 <= 64) {
     static bool attr = false;
     if (!attr) {
-      FIRAL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi<true>),
+      FIRAL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi<true, 1024>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize,
                                     (int)kJacobiSmemMax));
       attr = true;
     }
-    k_jacobi<true><<<nblk, 256, smem, st>>>(A_all, V_all, lam, m, d, n_vals, max_sweeps, tol);
+    k_jacobi<true, 1024><<<nblk, 1024, smem, st>>>(A_all, V_all, lam, m, d, n_vals, v_given,
+                                                   max_sweeps, tol);
   } else {
-    k_jacobi<false><<<nblk, 256, 0, st>>>(A_all, V_all, lam, m, d, n_vals, max_sweeps, tol);
+    k_jacobi<false, 512><<<nblk, 512, 0, st>>>(A_all, V_all, lam, m, d, n_vals, v_given,
+                                               max_sweeps, tol);
   }
   FIRAL_LAUNCHED();
   return FIRAL_OK;
@@ -389,7 +431,7 @@ __global__ void k_round_weights(const double* __restrict__ lamE, int m, int d, i
 // 16x16x4 MFMA, stages of 16 k-rows double-buffered through LDS) and keeps the per-row sums in
 // registers.  Workgroups are ordered class-major (XCD-aware), so one XCD's tiles share W_k.
 template <typename T>
-__global__ __launch_bounds__(256) void k_round_score(const T* __restrict__ X,
+__global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
                                                      const T* __restrict__ H, int64_t r0,
                                                      int64_t R, int d, int c,
                                                      const double* __restrict__ W, int ldw,
@@ -413,33 +455,32 @@ __global__ __launch_bounds__(256) void k_round_score(const T* __restrict__ X,
   const int nst = (d + TK - 1) / TK;
   const int nct = (ldw + TN - 1) / TN;
 
-  double s1[2][4], s2[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) s1[i][v] = s2[i][v] = 0.0;
+  // per-row sums of w1 y^2 and w2 y^2, one slot per column half of the workgroup
+  for (int e = tid; e < 2 * TM * 2; e += 256) (&red[0][0][0])[e] = 0.0;
 
-  // staging: A = 64 rows x 16 k (4 per thread), B = 16 k x 64 columns (4 per thread)
+  // staging: A = 64 rows x 16 k, thread (row tid/16 + 16u, k tid%16), u = 0..3;
+  // B = 16 k x 64 columns, thread (k tid/64 + 4u, column tid%64)
+  const int ak = tid & 15, ar = tid >> 4, bc = tid & 63, bk = tid >> 6;
+  const T* xa = X + (r0 + row0 + ar) * d + ak;
+  const int64_t arows = R - row0 - ar;              // rows of this thread's column in range
+  const double* wb = Wk + (int64_t)bk * ldw + bc;
   double ra[4], rb[4];
   int col0 = 0;
   auto load = [&](int st) {
     const int k0 = st * TK;
+    const bool ka = k0 + ak < d;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = tid + 256 * u;
-      const int row = e / TK, kk = e % TK;
-      const int64_t gr = row0 + row;
-      ra[u] = (gr < R && k0 + kk < d) ? (double)X[(r0 + gr) * d + k0 + kk] : 0.0;
-      const int kb = e / TN, cc = e % TN;
-      rb[u] = (k0 + kb < d && col0 + cc < ldw) ? Wk[(int64_t)(k0 + kb) * ldw + col0 + cc] : 0.0;
+      ra[u] = (ka && 16 * u < arows) ? (double)xa[(int64_t)16 * u * d + k0] : 0.0;
+      rb[u] = (k0 + bk + 4 * u < d && col0 + bc < ldw) ? wb[(int64_t)(k0 + 4 * u) * ldw + col0]
+                                                        : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = tid + 256 * u;
-      As[buf][e % TK][e / TK] = ra[u];
-      Bs[buf][e / TN][e % TN] = rb[u];
+      As[buf][ak][ar + 16 * u] = ra[u];
+      Bs[buf][bk + 4 * u][bc] = rb[u];
     }
   };
 
@@ -475,39 +516,36 @@ __global__ __launch_bounds__(256) void k_round_score(const T* __restrict__ X,
       if (st + 1 < nst) store(buf ^ 1);
       __syncthreads();
     }
+    // this tile's weighted squares, summed over the lane's columns, then over the 16 lanes
+    // of each row group; lane 0 of the group adds them to the row's slot
+    double w1[2], w2[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      if (!jon[j]) continue;
       const int col = col0 + wn + 16 * j + li;
-      const double w1 = wk[2 * col], w2 = wk[2 * col + 1];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const double y2 = acc[i][j][v] * acc[i][j][v];
-          s1[i][v] = fma(w1, y2, s1[i][v]);
-          s2[i][v] = fma(w2, y2, s2[i][v]);
-        }
+      w1[j] = jon[j] ? wk[2 * col] : 0.0;
+      w2[j] = jon[j] ? wk[2 * col + 1] : 0.0;
     }
-  }
-  // sums over the 16 columns of each lane group, then over the two column halves
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        s1[i][v] += __shfl_xor(s1[i][v], o, 64);
-        s2[i][v] += __shfl_xor(s2[i][v], o, 64);
-      }
-  if (li == 0) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = wm + 16 * i + MF::row(g, v);
-        red[wave >> 1][row][0] = s1[i][v];
-        red[wave >> 1][row][1] = s2[i][v];
+        double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double y2 = acc[i][j][v] * acc[i][j][v];
+          t1 = fma(w1[j], y2, t1);
+          t2 = fma(w2[j], y2, t2);
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          t1 += __shfl_xor(t1, o, 64);
+          t2 += __shfl_xor(t2, o, 64);
+        }
+        if (li == 0) {
+          const int row = wm + 16 * i + MF::row(g, v);
+          red[wave >> 1][row][0] += t1;
+          red[wave >> 1][row][1] += t2;
+        }
       }
   }
   __syncthreads();
@@ -681,11 +719,11 @@ __global__ __launch_bounds__(1024) void k_min_eig(const double* __restrict__ lam
 
 // ------------------------------------------------------------------ state
 struct Round {
-  Ctx* x;
+  Ctx* x;                // borrowed; its profiling marks also bracket the scoring launches
   int d, c, m, ldw, b, t;
   int64_t n_pool, N, R, nparts;
   double eta;
-  double *omega, *Lf, *Li, *Ho, *Ot, *Cm, *Hacc, *JA, *JV, *lam, *W, *wts, *Tb, *pval, *nu,
+  double *omega, *Lf, *Li, *Ho, *Ot, *Cm, *Hacc, *JA, *JV, *JT, *lam, *W, *wts, *Tb, *pval, *nu,
       *smax, *gpart, *crit;
   int64_t *pidx, *sel;
   int32_t *mask, *flags, *tiles;
@@ -693,7 +731,7 @@ struct Round {
 };
 
 static void free_round(Round* r) {
-  void* bufs[] = {r->omega, r->Lf, r->Li, r->Ho, r->Ot, r->Cm, r->Hacc, r->JA, r->JV, r->lam,
+  void* bufs[] = {r->omega, r->Lf, r->Li, r->Ho, r->Ot, r->Cm, r->Hacc, r->JA, r->JV, r->JT, r->lam,
                   r->W, r->wts, r->Tb, r->pval, r->nu, r->smax, r->gpart, r->crit, r->pidx,
                   r->sel, r->mask, r->flags, r->tiles};
   for (void* b : bufs)
@@ -739,7 +777,8 @@ static int round_operand(Round* r, const double* nu_p, hipStream_t st) {
   k_round_weights<<<(unsigned)cdiv((int64_t)c * r->ldw, 256), 256, 0, st>>>(
       r->lam + (int64_t)c * m, m, d, c, r->ldw, nu_p, r->eta, r->wts);
   FIRAL_LAUNCHED();
-  BGemm g{r->Li, dd, 1, d, r->JV, mm, m, 1, r->W, (int64_t)d * r->ldw, r->ldw, 1, d, d, d};
+  BGemm g{r->Li, dd, 1, d, r->JV, mm, m, 1, r->W, (int64_t)d * r->ldw, r->ldw, 1, d, d, d,
+          INT_MAX, INT_MAX};
   return bgemm(g, c, st);
 }
 
@@ -753,9 +792,11 @@ static int round_score_t(Round* r, double* r_out, hipStream_t st) {
   for (int64_t r0 = 0; r0 < r->n_pool; r0 += r->R) {
     const int64_t R = std::min<int64_t>(r->R, r->n_pool - r0);
     const int64_t nwg = cdiv(R, kScoreTM) * r->c;
+    FIRAL_CHECK(prof_mark(r->x, st, true));
     k_round_score<T><<<(unsigned)nwg, 256, 0, st>>>(X, H, r0, R, r->d, r->c, r->W, r->ldw, r->wts,
                                                     r->eta, r->Tb);
     FIRAL_LAUNCHED();
+    FIRAL_CHECK(prof_mark(r->x, st, false));
     k_round_rsum<<<(unsigned)cdiv(R, 256), 256, 0, st>>>(r->Tb, R, r->c, r0, r->mask, r_out,
                                                          r->pval, r->pidx);
     FIRAL_LAUNCHED();
@@ -783,7 +824,14 @@ static int round_step_launch(Round* r, hipStream_t st) {
                                              1.0 / r->b, r->sel, t, r->Li, r->Ho, r->Ot, r->Cm,
                                              r->Hacc, r->JA, r->mask, r->flags + 1);
   FIRAL_LAUNCHED();
-  FIRAL_CHECK(jacobi_launch(r->JA, r->JV, r->lam, m, d, c, c, st));
+  // both eigenproblems of the round in the previous round's eigenbasis Q (JV):
+  // JA_k <- Q^T JA_k Q, so they start close to diagonal; E's rotations accumulate onto Q
+  const int64_t mm = (int64_t)m * m;
+  FIRAL_CHECK(bgemm(BGemm{r->JA, mm, m, 1, r->JV, mm, m, 1, r->JT, mm, m, 1, m, m, m, INT_MAX, c},
+                    2 * c, st));
+  FIRAL_CHECK(bgemm(BGemm{r->JV, mm, 1, m, r->JT, mm, m, 1, r->JA, mm, m, 1, m, m, m, c, INT_MAX},
+                    2 * c, st));
+  FIRAL_CHECK(jacobi_launch(r->JA, r->JV, r->lam, m, d, c, c, 1, st));
   k_round_nu<<<1, 1024, 0, st>>>(r->lam, m, d, c, r->eta, r->nu + t + 1);
   FIRAL_LAUNCHED();
   FIRAL_CHECK(round_operand(r, r->nu + t + 1, st));
@@ -812,6 +860,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   RREQ(lambda >= 0.0 && std::isfinite(lambda), "firal_round_create: lambda must be >= 0");
   RREQ(b >= 1 && (int64_t)b <= x->n_pool, "firal_round_create: b = %d outside [1, n_pool]", b);
   RREQ(x->d <= kMaxD, "firal_round_create: d = %d above the Round step's limit %d", x->d, kMaxD);
+  RREQ(x->c <= 30000, "firal_round_create: c = %d above the Round step's limit 30000", x->c);
   hipStream_t st = (hipStream_t)stream;
   FIRAL_HIP(hipSetDevice(x->device));
   Round* r = new Round();
@@ -846,6 +895,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   RALLOC(r->Hacc, sizeof(double) * c * dd);
   RALLOC(r->JA, sizeof(double) * 2 * c * mm);
   RALLOC(r->JV, sizeof(double) * c * mm);
+  RALLOC(r->JT, sizeof(double) * 2 * c * mm);
   RALLOC(r->lam, sizeof(double) * 2 * c * m);
   RALLOC(r->W, sizeof(double) * c * d * r->ldw);
   RALLOC(r->wts, sizeof(double) * c * r->ldw * 2);
@@ -903,13 +953,15 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   k_tri_inv<<<c, 256, 0, st>>>(r->Lf, r->Li, d);
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
   // O_k = L^-1 H_o L^-T (JV as the intermediate H_o L^-T)
-  RCHK(bgemm(BGemm{r->Ho, dd, d, 1, r->Li, dd, 1, d, r->JV, dd, d, 1, d, d, d}, c, st));
-  RCHK(bgemm(BGemm{r->Li, dd, d, 1, r->JV, dd, d, 1, r->Ot, dd, d, 1, d, d, d}, c, st));
+  RCHK(bgemm(BGemm{r->Ho, dd, d, 1, r->Li, dd, 1, d, r->JV, dd, d, 1, d, d, d, INT_MAX, INT_MAX},
+             c, st));
+  RCHK(bgemm(BGemm{r->Li, dd, d, 1, r->JV, dd, d, 1, r->Ot, dd, d, 1, d, d, d, INT_MAX, INT_MAX},
+             c, st));
   // round 1: E = O / b, eigenpairs, nu_1 = sqrt(dc), W and weights
   k_pad_comb<<<(unsigned)cdiv((int64_t)c * mm, 256), 256, 0, st>>>(
       r->Ot, 1.0 / b, nullptr, 0.0, r->JA + (int64_t)c * mm, d, m, c);
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
-  RCHK(jacobi_launch(r->JA + (int64_t)c * mm, r->JV, r->lam + (int64_t)c * m, m, d, 0, c, st));
+  RCHK(jacobi_launch(r->JA + (int64_t)c * mm, r->JV, r->lam + (int64_t)c * m, m, d, 0, c, 0, st));
   RCHK(round_operand(r, r->nu, st));
   int32_t bad = INT_MAX;
   if (hipMemcpyAsync(&bad, r->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -977,7 +1029,7 @@ extern "C" int firal_round_criterion(firal_round round, double* out, void* strea
   k_pad_comb<<<(unsigned)cdiv((int64_t)c * m * m, 256), 256, 0, st>>>(r->Hacc, 1.0, nullptr, 0.0,
                                                                       r->JA, d, m, c);
   FIRAL_LAUNCHED();
-  FIRAL_CHECK(jacobi_launch(r->JA, nullptr, r->lam, m, d, c, 0, st));
+  FIRAL_CHECK(jacobi_launch(r->JA, nullptr, r->lam, m, d, c, 0, 0, st));
   k_min_eig<<<1, 1024, 0, st>>>(r->lam, m, d, c, r->crit);
   FIRAL_LAUNCHED();
   FIRAL_HIP(hipMemcpyAsync(out, r->crit, sizeof(double), hipMemcpyDeviceToHost, st));
