@@ -162,10 +162,12 @@ def grad_errors(p, project, n_cg=15):
     return {k: float(np.linalg.norm(g[k] - g["f64"]) / ref) for k in ("f32", "bf16x3")}
 
 
-def round_leg(p, w, eta, cpu_rounds=2):
+def round_leg(p, w, eta, fp32, cpu_rounds=2):
     """The Round step (Algorithm 3) at the same workload: all b rounds from z = b w (the
-    Relax leg's final weights), FP64 on the device.  Reports ms per selected point, the scoring
-    kernel's time and FP64 MFMA rate, and the FP64 oracle's time per round on the host."""
+    Relax leg's final weights).  fp32: the per-point objective and its argmax in FP32 (the
+    paper's precision), else FP64; the block state is FP64 either way.  Reports ms per selected
+    point, the scoring kernel's time and MFMA rate, and the oracle's time per round on the host
+    (same decision precision)."""
     import numpy as np
     import torch
 
@@ -176,13 +178,13 @@ def round_leg(p, w, eta, cpu_rounds=2):
     ctx = RelaxContext(X, H, p.n_pool, 1, "f32")
     z = (p.b * w).contiguous()
     b = int(p.b)
-    warm = RoundSolver(ctx, z, p.lam, eta, b)
+    warm = RoundSolver(ctx, z, p.lam, eta, b, fp32=fp32)
     warm.step(2)
     warm.result()
     warm.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rs = RoundSolver(ctx, z, p.lam, eta, b)
+    rs = RoundSolver(ctx, z, p.lam, eta, b, fp32=fp32)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     ctx.profile_begin()
@@ -202,17 +204,21 @@ def round_leg(p, w, eta, cpu_rounds=2):
     Ho = H.cpu().numpy().astype(np.float64)
     zo = z.cpu().numpy()
     tc = time.perf_counter()
-    st = orr.DiagonalRound(Xo, Ho, p.n_pool, zo, p.lam, eta, b)
+    st = orr.DiagonalRound(Xo, Ho, p.n_pool, zo, p.lam, eta, b, fp32=fp32)
     for _ in range(cpu_rounds):
         st.step()
     t_cpu = (time.perf_counter() - tc) / cpu_rounds
     same = [int(i) for i in st.selected] == [int(i) for i in res["selected"][:cpu_rounds]]
-    return {"rounds": res["t"], "eta": eta, "ms_per_point": 1e3 * elapsed / b,
+    pk = PEAK["f32" if fp32 else "f64"]
+    kname = ("k_round_score<float, float> (per-point objective, FP32 MFMA)" if fp32 else
+             "k_round_score<float, double> (per-point objective, FP64 MFMA)")
+    return {"decision": "fp32" if fp32 else "fp64", "rounds": res["t"], "eta": eta,
+            "ms_per_point": 1e3 * elapsed / b,
             "points_per_s": b / elapsed, "setup_ms": 1e3 * t_setup,
             "first_selected": [int(i) for i in res["selected"][:8]],
-            "roofline": {"bound": "mfma", "kernel": "k_round_score<float> (eq.-13 scores, FP64 MFMA)",
-                         "achieved": flops / t_kern / 1e12, "peak": PEAK["f64"],
-                         "unit": "TFLOP/s", "frac": flops / t_kern / 1e12 / PEAK["f64"],
+            "roofline": {"bound": "mfma", "kernel": kname,
+                         "achieved": flops / t_kern / 1e12, "peak": pk,
+                         "unit": "TFLOP/s", "frac": flops / t_kern / 1e12 / pk,
                          "kernel_us": t_kern * 1e6, "traffic": None,
                          "padded_columns": ldw},
             "cpu_oracle": {"s_per_round": t_cpu, "rounds_timed": cpu_rounds,
@@ -428,7 +434,9 @@ def main():
     if args.prec != "bf16x3" and not args.no_bf16x3:
         legs["bf16x3"] = run_leg(p, "bf16x3", args.steps, args.warmup, project, args.hvp_reps)
     errs = grad_errors(p, project)
-    rnd = None if args.no_round else round_leg(p, main_leg["w"], args.eta)
+    rnd = None if args.no_round else {
+        "fp32_decision": round_leg(p, main_leg["w"], args.eta, True),
+        "fp64_decision": round_leg(p, main_leg["w"], args.eta, False)}
     peak = PEAK[args.prec]
     res = {
         "metric": METRIC,

@@ -227,17 +227,25 @@ int firal_batch_destroy(firal_batch batch);
  * (Sigma_o)_k = lambda I + (H_o)_k + sum_i z_i g_ik x_i x_i^T over the pool rows (the blocks of
  * Sigma_z at the relaxed weights z); (H_o)_k = sum over the labeled rows of g_ik x_i x_i^T.  The
  * objective's numerator holds Sigma_o itself, as the proposition's proof derives it (the stated
- * objective prints its inverse).  All arithmetic is FP64 (FP32 X and H are read exactly).
+ * objective prints its inverse).  Arithmetic is FP64 (FP32 X and H are read exactly) except
+ * the objective in FIRAL_ROUND_FP32 mode.
  * Requires d <= 512 and c <= 30000.  The state borrows the context (X and H): destroy it first. */
 typedef struct firal_round_s* firal_round;
 
+/* firal_round_create flag: evaluate the per-point objective (the two quadratic forms, the class
+ * terms and their sum) and take the argmax in FP32, the precision of the paper's
+ * implementation (Section 3.3); without it they are FP64.  The block state (Sigma_o factors,
+ * eigenvalues, nu, the update) is FP64 either way. */
+#define FIRAL_ROUND_FP32 1u
+
 /* Set up rounds of one Round solve on ctx's rows: z (device FP64 [n_pool]) the relaxed
  * weights (read during the call only), lambda >= 0 the regulariser of Sigma_o, eta > 0 the
- * learning rate, b in [1, n_pool] the number of rounds (points to select).  Forms Sigma_o's
- * blocks and Cholesky factors, H_o's blocks and round 1's B^-1.  Synchronous.
+ * learning rate, b in [1, n_pool] the number of rounds (points to select), flags 0 or
+ * FIRAL_ROUND_FP32.  Forms Sigma_o's blocks and Cholesky factors, H_o's blocks and round 1's
+ * B^-1.  Synchronous.
  * Errors: EINVAL, ENOTSPD (a Sigma_o block is not positive definite), EHIP, ENOMEM. */
 int firal_round_create(firal_round* out, firal_ctx ctx, const double* z, double lambda,
-                       double eta, int32_t b, void* stream);
+                       double eta, int32_t b, uint32_t flags, void* stream);
 /* Enqueue the next `rounds` rounds (asynchronous; nothing is read back, so the calls may be
  * captured).  EINVAL if fewer than `rounds` of the b rounds are left. */
 int firal_round_step(firal_round round, int32_t rounds, void* stream);

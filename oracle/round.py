@@ -37,6 +37,11 @@ design notes):
   stops shrinking in float64.
 * The eta criterion of the experiments section is min_k lambda_min((H)_k)
   of Algorithm 3's (H)_k after the b rounds (which include H_o).
+* Decision precision: the paper's implementation computes in single
+  precision (Section 3.3).  With fp32=True the per-point objective (the two
+  quadratic forms, the class terms and their sum) is evaluated in float32
+  and the argmax taken on those float32 values, as the GPU's FP32 mode does;
+  the block state (Sigma_o, B^-1, eigenvalues, nu) stays float64 either way.
 """
 from __future__ import annotations
 
@@ -90,7 +95,7 @@ class DiagonalRound:
     b: number of rounds.
     """
 
-    def __init__(self, X, H, n_pool, z, lam, eta, b):
+    def __init__(self, X, H, n_pool, z, lam, eta, b, fp32: bool = False):
         self.X = np.asarray(X, dtype=np.float64)
         self.H = np.asarray(H, dtype=np.float64)
         self.n_pool = int(n_pool)
@@ -98,18 +103,19 @@ class DiagonalRound:
         self.c = self.H.shape[1]
         self.eta = float(eta)
         self.b = int(b)
+        self.fp32 = bool(fp32)
         self.G = class_weights(self.H)
         d, c = self.d, self.c
         w_lab = np.concatenate([np.zeros(self.n_pool), np.ones(self.N - self.n_pool)])
         w_all = np.concatenate([np.asarray(z, dtype=np.float64), np.ones(self.N - self.n_pool)])
-        # line 3: the blocks of Sigma_o = H_o + H_{z_o} (+ lam I)
+        # the blocks of Sigma_o = H_o + H_{z_o} (+ lam I)
         self.Ho = gram_blocks(self.X, self.G, w_lab)
         self.Sig = gram_blocks(self.X, self.G, w_all) + lam * np.eye(d)[None]
         self.Sig_mh = np.stack([inv_sqrt_spd(self.Sig[k]) for k in range(c)])
-        # line 4: B_1 = sqrt(dc) Sigma_o + (eta/b) H_o
+        # first round: B_1 = sqrt(dc) Sigma_o + (eta/b) H_o (A_1 = sqrt(dc) I)
         self.nu = math.sqrt(d * c)
         self.Binv = np.linalg.inv(self.nu * self.Sig + (self.eta / self.b) * self.Ho)
-        # line 5
+        # the accumulated (H)_k start at zero
         self.Hk = np.zeros((c, d, d))
         self.t = 1
         self.selected: list[int] = []
@@ -120,16 +126,19 @@ class DiagonalRound:
     def scores(self) -> np.ndarray:
         """The diagonal Round objective of every pool row at the current B_t
         (selected rows included; the caller masks them)."""
-        Xp = self.X[:self.n_pool]
-        Gp = self.G[:self.n_pool]
-        r = np.zeros(self.n_pool)
+        ft = np.float32 if self.fp32 else np.float64
+        Xp = self.X[:self.n_pool].astype(ft)
+        Gp = self.G[:self.n_pool].astype(ft)
+        eta = ft(self.eta)
+        r = np.zeros(self.n_pool, dtype=ft)
         for k in range(self.c):
-            Y = Xp @ self.Binv[k]                      # rows (B_k^-1 x_i)^T
-            q1 = np.sum(Y * Xp, axis=1)                # x^T B_k^-1 x
-            q2 = np.sum((Y @ self.Sig[k]) * Y, axis=1)  # x^T B_k^-1 Sigma_k B_k^-1 x
-            g = Gp[:, k]
-            r += g * q2 / (1.0 + self.eta * g * q1)
-        return r
+            Bk = self.Binv[k].astype(ft)
+            Y = Xp @ Bk                                               # rows (B_k^-1 x_i)^T
+            q1 = np.sum(Y * Xp, axis=1, dtype=ft)                     # x^T B_k^-1 x
+            q2 = np.sum((Y @ self.Sig[k].astype(ft)) * Y, axis=1, dtype=ft)
+            g = Gp[:, k]                                              # x^T B^-1 Sigma B^-1 x above
+            r += g * q2 / (ft(1.0) + eta * g * q1)
+        return r.astype(np.float64)
 
     def argmax(self, r: np.ndarray) -> int:
         """Largest score among the unselected rows, lowest index on ties."""
@@ -137,23 +146,24 @@ class DiagonalRound:
         return int(np.argmax(masked))
 
     def step(self, i: int | None = None) -> int:
-        """One round: line 7 (or the given index), then lines 8-12."""
+        """One round: the selection (or the given index), the update of (H)_k, the
+        eigenvalues, nu and the next B^-1."""
         if i is None:
             i = self.argmax(self.scores())
         if not self.available[i]:
             raise ValueError(f"row {i} was already selected")
         x = self.X[i]
-        # line 8: (H)_k += H_o,k / b + g_ik x x^T
+        # (H)_k += H_o,k / b + g_ik x x^T
         self.Hk += self.Ho / self.b + self.G[i][:, None, None] * np.outer(x, x)[None]
-        # line 9: eigenvalues of (H~)_k = Sigma_k^-1/2 (H)_k Sigma_k^-1/2
+        # eigenvalues of (H~)_k = Sigma_k^-1/2 (H)_k Sigma_k^-1/2
         self.lams = np.stack([np.linalg.eigvalsh(self.Sig_mh[k] @ self.Hk[k] @ self.Sig_mh[k])
                               for k in range(self.c)])
-        # line 10
+        # nu_{t+1} from Tr(A_{t+1}^-2) = 1
         self.nu = nu_bisection(self.lams, self.eta)
-        # line 11: B_{t+1}^-1
+        # B_{t+1}^-1
         self.Binv = np.linalg.inv(self.nu * self.Sig + self.eta * self.Hk
                                   + (self.eta / self.b) * self.Ho)
-        # line 12
+        # the selected set grows by the row
         self.selected.append(i)
         self.available[i] = False
         self.nus.append(self.nu)
@@ -165,10 +175,11 @@ class DiagonalRound:
         return float(min(np.linalg.eigvalsh(self.Hk[k])[0] for k in range(self.c)))
 
 
-def round_diag(X, H, n_pool, z, lam, eta, b, rounds: int | None = None) -> dict:
+def round_diag(X, H, n_pool, z, lam, eta, b, rounds: int | None = None,
+               fp32: bool = False) -> dict:
     """Run `rounds` (default b) rounds of Algorithm 3; returns the selected rows,
     nu_1..nu_{rounds+1}, the winning score of each round and the criterion."""
-    st = DiagonalRound(X, H, n_pool, z, lam, eta, b)
+    st = DiagonalRound(X, H, n_pool, z, lam, eta, b, fp32=fp32)
     smax = []
     for _ in range(b if rounds is None else rounds):
         r = st.scores()

@@ -12,8 +12,8 @@ import math
 import torch
 
 from . import _lib
-from ._lib import (BF16X3, F32, F64, PCG_PROJECT, FiralError, Info, WARN_NOT_CONVERGED, check,
-                   load)
+from ._lib import (BF16X3, F32, F64, PCG_PROJECT, ROUND_FP32, FiralError, Info,
+                   WARN_NOT_CONVERGED, check, load)
 
 __all__ = ["RelaxContext", "RelaxBatch", "RelaxObjective", "RoundSolver", "round_eta_sweep",
            "FiralError", "default_beta0", "F64", "F32", "BF16X3", "load"]
@@ -267,18 +267,22 @@ class RoundSolver:
     """Diagonal Round step (Algorithm 3) on a RelaxContext's rows.
 
     z: CUDA float64 relaxed weights of the pool rows (read at construction); lam: regulariser of
-    Sigma_o's blocks; eta: learning rate; b: rounds (points to select).  Everything runs in
-    FP64 on the device; step() only enqueues.  Keep the context alive while the solver lives.
+    Sigma_o's blocks; eta: learning rate; b: rounds (points to select); fp32: evaluate the
+    per-point objective and its argmax in FP32 (the paper's precision) instead of FP64.  The
+    block state is FP64; step() only enqueues.  Keep the context alive while the solver lives.
     """
 
-    def __init__(self, ctx: RelaxContext, z: torch.Tensor, lam: float, eta: float, b: int):
+    def __init__(self, ctx: RelaxContext, z: torch.Tensor, lam: float, eta: float, b: int,
+                 fp32: bool = False):
         self.lib = load()
         self.ctx = ctx
         self.b = int(b)
+        self.fp32 = bool(fp32)
         z = RelaxContext._f64(z, ctx.n_pool)
         self._r = _lib.ctypes.c_void_p()
         check(self.lib.firal_round_create(_lib.ctypes.byref(self._r), ctx._ctx, _ptr(z),
-                                          float(lam), float(eta), self.b, _stream()))
+                                          float(lam), float(eta), self.b,
+                                          ROUND_FP32 if self.fp32 else 0, _stream()))
 
     def step(self, rounds: int = 1):
         check(self.lib.firal_round_step(self._r, int(rounds), _stream()))
@@ -328,12 +332,13 @@ class RoundSolver:
             pass
 
 
-def round_eta_sweep(ctx: RelaxContext, z: torch.Tensor, lam: float, etas, b: int) -> dict:
+def round_eta_sweep(ctx: RelaxContext, z: torch.Tensor, lam: float, etas, b: int,
+                    fp32: bool = False) -> dict:
     """The eta choice of the experiments section: run the Round step for every eta and keep
     the one whose selection maximises min_k lambda_min((H)_k)."""
     crit, sels = [], []
     for eta in etas:
-        rs = RoundSolver(ctx, z, lam, eta, b)
+        rs = RoundSolver(ctx, z, lam, eta, b, fp32=fp32)
         sels.append(rs.run())
         crit.append(rs.criterion())
         rs.close()

@@ -13,6 +13,7 @@ OK = 0
 WARN_NOT_CONVERGED = 1
 EINVAL, EHIP, ENOMEM, ENOTSUP, EBREAKDOWN, ENOTSPD = -1, -2, -3, -4, -5, -6
 PCG_PROJECT = 1
+ROUND_FP32 = 1
 
 # every symbol include/firal.h declares
 EXPORTS = ("firal_create", "firal_destroy", "firal_hvp", "firal_build_precond",
@@ -84,7 +85,7 @@ def load() -> ctypes.CDLL:
         "firal_batch_info": [vp, i32, pinfo, vp],
         "firal_batch_next_t": [vp, i32, ctypes.POINTER(i32)],
         "firal_batch_destroy": [vp],
-        "firal_round_create": [ctypes.POINTER(vp), vp, vp, dbl, dbl, i32, vp],
+        "firal_round_create": [ctypes.POINTER(vp), vp, vp, dbl, dbl, i32, u32, vp],
         "firal_round_step": [vp, i32, vp],
         "firal_round_scores": [vp, vp, vp],
         "firal_round_result": [vp, vp, vp, vp, ctypes.POINTER(i32), vp],

@@ -10,7 +10,7 @@
 //   q1 = sum_j y_j^2 / (nu + eta lambda_kj),   q2 = sum_j y_j^2 / (nu + eta lambda_kj)^2,
 // so one product per class, Y_k = X W_k with W_k = L_k^-T Q_k, scores every row; the
 // product's epilogue forms the sums and the class term g q2 / (1 + eta g q1) (g = h(1 - h))
-// without writing Y.  The eigenvalues of (H~)_k (line 9) are those of C_k = L_k^-1 (H)_k
+// without writing Y.  The eigenvalues of (H~)_k that fix nu are those of C_k = L_k^-1 (H)_k
 // L_k^-T, which is similar to Sigma_k^-1/2 (H)_k Sigma_k^-1/2.
 //
 // A round: score (FP64 MFMA) -> sum over classes and argmax over the unselected rows (fixed
@@ -424,25 +424,33 @@ __global__ void k_round_weights(const double* __restrict__ lamE, int m, int d, i
   wts[2 * e + 1] = w1 * w1;
 }
 
+// FP32 copy of an FP64 array (the operand and weights of the FP32 decision mode)
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = (float)src[i];
+}
+
 // ------------------------------------------------------------------ scoring
 // T[k][row] = g q2 / (1 + eta g q1) for the chunk's rows [r0, r0 + R) and class k, with
 // (q1, q2) the weighted sums of squares of y = W_k^T x (see the file comment).  Workgroup: 64
 // rows x one class; it walks the class's columns in tiles of 64 (four waves of 32 x 32, FP64
 // 16x16x4 MFMA, stages of 16 k-rows double-buffered through LDS) and keeps the per-row sums in
-// registers.  Workgroups are ordered class-major (XCD-aware), so one XCD's tiles share W_k.
-template <typename T>
+// LDS.  Workgroups are ordered class-major (XCD-aware), so one XCD's tiles share W_k.
+// CT is the decision precision: every step from y = W^T x to the class term is computed in CT
+// (FP64, or FP32 on the FP32 MFMA as the paper's single-precision implementation does).
+template <typename T, typename CT>
 __global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
                                                      const T* __restrict__ H, int64_t r0,
                                                      int64_t R, int d, int c,
-                                                     const double* __restrict__ W, int ldw,
-                                                     const double* __restrict__ wts, double eta,
-                                                     double* __restrict__ Tout) {
+                                                     const CT* __restrict__ W, int ldw,
+                                                     const CT* __restrict__ wts, double eta,
+                                                     CT* __restrict__ Tout) {
   constexpr int TM = kScoreTM, TN = kScoreTN, TK = kScoreTK;
   constexpr int SA = TM + kScorePad, SB = TN + kScorePad;
-  __shared__ double As[2][TK][SA];
-  __shared__ double Bs[2][TK][SB];
-  __shared__ double red[2][TM][2];
-  typedef Mfma16<double> MF;
+  __shared__ CT As[2][TK][SA];
+  __shared__ CT Bs[2][TK][SB];
+  __shared__ CT red[2][TM][2];
+  typedef Mfma16<CT> MF;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t ntr = (R + TM - 1) / TM;
@@ -450,30 +458,30 @@ __global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
   const int k = (int)(lid / ntr);
   const int64_t row0 = (lid - (int64_t)k * ntr) * TM;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  const double* Wk = W + (int64_t)k * d * ldw;
-  const double* wk = wts + (int64_t)k * ldw * 2;
+  const CT* Wk = W + (int64_t)k * d * ldw;
+  const CT* wk = wts + (int64_t)k * ldw * 2;
   const int nst = (d + TK - 1) / TK;
   const int nct = (ldw + TN - 1) / TN;
 
   // per-row sums of w1 y^2 and w2 y^2, one slot per column half of the workgroup
-  for (int e = tid; e < 2 * TM * 2; e += 256) (&red[0][0][0])[e] = 0.0;
+  for (int e = tid; e < 2 * TM * 2; e += 256) (&red[0][0][0])[e] = CT(0);
 
   // staging: A = 64 rows x 16 k, thread (row tid/16 + 16u, k tid%16), u = 0..3;
   // B = 16 k x 64 columns, thread (k tid/64 + 4u, column tid%64)
   const int ak = tid & 15, ar = tid >> 4, bc = tid & 63, bk = tid >> 6;
   const T* xa = X + (r0 + row0 + ar) * d + ak;
   const int64_t arows = R - row0 - ar;              // rows of this thread's column in range
-  const double* wb = Wk + (int64_t)bk * ldw + bc;
-  double ra[4], rb[4];
+  const CT* wb = Wk + (int64_t)bk * ldw + bc;
+  CT ra[4], rb[4];
   int col0 = 0;
   auto load = [&](int st) {
     const int k0 = st * TK;
     const bool ka = k0 + ak < d;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      ra[u] = (ka && 16 * u < arows) ? (double)xa[(int64_t)16 * u * d + k0] : 0.0;
+      ra[u] = (ka && 16 * u < arows) ? (CT)xa[(int64_t)16 * u * d + k0] : CT(0);
       rb[u] = (k0 + bk + 4 * u < d && col0 + bc < ldw) ? wb[(int64_t)(k0 + 4 * u) * ldw + col0]
-                                                        : 0.0;
+                                                        : CT(0);
     }
   };
   auto store = [&](int buf) {
@@ -486,7 +494,7 @@ __global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
 
   for (int ct = 0; ct < nct; ++ct) {
     col0 = ct * TN;
-    MF::acc acc[2][2];
+    typename MF::acc acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -502,7 +510,7 @@ __global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
       if (st + 1 < nst) load(st + 1);
 #pragma unroll
       for (int q = 0; q < TK / 4; ++q) {
-        double av[2], bv[2];
+        CT av[2], bv[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) av[i] = As[buf][4 * q + g][wm + 16 * i + li];
 #pragma unroll
@@ -518,21 +526,21 @@ __global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
     }
     // this tile's weighted squares, summed over the lane's columns, then over the 16 lanes
     // of each row group; lane 0 of the group adds them to the row's slot
-    double w1[2], w2[2];
+    CT w1[2], w2[2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int col = col0 + wn + 16 * j + li;
-      w1[j] = jon[j] ? wk[2 * col] : 0.0;
-      w2[j] = jon[j] ? wk[2 * col + 1] : 0.0;
+      w1[j] = jon[j] ? wk[2 * col] : CT(0);
+      w2[j] = jon[j] ? wk[2 * col + 1] : CT(0);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        double t1 = 0.0, t2 = 0.0;
+        CT t1 = CT(0), t2 = CT(0);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          const double y2 = acc[i][j][v] * acc[i][j][v];
+          const CT y2 = acc[i][j][v] * acc[i][j][v];
           t1 = fma(w1[j], y2, t1);
           t2 = fma(w2[j], y2, t2);
         }
@@ -552,11 +560,11 @@ __global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
   if (tid < TM) {
     const int64_t gr = row0 + tid;
     if (gr < R) {
-      const double q1 = red[0][tid][0] + red[1][tid][0];
-      const double q2 = red[0][tid][1] + red[1][tid][1];
+      const CT q1 = red[0][tid][0] + red[1][tid][0];
+      const CT q2 = red[0][tid][1] + red[1][tid][1];
       const double h = (double)H[(r0 + gr) * c + k];
-      const double gk = h * (1.0 - h);
-      Tout[(int64_t)k * R + gr] = gk * q2 / (1.0 + eta * gk * q1);
+      const CT gk = (CT)(h * (1.0 - h));        // g formed in FP64, then rounded to CT
+      Tout[(int64_t)k * R + gr] = gk * q2 / (CT(1) + (CT)eta * gk * q1);
     }
   }
 }
@@ -567,9 +575,10 @@ __device__ __forceinline__ bool better(double v1, int64_t i1, double v2, int64_t
   return v1 > v2 || (v1 == v2 && i1 < i2);
 }
 
-// r_i = sum_k T[k][i] in class order for the chunk's rows; selected (and NaN) rows drop out.
-// Each block leaves its best (value, index) at part[r0 / 256 + block].
-__global__ __launch_bounds__(256) void k_round_rsum(const double* __restrict__ Tb, int64_t R,
+// r_i = sum_k T[k][i] in class order (in CT) for the chunk's rows; selected (and NaN) rows drop
+// out.  Each block leaves its best (value, index) at part[r0 / 256 + block].
+template <typename CT>
+__global__ __launch_bounds__(256) void k_round_rsum(const CT* __restrict__ Tb, int64_t R,
                                                     int c, int64_t r0,
                                                     const int32_t* __restrict__ mask,
                                                     double* __restrict__ r_out,
@@ -581,13 +590,13 @@ __global__ __launch_bounds__(256) void k_round_rsum(const double* __restrict__ T
   double v = -INFINITY;
   int64_t idx = -1;
   if (i < R) {
-    double s = 0.0;
+    CT s = CT(0);
     for (int k = 0; k < c; ++k) s += Tb[(int64_t)k * R + i];
     const int64_t gi = r0 + i;
     const bool sel = mask[gi] != 0;
-    if (r_out) r_out[gi] = sel ? -INFINITY : s;
+    if (r_out) r_out[gi] = sel ? -INFINITY : (double)s;
     if (!sel && s == s) {
-      v = s;
+      v = (double)s;
       idx = gi;
     }
   }
@@ -655,7 +664,7 @@ __global__ __launch_bounds__(1024) void k_round_pick(const double* __restrict__ 
   }
 }
 
-// Line 8 for the row selected in round t, per class k: (H)_k += (H_o)_k / b + g x x^T and
+// The update for the row selected in round t, per class k: (H)_k += (H_o)_k / b + g x x^T and
 // C_k += O_k / b + g u u^T with u = L_k^-1 x; the Jacobi inputs of the round (C_k, and
 // E_k = C_k + O_k / b) are written padded to m x m; the row leaves the candidates.
 template <typename T>
@@ -728,12 +737,14 @@ struct Round {
   int64_t *pidx, *sel;
   int32_t *mask, *flags, *tiles;
   int ntiles, splits;
+  int fp32;                // decision precision FP32 (FIRAL_ROUND_FP32)
+  float *Wf, *wtsf;        // FP32 copies of W and the weights in that mode
 };
 
 static void free_round(Round* r) {
   void* bufs[] = {r->omega, r->Lf, r->Li, r->Ho, r->Ot, r->Cm, r->Hacc, r->JA, r->JV, r->JT, r->lam,
                   r->W, r->wts, r->Tb, r->pval, r->nu, r->smax, r->gpart, r->crit, r->pidx,
-                  r->sel, r->mask, r->flags, r->tiles};
+                  r->sel, r->mask, r->flags, r->tiles, r->Wf, r->wtsf};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete r;
@@ -779,34 +790,47 @@ static int round_operand(Round* r, const double* nu_p, hipStream_t st) {
   FIRAL_LAUNCHED();
   BGemm g{r->Li, dd, 1, d, r->JV, mm, m, 1, r->W, (int64_t)d * r->ldw, r->ldw, 1, d, d, d,
           INT_MAX, INT_MAX};
-  return bgemm(g, c, st);
+  FIRAL_CHECK(bgemm(g, c, st));
+  if (r->fp32) {
+    const int64_t nw = (int64_t)c * d * r->ldw, nt = (int64_t)c * r->ldw * 2;
+    k_to_f32<<<(unsigned)cdiv(nw, 256), 256, 0, st>>>(r->W, r->Wf, nw);
+    FIRAL_LAUNCHED();
+    k_to_f32<<<(unsigned)cdiv(nt, 256), 256, 0, st>>>(r->wts, r->wtsf, nt);
+    FIRAL_LAUNCHED();
+  }
+  return FIRAL_OK;
 }
 
 // scores of every pool row at the current state into r_out (if non-null) and the block
 // partials of the argmax
-template <typename T>
-static int round_score_t(Round* r, double* r_out, hipStream_t st) {
+template <typename T, typename CT>
+static int round_score_t(Round* r, const CT* W, const CT* wts, double* r_out, hipStream_t st) {
   const Ctx* x = r->x;
   const T* X = (const T*)x->X;
   const T* H = (const T*)x->H;
+  CT* Tb = (CT*)r->Tb;
   for (int64_t r0 = 0; r0 < r->n_pool; r0 += r->R) {
     const int64_t R = std::min<int64_t>(r->R, r->n_pool - r0);
     const int64_t nwg = cdiv(R, kScoreTM) * r->c;
     FIRAL_CHECK(prof_mark(r->x, st, true));
-    k_round_score<T><<<(unsigned)nwg, 256, 0, st>>>(X, H, r0, R, r->d, r->c, r->W, r->ldw, r->wts,
-                                                    r->eta, r->Tb);
+    k_round_score<T, CT><<<(unsigned)nwg, 256, 0, st>>>(X, H, r0, R, r->d, r->c, W, r->ldw, wts,
+                                                        r->eta, Tb);
     FIRAL_LAUNCHED();
     FIRAL_CHECK(prof_mark(r->x, st, false));
-    k_round_rsum<<<(unsigned)cdiv(R, 256), 256, 0, st>>>(r->Tb, R, r->c, r0, r->mask, r_out,
-                                                         r->pval, r->pidx);
+    k_round_rsum<CT><<<(unsigned)cdiv(R, 256), 256, 0, st>>>(Tb, R, r->c, r0, r->mask, r_out,
+                                                             r->pval, r->pidx);
     FIRAL_LAUNCHED();
   }
   return FIRAL_OK;
 }
 
 static int round_score(Round* r, double* r_out, hipStream_t st) {
-  if (r->x->prec == FIRAL_F64) return round_score_t<double>(r, r_out, st);
-  return round_score_t<float>(r, r_out, st);
+  const bool f64 = r->x->prec == FIRAL_F64;
+  if (r->fp32)
+    return f64 ? round_score_t<double, float>(r, r->Wf, r->wtsf, r_out, st)
+               : round_score_t<float, float>(r, r->Wf, r->wtsf, r_out, st);
+  return f64 ? round_score_t<double, double>(r, r->W, r->wts, r_out, st)
+             : round_score_t<float, double>(r, r->W, r->wts, r_out, st);
 }
 
 static int round_step_launch(Round* r, hipStream_t st) {
@@ -852,7 +876,8 @@ using namespace firal;
   } while (0)
 
 extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double* z,
-                                  double lambda, double eta, int32_t b, void* stream) {
+                                  double lambda, double eta, int32_t b, uint32_t flags,
+                                  void* stream) {
   RREQ(out != nullptr && ctx != nullptr && z != nullptr, "firal_round_create: null argument");
   *out = nullptr;
   Ctx* x = C(ctx);
@@ -861,6 +886,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   RREQ(b >= 1 && (int64_t)b <= x->n_pool, "firal_round_create: b = %d outside [1, n_pool]", b);
   RREQ(x->d <= kMaxD, "firal_round_create: d = %d above the Round step's limit %d", x->d, kMaxD);
   RREQ(x->c <= 30000, "firal_round_create: c = %d above the Round step's limit 30000", x->c);
+  RREQ((flags & ~FIRAL_ROUND_FP32) == 0, "firal_round_create: unknown flags 0x%x", flags);
   hipStream_t st = (hipStream_t)stream;
   FIRAL_HIP(hipSetDevice(x->device));
   Round* r = new Round();
@@ -874,6 +900,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   r->n_pool = x->n_pool;
   r->N = x->N;
   r->eta = eta;
+  r->fp32 = (flags & FIRAL_ROUND_FP32) != 0;
   const int d = r->d, c = r->c, m = r->m;
   // rows per scoring chunk: the class-term buffer c x R stays within 1 GiB
   const int64_t cap = std::max<int64_t>(256, (((int64_t)1 << 27) / c) / 256 * 256);
@@ -910,6 +937,10 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   RALLOC(r->crit, sizeof(double));
   RALLOC(r->gpart, sizeof(double) * r->splits * c * dd);
   RALLOC(r->tiles, sizeof(int32_t) * tiles.size());
+  if (r->fp32) {
+    RALLOC(r->Wf, sizeof(float) * c * d * r->ldw);
+    RALLOC(r->wtsf, sizeof(float) * c * r->ldw * 2);
+  }
 #undef RALLOC
   if (rc != FIRAL_OK) {
     free_round(r);
@@ -939,7 +970,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   k_fill_i64<<<(unsigned)cdiv(b, 256), 256, 0, st>>>(r->sel, b, -1);
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
   RCHK(fill(r->nu, 1, std::sqrt((double)d * c), st));
-  // line 3: Sigma_o blocks (rows weighted by [z ; 1], plus lambda I), factorised
+  // Sigma_o blocks (rows weighted by [z ; 1], plus lambda I), factorised
   k_round_omega<<<(unsigned)cdiv(r->N, 256), 256, 0, st>>>(z, r->n_pool, r->N, r->omega);
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
   RCHK(gram64_launch(x->prec, x->X, x->H, r->omega, r->N, d, c, r->tiles, r->ntiles, r->splits,

@@ -8,7 +8,7 @@ no preconditioner, no solver, no gradient), so the CPU oracle and the GPU
 path can both take their inputs from it without sharing any method code.
 
 The shapes follow the paper's workloads (Table 4 for the accuracy datasets,
-Section 5.2 for the ImageNet-1k scaling runs); the datasets themselves are
+Section 4.2 for the ImageNet-1k single-GPU runs); the datasets themselves are
 replaced by mixtures with the same n, d, c.  Every array is a deterministic
 function of the integer seed it is given.
 

@@ -1,13 +1,18 @@
 """Parity of the GPU diagonal Round step (Algorithm 3) with the FP64 oracle.
 
-Both sides decide the argmax in FP64 (the GPU reads FP32 storage exactly; the oracle gets
-the same FP32 values).  Per case:
-* the GPU's selection sequence equals the oracle's own run (index work: exact);
-* teacher forcing: the oracle is advanced with the GPU's picks, and each pick must attain the
-  oracle's maximum (within 1e-9 of it, relative), with nu_{t+1} and the winning objective
-  equal to 1e-9 relative;
-* the objective of every pool row (firal_round_scores) against the oracle's, normwise 1e-9,
-  before the first round and after the last checked one;
+Default mode: both sides decide the argmax in FP64 (the GPU reads FP32 storage exactly; the
+oracle gets the same FP32 values).  FP32 mode (FIRAL_ROUND_FP32, the precision of the paper's
+implementation): both sides evaluate the objective and take the argmax in FP32 while the block
+state stays FP64; the two FP32 evaluations round differently (each rounds its own d-term
+products and its FP32 copy of B^-1 or W: about u32 kappa sqrt(d), u32 = 6e-8), so objectives
+agree to 1e-4 normwise and a pick may differ from the oracle's only in a round whose two best
+objectives are within 1e-4 of each other (either row is then a valid maximiser).  Per case:
+* teacher forcing: the oracle is advanced with the GPU's picks; in FP64 each pick must be the
+  oracle's own argmax (index work: exact, so the whole sequence equals the oracle's run), in
+  FP32 it must attain the oracle's maximum within 1e-4; nu_{t+1} (FP64 state in both modes)
+  to 1e-9 and the winning objective to the mode's tolerance;
+* the objective of every pool row (firal_round_scores) against the oracle's, normwise 1e-9
+  (FP32 mode: 1e-4), before the first round and after the last checked one;
 * the eta criterion min_k lambda_min((H)_k) to 1e-8.
 Shapes span several scoring tiles and a ragged tail, odd d (a padding index in the Jacobi
 solves), no labeled rows, c = 2, d = 1 and the whole pool selected; configuration 2 at its
@@ -44,38 +49,43 @@ def relerr(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def check_run(p, prec, b, eta, rounds=None, lam=1e-3, score_every=False):
+TOL32 = 1e-4
+
+
+def check_run(p, prec, b, eta, rounds=None, lam=1e-3, fp32=False):
     ctx, z, zn, Xo, Ho = setup(p, prec, b)
-    rs = RoundSolver(ctx, z, lam, eta, b)
-    st = orr.DiagonalRound(Xo, Ho, p.n_pool, zn, lam, eta, b)
+    rs = RoundSolver(ctx, z, lam, eta, b, fp32=fp32)
+    st = orr.DiagonalRound(Xo, Ho, p.n_pool, zn, lam, eta, b, fp32=fp32)
+    tol = TOL32 if fp32 else TOL
     nr = b if rounds is None else rounds
     g0 = rs.scores().cpu().numpy()
-    assert relerr(g0, st.scores()) <= TOL
+    assert relerr(g0, st.scores()) <= tol
     rs.step(nr)
     res = rs.result()
     assert res["t"] == nr
     sel = res["selected"]
     assert len(set(sel.tolist())) == nr and sel.min() >= 0 and sel.max() < p.n_pool
     # teacher-forced validity, nu and the winning objective
-    own = []
     for t in range(nr):
         r = st.scores()
         i_or = st.argmax(r)
-        own.append(i_or)
         i = int(sel[t])
         best = r[i_or]
-        assert r[i] >= best - TOL * abs(best), (t, i, i_or, r[i], best)
-        assert abs(res["score_max"][t] - r[i]) <= TOL * abs(r[i]), t
+        assert r[i] >= best - tol * abs(best), (t, i, i_or, r[i], best)
+        if i != i_or:
+            # only a near-tie may resolve differently, and never in FP64
+            assert fp32, ("selection", t, i, i_or)
+        assert abs(res["score_max"][t] - r[i]) <= tol * abs(r[i]), t
         st.step(i)
+        # the block state is FP64 in both modes
         assert abs(res["nu"][t + 1] - st.nu) <= TOL * abs(st.nu), (t, res["nu"][t + 1], st.nu)
-    assert np.array_equal(sel, np.array(own)), "selection sequence"
     assert res["nu"][0] == pytest.approx(np.sqrt(p.d * p.c), rel=1e-15)
     if nr < b:
         g1 = rs.scores().cpu().numpy()
         r1 = st.scores()
         m = st.available
         assert np.all(np.isneginf(g1[~m]))
-        assert relerr(g1[m], r1[m]) <= TOL
+        assert relerr(g1[m], r1[m]) <= tol
     crit = rs.criterion()
     assert crit == pytest.approx(st.criterion(), rel=1e-8, abs=1e-12)
     rs.close()
@@ -117,6 +127,19 @@ def test_round_selects_whole_pool():
 def test_round_configuration_2_full_size():
     p = make_problem(2)
     check_run(p, "f32", b=100, eta=50.0, rounds=4)
+
+
+@pytest.mark.parametrize("shape", [SMALL[1], SMALL[3], SMALL[5]])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_round_fp32_decision_matches_oracle(shape, prec):
+    n, nl, d, c, seed = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=seed)
+    check_run(p, prec, b=12, eta=10.0, fp32=True)
+
+
+def test_round_fp32_decision_configuration_2_full_size():
+    p = make_problem(2)
+    check_run(p, "f32", b=100, eta=50.0, rounds=4, fp32=True)
 
 
 def test_round_reduced_configuration_3_shape():

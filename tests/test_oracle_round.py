@@ -128,3 +128,20 @@ def test_round_invariants_and_eta_sweep():
     # the whole pool, one round each: every row is taken exactly once
     full = orr.round_diag(p.X, p.H, p.n_pool, z, 1e-3, 2.0, p.n_pool)
     assert sorted(full["selected"].tolist()) == list(range(p.n_pool))
+
+
+def test_float32_decision_follows_the_float64_one_up_to_rounding():
+    # the float32 objective differs from the float64 one by float32 rounding only, and the
+    # float32 argmax of a well-separated round is the float64 one
+    p, z = problem(n=60, n_lab=4, d=5, c=3, seed=31)
+    st64 = orr.DiagonalRound(p.X, p.H, p.n_pool, z, 1e-3, 4.0, 6)
+    st32 = orr.DiagonalRound(p.X, p.H, p.n_pool, z, 1e-3, 4.0, 6, fp32=True)
+    for _ in range(6):
+        r64, r32 = st64.scores(), st32.scores()
+        assert np.linalg.norm(r32 - r64) <= 1e-5 * np.linalg.norm(r64)
+        top = np.sort(r64[st64.available])[::-1]
+        if top[0] - top[1] > 1e-4 * top[0]:
+            assert st32.argmax(r32) == st64.argmax(r64)
+        i = st64.argmax(r64)
+        st64.step(i)
+        st32.step(i)
