@@ -57,6 +57,11 @@ def parse():
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5])
     ap.add_argument("--no-round", action="store_true", help="skip the Round-step leg")
+    ap.add_argument("--round-rounds", type=int, default=2,
+                    help="configurations 3/4: Round-step rounds timed per decision precision "
+                         "(0 skips the Round leg)")
+    ap.add_argument("--round-only", action="store_true",
+                    help="configurations 3/4: only the Round-step leg")
     ap.add_argument("--eta", type=float, default=None,
                     help="Round-step learning rate (default 8 sqrt(dc), the theorem's value at "
                          "epsilon = 1)")
@@ -193,9 +198,8 @@ def round_leg(p, w, eta, fp32, cpu_rounds=2):
     res = rs.result()
     elapsed = time.perf_counter() - t0
     k_ms, k_n = ctx.profile_end()
-    ldw = -(-p.d // 16) * 16
-    flops = 2.0 * p.n_pool * p.c * p.d * p.d     # y = W_k^T x for every pool row and class
-    t_kern = k_ms / 1e3 / max(k_n, 1)
+    flops = 2.0 * p.n_pool * p.c * p.d * p.d     # algorithmic: one d x d product per class
+    t_kern = k_ms / 1e3 / b                      # the round's scoring launches
     rs.close()
     ctx.close()
     # the oracle on the host: the first rounds of the same solve
@@ -210,8 +214,10 @@ def round_leg(p, w, eta, fp32, cpu_rounds=2):
     t_cpu = (time.perf_counter() - tc) / cpu_rounds
     same = [int(i) for i in st.selected] == [int(i) for i in res["selected"][:cpu_rounds]]
     pk = PEAK["f32" if fp32 else "f64"]
-    kname = ("k_round_score<float, float> (per-point objective, FP32 MFMA)" if fp32 else
-             "k_round_score<float, double> (per-point objective, FP64 MFMA)")
+    kname = ("k_round_score<float, float> (per-point objective, FP32 MFMA; achieved counts "
+             "2 n c d^2 per round)" if fp32 else
+             "k_round_score<float, double> (per-point objective, FP64 MFMA; achieved counts "
+             "2 n c d^2 per round)")
     return {"decision": "fp32" if fp32 else "fp64", "rounds": res["t"], "eta": eta,
             "ms_per_point": 1e3 * elapsed / b,
             "points_per_s": b / elapsed, "setup_ms": 1e3 * t_setup,
@@ -220,7 +226,7 @@ def round_leg(p, w, eta, fp32, cpu_rounds=2):
                          "achieved": flops / t_kern / 1e12, "peak": pk,
                          "unit": "TFLOP/s", "frac": flops / t_kern / 1e12 / pk,
                          "kernel_us": t_kern * 1e6, "traffic": None,
-                         "padded_columns": ldw},
+                         "executed_tflops": 1.5 * flops / t_kern / 1e12},
             "cpu_oracle": {"s_per_round": t_cpu, "rounds_timed": cpu_rounds,
                            "same_first_selections": same}}
 
@@ -252,6 +258,41 @@ def hvp_timing(ctx, p, reps):
     return t_call, k_ms / 1e3 / max(k_n, 1)
 
 
+def round_large(p, z, eta, rounds, fp32):
+    """The Round step on a large workload: set-up, then `rounds` rounds after one untimed
+    round, from the relaxed weights z (FP32 context; decision precision FP32 or FP64)."""
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, RoundSolver
+    ctx = RelaxContext(p.X.contiguous(), p.H.contiguous(), p.n_pool, 1, "f32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = RoundSolver(ctx, z, p.lam, eta, int(p.b), fp32=fp32)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    rs.step(1)
+    rs.result()
+    ctx.profile_begin()
+    t0 = time.perf_counter()
+    rs.step(rounds)
+    res = rs.result()
+    elapsed = time.perf_counter() - t0
+    k_ms, k_n = ctx.profile_end()
+    t_kern = k_ms / 1e3 / rounds               # the round's scoring launches (row chunks)
+    flops = 2.0 * p.n_pool * p.c * p.d * p.d   # algorithmic: one d x d product per class
+    executed = 1.5 * flops                     # u = L^-1 x (triangular) and v = D^-1 L^-1 x
+    pk = PEAK["f32" if fp32 else "f64"]
+    rs.close()
+    ctx.close()
+    return {"decision": "fp32" if fp32 else "fp64", "eta": eta, "rounds_timed": rounds,
+            "setup_s": t_setup, "s_per_point": elapsed / rounds,
+            "score_s_per_round": t_kern, "score_launches_per_round": k_n // rounds,
+            "score_tflops": flops / t_kern / 1e12,
+            "score_frac_of_peak": flops / t_kern / 1e12 / pk,
+            "score_executed_tflops": executed / t_kern / 1e12,
+            "selected": [int(i) for i in res["selected"]]}
+
+
 def large_workload(args):
     """Configurations 3 and 4: FP32 and bf16x3 legs plus the FP64 reference gradient."""
     import numpy as np
@@ -271,6 +312,24 @@ def large_workload(args):
         g.manual_seed(3003)
         e = -torch.log(torch.rand(p.n_pool, generator=g, device="cuda:0", dtype=torch.float64))
         z = p.b * e / e.sum()
+    if cfg == 4:   # relaxed weights for the Round leg
+        g = torch.Generator(device="cuda:0")
+        g.manual_seed(3004)
+        e = -torch.log(torch.rand(p.n_pool, generator=g, device="cuda:0", dtype=torch.float64))
+        z = p.b * e / e.sum()
+    eta = 8.0 * (p.d * p.c) ** 0.5
+    rounds = {}
+    if args.round_rounds > 0:
+        for fp32 in (True, False):
+            log(f"Round step, {'FP32' if fp32 else 'FP64'} decision")
+            rounds["fp32_decision" if fp32 else "fp64_decision"] = round_large(
+                p, z, eta, args.round_rounds, fp32)
+            torch.cuda.empty_cache()
+    if args.round_only:
+        print(json.dumps({"workload": f"configuration {cfg}", "round_step": rounds,
+                          "config": {"n_pool": p.n_pool, "n_lab": p.n_lab, "d": p.d, "c": p.c,
+                                     "b": p.b, "z": "b x Dirichlet(1), drawn on the GPU"}}))
+        return
     V = None
     legs, grads = {}, {}
     n_cg_err = 10
@@ -325,6 +384,8 @@ def large_workload(args):
                                 "frac": legs["bf16x3"]["kernel_tflops"] / PEAK["bf16x3"]},
                      "unit": "TFLOP/s"},
     }
+    if rounds:
+        res["round_step"] = rounds
     print(json.dumps(res))
 
 

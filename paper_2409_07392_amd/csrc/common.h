@@ -280,9 +280,11 @@ void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits)
 int gram64_launch(int prec, const void* X, const void* H, const double* omega, int64_t N, int d,
                   int c, const int32_t* tiles, int ntiles, int S, double shift, double* part,
                   double* out, hipStream_t st);
-// In-place Cholesky of c SPD blocks (lower factor, upper zeroed); for d <= 256 the blocks'
-// inverses go to Pinv.  *bad (preset to INT32_MAX) receives the smallest failing block.
-int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, hipStream_t st);
+// In-place Cholesky of c SPD blocks (lower factor, upper zeroed); the blocks' inverses go to
+// Pinv (for d > 256 only when want_inv).  *bad (preset to INT32_MAX) receives the smallest
+// failing block.
+int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool want_inv,
+                       hipStream_t st);
 int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,
                void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
                hipStream_t st);

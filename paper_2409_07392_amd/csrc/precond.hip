@@ -430,7 +430,8 @@ void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits)
                                                         mem_cap));
 }
 
-int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, hipStream_t st) {
+int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool want_inv,
+                       hipStream_t st) {
   int threads = 0;
   SweepKernel sw = pick_sweep(d, &threads);
   if (sw) {
@@ -439,6 +440,10 @@ int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, hipS
   } else {
     k_chol<<<c, 256, 0, st>>>(P, d, bad);
     FIRAL_LAUNCHED();
+    if (want_inv) {
+      k_chol_inv<<<c, 256, 0, st>>>(P, Pinv, d, bad);
+      FIRAL_LAUNCHED();
+    }
   }
   return FIRAL_OK;
 }

@@ -3,21 +3,20 @@
 // Every d x d quantity is block diagonal with c blocks.  With Sigma_k = L_k L_k^T (the blocks
 // of Sigma at the relaxed weights z_o, regulariser included), the round-t matrix
 //   B_k = nu Sigma_k + eta (H)_k + (eta / b) (H_o)_k = L_k D_k L_k^T,
-//   D_k = nu I + eta E_k,   E_k = L_k^-1 ((H)_k + (H_o)_k / b) L_k^-T = Q_k Lambda_k Q_k^T.
+//   D_k = nu I + eta (C_k + O_k / b),   C_k = L_k^-1 (H)_k L_k^-T,   O_k = L_k^-1 (H_o)_k L_k^-T.
 // The per-point objective of the Section 3.2 proposition needs, for every pool row x and class
-// k, q1 = x^T B_k^-1 x and q2 = x^T B_k^-1 Sigma_k B_k^-1 x.  With y = Q_k^T L_k^-1 x both are
-// weighted sums of squares of one vector,
-//   q1 = sum_j y_j^2 / (nu + eta lambda_kj),   q2 = sum_j y_j^2 / (nu + eta lambda_kj)^2,
-// so one product per class, Y_k = X W_k with W_k = L_k^-T Q_k, scores every row; the
-// product's epilogue forms the sums and the class term g q2 / (1 + eta g q1) (g = h(1 - h))
-// without writing Y.  The eigenvalues of (H~)_k that fix nu are those of C_k = L_k^-1 (H)_k
-// L_k^-T, which is similar to Sigma_k^-1/2 (H)_k Sigma_k^-1/2.
+// k, q1 = x^T B_k^-1 x and q2 = x^T B_k^-1 Sigma_k B_k^-1 x.  With u = L_k^-1 x and
+// v = D_k^-1 u they are q1 = u . v and q2 = v . v, so one product per class,
+// [u | v] = x^T [L_k^-T | (D_k^-1 L_k^-1)^T], scores every row (the L^-T half is triangular:
+// its zero stages are skipped); the product's epilogue forms u . v, v . v and the class term
+// g q2 / (1 + eta g q1) (g = h (1 - h)) without writing u or v.  The eigenvalues of
+// (H~)_k = Sigma_k^-1/2 (H)_k Sigma_k^-1/2 that fix nu are those of C_k (similar matrices).
 //
-// A round: score (FP64 MFMA) -> sum over classes and argmax over the unselected rows (fixed
-// order, lowest index on ties) -> update of C, (H) and the selection mask -> Jacobi
-// eigensolves of C (values) and E (values and vectors) -> nu_{t+1} (safeguarded Newton on
-// Tr((nu I + eta C)^-2) = 1) -> W and the weights of round t + 1.  All state stays on the
-// device and nothing is read back.
+// A round: score (MFMA) -> sum over classes and argmax over the unselected rows (fixed order,
+// lowest index on ties) -> update of C, (H) and the selection mask -> eigenvalues of C
+// (Householder tridiagonalisation, then bisection on Sturm counts) -> nu_{t+1} (safeguarded
+// Newton on Tr((nu I + eta C)^-2) = 1) -> D, its inverse (FP64 Cholesky) and the operand of
+// round t + 1.  All state stays on the device and nothing is read back.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -29,8 +28,11 @@ namespace firal {
 
 namespace {
 
-constexpr int kMaxD = 512;          // d limit of the Round step (Jacobi pair tables, LDS rows)
+constexpr int kMaxD = 512;          // d limit of the Round step (LDS rows of the update)
 constexpr int kScoreTM = 64, kScoreTN = 64, kScoreTK = 16, kScorePad = 4;
+constexpr int kTriThreads = 512;
+// tridiagonalisation in LDS up to this d (d^2 doubles), in global memory above
+constexpr int kTriSmemD = 128;
 
 __device__ __forceinline__ int64_t xcd_lid_r(int64_t b, int64_t n) {
   const int64_t q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
@@ -87,7 +89,6 @@ struct BGemm {
   int64_t sC;
   int64_t ci, cj;
   int M, N, K;
-  int amod, bmod;   // batch k reads A block k % amod and B block k % bmod
 };
 
 __global__ __launch_bounds__(256) void k_bgemm(BGemm g) {
@@ -96,8 +97,8 @@ __global__ __launch_bounds__(256) void k_bgemm(BGemm g) {
   const int ti = blockIdx.x / tiles_n, tj = blockIdx.x % tiles_n;
   const int64_t k = blockIdx.y;
   const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  const double* A = g.A + (k % g.amod) * g.sA;
-  const double* B = g.B + (k % g.bmod) * g.sB;
+  const double* A = g.A + k * g.sA;
+  const double* B = g.B + k * g.sB;
   double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   for (int p0 = 0; p0 < g.K; p0 += 32) {
     for (int e = threadIdx.x; e < 1024; e += 256) {
@@ -129,242 +130,165 @@ __global__ __launch_bounds__(256) void k_bgemm(BGemm g) {
     }
 }
 
-// dst_k (m x m, zero padding beyond d) = sa * A_k + sb * B_k (d x d each; A or B may be null)
-__global__ void k_pad_comb(const double* __restrict__ A, double sa, const double* __restrict__ B,
-                           double sb, double* __restrict__ dst, int d, int m, int c) {
+// transposed copy of the c blocks L^-1 into the operand's u half: W_k[a][j] = Li_k[j][a]
+__global__ void k_put_lit(const double* __restrict__ Li, int d, int c, int ldw,
+                          double* __restrict__ W) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t mm = (int64_t)m * m;
-  if (e >= (int64_t)c * mm) return;
-  const int64_t k = e / mm;
-  const int r = (int)(e - k * mm);
-  const int i = r / m, j = r - (r / m) * m;
-  double v = 0.0;
-  if (i < d && j < d) {
-    const int64_t s = k * d * d + (int64_t)i * d + j;
-    if (A) v += sa * A[s];
-    if (B) v += sb * B[s];
-  }
-  dst[e] = v;
+  const int64_t dd = (int64_t)d * d;
+  if (e >= (int64_t)c * dd) return;
+  const int64_t k = e / dd;
+  const int r = (int)(e - k * dd);
+  const int a = r / d, j = r - (r / d) * d;
+  W[(k * d + a) * ldw + j] = Li[k * dd + (int64_t)j * d + a];
 }
 
-// ------------------------------------------------------------------ Jacobi eigensolver
-// Cyclic two-sided Jacobi on symmetric m x m blocks (m even; a padding index d = m - 1 when d
-// is odd never rotates).  Each sweep visits every pair once in m - 1 steps of m/2 disjoint
-// pairs (round-robin: step r pairs (r, m-1) and ((r+p) mod (m-1), (r-p) mod (m-1)),
-// p = 1..m/2-1).  A step computes each pair's rotation (c, s) zeroing a_pq (Golub & Van Loan,
-// sym.schur2: tau = (a_qq - a_pp) / 2 a_pq, t = sign(tau) / (|tau| + sqrt(1 + tau^2))), then
-// applies J^T A J block by block: each 2 x 2 block of rows of pair P and columns of pair R is
-// computed once and written together with its transpose, so A stays exactly symmetric.
-// Off-diagonal entries at or below 2.3e-16 ||A||_F (FP64 unit roundoff of the block's norm,
-// evaluated at the start of each sweep) are zeroed without a rotation.  Sweeps
-// stop once ||offdiag(A)||_F <= tol ||diag(A)||_2 (checked before each sweep), after a sweep
-// without rotations, or after max_sweeps.  Blocks [0, n_vals) return eigenvalues only; later blocks also accumulate
-// V <- V J (V starts at I; its columns are the eigenvectors).  SMEM: A (and V) are held in
-// LDS for the whole solve.
-template <bool SMEM, int NT>
-__global__ __launch_bounds__(NT) void k_jacobi(double* __restrict__ A_all,
-                                               double* __restrict__ V_all,
-                                               double* __restrict__ lam_all, int m, int d,
-                                               int n_vals, int v_given, int max_sweeps,
-                                               double tol) {
-  constexpr int kHalf = SMEM ? 64 : kMaxD / 2;
+// ------------------------------------------------------------------ eigenvalues
+// Householder tridiagonalisation of each symmetric d x d block (Golub & Van Loan, Alg. 8.3.1):
+// step j maps column j below the diagonal onto its first entry with P = I - beta v v^T and
+// applies P A P to the trailing block as A - v w^T - w v^T with p = beta A v,
+// w = p - (beta/2)(p . v) v.  The block is destroyed; diag[j] = a_jj, off[j] = a_{j+1,j} of
+// the tridiagonal.  One workgroup per block; SMEM: the block is held in LDS.
+template <bool SMEM>
+__global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_all, int d,
+                                                          double* __restrict__ diag,
+                                                          double* __restrict__ off) {
   extern __shared__ double dyn[];
-  __shared__ double cs[kHalf], sn[kHalf], tn[kHalf];
-  __shared__ int pp[kHalf], qq[kHalf], act[kHalf];
-  __shared__ double stat[2];
-  __shared__ int any_rot;
-  int prev_rot = 1;
+  __shared__ double v[kMaxD], p[kMaxD];
+  __shared__ double bc[2];
   const int blk = blockIdx.x, tid = threadIdx.x;
-  const bool vecs = blk >= n_vals;
-  const int mm = m * m;
-  double* Ag = A_all + (int64_t)blk * mm;
-  double* Vg = vecs ? V_all + (int64_t)(blk - n_vals) * mm : nullptr;
-  double* A = Ag;
-  double* V = Vg;
+  const int64_t dd = (int64_t)d * d;
+  double* Ag = A_all + (int64_t)blk * dd;
+  double* A = SMEM ? dyn : Ag;
   if (SMEM) {
-    A = dyn;
-    V = vecs ? dyn + mm : nullptr;
-    for (int e = tid; e < mm; e += NT) A[e] = Ag[e];
+    for (int e = tid; e < d * d; e += kTriThreads) A[e] = Ag[e];
+    __syncthreads();
   }
-  if (vecs) {
-    if (v_given) {
-      if (SMEM)
-        for (int e = tid; e < mm; e += NT) V[e] = Vg[e];
-    } else {
-      for (int e = tid; e < mm; e += NT) V[e] = (e / m == e % m) ? 1.0 : 0.0;
+  double* dg = diag + (int64_t)blk * d;
+  double* of = off + (int64_t)blk * d;
+  for (int j = 0; j + 2 < d; ++j) {
+    const int r0 = j + 1, n2 = d - r0;   // trailing rows/columns r0 .. d-1
+    // sigma = sum of squares below the subdiagonal entry
+    double sg = 0.0;
+    for (int i = 1 + tid; i < n2; i += kTriThreads) {
+      const double x = A[(int64_t)(r0 + i) * d + j];
+      sg += x * x;
     }
+    sg = block_sum<kTriThreads>(sg);
+    if (tid == 0) bc[0] = sg;
+    __syncthreads();
+    sg = bc[0];
+    const double x0 = A[(int64_t)r0 * d + j];
+    if (tid == 0) dg[j] = A[(int64_t)j * d + j];
+    if (sg == 0.0) {          // already tridiagonal in this column
+      if (tid == 0) of[j] = x0;
+      __syncthreads();
+      continue;
+    }
+    const double nx = sqrt(x0 * x0 + sg);
+    const double alpha = x0 >= 0.0 ? -nx : nx;
+    const double v0 = x0 - alpha;
+    const double beta = 2.0 / (v0 * v0 + sg);
+    for (int i = tid; i < n2; i += kTriThreads) v[i] = i == 0 ? v0 : A[(int64_t)(r0 + i) * d + j];
+    if (tid == 0) of[j] = alpha;
+    __syncthreads();
+    // p = beta A_sub v (by columns of the symmetric block: consecutive threads, consecutive
+    // addresses), then K = (beta / 2) p . v
+    double pv = 0.0;
+    for (int i = tid; i < n2; i += kTriThreads) {
+      double acc = 0.0;
+      for (int q = 0; q < n2; ++q) acc = fma(A[(int64_t)(r0 + q) * d + r0 + i], v[q], acc);
+      p[i] = beta * acc;
+      pv += beta * acc * v[i];
+    }
+    pv = block_sum<kTriThreads>(pv);
+    if (tid == 0) bc[1] = 0.5 * beta * pv;
+    __syncthreads();
+    const double K = bc[1];
+    for (int i = tid; i < n2; i += kTriThreads) p[i] = p[i] - K * v[i];   // p := w
+    __syncthreads();
+    for (int e = tid; e < n2 * n2; e += kTriThreads) {
+      const int i = e / n2, q = e - (e / n2) * n2;
+      double* a = A + (int64_t)(r0 + i) * d + r0 + q;
+      *a = *a - v[i] * p[q] - p[i] * v[q];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (d >= 2) {
+      dg[d - 2] = A[(int64_t)(d - 2) * d + d - 2];
+      of[d - 2] = A[(int64_t)(d - 1) * d + d - 2];
+    }
+    dg[d - 1] = A[(int64_t)(d - 1) * d + d - 1];
+    of[d - 1] = 0.0;
+  }
+}
+
+// Eigenvalues of each tridiagonal (diag a, off-diagonal e) by bisection on Sturm counts: the
+// number of negative pivots of the LDL^T factorisation of T - x I is the number of eigenvalues
+// below x; eigenvalue j is bracketed by Gershgorin's bounds and bisected until the bracket
+// stops shrinking (one thread per eigenvalue).  Pivots smaller than pivmin are replaced by
+// -pivmin (LAPACK's safeguard).
+__global__ __launch_bounds__(256) void k_sturm(const double* __restrict__ diag,
+                                               const double* __restrict__ off, int d,
+                                               double* __restrict__ lam) {
+  __shared__ double a[kMaxD], e2[kMaxD];
+  __shared__ double bnd[3];
+  const int blk = blockIdx.x, tid = threadIdx.x;
+  const double* dg = diag + (int64_t)blk * d;
+  const double* of = off + (int64_t)blk * d;
+  double lo = INFINITY, hi = -INFINITY, emax = 0.0;
+  for (int i = tid; i < d; i += blockDim.x) {
+    a[i] = dg[i];
+    const double el = i > 0 ? fabs(of[i - 1]) : 0.0, er = i + 1 < d ? fabs(of[i]) : 0.0;
+    e2[i] = i + 1 < d ? of[i] * of[i] : 0.0;
+    lo = fmin(lo, dg[i] - el - er);
+    hi = fmax(hi, dg[i] + el + er);
+    emax = fmax(emax, er * er);
+  }
+  lo = -block_max<256>(-lo);
+  hi = block_max<256>(hi);
+  emax = block_max<256>(emax);
+  if (tid == 0) {
+    bnd[0] = lo;
+    bnd[1] = hi;
+    bnd[2] = 2.2250738585072014e-308 * fmax(1.0, emax);
   }
   __syncthreads();
-  const int nb = m / 2, M = m - 1, half = nb / 2;
-  // thread -> (pair myP, lane myq of stride nth): it updates the 2 x 2 blocks (myP, myP + dl)
-  // for dl = myq, myq + nth, ... <= half, and rows myq, myq + nth, ... of V's two columns of
-  // pair myP, loading the pair's rotation once
-  const int nth = NT / nb;
-  const int myP = tid % nb, myq = tid / nb;
-  const bool worker = myq < nth;
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0, dg = 0.0;
-    for (int i = wave; i < m; i += NT / 64)
-      for (int j = lane; j < m; j += 64) {
-        const double v = A[i * m + j];
-        if (i == j) dg += v * v;
-        else off += v * v;
+  const double L0 = bnd[0], H0 = bnd[1], pivmin = bnd[2];
+  const double slack = 2.3e-16 * fmax(fabs(L0), fabs(H0)) + pivmin;
+  for (int j = tid; j < d; j += blockDim.x) {
+    double l = L0 - slack, u = H0 + slack;
+    for (int it = 0; it < 200; ++it) {
+      const double x = 0.5 * (l + u);
+      if (!(x > l && x < u)) break;
+      int cnt = 0;
+      double q = a[0] - x;
+      if (fabs(q) < pivmin) q = -pivmin;
+      cnt += q < 0.0;
+      for (int i = 1; i < d; ++i) {
+        q = (a[i] - x) - e2[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        cnt += q < 0.0;
       }
-    off = block_sum<NT>(off);
-    dg = block_sum<NT>(dg);
-    if (tid == 0) {
-      stat[0] = off;
-      stat[1] = dg;
-      any_rot = 0;
+      if (cnt > j) u = x;
+      else l = x;
     }
-    __syncthreads();
-    const bool conv = stat[0] <= tol * tol * stat[1] || (sweep > 0 && prev_rot == 0);
-    // entries at the rounding level of the whole block are zeroed, not rotated: in a degenerate
-    // eigenspace (the zero eigenvalues of a rank-deficient block) rotations would only stir
-    // that noise and the sweeps would not settle
-    const double thr = 2.3e-16 * sqrt(stat[0] + stat[1]);
-    __syncthreads();
-    if (conv) break;
-    for (int r = 0; r < M; ++r) {
-      if (tid < nb) {
-        const int P = tid;
-        int p, q;
-        if (P == 0) {
-          p = r;
-          q = M;
-        } else {
-          p = r + P;
-          if (p >= M) p -= M;
-          q = r - P;
-          if (q < 0) q += M;
-        }
-        if (p > q) {
-          const int tmp = p;
-          p = q;
-          q = tmp;
-        }
-        double c = 1.0, s = 0.0, t = 0.0;
-        const double apq = A[p * m + q];
-        const double app = A[p * m + p], aqq = A[q * m + q];
-        int rot = 0;
-        if (q < d && fabs(apq) > thr) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-          any_rot = 1;
-          rot = 1;
-        }
-        pp[P] = p;
-        qq[P] = q;
-        cs[P] = c;
-        sn[P] = s;
-        tn[P] = t;
-        // 2: rotates; 1: only zeroes a_pq; 0: nothing to do
-        act[P] = rot ? 2 : (apq != 0.0 ? 1 : 0);
-      }
-      __syncthreads();
-      if (worker) {
-        const int P = myP;
-        const int aP = act[P], p = pp[P], q = qq[P];
-        const double cP = cs[P], sP = sn[P];
-        double* Ap = A + p * m;
-        double* Aq = A + q * m;
-        for (int dl = myq; dl <= half; dl += nth) {
-          if ((nb & 1) == 0 && dl == half && P >= half) continue;
-          if (dl == 0) {
-            if (aP == 0) continue;
-            const double apq = Ap[q], t = tn[P];
-            Ap[p] = Ap[p] - t * apq;
-            Aq[q] = Aq[q] + t * apq;
-            Ap[q] = 0.0;
-            Aq[p] = 0.0;
-            continue;
-          }
-          int R = P + dl;
-          if (R >= nb) R -= nb;
-          if (aP < 2 && act[R] < 2) continue;   // both rotations are the identity
-          const int r0 = pp[R], s0 = qq[R];
-          const double cR = cs[R], sR = sn[R];
-          const double a00 = Ap[r0], a01 = Ap[s0], a10 = Aq[r0], a11 = Aq[s0];
-          const double b00 = cP * a00 - sP * a10, b01 = cP * a01 - sP * a11;
-          const double b10 = sP * a00 + cP * a10, b11 = sP * a01 + cP * a11;
-          const double e00 = cR * b00 - sR * b01, e01 = sR * b00 + cR * b01;
-          const double e10 = cR * b10 - sR * b11, e11 = sR * b10 + cR * b11;
-          Ap[r0] = e00;
-          Ap[s0] = e01;
-          Aq[r0] = e10;
-          Aq[s0] = e11;
-          A[r0 * m + p] = e00;
-          A[s0 * m + p] = e01;
-          A[r0 * m + q] = e10;
-          A[s0 * m + q] = e11;
-        }
-        if (vecs && aP == 2) {
-#pragma unroll 4
-          for (int i = myq; i < m; i += nth) {
-            double* Vi = V + i * m;
-            const double v0 = Vi[p], v1 = Vi[q];
-            Vi[p] = cP * v0 - sP * v1;
-            Vi[q] = sP * v0 + cP * v1;
-          }
-        }
-      }
-      __syncthreads();
-    }
-    prev_rot = any_rot;
+    lam[(int64_t)blk * d + j] = 0.5 * (l + u);
   }
-  for (int i = tid; i < m; i += NT) lam_all[(int64_t)blk * m + i] = A[i * m + i];
-  if (SMEM && vecs)
-    for (int e = tid; e < mm; e += NT) Vg[e] = V[e];
 }
 
-size_t jacobi_smem_bytes(int m, bool vecs) { return (size_t)(vecs ? 2 : 1) * m * m * sizeof(double); }
-// LDS per workgroup is 160 KiB; the kernel's static arrays (pair tables, reduction slots) take
-// 2356 bytes when the blocks are held in LDS.
-constexpr size_t kJacobiSmemMax = 160 * 1024 - 2560;
-
-// Jacobi on n_vals value-only blocks followed by n_vec blocks with vectors (A_all holds them in
-// that order; V_all the n_vec vector blocks).
-int jacobi_launch(double* A_all, double* V_all, double* lam, int m, int d, int n_vals, int n_vec,
-                  int v_given, hipStream_t st) {
-  const int nblk = n_vals + n_vec;
-  if (nblk == 0) return FIRAL_OK;
-  const size_t smem = jacobi_smem_bytes(m, n_vec > 0);
-  const int max_sweeps = 40;
-  const double tol = 1e-14;
-  if (smem <= kJacobiSmemMax && m / 2 <= 64) {
-    static bool attr = false;
-    if (!attr) {
-      FIRAL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi<true, 1024>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)kJacobiSmemMax));
-      attr = true;
-    }
-    k_jacobi<true, 1024><<<nblk, 1024, smem, st>>>(A_all, V_all, lam, m, d, n_vals, v_given,
-                                                   max_sweeps, tol);
-  } else {
-    k_jacobi<false, 512><<<nblk, 512, 0, st>>>(A_all, V_all, lam, m, d, n_vals, v_given,
-                                               max_sweeps, tol);
-  }
-  FIRAL_LAUNCHED();
-  return FIRAL_OK;
-}
-
-// ------------------------------------------------------------------ nu and weights
+// ------------------------------------------------------------------ nu
 // nu_{t+1}: the root of phi(nu) = sum_kj (nu + eta lam_kj)^-2 = 1 on
 // [1 - eta lam_min, sqrt(cd) - eta lam_min] (phi decreases there from >= 1 to <= 1).
 // Newton steps on phi^-1/2 - 1 (close to linear in nu), replaced by bisection whenever they
 // leave the bracket; stops when the bracket or the step vanishes.  One workgroup.
-__global__ __launch_bounds__(1024) void k_round_nu(const double* __restrict__ lam, int m, int d,
-                                                   int c, double eta, double* __restrict__ nu_out) {
+__global__ __launch_bounds__(1024) void k_round_nu(const double* __restrict__ lam, int64_t n,
+                                                   double eta, double* __restrict__ nu_out) {
   __shared__ double bc[4];
   __shared__ int done;
-  const int n = c * d, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   double mn = INFINITY;
-  for (int e = tid; e < n; e += blockDim.x) mn = fmin(mn, lam[(int64_t)(e / d) * m + e % d]);
-  // block min through the max of -x
+  for (int64_t e = tid; e < n; e += blockDim.x) mn = fmin(mn, lam[e]);
   const double negmax = block_max<1024>(-mn);
   if (tid == 0) bc[0] = -negmax;
   __syncthreads();
@@ -375,8 +299,8 @@ __global__ __launch_bounds__(1024) void k_round_nu(const double* __restrict__ la
   __syncthreads();
   for (int it = 0; it < 300; ++it) {
     double f = 0.0, fp = 0.0;
-    for (int e = tid; e < n; e += blockDim.x) {
-      const double a = 1.0 / (nu + eta * lam[(int64_t)(e / d) * m + e % d]);
+    for (int64_t e = tid; e < n; e += blockDim.x) {
+      const double a = 1.0 / (nu + eta * lam[e]);
       const double a2 = a * a;
       f += a2;
       fp += a2 * a;
@@ -410,21 +334,19 @@ __global__ __launch_bounds__(1024) void k_round_nu(const double* __restrict__ la
   if (tid == 0) *nu_out = nu;
 }
 
-// weights of round t+1: w1_kj = 1 / (nu + eta lambda_kj), w2 = w1^2 (0 on padding columns)
-__global__ void k_round_weights(const double* __restrict__ lamE, int m, int d, int c, int ldw,
-                                const double* __restrict__ nu_p, double eta,
-                                double* __restrict__ wts) {
+// D_k = nu I + eta (C_k + O_k / b)
+__global__ void k_form_d(const double* __restrict__ Cm, const double* __restrict__ Ot,
+                         const double* __restrict__ nu_p, double eta, double inv_b, int d, int c,
+                         double* __restrict__ Dm) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)c * ldw) return;
-  const int64_t k = e / ldw;
-  const int j = (int)(e - k * ldw);
-  double w1 = 0.0;
-  if (j < d) w1 = 1.0 / (*nu_p + eta * lamE[k * m + j]);
-  wts[2 * e] = w1;
-  wts[2 * e + 1] = w1 * w1;
+  const int64_t dd = (int64_t)d * d;
+  if (e >= (int64_t)c * dd) return;
+  const int r = (int)(e % dd);
+  const int i = r / d, j = r - (r / d) * d;
+  Dm[e] = (i == j ? *nu_p : 0.0) + eta * (Cm[e] + Ot[e] * inv_b);
 }
 
-// FP32 copy of an FP64 array (the operand and weights of the FP32 decision mode)
+// FP32 copy of an FP64 array (the operand of the FP32 decision mode)
 __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = (float)src[i];
@@ -432,23 +354,25 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
 
 // ------------------------------------------------------------------ scoring
 // T[k][row] = g q2 / (1 + eta g q1) for the chunk's rows [r0, r0 + R) and class k, with
-// (q1, q2) the weighted sums of squares of y = W_k^T x (see the file comment).  Workgroup: 64
-// rows x one class; it walks the class's columns in tiles of 64 (four waves of 32 x 32, FP64
-// 16x16x4 MFMA, stages of 16 k-rows double-buffered through LDS) and keeps the per-row sums in
-// LDS.  Workgroups are ordered class-major (XCD-aware), so one XCD's tiles share W_k.
-// CT is the decision precision: every step from y = W^T x to the class term is computed in CT
-// (FP64, or FP32 on the FP32 MFMA as the paper's single-precision implementation does).
+// q1 = u . v and q2 = v . v, [u | v] = x^T W_k, W_k = [L^-T | (D^-1 L^-1)^T] (d x 2 ldo, the
+// halves at column offsets 0 and ldo; zero beyond d).  Workgroup: 64 rows x one class; it
+// walks the class's d columns in tiles of 64, each tile accumulating the matching u and v
+// columns (four waves of 32 x 32 each, 16x16x4 MFMA, stages of 16 k-rows double-buffered
+// through LDS; a u block skips the stages below its triangle) and adds u . v and v . v per row
+// to LDS slots.  Workgroups are ordered class-major (XCD-aware), so one XCD's tiles share W_k.
+// CT is the decision precision: every step from the products to the class term is computed
+// in CT (FP64, or FP32 on the FP32 MFMA as the paper's single-precision implementation does).
 template <typename T, typename CT>
-__global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
+__global__ __launch_bounds__(256, 2) void k_round_score(const T* __restrict__ X,
                                                      const T* __restrict__ H, int64_t r0,
                                                      int64_t R, int d, int c,
-                                                     const CT* __restrict__ W, int ldw,
-                                                     const CT* __restrict__ wts, double eta,
-                                                     CT* __restrict__ Tout) {
+                                                     const CT* __restrict__ W, int ldo,
+                                                     double eta, CT* __restrict__ Tout) {
   constexpr int TM = kScoreTM, TN = kScoreTN, TK = kScoreTK;
   constexpr int SA = TM + kScorePad, SB = TN + kScorePad;
   __shared__ CT As[2][TK][SA];
-  __shared__ CT Bs[2][TK][SB];
+  __shared__ CT Bu[2][TK][SB];
+  __shared__ CT Bv[2][TK][SB];
   __shared__ CT red[2][TM][2];
   typedef Mfma16<CT> MF;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -458,91 +382,95 @@ __global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
   const int k = (int)(lid / ntr);
   const int64_t row0 = (lid - (int64_t)k * ntr) * TM;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  const CT* Wk = W + (int64_t)k * d * ldw;
-  const CT* wk = wts + (int64_t)k * ldw * 2;
+  const CT* Wk = W + (int64_t)k * d * 2 * ldo;
   const int nst = (d + TK - 1) / TK;
-  const int nct = (ldw + TN - 1) / TN;
+  const int nct = (d + TN - 1) / TN;
 
-  // per-row sums of w1 y^2 and w2 y^2, one slot per column half of the workgroup
   for (int e = tid; e < 2 * TM * 2; e += 256) (&red[0][0][0])[e] = CT(0);
 
   // staging: A = 64 rows x 16 k, thread (row tid/16 + 16u, k tid%16), u = 0..3;
-  // B = 16 k x 64 columns, thread (k tid/64 + 4u, column tid%64)
+  // B = 16 k x 64 columns of each half, thread (k tid/64 + 4u, column tid%64)
   const int ak = tid & 15, ar = tid >> 4, bc = tid & 63, bk = tid >> 6;
   const T* xa = X + (r0 + row0 + ar) * d + ak;
   const int64_t arows = R - row0 - ar;              // rows of this thread's column in range
-  const CT* wb = Wk + (int64_t)bk * ldw + bc;
-  CT ra[4], rb[4];
+  const CT* wb = Wk + (int64_t)bk * 2 * ldo + bc;
+  CT ra[4], rbu[4], rbv[4];
   int col0 = 0;
   auto load = [&](int st) {
     const int k0 = st * TK;
     const bool ka = k0 + ak < d;
+    const bool cv = col0 + bc < d;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       ra[u] = (ka && 16 * u < arows) ? (CT)xa[(int64_t)16 * u * d + k0] : CT(0);
-      rb[u] = (k0 + bk + 4 * u < d && col0 + bc < ldw) ? wb[(int64_t)(k0 + 4 * u) * ldw + col0]
-                                                        : CT(0);
+      const bool kb = k0 + bk + 4 * u < d && cv;
+      const CT* w = wb + (int64_t)(k0 + 4 * u) * 2 * ldo + col0;
+      rbu[u] = kb ? w[0] : CT(0);
+      rbv[u] = kb ? w[ldo] : CT(0);
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       As[buf][ak][ar + 16 * u] = ra[u];
-      Bs[buf][bk + 4 * u][bc] = rb[u];
+      Bu[buf][bk + 4 * u][bc] = rbu[u];
+      Bv[buf][bk + 4 * u][bc] = rbv[u];
     }
   };
 
   for (int ct = 0; ct < nct; ++ct) {
     col0 = ct * TN;
-    typename MF::acc acc[2][2];
+    typename MF::acc au[2][2], av[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = MF::zero();
-    bool jon[2];
+      for (int j = 0; j < 2; ++j) au[i][j] = av[i][j] = MF::zero();
+    int jend[2];       // column block j is live and its u part has stages below k = jend
 #pragma unroll
-    for (int j = 0; j < 2; ++j) jon[j] = col0 + wn + 16 * j < ldw;
+    for (int j = 0; j < 2; ++j) {
+      const int cb = col0 + wn + 16 * j;
+      jend[j] = cb < d ? cb + 16 : 0;
+    }
     load(0);
     store(0);
     __syncthreads();
     for (int st = 0; st < nst; ++st) {
       const int buf = st & 1;
       if (st + 1 < nst) load(st + 1);
+      const int k0 = st * TK;
 #pragma unroll
       for (int q = 0; q < TK / 4; ++q) {
-        CT av[2], bv[2];
+        CT a[2], bu[2], bv[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) av[i] = As[buf][4 * q + g][wm + 16 * i + li];
+        for (int i = 0; i < 2; ++i) a[i] = As[buf][4 * q + g][wm + 16 * i + li];
 #pragma unroll
-        for (int j = 0; j < 2; ++j) bv[j] = Bs[buf][4 * q + g][wn + 16 * j + li];
+        for (int j = 0; j < 2; ++j) {
+          bu[j] = Bu[buf][4 * q + g][wn + 16 * j + li];
+          bv[j] = Bv[buf][4 * q + g][wn + 16 * j + li];
+        }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
-            if (jon[j]) acc[i][j] = MF::run(av[i], bv[j], acc[i][j]);
+          for (int j = 0; j < 2; ++j) {
+            if (jend[j] > 0) av[i][j] = MF::run(a[i], bv[j], av[i][j]);
+            if (k0 < jend[j]) au[i][j] = MF::run(a[i], bu[j], au[i][j]);
+          }
       }
       if (st + 1 < nst) store(buf ^ 1);
       __syncthreads();
     }
-    // this tile's weighted squares, summed over the lane's columns, then over the 16 lanes
-    // of each row group; lane 0 of the group adds them to the row's slot
-    CT w1[2], w2[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = col0 + wn + 16 * j + li;
-      w1[j] = jon[j] ? wk[2 * col] : CT(0);
-      w2[j] = jon[j] ? wk[2 * col + 1] : CT(0);
-    }
+    // this tile's u . v and v . v, summed over the lane's columns, then over the 16 lanes of
+    // each row group; lane 0 of the group adds them to the row's slot
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
+      for (int vv = 0; vv < 4; ++vv) {
         CT t1 = CT(0), t2 = CT(0);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          const CT y2 = acc[i][j][v] * acc[i][j][v];
-          t1 = fma(w1[j], y2, t1);
-          t2 = fma(w2[j], y2, t2);
+          const CT uu = au[i][j][vv], vq = av[i][j][vv];
+          t1 = fma(uu, vq, t1);
+          t2 = fma(vq, vq, t2);
         }
 #pragma unroll
         for (int o = 1; o < 16; o <<= 1) {
@@ -550,7 +478,7 @@ __global__ __launch_bounds__(256, 4) void k_round_score(const T* __restrict__ X,
           t2 += __shfl_xor(t2, o, 64);
         }
         if (li == 0) {
-          const int row = wm + 16 * i + MF::row(g, v);
+          const int row = wm + 16 * i + MF::row(g, vv);
           red[wave >> 1][row][0] += t1;
           red[wave >> 1][row][1] += t2;
         }
@@ -665,14 +593,14 @@ __global__ __launch_bounds__(1024) void k_round_pick(const double* __restrict__ 
 }
 
 // The update for the row selected in round t, per class k: (H)_k += (H_o)_k / b + g x x^T and
-// C_k += O_k / b + g u u^T with u = L_k^-1 x; the Jacobi inputs of the round (C_k, and
-// E_k = C_k + O_k / b) are written padded to m x m; the row leaves the candidates.
+// C_k += O_k / b + g u u^T with u = L_k^-1 x; a copy of C_k goes to the eigenvalue workspace;
+// the row leaves the candidates.
 template <typename T>
 __global__ __launch_bounds__(256) void k_round_update(
-    const T* __restrict__ X, const T* __restrict__ H, int d, int c, int m, double inv_b,
+    const T* __restrict__ X, const T* __restrict__ H, int d, int c, double inv_b,
     const int64_t* __restrict__ sel, int t, const double* __restrict__ Li,
     const double* __restrict__ Ho, const double* __restrict__ Ot, double* __restrict__ Cm,
-    double* __restrict__ Hacc, double* __restrict__ JA, int32_t* __restrict__ mask,
+    double* __restrict__ Hacc, double* __restrict__ Ework, int32_t* __restrict__ mask,
     int32_t* __restrict__ err) {
   __shared__ double xs[kMaxD], us[kMaxD];
   const int k = blockIdx.x, tid = threadIdx.x;
@@ -693,33 +621,22 @@ __global__ __launch_bounds__(256) void k_round_update(
   __syncthreads();
   const double h = (double)H[i * c + k];
   const double gk = h * (1.0 - h);
-  const int64_t mm = (int64_t)m * m;
-  double* JC = JA + (int64_t)k * mm;
-  double* JE = JA + ((int64_t)c + k) * mm;
-  for (int64_t e = tid; e < mm; e += blockDim.x) {
-    const int a = (int)(e / m), bb = (int)(e - (e / m) * m);
-    if (a < d && bb < d) {
-      const int64_t s = k * dd + (int64_t)a * d + bb;
-      const double o = Ot[s];
-      const double cn = Cm[s] + o * inv_b + gk * us[a] * us[bb];
-      Cm[s] = cn;
-      Hacc[s] = Hacc[s] + Ho[s] * inv_b + gk * xs[a] * xs[bb];
-      JC[e] = cn;
-      JE[e] = cn + o * inv_b;
-    } else {
-      JC[e] = 0.0;
-      JE[e] = 0.0;
-    }
+  for (int64_t e = tid; e < dd; e += blockDim.x) {
+    const int a = (int)(e / d), bb = (int)(e - (e / d) * d);
+    const int64_t s = k * dd + e;
+    const double cn = Cm[s] + Ot[s] * inv_b + gk * us[a] * us[bb];
+    Cm[s] = cn;
+    Hacc[s] = Hacc[s] + Ho[s] * inv_b + gk * xs[a] * xs[bb];
+    Ework[s] = cn;
   }
   if (k == 0 && tid == 0) mask[i] = 1;
 }
 
-// min over the c blocks' d eigenvalues (one workgroup)
-__global__ __launch_bounds__(1024) void k_min_eig(const double* __restrict__ lam, int m, int d,
-                                                  int c, double* __restrict__ out) {
+// min over all eigenvalues (one workgroup)
+__global__ __launch_bounds__(1024) void k_min_eig(const double* __restrict__ lam, int64_t n,
+                                                  double* __restrict__ out) {
   double mn = INFINITY;
-  for (int e = threadIdx.x; e < c * d; e += blockDim.x)
-    mn = fmin(mn, lam[(int64_t)(e / d) * m + e % d]);
+  for (int64_t e = threadIdx.x; e < n; e += blockDim.x) mn = fmin(mn, lam[e]);
   const double r = block_max<1024>(-mn);
   if (threadIdx.x == 0) *out = -r;
 }
@@ -729,22 +646,22 @@ __global__ __launch_bounds__(1024) void k_min_eig(const double* __restrict__ lam
 // ------------------------------------------------------------------ state
 struct Round {
   Ctx* x;                // borrowed; its profiling marks also bracket the scoring launches
-  int d, c, m, ldw, b, t;
+  int d, c, ldo, b, t;
   int64_t n_pool, N, R, nparts;
   double eta;
-  double *omega, *Lf, *Li, *Ho, *Ot, *Cm, *Hacc, *JA, *JV, *JT, *lam, *W, *wts, *Tb, *pval, *nu,
-      *smax, *gpart, *crit;
+  int fp32;              // decision precision FP32 (FIRAL_ROUND_FP32)
+  double *omega, *Lf, *Li, *Ho, *Ot, *Cm, *Hacc, *Ew, *Dm, *Dinv, *tdiag, *toff, *lam, *W, *Tb,
+      *pval, *nu, *smax, *gpart, *crit;
+  float* Wf;             // FP32 copy of W in that mode
   int64_t *pidx, *sel;
-  int32_t *mask, *flags, *tiles;
+  int32_t *mask, *flags, *tiles;   // flags: [0] Sigma_o not SPD, [1] no row left, [2] D not SPD
   int ntiles, splits;
-  int fp32;                // decision precision FP32 (FIRAL_ROUND_FP32)
-  float *Wf, *wtsf;        // FP32 copies of W and the weights in that mode
 };
 
 static void free_round(Round* r) {
-  void* bufs[] = {r->omega, r->Lf, r->Li, r->Ho, r->Ot, r->Cm, r->Hacc, r->JA, r->JV, r->JT, r->lam,
-                  r->W, r->wts, r->Tb, r->pval, r->nu, r->smax, r->gpart, r->crit, r->pidx,
-                  r->sel, r->mask, r->flags, r->tiles, r->Wf, r->wtsf};
+  void* bufs[] = {r->omega, r->Lf, r->Li, r->Ho, r->Ot, r->Cm, r->Hacc, r->Ew, r->Dm, r->Dinv,
+                  r->tdiag, r->toff, r->lam, r->W, r->Tb, r->pval, r->nu, r->smax, r->gpart,
+                  r->crit, r->Wf, r->pidx, r->sel, r->mask, r->flags, r->tiles};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   delete r;
@@ -781,21 +698,44 @@ static int bgemm(const BGemm& g, int batch, hipStream_t st) {
   return FIRAL_OK;
 }
 
-// W_k = L_k^-T Q_k (Q_k: the first d columns of block k of JV) and the weights for nu_p
-static int round_operand(Round* r, const double* nu_p, hipStream_t st) {
-  const int d = r->d, c = r->c, m = r->m;
-  const int64_t dd = (int64_t)d * d, mm = (int64_t)m * m;
-  k_round_weights<<<(unsigned)cdiv((int64_t)c * r->ldw, 256), 256, 0, st>>>(
-      r->lam + (int64_t)c * m, m, d, c, r->ldw, nu_p, r->eta, r->wts);
+// eigenvalues of the c blocks in A (destroyed) into lam (c x d)
+static int eigvals_launch(Round* r, double* A, hipStream_t st) {
+  const int d = r->d, c = r->c;
+  if (d <= kTriSmemD) {
+    const size_t smem = (size_t)d * d * sizeof(double);
+    static bool attr = false;
+    if (!attr) {
+      FIRAL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_tridiag<true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)(kTriSmemD * kTriSmemD * sizeof(double))));
+      attr = true;
+    }
+    k_tridiag<true><<<c, kTriThreads, smem, st>>>(A, d, r->tdiag, r->toff);
+  } else {
+    k_tridiag<false><<<c, kTriThreads, 0, st>>>(A, d, r->tdiag, r->toff);
+  }
   FIRAL_LAUNCHED();
-  BGemm g{r->Li, dd, 1, d, r->JV, mm, m, 1, r->W, (int64_t)d * r->ldw, r->ldw, 1, d, d, d,
-          INT_MAX, INT_MAX};
+  k_sturm<<<c, 256, 0, st>>>(r->tdiag, r->toff, d, r->lam);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
+// the operand of the round that uses nu_p: D = nu I + eta (C + O / b), D^-1 (FP64 Cholesky),
+// and the v half of W, (D^-1 L^-1)^T
+static int round_operand(Round* r, const double* nu_p, hipStream_t st) {
+  const int d = r->d, c = r->c;
+  const int64_t dd = (int64_t)d * d;
+  k_form_d<<<(unsigned)cdiv(c * dd, 256), 256, 0, st>>>(r->Cm, r->Ot, nu_p, r->eta, 1.0 / r->b,
+                                                        d, c, r->Dm);
+  FIRAL_LAUNCHED();
+  FIRAL_CHECK(chol_blocks_launch(r->Dm, r->Dinv, d, c, r->flags + 2, true, st));
+  // F = D^-1 L^-1 stored transposed: W_k[a][ldo + j] = F_k[j][a]
+  BGemm g{r->Dinv, dd, d, 1, r->Li, dd, d, 1, r->W + r->ldo, (int64_t)d * 2 * r->ldo, 1,
+          2 * r->ldo, d, d, d};
   FIRAL_CHECK(bgemm(g, c, st));
   if (r->fp32) {
-    const int64_t nw = (int64_t)c * d * r->ldw, nt = (int64_t)c * r->ldw * 2;
+    const int64_t nw = (int64_t)c * d * 2 * r->ldo;
     k_to_f32<<<(unsigned)cdiv(nw, 256), 256, 0, st>>>(r->W, r->Wf, nw);
-    FIRAL_LAUNCHED();
-    k_to_f32<<<(unsigned)cdiv(nt, 256), 256, 0, st>>>(r->wts, r->wtsf, nt);
     FIRAL_LAUNCHED();
   }
   return FIRAL_OK;
@@ -804,7 +744,7 @@ static int round_operand(Round* r, const double* nu_p, hipStream_t st) {
 // scores of every pool row at the current state into r_out (if non-null) and the block
 // partials of the argmax
 template <typename T, typename CT>
-static int round_score_t(Round* r, const CT* W, const CT* wts, double* r_out, hipStream_t st) {
+static int round_score_t(Round* r, const CT* W, double* r_out, hipStream_t st) {
   const Ctx* x = r->x;
   const T* X = (const T*)x->X;
   const T* H = (const T*)x->H;
@@ -813,7 +753,7 @@ static int round_score_t(Round* r, const CT* W, const CT* wts, double* r_out, hi
     const int64_t R = std::min<int64_t>(r->R, r->n_pool - r0);
     const int64_t nwg = cdiv(R, kScoreTM) * r->c;
     FIRAL_CHECK(prof_mark(r->x, st, true));
-    k_round_score<T, CT><<<(unsigned)nwg, 256, 0, st>>>(X, H, r0, R, r->d, r->c, W, r->ldw, wts,
+    k_round_score<T, CT><<<(unsigned)nwg, 256, 0, st>>>(X, H, r0, R, r->d, r->c, W, r->ldo,
                                                         r->eta, Tb);
     FIRAL_LAUNCHED();
     FIRAL_CHECK(prof_mark(r->x, st, false));
@@ -827,36 +767,29 @@ static int round_score_t(Round* r, const CT* W, const CT* wts, double* r_out, hi
 static int round_score(Round* r, double* r_out, hipStream_t st) {
   const bool f64 = r->x->prec == FIRAL_F64;
   if (r->fp32)
-    return f64 ? round_score_t<double, float>(r, r->Wf, r->wtsf, r_out, st)
-               : round_score_t<float, float>(r, r->Wf, r->wtsf, r_out, st);
-  return f64 ? round_score_t<double, double>(r, r->W, r->wts, r_out, st)
-             : round_score_t<float, double>(r, r->W, r->wts, r_out, st);
+    return f64 ? round_score_t<double, float>(r, r->Wf, r_out, st)
+               : round_score_t<float, float>(r, r->Wf, r_out, st);
+  return f64 ? round_score_t<double, double>(r, r->W, r_out, st)
+             : round_score_t<float, double>(r, r->W, r_out, st);
 }
 
 static int round_step_launch(Round* r, hipStream_t st) {
-  const int d = r->d, c = r->c, m = r->m, t = r->t;
+  const int d = r->d, c = r->c, t = r->t;
   FIRAL_CHECK(round_score(r, nullptr, st));
   k_round_pick<<<1, 1024, 0, st>>>(r->pval, r->pidx, r->nparts, r->sel, r->smax, t);
   FIRAL_LAUNCHED();
   const Ctx* x = r->x;
   if (x->prec == FIRAL_F64)
-    k_round_update<double><<<c, 256, 0, st>>>((const double*)x->X, (const double*)x->H, d, c, m,
+    k_round_update<double><<<c, 256, 0, st>>>((const double*)x->X, (const double*)x->H, d, c,
                                               1.0 / r->b, r->sel, t, r->Li, r->Ho, r->Ot, r->Cm,
-                                              r->Hacc, r->JA, r->mask, r->flags + 1);
+                                              r->Hacc, r->Ew, r->mask, r->flags + 1);
   else
-    k_round_update<float><<<c, 256, 0, st>>>((const float*)x->X, (const float*)x->H, d, c, m,
+    k_round_update<float><<<c, 256, 0, st>>>((const float*)x->X, (const float*)x->H, d, c,
                                              1.0 / r->b, r->sel, t, r->Li, r->Ho, r->Ot, r->Cm,
-                                             r->Hacc, r->JA, r->mask, r->flags + 1);
+                                             r->Hacc, r->Ew, r->mask, r->flags + 1);
   FIRAL_LAUNCHED();
-  // both eigenproblems of the round in the previous round's eigenbasis Q (JV):
-  // JA_k <- Q^T JA_k Q, so they start close to diagonal; E's rotations accumulate onto Q
-  const int64_t mm = (int64_t)m * m;
-  FIRAL_CHECK(bgemm(BGemm{r->JA, mm, m, 1, r->JV, mm, m, 1, r->JT, mm, m, 1, m, m, m, INT_MAX, c},
-                    2 * c, st));
-  FIRAL_CHECK(bgemm(BGemm{r->JV, mm, 1, m, r->JT, mm, m, 1, r->JA, mm, m, 1, m, m, m, c, INT_MAX},
-                    2 * c, st));
-  FIRAL_CHECK(jacobi_launch(r->JA, r->JV, r->lam, m, d, c, c, 1, st));
-  k_round_nu<<<1, 1024, 0, st>>>(r->lam, m, d, c, r->eta, r->nu + t + 1);
+  FIRAL_CHECK(eigvals_launch(r, r->Ew, st));
+  k_round_nu<<<1, 1024, 0, st>>>(r->lam, (int64_t)c * d, r->eta, r->nu + t + 1);
   FIRAL_LAUNCHED();
   FIRAL_CHECK(round_operand(r, r->nu + t + 1, st));
   r->t = t + 1;
@@ -885,7 +818,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   RREQ(lambda >= 0.0 && std::isfinite(lambda), "firal_round_create: lambda must be >= 0");
   RREQ(b >= 1 && (int64_t)b <= x->n_pool, "firal_round_create: b = %d outside [1, n_pool]", b);
   RREQ(x->d <= kMaxD, "firal_round_create: d = %d above the Round step's limit %d", x->d, kMaxD);
-  RREQ(x->c <= 30000, "firal_round_create: c = %d above the Round step's limit 30000", x->c);
+  RREQ(x->c <= 65535, "firal_round_create: c = %d above the Round step's limit 65535", x->c);
   RREQ((flags & ~FIRAL_ROUND_FP32) == 0, "firal_round_create: unknown flags 0x%x", flags);
   hipStream_t st = (hipStream_t)stream;
   FIRAL_HIP(hipSetDevice(x->device));
@@ -893,15 +826,14 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   r->x = x;
   r->d = x->d;
   r->c = x->c;
-  r->m = x->d + (x->d & 1);
-  r->ldw = (int)cdiv(x->d, 16) * 16;
+  r->ldo = (int)cdiv(x->d, 16) * 16;
   r->b = b;
   r->t = 0;
   r->n_pool = x->n_pool;
   r->N = x->N;
   r->eta = eta;
   r->fp32 = (flags & FIRAL_ROUND_FP32) != 0;
-  const int d = r->d, c = r->c, m = r->m;
+  const int d = r->d, c = r->c;
   // rows per scoring chunk: the class-term buffer c x R stays within 1 GiB
   const int64_t cap = std::max<int64_t>(256, (((int64_t)1 << 27) / c) / 256 * 256);
   r->R = std::min<int64_t>(cdiv(r->n_pool, 256) * 256, cap);
@@ -909,7 +841,8 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   std::vector<int32_t> tiles;
   syrk_plan(FIRAL_F64, d, c, &tiles, &r->splits);
   r->ntiles = (int)(tiles.size() / 2);
-  const int64_t dd = (int64_t)d * d, mm = (int64_t)m * m;
+  const int64_t dd = (int64_t)d * d;
+  const int64_t nw = (int64_t)c * d * 2 * r->ldo;
   int rc = FIRAL_OK;
 #define RALLOC(ptr, bytes)                                   \
   if (rc == FIRAL_OK) rc = rmalloc((void**)&(ptr), (bytes));
@@ -920,12 +853,13 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   RALLOC(r->Ot, sizeof(double) * c * dd);
   RALLOC(r->Cm, sizeof(double) * c * dd);
   RALLOC(r->Hacc, sizeof(double) * c * dd);
-  RALLOC(r->JA, sizeof(double) * 2 * c * mm);
-  RALLOC(r->JV, sizeof(double) * c * mm);
-  RALLOC(r->JT, sizeof(double) * 2 * c * mm);
-  RALLOC(r->lam, sizeof(double) * 2 * c * m);
-  RALLOC(r->W, sizeof(double) * c * d * r->ldw);
-  RALLOC(r->wts, sizeof(double) * c * r->ldw * 2);
+  RALLOC(r->Ew, sizeof(double) * c * dd);
+  RALLOC(r->Dm, sizeof(double) * c * dd);
+  RALLOC(r->Dinv, sizeof(double) * c * dd);
+  RALLOC(r->tdiag, sizeof(double) * c * d);
+  RALLOC(r->toff, sizeof(double) * c * d);
+  RALLOC(r->lam, sizeof(double) * c * d);
+  RALLOC(r->W, sizeof(double) * nw);
   RALLOC(r->Tb, sizeof(double) * c * r->R);
   RALLOC(r->pval, sizeof(double) * r->nparts);
   RALLOC(r->pidx, sizeof(int64_t) * r->nparts);
@@ -933,14 +867,11 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   RALLOC(r->smax, sizeof(double) * b);
   RALLOC(r->sel, sizeof(int64_t) * b);
   RALLOC(r->mask, sizeof(int32_t) * r->n_pool);
-  RALLOC(r->flags, sizeof(int32_t) * 2);
+  RALLOC(r->flags, sizeof(int32_t) * 3);
   RALLOC(r->crit, sizeof(double));
   RALLOC(r->gpart, sizeof(double) * r->splits * c * dd);
   RALLOC(r->tiles, sizeof(int32_t) * tiles.size());
-  if (r->fp32) {
-    RALLOC(r->Wf, sizeof(float) * c * d * r->ldw);
-    RALLOC(r->wtsf, sizeof(float) * c * r->ldw * 2);
-  }
+  if (r->fp32) RALLOC(r->Wf, sizeof(float) * nw);
 #undef RALLOC
   if (rc != FIRAL_OK) {
     free_round(r);
@@ -956,17 +887,18 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
     set_error("firal_round_create: copy failed");
     return fail(FIRAL_EHIP);
   }
-#define RCHK(e)                 \
-  do {                          \
-    int rc_ = (e);              \
+#define RCHK(e)                    \
+  do {                             \
+    int rc_ = (e);                 \
     if (rc_ < 0) return fail(rc_); \
   } while (0)
   RCHK(fill_i32(r->flags, 1, INT_MAX, st));
   RCHK(fill_i32(r->flags + 1, 1, 0, st));
+  RCHK(fill_i32(r->flags + 2, 1, INT_MAX, st));
   RCHK(fill_i32(r->mask, r->n_pool, 0, st));
   RCHK(fill(r->Cm, c * dd, 0.0, st));
   RCHK(fill(r->Hacc, c * dd, 0.0, st));
-  RCHK(fill(r->W, (int64_t)c * d * r->ldw, 0.0, st));
+  RCHK(fill(r->W, nw, 0.0, st));
   k_fill_i64<<<(unsigned)cdiv(b, 256), 256, 0, st>>>(r->sel, b, -1);
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
   RCHK(fill(r->nu, 1, std::sqrt((double)d * c), st));
@@ -975,7 +907,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
   RCHK(gram64_launch(x->prec, x->X, x->H, r->omega, r->N, d, c, r->tiles, r->ntiles, r->splits,
                      lambda, r->gpart, r->Lf, st));
-  RCHK(chol_blocks_launch(r->Lf, r->JA, d, c, r->flags, st));
+  RCHK(chol_blocks_launch(r->Lf, r->Dinv, d, c, r->flags, false, st));
   // H_o blocks: the labeled rows with unit weight
   const size_t es = x->prec == FIRAL_F64 ? 8 : 4;
   RCHK(gram64_launch(x->prec, (const char*)x->X + es * r->n_pool * d,
@@ -983,26 +915,26 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
                      r->tiles, r->ntiles, r->splits, 0.0, r->gpart, r->Ho, st));
   k_tri_inv<<<c, 256, 0, st>>>(r->Lf, r->Li, d);
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
-  // O_k = L^-1 H_o L^-T (JV as the intermediate H_o L^-T)
-  RCHK(bgemm(BGemm{r->Ho, dd, d, 1, r->Li, dd, 1, d, r->JV, dd, d, 1, d, d, d, INT_MAX, INT_MAX},
-             c, st));
-  RCHK(bgemm(BGemm{r->Li, dd, d, 1, r->JV, dd, d, 1, r->Ot, dd, d, 1, d, d, d, INT_MAX, INT_MAX},
-             c, st));
-  // round 1: E = O / b, eigenpairs, nu_1 = sqrt(dc), W and weights
-  k_pad_comb<<<(unsigned)cdiv((int64_t)c * mm, 256), 256, 0, st>>>(
-      r->Ot, 1.0 / b, nullptr, 0.0, r->JA + (int64_t)c * mm, d, m, c);
+  // O_k = L^-1 H_o L^-T (Ew as the intermediate H_o L^-T)
+  RCHK(bgemm(BGemm{r->Ho, dd, d, 1, r->Li, dd, 1, d, r->Ew, dd, d, 1, d, d, d}, c, st));
+  RCHK(bgemm(BGemm{r->Li, dd, d, 1, r->Ew, dd, d, 1, r->Ot, dd, d, 1, d, d, d}, c, st));
+  // the fixed u half of every class operand, then round 1's v half (nu_1 = sqrt(dc), C = 0)
+  k_put_lit<<<(unsigned)cdiv(c * dd, 256), 256, 0, st>>>(r->Li, d, c, 2 * r->ldo, r->W);
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
-  RCHK(jacobi_launch(r->JA + (int64_t)c * mm, r->JV, r->lam + (int64_t)c * m, m, d, 0, c, 0, st));
   RCHK(round_operand(r, r->nu, st));
-  int32_t bad = INT_MAX;
-  if (hipMemcpyAsync(&bad, r->flags, sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess ||
+  int32_t bad[3] = {INT_MAX, 0, INT_MAX};
+  if (hipMemcpyAsync(bad, r->flags, sizeof(bad), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     (void)hipGetLastError();
     set_error("firal_round_create: set-up failed");
     return fail(FIRAL_EHIP);
   }
-  if (bad != INT_MAX) {
-    set_error("Sigma block %d of the Round step is not positive definite", bad);
+  if (bad[0] != INT_MAX) {
+    set_error("Sigma block %d of the Round step is not positive definite", bad[0]);
+    return fail(FIRAL_ENOTSPD);
+  }
+  if (bad[2] != INT_MAX) {
+    set_error("block %d of the first Round-step matrix is not positive definite", bad[2]);
     return fail(FIRAL_ENOTSPD);
   }
 #undef RCHK
@@ -1035,8 +967,8 @@ extern "C" int firal_round_result(firal_round round, int64_t* selected, double* 
   hipStream_t st = (hipStream_t)stream;
   FIRAL_HIP(hipSetDevice(r->x->device));
   const int n = r->t;
-  int32_t err = 0;
-  FIRAL_HIP(hipMemcpyAsync(&err, r->flags + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  int32_t fl[3] = {INT_MAX, 0, INT_MAX};
+  FIRAL_HIP(hipMemcpyAsync(fl, r->flags, sizeof(fl), hipMemcpyDeviceToHost, st));
   if (selected && n > 0)
     FIRAL_HIP(hipMemcpyAsync(selected, r->sel, sizeof(int64_t) * n, hipMemcpyDeviceToHost, st));
   if (nu) FIRAL_HIP(hipMemcpyAsync(nu, r->nu, sizeof(double) * (n + 1), hipMemcpyDeviceToHost, st));
@@ -1044,9 +976,13 @@ extern "C" int firal_round_result(firal_round round, int64_t* selected, double* 
     FIRAL_HIP(hipMemcpyAsync(score_max, r->smax, sizeof(double) * n, hipMemcpyDeviceToHost, st));
   FIRAL_HIP(hipStreamSynchronize(st));
   if (t) *t = n;
-  if (err) {
+  if (fl[1]) {
     set_error("Round step: no unselected pool row with a finite score was left");
     return FIRAL_EINVAL;
+  }
+  if (fl[2] != INT_MAX) {
+    set_error("Round step: block %d of nu I + eta (C + O / b) is not positive definite", fl[2]);
+    return FIRAL_ENOTSPD;
   }
   return FIRAL_OK;
 }
@@ -1056,12 +992,10 @@ extern "C" int firal_round_criterion(firal_round round, double* out, void* strea
   Round* r = reinterpret_cast<Round*>(round);
   hipStream_t st = (hipStream_t)stream;
   FIRAL_HIP(hipSetDevice(r->x->device));
-  const int d = r->d, c = r->c, m = r->m;
-  k_pad_comb<<<(unsigned)cdiv((int64_t)c * m * m, 256), 256, 0, st>>>(r->Hacc, 1.0, nullptr, 0.0,
-                                                                      r->JA, d, m, c);
-  FIRAL_LAUNCHED();
-  FIRAL_CHECK(jacobi_launch(r->JA, nullptr, r->lam, m, d, c, 0, 0, st));
-  k_min_eig<<<1, 1024, 0, st>>>(r->lam, m, d, c, r->crit);
+  const int64_t n = (int64_t)r->c * r->d * r->d;
+  FIRAL_HIP(hipMemcpyAsync(r->Ew, r->Hacc, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  FIRAL_CHECK(eigvals_launch(r, r->Ew, st));
+  k_min_eig<<<1, 1024, 0, st>>>(r->lam, (int64_t)r->c * r->d, r->crit);
   FIRAL_LAUNCHED();
   FIRAL_HIP(hipMemcpyAsync(out, r->crit, sizeof(double), hipMemcpyDeviceToHost, st));
   FIRAL_HIP(hipStreamSynchronize(st));
