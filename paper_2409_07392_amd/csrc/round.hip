@@ -14,7 +14,7 @@
 //
 // A round: score (MFMA) -> sum over classes and argmax over the unselected rows (fixed order,
 // lowest index on ties) -> update of C, (H) and the selection mask -> eigenvalues of C
-// (Householder tridiagonalisation, then bisection on Sturm counts) -> nu_{t+1} (safeguarded
+// (Householder tridiagonalisation, then multisection on Sturm counts) -> nu_{t+1} (safeguarded
 // Newton on Tr((nu I + eta C)^-2) = 1) -> D, its inverse (FP64 Cholesky) and the operand of
 // round t + 1.  All state stays on the device and nothing is read back.
 #include <algorithm>
@@ -195,8 +195,17 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
     // addresses), then K = (beta / 2) p . v
     double pv = 0.0;
     for (int i = tid; i < n2; i += kTriThreads) {
-      double acc = 0.0;
-      for (int q = 0; q < n2; ++q) acc = fma(A[(int64_t)(r0 + q) * d + r0 + i], v[q], acc);
+      const double* col = A + (int64_t)r0 * d + r0 + i;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four chains in flight
+      int q = 0;
+      for (; q + 3 < n2; q += 4) {
+        s0 = fma(col[(int64_t)q * d], v[q], s0);
+        s1 = fma(col[(int64_t)(q + 1) * d], v[q + 1], s1);
+        s2 = fma(col[(int64_t)(q + 2) * d], v[q + 2], s2);
+        s3 = fma(col[(int64_t)(q + 3) * d], v[q + 3], s3);
+      }
+      for (; q < n2; ++q) s0 = fma(col[(int64_t)q * d], v[q], s0);
+      const double acc = (s0 + s1) + (s2 + s3);
       p[i] = beta * acc;
       pv += beta * acc * v[i];
     }
@@ -223,14 +232,19 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
   }
 }
 
-// Eigenvalues of each tridiagonal (diag a, off-diagonal e) by bisection on Sturm counts: the
-// number of negative pivots of the LDL^T factorisation of T - x I is the number of eigenvalues
-// below x; eigenvalue j is bracketed by Gershgorin's bounds and bisected until the bracket
-// stops shrinking (one thread per eigenvalue).  Pivots smaller than pivmin are replaced by
-// -pivmin (LAPACK's safeguard).
+// Eigenvalues of each tridiagonal (diag a, off-diagonal e) on Sturm counts: the number of
+// negative pivots of the LDL^T factorisation of T - x I is the number of eigenvalues below x
+// (monotone in x).  Eigenvalue j starts from Gershgorin's bounds; S lanes of a wave share it
+// and each evaluates one of S interior points of its bracket, a ballot finds the first point
+// above the eigenvalue, and the bracket shrinks (S + 1)-fold per step (S = 1: bisection).
+// Steps stop once the bracket is within 4 u ||T|| + 4 u |x| (u = 2^-53, the accuracy of the
+// counts) or stops shrinking.  Pivots smaller than pivmin are replaced by -pivmin (LAPACK's
+// safeguard).  Grid: (block, eigenvalue range of 256 / S).
+template <int S>
 __global__ __launch_bounds__(256) void k_sturm(const double* __restrict__ diag,
                                                const double* __restrict__ off, int d,
                                                double* __restrict__ lam) {
+  constexpr int EPW = 256 / S;
   __shared__ double a[kMaxD], e2[kMaxD];
   __shared__ double bnd[3];
   const int blk = blockIdx.x, tid = threadIdx.x;
@@ -255,13 +269,18 @@ __global__ __launch_bounds__(256) void k_sturm(const double* __restrict__ diag,
   }
   __syncthreads();
   const double L0 = bnd[0], H0 = bnd[1], pivmin = bnd[2];
-  const double slack = 2.3e-16 * fmax(fabs(L0), fabs(H0)) + pivmin;
-  for (int j = tid; j < d; j += blockDim.x) {
-    double l = L0 - slack, u = H0 + slack;
-    for (int it = 0; it < 200; ++it) {
-      const double x = 0.5 * (l + u);
-      if (!(x > l && x < u)) break;
-      int cnt = 0;
+  const double nrm = fmax(fabs(L0), fabs(H0));
+  const double tol = 4.0 * 1.1102230246251565e-16 * nrm + pivmin;
+  const int sl = tid % S, j = blockIdx.y * EPW + tid / S;
+  const int gshift = (tid & 63) / S * S;        // first lane of this lane's group in the wave
+  const bool on = j < d;
+  double l = L0 - tol, u = H0 + tol;
+  bool active = on;
+  for (int it = 0; it < 200 && __any(active); ++it) {
+    const double h = (u - l) / (S + 1);
+    const double x = l + (sl + 1) * h;
+    int cnt = 0;
+    if (active) {
       double q = a[0] - x;
       if (fabs(q) < pivmin) q = -pivmin;
       cnt += q < 0.0;
@@ -270,11 +289,20 @@ __global__ __launch_bounds__(256) void k_sturm(const double* __restrict__ diag,
         if (fabs(q) < pivmin) q = -pivmin;
         cnt += q < 0.0;
       }
-      if (cnt > j) u = x;
-      else l = x;
     }
-    lam[(int64_t)blk * d + j] = 0.5 * (l + u);
+    const uint64_t m = __ballot(active && cnt > j);
+    if (active) {
+      const uint32_t bits = (uint32_t)((m >> gshift) & ((S == 64 ? ~0ull : (1ull << S) - 1)));
+      const double nl = bits == 0 ? l + S * h : (bits & 1u ? l : l + (__ffs(bits) - 1) * h);
+      const double nu = bits == 0 ? u : l + __ffs(bits) * h;
+      if (!(nu - nl > tol + 4.0 * 1.1102230246251565e-16 * fmax(fabs(nl), fabs(nu))) ||
+          (nl == l && nu == u))
+        active = false;
+      l = nl;
+      u = nu;
+    }
   }
+  if (on && sl == 0) lam[(int64_t)blk * d + j] = 0.5 * (l + u);
 }
 
 // ------------------------------------------------------------------ nu
@@ -715,7 +743,12 @@ static int eigvals_launch(Round* r, double* A, hipStream_t st) {
     k_tridiag<false><<<c, kTriThreads, 0, st>>>(A, d, r->tdiag, r->toff);
   }
   FIRAL_LAUNCHED();
-  k_sturm<<<c, 256, 0, st>>>(r->tdiag, r->toff, d, r->lam);
+  // few eigenvalues: 16 lanes share each one (17-section); many: one lane each (bisection)
+  if ((int64_t)c * d <= 65536)
+    k_sturm<16><<<dim3(c, (unsigned)cdiv(d, 256 / 16)), 256, 0, st>>>(r->tdiag, r->toff, d,
+                                                                      r->lam);
+  else
+    k_sturm<1><<<dim3(c, (unsigned)cdiv(d, 256)), 256, 0, st>>>(r->tdiag, r->toff, d, r->lam);
   FIRAL_LAUNCHED();
   return FIRAL_OK;
 }
