@@ -14,11 +14,11 @@ objectives are within 1e-4 of each other (either row is then a valid maximiser).
 * the objective of every pool row (firal_round_scores) against the oracle's, normwise 1e-9
   (FP32 mode: 1e-4), before the first round and after the last checked one;
 * the eta criterion min_k lambda_min((H)_k) to 1e-8.
-Shapes span several scoring tiles and a ragged tail, odd d (a padding index in the Jacobi
-solves), no labeled rows, c = 2, d = 1 and the whole pool selected; configuration 2 at its
-full size (n = 50,000, d = 100, c = 10, the bench's launch configuration) over its first
-rounds; a reduced configuration-3 shape (d = 256, c = 100) for the global-memory Jacobi path
-and several column tiles per class.
+Shapes span several scoring tiles and a ragged tail, odd d, no labeled rows, c = 2, d = 1
+and the whole pool selected; configuration 2 at its full size (n = 50,000, d = 100, c = 10,
+the bench's launch configuration) over its first rounds; a reduced configuration-3 shape
+(d = 256, c = 100) for the global-memory tridiagonalisation and several column tiles per
+class.
 """
 import numpy as np
 import pytest
