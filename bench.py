@@ -17,8 +17,10 @@ configuration 4 (n = 1,280,000, d = 384, c = 1000, s = 16) times Relax iteration
 with a fixed number of CG iterations per solve (--fixed-cg).  Both report the
 product's TFLOP/s and the gradient error against the GPU FP64 mode for FP32 and
 bf16x3.  --workload 5 runs the batch workload (64 uneven problems, 30 iterations) as one
-captured graph and one call at a time.  These are measurements of the other workloads, not
-the bench line.
+captured graph and one call at a time.  --workload table5 runs the first active-learning
+round (Relax, then Round) at the ImageNet-50 and Caltech-101 shapes of the paper's
+single-GPU timing table.  These are measurements of the other workloads, not the bench
+line.  The default run also reports the Round step (Algorithm 3) on the Relax leg's weights.
 """
 from __future__ import annotations
 
@@ -55,7 +57,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5])
+    ap.add_argument("--workload", default="2", choices=["2", "3", "4", "5", "table5"])
     ap.add_argument("--no-round", action="store_true", help="skip the Round-step leg")
     ap.add_argument("--round-rounds", type=int, default=2,
                     help="configurations 3/4: Round-step rounds timed per decision precision "
@@ -293,6 +295,84 @@ def round_large(p, z, eta, rounds, fp32):
             "selected": [int(i) for i in res["selected"]]}
 
 
+# The first active-learning round of the paper's single-GPU timing table (Table 5):
+# ImageNet-50 and Caltech-101 shapes (Table 4), synthetic stand-ins of those sizes.
+TABLE5 = {
+    "imagenet50": dict(n=5000, n_lab=50, d=50, c=50, b=50, paper_relax_s=1.3, paper_round_s=1.1),
+    "caltech101": dict(n=1715, n_lab=101, d=100, c=101, b=101, paper_relax_s=1.9,
+                       paper_round_s=4.4),
+}
+
+
+def table5_workload(args):
+    """Relax (s = 10, CG relative residual 0.1, stop at a relative change of the objective
+    estimate below 1e-4, at most 100 iterations) then Round (b = budget) on each Table-5 shape,
+    wall-clock on one MI355X; the paper's A100 seconds are printed beside them as context."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, RoundSolver, default_beta0, round_eta_sweep
+    from synthdata import make_problem
+    out = {}
+    for name, sh in TABLE5.items():
+        p = make_problem(2, n=sh["n"], n_lab=sh["n_lab"], d=sh["d"], c=sh["c"], s=10,
+                         b=float(sh["b"]), K=sh["c"], tol=0.1, T=100, seed=7000 + sh["c"])
+        dev = torch.device("cuda:0")
+        X = torch.as_tensor(p.X, dtype=torch.float32, device=dev).contiguous()
+        H = torch.as_tensor(p.H, dtype=torch.float32, device=dev).contiguous()
+        ctx = RelaxContext(X, H, p.n_pool, p.s, "f32")
+        beta0 = default_beta0(p.n_pool, 100)
+        eta = 8.0 * (p.d * p.c) ** 0.5
+
+        def solve():
+            w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
+            f_prev, it = None, 0
+            for t in range(1, 101):
+                info = ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, 0.1, 1000, True)
+                it = t
+                f = info["f_hat"]
+                if f_prev is not None and abs(f - f_prev) <= 1e-4 * abs(f_prev):
+                    break
+                f_prev = f
+            return w, it
+
+        solve()                                         # warm-up (first launches)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w, iters = solve()
+        torch.cuda.synchronize()
+        t_relax = time.perf_counter() - t0
+        z = (p.b * w).contiguous()
+        warm = RoundSolver(ctx, z, p.lam, eta, int(p.b), fp32=True)
+        warm.run()
+        warm.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = RoundSolver(ctx, z, p.lam, eta, int(p.b), fp32=True)
+        sel = rs.run()
+        t_round = time.perf_counter() - t0
+        rs.close()
+        t0 = time.perf_counter()
+        sweep = round_eta_sweep(ctx, z, p.lam, [eta / 8, eta / 2, eta, 2 * eta, 8 * eta],
+                                int(p.b), fp32=True)
+        t_sweep = time.perf_counter() - t0
+        ctx.close()
+        out[name] = {"n_pool": p.n_pool, "n_lab": p.n_lab, "d": p.d, "c": p.c, "b": p.b,
+                     "relax_s": t_relax, "relax_iters": iters,
+                     "round_s": t_round, "round_eta": eta, "selected_first": [int(i) for i in sel[:5]],
+                     "eta_sweep_s": t_sweep, "eta_sweep_best": sweep["best"],
+                     "paper_a100_relax_s": sh["paper_relax_s"],
+                     "paper_a100_round_s": sh["paper_round_s"]}
+        log(f"{name}: relax {t_relax:.3f} s ({iters} it), round {t_round:.3f} s")
+    print(json.dumps({"workload": "Table 5 shapes (first active-learning round)",
+                      "data": "synthetic stand-ins of the ImageNet-50 and Caltech-101 shapes",
+                      "relax": "s = 10, CG relative residual 0.1, stop at relative change of "
+                               "f_hat < 1e-4 (at most 100 iterations), projected PCG, FP32",
+                      "round": "b = budget rounds, FP32 decision, eta = 8 sqrt(dc); the sweep "
+                               "runs 5 etas",
+                      "results": out}))
+
+
 def large_workload(args):
     """Configurations 3 and 4: FP32 and bf16x3 legs plus the FP64 reference gradient."""
     import numpy as np
@@ -477,6 +557,10 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Relax path "
               "of this build is single-GPU.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "table5":
+        table5_workload(args)
+        return
+    args.workload = int(args.workload)
     if args.workload == 5:
         batch_workload(args)
         return
