@@ -57,7 +57,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--workload", default="2", choices=["2", "3", "4", "5", "table5"])
+    ap.add_argument("--workload", default="2",
+                    choices=["2", "3", "4", "5", "table5", "studies"])
+    ap.add_argument("--study", default="fig1,fig4,fig5",
+                    help="--workload studies: comma-separated subset of fig1, fig4, fig5")
     ap.add_argument("--no-round", action="store_true", help="skip the Round-step leg")
     ap.add_argument("--round-rounds", type=int, default=2,
                     help="configurations 3/4: Round-step rounds timed per decision precision "
@@ -373,6 +376,130 @@ def table5_workload(args):
                       "results": out}))
 
 
+def studies_workload(args):
+    """Relax and Round studies on synthetic data, analogues of the paper's figures:
+    fig1 - CG against block-Jacobi PCG (literal and projected) in the first mirror-descent
+           iteration: relative residual after k iterations, and iterations to 1e-6;
+    fig4 - the objective f(z_t) = Tr(Sigma^-1 H_p) (exact: all dc unit probes) along the
+           Relax iterations for several probe counts s and CG tolerances;
+    fig5 - Relax (preconditioner, 50 fixed CG iterations) and Round (one round: scoring
+           and the rest) times as d and c grow."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, RoundSolver, default_beta0
+    from synthdata import make_problem
+    from synthdata.device import draw_device
+    dev = torch.device("cuda:0")
+    res = {}
+    parts = args.study.split(",")
+
+    def ctx_for(p, s_max):
+        X = torch.as_tensor(p.X, dtype=torch.float32, device=dev).contiguous()
+        H = torch.as_tensor(p.H, dtype=torch.float32, device=dev).contiguous()
+        return RelaxContext(X, H, p.n_pool, s_max, "f32")
+
+    # CIFAR-10 shape of the accuracy experiments (Table 4): n = 3000, d = 20, c = 10, n_o = 10
+    small = make_problem(2, n=3000, n_lab=10, d=20, c=10, s=10, b=10.0, K=10, seed=7010)
+    if "fig1" in parts:
+        log("fig1: CG and PCG residuals")
+        p = small
+        ctx = ctx_for(p, p.s)
+        om = torch.full((p.N,), 1.0, dtype=torch.float64, device=dev)
+        om[:p.n_pool] = p.b / p.n_pool
+        V = ctx.probes(p.probe_seed, 1, p.s)
+        _, Pinv, _ = ctx.build_precond(om, p.lam, want_L=False)
+        eye = torch.eye(p.d, dtype=torch.float64, device=dev).expand(p.c, p.d, p.d).contiguous()
+        variants = {"cg": (eye, False), "cg_projected": (eye, True),
+                    "pcg": (Pinv, False), "pcg_projected": (Pinv, True)}
+        fig1 = {}
+        for name, (P, proj) in variants.items():
+            curve = []
+            for k in range(1, 61):
+                _, info = ctx.pcg_solve(V, P, om, p.lam, tol=0.0, max_iter=k, project=proj)
+                curve.append(info["relres_max"])
+            _, info = ctx.pcg_solve(V, P, om, p.lam, tol=1e-6, max_iter=5000, project=proj)
+            fig1[name] = {"relres_after_k": curve, "iters_to_1e-6": info["cg_iters"][0]}
+        ctx.close()
+        res["fig1"] = {"problem": "n = 3000 + 10, d = 20, c = 10, s = 10, z = b/n (first "
+                                  "mirror-descent iteration), lambda = 1e-3",
+                       "variants": fig1}
+    if "fig4" in parts:
+        log("fig4: objective trajectories")
+        p = small
+        dc = p.d * p.c
+        ctx = ctx_for(p, dc)
+        U = torch.zeros((p.d, dc, p.c), dtype=torch.float32, device=dev)   # all unit probes
+        for k in range(p.c):
+            for a in range(p.d):
+                U[a, k * p.d + a, k] = 1.0
+
+        def exact_f(w):
+            f, _, _ = ctx.sampled_objective((p.b * w).contiguous(), p.lam, U, tol=1e-9,
+                                            max_iter=5000, project=False, grad=False)
+            return f * dc
+        T = 30
+        beta0 = default_beta0(p.n_pool, T)
+        runs = {}
+        for s_, tol in ((2, 1e-3), (10, 1e-3), (50, 1e-3), (10, 1e-1), (10, 1e-6)):
+            w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
+            traj = {0: exact_f(w)}
+            for t in range(1, T + 1):
+                ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, s_, tol, 5000, True)
+                if t in (1, 2, 5, 10, 20, 30):
+                    traj[t] = exact_f(w)
+            runs[f"s={s_},cg_tol={tol:g}"] = traj
+        ctx.close()
+        res["fig4"] = {"problem": "n = 3000 + 10, d = 20, c = 10, b = 10, T = 30, projected "
+                                  "PCG; f exact (all dc unit probes, PCG to 1e-9)",
+                       "objective_at_iteration": runs}
+    if "fig5" in parts:
+        fig5 = {"d_sweep": {}, "c_sweep": {}}
+
+        def one(name, n, n_lab, d, c, key, store):
+            log(f"fig5: {name}")
+            pr = dict(n=n, n_lab=n_lab, d=d, c=c, s=10, b=float(c), lam=1e-3, tol=1e-6, T=1,
+                      K=c, whiten=False, probs="maxprob")
+            q = draw_device(name, pr, 9000 + d + c, 9500 + d + c, dev, torch.float32)
+            ctx = RelaxContext(q.X, q.H, q.n_pool, 10, "f32")
+            om = torch.full((q.N,), 1.0, dtype=torch.float64, device=dev)
+            om[:q.n_pool] = q.b / q.n_pool
+            ctx.build_precond(om, q.lam, want_L=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, Pinv, _ = ctx.build_precond(om, q.lam, want_L=False)
+            torch.cuda.synchronize()
+            t_pre = time.perf_counter() - t0
+            V = ctx.probes(q.probe_seed, 1, 10)
+            t0 = time.perf_counter()
+            ctx.pcg_solve(V, Pinv, om, q.lam, tol=0.0, max_iter=50, project=True)
+            torch.cuda.synchronize()
+            t_cg = time.perf_counter() - t0
+            z = om[:q.n_pool].contiguous()
+            rs = RoundSolver(ctx, z, q.lam, 8.0 * (d * c) ** 0.5, 2, fp32=True)
+            ctx.profile_begin()
+            t0 = time.perf_counter()
+            rs.step(1)
+            rs.result()
+            t_round = time.perf_counter() - t0
+            k_ms, _ = ctx.profile_end()
+            rs.close()
+            ctx.close()
+            del q, ctx, Pinv, V
+            torch.cuda.empty_cache()
+            store[key] = {"n": n, "d": d, "c": c, "precond_s": t_pre, "cg50_s": t_cg,
+                          "round_s": t_round, "round_score_s": k_ms / 1e3,
+                          "round_other_s": t_round - k_ms / 1e3}
+        for d in (383, 766, 1022):
+            one(f"d{d}", 100000, 1000, d, 1000, d, fig5["d_sweep"])
+        for c in (100, 200, 400, 800, 1000):
+            one(f"c{c}", 1280000, 2000, 383, c, c, fig5["c_sweep"])
+        res["fig5"] = dict(fig5, problem="d sweep: n = 1e5, c = 1000; c sweep: n = 1.28e6, "
+                                         "d = 383; s = 10, 50 fixed CG iterations, FP32; one "
+                                         "Round round with the FP32 decision")
+    print(json.dumps({"workload": "studies", "data": "synthetic", "results": res}))
+
+
 def large_workload(args):
     """Configurations 3 and 4: FP32 and bf16x3 legs plus the FP64 reference gradient."""
     import numpy as np
@@ -559,6 +686,9 @@ def main():
         sys.exit(2)
     if args.workload == "table5":
         table5_workload(args)
+        return
+    if args.workload == "studies":
+        studies_workload(args)
         return
     args.workload = int(args.workload)
     if args.workload == 5:

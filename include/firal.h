@@ -229,7 +229,7 @@ int firal_batch_destroy(firal_batch batch);
  * objective's numerator holds Sigma_o itself, as the proposition's proof derives it (the stated
  * objective prints its inverse).  Arithmetic is FP64 (FP32 X and H are read exactly) except
  * the objective in FIRAL_ROUND_FP32 mode.
- * Requires d <= 512 and c <= 30000.  The state borrows the context (X and H): destroy it first. */
+ * Requires d <= 1024 and c <= 65535.  The state borrows the context (X and H): destroy it first. */
 typedef struct firal_round_s* firal_round;
 
 /* firal_round_create flag: evaluate the per-point objective (the two quadratic forms, the class

@@ -28,7 +28,7 @@ namespace firal {
 
 namespace {
 
-constexpr int kMaxD = 512;          // d limit of the Round step (LDS rows of the update)
+constexpr int kMaxD = 1024;         // d limit of the Round step (LDS rows of the update)
 constexpr int kScoreTM = 64, kScoreTN = 64, kScoreTK = 16, kScorePad = 4;
 constexpr int kTriThreads = 512;
 // tridiagonalisation in LDS up to this d (d^2 doubles), in global memory above

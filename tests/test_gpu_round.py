@@ -147,6 +147,13 @@ def test_round_reduced_configuration_3_shape():
     check_run(p, "f32", b=1000, eta=50.0, rounds=2)
 
 
+def test_round_wide_features():
+    # d = 600: the global-memory tridiagonalisation, factor and inverse of D (d > 256), ten
+    # column tiles per class
+    p = make_small(n=1500, n_lab=10, d=600, c=3, s=1, seed=25)
+    check_run(p, "f32", b=20, eta=30.0, rounds=3)
+
+
 def test_round_eta_sweep_matches_oracle():
     p = make_small(n=300, n_lab=5, d=10, c=4, s=1, seed=23)
     ctx, z, zn, Xo, Ho = setup(p, "f64", 8)
