@@ -246,8 +246,9 @@ typedef struct firal_round_s* firal_round;
  * Errors: EINVAL, ENOTSPD (a Sigma_o block is not positive definite), EHIP, ENOMEM. */
 int firal_round_create(firal_round* out, firal_ctx ctx, const double* z, double lambda,
                        double eta, int32_t b, uint32_t flags, void* stream);
-/* Enqueue the next `rounds` rounds (asynchronous; nothing is read back, so the calls may be
- * captured).  EINVAL if fewer than `rounds` of the b rounds are left. */
+/* Enqueue the next `rounds` rounds (asynchronous: nothing is read back and the host does not
+ * wait; each round's index is fixed when it is enqueued, so a captured call replays the same
+ * rounds).  EINVAL if fewer than `rounds` of the b rounds are left. */
 int firal_round_step(firal_round round, int32_t rounds, void* stream);
 /* The per-point objective of every pool row at the current round (device FP64 [n_pool];
  * selected rows get -inf).  Asynchronous; changes no state. */

@@ -24,7 +24,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "gaussian_mixture", "whiten", "softmax_rows", "tune_tau_maxprob",
-    "entropy_spread_probs", "make_problem", "dirichlet_weights", "CONFIGS",
+    "entropy_spread_probs", "make_problem", "dirichlet_weights", "labeled_mixture", "CONFIGS",
 ]
 
 
@@ -62,6 +62,16 @@ def gaussian_mixture(rng: np.random.Generator, n: int, d: int, k: int,
     out = rng.standard_normal((n, d))
     out += means[lab]
     return out
+
+
+def labeled_mixture(rng: np.random.Generator, n: int, d: int, c: int,
+                    mean_std: float = 0.5) -> tuple:
+    """n rows from c equally weighted unit-variance clusters with means ~ N(0, mean_std^2 I),
+    and each row's cluster as its class label (for active-learning loops with known labels)."""
+    means = rng.standard_normal((c, d)) * mean_std
+    y = rng.integers(0, c, size=n)
+    X = rng.standard_normal((n, d)) + means[y]
+    return X, y
 
 
 def whiten(X: np.ndarray) -> np.ndarray:
