@@ -42,7 +42,10 @@ KERNEL_NAME = {"f32": "k_hvp_fused<7,1> (fused Lemma 1 product, FP32)",
 # HBM bytes per launch of the main kernel from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # each scaled by the copy-kernel calibration factor (profiles/; None until measured for
 # the current kernel)
-TRAFFIC = {"f32": (24.01 + 9.69) * 1e6}   # k_hvp_fused<7,1>: fetched + written bytes per launch
+TRAFFIC = {"f32": (24.01 + 9.69) * 1e6,    # k_hvp_fused<7,1>: fetched + written bytes per launch
+           "bf16x3": (45.71 + 17.96) * 1e6}  # k_hvp_fused_bf3<7,2>
+# the same for the Round step's scoring kernel at configuration 2 (per round, one launch)
+ROUND_TRAFFIC = {True: (29.50 + 2.00) * 1e6, False: (36.69 + 4.00) * 1e6}
 
 
 def parse():
@@ -230,7 +233,7 @@ def round_leg(p, w, eta, fp32, cpu_rounds=2):
             "roofline": {"bound": "mfma", "kernel": kname,
                          "achieved": flops / t_kern / 1e12, "peak": pk,
                          "unit": "TFLOP/s", "frac": flops / t_kern / 1e12 / pk,
-                         "kernel_us": t_kern * 1e6, "traffic": None,
+                         "kernel_us": t_kern * 1e6, "traffic": ROUND_TRAFFIC[fp32],
                          "executed_tflops": 1.5 * flops / t_kern / 1e12},
             "cpu_oracle": {"s_per_round": t_cpu, "rounds_timed": cpu_rounds,
                            "same_first_selections": same}}
@@ -820,6 +823,7 @@ def main():
                                "hvp_ms": v["t_hvp"] * 1e3, "hvp_tflops": v["hvp_tflops"],
                                "kernel_us": v["t_kern"] * 1e6, "kernel_tflops": v["kern_tflops"],
                                "mean_cg_iters_per_step": v["cg"],
+                               "kernel_traffic_bytes": TRAFFIC.get(k),
                                "rel_grad_err_vs_f64": errs.get(k)}
                            for k, v in legs.items()},
         "roofline": {"bound": "mfma", "kernel": KERNEL_NAME.get(args.prec),

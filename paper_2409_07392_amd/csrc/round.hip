@@ -387,7 +387,8 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
 // walks the class's d columns in tiles of 64, each tile accumulating the matching u and v
 // columns (four waves of 32 x 32 each, 16x16x4 MFMA, stages of 16 k-rows double-buffered
 // through LDS; a u block skips the stages below its triangle) and adds u . v and v . v per row
-// to LDS slots.  Workgroups are ordered class-major (XCD-aware), so one XCD's tiles share W_k.
+// to LDS slots.  Workgroup order (XCD-aware): row tile then class when all class operands
+// fit in L2 together, else class then row tile.
 // CT is the decision precision: every step from the products to the class term is computed
 // in CT (FP64, or FP32 on the FP32 MFMA as the paper's single-precision implementation does).
 template <typename T, typename CT>
@@ -395,7 +396,8 @@ __global__ __launch_bounds__(256, 2) void k_round_score(const T* __restrict__ X,
                                                      const T* __restrict__ H, int64_t r0,
                                                      int64_t R, int d, int c,
                                                      const CT* __restrict__ W, int ldo,
-                                                     double eta, CT* __restrict__ Tout) {
+                                                     double eta, int rows_major,
+                                                     CT* __restrict__ Tout) {
   constexpr int TM = kScoreTM, TN = kScoreTN, TK = kScoreTK;
   constexpr int SA = TM + kScorePad, SB = TN + kScorePad;
   __shared__ CT As[2][TK][SA];
@@ -407,8 +409,11 @@ __global__ __launch_bounds__(256, 2) void k_round_score(const T* __restrict__ X,
   const int li = lane & 15, g = lane >> 4;
   const int64_t ntr = (R + TM - 1) / TM;
   const int64_t lid = xcd_lid_r(blockIdx.x, (int64_t)gridDim.x);
-  const int k = (int)(lid / ntr);
-  const int64_t row0 = (lid - (int64_t)k * ntr) * TM;
+  // rows_major: consecutive workgroups walk the classes of one row tile (the X tile is reused
+  // from L2, every class operand stays resident); else the row tiles of one class (W_k stays
+  // resident while X streams)
+  const int k = rows_major ? (int)(lid % c) : (int)(lid / ntr);
+  const int64_t row0 = (rows_major ? lid / c : lid - (int64_t)k * ntr) * TM;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const CT* Wk = W + (int64_t)k * d * 2 * ldo;
   const int nst = (d + TK - 1) / TK;
@@ -786,8 +791,10 @@ static int round_score_t(Round* r, const CT* W, double* r_out, hipStream_t st) {
     const int64_t R = std::min<int64_t>(r->R, r->n_pool - r0);
     const int64_t nwg = cdiv(R, kScoreTM) * r->c;
     FIRAL_CHECK(prof_mark(r->x, st, true));
+    // all c operands (d x 2 ldo each) within 2 MiB: walk the classes of a row tile together
+    const int rows_major = (int64_t)r->c * r->d * 2 * r->ldo * sizeof(CT) <= ((int64_t)2 << 20);
     k_round_score<T, CT><<<(unsigned)nwg, 256, 0, st>>>(X, H, r0, R, r->d, r->c, W, r->ldo,
-                                                        r->eta, Tb);
+                                                        r->eta, rows_major, Tb);
     FIRAL_LAUNCHED();
     FIRAL_CHECK(prof_mark(r->x, st, false));
     k_round_rsum<CT><<<(unsigned)cdiv(R, 256), 256, 0, st>>>(Tb, R, r->c, r0, r->mask, r_out,
