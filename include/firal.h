@@ -111,8 +111,9 @@ int firal_build_precond(firal_ctx ctx, const double* omega, double shift, double
                         double* Pinv, firal_info* info, void* stream);
 
 /* Block-Jacobi preconditioned CG for (sum_i omega_i H_i + shift I) Xsol_j = B_j, all s
- * columns in lock-step from x0 = 0 (Algorithm 2, solve lines).  Pinv: device FP64
- * c x d x d from firal_build_precond.  Column j stops once ||r_j|| <= tol ||b_j||; the
+ * columns in lock-step from x0 = 0 (the two solves of Algorithm 2).  Pinv: device FP64
+ * c x d x d from firal_build_precond.  B, Xsol: device blocks d x s x c that either
+ * coincide or do not overlap.  Column j stops once ||r_j|| <= tol ||b_j||; the
  * loop ends when all have stopped or after max_iter iterations (tol = 0: exactly
  * max_iter).  flags: FIRAL_PCG_PROJECT.  Synchronous; returns WARN_NOT_CONVERGED or
  * EBREAKDOWN; info (host, may be NULL) gets cg_iters[0], converged, relres_max. */

@@ -64,12 +64,14 @@ int prof_mark(Ctx* x, hipStream_t st, bool start) {
 static void free_ctx(Ctx* x) {
   drop_events(x);
   void* bufs[] = {x->G, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->XThi, x->XTlo, x->P, x->Pinv, x->syrk_part, x->syrk_tiles, x->V, x->W1, x->Y,
-                  x->W2, x->cx, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
+                  x->W2, x->cx, x->cgd, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
-                  x->redpart, x->status, x->counter, x->t_dev};
+                  x->redpart, x->status, x->t_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (x->status_host) (void)hipHostFree(x->status_host);
+  for (void* e : x->chk_ev)
+    if (e) (void)hipEventDestroy((hipEvent_t)e);
   delete x;
 }
 
@@ -261,6 +263,7 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   ALLOC(x->Y, blk * es);
   ALLOC(x->W2, blk * es);
   ALLOC(x->cx, blk * es);
+  if (col_cg_scratch(d, c, s_max) > 0) ALLOC(x->cgd, col_cg_scratch(d, c, s_max) * 8);
   ALLOC(x->cr, blk * es);
   ALLOC(x->cz, blk * es);
   ALLOC(x->cp, blk * es);
@@ -278,20 +281,27 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   ALLOC(x->done, 2 * s_max * 4);   // two flag buffers (column-local CG)
   ALLOC(x->redpart, (3 * (int64_t)x->red_blocks + 1) * 8);
   ALLOC(x->status, sizeof(Status));
-  ALLOC(x->counter, sizeof(int32_t));
   ALLOC(x->t_dev, sizeof(int32_t));
 #undef ALLOC
   if (rc == FIRAL_OK) {
-    hipError_t he = hipHostMalloc((void**)&x->status_host, sizeof(Status), hipHostMallocDefault);
+    hipError_t he = hipHostMalloc((void**)&x->status_host, 3 * sizeof(Status), hipHostMallocDefault);
     if (he != hipSuccess) {
       set_error("hipHostMalloc failed: %s", hipGetErrorString(he));
       rc = FIRAL_ENOMEM;
+    }
+    for (int i = 0; i < 2 && rc == FIRAL_OK; ++i) {
+      hipEvent_t e = nullptr;
+      he = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+      if (he != hipSuccess) {
+        set_error("hipEventCreateWithFlags failed: %s", hipGetErrorString(he));
+        rc = FIRAL_EHIP;
+      }
+      x->chk_ev[i] = e;
     }
   }
   if (rc == FIRAL_OK) {
     hipStream_t st = (hipStream_t)stream;
     if (hipMemsetAsync(x->status, 0, sizeof(Status), st) != hipSuccess ||
-        hipMemsetAsync(x->counter, 0, sizeof(int32_t), st) != hipSuccess ||
         hipMemcpyAsync(x->syrk_tiles, syrk_tiles.data(), syrk_tiles.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
         (prec == FIRAL_BF16X3 && split_x_launch(x, st) != FIRAL_OK) ||

@@ -114,6 +114,7 @@ struct Ctx {
   // per-column scalars and reduction partials
   int col_parts;        // partial sums per column
   double* colpart;      // 4 * s_max * col_parts
+  double* cgd;          // column-local CG: rd and zd, 2 * d * c * s_max (null when unused)
   double* rho;          // s_max
   double* bnorm;        // s_max
   double* alpha;        // s_max
@@ -123,9 +124,9 @@ struct Ctx {
   int red_blocks;       // blocks of the n_pool reductions
   double* redpart;      // 3 * red_blocks
 
-  int32_t* counter;     // device: arrival counter of the column-local CG kernels (kept at 0)
   Status* status;       // device
-  Status* status_host;  // pinned host mirror
+  Status* status_host;  // pinned host mirror: [0] end-of-call reads, [1], [2] PCG check points
+  void* chk_ev[2];      // hipEvent_t recorded after each PCG check point's status copy
 
   // firal_profile_begin/end: event pairs around each main product kernel
   int profiling;
@@ -285,6 +286,8 @@ int gram64_launch(int prec, const void* X, const void* H, const double* omega, i
 // failing block.
 int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool want_inv,
                        hipStream_t st);
+// doubles of column-local CG scratch for d, c, s_max; 0 when that path does not fit
+int64_t col_cg_scratch(int d, int c, int s_max);
 int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,
                void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
                hipStream_t st);

@@ -256,12 +256,21 @@ __global__ void k_cg_finish(Status* st, int slot) {
 // Every vector operation of a CG iteration except the Hessian product acts on one probe
 // column j alone: alpha_j needs <p_j, q_j>, the residual test, the projection (a mean over
 // the classes of each feature) and z_j = M^-1 r_j (one d x d product per class) stay inside
-// the column.  One block per column does the whole step with r_j and z_j in LDS (FP64), so a
-// CG iteration is the product plus this kernel.  The last block to finish (counter) folds
-// the per-column flags into the status.  Used when 2 d c doubles fit in LDS.
+// the column.  A CG iteration is the product plus three small kernels (k_cg_col_alpha,
+// k_cg_col_apply, k_cg_col_beta below) that keep the column vectors in LDS (FP64) and spread
+// the block apply over classes; k_cg_col_init starts a solve with one block per column, and
+// k_col_status folds the per-column flags into the status at each check point.  Used when
+// (3 + kColSplit) d c doubles fit in LDS.
 
 constexpr int kColThreads = 1024;
 constexpr int kColSplit = 4;     // each output of the apply is summed in 4 pieces over b
+constexpr int kApplyCols = 4;    // columns per block of k_cg_col_apply
+
+int64_t col_cg_scratch(int d, int c, int s_max) {
+  // the column-local path needs the init kernel's (3 + kColSplit) d c doubles in LDS
+  if ((int64_t)(3 + kColSplit) * d * c * 8 > 128 * 1024) return 0;
+  return 2 * (int64_t)d * c * s_max;
+}
 
 __device__ __forceinline__ double block_sum_col(double v, double* red) {
   v = wave_sum(v);
@@ -388,17 +397,27 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_init(const T* __restrict
   }
 }
 
-// One CG iteration for column j.  done_prev holds every column's flag after the previous
-// iteration (read-only here); done_next receives this iteration's flags, so no block ever
-// reads a flag another block of the same launch writes.
+// One CG iteration of column j in three kernels around the block apply.  done_prev holds
+// every column's flag after the previous iteration (read-only here); done_next receives this
+// iteration's flags, so no block ever reads a flag another block of the same launch writes.
+//
+// k_cg_col_alpha (one block per column): alpha = rho / <p, q>, x += alpha p, r -= alpha q,
+// projection of r, the residual test; an active column leaves its stored r, projected once
+// more in FP64, in rd ([column][class][feature]).
+// k_cg_col_apply (one block per class and group of columns): zd = P_k^-1 rd for the group,
+// so each block of P^-1 is read once per group instead of once per column.
+// k_cg_col_beta (one block per column): projection of z, rz = <r, z>, beta = rz / rho,
+// p = z + beta p.
+// The reductions keep one element per thread in the same order in all three, and the apply
+// sums each output in kColSplit pieces over b exactly as col_apply does.
 template <typename T>
-__global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv, T* __restrict__ r,
-                                                     T* __restrict__ p, const T* __restrict__ q,
-                                                     const double* __restrict__ Pinv, int d, int s,
-                                                     int c, int project, double tol, double* rho,
-                                                     const double* bnorm, double* relres,
-                                                     const int32_t* done_prev, int32_t* done_next,
-                                                     Status* st) {
+__global__ __launch_bounds__(kColThreads) void k_cg_col_alpha(T* __restrict__ xv, T* __restrict__ r,
+                                                      const T* __restrict__ p,
+                                                      const T* __restrict__ q, int d, int s,
+                                                      int c, int project, double tol, double* rho,
+                                                      const double* bnorm, double* relres,
+                                                      const int32_t* done_prev, int32_t* done_next,
+                                                      double* __restrict__ rd, Status* st) {
   if (skip_now(skip_all(done_prev, s))) {
     // nothing left: carry the flags forward so the next launch reads a current set
     if (threadIdx.x == 0) done_next[blockIdx.x] = 1;
@@ -406,15 +425,11 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv,
   }
   extern __shared__ double sh[];
   __shared__ double red[kColThreads / 64];
-  double* rs = sh;
-  double* zs = sh + d * c;
-  double* zp = zs + d * c;
-  double* r0s = zp + kColSplit * d * c;
+  double* r0s = sh;   // [c][d]
   const int j = blockIdx.x, n = d * c;
   const int64_t sc = (int64_t)s * c;
-  const bool was_done = done_prev[j] != 0;
   if (j == 0 && threadIdx.x == 0) st->iters += 1;
-  if (was_done) {
+  if (done_prev[j] != 0) {
     if (threadIdx.x == 0) done_next[j] = 1;
     return;
   }
@@ -461,7 +476,6 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv,
     const int l = k * d + a;
     const T rv = (T)r0s[l];
     r[a * sc + (int64_t)j * c + k] = rv;
-    rs[l] = (double)rv;
     r0s[l] = (double)rv;
     rr += (double)rv * (double)rv;
   }
@@ -473,8 +487,105 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_step(T* __restrict__ xv,
     relres[j] = bnorm[j] > 0.0 ? rn / bnorm[j] : 0.0;
   }
   if (now_done) return;
-  // rz = <r, M^-1 r> with the stored (unprojected) r, kept in r0s; col_apply may project rs
-  col_apply(Pinv, rs, zs, zp, d, c, project);
+  // the apply's input: the stored r, projected again in FP64 when asked
+  double* rj = rd + (int64_t)j * n;
+  if (project) {
+    for (int a = threadIdx.x; a < d; a += blockDim.x) {
+      double m = 0.0;
+      for (int k = 0; k < c; ++k) m += r0s[k * d + a];
+      m /= c;
+      for (int k = 0; k < c; ++k) rj[k * d + a] = r0s[k * d + a] - m;
+    }
+  } else {
+    for (int e = threadIdx.x; e < n; e += blockDim.x) rj[e] = r0s[e];
+  }
+}
+
+// zd[j][k][:] = P_k^-1 rd[j][k][:] for class k = blockIdx.x and the JT columns of group
+// blockIdx.y; columns whose flag is set are skipped.  LDS: rd of the group (JT d doubles)
+// and the kColSplit partial sums (kColSplit JT d doubles).
+template <int JT>
+__global__ __launch_bounds__(512) void k_cg_col_apply(const double* __restrict__ Pinv,
+                                                      const double* __restrict__ rd,
+                                                      double* __restrict__ zd, int d, int s,
+                                                      int c, const int32_t* done) {
+  extern __shared__ double sh[];
+  double* rsh = sh;              // [JT][d]
+  double* zp = sh + JT * d;      // [kColSplit][JT][d]
+  const int k = blockIdx.x, j0 = blockIdx.y * JT;
+  const int jn = min(JT, s - j0);
+  const int n = d * c;
+  int active = 0;
+  for (int jj = 0; jj < jn; ++jj) active |= done[j0 + jj] == 0;
+  if (!active) return;   // the same for every thread of the block
+  for (int e = threadIdx.x; e < JT * d; e += blockDim.x) {
+    const int jj = e / d, b = e - jj * d;
+    rsh[e] = jj < jn ? rd[(int64_t)(j0 + jj) * n + (int64_t)k * d + b] : 0.0;
+  }
+  __syncthreads();
+  const double* Pk = Pinv + (int64_t)k * d * d;
+  const int piece = (d + kColSplit - 1) / kColSplit;
+  for (int w = threadIdx.x; w < kColSplit * d; w += blockDim.x) {
+    const int qq = w / d, a = w - qq * d;
+    const int b0 = qq * piece, b1 = min(d, b0 + piece);
+    double acc[JT];
+#pragma unroll
+    for (int jj = 0; jj < JT; ++jj) acc[jj] = 0.0;
+    for (int bb = b0; bb < b1; bb += 16) {
+      // sixteen independent loads in flight before the products
+      double pv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) pv[u] = bb + u < b1 ? Pk[(int64_t)(bb + u) * d + a] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (bb + u < b1) {
+#pragma unroll
+          for (int jj = 0; jj < JT; ++jj) acc[jj] += pv[u] * rsh[jj * d + bb + u];
+        }
+    }
+#pragma unroll
+    for (int jj = 0; jj < JT; ++jj) zp[(qq * JT + jj) * d + a] = acc[jj];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < jn * d; e += blockDim.x) {
+    const int jj = e / d, a = e - jj * d;
+    double z = 0.0;
+#pragma unroll
+    for (int qq = 0; qq < kColSplit; ++qq) z += zp[(qq * JT + jj) * d + a];
+    zd[(int64_t)(j0 + jj) * n + (int64_t)k * d + a] = z;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kColThreads) void k_cg_col_beta(const T* __restrict__ r,
+                                                     T* __restrict__ p,
+                                                     const double* __restrict__ zd, int d,
+                                                     int s, int c, int project, double* rho,
+                                                     const int32_t* done) {
+  const int j = blockIdx.x, n = d * c;
+  if (done[j] != 0) return;
+  extern __shared__ double sh[];
+  __shared__ double red[kColThreads / 64];
+  double* zs = sh;       // [c][d]
+  double* r0s = sh + n;  // [c][d]
+  const int64_t sc = (int64_t)s * c;
+  const double* zj = zd + (int64_t)j * n;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) zs[e] = zj[e];
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int a = e / c, k = e - a * c;
+    r0s[k * d + a] = (double)r[a * sc + (int64_t)j * c + k];
+  }
+  __syncthreads();
+  if (project) {
+    for (int a = threadIdx.x; a < d; a += blockDim.x) {
+      double m = 0.0;
+      for (int k = 0; k < c; ++k) m += zs[k * d + a];
+      m /= c;
+      for (int k = 0; k < c; ++k) zs[k * d + a] -= m;
+    }
+    __syncthreads();
+  }
+  // rz = <r, M^-1 r> with the stored (unprojected) r
   double rz = 0.0;
   for (int e = threadIdx.x; e < n; e += blockDim.x) rz += r0s[e] * (double)(T)zs[e];
   rz = block_sum_col(rz, red);
@@ -556,16 +667,34 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
   const unsigned nb = (unsigned)cdiv(n, 256);
 
   const size_t col_lds = (size_t)(3 + kColSplit) * d * c * sizeof(double);
-  if (col_lds <= 128 * 1024 && !x->force_multik) {
-    // column-local CG: init, then per iteration the product and one step kernel
+  if (x->cgd && !x->force_multik) {
+    // column-local CG: init, then per iteration the product and the three column kernels.
+    // The iterate lives in the solution buffer itself when the caller gives one.
+    if (Xsol && Xsol != B && Xsol != r && Xsol != p && Xsol != q) xv = Xsol;
     static bool attr[2] = {false, false};
     if (!attr[sizeof(T) == 8]) {
       FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_init<T>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
-      FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_step<T>,
+      FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_alpha<T>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+      FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_beta<T>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+      FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_apply<1>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
+      FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_apply<kApplyCols>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
       attr[sizeof(T) == 8] = true;
     }
+    double* rd = x->cgd;
+    double* zd = x->cgd + (int64_t)d * c * x->s_max;
+    const size_t alpha_lds = (size_t)d * c * sizeof(double);
+    const size_t beta_lds = 2 * alpha_lds;
+    // columns per apply block: kApplyCols while its LDS (rd and the partial sums of the
+    // group) stays within 64 KiB, else one
+    const int jt = (size_t)(1 + kColSplit) * kApplyCols * d * sizeof(double) <= 64 * 1024
+                       ? kApplyCols : 1;
+    const size_t apply_lds = (size_t)(1 + kColSplit) * jt * d * sizeof(double);
+    const dim3 apply_grid((unsigned)c, (unsigned)cdiv(s, jt));
     int32_t* flags[2] = {x->done, x->done + x->s_max};
     k_cg_col_init<T><<<s, kColThreads, col_lds, st>>>(B, xv, r, p, Pinv, d, s, c, project, x->rho,
                                                       x->bnorm, x->relres, flags[0], x->status);
@@ -576,26 +705,50 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
     const bool mixed = x->prec == FIRAL_BF16X3 && tol > 0.0 && !x->async;
     bool precise = false;
     const int check_every = tol > 0.0 && !x->async ? 4 : (max_iter > 0 ? max_iter : 1);
-    int launched = 0;
+    // Check points are pipelined: the status of batch k is copied to a host slot behind an
+    // event, and the host waits for it only after batch k+1 is enqueued, so the GPU never
+    // idles on the host.  A batch enqueued after convergence costs only launches whose
+    // kernels skip on the device flags.  While the bf16x3 switch is pending the check is
+    // synchronous, so the switch takes effect at the next batch.
+    int launched = 0, hslot = 0;
+    bool pending = false;   // a check point copy (hslot ^ 1) not yet read
     while (launched < max_iter) {
       const int batch = std::min(check_every, max_iter - launched);
       for (int it = 0; it < batch; ++it) {
         const int32_t* dp = flags[(launched + it) & 1];
         int32_t* dn = flags[(launched + it + 1) & 1];
         FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip_all(dp, s), st, precise));
-        k_cg_col_step<T><<<s, kColThreads, col_lds, st>>>(xv, r, p, q, Pinv, d, s, c, project, tol,
-                                                          x->rho, x->bnorm, x->relres, dp, dn,
-                                                          x->status);
+        k_cg_col_alpha<T><<<s, kColThreads, alpha_lds, st>>>(xv, r, p, q, d, s, c, project, tol,
+                                                             x->rho, x->bnorm, x->relres, dp, dn,
+                                                             rd, x->status);
+        FIRAL_LAUNCHED();
+        if (jt == kApplyCols)
+          k_cg_col_apply<kApplyCols><<<apply_grid, 512, apply_lds, st>>>(Pinv, rd, zd, d, s, c, dn);
+        else
+          k_cg_col_apply<1><<<apply_grid, 512, apply_lds, st>>>(Pinv, rd, zd, d, s, c, dn);
+        FIRAL_LAUNCHED();
+        k_cg_col_beta<T><<<s, kColThreads, beta_lds, st>>>(r, p, zd, d, s, c, project, x->rho, dn);
         FIRAL_LAUNCHED();
       }
       launched += batch;
       k_col_status<<<1, 256, 0, st>>>(flags[launched & 1], x->relres, s, x->status);
       FIRAL_LAUNCHED();
-      if (launched < max_iter) {
+      if (launched >= max_iter) break;
+      if (mixed && !precise) {
         FIRAL_CHECK(read_status(x, st));
         if (x->status_host->all_done) break;
-        if (mixed && x->status_host->relres_max < x->bf3_switch) precise = true;
+        if (x->status_host->relres_max < x->bf3_switch) precise = true;
+        continue;
       }
+      Status* hs = x->status_host + 1 + hslot;
+      FIRAL_HIP(hipMemcpyAsync(hs, x->status, sizeof(Status), hipMemcpyDeviceToHost, st));
+      FIRAL_HIP(hipEventRecord((hipEvent_t)x->chk_ev[hslot], st));
+      hslot ^= 1;
+      if (pending) {
+        FIRAL_HIP(hipEventSynchronize((hipEvent_t)x->chk_ev[hslot]));
+        if (x->status_host[1 + hslot].all_done) break;
+      }
+      pending = true;
     }
     if (max_iter == 0) {
       k_col_status<<<1, 256, 0, st>>>(flags[0], x->relres, s, x->status);
@@ -603,7 +756,8 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
     }
     k_cg_finish<<<1, 1, 0, st>>>(x->status, slot);
     FIRAL_LAUNCHED();
-    if (Xsol != xv) FIRAL_HIP(hipMemcpyAsync(Xsol, xv, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (Xsol && Xsol != xv)
+      FIRAL_HIP(hipMemcpyAsync(Xsol, xv, n * sizeof(T), hipMemcpyDeviceToDevice, st));
     return FIRAL_OK;
   }
 
