@@ -70,8 +70,7 @@ static void free_ctx(Ctx* x) {
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (x->status_host) (void)hipHostFree(x->status_host);
-  for (void* e : x->chk_ev)
-    if (e) (void)hipEventDestroy((hipEvent_t)e);
+  if (x->chk_word) (void)hipHostFree(x->chk_word);
   delete x;
 }
 
@@ -284,20 +283,21 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   ALLOC(x->t_dev, sizeof(int32_t));
 #undef ALLOC
   if (rc == FIRAL_OK) {
-    hipError_t he = hipHostMalloc((void**)&x->status_host, 3 * sizeof(Status), hipHostMallocDefault);
+    hipError_t he = hipHostMalloc((void**)&x->status_host, sizeof(Status), hipHostMallocDefault);
     if (he != hipSuccess) {
       set_error("hipHostMalloc failed: %s", hipGetErrorString(he));
       rc = FIRAL_ENOMEM;
     }
-    for (int i = 0; i < 2 && rc == FIRAL_OK; ++i) {
-      hipEvent_t e = nullptr;
-      he = hipEventCreateWithFlags(&e, hipEventDisableTiming);
-      if (he != hipSuccess) {
-        set_error("hipEventCreateWithFlags failed: %s", hipGetErrorString(he));
-        rc = FIRAL_EHIP;
-      }
-      x->chk_ev[i] = e;
+    // check-point words written by the PCG kernels and polled by the host (zero: no tag)
+    if (rc == FIRAL_OK &&
+        (hipHostMalloc((void**)&x->chk_word, 2 * (size_t)s_max * sizeof(uint32_t),
+                       hipHostMallocCoherent) != hipSuccess ||
+         hipHostGetDevicePointer((void**)&x->chk_word_dev, x->chk_word, 0) != hipSuccess)) {
+      (void)hipGetLastError();
+      set_error("pinned check-point words could not be allocated or mapped");
+      rc = FIRAL_ENOMEM;
     }
+    if (rc == FIRAL_OK) std::memset(x->chk_word, 0, 2 * (size_t)s_max * sizeof(uint32_t));
   }
   if (rc == FIRAL_OK) {
     hipStream_t st = (hipStream_t)stream;

@@ -125,8 +125,11 @@ struct Ctx {
   double* redpart;      // 3 * red_blocks
 
   Status* status;       // device
-  Status* status_host;  // pinned host mirror: [0] end-of-call reads, [1], [2] PCG check points
-  void* chk_ev[2];      // hipEvent_t recorded after each PCG check point's status copy
+  Status* status_host;  // pinned host mirror
+  uint32_t chk_tag;     // tag of the last column-local PCG iteration enqueued
+  uint32_t* chk_word;   // pinned coherent host memory [2][s_max], one word per column:
+                        //   (tag << 2) | (relres < bf3_switch) << 1 | column stopped
+  uint32_t* chk_word_dev;  // its device address
 
   // firal_profile_begin/end: event pairs around each main product kernel
   int profiling;

@@ -11,6 +11,7 @@
 // Column j freezes (x_j, r_j, p_j no longer change) when
 // ||r_j|| <= tol ||b_j|| on the recurrence residual.
 #include <algorithm>
+#include <chrono>
 #include <climits>
 
 #include "common.h"
@@ -410,6 +411,13 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_init(const T* __restrict
 // p = z + beta p.
 // The reductions keep one element per thread in the same order in all three, and the apply
 // sums each output in kColSplit pieces over b exactly as col_apply does.
+// One 32-bit word per column and iteration, so the host never sees half of it:
+// (tag << 2) | (relative residual below the bf16x3 switch) << 1 | column stopped.
+__device__ __forceinline__ void put_check(uint32_t* hword, int j, uint32_t tag, bool done,
+                                          bool below) {
+  if (hword) hword[j] = (tag << 2) | (below ? 2u : 0u) | (done ? 1u : 0u);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kColThreads) void k_cg_col_alpha(T* __restrict__ xv, T* __restrict__ r,
                                                       const T* __restrict__ p,
@@ -417,10 +425,17 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_alpha(T* __restrict__ xv
                                                       int c, int project, double tol, double* rho,
                                                       const double* bnorm, double* relres,
                                                       const int32_t* done_prev, int32_t* done_next,
-                                                      double* __restrict__ rd, Status* st) {
+                                                      double* __restrict__ rd, uint32_t* hword,
+                                                      uint32_t tag, double res_switch,
+                                                      Status* st) {
+  // hword (may be null): this iteration's host-visible check word of each column, written on
+  // every path so that the host finds all s words tagged
   if (skip_now(skip_all(done_prev, s))) {
     // nothing left: carry the flags forward so the next launch reads a current set
-    if (threadIdx.x == 0) done_next[blockIdx.x] = 1;
+    if (threadIdx.x == 0) {
+      done_next[blockIdx.x] = 1;
+      put_check(hword, blockIdx.x, tag, true, relres[blockIdx.x] < res_switch);
+    }
     return;
   }
   extern __shared__ double sh[];
@@ -430,7 +445,10 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_alpha(T* __restrict__ xv
   const int64_t sc = (int64_t)s * c;
   if (j == 0 && threadIdx.x == 0) st->iters += 1;
   if (done_prev[j] != 0) {
-    if (threadIdx.x == 0) done_next[j] = 1;
+    if (threadIdx.x == 0) {
+      done_next[j] = 1;
+      put_check(hword, j, tag, true, relres[j] < res_switch);
+    }
     return;
   }
   // global accesses walk (a, k) with k fastest: the c classes of a probe are contiguous in
@@ -446,6 +464,7 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_alpha(T* __restrict__ xv
     if (threadIdx.x == 0) {
       st->breakdown = 1;
       done_next[j] = 1;
+      put_check(hword, j, tag, true, relres[j] < res_switch);
     }
     return;
   }
@@ -483,8 +502,10 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_alpha(T* __restrict__ xv
   const double rn = sqrt(rr);
   const bool now_done = rn <= tol * bnorm[j];
   if (threadIdx.x == 0) {
+    const double rel = bnorm[j] > 0.0 ? rn / bnorm[j] : 0.0;
     done_next[j] = now_done;
-    relres[j] = bnorm[j] > 0.0 ? rn / bnorm[j] : 0.0;
+    relres[j] = rel;
+    put_check(hword, j, tag, now_done, rel < res_switch);
   }
   if (now_done) return;
   // the apply's input: the stored r, projected again in FP64 when asked
@@ -643,6 +664,40 @@ __global__ __launch_bounds__(256) void k_fill(T* __restrict__ v, int64_t n, T va
   if (i < n) v[i] = value;
 }
 
+// Wait until all s check words of one iteration carry its tag, then fold them: all columns
+// stopped, all relative residuals below the bf16x3 switch.  The words arrive while the GPU
+// runs ahead; after 1 ms of polling the host waits for the stream instead (long iterations),
+// after which every word must be there.
+static int poll_check(Ctx* x, const uint32_t* words, uint32_t tag, int s, hipStream_t st,
+                      bool* all, bool* below) {
+  const volatile uint32_t* w = words;
+  auto tagged = [&]() {
+    for (int j = 0; j < s; ++j)
+      if ((w[j] >> 2) != tag) return false;
+    return true;
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  while (!tagged()) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(1)) {
+      FIRAL_HIP(hipStreamSynchronize(st));
+      if (!tagged()) {
+        set_error("PCG check point: the column words of an iteration are missing");
+        return FIRAL_EHIP;
+      }
+      break;
+    }
+  }
+  bool a = true, b = true;
+  for (int j = 0; j < s; ++j) {
+    const uint32_t v = w[j];
+    a = a && (v & 1u) != 0;
+    b = b && (v & 2u) != 0;
+  }
+  *all = a;
+  *below = b;
+  return FIRAL_OK;
+}
+
 static int read_status(Ctx* x, hipStream_t st) {
   FIRAL_HIP(hipMemcpyAsync(x->status_host, x->status, sizeof(Status), hipMemcpyDeviceToHost, st));
   FIRAL_HIP(hipStreamSynchronize(st));
@@ -700,60 +755,50 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
                                                       x->bnorm, x->relres, flags[0], x->status);
     FIRAL_LAUNCHED();
     // Mixed precision (BF16X3): bf16x3 products while every column's relative residual is
-    // above bf3_switch, FP32 products from the first check point where none is.  The switch
-    // keeps the operator error of the split products from stalling the last iterations.
+    // above bf3_switch, FP32 products once none is.  The switch keeps the operator error of
+    // the split products from stalling the last iterations.
     const bool mixed = x->prec == FIRAL_BF16X3 && tol > 0.0 && !x->async;
     bool precise = false;
-    const int check_every = tol > 0.0 && !x->async ? 4 : (max_iter > 0 ? max_iter : 1);
-    // Check points are pipelined: the status of batch k is copied to a host slot behind an
-    // event, and the host waits for it only after batch k+1 is enqueued, so the GPU never
-    // idles on the host.  A batch enqueued after convergence costs only launches whose
-    // kernels skip on the device flags.  While the bf16x3 switch is pending the check is
-    // synchronous, so the switch takes effect at the next batch.
-    int launched = 0, hslot = 0;
-    bool pending = false;   // a check point copy (hslot ^ 1) not yet read
+    // Host check points (tol > 0, not captured): iteration k's alpha kernel leaves one tagged
+    // word per column in pinned host memory (slot k & 1).  Once iteration k is enqueued the
+    // host polls iteration k-1's words, so the GPU always has an iteration queued and the
+    // stream holds no extra packets.  When all columns have stopped, the one iteration
+    // already enqueued runs kernels that skip on the device flags; a bf16x3 switch decided
+    // at iteration k-1 takes effect from iteration k+1.
+    const bool checks = tol > 0.0 && !x->async;
+    const double res_switch = mixed ? x->bf3_switch : 0.0;
+    uint32_t tags[2] = {0, 0};
+    int launched = 0;
     while (launched < max_iter) {
-      const int batch = std::min(check_every, max_iter - launched);
-      for (int it = 0; it < batch; ++it) {
-        const int32_t* dp = flags[(launched + it) & 1];
-        int32_t* dn = flags[(launched + it + 1) & 1];
-        FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip_all(dp, s), st, precise));
-        k_cg_col_alpha<T><<<s, kColThreads, alpha_lds, st>>>(xv, r, p, q, d, s, c, project, tol,
-                                                             x->rho, x->bnorm, x->relres, dp, dn,
-                                                             rd, x->status);
-        FIRAL_LAUNCHED();
-        if (jt == kApplyCols)
-          k_cg_col_apply<kApplyCols><<<apply_grid, 512, apply_lds, st>>>(Pinv, rd, zd, d, s, c, dn);
-        else
-          k_cg_col_apply<1><<<apply_grid, 512, apply_lds, st>>>(Pinv, rd, zd, d, s, c, dn);
-        FIRAL_LAUNCHED();
-        k_cg_col_beta<T><<<s, kColThreads, beta_lds, st>>>(r, p, zd, d, s, c, project, x->rho, dn);
-        FIRAL_LAUNCHED();
-      }
-      launched += batch;
-      k_col_status<<<1, 256, 0, st>>>(flags[launched & 1], x->relres, s, x->status);
+      const int it = launched++;
+      const int32_t* dp = flags[it & 1];
+      int32_t* dn = flags[(it + 1) & 1];
+      uint32_t* hw = checks ? x->chk_word_dev + (it & 1) * x->s_max : nullptr;
+      tags[it & 1] = (++x->chk_tag) & 0x3fffffffu;
+      if (tags[it & 1] == 0) tags[it & 1] = x->chk_tag = 1;   // zero marks an unwritten word
+      FIRAL_CHECK(hvp_launch(x, omega, x->N, shift, p, q, s, skip_all(dp, s), st, precise));
+      k_cg_col_alpha<T><<<s, kColThreads, alpha_lds, st>>>(xv, r, p, q, d, s, c, project, tol,
+                                                           x->rho, x->bnorm, x->relres, dp, dn,
+                                                           rd, hw, tags[it & 1], res_switch,
+                                                           x->status);
       FIRAL_LAUNCHED();
-      if (launched >= max_iter) break;
-      if (mixed && !precise) {
-        FIRAL_CHECK(read_status(x, st));
-        if (x->status_host->all_done) break;
-        if (x->status_host->relres_max < x->bf3_switch) precise = true;
-        continue;
-      }
-      Status* hs = x->status_host + 1 + hslot;
-      FIRAL_HIP(hipMemcpyAsync(hs, x->status, sizeof(Status), hipMemcpyDeviceToHost, st));
-      FIRAL_HIP(hipEventRecord((hipEvent_t)x->chk_ev[hslot], st));
-      hslot ^= 1;
-      if (pending) {
-        FIRAL_HIP(hipEventSynchronize((hipEvent_t)x->chk_ev[hslot]));
-        if (x->status_host[1 + hslot].all_done) break;
-      }
-      pending = true;
-    }
-    if (max_iter == 0) {
-      k_col_status<<<1, 256, 0, st>>>(flags[0], x->relres, s, x->status);
+      if (jt == kApplyCols)
+        k_cg_col_apply<kApplyCols><<<apply_grid, 512, apply_lds, st>>>(Pinv, rd, zd, d, s, c, dn);
+      else
+        k_cg_col_apply<1><<<apply_grid, 512, apply_lds, st>>>(Pinv, rd, zd, d, s, c, dn);
       FIRAL_LAUNCHED();
+      k_cg_col_beta<T><<<s, kColThreads, beta_lds, st>>>(r, p, zd, d, s, c, project, x->rho, dn);
+      FIRAL_LAUNCHED();
+      if (!checks || it == 0) continue;
+      bool all = true, below = true;
+      FIRAL_CHECK(poll_check(x, x->chk_word + ((it - 1) & 1) * x->s_max, tags[(it - 1) & 1], s,
+                             st, &all, &below));
+      if (all) break;
+      if (mixed && below) precise = true;
     }
+    // the status of the last enqueued iteration (all_done, relres_max) for k_cg_finish
+    k_col_status<<<1, 256, 0, st>>>(flags[launched & 1], x->relres, s, x->status);
+    FIRAL_LAUNCHED();
     k_cg_finish<<<1, 1, 0, st>>>(x->status, slot);
     FIRAL_LAUNCHED();
     if (Xsol && Xsol != xv)
