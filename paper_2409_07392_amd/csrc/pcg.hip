@@ -266,10 +266,13 @@ __global__ void k_cg_finish(Status* st, int slot) {
 constexpr int kColThreads = 1024;
 constexpr int kColSplit = 4;     // each output of the apply is summed in 4 pieces over b
 constexpr int kApplyCols = 4;    // columns per block of k_cg_col_apply
+constexpr int kColE = 3;         // column elements per thread in k_cg_col_alpha / _beta
 
 int64_t col_cg_scratch(int d, int c, int s_max) {
   // the column-local path needs the init kernel's (3 + kColSplit) d c doubles in LDS
+  // (so d c <= 2340), and at most kColE elements of a column per thread
   if ((int64_t)(3 + kColSplit) * d * c * 8 > 128 * 1024) return 0;
+  if ((int64_t)d * c > (int64_t)kColE * kColThreads) return 0;
   return 2 * (int64_t)d * c * s_max;
 }
 
@@ -430,52 +433,67 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_alpha(T* __restrict__ xv
                                                       Status* st) {
   // hword (may be null): this iteration's host-visible check word of each column, written on
   // every path so that the host finds all s words tagged
-  if (skip_now(skip_all(done_prev, s))) {
-    // nothing left: carry the flags forward so the next launch reads a current set
-    if (threadIdx.x == 0) {
-      done_next[blockIdx.x] = 1;
-      put_check(hword, blockIdx.x, tag, true, relres[blockIdx.x] < res_switch);
-    }
-    return;
-  }
   extern __shared__ double sh[];
   __shared__ double red[kColThreads / 64];
   double* r0s = sh;   // [c][d]
   const int j = blockIdx.x, n = d * c;
   const int64_t sc = (int64_t)s * c;
-  if (j == 0 && threadIdx.x == 0) st->iters += 1;
-  if (done_prev[j] != 0) {
+  // Every global value of the step is loaded up front, before the flags are known (all in
+  // bounds), so the step waits on memory once.  Element e = threadIdx.x + u kColThreads walks
+  // (a, k) with k fastest: the c classes of a probe are contiguous in the block layout; the
+  // LDS vectors keep the vec order k d + a.
+  T pv[kColE], qv[kColE], rv[kColE], xw[kColE];
+  int64_t gi[kColE];
+  int li[kColE];
+#pragma unroll
+  for (int u = 0; u < kColE; ++u) {
+    const int e = threadIdx.x + u * kColThreads;
+    const int a = e / c, k = e - a * c;
+    gi[u] = e < n ? a * sc + (int64_t)j * c + k : 0;
+    li[u] = k * d + a;
+    pv[u] = e < n ? p[gi[u]] : T(0);
+    qv[u] = e < n ? q[gi[u]] : T(0);
+    rv[u] = e < n ? r[gi[u]] : T(0);
+    xw[u] = e < n ? xv[gi[u]] : T(0);
+  }
+  const double rho_j = rho[j], bn = bnorm[j], rel_prev = relres[j];
+  const bool was_done = done_prev[j] != 0;
+  if (skip_now(skip_all(done_prev, s))) {
+    // nothing left: carry the flags forward so the next launch reads a current set
     if (threadIdx.x == 0) {
       done_next[j] = 1;
-      put_check(hword, j, tag, true, relres[j] < res_switch);
+      put_check(hword, j, tag, true, rel_prev < res_switch);
     }
     return;
   }
-  // global accesses walk (a, k) with k fastest: the c classes of a probe are contiguous in
-  // the block layout; the LDS vectors keep the vec order k d + a
-  double pq = 0.0;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int a = e / c, k = e - a * c;
-    const int64_t gi = a * sc + (int64_t)j * c + k;
-    pq += (double)p[gi] * (double)q[gi];
+  if (j == 0 && threadIdx.x == 0) st->iters += 1;
+  if (was_done) {
+    if (threadIdx.x == 0) {
+      done_next[j] = 1;
+      put_check(hword, j, tag, true, rel_prev < res_switch);
+    }
+    return;
   }
+  double pq = 0.0;
+#pragma unroll
+  for (int u = 0; u < kColE; ++u)
+    if (threadIdx.x + u * kColThreads < n) pq += (double)pv[u] * (double)qv[u];
   pq = block_sum_col(pq, red);
   if (!(pq > 0.0)) {   // breakdown: report it and freeze the column
     if (threadIdx.x == 0) {
       st->breakdown = 1;
       done_next[j] = 1;
-      put_check(hword, j, tag, true, relres[j] < res_switch);
+      put_check(hword, j, tag, true, rel_prev < res_switch);
     }
     return;
   }
-  const T at = (T)(rho[j] / pq);
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int a = e / c, k = e - a * c;
-    const int64_t gi = a * sc + (int64_t)j * c + k;
-    const T pv = p[gi];
-    xv[gi] += at * pv;
-    r0s[k * d + a] = (double)(r[gi] - at * q[gi]);
-  }
+  const T at = (T)(rho_j / pq);
+#pragma unroll
+  for (int u = 0; u < kColE; ++u)
+    if (threadIdx.x + u * kColThreads < n) {
+      xv[gi[u]] = xw[u] + at * pv[u];
+      r0s[li[u]] = (double)(rv[u] - at * qv[u]);
+    }
   __syncthreads();
   if (project) {
     // r stays in the complement of {1_c (x) u} in exact arithmetic; remove the rounding
@@ -490,19 +508,19 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_alpha(T* __restrict__ xv
     __syncthreads();
   }
   double rr = 0.0;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int a = e / c, k = e - a * c;
-    const int l = k * d + a;
-    const T rv = (T)r0s[l];
-    r[a * sc + (int64_t)j * c + k] = rv;
-    r0s[l] = (double)rv;
-    rr += (double)rv * (double)rv;
-  }
+#pragma unroll
+  for (int u = 0; u < kColE; ++u)
+    if (threadIdx.x + u * kColThreads < n) {
+      const T rs = (T)r0s[li[u]];
+      r[gi[u]] = rs;
+      r0s[li[u]] = (double)rs;
+      rr += (double)rs * (double)rs;
+    }
   rr = block_sum_col(rr, red);
   const double rn = sqrt(rr);
-  const bool now_done = rn <= tol * bnorm[j];
+  const bool now_done = rn <= tol * bn;
   if (threadIdx.x == 0) {
-    const double rel = bnorm[j] > 0.0 ? rn / bnorm[j] : 0.0;
+    const double rel = bn > 0.0 ? rn / bn : 0.0;
     done_next[j] = now_done;
     relres[j] = rel;
     put_check(hword, j, tag, now_done, rel < res_switch);
@@ -536,6 +554,18 @@ __global__ __launch_bounds__(512) void k_cg_col_apply(const double* __restrict__
   const int k = blockIdx.x, j0 = blockIdx.y * JT;
   const int jn = min(JT, s - j0);
   const int n = d * c;
+  const double* Pk = Pinv + (int64_t)k * d * d;
+  const int piece = (d + kColSplit - 1) / kColSplit;
+  // the first sixteen P^-1 values of this thread's first output, loaded together with the
+  // flags and rd (the first pass of the loop below uses them)
+  double pre[16];
+  {
+    const int w = threadIdx.x, qq = w / d, a = w - qq * d;
+    const int b0 = qq * piece, b1 = min(d, b0 + piece);
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      pre[u] = w < kColSplit * d && b0 + u < b1 ? Pk[(int64_t)(b0 + u) * d + a] : 0.0;
+  }
   int active = 0;
   for (int jj = 0; jj < jn; ++jj) active |= done[j0 + jj] == 0;
   if (!active) return;   // the same for every thread of the block
@@ -544,8 +574,6 @@ __global__ __launch_bounds__(512) void k_cg_col_apply(const double* __restrict__
     rsh[e] = jj < jn ? rd[(int64_t)(j0 + jj) * n + (int64_t)k * d + b] : 0.0;
   }
   __syncthreads();
-  const double* Pk = Pinv + (int64_t)k * d * d;
-  const int piece = (d + kColSplit - 1) / kColSplit;
   for (int w = threadIdx.x; w < kColSplit * d; w += blockDim.x) {
     const int qq = w / d, a = w - qq * d;
     const int b0 = qq * piece, b1 = min(d, b0 + piece);
@@ -555,8 +583,10 @@ __global__ __launch_bounds__(512) void k_cg_col_apply(const double* __restrict__
     for (int bb = b0; bb < b1; bb += 16) {
       // sixteen independent loads in flight before the products
       double pv[16];
+      const bool first = w == (int)threadIdx.x && bb == b0;
 #pragma unroll
-      for (int u = 0; u < 16; ++u) pv[u] = bb + u < b1 ? Pk[(int64_t)(bb + u) * d + a] : 0.0;
+      for (int u = 0; u < 16; ++u)
+        pv[u] = first ? pre[u] : (bb + u < b1 ? Pk[(int64_t)(bb + u) * d + a] : 0.0);
 #pragma unroll
       for (int u = 0; u < 16; ++u)
         if (bb + u < b1) {
@@ -583,19 +613,36 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_beta(const T* __restrict
                                                      const double* __restrict__ zd, int d,
                                                      int s, int c, int project, double* rho,
                                                      const int32_t* done) {
-  const int j = blockIdx.x, n = d * c;
-  if (done[j] != 0) return;
   extern __shared__ double sh[];
   __shared__ double red[kColThreads / 64];
+  const int j = blockIdx.x, n = d * c;
   double* zs = sh;       // [c][d]
   double* r0s = sh + n;  // [c][d]
   const int64_t sc = (int64_t)s * c;
   const double* zj = zd + (int64_t)j * n;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) zs[e] = zj[e];
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+  // all global loads first (in bounds whatever the flag), as in k_cg_col_alpha
+  double zv[kColE];
+  T rv[kColE], pv[kColE];
+  int64_t gi[kColE];
+  int li[kColE];
+#pragma unroll
+  for (int u = 0; u < kColE; ++u) {
+    const int e = threadIdx.x + u * kColThreads;
     const int a = e / c, k = e - a * c;
-    r0s[k * d + a] = (double)r[a * sc + (int64_t)j * c + k];
+    gi[u] = e < n ? a * sc + (int64_t)j * c + k : 0;
+    li[u] = k * d + a;
+    zv[u] = e < n ? zj[e] : 0.0;
+    rv[u] = e < n ? r[gi[u]] : T(0);
+    pv[u] = e < n ? p[gi[u]] : T(0);
   }
+  const double rho_j = rho[j];
+  if (done[j] != 0) return;
+#pragma unroll
+  for (int u = 0; u < kColE; ++u)
+    if (threadIdx.x + u * kColThreads < n) {
+      zs[threadIdx.x + u * kColThreads] = zv[u];
+      r0s[li[u]] = (double)rv[u];
+    }
   __syncthreads();
   if (project) {
     for (int a = threadIdx.x; a < d; a += blockDim.x) {
@@ -610,14 +657,11 @@ __global__ __launch_bounds__(kColThreads) void k_cg_col_beta(const T* __restrict
   double rz = 0.0;
   for (int e = threadIdx.x; e < n; e += blockDim.x) rz += r0s[e] * (double)(T)zs[e];
   rz = block_sum_col(rz, red);
-  const double beta = rz / (rho[j] != 0.0 ? rho[j] : 1.0);
+  const double beta = rz / (rho_j != 0.0 ? rho_j : 1.0);
   const T bt = (T)beta;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int a = e / c, k = e - a * c;
-    const int64_t gi = a * sc + (int64_t)j * c + k;
-    p[gi] = (T)zs[k * d + a] + bt * p[gi];
-  }
-  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kColE; ++u)
+    if (threadIdx.x + u * kColThreads < n) p[gi[u]] = (T)zs[li[u]] + bt * pv[u];
   if (threadIdx.x == 0) rho[j] = rz;
 }
 
