@@ -341,7 +341,7 @@ int firal_build_precond(firal_ctx ctx, const double* omega, double shift, double
   FIRAL_REQ(ctx != nullptr, "null context");
   Ctx* x = C(ctx);
   hipStream_t st = (hipStream_t)stream;
-  FIRAL_CHECK(precond_launch(x, omega, shift, st));
+  FIRAL_CHECK(precond_launch(x, omega, shift, st, L != nullptr));
   const size_t bytes = (size_t)x->c * x->d * x->d * 8;
   if (L) FIRAL_HIP(hipMemcpyAsync(L, x->P, bytes, hipMemcpyDeviceToDevice, st));
   if (Pinv) FIRAL_HIP(hipMemcpyAsync(Pinv, x->Pinv, bytes, hipMemcpyDeviceToDevice, st));

@@ -276,7 +276,9 @@ int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_
 // precise: in a BF16X3 context, take the FP32 products for this call (mixed-precision PCG)
 int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
                void* out, int s, Skip skip, hipStream_t st, bool precise = false);
-int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st);
+// Gram blocks, then P^-1 into x->Pinv; the factor L goes to x->P only when want_l (for d <= 256
+// x->P otherwise keeps the Gram blocks)
+int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st, bool want_l = false);
 void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits);
 // FP64 weighted Gram blocks sum_r omega_r h_rk (1 - h_rk) x_r x_r^T + shift I over rows [0, N)
 // of X and H (storage FP32 unless prec is FIRAL_F64; omega null: weight 1) into out
@@ -284,11 +286,11 @@ void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits)
 int gram64_launch(int prec, const void* X, const void* H, const double* omega, int64_t N, int d,
                   int c, const int32_t* tiles, int ntiles, int S, double shift, double* part,
                   double* out, hipStream_t st);
-// In-place Cholesky of c SPD blocks (lower factor, upper zeroed); the blocks' inverses go to
-// Pinv (for d > 256 only when want_inv).  *bad (preset to INT32_MAX) receives the smallest
-// failing block.
+// Cholesky of c SPD blocks: the lower factor replaces P (upper part zeroed) when want_l (always
+// for d > 256); the blocks' inverses go to Pinv (for d > 256 only when want_inv).  *bad
+// (preset to INT32_MAX) receives the smallest failing block.
 int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool want_inv,
-                       hipStream_t st);
+                       bool want_l, hipStream_t st);
 // doubles of column-local CG scratch for d, c, s_max; 0 when that path does not fit
 int64_t col_cg_scratch(int d, int c, int s_max);
 int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, const void* B,

@@ -243,7 +243,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const double* __restrict__ L,
 // L is written over P (P is read completely before the first pivot).
 template <int TT, int TB>
 __global__ __launch_bounds__(TT* TT) void k_sweep(double* __restrict__ P, double* __restrict__ Pinv,
-                                                  int d, int32_t* bad) {
+                                                  int d, int32_t* bad, int write_l) {
   const int kb = blockIdx.x;
   double* A0 = P + (int64_t)kb * d * d;
   double* Y = Pinv + (int64_t)kb * d * d;
@@ -275,7 +275,8 @@ __global__ __launch_bounds__(TT* TT) void k_sweep(double* __restrict__ P, double
       return;
     }
     const double ip = 1.0 / piv;
-    if (tx == 0) {
+    // the factor's column j (only when asked: each step's barrier then waits for these stores)
+    if (write_l && tx == 0) {
       const double sq = sqrt(piv);
 #pragma unroll
       for (int u = 0; u < TB; ++u) {
@@ -319,12 +320,12 @@ __global__ __launch_bounds__(TT* TT) void k_sweep(double* __restrict__ P, double
       const int i = ty + TT * u, q = tx + TT * v;
       if (i < d && q < d) {
         Y[(int64_t)i * d + q] = -a[u][v];
-        if (q > i) A0[(int64_t)i * d + q] = 0.0;
+        if (write_l && q > i) A0[(int64_t)i * d + q] = 0.0;
       }
     }
 }
 
-typedef void (*SweepKernel)(double*, double*, int, int32_t*);
+typedef void (*SweepKernel)(double*, double*, int, int32_t*, int);
 
 static SweepKernel pick_sweep(int d, int* threads) {
   if (d <= 128) {
@@ -380,7 +381,7 @@ static void launch_syrk(Ctx* x, const double* omega, int64_t rps, hipStream_t st
 }
 
 template <typename T>
-static int precond_t(Ctx* x, const double* omega, double shift, hipStream_t st) {
+static int precond_t(Ctx* x, const double* omega, double shift, bool want_l, hipStream_t st) {
   const int d = x->d, c = x->c;
   const int S = x->syrk_splits;
   const int64_t rps = cdiv(x->N, S);
@@ -399,7 +400,7 @@ static int precond_t(Ctx* x, const double* omega, double shift, hipStream_t st) 
   int threads = 0;
   SweepKernel sw = pick_sweep(d, &threads);
   if (sw) {
-    sw<<<c, threads, 0, st>>>(x->P, x->Pinv, d, &x->status->bad_block);
+    sw<<<c, threads, 0, st>>>(x->P, x->Pinv, d, &x->status->bad_block, want_l ? 1 : 0);
     FIRAL_LAUNCHED();
   } else {
     k_chol<<<c, 256, 0, st>>>(x->P, d, &x->status->bad_block);
@@ -431,11 +432,11 @@ void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits)
 }
 
 int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool want_inv,
-                       hipStream_t st) {
+                       bool want_l, hipStream_t st) {
   int threads = 0;
   SweepKernel sw = pick_sweep(d, &threads);
   if (sw) {
-    sw<<<c, threads, 0, st>>>(P, Pinv, d, bad);
+    sw<<<c, threads, 0, st>>>(P, Pinv, d, bad, want_l ? 1 : 0);
     FIRAL_LAUNCHED();
   } else {
     k_chol<<<c, 256, 0, st>>>(P, d, bad);
@@ -485,9 +486,9 @@ int gram64_launch(int prec, const void* X, const void* H, const double* omega, i
                          shift, part, out, st);
 }
 
-int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st) {
-  if (x->prec == FIRAL_F64) return precond_t<double>(x, omega, shift, st);
-  return precond_t<float>(x, omega, shift, st);
+int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st, bool want_l) {
+  if (x->prec == FIRAL_F64) return precond_t<double>(x, omega, shift, want_l, st);
+  return precond_t<float>(x, omega, shift, want_l, st);
 }
 
 }  // namespace firal

@@ -766,7 +766,7 @@ static int round_operand(Round* r, const double* nu_p, hipStream_t st) {
   k_form_d<<<(unsigned)cdiv(c * dd, 256), 256, 0, st>>>(r->Cm, r->Ot, nu_p, r->eta, 1.0 / r->b,
                                                         d, c, r->Dm);
   FIRAL_LAUNCHED();
-  FIRAL_CHECK(chol_blocks_launch(r->Dm, r->Dinv, d, c, r->flags + 2, true, st));
+  FIRAL_CHECK(chol_blocks_launch(r->Dm, r->Dinv, d, c, r->flags + 2, true, false, st));
   // F = D^-1 L^-1 stored transposed: W_k[a][ldo + j] = F_k[j][a]
   BGemm g{r->Dinv, dd, d, 1, r->Li, dd, d, 1, r->W + r->ldo, (int64_t)d * 2 * r->ldo, 1,
           2 * r->ldo, d, d, d};
@@ -947,7 +947,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
   RCHK(gram64_launch(x->prec, x->X, x->H, r->omega, r->N, d, c, r->tiles, r->ntiles, r->splits,
                      lambda, r->gpart, r->Lf, st));
-  RCHK(chol_blocks_launch(r->Lf, r->Dinv, d, c, r->flags, false, st));
+  RCHK(chol_blocks_launch(r->Lf, r->Dinv, d, c, r->flags, false, true, st));
   // H_o blocks: the labeled rows with unit weight
   const size_t es = x->prec == FIRAL_F64 ? 8 : 4;
   RCHK(gram64_launch(x->prec, (const char*)x->X + es * r->n_pool * d,
