@@ -147,24 +147,27 @@ __global__ void k_put_lit(const double* __restrict__ Li, int d, int c, int ldw,
 // step j maps column j below the diagonal onto its first entry with P = I - beta v v^T and
 // applies P A P to the trailing block as A - v w^T - w v^T with p = beta A v,
 // w = p - (beta/2)(p . v) v.  The block is destroyed; diag[j] = a_jj, off[j] = a_{j+1,j} of
-// the tridiagonal.  One workgroup per block; SMEM: the block is held in LDS.
+// the tridiagonal.  One workgroup per block; SMEM: the block is held in LDS.  diag and off
+// are collected in LDS and written once at the end (a global store inside the loop would
+// make every step's barrier wait for it).
 template <bool SMEM>
 __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_all, int d,
                                                           double* __restrict__ diag,
                                                           double* __restrict__ off) {
-  extern __shared__ double dyn[];
-  __shared__ double v[kMaxD], p[kMaxD];
+  constexpr int VD = SMEM ? kTriSmemD : kMaxD;
+  extern __shared__ double dyn[];   // SMEM: the block, then pp; else pp only
+  __shared__ double v[VD], p[VD], dg[VD], of[VD];
   __shared__ double bc[2];
   const int blk = blockIdx.x, tid = threadIdx.x;
   const int64_t dd = (int64_t)d * d;
   double* Ag = A_all + (int64_t)blk * dd;
   double* A = SMEM ? dyn : Ag;
+  double* pp = SMEM ? dyn + dd : dyn;   // [4 d]: the four partial sums of each entry of A v
+  const int tc = tid & 31, tr = tid >> 5;   // 16 x 32 threads for the rank-2 update
   if (SMEM) {
     for (int e = tid; e < d * d; e += kTriThreads) A[e] = Ag[e];
     __syncthreads();
   }
-  double* dg = diag + (int64_t)blk * d;
-  double* of = off + (int64_t)blk * d;
   for (int j = 0; j + 2 < d; ++j) {
     const int r0 = j + 1, n2 = d - r0;   // trailing rows/columns r0 .. d-1
     // sigma = sum of squares below the subdiagonal entry
@@ -191,21 +194,23 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
     for (int i = tid; i < n2; i += kTriThreads) v[i] = i == 0 ? v0 : A[(int64_t)(r0 + i) * d + j];
     if (tid == 0) of[j] = alpha;
     __syncthreads();
-    // p = beta A_sub v (by columns of the symmetric block: consecutive threads, consecutive
-    // addresses), then K = (beta / 2) p . v
+    // p = beta A_sub v by columns of the symmetric block, four threads per column: thread
+    // part k sums q = k mod 4 below the last multiple of four (part 0 also the rest), and the
+    // column's sum is (s0 + s1) + (s2 + s3); then K = (beta / 2) p . v
+    const int n4 = n2 & ~3;
+    for (int t = tid; t < 4 * n2; t += kTriThreads) {
+      const int i = t >> 2, part = t & 3;
+      const double* col = A + (int64_t)r0 * d + r0 + i;
+      double sk = 0.0;
+      for (int q = part; q < n4; q += 4) sk = fma(col[(int64_t)q * d], v[q], sk);
+      if (part == 0)
+        for (int q = n4; q < n2; ++q) sk = fma(col[(int64_t)q * d], v[q], sk);
+      pp[t] = sk;
+    }
+    __syncthreads();
     double pv = 0.0;
     for (int i = tid; i < n2; i += kTriThreads) {
-      const double* col = A + (int64_t)r0 * d + r0 + i;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;   // four chains in flight
-      int q = 0;
-      for (; q + 3 < n2; q += 4) {
-        s0 = fma(col[(int64_t)q * d], v[q], s0);
-        s1 = fma(col[(int64_t)(q + 1) * d], v[q + 1], s1);
-        s2 = fma(col[(int64_t)(q + 2) * d], v[q + 2], s2);
-        s3 = fma(col[(int64_t)(q + 3) * d], v[q + 3], s3);
-      }
-      for (; q < n2; ++q) s0 = fma(col[(int64_t)q * d], v[q], s0);
-      const double acc = (s0 + s1) + (s2 + s3);
+      const double acc = (pp[4 * i] + pp[4 * i + 1]) + (pp[4 * i + 2] + pp[4 * i + 3]);
       p[i] = beta * acc;
       pv += beta * acc * v[i];
     }
@@ -215,10 +220,10 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
     const double K = bc[1];
     for (int i = tid; i < n2; i += kTriThreads) p[i] = p[i] - K * v[i];   // p := w
     __syncthreads();
-    for (int e = tid; e < n2 * n2; e += kTriThreads) {
-      const int i = e / n2, q = e - (e / n2) * n2;
-      double* a = A + (int64_t)(r0 + i) * d + r0 + q;
-      *a = *a - v[i] * p[q] - p[i] * v[q];
+    for (int i = tr; i < n2; i += kTriThreads / 32) {
+      double* arow = A + (int64_t)(r0 + i) * d + r0;
+      const double vi = v[i], pi = p[i];
+      for (int q = tc; q < n2; q += 32) arow[q] = arow[q] - vi * p[q] - pi * v[q];
     }
     __syncthreads();
   }
@@ -229,6 +234,11 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
     }
     dg[d - 1] = A[(int64_t)(d - 1) * d + d - 1];
     of[d - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < d; i += kTriThreads) {
+    diag[(int64_t)blk * d + i] = dg[i];
+    off[(int64_t)blk * d + i] = of[i];
   }
 }
 
@@ -734,18 +744,21 @@ static int bgemm(const BGemm& g, int batch, hipStream_t st) {
 // eigenvalues of the c blocks in A (destroyed) into lam (c x d)
 static int eigvals_launch(Round* r, double* A, hipStream_t st) {
   const int d = r->d, c = r->c;
+  // dynamic LDS: the block (d <= kTriSmemD) and the 4 d partial sums of A v
   if (d <= kTriSmemD) {
-    const size_t smem = (size_t)d * d * sizeof(double);
+    const size_t smem = ((size_t)d * d + 4 * (size_t)d) * sizeof(double);
     static bool attr = false;
     if (!attr) {
-      FIRAL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_tridiag<true>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)(kTriSmemD * kTriSmemD * sizeof(double))));
+      FIRAL_HIP(hipFuncSetAttribute(
+          reinterpret_cast<const void*>(k_tridiag<true>),
+          hipFuncAttributeMaxDynamicSharedMemorySize,
+          (int)((kTriSmemD * kTriSmemD + 4 * kTriSmemD) * sizeof(double))));
       attr = true;
     }
     k_tridiag<true><<<c, kTriThreads, smem, st>>>(A, d, r->tdiag, r->toff);
   } else {
-    k_tridiag<false><<<c, kTriThreads, 0, st>>>(A, d, r->tdiag, r->toff);
+    k_tridiag<false><<<c, kTriThreads, 4 * (size_t)d * sizeof(double), st>>>(A, d, r->tdiag,
+                                                                            r->toff);
   }
   FIRAL_LAUNCHED();
   // few eigenvalues: 16 lanes share each one (17-section); many: one lane each (bisection)
