@@ -159,11 +159,13 @@ int firal_sampled_objective(firal_ctx ctx, const double* z, double lambda, const
 
 /* Measurement of the main Hessian-product kernel (the fused product kernel; for the general
  * path, the span of its per-chunk contraction and Gamma kernels before the final reduction of
- * the split sums): between firal_profile_begin and
- * firal_profile_end the library records a HIP event pair on the call's stream around every
- * launch of that kernel.  firal_profile_end synchronises the device and returns the summed
- * kernel time in milliseconds (host double) and the number of launches (host int64); either
- * pointer may be NULL.  Recording adds no synchronisation to the timed calls. */
+ * the split sums) and of the Round step's scoring kernel: between firal_profile_begin and
+ * firal_profile_end the library attaches a HIP event pair to every launch of that kernel
+ * (hipExtLaunchKernel, so the pair spans the kernel's own execution; for the general path,
+ * events recorded on the call's stream before and after the span).  firal_profile_end
+ * synchronises the device and returns the summed kernel time in milliseconds (host double)
+ * and the number of launches (host int64); either pointer may be NULL.  Recording adds no
+ * synchronisation to the timed calls. */
 int firal_profile_begin(firal_ctx ctx);
 int firal_profile_end(firal_ctx ctx, double* total_ms, int64_t* launches);
 

@@ -50,6 +50,18 @@ static void drop_events(Ctx* x) {
   x->prof_events = nullptr;
 }
 
+int prof_pair(Ctx* x, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (!x->profiling) return FIRAL_OK;
+  EventPairs* ev = (EventPairs*)x->prof_events;
+  ev->push_back({nullptr, nullptr});
+  FIRAL_HIP(hipEventCreate(&ev->back().first));
+  FIRAL_HIP(hipEventCreate(&ev->back().second));
+  *e0 = ev->back().first;
+  *e1 = ev->back().second;
+  return FIRAL_OK;
+}
+
 int prof_mark(Ctx* x, hipStream_t st, bool start) {
   if (!x->profiling) return FIRAL_OK;
   EventPairs* ev = (EventPairs*)x->prof_events;

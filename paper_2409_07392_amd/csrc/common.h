@@ -138,6 +138,9 @@ struct Ctx {
 
 // record an event on `st` when profiling (start: true before the kernel, false after)
 int prof_mark(Ctx* x, hipStream_t st, bool start);
+// when profiling, a new event pair for one launch through hipExtLaunchKernel, which records
+// the kernel's own start and end in it (null events otherwise: a plain launch)
+int prof_pair(Ctx* x, hipEvent_t* e0, hipEvent_t* e1);
 
 inline Ctx* C(firal_ctx p) { return reinterpret_cast<Ctx*>(p); }
 

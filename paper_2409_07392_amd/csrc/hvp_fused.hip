@@ -16,6 +16,8 @@
 // each lane's four operands are contiguous in LDS (one 128-bit read).
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace firal {
@@ -663,17 +665,16 @@ int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_
   const int SC = s * x->c;
   const int nwg = (int)(((int64_t)p.n_splits * p.n_ctiles + 7) / 8 * 8);
   float* part = (float*)x->fused_part;
-  FIRAL_CHECK(prof_mark(x, st, true));
-  k<<<nwg, kThreads, p.lds_bytes, st>>>((const float*)x->X, (const float*)x->H, omega, n_rows,
-                                        x->d, x->c, SC, B, p.probes_per_tile, s, p.n_ctiles,
-                                        p.rows_per_split, p.n_splits, p.XS, p.XT, p.GT, p.CP,
-                                        part,
-                                        XPlanes{(const __bf16*)x->Xhi, (const __bf16*)x->Xlo,
-                                                (const __bf16*)x->XThi, (const __bf16*)x->XTlo,
-                                                x->ldt},
-                                        skip);
+  hipEvent_t e0, e1;   // the kernel's own execution when profiling
+  FIRAL_CHECK(prof_pair(x, &e0, &e1));
+  hipExtLaunchKernelGGL(k, dim3(nwg), dim3(kThreads), (uint32_t)p.lds_bytes, st, e0, e1, 0u,
+                        (const float*)x->X, (const float*)x->H, omega, n_rows, x->d, x->c, SC, B,
+                        p.probes_per_tile, s, p.n_ctiles, p.rows_per_split, p.n_splits, p.XS, p.XT,
+                        p.GT, p.CP, part,
+                        XPlanes{(const __bf16*)x->Xhi, (const __bf16*)x->Xlo,
+                                (const __bf16*)x->XThi, (const __bf16*)x->XTlo, x->ldt},
+                        skip);
   FIRAL_LAUNCHED();
-  FIRAL_CHECK(prof_mark(x, st, false));
   return reduce_parts_launch<float>(part, (int64_t)x->d * SC, p.n_splits, shift, B, out, skip, st);
 }
 

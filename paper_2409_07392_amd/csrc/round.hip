@@ -22,6 +22,8 @@
 #include <cmath>
 #include <vector>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace firal {
@@ -803,13 +805,13 @@ static int round_score_t(Round* r, const CT* W, double* r_out, hipStream_t st) {
   for (int64_t r0 = 0; r0 < r->n_pool; r0 += r->R) {
     const int64_t R = std::min<int64_t>(r->R, r->n_pool - r0);
     const int64_t nwg = cdiv(R, kScoreTM) * r->c;
-    FIRAL_CHECK(prof_mark(r->x, st, true));
+    hipEvent_t e0, e1;   // the kernel's own execution when profiling
+    FIRAL_CHECK(prof_pair(r->x, &e0, &e1));
     // all c operands (d x 2 ldo each) within 2 MiB: walk the classes of a row tile together
     const int rows_major = (int64_t)r->c * r->d * 2 * r->ldo * sizeof(CT) <= ((int64_t)2 << 20);
-    k_round_score<T, CT><<<(unsigned)nwg, 256, 0, st>>>(X, H, r0, R, r->d, r->c, W, r->ldo,
-                                                        r->eta, rows_major, Tb);
+    hipExtLaunchKernelGGL(k_round_score<T, CT>, dim3((unsigned)nwg), dim3(256), 0u, st, e0, e1,
+                          0u, X, H, r0, R, r->d, r->c, W, r->ldo, r->eta, rows_major, Tb);
     FIRAL_LAUNCHED();
-    FIRAL_CHECK(prof_mark(r->x, st, false));
     k_round_rsum<CT><<<(unsigned)cdiv(R, 256), 256, 0, st>>>(Tb, R, r->c, r0, r->mask, r_out,
                                                              r->pval, r->pidx);
     FIRAL_LAUNCHED();
