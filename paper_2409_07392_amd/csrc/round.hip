@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
   constexpr int VD = SMEM ? kTriSmemD : kMaxD;
   extern __shared__ double dyn[];   // SMEM: the block, then pp; else pp only
   __shared__ double v[VD], p[VD], dg[VD], of[VD];
-  __shared__ double bc[2];
+  __shared__ double bc[2][2];
   const int blk = blockIdx.x, tid = threadIdx.x;
   const int64_t dd = (int64_t)d * d;
   double* Ag = A_all + (int64_t)blk * dd;
@@ -172,33 +172,42 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
   }
   for (int j = 0; j + 2 < d; ++j) {
     const int r0 = j + 1, n2 = d - r0;   // trailing rows/columns r0 .. d-1
-    // sigma = sum of squares below the subdiagonal entry
-    double sg = 0.0;
-    for (int i = 1 + tid; i < n2; i += kTriThreads) {
-      const double x = A[(int64_t)(r0 + i) * d + j];
-      sg += x * x;
+    double* bj = bc[j & 1];   // this step's scalars (alternate sets: no reader of the last
+                              // step's set can see this step's values)
+    // 1. wave 0: sigma = sum of squares below the subdiagonal entry, the reflector v and
+    //    beta; bj[1] = 0 when column j is already reduced
+    if (tid < 64) {
+      double sg = 0.0;
+      for (int i = 1 + tid; i < n2; i += 64) {
+        const double x = A[(int64_t)(r0 + i) * d + j];
+        sg += x * x;
+      }
+      sg = __shfl(wave_sum(sg), 0, 64);   // the sum is formed in lane 0; every lane needs it
+      const double x0 = A[(int64_t)r0 * d + j];
+      if (tid == 0) dg[j] = A[(int64_t)j * d + j];
+      if (sg == 0.0) {
+        if (tid == 0) {
+          of[j] = x0;
+          bj[1] = 0.0;
+        }
+      } else {
+        const double nx = sqrt(x0 * x0 + sg);
+        const double alpha = x0 >= 0.0 ? -nx : nx;
+        const double v0 = x0 - alpha;
+        for (int i = tid; i < n2; i += 64) v[i] = i == 0 ? v0 : A[(int64_t)(r0 + i) * d + j];
+        if (tid == 0) {
+          of[j] = alpha;
+          bj[0] = 2.0 / (v0 * v0 + sg);
+          bj[1] = 1.0;
+        }
+      }
     }
-    sg = block_sum<kTriThreads>(sg);
-    if (tid == 0) bc[0] = sg;
     __syncthreads();
-    sg = bc[0];
-    const double x0 = A[(int64_t)r0 * d + j];
-    if (tid == 0) dg[j] = A[(int64_t)j * d + j];
-    if (sg == 0.0) {          // already tridiagonal in this column
-      if (tid == 0) of[j] = x0;
-      __syncthreads();
-      continue;
-    }
-    const double nx = sqrt(x0 * x0 + sg);
-    const double alpha = x0 >= 0.0 ? -nx : nx;
-    const double v0 = x0 - alpha;
-    const double beta = 2.0 / (v0 * v0 + sg);
-    for (int i = tid; i < n2; i += kTriThreads) v[i] = i == 0 ? v0 : A[(int64_t)(r0 + i) * d + j];
-    if (tid == 0) of[j] = alpha;
-    __syncthreads();
-    // p = beta A_sub v by columns of the symmetric block, four threads per column: thread
-    // part k sums q = k mod 4 below the last multiple of four (part 0 also the rest), and the
-    // column's sum is (s0 + s1) + (s2 + s3); then K = (beta / 2) p . v
+    if (bj[1] == 0.0) continue;   // already tridiagonal in this column
+    const double beta = bj[0];
+    // 2. p = beta A_sub v by columns of the symmetric block, four threads per column: thread
+    //    part k sums q = k mod 4 below the last multiple of four (part 0 also the rest), and
+    //    the column's sum is (s0 + s1) + (s2 + s3)
     const int n4 = n2 & ~3;
     for (int t = tid; t < 4 * n2; t += kTriThreads) {
       const int i = t >> 2, part = t & 3;
@@ -210,18 +219,19 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
       pp[t] = sk;
     }
     __syncthreads();
-    double pv = 0.0;
-    for (int i = tid; i < n2; i += kTriThreads) {
-      const double acc = (pp[4 * i] + pp[4 * i + 1]) + (pp[4 * i + 2] + pp[4 * i + 3]);
-      p[i] = beta * acc;
-      pv += beta * acc * v[i];
+    // 3. wave 0: p = beta A v, K = (beta / 2) p . v, p := w = p - K v
+    if (tid < 64) {
+      double pv = 0.0;
+      for (int i = tid; i < n2; i += 64) {
+        const double acc = (pp[4 * i] + pp[4 * i + 1]) + (pp[4 * i + 2] + pp[4 * i + 3]);
+        p[i] = beta * acc;
+        pv += beta * acc * v[i];
+      }
+      const double K = 0.5 * beta * __shfl(wave_sum(pv), 0, 64);
+      for (int i = tid; i < n2; i += 64) p[i] = p[i] - K * v[i];
     }
-    pv = block_sum<kTriThreads>(pv);
-    if (tid == 0) bc[1] = 0.5 * beta * pv;
     __syncthreads();
-    const double K = bc[1];
-    for (int i = tid; i < n2; i += kTriThreads) p[i] = p[i] - K * v[i];   // p := w
-    __syncthreads();
+    // 4. A_sub -= v w^T + w v^T
     for (int i = tr; i < n2; i += kTriThreads / 32) {
       double* arow = A + (int64_t)(r0 + i) * d + r0;
       const double vi = v[i], pi = p[i];
