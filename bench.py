@@ -8,7 +8,7 @@ clusters, whitened) and softmax probabilities with mean max-prob 0.7.
 
     python bench.py [--steps K] [--warmup W] [--prec f32|f64] [--literal]
 
-Prints one JSON line.  --gpus N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 
 --workload 3 / 4 measures the larger configurations instead (their inputs drawn on
 the GPU with the same recipes): configuration 3 (n = 200,000, d = 256, c = 100,
@@ -768,8 +768,8 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Relax path "
-              "of this build is single-GPU.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library's "
+              "Relax and Round paths are single-GPU.", file=sys.stderr)
         sys.exit(2)
     if args.workload == "table5":
         table5_workload(args)

@@ -244,7 +244,7 @@ typedef struct firal_round_s* firal_round;
 /* Set up rounds of one Round solve on ctx's rows: z (device FP64 [n_pool]) the relaxed
  * weights (read during the call only), lambda >= 0 the regulariser of Sigma_o, eta > 0 the
  * learning rate, b in [1, n_pool] the number of rounds (points to select), flags 0 or
- * FIRAL_ROUND_FP32.  Forms Sigma_o's blocks and Cholesky factors, H_o's blocks and round 1's
+ * FIRAL_ROUND_FP32.  Forms Sigma_o's blocks and Cholesky factors, H_o's blocks and the first round's
  * B^-1.  Synchronous.
  * Errors: EINVAL, ENOTSPD (a Sigma_o block is not positive definite), EHIP, ENOMEM. */
 int firal_round_create(firal_round* out, firal_ctx ctx, const double* z, double lambda,

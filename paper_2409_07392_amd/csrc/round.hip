@@ -983,7 +983,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   // O_k = L^-1 H_o L^-T (Ew as the intermediate H_o L^-T)
   RCHK(bgemm(BGemm{r->Ho, dd, d, 1, r->Li, dd, 1, d, r->Ew, dd, d, 1, d, d, d}, c, st));
   RCHK(bgemm(BGemm{r->Li, dd, d, 1, r->Ew, dd, d, 1, r->Ot, dd, d, 1, d, d, d}, c, st));
-  // the fixed u half of every class operand, then round 1's v half (nu_1 = sqrt(dc), C = 0)
+  // the fixed u half of every class operand, then the first round's v half (nu_1 = sqrt(dc), C = 0)
   k_put_lit<<<(unsigned)cdiv(c * dd, 256), 256, 0, st>>>(r->Li, d, c, 2 * r->ldo, r->W);
   if (hipGetLastError() != hipSuccess) return fail(FIRAL_EHIP);
   RCHK(round_operand(r, r->nu, st));
