@@ -8,6 +8,7 @@
 // slices of rows are reduced afterwards in FP64 in a fixed order.
 #include <algorithm>
 #include <climits>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -325,6 +326,158 @@ __global__ __launch_bounds__(TT* TT) void k_sweep(double* __restrict__ P, double
     }
 }
 
+// Inverse of each SPD block (d <= 128) by the sweep operator taken sixteen pivots at a time,
+// for callers that do not ask for the factor.  Sweeping a pivot block K of the current
+// (symmetric) M gives M_KK <- N = -M_KK^-1, M_IK <- T_I = -M_IK N (and M_KI <- T_I^T),
+// M_IJ <- M_IJ - T_I M_KJ for the other rows and columns, the same matrix as sweeping K's
+// pivots one at a time; after every block M = -P^-1.  Thread (ty, tx) of 16 x 16 keeps
+// M[ty + 16u][tx + 16v] in registers (padding: identity); per block one wave sweeps the
+// 16 x 16 pivot block in registers (four entries a lane, shuffles, no barrier), then the
+// panel T goes through LDS and every thread updates its entries: four barriers per block.
+constexpr int kSwLD = 17;   // row stride of the LDS panels (odd: no bank conflicts by column)
+
+struct SweepLds {
+  double* Kb;   // [16][kSwLD] the pivot block, then N
+  double* PK;   // [DP][kSwLD] column panel M[i][K0 + m]
+  double* Tp;   // [DP][kSwLD] T[i][m]
+  int* fail;
+};
+
+// one pivot block K (a compile-time index into the register tile); false when a pivot of
+// the block is not positive (the workgroup stops)
+template <int K, int D16>
+__device__ __forceinline__ bool sweep_block(double (&a)[D16][D16], const SweepLds& L, int tid,
+                                            int32_t* bad, int kb) {
+  constexpr int LD = kSwLD;
+  const int ty = tid >> 4, tx = tid & 15;
+  // the pivot block and the column panel to LDS
+  L.Kb[ty * LD + tx] = a[K][K];
+#pragma unroll
+  for (int u = 0; u < D16; ++u) L.PK[(ty + 16 * u) * LD + tx] = a[u][K];
+  __syncthreads();
+  // 1. wave 0: N = sweep of the 16 x 16 block; lane l holds row l / 4, columns 4 (l % 4) + k
+  if (tid < 64) {
+    const int r = tid >> 2, cg = (tid & 3) * 4;
+    double b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) b[k] = L.Kb[r * LD + cg + k];
+    bool ok = true;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const double piv = __shfl(b[p & 3], 4 * p + (p >> 2), 64);
+      ok = ok && piv > 0.0;
+      const double ip = 1.0 / piv;
+      const double arp = __shfl(b[p & 3], 4 * r + (p >> 2), 64);   // M[r][p]
+      double apc[4];                                                 // M[p][cg + k]
+#pragma unroll
+      for (int k = 0; k < 4; ++k) apc[k] = __shfl(b[k], 4 * p + (tid & 3), 64);
+      const double pri = arp * ip;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int c = cg + k;
+        b[k] = r != p ? (c != p ? fma(-pri, apc[k], b[k]) : pri) : (c != p ? apc[k] * ip : -ip);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) L.Kb[r * LD + cg + k] = b[k];
+    if (!__all(ok) && tid == 0) {
+      *L.fail = 1;
+      atomicMin(bad, kb);
+    }
+  }
+  __syncthreads();
+  if (*L.fail) return false;   // the same for every thread
+  // 2. T[i][c] = -sum_m M[i][K0 + m] N[m][c]
+#pragma unroll
+  for (int u = 0; u < D16; ++u) {
+    const int i = ty + 16 * u;
+    double t = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) t = fma(L.PK[i * LD + m], L.Kb[m * LD + tx], t);
+    L.Tp[i * LD + tx] = -t;
+  }
+  __syncthreads();
+  // 3. M_IJ -= T_I M_KJ (M_KJ[m][j] = M[j][K0 + m] by symmetry), one m at a time over the
+  //    thread's entries (not unrolled: the operands of one m at a time stay in registers);
+  //    then the panel becomes T and the pivot block N
+#pragma unroll 1
+  for (int m = 0; m < 16; ++m) {
+    double tu[D16], pv[D16];
+#pragma unroll
+    for (int u = 0; u < D16; ++u) tu[u] = L.Tp[(ty + 16 * u) * LD + m];
+#pragma unroll
+    for (int v = 0; v < D16; ++v) pv[v] = L.PK[(tx + 16 * v) * LD + m];
+#pragma unroll
+    for (int u = 0; u < D16; ++u)
+#pragma unroll
+      for (int v = 0; v < D16; ++v)
+        if (u != K && v != K) a[u][v] = fma(-tu[u], pv[v], a[u][v]);
+  }
+#pragma unroll
+  for (int u = 0; u < D16; ++u) {
+    a[u][K] = u == K ? L.Kb[ty * LD + tx] : L.Tp[(ty + 16 * u) * LD + tx];
+    if (u != K) a[K][u] = L.Tp[(tx + 16 * u) * LD + ty];
+  }
+  __syncthreads();
+  return true;
+}
+
+template <int D16, int... Ks>
+__device__ __forceinline__ bool sweep_blocks(double (&a)[D16][D16], const SweepLds& L, int tid,
+                                             int32_t* bad, int kb,
+                                             std::integer_sequence<int, Ks...>) {
+  return (sweep_block<Ks, D16>(a, L, tid, bad, kb) && ...);   // in order, stops at a failure
+}
+
+template <int D16>
+__global__ __launch_bounds__(256) void k_sweep_blk(const double* __restrict__ P,
+                                                   double* __restrict__ Pinv, int d,
+                                                   int32_t* bad) {
+  constexpr int DP = 16 * D16;
+  __shared__ double Kb[16 * kSwLD];
+  __shared__ double PK[DP * kSwLD];
+  __shared__ double Tp[DP * kSwLD];
+  __shared__ int fail;
+  const int kb = blockIdx.x, tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  const double* A0 = P + (int64_t)kb * d * d;
+  double a[D16][D16];
+#pragma unroll
+  for (int u = 0; u < D16; ++u)
+#pragma unroll
+    for (int v = 0; v < D16; ++v) {
+      const int i = ty + 16 * u, j = tx + 16 * v;
+      a[u][v] = (i < d && j < d) ? A0[(int64_t)i * d + j] : (i == j ? 1.0 : 0.0);
+    }
+  if (tid == 0) fail = 0;   // seen by all after the first step's barrier
+  const SweepLds L{Kb, PK, Tp, &fail};
+  if (!sweep_blocks<D16>(a, L, tid, bad, kb, std::make_integer_sequence<int, D16>{})) return;
+  double* Y = Pinv + (int64_t)kb * d * d;
+#pragma unroll
+  for (int u = 0; u < D16; ++u)
+#pragma unroll
+    for (int v = 0; v < D16; ++v) {
+      const int i = ty + 16 * u, j = tx + 16 * v;
+      if (i < d && j < d) Y[(int64_t)i * d + j] = -a[u][v];
+    }
+}
+
+typedef void (*SweepBlkKernel)(const double*, double*, int, int32_t*);
+
+static SweepBlkKernel pick_sweep_blk(int d) {
+  if (d > 128) return nullptr;
+  switch ((d + 15) / 16) {
+    case 1: return k_sweep_blk<1>;
+    case 2: return k_sweep_blk<2>;
+    case 3: return k_sweep_blk<3>;
+    case 4: return k_sweep_blk<4>;
+    case 5: return k_sweep_blk<5>;
+    case 6: return k_sweep_blk<6>;
+    case 7: return k_sweep_blk<7>;
+    default: return k_sweep_blk<8>;
+  }
+}
+
 typedef void (*SweepKernel)(double*, double*, int, int32_t*, int);
 
 static SweepKernel pick_sweep(int d, int* threads) {
@@ -399,7 +552,11 @@ static int precond_t(Ctx* x, const double* omega, double shift, bool want_l, hip
   FIRAL_LAUNCHED();
   int threads = 0;
   SweepKernel sw = pick_sweep(d, &threads);
-  if (sw) {
+  SweepBlkKernel sb = want_l ? nullptr : pick_sweep_blk(d);
+  if (sb) {
+    sb<<<c, 256, 0, st>>>(x->P, x->Pinv, d, &x->status->bad_block);
+    FIRAL_LAUNCHED();
+  } else if (sw) {
     sw<<<c, threads, 0, st>>>(x->P, x->Pinv, d, &x->status->bad_block, want_l ? 1 : 0);
     FIRAL_LAUNCHED();
   } else {
@@ -435,7 +592,11 @@ int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool
                        bool want_l, hipStream_t st) {
   int threads = 0;
   SweepKernel sw = pick_sweep(d, &threads);
-  if (sw) {
+  SweepBlkKernel sb = want_l ? nullptr : pick_sweep_blk(d);
+  if (sb) {
+    sb<<<c, 256, 0, st>>>(P, Pinv, d, bad);
+    FIRAL_LAUNCHED();
+  } else if (sw) {
     sw<<<c, threads, 0, st>>>(P, Pinv, d, bad, want_l ? 1 : 0);
     FIRAL_LAUNCHED();
   } else {

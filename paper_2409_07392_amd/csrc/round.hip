@@ -384,6 +384,53 @@ __global__ __launch_bounds__(1024) void k_round_nu(const double* __restrict__ la
   if (tid == 0) *nu_out = nu;
 }
 
+// The same iteration for up to 64 kNuPerLane eigenvalues in one wave: each lane keeps its
+// eigenvalues in registers and the sums are formed in lane 0 and broadcast, so every lane
+// takes the same steps and no barrier is needed.
+constexpr int kNuPerLane = 32;
+__global__ __launch_bounds__(64) void k_round_nu_wave(const double* __restrict__ lam, int n,
+                                                      double eta, double* __restrict__ nu_out) {
+  const int l = threadIdx.x;
+  double lv[kNuPerLane];
+  double mn = INFINITY;
+#pragma unroll
+  for (int u = 0; u < kNuPerLane; ++u) {
+    const int e = l + 64 * u;
+    lv[u] = e < n ? lam[e] : 0.0;
+    if (e < n) mn = fmin(mn, lv[u]);
+  }
+  for (int o = 32; o > 0; o >>= 1) mn = fmin(mn, __shfl_xor(mn, o, 64));   // exact: any order
+  double lo = 1.0 - eta * mn, hi = sqrt((double)n) - eta * mn;
+  double nu = lo;
+  for (int it = 0; it < 300; ++it) {
+    double f = 0.0, fp = 0.0;
+#pragma unroll
+    for (int u = 0; u < kNuPerLane; ++u)
+      if (l + 64 * u < n) {
+        const double a = 1.0 / (nu + eta * lv[u]);
+        const double a2 = a * a;
+        f += a2;
+        fp += a2 * a;
+      }
+    f = __shfl(wave_sum(f), 0, 64);
+    fp = __shfl(wave_sum(fp), 0, 64);
+    const double phi = f, dphi = -2.0 * fp;
+    if (phi > 1.0) lo = nu;
+    else if (phi < 1.0) hi = nu;
+    double nn;
+    if (phi == 1.0) {
+      nn = nu;
+    } else {
+      nn = nu + 2.0 * phi * (1.0 - sqrt(phi)) / dphi;
+      if (!(nn > lo && nn < hi)) nn = 0.5 * (lo + hi);
+    }
+    const bool stop = nn == nu || !(hi - lo > 4e-16 * fabs(hi));
+    nu = nn;
+    if (stop) break;
+  }
+  if (l == 0) *nu_out = nu;
+}
+
 // D_k = nu I + eta (C_k + O_k / b)
 __global__ void k_form_d(const double* __restrict__ Cm, const double* __restrict__ Ot,
                          const double* __restrict__ nu_p, double eta, double inv_b, int d, int c,
@@ -773,8 +820,12 @@ static int eigvals_launch(Round* r, double* A, hipStream_t st) {
                                                                             r->toff);
   }
   FIRAL_LAUNCHED();
-  // few eigenvalues: 16 lanes share each one (17-section); many: one lane each (bisection)
-  if ((int64_t)c * d <= 65536)
+  // few eigenvalues: 32 or 16 lanes share each one (33- or 17-section); many: one lane each
+  // (bisection)
+  if ((int64_t)c * d <= 32768)
+    k_sturm<32><<<dim3(c, (unsigned)cdiv(d, 256 / 32)), 256, 0, st>>>(r->tdiag, r->toff, d,
+                                                                      r->lam);
+  else if ((int64_t)c * d <= 65536)
     k_sturm<16><<<dim3(c, (unsigned)cdiv(d, 256 / 16)), 256, 0, st>>>(r->tdiag, r->toff, d,
                                                                       r->lam);
   else
@@ -854,7 +905,10 @@ static int round_step_launch(Round* r, hipStream_t st) {
                                              r->Hacc, r->Ew, r->mask, r->flags + 1);
   FIRAL_LAUNCHED();
   FIRAL_CHECK(eigvals_launch(r, r->Ew, st));
-  k_round_nu<<<1, 1024, 0, st>>>(r->lam, (int64_t)c * d, r->eta, r->nu + t + 1);
+  if ((int64_t)c * d <= 64 * kNuPerLane)
+    k_round_nu_wave<<<1, 64, 0, st>>>(r->lam, c * d, r->eta, r->nu + t + 1);
+  else
+    k_round_nu<<<1, 1024, 0, st>>>(r->lam, (int64_t)c * d, r->eta, r->nu + t + 1);
   FIRAL_LAUNCHED();
   FIRAL_CHECK(round_operand(r, r->nu + t + 1, st));
   r->t = t + 1;
