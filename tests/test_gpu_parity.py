@@ -215,14 +215,33 @@ def test_precond_matches_oracle(prec, shape):
     assert_close(host(Pinv), np.linalg.inv(P), TOL[prec] * max(10.0, 10 * kappa), "block inverse")
 
 
-def test_precond_reports_non_spd_block():
+@pytest.mark.parametrize("want_L", [True, False])
+def test_precond_reports_non_spd_block(want_L):
+    # want_L=False: the inverse alone (the blocked sweep for d <= 128)
     p = make_small(n=200, n_lab=3, d=6, c=4, s=1, seed=7)
     H = p.H.copy()
     H[:, 2] = 0.0
     ctx = RelaxContext(dev(p.X, torch.float64), dev(H, torch.float64), p.n_pool, 1, "f64")
     with pytest.raises(FiralError) as ei:
-        ctx.build_precond(shift=0.0)
+        ctx.build_precond(shift=0.0, want_L=want_L)
     assert ei.value.code == _lib.ENOTSPD
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(2000, 50, 20, 5), (3001, 7, 100, 10), (517, 3, 37, 13),
+                                   (777, 5, 128, 3), (600, 3, 45, 40), (300, 2, 1, 3)])
+def test_precond_inverse_alone_matches_oracle(prec, shape):
+    # without the factor, d <= 128 takes the blocked sweep (16-pivot blocks; d = 1, 37, 45:
+    # partial blocks padded with the identity, d = 128: eight full blocks)
+    n, nl, d, c = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=8)
+    ctx, X, H = context(p, prec, 1)
+    om = np.random.default_rng(9).uniform(0.0, 1.0, p.N)
+    L, Pinv, info = ctx.build_precond(dev(om, torch.float64), shift=1e-3, want_L=False)
+    assert L is None and info["bad_block"] == -1
+    P = orc.precond_blocks(X, H, om, 1e-3)
+    kappa = max(np.linalg.cond(Pk) for Pk in P)
+    assert_close(host(Pinv), np.linalg.inv(P), TOL[prec] * max(10.0, 10 * kappa), "block inverse")
 
 
 # ------------------------------------------------------------------------ pcg
