@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <utility>
 #include <vector>
 
 #include <hip/hip_ext.h>
@@ -249,6 +250,155 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_
   }
   __syncthreads();
   for (int i = tid; i < d; i += kTriThreads) {
+    diag[(int64_t)blk * d + i] = dg[i];
+    off[(int64_t)blk * d + i] = of[i];
+  }
+}
+
+// The same reduction for d <= 128 with the block in registers: thread (ty, tx) of 16 x 16
+// keeps A[ty + 16u][tx + 16w] (zero padding), and per step only column j, the partial sums
+// of A v by thread column, and v and w go through LDS.  v and p are zero on the finished
+// rows 0..j, so the rank-2 update leaves them alone.  The columns are walked in blocks of
+// 16 (compile-time block index into the register tile).
+struct TriLds {
+  double* col;   // [128] column j of the current matrix
+  double* v;     // [128]
+  double* w;     // [128]
+  double* part;  // [16][129] partial sums of A v, by thread column
+  double* dg;    // [128]
+  double* of;    // [128]
+  double* bc;    // [2][2] beta and the "reflect" flag, alternate sets by step parity
+};
+
+template <int J, int D16>
+__device__ __forceinline__ void tri_block(double (&a)[D16][D16], const TriLds& L, int d, int tid) {
+  constexpr int PL = 129;
+  const int ty = tid >> 4, tx = tid & 15;
+  for (int jj = 0; jj < 16; ++jj) {
+    const int j = 16 * J + jj;
+    if (j + 2 >= d) return;   // uniform
+    const int r0 = j + 1, n2 = d - r0;
+    // 1. column j (rows below the diagonal) and the diagonal entry to LDS
+    if (tx == jj) {
+#pragma unroll
+      for (int u = 0; u < D16; ++u) {
+        const int i = ty + 16 * u;
+        if (i > j) L.col[i] = a[u][J];
+        if (i == j) L.dg[j] = a[u][J];
+      }
+    }
+    __syncthreads();
+    double* bj = L.bc + 2 * (j & 1);
+    // 2. wave 0: sigma, the reflector v (zero on rows 0..j) and beta
+    if (tid < 64) {
+      double sg = 0.0;
+      for (int i = r0 + 1 + tid; i < d; i += 64) sg += L.col[i] * L.col[i];
+      sg = __shfl(wave_sum(sg), 0, 64);
+      const double x0 = L.col[r0];
+      if (sg == 0.0) {
+        if (tid == 0) {
+          L.of[j] = x0;
+          bj[1] = 0.0;
+        }
+      } else {
+        const double nx = sqrt(x0 * x0 + sg);
+        const double alpha = x0 >= 0.0 ? -nx : nx;
+        const double v0 = x0 - alpha;
+        for (int i = tid; i < 16 * D16; i += 64) L.v[i] = i < r0 || i >= d ? 0.0 : (i == r0 ? v0 : L.col[i]);
+        if (tid == 0) {
+          L.of[j] = alpha;
+          bj[0] = 2.0 / (v0 * v0 + sg);
+          bj[1] = 1.0;
+        }
+      }
+    }
+    __syncthreads();
+    if (bj[1] == 0.0) continue;   // already tridiagonal in this column
+    const double beta = bj[0];
+    // 3. partial sums of A v over this thread's columns, for its rows
+    double vq[D16];
+#pragma unroll
+    for (int w = 0; w < D16; ++w) vq[w] = L.v[tx + 16 * w];
+#pragma unroll
+    for (int u = 0; u < D16; ++u) {
+      double sp = 0.0;
+#pragma unroll
+      for (int w = 0; w < D16; ++w) sp = fma(a[u][w], vq[w], sp);
+      L.part[tx * PL + ty + 16 * u] = sp;
+    }
+    __syncthreads();
+    // 4. wave 0: p = beta A v on the trailing rows (zero on 0..j), K = (beta/2) p . v,
+    //    w = p - K v
+    if (tid < 64) {
+      double pv = 0.0;
+      for (int i = tid; i < 16 * D16; i += 64) {
+        double sum = 0.0;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) sum += L.part[t * PL + i];
+        const double pi = i > j && i < d ? beta * sum : 0.0;
+        L.w[i] = pi;
+        pv += pi * L.v[i];
+      }
+      const double K = 0.5 * beta * __shfl(wave_sum(pv), 0, 64);
+      for (int i = tid; i < 16 * D16; i += 64) L.w[i] = L.w[i] - K * L.v[i];
+    }
+    __syncthreads();
+    // 5. A -= v w^T + w v^T on this thread's entries
+    double vi[D16], wi[D16], wq[D16];
+#pragma unroll
+    for (int u = 0; u < D16; ++u) {
+      vi[u] = L.v[ty + 16 * u];
+      wi[u] = L.w[ty + 16 * u];
+      wq[u] = L.w[tx + 16 * u];
+    }
+#pragma unroll
+    for (int u = 0; u < D16; ++u)
+#pragma unroll
+      for (int w = 0; w < D16; ++w) a[u][w] = a[u][w] - vi[u] * wq[w] - wi[u] * vq[w];
+  }
+}
+
+template <int D16, int... Js>
+__device__ __forceinline__ void tri_blocks(double (&a)[D16][D16], const TriLds& L, int d, int tid,
+                                           std::integer_sequence<int, Js...>) {
+  (tri_block<Js, D16>(a, L, d, tid), ...);
+}
+
+template <int D16>
+__global__ __launch_bounds__(256) void k_tridiag_reg(double* __restrict__ A_all, int d,
+                                                     double* __restrict__ diag,
+                                                     double* __restrict__ off) {
+  __shared__ double col[128], v[128], w[128], dg[128], of[128];
+  __shared__ double part[16 * 129];
+  __shared__ double bc[4];
+  const int blk = blockIdx.x, tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  const double* Ag = A_all + (int64_t)blk * d * d;
+  double a[D16][D16];
+#pragma unroll
+  for (int u = 0; u < D16; ++u)
+#pragma unroll
+    for (int q = 0; q < D16; ++q) {
+      const int i = ty + 16 * u, j = tx + 16 * q;
+      a[u][q] = i < d && j < d ? Ag[(int64_t)i * d + j] : 0.0;
+    }
+  const TriLds L{col, v, w, part, dg, of, bc};
+  tri_blocks<D16>(a, L, d, tid, std::make_integer_sequence<int, D16>{});
+  // the last 2 x 2 (or 1 x 1) block
+#pragma unroll
+  for (int u = 0; u < D16; ++u)
+#pragma unroll
+    for (int q = 0; q < D16; ++q) {
+      const int i = ty + 16 * u, j = tx + 16 * q;
+      if (d >= 2 && i == d - 2 && j == d - 2) dg[d - 2] = a[u][q];
+      if (d >= 2 && i == d - 1 && j == d - 2) of[d - 2] = a[u][q];
+      if (i == d - 1 && j == d - 1) {
+        dg[d - 1] = a[u][q];
+        of[d - 1] = 0.0;
+      }
+    }
+  __syncthreads();
+  for (int i = tid; i < d; i += 256) {
     diag[(int64_t)blk * d + i] = dg[i];
     off[(int64_t)blk * d + i] = of[i];
   }
@@ -803,8 +953,20 @@ static int bgemm(const BGemm& g, int batch, hipStream_t st) {
 // eigenvalues of the c blocks in A (destroyed) into lam (c x d)
 static int eigvals_launch(Round* r, double* A, hipStream_t st) {
   const int d = r->d, c = r->c;
-  // dynamic LDS: the block (d <= kTriSmemD) and the 4 d partial sums of A v
-  if (d <= kTriSmemD) {
+  // d <= 128: the block in registers; else the global-memory form (dynamic LDS: the 4 d
+  // partial sums of A v)
+  if (d <= 128) {
+    switch ((d + 15) / 16) {
+      case 1: k_tridiag_reg<1><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
+      case 2: k_tridiag_reg<2><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
+      case 3: k_tridiag_reg<3><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
+      case 4: k_tridiag_reg<4><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
+      case 5: k_tridiag_reg<5><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
+      case 6: k_tridiag_reg<6><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
+      case 7: k_tridiag_reg<7><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
+      default: k_tridiag_reg<8><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
+    }
+  } else if (d <= kTriSmemD) {
     const size_t smem = ((size_t)d * d + 4 * (size_t)d) * sizeof(double);
     static bool attr = false;
     if (!attr) {
