@@ -34,8 +34,6 @@ namespace {
 constexpr int kMaxD = 1024;         // d limit of the Round step (LDS rows of the update)
 constexpr int kScoreTM = 64, kScoreTN = 64, kScoreTK = 16, kScorePad = 4;
 constexpr int kTriThreads = 512;
-// tridiagonalisation in LDS up to this d (d^2 doubles), in global memory above
-constexpr int kTriSmemD = 128;
 
 __device__ __forceinline__ int64_t xcd_lid_r(int64_t b, int64_t n) {
   const int64_t q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
@@ -150,27 +148,18 @@ __global__ void k_put_lit(const double* __restrict__ Li, int d, int c, int ldw,
 // step j maps column j below the diagonal onto its first entry with P = I - beta v v^T and
 // applies P A P to the trailing block as A - v w^T - w v^T with p = beta A v,
 // w = p - (beta/2)(p . v) v.  The block is destroyed; diag[j] = a_jj, off[j] = a_{j+1,j} of
-// the tridiagonal.  One workgroup per block; SMEM: the block is held in LDS.  diag and off
-// are collected in LDS and written once at the end (a global store inside the loop would
-// make every step's barrier wait for it).
-template <bool SMEM>
-__global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A_all, int d,
-                                                          double* __restrict__ diag,
-                                                          double* __restrict__ off) {
-  constexpr int VD = SMEM ? kTriSmemD : kMaxD;
-  extern __shared__ double dyn[];   // SMEM: the block, then pp; else pp only
-  __shared__ double v[VD], p[VD], dg[VD], of[VD];
+// the tridiagonal.  One workgroup per block, the block in global memory (d > 128; smaller
+// blocks take k_tridiag_reg below).  diag and off are collected in LDS and written once at
+// the end (a global store inside the loop would make every step's barrier wait for it).
+__global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A, int d,
+                                                         double* __restrict__ diag,
+                                                         double* __restrict__ off) {
+  extern __shared__ double pp[];   // [4 d]: the four partial sums of each entry of A v
+  __shared__ double v[kMaxD], p[kMaxD], dg[kMaxD], of[kMaxD];
   __shared__ double bc[2][2];
   const int blk = blockIdx.x, tid = threadIdx.x;
-  const int64_t dd = (int64_t)d * d;
-  double* Ag = A_all + (int64_t)blk * dd;
-  double* A = SMEM ? dyn : Ag;
-  double* pp = SMEM ? dyn + dd : dyn;   // [4 d]: the four partial sums of each entry of A v
+  A += (int64_t)blk * d * d;
   const int tc = tid & 31, tr = tid >> 5;   // 16 x 32 threads for the rank-2 update
-  if (SMEM) {
-    for (int e = tid; e < d * d; e += kTriThreads) A[e] = Ag[e];
-    __syncthreads();
-  }
   for (int j = 0; j + 2 < d; ++j) {
     const int r0 = j + 1, n2 = d - r0;   // trailing rows/columns r0 .. d-1
     double* bj = bc[j & 1];   // this step's scalars (alternate sets: no reader of the last
@@ -966,20 +955,8 @@ static int eigvals_launch(Round* r, double* A, hipStream_t st) {
       case 7: k_tridiag_reg<7><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
       default: k_tridiag_reg<8><<<c, 256, 0, st>>>(A, d, r->tdiag, r->toff); break;
     }
-  } else if (d <= kTriSmemD) {
-    const size_t smem = ((size_t)d * d + 4 * (size_t)d) * sizeof(double);
-    static bool attr = false;
-    if (!attr) {
-      FIRAL_HIP(hipFuncSetAttribute(
-          reinterpret_cast<const void*>(k_tridiag<true>),
-          hipFuncAttributeMaxDynamicSharedMemorySize,
-          (int)((kTriSmemD * kTriSmemD + 4 * kTriSmemD) * sizeof(double))));
-      attr = true;
-    }
-    k_tridiag<true><<<c, kTriThreads, smem, st>>>(A, d, r->tdiag, r->toff);
   } else {
-    k_tridiag<false><<<c, kTriThreads, 4 * (size_t)d * sizeof(double), st>>>(A, d, r->tdiag,
-                                                                            r->toff);
+    k_tridiag<<<c, kTriThreads, 4 * (size_t)d * sizeof(double), st>>>(A, d, r->tdiag, r->toff);
   }
   FIRAL_LAUNCHED();
   // few eigenvalues: 32 or 16 lanes share each one (33- or 17-section); many: one lane each
