@@ -35,6 +35,10 @@
  * are reported through firal_info by the calls that take one.  The
  * detail of the last failure on the calling thread is firal_last_error().
  * A context must not be used from two host threads or two streams at once.
+ * Calls that run PCG with a tolerance (firal_pcg_solve, firal_relax_step,
+ * firal_sampled_objective) read each CG iteration's per-column flags from pinned
+ * host memory one iteration behind the GPU: the calling thread spins on them,
+ * for at most 1 ms at a time before it waits on the stream instead.
  */
 #ifndef FIRAL_H
 #define FIRAL_H
