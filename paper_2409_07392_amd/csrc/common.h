@@ -305,6 +305,10 @@ int hvp_tiled_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, 
                      void* out, int s, Skip skip, hipStream_t st, bool precise);
 // buffer sizing of the row-tiled kernels
 int64_t tiled_col_tiles(int prec, int c, int s);
+// Fused FP32 gradient pass (d <= 128) into x->gpart: per pool row, one partial per tile of
+// probes; *n_tiles = 0 when the shape is not covered (nothing launched)
+int grad_fused_launch(Ctx* x, const float* U, const float* W, int s, hipStream_t st,
+                      int* n_tiles);
 int split_x_launch(Ctx* x, hipStream_t st);
 int64_t tiled_out_tiles(int prec, int d, int64_t sc);
 int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st,

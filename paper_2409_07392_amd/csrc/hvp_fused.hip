@@ -300,6 +300,191 @@ __global__ __launch_bounds__(kThreads) void k_hvp_fused(
   }
 }
 
+// ------------------------------------------------------ fused FP32 gradient (eq. 11)
+// One pass over the pool rows for d <= 128: per workgroup a row range and a tile of whole
+// probes; per 32-row chunk (staged as in k_hvp_fused, fetched one chunk ahead) B = X W and
+// A = X U on MFMA (the W and U slices of one 16-column block per wave in registers), then per
+// (row, probe) alpha = b . h and t = a . ((b - alpha) h) = u_j^T H_i w_j in FP64, and per
+// row the sum over the tile's probes in probe order into gpart[tile][row] (k_grad_sum adds
+// the tiles in order and scales by -1/s).
+template <int D16>
+__global__ __launch_bounds__(kThreads) void k_grad_fused(
+    const float* __restrict__ X, const float* __restrict__ H, int64_t n_rows, int d, int c,
+    int SC, const float* __restrict__ U, const float* __restrict__ W, int probes_per_tile, int s,
+    int n_ctiles, int64_t rows_per_split, int n_splits, int XS, int GT, int CP,
+    double* __restrict__ gpart) {
+  const int nwg = gridDim.x;
+  const int lid = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+  if (lid >= n_splits * n_ctiles) return;
+  const int ct = lid % n_ctiles;
+  const int split = lid / n_ctiles;
+  const int j0 = ct * probes_per_tile;
+  const int sp = min(probes_per_tile, s - j0);
+  const int col0 = j0 * c;
+  const int CT = sp * c;
+  const int C16 = (CT + 15) >> 4;
+  const int64_t rb = (int64_t)split * rows_per_split;
+  const int64_t re = rb + rows_per_split < n_rows ? rb + rows_per_split : n_rows;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  constexpr int DP = 16 * D16;
+
+  extern __shared__ float lds[];
+  float* Xs = lds;                          // [kRC][XS]
+  float* Bs = Xs + kRC * XS;                // [CP][GT] X W of the chunk, column-major
+  float* As = Bs + CP * GT;                 // [CP][GT] X U
+  float* Hs = As + CP * GT;                 // [kRC][c]
+  double* Ts = (double*)(Hs + ((kRC * c + 1) & ~1));   // [kRC][probes_per_tile]
+
+  // W and U slices of this wave's column block: k index 16g + 4lk + t for step 4g + t
+  float bw[4 * D16], bu[4 * D16];
+  {
+    const int col = wave * 16 + li;
+    const bool ok = wave < C16 && col < CT;
+#pragma unroll
+    for (int g = 0; g < D16; ++g)
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = 16 * g + 4 * lk + t;
+        const int64_t o = (int64_t)k * SC + col0 + col;
+        bw[4 * g + t] = (ok && k < d) ? W[o] : 0.f;
+        bu[4 * g + t] = (ok && k < d) ? U[o] : 0.f;
+      }
+  }
+  constexpr int NX = kRC * DP / kThreads;
+  const int nh = (kRC * c + kThreads - 1) / kThreads;
+  float xr[NX], hr[kHP];
+  auto fetch = [&](int64_t r0) {
+    const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int e = tid + kThreads * q, r = e / DP, a = e - r * DP;
+      xr[q] = (r < R && a < d) ? X[(r0 + r) * d + a] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < kHP; ++q) {
+      const int e = tid + kThreads * q;
+      if (q < nh) hr[q] = (e < kRC * c && e / c < R) ? H[r0 * c + e] : 0.f;
+    }
+  };
+  if (rb < re) fetch(rb);
+  for (int64_t r0 = rb; r0 < re; r0 += kRC) {
+    const int R = (int)(re - r0 < kRC ? re - r0 : kRC);
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int e = tid + kThreads * q, r = e / DP, a = e - r * DP;
+      Xs[r * XS + a] = xr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < kHP; ++q) {
+      const int e = tid + kThreads * q;
+      if (q < nh && e < kRC * c) Hs[e] = hr[q];
+    }
+    for (int q = kHP; q < nh; ++q) {   // beyond c = 32 the rest of h is read directly
+      const int e = tid + kThreads * q;
+      if (e < kRC * c) Hs[e] = e / c < R ? H[r0 * c + e] : 0.f;
+    }
+    __syncthreads();
+    if (r0 + kRC < re) fetch(r0 + kRC);
+
+    // B = X_chunk W_tile and A = X_chunk U_tile for this wave's column block
+    f32x4 ab0 = {0.f, 0.f, 0.f, 0.f}, ab1 = ab0, aa0 = ab0, aa1 = ab0;
+#pragma unroll
+    for (int g = 0; g < D16; ++g) {
+      const f32x4v a0 = *(const f32x4v*)(Xs + li * XS + 16 * g + 4 * lk);
+      const f32x4v a1 = *(const f32x4v*)(Xs + (16 + li) * XS + 16 * g + 4 * lk);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        ab0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[t], bw[4 * g + t], ab0, 0, 0, 0);
+        ab1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[t], bw[4 * g + t], ab1, 0, 0, 0);
+        aa0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[t], bu[4 * g + t], aa0, 0, 0, 0);
+        aa1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[t], bu[4 * g + t], aa1, 0, 0, 0);
+      }
+    }
+    if (wave < C16) {
+      // lane holds rows 4lk + v (and 16 + 4lk + v) of column wave * 16 + li
+      float* bc = Bs + (wave * 16 + li) * GT + 4 * lk;
+      float* ac = As + (wave * 16 + li) * GT + 4 * lk;
+      *(f32x4v*)bc = f32x4v{ab0[0], ab0[1], ab0[2], ab0[3]};
+      *(f32x4v*)(bc + 16) = f32x4v{ab1[0], ab1[1], ab1[2], ab1[3]};
+      *(f32x4v*)ac = f32x4v{aa0[0], aa0[1], aa0[2], aa0[3]};
+      *(f32x4v*)(ac + 16) = f32x4v{aa1[0], aa1[1], aa1[2], aa1[3]};
+    }
+    __syncthreads();
+
+    // per (row, probe): u_j^T H_i w_j = a . ((b - alpha) h), alpha = b . h (FP64)
+    for (int e = tid; e < kRC * sp; e += kThreads) {
+      const int r = e % kRC, j = e / kRC;
+      const float* bcol = Bs + j * c * GT + r;
+      const float* acol = As + j * c * GT + r;
+      const float* hrow = Hs + r * c;
+      double al = 0.0;
+      for (int k = 0; k < c; ++k) al += (double)bcol[k * GT] * (double)hrow[k];
+      double t = 0.0;
+      for (int k = 0; k < c; ++k)
+        t += (double)acol[k * GT] * (((double)bcol[k * GT] - al) * (double)hrow[k]);
+      Ts[r * probes_per_tile + j] = t;
+    }
+    __syncthreads();
+    if (tid < R) {
+      double q = 0.0;
+      for (int j = 0; j < sp; ++j) q += Ts[tid * probes_per_tile + j];
+      gpart[(int64_t)ct * n_rows + r0 + tid] = q;
+    }
+  }
+}
+
+typedef void (*GradFusedKernel)(const float*, const float*, int64_t, int, int, int, const float*,
+                                const float*, int, int, int, int64_t, int, int, int, int, double*);
+
+template <int D16>
+static GradFusedKernel grad_fused_kernel() {
+  return k_grad_fused<D16>;
+}
+
+int grad_fused_launch(Ctx* x, const float* U, const float* W, int s, hipStream_t st,
+                      int* n_tiles) {
+  *n_tiles = 0;
+  const int d = x->d, c = x->c;
+  const int64_t n = x->n_pool;
+  const int D16 = (d + 15) / 16;
+  if (x->prec != FIRAL_F32 || D16 > 8 || c > 128 || n <= 0) return FIRAL_OK;
+  // tiles of whole probes, at most one 16-column block per wave
+  int pp = std::min(s, kNW * 16 / c);
+  const int n_ct = (s + pp - 1) / pp;
+  pp = (s + n_ct - 1) / n_ct;
+  const int C16 = (pp * c + 15) / 16;
+  // the per-row tile partials must fit the gradient's partial buffer
+  const int64_t cap = std::min<int64_t>(x->chunk_rows, n) * tiled_col_tiles(x->prec, c, x->s_max);
+  if (n * n_ct > cap) return FIRAL_OK;
+  const int XS = 16 * D16 + 4, GT = kRC + 4, CP = 16 * C16;
+  const size_t lds = 4 * ((size_t)kRC * XS + 2 * (size_t)CP * GT + ((kRC * c + 1) & ~1)) +
+                     8 * (size_t)kRC * pp;
+  if (lds > 64 * 1024) return FIRAL_OK;
+  const int64_t chunks = (n + kRC - 1) / kRC;
+  int64_t splits = std::max<int64_t>(1, std::min<int64_t>(chunks, 256 / n_ct));
+  const int64_t rps = ((n + splits - 1) / splits + kRC - 1) / kRC * kRC;
+  splits = (n + rps - 1) / rps;
+  GradFusedKernel k = nullptr;
+  switch (D16) {
+    case 1: k = grad_fused_kernel<1>(); break;
+    case 2: k = grad_fused_kernel<2>(); break;
+    case 3: k = grad_fused_kernel<3>(); break;
+    case 4: k = grad_fused_kernel<4>(); break;
+    case 5: k = grad_fused_kernel<5>(); break;
+    case 6: k = grad_fused_kernel<6>(); break;
+    case 7: k = grad_fused_kernel<7>(); break;
+    default: k = grad_fused_kernel<8>(); break;
+  }
+  const int nwg = (int)((splits * n_ct + 7) / 8 * 8);
+  k<<<nwg, kThreads, lds, st>>>((const float*)x->X, (const float*)x->H, n, d, c, s * c, U, W, pp,
+                                s, n_ct, rps, (int)splits, XS, GT, CP, x->gpart);
+  FIRAL_LAUNCHED();
+  *n_tiles = n_ct;
+  return FIRAL_OK;
+}
+
 // ------------------------------------------------------------- bf16x3 variant
 // Same tiling with each FP32 product taken as three bf16 products on the
 // 16x16x32 bf16 MFMA (FP32 accumulation): x y ~ xh yh + xh yl + xl yh with

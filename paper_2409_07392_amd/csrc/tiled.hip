@@ -803,6 +803,16 @@ static int grad_tiled_t(Ctx* x, const T* U, const T* W, int s, double* g, hipStr
 }
 
 int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st) {
+  if (x->prec == FIRAL_F32 && !x->force_tiled) {
+    int n_tiles = 0;
+    FIRAL_CHECK(grad_fused_launch(x, (const float*)U, (const float*)W, s, st, &n_tiles));
+    if (n_tiles > 0) {
+      k_grad_sum<<<(unsigned)cdiv(x->n_pool, 256), 256, 0, st>>>(x->gpart, x->n_pool, n_tiles, s,
+                                                                 g);
+      FIRAL_LAUNCHED();
+      return FIRAL_OK;
+    }
+  }
   if (x->prec == FIRAL_F64)
     return grad_tiled_t<double, false>(x, (const double*)U, (const double*)W, s, g, st);
   if (x->prec == FIRAL_BF16X3)

@@ -314,9 +314,12 @@ def test_pcg_breakdown_and_not_converged(unfused, monkeypatch):
 
 # ----------------------------------------------------------------------- grad
 
+@pytest.mark.parametrize("unfused", ["0", "1"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_grad_matches_oracle(prec, shape):
+def test_grad_matches_oracle(prec, shape, unfused, monkeypatch):
+    # FP32 with d <= 128: the fused one-pass gradient, or (FIRAL_UNFUSED=1) the row-tiled passes
+    monkeypatch.setenv("FIRAL_UNFUSED", unfused)
     n, nl, d, c, s = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=12)
     ctx, X, H = context(p, prec, s)
