@@ -14,6 +14,9 @@
 //      chunks of the range.
 // The contraction index of every MFMA is permuted within groups of 16 so that
 // each lane's four operands are contiguous in LDS (one 128-bit read).
+// The same staging serves the bf16x3 form of the product and the fused FP32
+// gradient of eq. 11 (k_grad_fused: X U and X W per chunk, then the per-row
+// contraction, with no second product).
 #include <algorithm>
 
 #include <hip/hip_ext.h>
