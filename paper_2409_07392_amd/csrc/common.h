@@ -79,7 +79,8 @@ struct Ctx {
   int64_t fused_part_elems;
   int fused_max_ncb;    // fused product: column blocks per wave, 2 (wide tiles) or 1 (two
                         // workgroups' registers per CU, next chunk fetched ahead)
-  int force_tiled;      // product: the row-tiled kernels even where the fused plan fits
+  int force_tiled;      // product and FP32 gradient: the row-tiled kernels even where the
+                        // fused ones fit
   int force_multik;     // PCG: separate kernels even where the column-local step fits
                         // (FIRAL_UNFUSED=1 sets both; firal_autotune chooses them)
   int async;            // enqueue without host reads (graph capture): fixed-trip PCG whose
