@@ -179,8 +179,9 @@ int firal_profile_end(firal_ctx ctx, double* total_ms, int64_t* launches);
  * context and remembers the choice for the process per bucket (precision, d, c, s, n_pool +
  * n_lab rounded up to a power of two); a bucket already tuned is applied without timing.
  * The context's work blocks and preconditioner are overwritten.  choice (host, may be NULL)
- * gets bit 0 = row-tiled product (and FP32 gradient), bit 1 = separate-kernel PCG, bit 2 = fused product with two
- * column blocks per wave (else one, the next row chunk fetched ahead).  Synchronous. */
+ * gets bit 0 = row-tiled product (and FP32 gradient), bit 1 = separate-kernel PCG, bit 2 =
+ * fused product with two column blocks per wave (else one, the next row chunk fetched
+ * ahead).  Synchronous. */
 int firal_autotune(firal_ctx ctx, int32_t s, int32_t* choice, void* stream);
 
 /* Batch of independent Relax problems (extension (2)): one Relax iteration (Algorithm 2) of
