@@ -199,9 +199,29 @@ __device__ __forceinline__ f32x4 mfma3(const bf16x8& ah, const bf16x8& al, const
 }
 
 // ------------------------------------------------------- reductions
+// v + (v moved across lanes by one DPP pattern): both 32-bit halves move with the same
+// control; lanes the row/bank masks leave unwritten, or whose source lies outside the row
+// (bound_ctrl), add 0.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, BANK_MASK, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, BANK_MASK, true);
+  return v + __hiloint2double(hi, lo);
+}
+// Sum over the 64 lanes of a wave in a fixed order, returned in every lane: pairs and quads
+// by quad permutes, the 16-lane rows by right shifts of 4 and 8, then row 1 collects row 0
+// and row 3 row 2 (row broadcast of lane 15), and row 3 collects rows 0-1 (broadcast of
+// lane 31). The total lands in lane 63, which a readlane hands to all lanes.
 __device__ __forceinline__ double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-  return v;
+  v = dpp_add<0xB1, 0xF, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xF, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x114, 0xF, 0xE>(v);   // row_shr:4, lanes 4-15 of each row
+  v = dpp_add<0x118, 0xF, 0xC>(v);   // row_shr:8, lanes 8-15 of each row
+  v = dpp_add<0x142, 0xA, 0xF>(v);   // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC, 0xF>(v);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));

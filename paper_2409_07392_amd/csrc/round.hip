@@ -172,7 +172,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A,
         const double x = A[(int64_t)(r0 + i) * d + j];
         sg += x * x;
       }
-      sg = __shfl(wave_sum(sg), 0, 64);   // the sum is formed in lane 0; every lane needs it
+      sg = wave_sum(sg);
       const double x0 = A[(int64_t)r0 * d + j];
       if (tid == 0) dg[j] = A[(int64_t)j * d + j];
       if (sg == 0.0) {
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(kTriThreads) void k_tridiag(double* __restrict__ A,
         p[i] = beta * acc;
         pv += beta * acc * v[i];
       }
-      const double K = 0.5 * beta * __shfl(wave_sum(pv), 0, 64);
+      const double K = 0.5 * beta * wave_sum(pv);
       for (int i = tid; i < n2; i += 64) p[i] = p[i] - K * v[i];
     }
     __syncthreads();
@@ -282,7 +282,7 @@ __device__ __forceinline__ void tri_block(double (&a)[D16][D16], const TriLds& L
     if (tid < 64) {
       double sg = 0.0;
       for (int i = r0 + 1 + tid; i < d; i += 64) sg += L.col[i] * L.col[i];
-      sg = __shfl(wave_sum(sg), 0, 64);
+      sg = wave_sum(sg);
       const double x0 = L.col[r0];
       if (sg == 0.0) {
         if (tid == 0) {
@@ -328,7 +328,7 @@ __device__ __forceinline__ void tri_block(double (&a)[D16][D16], const TriLds& L
         L.w[i] = pi;
         pv += pi * L.v[i];
       }
-      const double K = 0.5 * beta * __shfl(wave_sum(pv), 0, 64);
+      const double K = 0.5 * beta * wave_sum(pv);
       for (int i = tid; i < 16 * D16; i += 64) L.w[i] = L.w[i] - K * L.v[i];
     }
     __syncthreads();
@@ -524,8 +524,8 @@ __global__ __launch_bounds__(1024) void k_round_nu(const double* __restrict__ la
 }
 
 // The same iteration for up to 64 kNuPerLane eigenvalues in one wave: each lane keeps its
-// eigenvalues in registers and the sums are formed in lane 0 and broadcast, so every lane
-// takes the same steps and no barrier is needed.
+// eigenvalues in registers and every lane receives the wave-wide sums, so all lanes take
+// the same steps and no barrier is needed.
 constexpr int kNuPerLane = 32;
 __global__ __launch_bounds__(64) void k_round_nu_wave(const double* __restrict__ lam, int n,
                                                       double eta, double* __restrict__ nu_out) {
@@ -551,8 +551,8 @@ __global__ __launch_bounds__(64) void k_round_nu_wave(const double* __restrict__
         f += a2;
         fp += a2 * a;
       }
-    f = __shfl(wave_sum(f), 0, 64);
-    fp = __shfl(wave_sum(fp), 0, 64);
+    f = wave_sum(f);
+    fp = wave_sum(fp);
     const double phi = f, dphi = -2.0 * fp;
     if (phi > 1.0) lo = nu;
     else if (phi < 1.0) hi = nu;

@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) void k_gamma_rows(T* __restrict__ G, int64_t R
       a += (double)gv[q].x * hv[q].x + (double)gv[q].y * hv[q].y + (double)gv[q].z * hv[q].z +
            (double)gv[q].w * hv[q].w;
     a = wave_sum(a);
-    const float al = (float)__shfl(a, 0, 64);
+    const float al = (float)a;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int k4 = lane + 64 * q;
@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_gamma_rows(T* __restrict__ G, int64_t R
     double a = 0.0;
     for (int k = lane; k < c; k += 64) a += (double)gr[k] * (double)hr[k];
     a = wave_sum(a);
-    const T al = (T)__shfl(a, 0, 64);
+    const T al = (T)a;
     for (int k = lane; k < c; k += 64) gr[k] = om * ((gr[k] - al) * hr[k]);
   }
 }
