@@ -32,6 +32,7 @@ namespace firal {
 namespace {
 
 constexpr int kMaxD = 1024;         // d limit of the Round step (LDS rows of the update)
+constexpr int kUpdSplit = 8;        // workgroups per class of the update, by row range
 constexpr int kScoreTM = 64, kScoreTN = 64, kScoreTK = 16, kScorePad = 4;
 constexpr int kTriThreads = 512;
 
@@ -835,7 +836,8 @@ __global__ __launch_bounds__(1024) void k_round_pick(const double* __restrict__ 
 
 // The update for the row selected in round t, per class k: (H)_k += (H_o)_k / b + g x x^T and
 // C_k += O_k / b + g u u^T with u = L_k^-1 x; a copy of C_k goes to the eigenvalue workspace;
-// the row leaves the candidates.
+// the row leaves the candidates.  Grid (c, kUpdSplit): each workgroup forms u for its class and
+// updates one range of rows of the class's blocks.
 template <typename T>
 __global__ __launch_bounds__(256) void k_round_update(
     const T* __restrict__ X, const T* __restrict__ H, int d, int c, double inv_b,
@@ -844,10 +846,11 @@ __global__ __launch_bounds__(256) void k_round_update(
     double* __restrict__ Hacc, double* __restrict__ Ework, int32_t* __restrict__ mask,
     int32_t* __restrict__ err) {
   __shared__ double xs[kMaxD], us[kMaxD];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = blockIdx.x, part = blockIdx.y, tid = threadIdx.x;
+  const bool lead = k == 0 && part == 0 && tid == 0;
   const int64_t i = sel[t];
   if (i < 0) {
-    if (k == 0 && tid == 0) err[0] = 1;
+    if (lead) err[0] = 1;
     return;
   }
   for (int a = tid; a < d; a += blockDim.x) xs[a] = (double)X[i * d + a];
@@ -862,15 +865,18 @@ __global__ __launch_bounds__(256) void k_round_update(
   __syncthreads();
   const double h = (double)H[i * c + k];
   const double gk = h * (1.0 - h);
-  for (int64_t e = tid; e < dd; e += blockDim.x) {
-    const int a = (int)(e / d), bb = (int)(e - (e / d) * d);
+  // this workgroup's rows of the class-k blocks (d <= kMaxD: an offset in a block fits int)
+  const int rows = (d + kUpdSplit - 1) / kUpdSplit;
+  const int a0 = part * rows, a1 = min(d, a0 + rows);
+  for (int e = a0 * d + tid; e < a1 * d; e += blockDim.x) {
+    const int a = e / d, bb = e - a * d;
     const int64_t s = k * dd + e;
     const double cn = Cm[s] + Ot[s] * inv_b + gk * us[a] * us[bb];
     Cm[s] = cn;
     Hacc[s] = Hacc[s] + Ho[s] * inv_b + gk * xs[a] * xs[bb];
     Ework[s] = cn;
   }
-  if (k == 0 && tid == 0) mask[i] = 1;
+  if (lead) mask[i] = 1;
 }
 
 // min over all eigenvalues (one workgroup)
@@ -1035,11 +1041,11 @@ static int round_step_launch(Round* r, hipStream_t st) {
   FIRAL_LAUNCHED();
   const Ctx* x = r->x;
   if (x->prec == FIRAL_F64)
-    k_round_update<double><<<c, 256, 0, st>>>((const double*)x->X, (const double*)x->H, d, c,
+    k_round_update<double><<<dim3(c, kUpdSplit), 256, 0, st>>>((const double*)x->X, (const double*)x->H, d, c,
                                               1.0 / r->b, r->sel, t, r->Li, r->Ho, r->Ot, r->Cm,
                                               r->Hacc, r->Ew, r->mask, r->flags + 1);
   else
-    k_round_update<float><<<c, 256, 0, st>>>((const float*)x->X, (const float*)x->H, d, c,
+    k_round_update<float><<<dim3(c, kUpdSplit), 256, 0, st>>>((const float*)x->X, (const float*)x->H, d, c,
                                              1.0 / r->b, r->sel, t, r->Li, r->Ho, r->Ot, r->Cm,
                                              r->Hacc, r->Ew, r->mask, r->flags + 1);
   FIRAL_LAUNCHED();
