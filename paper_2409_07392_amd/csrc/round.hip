@@ -435,6 +435,7 @@ __global__ __launch_bounds__(256) void k_sturm(const double* __restrict__ diag,
   const double tol = 4.0 * 1.1102230246251565e-16 * nrm + pivmin;
   const int sl = tid % S, j = blockIdx.y * EPW + tid / S;
   const int gshift = (tid & 63) / S * S;        // first lane of this lane's group in the wave
+  constexpr unsigned long long kGroupMask = S == 64 ? ~0ull : (1ull << (S % 64)) - 1;
   const bool on = j < d;
   double l = L0 - tol, u = H0 + tol;
   bool active = on;
@@ -454,9 +455,9 @@ __global__ __launch_bounds__(256) void k_sturm(const double* __restrict__ diag,
     }
     const uint64_t m = __ballot(active && cnt > j);
     if (active) {
-      const uint32_t bits = (uint32_t)((m >> gshift) & ((S == 64 ? ~0ull : (1ull << S) - 1)));
-      const double nl = bits == 0 ? l + S * h : (bits & 1u ? l : l + (__ffs(bits) - 1) * h);
-      const double nu = bits == 0 ? u : l + __ffs(bits) * h;
+      const unsigned long long bits = (m >> gshift) & kGroupMask;
+      const double nl = bits == 0 ? l + S * h : (bits & 1ull ? l : l + (__ffsll(bits) - 1) * h);
+      const double nu = bits == 0 ? u : l + __ffsll(bits) * h;
       if (!(nu - nl > tol + 4.0 * 1.1102230246251565e-16 * fmax(fabs(nl), fabs(nu))) ||
           (nl == l && nu == u))
         active = false;
@@ -965,9 +966,12 @@ static int eigvals_launch(Round* r, double* A, hipStream_t st) {
     k_tridiag<<<c, kTriThreads, 4 * (size_t)d * sizeof(double), st>>>(A, d, r->tdiag, r->toff);
   }
   FIRAL_LAUNCHED();
-  // few eigenvalues: 32 or 16 lanes share each one (33- or 17-section); many: one lane each
-  // (bisection)
-  if ((int64_t)c * d <= 32768)
+  // few eigenvalues: 64, 32 or 16 lanes share each one (65-, 33- or 17-section); many: one lane
+  // each (bisection)
+  if ((int64_t)c * d <= 16384)
+    k_sturm<64><<<dim3(c, (unsigned)cdiv(d, 256 / 64)), 256, 0, st>>>(r->tdiag, r->toff, d,
+                                                                      r->lam);
+  else if ((int64_t)c * d <= 32768)
     k_sturm<32><<<dim3(c, (unsigned)cdiv(d, 256 / 32)), 256, 0, st>>>(r->tdiag, r->toff, d,
                                                                       r->lam);
   else if ((int64_t)c * d <= 65536)
