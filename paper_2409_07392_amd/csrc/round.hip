@@ -967,8 +967,10 @@ static int eigvals_launch(Round* r, double* A, hipStream_t st) {
   }
   FIRAL_LAUNCHED();
   // few eigenvalues: 64, 32 or 16 lanes share each one (65-, 33- or 17-section); many: one lane
-  // each (bisection)
-  if ((int64_t)c * d <= 16384)
+  // each (bisection).  A whole wave per eigenvalue pays while it keeps the waves at about four
+  // per SIMD or fewer (c d <= 4096); beyond that the doubled count work costs more than the
+  // steps it saves.
+  if ((int64_t)c * d <= 4096)
     k_sturm<64><<<dim3(c, (unsigned)cdiv(d, 256 / 64)), 256, 0, st>>>(r->tdiag, r->toff, d,
                                                                       r->lam);
   else if ((int64_t)c * d <= 32768)
