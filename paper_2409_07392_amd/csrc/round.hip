@@ -601,8 +601,10 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
 // fit in L2 together, else class then row tile.
 // CT is the decision precision: every step from the products to the class term is computed
 // in CT (FP64, or FP32 on the FP32 MFMA as the paper's single-precision implementation does).
+// FP32 operands run four workgroups per CU (128 VGPRs, 56 bytes per lane spilled, still
+// faster than three without spills), FP64 two.
 template <typename T, typename CT>
-__global__ __launch_bounds__(256, 2) void k_round_score(const T* __restrict__ X,
+__global__ __launch_bounds__(256, sizeof(CT) == 4 ? 4 : 2) void k_round_score(const T* __restrict__ X,
                                                      const T* __restrict__ H, int64_t r0,
                                                      int64_t R, int d, int c,
                                                      const CT* __restrict__ W, int ldo,
