@@ -45,7 +45,7 @@ KERNEL_NAME = {"f32": "k_hvp_fused<7,1> (fused Lemma 1 product, FP32)",
 TRAFFIC = {"f32": (24.01 + 9.69) * 1e6,    # k_hvp_fused<7,1>: fetched + written bytes per launch
            "bf16x3": (45.71 + 17.96) * 1e6}  # k_hvp_fused_bf3<7,2>
 # the same for the Round step's scoring kernel at configuration 2 (per round, one launch)
-ROUND_TRAFFIC = {True: (43.15 + 101.10) * 1e6, False: (36.69 + 4.00) * 1e6}
+ROUND_TRAFFIC = {True: (43.15 + 101.10) * 1e6, False: (189.33 + 180.15) * 1e6}
 
 
 def parse():

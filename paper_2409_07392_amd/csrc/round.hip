@@ -602,16 +602,18 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
 // CT is the decision precision: every step from the products to the class term is computed
 // in CT (FP64, or FP32 on the FP32 MFMA as the paper's single-precision implementation does).
 // FP32 operands run four workgroups per CU (128 VGPRs, 56 bytes per lane spilled, still
-// faster than three without spills), FP64 two.
+// faster than three without spills), FP64 three (168 VGPRs, 92 bytes spilled, rows padded by
+// two values instead of four so that three fit in LDS; faster than two without spills).
 template <typename T, typename CT>
-__global__ __launch_bounds__(256, sizeof(CT) == 4 ? 4 : 2) void k_round_score(const T* __restrict__ X,
+__global__ __launch_bounds__(256, sizeof(CT) == 4 ? 4 : 3) void k_round_score(const T* __restrict__ X,
                                                      const T* __restrict__ H, int64_t r0,
                                                      int64_t R, int d, int c,
                                                      const CT* __restrict__ W, int ldo,
                                                      double eta, int rows_major,
                                                      CT* __restrict__ Tout) {
   constexpr int TM = kScoreTM, TN = kScoreTN, TK = kScoreTK;
-  constexpr int SA = TM + kScorePad, SB = TN + kScorePad;
+  constexpr int PAD = sizeof(CT) == 4 ? kScorePad : kScorePad / 2;   // FP64: three per CU fit
+  constexpr int SA = TM + PAD, SB = TN + PAD;
   __shared__ CT As[2][TK][SA];
   __shared__ CT Bu[2][TK][SB];
   __shared__ CT Bv[2][TK][SB];
