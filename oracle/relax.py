@@ -325,9 +325,21 @@ def relax_iteration(X, H, n_pool, w, b, lam, beta0, seed, t, s, tol, max_iter,
     return w_new, info
 
 
+def relative_change_small(f_prev: float, f_cur: float, stop_rel: float) -> bool:
+    """The stop test of the experiments section: the objective moved by at most stop_rel
+    relative to its previous value, |f_cur - f_prev| <= stop_rel * |f_prev|."""
+    return abs(f_cur - f_prev) <= stop_rel * abs(f_prev)
+
+
 def relax(X, H, n_pool, b, lam, beta0, seed, T, s, tol, max_iter, project=False,
-          w0=None, callback=None):
-    """T iterations of Algorithm 2 from w = 1/n; returns (z = b*w, history)."""
+          w0=None, callback=None, stop_rel=0.0):
+    """Algorithm 2 from w = 1/n for at most T iterations; returns (z = b*w, history).
+
+    stop_rel > 0 adds the termination of the experiments section: after iteration t >= 2
+    the loop ends when the objective estimate f_hat of iteration t differs from that of
+    iteration t-1 by at most stop_rel times the latter (the weights of iteration t are kept).
+    len(history) is the number of iterations run.
+    """
     w = np.full(n_pool, 1.0 / n_pool) if w0 is None else w0.copy()
     hist = []
     for t in range(1, T + 1):
@@ -337,6 +349,9 @@ def relax(X, H, n_pool, b, lam, beta0, seed, T, s, tol, max_iter, project=False,
                                                                "g_absmax", "beta")})
         if callback is not None:
             callback(t, w, info)
+        if stop_rel > 0.0 and t >= 2 and relative_change_small(hist[-2]["f_hat"],
+                                                                hist[-1]["f_hat"], stop_rel):
+            break
     return b * w, hist
 
 

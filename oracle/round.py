@@ -190,9 +190,12 @@ def round_diag(X, H, n_pool, z, lam, eta, b, rounds: int | None = None,
                 score_max=np.array(smax), criterion=st.criterion(), state=st)
 
 
-def eta_sweep(X, H, n_pool, z, lam, etas, b) -> dict:
+def eta_sweep(X, H, n_pool, z, lam, etas, b, fp32: bool = False) -> dict:
     """The eta choice of the experiments section: run the Round step for each eta
-    and keep the one whose selection maximises min_k lambda_min((H)_k)."""
-    crit = [round_diag(X, H, n_pool, z, lam, e, b)["criterion"] for e in etas]
+    and keep the one whose selection maximises min_k lambda_min((H)_k) (the first
+    such eta in the list on ties)."""
+    runs = [round_diag(X, H, n_pool, z, lam, e, b, fp32=fp32) for e in etas]
+    crit = [r["criterion"] for r in runs]
     best = int(np.argmax(crit))
-    return dict(etas=list(etas), criterion=crit, best=etas[best])
+    return dict(etas=list(etas), criterion=crit, best=etas[best], best_index=best,
+                selected=runs[best]["selected"])

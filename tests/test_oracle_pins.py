@@ -323,3 +323,31 @@ def test_projected_and_literal_modes_agree():
     assert abs(i0["f_hat"] - i1["f_hat"]) < 1e-9 * abs(i0["f_hat"])
     np.testing.assert_allclose(i0["g"], i1["g"], rtol=1e-7, atol=1e-9 * np.abs(i0["g"]).max())
     np.testing.assert_allclose(w0, w1, rtol=1e-9)
+
+
+# ------------------------------------------------------------ stop rule
+
+def test_relative_change_stop_rule_hand_values():
+    # |f_t - f_{t-1}| <= tol |f_{t-1}| (experiments section: relative change below 1e-4)
+    assert orc.relative_change_small(100.0, 100.005, 1e-4)
+    assert orc.relative_change_small(1024.0, 1023.0, 2.0 ** -10)  # exactly on the bound
+    assert not orc.relative_change_small(1024.0, 1022.0, 2.0 ** -10)
+    assert not orc.relative_change_small(100.0, 100.02, 1e-4)
+    assert orc.relative_change_small(-50.0, -50.004, 1e-4)
+    assert not orc.relative_change_small(-50.0, -49.99, 1e-4)
+
+
+def test_relax_stop_rule_ends_at_the_first_small_change():
+    p = make_small(n=60, n_lab=4, d=3, c=4, s=4, seed=91)
+    full_w = []
+    _, full = orc.relax(p.X, p.H, p.n_pool, 4.0, 1e-3, 0.3, 5, 25, p.s, 1e-10, 500,
+                        project=True, callback=lambda t, w, info: full_w.append(w.copy()))
+    f = [h["f_hat"] for h in full]
+    rel = [abs(f[t] - f[t - 1]) / abs(f[t - 1]) for t in range(1, len(f))]
+    stop_rel = float(np.median(rel))      # some change along the run passes, earlier ones do not
+    want = 1 + next(t for t in range(1, len(f)) if rel[t - 1] <= stop_rel)
+    z, hist = orc.relax(p.X, p.H, p.n_pool, 4.0, 1e-3, 0.3, 5, 25, p.s, 1e-10, 500,
+                        project=True, stop_rel=stop_rel)
+    assert len(hist) == want
+    assert [h["f_hat"] for h in hist] == f[:want]
+    np.testing.assert_allclose(z, 4.0 * full_w[want - 1], rtol=0, atol=0)
