@@ -1,32 +1,36 @@
 """Benchmark of the Relax step (Algorithm 2) on one MI355X.
 
-A "step" is one Relax iteration (probes, preconditioner, two PCG solves,
-H_p product, gradient, mirror-descent update) over the configuration-2
-workload: n = 50,000 pool points + 10 labeled, d = 100, c = 10, s = 20
-probes, PCG tol 1e-6, b = 100, synthetic Gaussian-mixture features (10
-clusters, whitened) and softmax probabilities with mean max-prob 0.7.
+Default (the headline): configuration 4, n = 1,280,000 pool points + 2000 labeled, d = 384,
+c = 1000, s = 16 probes, b = 1000, PCG tol 1e-5; Gaussian-mixture features (1000 clusters)
+and softmax probabilities whose entropies are spread uniformly over [0.2, 0.9] log c, drawn on
+the GPU.  A "step" is one full Hessian product of Lemma 1 over all 1,282,000 rows with all 16
+probes (4 N c d s = 3.15e13 flop), the operation every PCG iteration of Algorithm 2 spends its
+time in; `value` is its rate in TFLOP/s for the FP32 leg.  Measured beside it, for FP32 and for
+bf16x3 (products as three bf16 MFMA passes), and reported in `precision_legs`:
+  * the product's rate and the time of its kernels (event pairs attached to their launches);
+  * one full Relax iteration (Algorithm 2 from w = 1/n: probes, preconditioner with FP64
+    factors, two PCG solves to the relative residual 1e-5, the H_p product, the gradient, the
+    mirror step), its wall time and CG counts;
+  * the relative error of the eq. 11 gradient against the GPU's FP64 mode with the same
+    probes and the same fixed CG count (the FP64 mode is itself held to the oracle at 1e-10 on
+    a 1% row sample of this workload by the test suite).
 
-    python bench.py [--steps K] [--warmup W] [--prec f32|f64] [--literal]
+    python bench.py [--steps K] [--warmup W] [--relax-iters R] [--no-cpu-baseline]
 
 Prints one JSON line.  --gpus N > 1 is refused: the library runs on one GPU.
 
---workload 3 / 4 measures the larger configurations instead (their inputs drawn on
-the GPU with the same recipes): configuration 3 (n = 200,000, d = 256, c = 100,
-s = 32) times the sampled objective and its adjoint gradient at a Dirichlet z;
-configuration 4 (n = 1,280,000, d = 384, c = 1000, s = 16) times Relax iterations
-with a fixed number of CG iterations per solve (--fixed-cg).  Both report the
-product's TFLOP/s and the gradient error against the GPU FP64 mode for FP32 and
-bf16x3.  --workload 5 runs the batch workload (64 uneven problems, 30 iterations) as one
-captured graph and one call at a time.  --workload table5 runs the first active-learning
-round (Relax, then Round) at the ImageNet-50 and Caltech-101 shapes of the paper's
-single-GPU timing table.  These are measurements of the other workloads, not the bench
-line.  The default run also reports the Round step (Algorithm 3) on the Relax leg's weights.
+Other workloads (not the bench line): --workload 2 (configuration 2: n = 50,000, d = 100,
+c = 10, s = 20; whole Relax iterations per step, plus the Round step), 3 (configuration 3:
+the sampled objective and its adjoint gradient), 5 (64 uneven problems as a batch), studies
+(convergence and scaling studies), al (a synthetic active-learning loop).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,56 +40,252 @@ sys.path.insert(0, ROOT)
 METRIC = "Relax iter time + HVP TFLOP/s, FP32 vs bf16x3 at ≤1e-4 rel grad error"
 # TFLOP/s, MI355X dense MFMA; bf16x3 counts the FP32-equivalent products of three bf16 passes
 PEAK = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0 / 3}
-KERNEL_NAME = {"f32": "k_hvp_fused<7,1> (fused Lemma 1 product, FP32)",
-               "bf16x3": "k_hvp_fused_bf3<7,2> (fused Lemma 1 product, bf16x3)",
-               "f64": "row-tiled product kernels (FP64), per-chunk span"}
-# HBM bytes per launch of the main kernel from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
-# each scaled by the copy-kernel calibration factor (profiles/; None until measured for
-# the current kernel)
-TRAFFIC = {"f32": (24.01 + 9.69) * 1e6,    # k_hvp_fused<7,1>: fetched + written bytes per launch
-           "bf16x3": (45.71 + 17.96) * 1e6}  # k_hvp_fused_bf3<7,2>
-# the same for the Round step's scoring kernel at configuration 2 (per round, one launch)
-ROUND_TRAFFIC = {True: (43.15 + 101.10) * 1e6, False: (189.33 + 180.15) * 1e6}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16x3"])
+    ap.add_argument("--workload", default="4", choices=["2", "3", "4", "5", "studies", "al"])
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64", "bf16x3"],
+                    help="workloads 2 and 5: the precision of the main leg")
     ap.add_argument("--no-bf16x3", action="store_true", help="skip the bf16x3 leg")
     ap.add_argument("--literal", action="store_true", help="PCG without the null-space projection")
     ap.add_argument("--hvp-reps", type=int, default=50)
+    ap.add_argument("--prof-reps", type=int, default=3,
+                    help="configuration 4: product calls timed kernel by kernel")
+    ap.add_argument("--relax-iters", type=int, default=1,
+                    help="configuration 4: Relax iterations timed per precision (tol 1e-5)")
+    ap.add_argument("--relax-max-cg", type=int, default=200,
+                    help="configuration 4: cap on the CG iterations of each solve")
+    ap.add_argument("--grad-cg", type=int, default=10,
+                    help="configuration 4: fixed CG iterations of the gradient-error runs")
+    ap.add_argument("--no-grad-error", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--workload", default="2",
-                    choices=["2", "3", "4", "5", "table5", "studies", "al"])
     ap.add_argument("--study", default="fig1,fig4,fig5",
                     help="--workload studies: comma-separated subset of fig1, fig4, fig5")
     ap.add_argument("--no-round", action="store_true", help="skip the Round-step leg")
-    ap.add_argument("--round-rounds", type=int, default=2,
-                    help="configurations 3/4: Round-step rounds timed per decision precision "
-                         "(0 skips the Round leg)")
+    ap.add_argument("--round-rounds", type=int, default=0,
+                    help="configurations 3/4: Round-step rounds timed per decision precision")
     ap.add_argument("--round-only", action="store_true",
                     help="configurations 3/4: only the Round-step leg")
     ap.add_argument("--eta", type=float, default=None,
                     help="Round-step learning rate (default 8 sqrt(dc), the theorem's value at "
                          "epsilon = 1)")
-    ap.add_argument("--fixed-cg", type=int, default=50,
-                    help="configuration 4: CG iterations per solve of each timed Relax iteration")
     return ap.parse_args()
 
 
-def cpu_baseline(p, beta0, project, budget_s=10.0, max_iters=8):
-    """Time the FP64 oracle on full-size Relax iterations of the same workload: iterations
-    t = 1, 2, ... until about budget_s seconds of CPU work (at most max_iters)."""
-    import numpy as np
+def log(msg):
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
+
+
+def read_traffic(summary: str):
+    """HBM bytes per launch from a committed counter summary under profiles/ (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the copy-kernel calibration): the summary's
+    `traffic_bytes_per_launch:` line, or None when the summary is missing or the kernel's source
+    file (`source:` and `source_sha256:` lines) has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", summary)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"^traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt, re.M)
+    src = re.search(r"^source:\s*(\S+)", txt, re.M)
+    sha = re.search(r"^source_sha256:\s*([0-9a-f]+)", txt, re.M)
+    if not (m and src and sha):
+        return None
+    fpath = os.path.join(ROOT, src.group(1))
+    if not os.path.exists(fpath):
+        return None
+    if hashlib.sha256(open(fpath, "rb").read()).hexdigest() != sha.group(1):
+        return None
+    return float(m.group(1))
+
+
+def host_threads():
     from threadpoolctl import threadpool_info
+    return max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+
+
+# --------------------------------------------------------------- configuration 4
+
+def product_leg(ctx, p, prec, steps, warmup, prof_reps):
+    """Time `steps` full products after `warmup`, then each row-tiled kernel on its own."""
+    import torch
+    flops = 4.0 * p.N * p.c * p.d * p.s
+    B = ctx.probes(p.probe_seed, 1, p.s)
+    out = torch.empty_like(B)
+    om = torch.full((p.N,), 1.0, dtype=torch.float64, device="cuda:0")
+    om[:p.n_pool] = p.b / p.n_pool
+    for _ in range(warmup):
+        ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.hvp(B, omega=om, shift=p.lam, out=out)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    leg = {"hvp_ms": 1e3 * el / steps, "hvp_tflops": flops * steps / el / 1e12}
+    # the kernels of the product, each with event pairs attached to its launches; each of the
+    # two contractions does half of the product's algorithmic flops (2 N c d s)
+    kern = {}
+    for name in ("product", "product_t"):
+        ctx.profile_begin(name)
+        for _ in range(prof_reps):
+            ctx.hvp(B, omega=om, shift=p.lam, out=out)
+        ms, n = ctx.profile_end()
+        if n == 0:
+            continue
+        half = 2.0 * p.N * p.c * p.d * p.s * prof_reps
+        kern[name] = {"launches_per_product": n // prof_reps, "ms_per_product": ms / prof_reps,
+                      "avg_launch_us": 1e3 * ms / n, "tflops": half / (ms / 1e3) / 1e12}
+    leg["kernels"] = kern
+    return leg, el
+
+
+def relax_leg(ctx, p, iters, max_cg):
+    """Whole Relax iterations t = 1..iters from w = 1/n at the workload's PCG tolerance."""
+    import torch
+
+    from paper_2409_07392_amd import default_beta0
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda:0")
+    beta0 = default_beta0(p.n_pool, p.T)
+    out = []
+    for t in range(1, iters + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, max_cg, True)
+        torch.cuda.synchronize()
+        out.append({"t": t, "s": time.perf_counter() - t0, "cg_iters": list(info["cg_iters"]),
+                    "converged": info["converged"], "relres_max": info["relres_max"],
+                    "f_hat": info["f_hat"]})
+        log(f"  Relax iteration {t}: {out[-1]['s']:.2f} s, CG {info['cg_iters']}")
+    return out
+
+
+def fixed_cg_gradient(ctx, p, n_cg):
+    """The eq. 11 gradient of iteration 1 with exactly n_cg CG iterations per solve."""
+    import torch
+
+    from paper_2409_07392_amd import default_beta0
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda:0")
+    g = torch.empty_like(w)
+    ctx.relax_step(w, p.b, p.lam, default_beta0(p.n_pool, p.T), p.probe_seed, 1, p.s, 0.0, n_cg,
+                   True, g_out=g)
+    return g.cpu().numpy()
+
+
+def cpu_baseline_products(p, rows=12820, budget_s=20.0):
+    """The FP64 oracle's product (Lemma 1, NumPy) on the first `rows` rows (1%) of the same
+    workload, timed on the host: TFLOP/s over whole calls."""
+    import numpy as np
 
     from oracle import relax as orc
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    X = p.X[:rows].double().cpu().numpy()
+    H = p.H[:rows].double().cpu().numpy()
+    from oracle.relax import probes
+    B = probes(p.probe_seed, 1, p.d, p.s, p.c)
+    om = np.full(rows, p.b / p.n_pool)
+    flops = 4.0 * rows * p.c * p.d * p.s
+    t0 = time.perf_counter()
+    calls = 0
+    while calls < 1 or (time.perf_counter() - t0 < budget_s and calls < 8):
+        orc.hvp(X, H, om, p.lam, B)
+        calls += 1
+    dt = time.perf_counter() - t0
+    return {"value": flops * calls / dt / 1e12, "unit": "TFLOP/s", "cores": int(host_threads()),
+            "kind": "oracle",
+            "sample": f"{calls} calls of the FP64 NumPy product over the first {rows} rows (1%) "
+                      f"of the same workload ({p.d} x {p.s} x {p.c} blocks), {dt:.1f} s; the "
+                      "rate is per Hessian-product flop, as `value`"}
+
+
+def headline(args):
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext
+    from synthdata.device import make_problem_device
+    log("drawing configuration 4 on the GPU")
+    p = make_problem_device(4, device="cuda:0")
+    flops = 4.0 * p.N * p.c * p.d * p.s
+    legs, grads, main = {}, {}, None
+    precs = ["f32"] + ([] if args.no_bf16x3 else ["bf16x3"])
+    for prec in precs:
+        log(f"{prec}: context")
+        ctx = RelaxContext(p.X, p.H, p.n_pool, p.s, prec)
+        log(f"{prec}: {args.steps} timed products")
+        leg, el = product_leg(ctx, p, prec, args.steps, args.warmup, args.prof_reps)
+        if prec == "f32":
+            main = (leg, el)
+        log(f"{prec}: {leg['hvp_ms']:.1f} ms per product; Relax iterations at tol {p.tol}")
+        leg["relax_iterations"] = relax_leg(ctx, p, args.relax_iters, args.relax_max_cg)
+        leg["relax_iter_s"] = float(np.median([r["s"] for r in leg["relax_iterations"]]))
+        if not args.no_grad_error:
+            log(f"{prec}: gradient at {args.grad_cg} fixed CG iterations")
+            grads[prec] = fixed_cg_gradient(ctx, p, args.grad_cg)
+        legs[prec] = leg
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    if not args.no_grad_error:
+        log("f64: reference gradient")
+        ctx = RelaxContext(p.X.double(), p.H.double(), p.n_pool, p.s, "f64")
+        ref = fixed_cg_gradient(ctx, p, args.grad_cg)
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+        nrm = np.linalg.norm(ref)
+        for k in grads:
+            legs[k]["rel_grad_err_vs_f64"] = float(np.linalg.norm(grads[k] - ref) / nrm)
+            legs[k]["grad_error_cg_iters"] = args.grad_cg
+    leg, el = main
+    kern = leg["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["ms_per_product"])
+    kname = {"product": "k_xv (first contraction X V with the row step of Lemma 1, FP32)",
+             "product_t": "k_xtg (second contraction X^T G', FP32)"}[dom]
+    traffic_file = {"product": "k_xv_cfg4_traffic.md", "product_t": "k_xtg_cfg4_traffic.md"}[dom]
+    res = {
+        "metric": METRIC,
+        "value": flops * args.steps / el / 1e12,
+        "unit": "TFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "cfg4: full Hessian product (Lemma 1) per step, n=1280000+2000 "
+                               "labeled, d=384, c=1000, s=16, b=1000, PCG tol 1e-5",
+                   "step_flop": flops, "pcg": "projected",
+                   "relax_iter_s_f32": legs["f32"]["relax_iter_s"],
+                   "relax_iter_s_bf16x3": legs.get("bf16x3", {}).get("relax_iter_s")},
+        "precision_legs": legs,
+        "roofline": {"bound": "mfma", "kernel": kname,
+                     "achieved": kern[dom]["tflops"], "peak": PEAK["f32"], "unit": "TFLOP/s",
+                     "frac": kern[dom]["tflops"] / PEAK["f32"],
+                     "avg_launch_us": kern[dom]["avg_launch_us"],
+                     "algorithmic_flop_per_launch": 2.0 * p.N * p.c * p.d * p.s /
+                     max(kern[dom]["launches_per_product"], 1),
+                     "traffic": read_traffic(traffic_file)},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle products on a 1% row sample")
+        res["cpu_baseline"] = cpu_baseline_products(p)
+    print(json.dumps(res), flush=True)
+
+
+# --------------------------------------------------------------- configuration 2
+
+def cpu_baseline_relax(p, beta0, project, budget_s=10.0, max_iters=8):
+    """Time the FP64 oracle on full-size Relax iterations of configuration 2: iterations
+    t = 1, 2, ... until about budget_s seconds of CPU work (at most max_iters)."""
+    import numpy as np
+
+    from oracle import relax as orc
     w = np.full(p.n_pool, 1.0 / p.n_pool)
     t0 = time.perf_counter()
     it = 0
@@ -94,7 +294,8 @@ def cpu_baseline(p, beta0, project, budget_s=10.0, max_iters=8):
         w, _ = orc.relax_iteration(p.X, p.H, p.n_pool, w, p.b, p.lam, beta0, p.probe_seed, it,
                                    p.s, p.tol, 1000, project=project)
     dt = time.perf_counter() - t0
-    return {"value": it / dt, "unit": "relax_iter/s", "cores": int(threads), "kind": "oracle",
+    return {"value": it / dt, "unit": "relax_iter/s", "cores": int(host_threads()),
+            "kind": "oracle",
             "sample": f"Relax iterations t=1..{it} of the same full-size workload in FP64 NumPy "
                       f"on the host, {dt:.1f} s"}
 
@@ -150,6 +351,7 @@ def run_leg(p, prec, steps, warmup, project, hvp_reps):
                 kern_tflops=flops / t_kern / 1e12, f_hat_last=infos[-1]["f_hat"])
 
 
+
 def grad_errors(p, project, n_cg=15):
     """Relative gradient error of FP32 and bf16x3 against the GPU FP64 mode (same probes,
     same fixed number of CG iterations, so only arithmetic precision differs)."""
@@ -173,6 +375,7 @@ def grad_errors(p, project, n_cg=15):
         ctx.close()
     ref = np.linalg.norm(g["f64"])
     return {k: float(np.linalg.norm(g[k] - g["f64"]) / ref) for k in ("f32", "bf16x3")}
+
 
 
 def round_leg(p, w, eta, fp32, cpu_rounds=2):
@@ -200,7 +403,7 @@ def round_leg(p, w, eta, fp32, cpu_rounds=2):
     rs = RoundSolver(ctx, z, p.lam, eta, b, fp32=fp32)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    ctx.profile_begin()
+    ctx.profile_begin("round_score")
     t0 = time.perf_counter()
     rs.step(b)
     res = rs.result()
@@ -233,37 +436,12 @@ def round_leg(p, w, eta, fp32, cpu_rounds=2):
             "roofline": {"bound": "mfma", "kernel": kname,
                          "achieved": flops / t_kern / 1e12, "peak": pk,
                          "unit": "TFLOP/s", "frac": flops / t_kern / 1e12 / pk,
-                         "kernel_us": t_kern * 1e6, "traffic": ROUND_TRAFFIC[fp32],
+                         "kernel_us": t_kern * 1e6, "traffic": read_traffic("round_score_fp32_cfg2_traffic.md" if fp32 else "round_score_fp64_cfg2_traffic.md"),
                          "executed_tflops": 1.5 * flops / t_kern / 1e12},
             "cpu_oracle": {"s_per_round": t_cpu, "rounds_timed": cpu_rounds,
                            "same_first_selections": same}}
 
 
-def log(msg):
-    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
-
-
-def hvp_timing(ctx, p, reps):
-    """(seconds per product call, seconds per main-kernel span) with omega = [b/n; 1]."""
-    import torch
-    B = ctx.probes(p.probe_seed, 1, p.s)
-    out = torch.empty_like(B)
-    om = torch.full((p.N,), 1.0, dtype=torch.float64, device="cuda:0")
-    om[:p.n_pool] = p.b / p.n_pool
-    ctx.hvp(B, omega=om, shift=p.lam, out=out)
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(reps):
-        ctx.hvp(B, omega=om, shift=p.lam, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    t_call = ev0.elapsed_time(ev1) / 1e3 / reps
-    ctx.profile_begin()
-    for _ in range(reps):
-        ctx.hvp(B, omega=om, shift=p.lam, out=out)
-    k_ms, k_n = ctx.profile_end()
-    return t_call, k_ms / 1e3 / max(k_n, 1)
 
 
 def round_large(p, z, eta, rounds, fp32):
@@ -280,7 +458,7 @@ def round_large(p, z, eta, rounds, fp32):
     t_setup = time.perf_counter() - t0
     rs.step(1)
     rs.result()
-    ctx.profile_begin()
+    ctx.profile_begin("round_score")
     t0 = time.perf_counter()
     rs.step(rounds)
     res = rs.result()
@@ -300,83 +478,6 @@ def round_large(p, z, eta, rounds, fp32):
             "score_executed_tflops": executed / t_kern / 1e12,
             "selected": [int(i) for i in res["selected"]]}
 
-
-# The first active-learning round of the paper's single-GPU timing table (Table 5):
-# ImageNet-50 and Caltech-101 shapes (Table 4), synthetic stand-ins of those sizes.
-TABLE5 = {
-    "imagenet50": dict(n=5000, n_lab=50, d=50, c=50, b=50, paper_relax_s=1.3, paper_round_s=1.1),
-    "caltech101": dict(n=1715, n_lab=101, d=100, c=101, b=101, paper_relax_s=1.9,
-                       paper_round_s=4.4),
-}
-
-
-def table5_workload(args):
-    """Relax (s = 10, CG relative residual 0.1, stop at a relative change of the objective
-    estimate below 1e-4, at most 100 iterations) then Round (b = budget) on each Table-5 shape,
-    wall-clock on one MI355X; the paper's A100 seconds are printed beside them as context."""
-    import numpy as np
-    import torch
-
-    from paper_2409_07392_amd import RelaxContext, RoundSolver, default_beta0, round_eta_sweep
-    from synthdata import make_problem
-    out = {}
-    for name, sh in TABLE5.items():
-        p = make_problem(2, n=sh["n"], n_lab=sh["n_lab"], d=sh["d"], c=sh["c"], s=10,
-                         b=float(sh["b"]), K=sh["c"], tol=0.1, T=100, seed=7000 + sh["c"])
-        dev = torch.device("cuda:0")
-        X = torch.as_tensor(p.X, dtype=torch.float32, device=dev).contiguous()
-        H = torch.as_tensor(p.H, dtype=torch.float32, device=dev).contiguous()
-        ctx = RelaxContext(X, H, p.n_pool, p.s, "f32")
-        beta0 = default_beta0(p.n_pool, 100)
-        eta = 8.0 * (p.d * p.c) ** 0.5
-
-        def solve():
-            w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device=dev)
-            f_prev, it = None, 0
-            for t in range(1, 101):
-                info = ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, 0.1, 1000, True)
-                it = t
-                f = info["f_hat"]
-                if f_prev is not None and abs(f - f_prev) <= 1e-4 * abs(f_prev):
-                    break
-                f_prev = f
-            return w, it
-
-        solve()                                         # warm-up (first launches)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        w, iters = solve()
-        torch.cuda.synchronize()
-        t_relax = time.perf_counter() - t0
-        z = (p.b * w).contiguous()
-        warm = RoundSolver(ctx, z, p.lam, eta, int(p.b), fp32=True)
-        warm.run()
-        warm.close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rs = RoundSolver(ctx, z, p.lam, eta, int(p.b), fp32=True)
-        sel = rs.run()
-        t_round = time.perf_counter() - t0
-        rs.close()
-        t0 = time.perf_counter()
-        sweep = round_eta_sweep(ctx, z, p.lam, [eta / 8, eta / 2, eta, 2 * eta, 8 * eta],
-                                int(p.b), fp32=True)
-        t_sweep = time.perf_counter() - t0
-        ctx.close()
-        out[name] = {"n_pool": p.n_pool, "n_lab": p.n_lab, "d": p.d, "c": p.c, "b": p.b,
-                     "relax_s": t_relax, "relax_iters": iters,
-                     "round_s": t_round, "round_eta": eta, "selected_first": [int(i) for i in sel[:5]],
-                     "eta_sweep_s": t_sweep, "eta_sweep_best": sweep["best"],
-                     "paper_a100_relax_s": sh["paper_relax_s"],
-                     "paper_a100_round_s": sh["paper_round_s"]}
-        log(f"{name}: relax {t_relax:.3f} s ({iters} it), round {t_round:.3f} s")
-    print(json.dumps({"workload": "Table 5 shapes (first active-learning round)",
-                      "data": "synthetic stand-ins of the ImageNet-50 and Caltech-101 shapes",
-                      "relax": "s = 10, CG relative residual 0.1, stop at relative change of "
-                               "f_hat < 1e-4 (at most 100 iterations), projected PCG, FP32",
-                      "round": "b = budget rounds, FP32 decision, eta = 8 sqrt(dc); the sweep "
-                               "runs 5 etas",
-                      "results": out}))
 
 
 def studies_workload(args):
@@ -480,7 +581,7 @@ def studies_workload(args):
             t_cg = time.perf_counter() - t0
             z = om[:q.n_pool].contiguous()
             rs = RoundSolver(ctx, z, q.lam, 8.0 * (d * c) ** 0.5, 2, fp32=True)
-            ctx.profile_begin()
+            ctx.profile_begin("round_score")
             t0 = time.perf_counter()
             rs.step(1)
             rs.result()
@@ -502,185 +603,6 @@ def studies_workload(args):
                                          "Round round with the FP32 decision")
     print(json.dumps({"workload": "studies", "data": "synthetic", "results": res}))
 
-
-def al_workload(args):
-    """A synthetic active-learning loop at the ImageNet-50 shape of Table 4 (c = 50 classes,
-    d = 50, pool 5000, 20,000 evaluation points, one labeled point per class to start, 6
-    rounds of 50): each round trains a multinomial logistic regression (scikit-learn, host)
-    on the labeled points and selects the next 50 by FIRAL (Relax with s = 10, CG relative
-    residual 0.1 and the relative-change stop, then Round with the eta sweep, on the GPU), by
-    random choice, or by largest predictive entropy.  Reports the evaluation accuracy after
-    every round and FIRAL's GPU seconds per round."""
-    import numpy as np
-    import torch
-    from sklearn.linear_model import LogisticRegression
-
-    from paper_2409_07392_amd import RelaxContext, default_beta0, round_eta_sweep
-    from synthdata import labeled_mixture
-    c, d, n_pool, n_eval, rounds, b = 50, 50, 5000, 20000, 6, 50
-    rng = np.random.default_rng(8000)
-    X, y = labeled_mixture(rng, n_pool + n_eval, d, c, 0.5)
-    Xp, yp, Xe, ye = X[:n_pool], y[:n_pool], X[n_pool:], y[n_pool:]
-    init = np.array([rng.choice(np.flatnonzero(yp == k)) for k in range(c)])
-    dev = torch.device("cuda:0")
-    lam, s, eta0 = 1e-3, 10, 8.0 * (d * c) ** 0.5
-
-    def fit(idx):
-        return LogisticRegression(C=1.0, max_iter=2000).fit(Xp[idx], yp[idx])
-
-    def firal_pick(clf, labeled, unl, t_round):
-        P_u = clf.predict_proba(Xp[unl])
-        P_l = clf.predict_proba(Xp[labeled])
-        Xf = torch.as_tensor(np.concatenate([Xp[unl], Xp[labeled]]), dtype=torch.float32,
-                             device=dev).contiguous()
-        Hf = torch.as_tensor(np.concatenate([P_u, P_l]), dtype=torch.float32,
-                             device=dev).contiguous()
-        ctx = RelaxContext(Xf, Hf, len(unl), s, "f32")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        w = torch.full((len(unl),), 1.0 / len(unl), dtype=torch.float64, device=dev)
-        beta0 = default_beta0(len(unl), 100)
-        f_prev = None
-        for it in range(1, 101):
-            info = ctx.relax_step(w, float(b), lam, beta0, 9000 + t_round, it, s, 0.1, 1000, True)
-            f = info["f_hat"]
-            if f_prev is not None and abs(f - f_prev) <= 1e-4 * abs(f_prev):
-                break
-            f_prev = f
-        torch.cuda.synchronize()
-        t_relax = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        sw = round_eta_sweep(ctx, (b * w).contiguous(), lam,
-                             [eta0 / 8, eta0 / 2, eta0, 2 * eta0, 8 * eta0], b, fp32=True)
-        t_round = time.perf_counter() - t0
-        ctx.close()
-        return unl[np.asarray(sw["selected"])], t_relax, t_round, it, sw["best"]
-
-    curves, firal_times = {}, []
-    for method in ("firal", "random", "entropy"):
-        log(f"active learning: {method}")
-        mrng = np.random.default_rng(8100)
-        labeled = init.copy()
-        acc = []
-        for t in range(rounds + 1):
-            clf = fit(labeled)
-            acc.append(float(clf.score(Xe, ye)))
-            if t == rounds:
-                break
-            unl = np.setdiff1d(np.arange(n_pool), labeled)
-            if method == "random":
-                pick = mrng.choice(unl, b, replace=False)
-            elif method == "entropy":
-                P = clf.predict_proba(Xp[unl])
-                ent = -(P * np.log(np.clip(P, 1e-30, None))).sum(axis=1)
-                pick = unl[np.argsort(-ent, kind="stable")[:b]]
-            else:
-                pick, tr, tn, its, eta = firal_pick(clf, labeled, unl, t)
-                firal_times.append({"round": t + 1, "relax_s": tr, "relax_iters": its,
-                                    "round_and_eta_sweep_s": tn, "eta": eta})
-            labeled = np.concatenate([labeled, pick])
-        curves[method] = acc
-    print(json.dumps({"workload": "synthetic active learning, ImageNet-50 shape",
-                      "data": "labeled Gaussian mixture: 50 classes, d = 50, cluster means "
-                              "N(0, 0.25 I), unit noise; pool 5000, evaluation 20,000",
-                      "classifier": "scikit-learn LogisticRegression (multinomial, C = 1)",
-                      "eval_accuracy_after_round": curves, "firal_gpu_seconds": firal_times}))
-
-
-def large_workload(args):
-    """Configurations 3 and 4: FP32 and bf16x3 legs plus the FP64 reference gradient."""
-    import numpy as np
-    import torch
-
-    from paper_2409_07392_amd import RelaxContext, default_beta0
-    from synthdata.device import make_problem_device
-    cfg = args.workload
-    log(f"drawing configuration {cfg} on the GPU")
-    p = make_problem_device(cfg, device="cuda:0")
-    flops = 4.0 * p.N * p.c * p.d * p.s
-    beta0 = default_beta0(p.n_pool, max(p.T, 1))
-    reps = 20 if cfg == 3 else 5
-    z = None
-    if cfg == 3:   # z = b * Dirichlet(1_n), drawn on the device
-        g = torch.Generator(device="cuda:0")
-        g.manual_seed(3003)
-        e = -torch.log(torch.rand(p.n_pool, generator=g, device="cuda:0", dtype=torch.float64))
-        z = p.b * e / e.sum()
-    if cfg == 4:   # relaxed weights for the Round leg
-        g = torch.Generator(device="cuda:0")
-        g.manual_seed(3004)
-        e = -torch.log(torch.rand(p.n_pool, generator=g, device="cuda:0", dtype=torch.float64))
-        z = p.b * e / e.sum()
-    eta = 8.0 * (p.d * p.c) ** 0.5
-    rounds = {}
-    if args.round_rounds > 0:
-        for fp32 in (True, False):
-            log(f"Round step, {'FP32' if fp32 else 'FP64'} decision")
-            rounds["fp32_decision" if fp32 else "fp64_decision"] = round_large(
-                p, z, eta, args.round_rounds, fp32)
-            torch.cuda.empty_cache()
-    if args.round_only:
-        print(json.dumps({"workload": f"configuration {cfg}", "round_step": rounds,
-                          "config": {"n_pool": p.n_pool, "n_lab": p.n_lab, "d": p.d, "c": p.c,
-                                     "b": p.b, "z": "b x Dirichlet(1), drawn on the GPU"}}))
-        return
-    V = None
-    legs, grads = {}, {}
-    n_cg_err = 10
-    for prec in ("f32", "bf16x3", "f64"):
-        dt = torch.float64 if prec == "f64" else torch.float32
-        ctx = RelaxContext(p.X.to(dt).contiguous(), p.H.to(dt).contiguous(), p.n_pool, p.s, prec)
-        w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda:0")
-        gt = torch.empty_like(w)
-        if prec != "f64":
-            log(f"{prec}: product timing")
-            t_call, t_kern = hvp_timing(ctx, p, reps)
-            leg = {"hvp_ms": t_call * 1e3, "hvp_tflops": flops / t_call / 1e12,
-                   "kernel_ms": t_kern * 1e3, "kernel_tflops": flops / t_kern / 1e12}
-            log(f"{prec}: timed step")
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            if cfg == 4:
-                info = ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, 0.0,
-                                      args.fixed_cg, True)
-                leg["relax_iter_ms_fixed_cg"] = (time.perf_counter() - t0) * 1e3
-                leg["cg_iters"] = list(info["cg_iters"])
-            else:
-                Vd = ctx.probes(p.probe_seed, 1, p.s)
-                f, _, info = ctx.sampled_objective(z, p.lam, Vd, tol=p.tol, max_iter=1000,
-                                                   project=True)
-                leg["objective_and_adjoint_ms"] = (time.perf_counter() - t0) * 1e3
-                leg["cg_iters"] = list(info["cg_iters"])
-                leg["f"] = f
-            legs[prec] = leg
-        log(f"{prec}: gradient at {n_cg_err} fixed CG iterations")
-        w.fill_(1.0 / p.n_pool)
-        ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, 1, p.s, 0.0, n_cg_err, True, g_out=gt)
-        grads[prec] = gt.cpu().numpy()
-        ctx.close()
-        del ctx
-        torch.cuda.empty_cache()
-    ref = np.linalg.norm(grads["f64"])
-    for prec in ("f32", "bf16x3"):
-        legs[prec]["rel_grad_err_vs_f64"] = float(np.linalg.norm(grads[prec] - grads["f64"]) / ref)
-    main = legs["f32"]
-    res = {
-        "metric": METRIC,
-        "workload": f"configuration {cfg}",
-        "config": {"n_pool": p.n_pool, "n_lab": p.n_lab, "d": p.d, "c": p.c, "s": p.s,
-                   "b": p.b, "tol": p.tol, "inputs": "drawn on the GPU (synthdata.device)"},
-        "precision_legs": legs,
-        "roofline": {"bound": "mfma", "kernel": "row-tiled product (per-chunk span)",
-                     "f32": {"achieved": main["kernel_tflops"], "peak": PEAK["f32"],
-                             "frac": main["kernel_tflops"] / PEAK["f32"]},
-                     "bf16x3": {"achieved": legs["bf16x3"]["kernel_tflops"],
-                                "peak": PEAK["bf16x3"],
-                                "frac": legs["bf16x3"]["kernel_tflops"] / PEAK["bf16x3"]},
-                     "unit": "TFLOP/s"},
-    }
-    if rounds:
-        res["round_step"] = rounds
-    print(json.dumps(res))
 
 
 def batch_workload(args):
@@ -750,6 +672,7 @@ def batch_workload(args):
     print(json.dumps(res))
 
 
+
 def calibrate_copy(mib):
     """A plain device copy of `mib` MiB (for scaling the FETCH_SIZE / WRITE_SIZE counters)."""
     import torch
@@ -762,33 +685,12 @@ def calibrate_copy(mib):
     print(json.dumps({"copy_bytes": n * 4}))
 
 
-def main():
-    args = parse()
-    if args.calibrate_copy:
-        calibrate_copy(args.calibrate_copy)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library's "
-              "Relax and Round paths are single-GPU.", file=sys.stderr)
-        sys.exit(2)
-    if args.workload == "table5":
-        table5_workload(args)
-        return
-    if args.workload == "studies":
-        studies_workload(args)
-        return
-    if args.workload == "al":
-        al_workload(args)
-        return
-    args.workload = int(args.workload)
-    if args.workload == 5:
-        batch_workload(args)
-        return
-    if args.workload != 2:
-        large_workload(args)
-        return
-    from synthdata import make_problem
+
+def workload2(args):
+    """Configuration 2: whole Relax iterations per step (FP32, then bf16x3), the Round step on
+    the Relax leg's weights, and the oracle's Relax iterations on the host."""
     from paper_2409_07392_amd import default_beta0
+    from synthdata import make_problem
 
     p = make_problem(2)
     if args.eta is None:
@@ -803,6 +705,11 @@ def main():
         "fp32_decision": round_leg(p, main_leg["w"], args.eta, True),
         "fp64_decision": round_leg(p, main_leg["w"], args.eta, False)}
     peak = PEAK[args.prec]
+    kname = {"f32": "k_hvp_fused (fused Lemma 1 product, FP32)",
+             "bf16x3": "k_hvp_fused_bf3 (fused Lemma 1 product, bf16x3)",
+             "f64": "k_xv (row-tiled first contraction, FP64)"}[args.prec]
+    tfile = {"f32": "k_hvp_fused_cfg2_traffic.md", "bf16x3": "k_hvp_fused_bf3_cfg2_traffic.md",
+             "f64": ""}[args.prec]
     res = {
         "metric": METRIC,
         "value": main_leg["value"],
@@ -823,20 +730,141 @@ def main():
                                "hvp_ms": v["t_hvp"] * 1e3, "hvp_tflops": v["hvp_tflops"],
                                "kernel_us": v["t_kern"] * 1e6, "kernel_tflops": v["kern_tflops"],
                                "mean_cg_iters_per_step": v["cg"],
-                               "kernel_traffic_bytes": TRAFFIC.get(k),
                                "rel_grad_err_vs_f64": errs.get(k)}
                            for k, v in legs.items()},
-        "roofline": {"bound": "mfma", "kernel": KERNEL_NAME.get(args.prec),
+        "roofline": {"bound": "mfma", "kernel": kname,
                      "achieved": main_leg["kern_tflops"], "peak": peak, "unit": "TFLOP/s",
                      "frac": main_leg["kern_tflops"] / peak,
                      "kernel_us": main_leg["t_kern"] * 1e6,
-                     "traffic": TRAFFIC.get(args.prec)},
+                     "traffic": read_traffic(tfile) if tfile else None},
     }
     if rnd is not None:
         res["round_step"] = rnd
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(p, default_beta0(p.n_pool, p.T), project)
+        res["cpu_baseline"] = cpu_baseline_relax(p, default_beta0(p.n_pool, p.T), project)
     print(json.dumps(res))
+
+
+def workload3(args):
+    """Configuration 3: the sampled objective and its adjoint gradient (extension 3) at a
+    Dirichlet z, FP32 and bf16x3, with the gradient error against the GPU FP64 mode at a fixed CG
+    count; optionally the Round step."""
+    import numpy as np
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext
+    from synthdata.device import make_problem_device
+    log("drawing configuration 3 on the GPU")
+    p = make_problem_device(3, device="cuda:0")
+    flops = 4.0 * p.N * p.c * p.d * p.s
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(3003)
+    e = -torch.log(torch.rand(p.n_pool, generator=g, device="cuda:0", dtype=torch.float64))
+    z = p.b * e / e.sum()
+    eta = 8.0 * (p.d * p.c) ** 0.5 if args.eta is None else args.eta
+    rounds = {}
+    if args.round_rounds > 0:
+        for fp32 in (True, False):
+            log(f"Round step, {'FP32' if fp32 else 'FP64'} decision")
+            rounds["fp32_decision" if fp32 else "fp64_decision"] = round_large(
+                p, z, eta, args.round_rounds, fp32)
+            torch.cuda.empty_cache()
+    if args.round_only:
+        print(json.dumps({"workload": "configuration 3", "round_step": rounds}))
+        return
+    legs, grads = {}, {}
+    n_cg = 20
+    for prec in ("f32", "bf16x3", "f64"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        ctx = RelaxContext(p.X.to(dt).contiguous(), p.H.to(dt).contiguous(), p.n_pool, p.s, prec)
+        V = ctx.probes(p.probe_seed, 1, p.s)
+        if prec != "f64":
+            log(f"{prec}: products and the objective with its adjoint")
+            leg, _ = product_leg(ctx, p, prec, 20, 2, 3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            f, _, info = ctx.sampled_objective(z, p.lam, V, tol=p.tol, max_iter=1000, project=True)
+            torch.cuda.synchronize()
+            leg["objective_and_adjoint_ms"] = (time.perf_counter() - t0) * 1e3
+            leg["cg_iters"] = list(info["cg_iters"])
+            leg["f"] = f
+            legs[prec] = leg
+        log(f"{prec}: adjoint gradient at {n_cg} fixed CG iterations")
+        _, gv, _ = ctx.sampled_objective(z, p.lam, V, tol=0.0, max_iter=n_cg, project=True)
+        grads[prec] = gv.cpu().numpy()
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    ref = np.linalg.norm(grads["f64"])
+    for prec in ("f32", "bf16x3"):
+        legs[prec]["rel_grad_err_vs_f64"] = float(np.linalg.norm(grads[prec] - grads["f64"]) / ref)
+    res = {"metric": METRIC, "workload": "configuration 3",
+           "config": {"n_pool": p.n_pool, "n_lab": p.n_lab, "d": p.d, "c": p.c, "s": p.s,
+                      "b": p.b, "tol": p.tol, "z": "b x Dirichlet(1), drawn on the GPU",
+                      "step_flop": flops},
+           "precision_legs": legs}
+    if rounds:
+        res["round_step"] = rounds
+    print(json.dumps(res))
+
+
+def al_workload(args):
+    """A synthetic active-learning loop (ImageNet-50 shape of the accuracy experiments: c = 50,
+    d = 50, pool 5000, 20,000 evaluation points, one labeled point per class to start, 6 rounds
+    of 50): each round a multinomial logistic regression (scikit-learn, host) is trained on the
+    labeled points and FIRAL selects the next 50 on the GPU: Relax (s = 10, CG relative residual
+    0.1, the relative-change stop at 1e-4, at most 100 iterations) then the Round step with the
+    eta choice over 5 values around 8 sqrt(dc), FP32 decision.  Reports the evaluation accuracy
+    after every round and the GPU seconds per round."""
+    import torch
+
+    from paper_2409_07392_amd import RelaxContext, round_eta_sweep
+    from synthdata.al import al_loop
+    c, d, n_pool, n_eval, rounds, b = 50, 50, 5000, 20000, 6, 50
+    lam, s, eta0 = 1e-3, 10, 8.0 * (d * c) ** 0.5
+    times = []
+
+    def select(X, H, n_unl, t):
+        dev = torch.device("cuda:0")
+        ctx = RelaxContext(torch.as_tensor(X, dtype=torch.float32, device=dev).contiguous(),
+                           torch.as_tensor(H, dtype=torch.float32, device=dev).contiguous(),
+                           n_unl, s, "f32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        z, info = ctx.relax(float(b), lam, 9000 + t, 100, s, 0.1, 1000, project=True,
+                            stop_rel=1e-4)
+        torch.cuda.synchronize()
+        t_relax = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sw = round_eta_sweep(ctx, z, lam, [eta0 / 8, eta0 / 2, eta0, 2 * eta0, 8 * eta0], b,
+                             fp32=True)
+        t_round = time.perf_counter() - t0
+        ctx.close()
+        times.append({"round": t + 1, "relax_s": t_relax, "relax_iters": info["iters"],
+                      "round_and_eta_choice_s": t_round, "eta": sw["best"]})
+        log(f"round {t + 1}: Relax {t_relax:.3f} s ({info['iters']} iterations), "
+            f"Round {t_round:.3f} s")
+        return sw["selected"]
+
+    res = al_loop(select, c, d, n_pool, n_eval, rounds, seed=8000)
+    print(json.dumps({"workload": "synthetic active learning, ImageNet-50 shape",
+                      "data": "labeled Gaussian mixture: 50 classes, d = 50, cluster means "
+                              "N(0, 0.25 I), unit noise; pool 5000, evaluation 20,000",
+                      "classifier": "scikit-learn LogisticRegression (multinomial, C = 1)",
+                      "eval_accuracy_after_round": res["accuracy"], "firal_gpu_seconds": times}))
+
+
+def main():
+    args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library's "
+              "Relax and Round paths are single-GPU.", file=sys.stderr)
+        sys.exit(2)
+    {"4": headline, "2": workload2, "3": workload3, "5": batch_workload,
+     "studies": studies_workload, "al": al_workload}[args.workload](args)
 
 
 if __name__ == "__main__":

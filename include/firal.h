@@ -147,6 +147,27 @@ int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double b
                      uint64_t seed, int32_t t, int32_t s, double tol, int32_t max_iter,
                      uint32_t flags, double* g_out, firal_info* info, void* stream);
 
+/* The default mirror-descent step scale for T iterations over n weights: sqrt(2 ln n / T), the
+ * textbook step of entropic mirror descent (Algorithm 2 leaves the schedule beta_t open; the
+ * step of iteration t is this scale divided by max_i |g_i|).  0 for n < 1. */
+double firal_default_beta0(int64_t n, int32_t T);
+
+/* The fast Relax solve (Algorithm 2): up to T iterations of firal_relax_step from the uniform
+ * weights w_i = 1/n_pool, then z = b w.  beta0 < 0 selects firal_default_beta0(n_pool, T).
+ * stop_rel > 0 adds the termination of the experiments section: after iteration t >= 2 the loop
+ * ends when |f_t - f_{t-1}| <= stop_rel |f_{t-1}|, f_t the objective estimate f_hat of iteration
+ * t (its weights are kept); stop_rel = 0 runs all T iterations.
+ * z: device FP64 [n_pool], written (it holds w while the iterations run).  f_hist (host double
+ * [T]), cg_hist (host int32 [2T]: both solves of each iteration) and iters (host, the number of
+ * iterations run) may be NULL.  info gets the last iteration's fields, with converged = 1 only if
+ * every solve of every iteration converged.  Synchronous.  Returns WARN_NOT_CONVERGED if some
+ * solve did not converge; on ENOTSPD or EBREAKDOWN the loop stops at that iteration, whose
+ * weights are left unchanged, and z = b w of the iterations before it. */
+int firal_relax_solve(firal_ctx ctx, double b, double lambda, double beta0, uint64_t seed,
+                      int32_t T, int32_t s, double tol, int32_t max_iter, uint32_t flags,
+                      double stop_rel, double* z, double* f_hist, int32_t* cg_hist,
+                      int32_t* iters, firal_info* info, void* stream);
+
 /* Sampled objective and its gradient (the objective of eq. 4-5 with the trace replaced by
  * the Hutchinson estimate of eq. 11 for a fixed probe block V):
  *   f_V(z) = (1/s) sum_j v_j^T Sigma_z^-1 H_p v_j,   Sigma_z = H_o + H_z + lambda I (eq. 7),
@@ -161,16 +182,24 @@ int firal_sampled_objective(firal_ctx ctx, const double* z, double lambda, const
                             int32_t s, double tol, int32_t max_iter, uint32_t flags, double* f,
                             double* g, firal_info* info, void* stream);
 
-/* Measurement of the main Hessian-product kernel (the fused product kernel; for the general
- * path, the span of its per-chunk contraction and Gamma kernels before the final reduction of
- * the split sums) and of the Round step's scoring kernel: between firal_profile_begin and
- * firal_profile_end the library attaches a HIP event pair to every launch of that kernel
- * (hipExtLaunchKernel, so the pair spans the kernel's own execution; for the general path,
- * events recorded on the call's stream before and after the span).  firal_profile_end
- * synchronises the device and returns the summed kernel time in milliseconds (host double)
- * and the number of launches (host int64); either pointer may be NULL.  Recording adds no
- * synchronisation to the timed calls. */
-int firal_profile_begin(firal_ctx ctx);
+/* Kernels that firal_profile_begin can time (the kernels of the product of Lemma 1 and of the
+ * Round step's per-point objective):
+ *   FIRAL_PROF_PRODUCT      the product's main kernel: the fused single-pass kernel where it
+ *                           applies, else the row-tiled path's first contraction X V with the
+ *                           row step of Lemma 1 (one launch per row chunk);
+ *   FIRAL_PROF_PRODUCT_T    the row-tiled path's second contraction X^T G' (one launch per chunk);
+ *   FIRAL_PROF_ROUND_SCORE  the Round step's scoring kernel (one launch per row chunk and round). */
+#define FIRAL_PROF_PRODUCT 0
+#define FIRAL_PROF_PRODUCT_T 1
+#define FIRAL_PROF_ROUND_SCORE 2
+
+/* Measurement: between firal_profile_begin and firal_profile_end the library attaches a HIP
+ * event pair to every launch of the chosen kernel (hipExtLaunchKernel, so each pair spans the
+ * kernel's own execution, as a profiler's kernel trace does).  firal_profile_end synchronises
+ * the device and returns the summed kernel time in milliseconds (host double) and the number of
+ * launches (host int64); either pointer may be NULL.  Recording adds no synchronisation to the
+ * timed calls.  Errors: EINVAL (null context, unknown kernel, end without begin). */
+int firal_profile_begin(firal_ctx ctx, int32_t kernel);
 int firal_profile_end(firal_ctx ctx, double* total_ms, int64_t* launches);
 
 /* Kernel-variant tuner (the tile plan of extension (2); usable on any context).  Times on this
@@ -272,6 +301,17 @@ int firal_round_result(firal_round round, int64_t* selected, double* nu, double*
 int firal_round_criterion(firal_round round, double* out, void* stream);
 /* Release the state (NULL is a no-op). */
 int firal_round_destroy(firal_round round);
+
+/* The eta choice of the experiments section: run all b rounds of the Round step for each of the
+ * n_eta learning rates etas[] (host array) on ctx's rows with the relaxed weights z (device FP64
+ * [n_pool]), lambda and flags as in firal_round_create, and keep the run whose (H)_k maximise
+ * min_k lambda_min((H)_k) (firal_round_criterion; the first such eta on ties).  selected (host
+ * int64 [b]) gets that run's selections in round order, criteria (host double [n_eta], may be
+ * NULL) each run's criterion, best (host, may be NULL) the index of the kept eta.  Synchronous.
+ * Errors: EINVAL (null argument, n_eta < 1, b outside [1, n_pool]), and those of the Round calls. */
+int firal_round_eta_sweep(firal_ctx ctx, const double* z, double lambda, const double* etas,
+                          int32_t n_eta, int32_t b, uint32_t flags, int64_t* selected,
+                          double* criteria, int32_t* best, void* stream);
 
 /* Static description of a return code. */
 const char* firal_strerror(int code);

@@ -7,8 +7,6 @@ constructing a context without the built library or without a GPU raises.
 """
 from __future__ import annotations
 
-import math
-
 import torch
 
 from . import _lib
@@ -22,8 +20,9 @@ _DTYPE = {F64: torch.float64, F32: torch.float32, BF16X3: torch.float32}
 
 
 def default_beta0(n: int, T: int) -> float:
-    """sqrt(2 ln n / T), the standard entropic mirror-descent step for T iterations."""
-    return math.sqrt(2.0 * math.log(n) / max(T, 1))
+    """The library's default mirror-descent step scale for T iterations over n weights
+    (firal_default_beta0)."""
+    return float(load().firal_default_beta0(int(n), int(T)))
 
 
 def _stream() -> int:
@@ -147,14 +146,32 @@ class RelaxContext:
         d["rc"] = rc
         return d
 
-    def relax(self, b, lam, beta0, seed, T, s=None, tol=1e-6, max_iter=1000, project=False,
-              w0=None):
-        """T iterations from w = 1/n; returns (z = b w, list of per-iteration info)."""
-        w = (torch.full((self.n_pool,), 1.0 / self.n_pool, dtype=torch.float64,
-                        device=self.X.device) if w0 is None else w0.clone())
-        hist = [self.relax_step(w, b, lam, beta0, seed, t, s, tol, max_iter, project)
-                for t in range(1, T + 1)]
-        return b * w, hist
+    def relax(self, b, lam, seed, T, s=None, tol=1e-6, max_iter=1000, project=False,
+              beta0=None, stop_rel=0.0):
+        """The Relax solve (firal_relax_solve): up to T iterations from the uniform weights, with
+        the relative-change stop when stop_rel > 0.  beta0=None takes the library's default.
+        Returns (z = b w as a CUDA float64 tensor, dict with f_hat and cg_iters per iteration,
+        iters, rc and the last iteration's info)."""
+        import numpy as np
+        s = self.s_max if s is None else int(s)
+        z = torch.empty(self.n_pool, dtype=torch.float64, device=self.X.device)
+        f_hist = np.zeros(int(T), dtype=np.float64)
+        cg_hist = np.zeros(2 * int(T), dtype=np.int32)
+        iters = _lib.ctypes.c_int32()
+        info = Info()
+        rc = self.lib.firal_relax_solve(
+            self._ctx, float(b), float(lam), -1.0 if beta0 is None else float(beta0),
+            int(seed) & (2**64 - 1), int(T), s, float(tol), int(max_iter),
+            PCG_PROJECT if project else 0, float(stop_rel), _ptr(z),
+            f_hist.ctypes.data_as(_lib.ctypes.c_void_p),
+            cg_hist.ctypes.data_as(_lib.ctypes.c_void_p), _lib.ctypes.byref(iters),
+            _lib.ctypes.byref(info), _stream())
+        check(rc)
+        n = iters.value
+        out = info.as_dict()
+        out.update(rc=rc, iters=n, f_hat_hist=f_hist[:n].tolist(),
+                   cg_hist=[(int(cg_hist[2 * i]), int(cg_hist[2 * i + 1])) for i in range(n)])
+        return z, out
 
     def sampled_objective(self, z, lam, V, tol=1e-10, max_iter=1000, project=True, grad=True):
         """f_V(z) = (1/s) sum_j v_j^T Sigma_z^-1 H_p v_j and, if grad, df_V/dz (FP64 CUDA)."""
@@ -184,9 +201,14 @@ class RelaxContext:
         check(self.lib.firal_autotune(self._ctx, s, _lib.ctypes.byref(ch), _stream()))
         return ch.value
 
-    def profile_begin(self):
-        """Start timing every launch of the main product kernel with events on its stream."""
-        check(self.lib.firal_profile_begin(self._ctx))
+    def profile_begin(self, kernel: str = "product"):
+        """Start timing every launch of one kernel with event pairs attached to its launches:
+        'product' (the product's main kernel: the fused kernel, or the row-tiled first
+        contraction X V with the row step), 'product_t' (the row-tiled X^T G' contraction) or
+        'round_score' (the Round step's scoring kernel)."""
+        k = {"product": _lib.PROF_PRODUCT, "product_t": _lib.PROF_PRODUCT_T,
+             "round_score": _lib.PROF_ROUND_SCORE}[kernel]
+        check(self.lib.firal_profile_begin(self._ctx, k))
 
     def profile_end(self):
         """Stop timing; returns (total kernel milliseconds, number of launches)."""
@@ -334,16 +356,24 @@ class RoundSolver:
 
 def round_eta_sweep(ctx: RelaxContext, z: torch.Tensor, lam: float, etas, b: int,
                     fp32: bool = False) -> dict:
-    """The eta choice of the experiments section: run the Round step for every eta and keep
-    the one whose selection maximises min_k lambda_min((H)_k)."""
-    crit, sels = [], []
-    for eta in etas:
-        rs = RoundSolver(ctx, z, lam, eta, b, fp32=fp32)
-        sels.append(rs.run())
-        crit.append(rs.criterion())
-        rs.close()
-    best = max(range(len(crit)), key=lambda i: (crit[i], -i))
-    return dict(etas=list(etas), criterion=crit, best=etas[best], selected=sels[best])
+    """The eta choice of the experiments section (firal_round_eta_sweep): the Round step for
+    every eta, keeping the selection that maximises min_k lambda_min((H)_k)."""
+    import numpy as np
+    lib = load()
+    etas = [float(e) for e in etas]
+    z = RelaxContext._f64(z, ctx.n_pool)
+    e_arr = np.asarray(etas, dtype=np.float64)
+    sel = np.zeros(int(b), dtype=np.int64)
+    crit = np.zeros(len(etas), dtype=np.float64)
+    best = _lib.ctypes.c_int32()
+    check(lib.firal_round_eta_sweep(ctx._ctx, _ptr(z), float(lam),
+                                    e_arr.ctypes.data_as(_lib.ctypes.c_void_p), len(etas),
+                                    int(b), ROUND_FP32 if fp32 else 0,
+                                    sel.ctypes.data_as(_lib.ctypes.c_void_p),
+                                    crit.ctypes.data_as(_lib.ctypes.c_void_p),
+                                    _lib.ctypes.byref(best), _stream()))
+    return dict(etas=etas, criterion=crit.tolist(), best=etas[best.value],
+                best_index=best.value, selected=sel)
 
 
 class RelaxObjective(torch.autograd.Function):

@@ -14,6 +14,7 @@ WARN_NOT_CONVERGED = 1
 EINVAL, EHIP, ENOMEM, ENOTSUP, EBREAKDOWN, ENOTSPD = -1, -2, -3, -4, -5, -6
 PCG_PROJECT = 1
 ROUND_FP32 = 1
+PROF_PRODUCT, PROF_PRODUCT_T, PROF_ROUND_SCORE = 0, 1, 2
 
 # every symbol include/firal.h declares
 EXPORTS = ("firal_create", "firal_destroy", "firal_hvp", "firal_build_precond",
@@ -22,7 +23,8 @@ EXPORTS = ("firal_create", "firal_destroy", "firal_hvp", "firal_build_precond",
            "firal_autotune", "firal_batch_create", "firal_batch_run", "firal_batch_info",
            "firal_batch_next_t", "firal_batch_destroy", "firal_round_create", "firal_round_step",
            "firal_round_scores", "firal_round_result", "firal_round_criterion",
-           "firal_round_destroy", "firal_strerror", "firal_last_error")
+           "firal_round_destroy", "firal_round_eta_sweep", "firal_default_beta0",
+           "firal_relax_solve", "firal_strerror", "firal_last_error")
 
 
 class Info(ctypes.Structure):
@@ -77,6 +79,8 @@ def load() -> ctypes.CDLL:
         "firal_grad_z": [vp, vp, vp, i32, vp, vp],
         "firal_probes": [vp, u64, i32, i32, vp, vp],
         "firal_relax_step": [vp, vp, dbl, dbl, dbl, u64, i32, i32, dbl, i32, u32, vp, pinfo, vp],
+        "firal_relax_solve": [vp, dbl, dbl, dbl, u64, i32, i32, dbl, i32, u32, dbl, vp, vp, vp,
+                              ctypes.POINTER(i32), pinfo, vp],
         "firal_sampled_objective": [vp, vp, dbl, vp, i32, dbl, i32, u32, ctypes.POINTER(dbl), vp,
                                     pinfo, vp],
         "firal_autotune": [vp, i32, ctypes.POINTER(i32), vp],
@@ -91,7 +95,8 @@ def load() -> ctypes.CDLL:
         "firal_round_result": [vp, vp, vp, vp, ctypes.POINTER(i32), vp],
         "firal_round_criterion": [vp, ctypes.POINTER(dbl), vp],
         "firal_round_destroy": [vp],
-        "firal_profile_begin": [vp],
+        "firal_round_eta_sweep": [vp, vp, dbl, vp, i32, i32, u32, vp, vp, ctypes.POINTER(i32), vp],
+        "firal_profile_begin": [vp, i32],
         "firal_profile_end": [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         "firal_strerror": [ctypes.c_int],
         "firal_last_error": [],
@@ -100,6 +105,8 @@ def load() -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.firal_default_beta0.argtypes = [i64, i32]
+    lib.firal_default_beta0.restype = dbl
     lib.firal_strerror.restype = ctypes.c_char_p
     lib.firal_last_error.restype = ctypes.c_char_p
     _lib = lib

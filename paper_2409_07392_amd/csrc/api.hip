@@ -2,6 +2,7 @@
 // the synchronous calls that report device-side status through firal_info.
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -50,26 +51,15 @@ static void drop_events(Ctx* x) {
   x->prof_events = nullptr;
 }
 
-int prof_pair(Ctx* x, hipEvent_t* e0, hipEvent_t* e1) {
+int prof_pair(Ctx* x, int kernel, hipEvent_t* e0, hipEvent_t* e1) {
   *e0 = *e1 = nullptr;
-  if (!x->profiling) return FIRAL_OK;
+  if (!x->profiling || kernel != x->prof_kernel) return FIRAL_OK;
   EventPairs* ev = (EventPairs*)x->prof_events;
   ev->push_back({nullptr, nullptr});
   FIRAL_HIP(hipEventCreate(&ev->back().first));
   FIRAL_HIP(hipEventCreate(&ev->back().second));
   *e0 = ev->back().first;
   *e1 = ev->back().second;
-  return FIRAL_OK;
-}
-
-int prof_mark(Ctx* x, hipStream_t st, bool start) {
-  if (!x->profiling) return FIRAL_OK;
-  EventPairs* ev = (EventPairs*)x->prof_events;
-  hipEvent_t e;
-  FIRAL_HIP(hipEventCreate(&e));
-  FIRAL_HIP(hipEventRecord(e, st));
-  if (start) ev->push_back({e, nullptr});
-  else ev->back().second = e;
   return FIRAL_OK;
 }
 
@@ -131,11 +121,14 @@ const char* firal_strerror(int code) {
 
 const char* firal_last_error(void) { return g_last_error; }
 
-int firal_profile_begin(firal_ctx ctx) {
+int firal_profile_begin(firal_ctx ctx, int32_t kernel) {
   FIRAL_REQ(ctx != nullptr, "null context");
+  FIRAL_REQ(kernel >= FIRAL_PROF_PRODUCT && kernel <= FIRAL_PROF_ROUND_SCORE,
+            "unknown kernel %d", kernel);
   Ctx* x = C(ctx);
   drop_events(x);
   x->prof_events = new EventPairs();
+  x->prof_kernel = kernel;
   x->profiling = 1;
   return FIRAL_OK;
 }
@@ -454,22 +447,9 @@ int firal_sampled_objective(firal_ctx ctx, const double* z, double lambda, const
   return h.converged ? FIRAL_OK : FIRAL_WARN_NOT_CONVERGED;
 }
 
-int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double beta0,
-                     uint64_t seed, int32_t t, int32_t s, double tol, int32_t max_iter,
-                     uint32_t flags, double* g_out, firal_info* info, void* stream) {
-  FIRAL_CHECK(check_common(ctx, s));
-  Ctx* x = C(ctx);
-  FIRAL_REQ(w != nullptr, "null w");
-  FIRAL_REQ(b > 0.0, "b must be > 0");
-  FIRAL_REQ(lambda >= 0.0, "lambda < 0");
-  FIRAL_REQ(beta0 >= 0.0, "beta0 < 0");
-  FIRAL_REQ(t >= 1, "t = %d < 1", t);
-  FIRAL_REQ(tol >= 0.0, "tol < 0");
-  FIRAL_REQ(max_iter >= 0, "max_iter < 0");
-  FIRAL_REQ((flags & ~FIRAL_PCG_PROJECT) == 0, "unknown flags 0x%x", flags);
-  hipStream_t st = (hipStream_t)stream;
-  FIRAL_CHECK(relax_step_launch(x, w, b, lambda, beta0, seed, t, s, tol, max_iter, flags, g_out, st));
-  FIRAL_CHECK(finish_sync(x, st));
+// The status of the Relax iteration that finish_sync has just read back, as firal_info and a
+// return code (ENOTSPD, EBREAKDOWN, WARN_NOT_CONVERGED or OK).
+static int step_result(Ctx* x, firal_info* info) {
   const Status& h = *x->status_host;
   const int bad = h.bad_block == INT_MAX ? -1 : h.bad_block;
   if (info) {
@@ -491,6 +471,89 @@ int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double b
     return FIRAL_EBREAKDOWN;
   }
   return h.converged ? FIRAL_OK : FIRAL_WARN_NOT_CONVERGED;
+}
+
+static int check_step_args(firal_ctx ctx, double b, double lambda, int32_t s, double tol,
+                           int32_t max_iter, uint32_t flags) {
+  FIRAL_CHECK(check_common(ctx, s));
+  FIRAL_REQ(b > 0.0, "b must be > 0");
+  FIRAL_REQ(lambda >= 0.0, "lambda < 0");
+  FIRAL_REQ(tol >= 0.0, "tol < 0");
+  FIRAL_REQ(max_iter >= 0, "max_iter < 0");
+  FIRAL_REQ((flags & ~FIRAL_PCG_PROJECT) == 0, "unknown flags 0x%x", flags);
+  return FIRAL_OK;
+}
+
+double firal_default_beta0(int64_t n, int32_t T) {
+  if (n < 1) return 0.0;
+  return std::sqrt(2.0 * std::log((double)n) / (double)std::max<int32_t>(T, 1));
+}
+
+int firal_relax_step(firal_ctx ctx, double* w, double b, double lambda, double beta0,
+                     uint64_t seed, int32_t t, int32_t s, double tol, int32_t max_iter,
+                     uint32_t flags, double* g_out, firal_info* info, void* stream) {
+  FIRAL_CHECK(check_step_args(ctx, b, lambda, s, tol, max_iter, flags));
+  Ctx* x = C(ctx);
+  FIRAL_REQ(w != nullptr, "null w");
+  FIRAL_REQ(beta0 >= 0.0, "beta0 < 0");
+  FIRAL_REQ(t >= 1, "t = %d < 1", t);
+  hipStream_t st = (hipStream_t)stream;
+  FIRAL_CHECK(relax_step_launch(x, w, b, lambda, beta0, seed, t, s, tol, max_iter, flags, g_out, st));
+  FIRAL_CHECK(finish_sync(x, st));
+  return step_result(x, info);
+}
+
+int firal_relax_solve(firal_ctx ctx, double b, double lambda, double beta0, uint64_t seed,
+                      int32_t T, int32_t s, double tol, int32_t max_iter, uint32_t flags,
+                      double stop_rel, double* z, double* f_hist, int32_t* cg_hist,
+                      int32_t* iters, firal_info* info, void* stream) {
+  FIRAL_CHECK(check_step_args(ctx, b, lambda, s, tol, max_iter, flags));
+  Ctx* x = C(ctx);
+  FIRAL_REQ(z != nullptr, "null z");
+  FIRAL_REQ(T >= 1, "T = %d < 1", T);
+  FIRAL_REQ(stop_rel >= 0.0, "stop_rel < 0");
+  FIRAL_REQ(!(beta0 != beta0), "beta0 is NaN");
+  if (beta0 < 0.0) beta0 = firal_default_beta0(x->n_pool, T);
+  if (iters) *iters = 0;
+  hipStream_t st = (hipStream_t)stream;
+  // z holds the simplex weights w while the iterations run (w^0 = 1/n), then b w
+  FIRAL_CHECK(fill_scale_launch(z, x->n_pool, 1.0 / (double)x->n_pool, false, st));
+  int rc_all = FIRAL_OK;
+  double f_prev = 0.0;
+  firal_info last;
+  std::memset(&last, 0, sizeof(last));
+  int conv_all = 1;
+  for (int32_t t = 1; t <= T; ++t) {
+    FIRAL_CHECK(relax_step_launch(x, z, b, lambda, beta0, seed, t, s, tol, max_iter, flags,
+                                  nullptr, st));
+    FIRAL_CHECK(finish_sync(x, st));
+    const int rc = step_result(x, &last);
+    if (rc < 0) {   // the failed iteration left w unchanged
+      if (info) *info = last;
+      FIRAL_CHECK(fill_scale_launch(z, x->n_pool, b, true, st));
+      FIRAL_HIP(hipStreamSynchronize(st));
+      return rc;
+    }
+    if (rc == FIRAL_WARN_NOT_CONVERGED) rc_all = rc;
+    conv_all &= last.converged;
+    if (f_hist) f_hist[t - 1] = last.f_hat;
+    if (cg_hist) {
+      cg_hist[2 * (t - 1)] = last.cg_iters[0];
+      cg_hist[2 * (t - 1) + 1] = last.cg_iters[1];
+    }
+    if (iters) *iters = t;
+    const bool stop = stop_rel > 0.0 && t >= 2 &&
+                      std::fabs(last.f_hat - f_prev) <= stop_rel * std::fabs(f_prev);
+    f_prev = last.f_hat;
+    if (stop) break;
+  }
+  FIRAL_CHECK(fill_scale_launch(z, x->n_pool, b, true, st));
+  FIRAL_HIP(hipStreamSynchronize(st));
+  if (info) {
+    *info = last;
+    info->converged = conv_all;
+  }
+  return rc_all;
 }
 
 }  // extern "C"

@@ -132,16 +132,17 @@ struct Ctx {
                         //   (tag << 2) | (relres < bf3_switch) << 1 | column stopped
   uint32_t* chk_word_dev;  // its device address
 
-  // firal_profile_begin/end: event pairs around each main product kernel
+  // firal_profile_begin/end: event pairs around each launch of one kernel (prof_kernel, a
+  // FIRAL_PROF_* value)
   int profiling;
+  int prof_kernel;
   void* prof_events;    // std::vector<std::pair<hipEvent_t, hipEvent_t>>*
 };
 
-// record an event on `st` when profiling (start: true before the kernel, false after)
-int prof_mark(Ctx* x, hipStream_t st, bool start);
-// when profiling, a new event pair for one launch through hipExtLaunchKernel, which records
-// the kernel's own start and end in it (null events otherwise: a plain launch)
-int prof_pair(Ctx* x, hipEvent_t* e0, hipEvent_t* e1);
+// when profiling `kernel` (a FIRAL_PROF_* value), a new event pair for one launch through
+// hipExtLaunchKernel, which records the kernel's own start and end in it (null events
+// otherwise: a plain launch)
+int prof_pair(Ctx* x, int kernel, hipEvent_t* e0, hipEvent_t* e1);
 
 inline Ctx* C(firal_ctx p) { return reinterpret_cast<Ctx*>(p); }
 
@@ -337,6 +338,8 @@ int probes_launch(Ctx* x, uint64_t seed, int t, int s, void* V, hipStream_t st,
 int relax_step_launch(Ctx* x, double* w, double b, double lambda, double beta0, uint64_t seed,
                       int t, int s, double tol, int max_iter, uint32_t flags, double* g_out,
                       hipStream_t st);
+// w = v everywhere (scale false) or w *= v (scale true), n FP64 entries
+int fill_scale_launch(double* w, int64_t n, double v, bool scale, hipStream_t st);
 int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, Skip skip,
                   hipStream_t st);
 

@@ -854,7 +854,7 @@ int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_
   const int nwg = (int)(((int64_t)p.n_splits * p.n_ctiles + 7) / 8 * 8);
   float* part = (float*)x->fused_part;
   hipEvent_t e0, e1;   // the kernel's own execution when profiling
-  FIRAL_CHECK(prof_pair(x, &e0, &e1));
+  FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT, &e0, &e1));
   hipExtLaunchKernelGGL(k, dim3(nwg), dim3(kThreads), (uint32_t)p.lds_bytes, st, e0, e1, 0u,
                         (const float*)x->X, (const float*)x->H, omega, n_rows, x->d, x->c, SC, B,
                         p.probes_per_tile, s, p.n_ctiles, p.rows_per_split, p.n_splits, p.XS, p.XT,

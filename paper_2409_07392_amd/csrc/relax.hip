@@ -167,6 +167,20 @@ __global__ void k_step_reset(Status* st, double* keep) {
 
 __global__ void k_advance(int32_t* t) { *t += 1; }
 
+// w_i = v (the first iterate 1/n of Algorithm 2) or w_i *= v (z = b w after the last one)
+__global__ __launch_bounds__(256) void k_fill_scale(double* __restrict__ w, int64_t n, double v,
+                                                    int scale) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = scale ? w[i] * v : v;
+}
+
+int fill_scale_launch(double* w, int64_t n, double v, bool scale, hipStream_t st) {
+  if (n <= 0) return FIRAL_OK;
+  k_fill_scale<<<(unsigned)cdiv(n, 256), 256, 0, st>>>(w, n, v, scale ? 1 : 0);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
 __global__ void k_relres_merge(Status* st, double* keep) {
   // keeps the max recurrence residual over both solves
   *keep = fmax(*keep, st->relres_max);

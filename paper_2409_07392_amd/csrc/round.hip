@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstring>
 #include <utility>
 #include <vector>
 
@@ -1014,7 +1015,7 @@ static int round_operand(Round* r, const double* nu_p, hipStream_t st) {
 // partials of the argmax
 template <typename T, typename CT>
 static int round_score_t(Round* r, const CT* W, double* r_out, hipStream_t st) {
-  const Ctx* x = r->x;
+  Ctx* x = r->x;
   const T* X = (const T*)x->X;
   const T* H = (const T*)x->H;
   CT* Tb = (CT*)r->Tb;
@@ -1022,7 +1023,7 @@ static int round_score_t(Round* r, const CT* W, double* r_out, hipStream_t st) {
     const int64_t R = std::min<int64_t>(r->R, r->n_pool - r0);
     const int64_t nwg = cdiv(R, kScoreTM) * r->c;
     hipEvent_t e0, e1;   // the kernel's own execution when profiling
-    FIRAL_CHECK(prof_pair(r->x, &e0, &e1));
+    FIRAL_CHECK(prof_pair(r->x, FIRAL_PROF_ROUND_SCORE, &e0, &e1));
     // all c operands (d x 2 ldo each) within 2 MiB: walk the classes of a row tile together
     const int rows_major = (int64_t)r->c * r->d * 2 * r->ldo * sizeof(CT) <= ((int64_t)2 << 20);
     hipExtLaunchKernelGGL(k_round_score<T, CT>, dim3((unsigned)nwg), dim3(256), 0u, st, e0, e1,
@@ -1281,5 +1282,39 @@ extern "C" int firal_round_destroy(firal_round round) {
   Round* r = reinterpret_cast<Round*>(round);
   (void)hipSetDevice(r->x->device);
   free_round(r);
+  return FIRAL_OK;
+}
+
+// The eta choice of the experiments section: the Round step for each eta of the list, keeping
+// the selection whose (H)_k maximise min_k lambda_min((H)_k) (the first such eta on ties).
+extern "C" int firal_round_eta_sweep(firal_ctx ctx, const double* z, double lambda,
+                                     const double* etas, int32_t n_eta, int32_t b, uint32_t flags,
+                                     int64_t* selected, double* criteria, int32_t* best,
+                                     void* stream) {
+  RREQ(ctx != nullptr && z != nullptr && etas != nullptr && selected != nullptr,
+       "firal_round_eta_sweep: null argument");
+  RREQ(n_eta >= 1, "firal_round_eta_sweep: n_eta = %d < 1", n_eta);
+  RREQ(b >= 1, "firal_round_eta_sweep: b = %d < 1", b);
+  std::vector<int64_t> sel((size_t)b);
+  double best_crit = -INFINITY;
+  int best_i = -1;
+  for (int i = 0; i < n_eta; ++i) {
+    firal_round r = nullptr;
+    FIRAL_CHECK(firal_round_create(&r, ctx, z, lambda, etas[i], b, flags, stream));
+    int rc = firal_round_step(r, b, stream);
+    int32_t t = 0;
+    if (rc >= 0) rc = firal_round_result(r, sel.data(), nullptr, nullptr, &t, stream);
+    double crit = 0.0;
+    if (rc >= 0) rc = firal_round_criterion(r, &crit, stream);
+    (void)firal_round_destroy(r);
+    if (rc < 0) return rc;
+    if (criteria) criteria[i] = crit;
+    if (best_i < 0 || crit > best_crit) {
+      best_crit = crit;
+      best_i = i;
+      std::memcpy(selected, sel.data(), sizeof(int64_t) * (size_t)b);
+    }
+  }
+  if (best) *best = best_i;
   return FIRAL_OK;
 }

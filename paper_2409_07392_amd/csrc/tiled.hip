@@ -18,6 +18,8 @@
 // All sums are in a fixed order (no float atomics): results are reproducible run to run.
 #include <algorithm>
 
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace firal {
@@ -683,25 +685,31 @@ XRows<T> chunk_rows_of(const Ctx* x, int64_t r0) {
 
 // G = Gamma-step(omega, X_chunk B) for the chunk's R rows: the whole-probe epilogue when tiles
 // hold whole probes, else the raw product followed by the per-(row, probe) pass.
+// prof: attach the profiling event pair of the product's first contraction (product calls
+// only; the gradient's use of this step is not timed).
 template <typename T, bool BF3>
-int xv_gamma(const ColMap& cm, const XRows<T>& xr, int d, int64_t R, const T* B, const T* Hc,
-             const double* om, T* G, Skip skip, hipStream_t st) {
+int xv_gamma(Ctx* x, bool prof, const ColMap& cm, const XRows<T>& xr, int d, int64_t R,
+             const T* B, const T* Hc, const double* om, T* G, Skip skip, hipStream_t st) {
   typedef Shape<T> S_;
   constexpr int TM1 = 32 * S_::WM1;
   const unsigned nwg = (unsigned)(cdiv(R, TM1) * cm.ntiles);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (prof) FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT, &e0, &e1));
   if (cm.full) {
     auto k = k_xv<T, S_::WM1, S_::WN1, kGamma, BF3>;
     constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kGamma, BF3>();
     static bool attr = false;
     FIRAL_CHECK(set_lds(k, lds, attr));
-    k<<<nwg, 256, lds, st>>>(xr.x, xr.xh, xr.xl, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
+    hipExtLaunchKernelGGL(k, dim3(nwg), dim3(256), lds, st, e0, e1, 0u, xr.x, xr.xh, xr.xl, d, R,
+                          B, Hc, om, cm, G, (const T*)nullptr, (double*)nullptr, skip);
     FIRAL_LAUNCHED();
   } else {
     auto k = k_xv<T, S_::WM1, S_::WN1, kRaw, BF3>;
     constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kRaw, BF3>();
     static bool attr = false;
     FIRAL_CHECK(set_lds(k, lds, attr));
-    k<<<nwg, 256, lds, st>>>(xr.x, xr.xh, xr.xl, d, R, B, Hc, om, cm, G, nullptr, nullptr, skip);
+    hipExtLaunchKernelGGL(k, dim3(nwg), dim3(256), lds, st, e0, e1, 0u, xr.x, xr.xh, xr.xl, d, R,
+                          B, Hc, om, cm, G, (const T*)nullptr, (double*)nullptr, skip);
     FIRAL_LAUNCHED();
     const unsigned nb = (unsigned)cdiv(R * cm.s, 4);
     if (sizeof(T) == 4 && cm.c % 4 == 0 && cm.c <= 1024)
@@ -747,19 +755,20 @@ static int hvp_tiled_t(Ctx* x, const double* omega, int64_t n_rows, double shift
   static bool attr2 = false;
   FIRAL_CHECK(set_lds(k2, lds2, attr2));
 
-  FIRAL_CHECK(prof_mark(x, st, true));
   for (int64_t r0 = 0; r0 < n_rows; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, n_rows - r0);
     const XRows<T> xr = chunk_rows_of<T>(x, r0);
-    FIRAL_CHECK((xv_gamma<T, BF3>(cm, xr, d, R, B, H + r0 * c, omega ? omega + r0 : nullptr, G,
-                                  skip, st)));
+    FIRAL_CHECK((xv_gamma<T, BF3>(x, true, cm, xr, d, R, B, H + r0 * c,
+                                  omega ? omega + r0 : nullptr, G, skip, st)));
     // splits start on a multiple of 32 rows (the bf16x3 kernel reads X^T in 8-row chunks)
     const int64_t rps = cdiv(cdiv(R, S), 32) * 32;
-    k2<<<(unsigned)(tiles * S), 256, lds2, st>>>(xr.x, xr.xth, xr.xtl, xr.ldt, d, G, SC, R, rps,
-                                                nmt, nct, part, n_out, r0 > 0, skip);
+    hipEvent_t e0, e1;
+    FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT_T, &e0, &e1));
+    hipExtLaunchKernelGGL(k2, dim3((unsigned)(tiles * S)), dim3(256), lds2, st, e0, e1, 0u, xr.x,
+                          xr.xth, xr.xtl, xr.ldt, d, (const T*)G, SC, R, rps, nmt, nct, part,
+                          n_out, (int)(r0 > 0), skip);
     FIRAL_LAUNCHED();
   }
-  FIRAL_CHECK(prof_mark(x, st, false));
   return reduce_parts_launch<T>(part, n_out, n_rows > 0 ? S : 0, shift, B, out, skip, st);
 }
 
@@ -792,7 +801,7 @@ static int grad_tiled_t(Ctx* x, const T* U, const T* W, int s, double* g, hipStr
     const int64_t R = std::min<int64_t>(x->chunk_rows, x->n_pool - r0);
     const XRows<T> xr = chunk_rows_of<T>(x, r0);
     const T* Hc = (const T*)x->H + r0 * c;
-    FIRAL_CHECK((xv_gamma<T, BF3>(cm, xr, d, R, W, Hc, nullptr, G, skip_none(), st)));
+    FIRAL_CHECK((xv_gamma<T, BF3>(x, false, cm, xr, d, R, W, Hc, nullptr, G, skip_none(), st)));
     kd<<<(unsigned)(cdiv(R, TM1) * cm.ntiles), 256, lds, st>>>(
         xr.x, xr.xh, xr.xl, d, R, U, Hc, nullptr, cm, nullptr, G, x->gpart, skip_none());
     FIRAL_LAUNCHED();

@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "firal.h")
 
 def header_functions():
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(firal_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:int|double|const char\*)\s+(firal_\w+)\s*\(", txt, re.M)))
 
 
 def test_header_declares_the_binding_exports():
@@ -77,7 +77,24 @@ def test_calls_reject_null_context():
     assert lib.firal_probes(None, 1, 1, 1, 1, None) == _lib.EINVAL
     assert lib.firal_relax_step(None, 1, 1.0, 1e-3, 0.1, 1, 1, 1, 1e-6, 10, 0, None,
                                 ctypes.byref(info), None) == _lib.EINVAL
+    it = ctypes.c_int32()
+    assert lib.firal_relax_solve(None, 1.0, 1e-3, -1.0, 1, 5, 1, 1e-6, 10, 0, 0.0, 1, None,
+                                 None, ctypes.byref(it), ctypes.byref(info), None) == _lib.EINVAL
+    best = ctypes.c_int32()
+    etas = (ctypes.c_double * 2)(1.0, 2.0)
+    assert lib.firal_round_eta_sweep(None, 1, 1e-3, etas, 2, 3, 0, 1, None, ctypes.byref(best),
+                                     None) == _lib.EINVAL
     assert lib.firal_destroy(None) == _lib.OK
+
+
+def test_default_beta0_is_the_entropic_mirror_descent_step():
+    # sqrt(2 ln n / T) (host arithmetic only; no device needed)
+    import math
+    lib = _lib.load()
+    for n, T in [(2000, 50), (50000, 100), (1, 1), (1280000, 20)]:
+        assert lib.firal_default_beta0(n, T) == pytest.approx(math.sqrt(2 * math.log(n) / T),
+                                                              rel=1e-15, abs=0)
+    assert lib.firal_default_beta0(0, 5) == 0.0
 
 
 def test_create_without_device_reports_hip_error():

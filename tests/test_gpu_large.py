@@ -85,3 +85,30 @@ def test_configuration_4_rows_and_properties(cfg4, prec):
     scale = float(U.double().norm() * HB.double().norm())
     assert abs(lhs - rhs) <= BAR[prec] * scale, (lhs, rhs, scale)
     ctx.close()
+
+
+def test_configuration_4_one_percent_sample_f64_relax_step(cfg4):
+    # The GPU FP64 mode is the reference of the bench's FP32 and bf16x3 gradient errors at full
+    # size; here it is held to the oracle at the FP64 bar on a 1% row sample of the same
+    # workload (the first 12,800 pool rows and the first 20 labeled rows, b scaled to 10), one
+    # whole Relax iteration at 2 fixed CG iterations per solve.
+    from paper_2409_07392_amd import default_beta0
+    p = cfg4
+    npl, nlb = 12800, 20
+    Xs = torch.cat([p.X[:npl], p.X[p.n_pool:p.n_pool + nlb]]).double().contiguous()
+    Hs = torch.cat([p.H[:npl], p.H[p.n_pool:p.n_pool + nlb]]).double().contiguous()
+    ctx = RelaxContext(Xs, Hs, npl, p.s, "f64")
+    b, beta0 = 10.0, default_beta0(npl, p.T)
+    w = torch.full((npl,), 1.0 / npl, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(w)
+    info = ctx.relax_step(w, b, p.lam, beta0, p.probe_seed, 1, p.s, 0.0, 2, True, g_out=g)
+    assert info["cg_iters"] == (2, 2)
+    X, H = Xs.cpu().numpy(), Hs.cpu().numpy()
+    wr, ir = orc.relax_iteration(X, H, npl, np.full(npl, 1.0 / npl), b, p.lam, beta0,
+                                 p.probe_seed, 1, p.s, 0.0, 2, project=True)
+    eg = relerr(g.cpu().numpy(), ir["g"])
+    ew = relerr(w.cpu().numpy(), wr)
+    ef = abs(info["f_hat"] - ir["f_hat"]) / abs(ir["f_hat"])
+    print(f"configuration 4, 1% sample, FP64: gradient {eg:.2e}, weights {ew:.2e}, f {ef:.2e}")
+    assert eg <= 1e-10 and ew <= 1e-10 and ef <= 1e-10, (eg, ew, ef)
+    ctx.close()

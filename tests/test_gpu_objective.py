@@ -1,9 +1,9 @@
 """The sampled objective f_V(z) and its adjoint gradient (firal_sampled_objective,
 RelaxObjective) against the FP64 oracle, finite differences and gradcheck.
 
-Tolerances: FP64 results at PCG tol 1e-13 are compared at 1e-9 normwise (the two
-solves meet 1e-13 on the recurrence residual; kappa of the projected operator is
-O(10-100)); FP32 against FP64 at the same fixed CG count at 1e-5.
+Tolerances: FP64 results at PCG tol 1e-13 are compared at the FP64 bar 1e-10 normwise
+(the two solves meet 1e-13 on the recurrence residual; kappa of the projected operator is
+O(10-100)); FP32 against FP64 at the same fixed CG count at the FP32 bar 1e-5.
 """
 import numpy as np
 import pytest
@@ -36,8 +36,10 @@ def test_objective_and_adjoint_match_oracle(project, shape):
                                        project=project)
     fr, gr = orc.sampled_objective_grad(p.X, p.H, p.n_pool, z, 1e-3, V, 1e-13, 5000, project)
     assert info["rc"] == 0
-    assert abs(f - fr) <= 1e-9 * abs(fr)
-    assert relerr(g.cpu().numpy(), gr) <= 1e-8
+    ef, eg = abs(f - fr) / abs(fr), relerr(g.cpu().numpy(), gr)
+    print(f"objective {shape} project={project}: f {ef:.2e}, gradient {eg:.2e}")
+    assert ef <= 1e-10, ef
+    assert eg <= 1e-10, eg
 
 
 def test_autograd_gradcheck_tiny():

@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import dense
 from oracle import relax as orc
 from paper_2409_07392_amd import FiralError, RelaxContext, _lib
 from synthdata import make_problem, make_small
@@ -262,7 +263,18 @@ def test_pcg_f64_matches_oracle(project, unfused, monkeypatch):
                              shift=1e-3, tol=0.0, max_iter=40, project=project)
     xr, it, _ = orc.pcg(X, H, om, 1e-3, L, B, 0.0, 40, project)
     assert info["cg_iters"][0] == it == 40
-    assert_close(host(Xs), xr, 1e-8, "pcg iterate after 40 iterations")
+    # the two sides round in different orders; each CG iteration can move the iterate by
+    # about kappa(A) u relative, so after k iterations the bar is max(1e-10, kappa u k): the
+    # FP64 bar itself with the projection (kappa ~ 10 on the complement), 8e-10 without it
+    # (kappa = 1.8e5: the lambda eigenspace)
+    A = dense.sum_fisher(X, H, om) + 1e-3 * np.eye(12 * 5)
+    ev = np.linalg.eigvalsh(A)
+    kappa = ev[-1] / ev[0] if not project else 1.0
+    bar = max(TOL["f64"], kappa * np.finfo(np.float64).eps / 2 * 40)
+    e = relerr(host(Xs), xr)
+    print(f"FP64 PCG iterate after 40 iterations (project={project}): rel err {e:.2e}, "
+          f"bar {bar:.2e}")
+    assert_close(host(Xs), xr, bar, "pcg iterate after 40 iterations")
     # stopping rule: with the projection (kappa ~ 10) the counts agree exactly; without it
     # (kappa ~ 1e4, the lambda eigenspace) finite-precision CG loses orthogonality and the
     # summation order moves the crossing of tol by a few percent of the count (113 against
@@ -274,10 +286,17 @@ def test_pcg_f64_matches_oracle(project, unfused, monkeypatch):
     assert info["relres_max"] <= 1e-9
     if project:
         assert info["cg_iters"][0] == it
-        assert_close(host(Xs), xr, 1e-8, "pcg solution")
+        assert_close(host(Xs), xr, TOL["f64"], "pcg solution")
     else:
+        # both sides stop with ||r|| <= tol ||b||, so their solutions differ by at most
+        # 2 kappa(A) tol relative to the solution (A = sum omega_i H_i + shift I, 2-norm)
         assert abs(info["cg_iters"][0] - it) <= max(3, 0.05 * it)
-        assert relerr(host(Xs), xr) <= 1e-4
+        A = dense.sum_fisher(X, H, om) + 1e-3 * np.eye(12 * 5)
+        ev = np.linalg.eigvalsh(A)
+        bar = 2.0 * (ev[-1] / ev[0]) * 1e-9
+        e = relerr(host(Xs), xr)
+        print(f"literal PCG at tol 1e-9: rel diff {e:.2e}, kappa-derived bar {bar:.2e}")
+        assert e <= bar, (e, bar)
 
 
 @pytest.mark.parametrize("unfused", ["0", "1"])
@@ -294,7 +313,9 @@ def test_pcg_f32_fixed_iterations(unfused, monkeypatch):
     assert info["cg_iters"][0] == 12
     L, _ = orc.precond_factor(orc.precond_blocks(X, H, om, 1e-3))
     xr, _, _ = orc.pcg(X, H, om, 1e-3, L, B, 0.0, 12, True)
-    assert relerr(host(Xs), xr) <= 1e-4
+    e = relerr(host(Xs), xr)
+    print(f"FP32 PCG iterate after 12 iterations: rel err {e:.2e}")
+    assert e <= TOL["f32"], e
 
 
 @pytest.mark.parametrize("unfused", ["0", "1"])
@@ -347,10 +368,10 @@ def test_relax_f64_trajectory_matches_oracle(unfused, monkeypatch):
         wr, ir = orc.relax_iteration(X, H, p.n_pool, wr, p.b, p.lam, beta0, p.probe_seed, t, p.s,
                                      p.tol, 1000, project=True)
         assert info["cg_iters"] == ir["cg_iters"], t
-        assert abs(info["f_hat"] - ir["f_hat"]) <= 1e-9 * abs(ir["f_hat"])
-        assert abs(info["g_absmax"] - ir["g_absmax"]) <= 1e-9 * ir["g_absmax"]
-        assert_close(host(g), ir["g"], 1e-9, f"gradient t={t}")
-        assert_close(host(w), wr, 1e-9, f"weights t={t}")
+        assert abs(info["f_hat"] - ir["f_hat"]) <= TOL["f64"] * abs(ir["f_hat"])
+        assert abs(info["g_absmax"] - ir["g_absmax"]) <= TOL["f64"] * ir["g_absmax"]
+        assert_close(host(g), ir["g"], TOL["f64"], f"gradient t={t}")
+        assert_close(host(w), wr, TOL["f64"], f"weights t={t}")
     wh = host(w)
     assert abs(wh.sum() - 1.0) < 1e-12 and np.all(wh > 0)
 
@@ -365,7 +386,9 @@ def test_relax_literal_mode_f64():
     wr, ir = orc.relax_iteration(X, H, p.n_pool, w0, 5.0, 1e-3, 0.3, 77, 1, 4, 0.0, 60,
                                  project=False)
     assert info["cg_iters"] == ir["cg_iters"] == (60, 60)
-    assert_close(host(w), wr, 1e-8, "weights (literal, 60 CG iterations)")
+    e = relerr(host(w), wr)
+    print(f"literal Relax step at 60 fixed CG iterations: weights rel err {e:.2e}")
+    assert_close(host(w), wr, TOL["f64"], "weights (literal, 60 CG iterations)")
     # tolerance-based stop (kappa ~ 1e4 here): counts within 3, weights close
     w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
     info = ctx.relax_step(w, 5.0, 1e-3, 0.3, 77, 1, 4, 1e-8, 3000, project=False)
@@ -401,8 +424,10 @@ def test_relax_f32_gradient_error_fixed_iterations():
                                  beta0, p.probe_seed, 1, p.s, 0.0, 15, project=True)
     assert info["cg_iters"] == (15, 15)
     e = relerr(host(g), ir["g"])
-    assert e <= 1e-4, e
-    assert abs(info["f_hat"] - ir["f_hat"]) <= 1e-5 * abs(ir["f_hat"])
+    print(f"FP32 Relax gradient at 15 CG iterations: rel err {e:.2e}")
+    assert e <= TOL["f32"], e
+    assert abs(info["f_hat"] - ir["f_hat"]) <= TOL["f32"] * abs(ir["f_hat"])
+    assert relerr(host(w), wr) <= TOL["f32"]
 
 
 # -------------------------------------------------------------------- bf16x3
