@@ -222,7 +222,8 @@ def headline(args):
             main = (leg, el)
         log(f"{prec}: {leg['hvp_ms']:.1f} ms per product; Relax iterations at tol {p.tol}")
         leg["relax_iterations"] = relax_leg(ctx, p, args.relax_iters, args.relax_max_cg)
-        leg["relax_iter_s"] = float(np.median([r["s"] for r in leg["relax_iterations"]]))
+        leg["relax_iter_s"] = (float(np.median([r["s"] for r in leg["relax_iterations"]]))
+                               if leg["relax_iterations"] else None)
         if not args.no_grad_error:
             log(f"{prec}: gradient at {args.grad_cg} fixed CG iterations")
             grads[prec] = fixed_cg_gradient(ctx, p, args.grad_cg)

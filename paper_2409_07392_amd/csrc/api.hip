@@ -65,7 +65,8 @@ int prof_pair(Ctx* x, int kernel, hipEvent_t* e0, hipEvent_t* e1) {
 
 static void free_ctx(Ctx* x) {
   drop_events(x);
-  void* bufs[] = {x->G, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->XThi, x->XTlo, x->P, x->Pinv, x->syrk_part, x->syrk_tiles, x->V, x->W1, x->Y,
+  void* bufs[] = {x->G, x->gpart, x->part, x->fused_part, x->Xhi, x->Xlo, x->XThi, x->XTlo,
+                  x->XTf, x->HTf, x->VTf, x->ntpart, x->P, x->Pinv, x->syrk_part, x->syrk_tiles, x->V, x->W1, x->Y,
                   x->W2, x->cx, x->cgd, x->cr, x->cz, x->cp, x->cq, x->mean, x->omega, x->gbuf, x->ebuf,
                   x->colpart, x->rho, x->bnorm, x->alpha, x->beta, x->relres, x->done,
                   x->redpart, x->status, x->t_dev};
@@ -205,8 +206,11 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
     const long long v = atoll(env);
     if (v >= 1 && v < rows) rows = v;
   }
-  // bf16x3: chunks start on multiples of 32 rows (the X^T planes are read 8 rows at a time)
-  if (prec == FIRAL_BF16X3) rows = std::max<int64_t>(32, rows - rows % 32);
+  // bf16x3: chunks start on multiples of 32 rows (the X^T planes are read 8 rows at a time);
+  // the wide FP32 path reads its transposed operands 4 rows at a time from 32-row stages
+  const char* nt_env = getenv("FIRAL_NT");
+  x->use_nt = nt_applies(x) && !(nt_env && atoi(nt_env) == 0);
+  if (prec == FIRAL_BF16X3 || x->use_nt) rows = std::max<int64_t>(32, rows - rows % 32);
   x->chunk_rows = rows;
   const int64_t tiles = tiled_out_tiles(prec, d, sc);
   x->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(4096, tiles), 64));
@@ -255,6 +259,14 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   ALLOC(x->Pinv, (int64_t)c * d * d * 8);
   ALLOC(x->syrk_part, (int64_t)x->syrk_splits * c * d * d * es);
   ALLOC(x->syrk_tiles, syrk_tiles.size() * sizeof(int32_t));
+  if (x->use_nt) {
+    x->ldn = nt_ld(x->N);
+    const int64_t ldg = nt_ld(rows), nw = nt_windows(c);
+    ALLOC(x->XTf, x->ldn * d * 4);
+    ALLOC(x->HTf, x->ldn * c * 4);
+    ALLOC(x->VTf, blk * 4);
+    ALLOC(x->ntpart, ((int64_t)s_max * nw * ldg + (int64_t)s_max * ldg) * 4);
+  }
   if (prec == FIRAL_BF16X3) {
     x->ldt = cdiv(x->N, 8) * 8;
     ALLOC(x->Xhi, x->N * d * 2);
@@ -310,6 +322,7 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
         hipMemcpyAsync(x->syrk_tiles, syrk_tiles.data(), syrk_tiles.size() * sizeof(int32_t),
                        hipMemcpyHostToDevice, st) != hipSuccess ||
         (prec == FIRAL_BF16X3 && split_x_launch(x, st) != FIRAL_OK) ||
+        (x->use_nt && nt_prepare_ctx(x, st) != FIRAL_OK) ||
         hipStreamSynchronize(st) != hipSuccess) {
       set_error("status initialisation failed");
       rc = FIRAL_EHIP;

@@ -96,6 +96,16 @@ struct Ctx {
   void* XTlo;
   int64_t ldt;
 
+  // wide FP32 path (gemm_nt.hip; d > 128, d % 4 == 0, c > 128): X^T (d x ldn) and H^T
+  // (c x ldn) in FP32, ldn = N rounded up to a multiple of 4 (padding zero), made at creation;
+  // the transposed probe block (s_max c x d); per chunk alpha partials, alpha and omega
+  int use_nt;
+  int64_t ldn;
+  void* XTf;
+  void* HTf;
+  void* VTf;
+  void* ntpart;
+
   // preconditioner
   double* P;            // c * d * d: blocks, factorised in place
   double* Pinv;         // c * d * d
@@ -322,6 +332,13 @@ int pcg_launch(Ctx* x, const double* omega, double shift, const double* Pinv, co
                void* Xsol, int s, double tol, int max_iter, uint32_t flags, int slot,
                hipStream_t st);
 int grad_launch(Ctx* x, const void* U, const void* W, int s, double* g, hipStream_t st);
+// wide FP32 path (gemm_nt.hip)
+bool nt_applies(const Ctx* x);
+int64_t nt_ld(int64_t rows);
+int nt_windows(int c);
+int nt_prepare_ctx(Ctx* x, hipStream_t st);
+int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const float* B,
+                  float* out, int s, Skip skip, hipStream_t st);
 // general (any d, c) product through the row-tiled kernels of tiled.hip
 int hvp_tiled_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const void* B,
                      void* out, int s, Skip skip, hipStream_t st, bool precise);

@@ -1,0 +1,428 @@
+// FP32 Hessian product of Lemma 1 for wide problems (d > 128, c > 128, d a multiple of 4):
+// both contractions as GEMMs whose operands are stored with the contraction index contiguous,
+// so every operand moves as 16-byte vectors from HBM to LDS and from LDS to the MFMA inputs.
+//
+// Per chunk of R rows (rows r0 .. r0 + R):
+//   k_nt_xv     G = X V^T[n][.] (X row-major; V^T: the probe block transposed once per call),
+//               stored transposed and scaled by the row weights, E^T[n][r] = omega_r G[r][n]; its
+//               epilogue also forms, per row and tile, beta_part[p][w][r] = sum over the tile's
+//               columns of E h (the tiles of probe p are its column windows w: c > 128, so a
+//               tile never mixes probes)
+//   k_nt_alpha  beta[p][r] = sum_w beta_part[p][w][r] (FP64, fixed order) = omega_r alpha_rp
+//   k_nt_xtg    part[sp][a][n] (+)= sum_r X^T[a][r] G'^T[n][r] over the split's rows, with the
+//               row step of Lemma 1, G' = omega (G - alpha) h = (E - beta) h, applied while E^T
+//               is staged (X^T and H^T: transposed FP32 copies made at context creation)
+// and the split sums are reduced in a fixed order (hvp.hip).
+//
+// MFMA: v_mfma_f32_16x16x4f32.  Within a 16-deep k group the four instructions q = 0..3 take
+// k = 4 g + q from lane group g = lane / 16, so a lane's four k values are contiguous and one
+// 128-bit LDS read feeds four instructions; the result lane (g, l % 16) holds rows 4 g .. 4 g + 3
+// of column l % 16, contiguous in a transposed store.
+#include <algorithm>
+
+#include <hip/hip_ext.h>
+
+#include "common.h"
+
+namespace firal {
+
+namespace {
+
+constexpr int kNtBM = 128, kNtBN = 128;   // workgroup tile (rows x columns of the output)
+constexpr int kNtKS = 32;                 // k per pipeline stage
+constexpr int kNtSK = kNtKS + 4;          // LDS row stride in floats (16-byte reads spread over
+                                          // all banks: rows 36 floats apart)
+constexpr int kNtWG = 256;                // four waves, 2 x 2, each 64 x 64
+constexpr size_t kNtLds = (size_t)2 * (kNtBM + kNtBN) * kNtSK * 4;   // 73,728 bytes
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Workgroup b of n runs on XCD b % 8; give each XCD a contiguous range of logical tiles.
+__device__ __forceinline__ int64_t nt_lid(int64_t b, int64_t n) {
+  const int64_t q = n >> 3, r = n & 7, x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// One 32-deep stage of a wave's 4 x 4 blocks of 16 x 16 from LDS tiles a[m][k], b[n][k].
+__device__ __forceinline__ void nt_stage(const float* __restrict__ a, const float* __restrict__ b,
+                                         int wm, int wn, int li, int g, f32x4 (&acc)[4][4]) {
+#pragma unroll
+  for (int kg = 0; kg < kNtKS / 16; ++kg) {
+    f4 av[4], bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      av[i] = *reinterpret_cast<const f4*>(a + (wm + 16 * i + li) * kNtSK + 16 * kg + 4 * g);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      bv[j] = *reinterpret_cast<const f4*>(b + (wn + 16 * j + li) * kNtSK + 16 * kg + 4 * g);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Tile loads: a 128 x 32 tile of a row-major source (leading dimension ld, k contiguous) as
+// 1024 16-byte vectors, four per thread: vector e = tid + 256 t covers row e / 8, k 4 (e % 8).
+// Rows at or beyond nrow and k at or beyond nk read as zero (nk is a multiple of 4).
+__device__ __forceinline__ void nt_load(const float* __restrict__ src, int64_t ld, int64_t row0,
+                                        int64_t nrow, int64_t k0, int64_t nk, int tid, f4 (&v)[4]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = tid + kNtWG * t, rr = e >> 3, kk = 4 * (e & 7);
+    const int64_t row = row0 + rr, k = k0 + kk;
+    v[t] = (row < nrow && k < nk) ? *reinterpret_cast<const f4*>(src + row * ld + k)
+                                  : f4{0.f, 0.f, 0.f, 0.f};
+  }
+}
+__device__ __forceinline__ void nt_store(float* __restrict__ dst, int tid, const f4 (&v)[4]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = tid + kNtWG * t, rr = e >> 3, kk = 4 * (e & 7);
+    *reinterpret_cast<f4*>(dst + rr * kNtSK + kk) = v[t];
+  }
+}
+
+// Kernel 1.  Tiles: row tile rt (kNtBM rows of the chunk) x column tile ct of the flat column
+// space of s probes cut into windows of kNtBN columns per probe (nw windows each).
+__global__ __launch_bounds__(kNtWG, 2) void k_nt_xv(
+    const float* __restrict__ X, int d, int64_t R, const float* __restrict__ VT, int c, int nw,
+    int ntc, const float* __restrict__ HT, int64_t ldh, const double* __restrict__ omega,
+    float* __restrict__ GT, int64_t ldg, float* __restrict__ apart, Skip skip) {
+  if (skip_now(skip)) return;
+  extern __shared__ __align__(16) float nt_lds[];
+  float* As = nt_lds;                          // [2][kNtBM][kNtSK]
+  float* Bs = nt_lds + 2 * kNtBM * kNtSK;      // [2][kNtBN][kNtSK]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  // tiles in groups of 8 row tiles: consecutive logical ids take the 8 row tiles of a group for
+  // one column tile, then the next column tile, so that 64 workgroups resident on one XCD share
+  // 8 tiles of X and 8 of V^T in its L2 (the last group may hold fewer row tiles)
+  const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
+  const int64_t nrt = (R + kNtBM - 1) / kNtBM;
+  const int64_t grp = lid / (8 * (int64_t)ntc);
+  const int64_t g0 = grp * 8;
+  const int64_t gsz = nrt - g0 < 8 ? nrt - g0 : 8;
+  const int64_t in = lid - grp * 8 * (int64_t)ntc;
+  const int ct = (int)(in / gsz);
+  const int64_t rt = g0 + (in - (int64_t)ct * gsz);
+  const int p = ct / nw, w = ct - p * nw;
+  const int64_t row0 = rt * kNtBM;
+  const int col0 = w * kNtBN;                              // within the probe
+  const int width = c - col0 < kNtBN ? c - col0 : kNtBN;  // columns of the window
+  const int64_t n0 = (int64_t)p * c + col0;                // first column of V^T
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  f4 ra[4], rb[4];
+  const int nst = (d + kNtKS - 1) / kNtKS;
+  nt_load(X, d, row0, R, 0, d, tid, ra);
+  nt_load(VT + n0 * d, d, 0, width, 0, d, tid, rb);
+  nt_store(As, tid, ra);
+  nt_store(Bs, tid, rb);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) {
+      nt_load(X, d, row0, R, (int64_t)(st + 1) * kNtKS, d, tid, ra);
+      nt_load(VT + n0 * d, d, 0, width, (int64_t)(st + 1) * kNtKS, d, tid, rb);
+    }
+    nt_stage(As + buf * kNtBM * kNtSK, Bs + buf * kNtBN * kNtSK, wm, wn, li, g, acc);
+    if (st + 1 < nst) {
+      nt_store(As + (buf ^ 1) * kNtBM * kNtSK, tid, ra);
+      nt_store(Bs + (buf ^ 1) * kNtBN * kNtSK, tid, rb);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue.  Lane (g, li) of block (i, j) holds G[r][n] for r = row0 + wm + 16 i + 4 g + v,
+  // n = col0 + wn + 16 j + li (v = 0..3).  (1) E^T = (omega G)^T as 16-byte stores of four rows;
+  // (2) per row the sum over this wave's columns of E h, then over the 16 lanes of a column
+  // group, then over the two waves of a row band through LDS, into beta_part[p][w][r].
+  float* red = nt_lds;   // [2][kNtBM]: the main buffers are free after the last barrier
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = row0 + wm + 16 * i + 4 * g;   // first of the lane's four rows
+    float om[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) om[v] = r + v < R ? (omega ? (float)omega[r + v] : 1.f) : 0.f;
+    float t[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int nl = wn + 16 * j + li;              // column within the window
+      if (nl < width && r < R) {
+        const int64_t n = n0 + nl;
+        const f4 e = f4{om[0] * acc[i][j][0], om[1] * acc[i][j][1], om[2] * acc[i][j][2],
+                        om[3] * acc[i][j][3]};
+        // R is a multiple of 4 except at the end of the rows; guard the last vector
+        if (r + 3 < R) {
+          *reinterpret_cast<f4*>(GT + n * ldg + r) = e;
+        } else {
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (r + v < R) GT[n * ldg + r + v] = e[v];
+        }
+        const f4 h = *reinterpret_cast<const f4*>(HT + (int64_t)(col0 + nl) * ldh + r);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) t[v] = fmaf(e[v], h[v], t[v]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float s = t[v];
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      s += __shfl_xor(s, 4, 64);
+      s += __shfl_xor(s, 8, 64);
+      t[v] = s;
+    }
+    if (li == 0) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(wave & 1) * kNtBM + wm + 16 * i + 4 * g + v] = t[v];
+    }
+  }
+  __syncthreads();
+  if (tid < kNtBM) {
+    const int64_t r = row0 + tid;
+    if (r < R) apart[((int64_t)p * nw + w) * ldg + r] = red[tid] + red[kNtBM + tid];
+  }
+}
+
+// beta[p][r] = sum_w beta_part[p][w][r] in FP64, fixed order (= omega_r alpha_rp).
+__global__ __launch_bounds__(256) void k_nt_alpha(const float* __restrict__ apart, int nw, int s,
+                                                  int64_t R, int64_t ldg,
+                                                  float* __restrict__ beta, Skip skip) {
+  if (skip_now(skip)) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)s * R) return;
+  const int p = (int)(e / R);
+  const int64_t r = e - (int64_t)p * R;
+  double a = 0.0;
+  for (int w = 0; w < nw; ++w) a += (double)apart[((int64_t)p * nw + w) * ldg + r];
+  beta[(int64_t)p * ldg + r] = (float)a;
+}
+
+// E^T and h of four consecutive columns nb .. nb + 3 (nvalid of them valid; the class of nb is
+// k_first) at rows r .. r + 3 (zero when r >= re).
+__device__ __forceinline__ void nt_load_e(const float* __restrict__ GT, int64_t ldg,
+                                          const float* __restrict__ HT, int64_t ldh, int nb,
+                                          int nvalid, int k_first, int c, int64_t r, int64_t re,
+                                          f4 (&gv)[4], f4 (&hv)[4]) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    int k = k_first + t;
+    if (k >= c) k -= c;   // the next probe's first classes
+    const bool ok = t < nvalid && r < re;
+    gv[t] = ok ? *reinterpret_cast<const f4*>(GT + (int64_t)(nb + t) * ldg + r)
+               : f4{0.f, 0.f, 0.f, 0.f};
+    hv[t] = ok ? *reinterpret_cast<const f4*>(HT + (int64_t)k * ldh + r) : f4{0.f, 0.f, 0.f, 0.f};
+  }
+}
+// G'^T = (E^T - beta[p]) h of the four columns into the LDS tile b[n][k] (rows at or beyond re
+// stage as zero).
+__device__ __forceinline__ void nt_store_g(float* __restrict__ b, int tid, int64_t r, int64_t re,
+                                           const float* __restrict__ beta, int64_t ldg, int nb,
+                                           int c, int p_lo, int p_hi, const f4 (&gv)[4],
+                                           const f4 (&hv)[4]) {
+  const bool rok = r < re;   // re is a multiple of 4 except at the end of the rows
+  const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+  const f4 b_lo = rok ? *reinterpret_cast<const f4*>(beta + (int64_t)p_lo * ldg + r) : z4;
+  const f4 b_hi = rok ? *reinterpret_cast<const f4*>(beta + (int64_t)p_hi * ldg + r) : z4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const f4 bt = (nb + t) / c == p_lo ? b_lo : b_hi;
+    f4 x;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) x[v] = r + v < re ? (gv[t][v] - bt[v]) * hv[t][v] : 0.f;
+    *reinterpret_cast<f4*>(b + (4 * (tid >> 3) + t) * kNtSK + (int)(4 * (tid & 7))) = x;
+  }
+}
+
+// Kernel 2.  Output tiles: a-tile mt (kNtBM values of a) x column tile ct (kNtBN flat columns),
+// split sp of the chunk's rows.  B is staged as G'^T[n][r] = (E^T[n][r] - beta[p][r]) h_rk with
+// p = n / c, k = n % c.  Thread tid stages columns n0 + 4 (tid / 8) + t, t = 0..3, at rows
+// 4 (tid % 8) of the stage: E^T and h are fetched before the stage's products, beta (at most two
+// probes among four consecutive columns) after them.
+__global__ __launch_bounds__(kNtWG, 2) void k_nt_xtg(
+    const float* __restrict__ XT, int64_t ldx, int d, const float* __restrict__ GT, int64_t ldg,
+    int SC, int c, const float* __restrict__ HT, int64_t ldh, const float* __restrict__ beta,
+    int64_t R, int64_t rows_per_split, int nmt, int nct, float* __restrict__ part,
+    int64_t part_stride, int accumulate, Skip skip) {
+  if (skip_now(skip)) return;
+  extern __shared__ __align__(16) float nt_lds[];
+  float* As = nt_lds;
+  float* Bs = nt_lds + 2 * kNtBM * kNtSK;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
+  const int mt = (int)(lid % nmt);
+  const int64_t rest = lid / nmt;
+  const int ct = (int)(rest % nct);
+  const int sp = (int)(rest / nct);
+  const int a0 = mt * kNtBM, n0 = ct * kNtBN;
+  const int64_t rb = (int64_t)sp * rows_per_split;
+  const int64_t re = rb + rows_per_split < R ? rb + rows_per_split : R;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // B staging: columns nb + t (t = 0..3) at rows 4 (tid % 8) of the stage; the columns' probes
+  // (the first and last of the four may differ), classes and validity are fixed per thread
+  const int nb = n0 + 4 * (tid >> 3);
+  const int rk = 4 * (tid & 7);
+  const int nvalid = SC - nb < 4 ? (SC - nb > 0 ? SC - nb : 0) : 4;
+  const int k_first = nb < SC ? nb % c : 0;
+  const int p_lo = nb < SC ? nb / c : 0;
+  const int p_hi = nb + 3 < SC ? (nb + 3) / c : p_lo;
+  f4 ra[4], gv[4], hv[4];
+  const int64_t nrows = re > rb ? re - rb : 0;
+  const int nst = (int)((nrows + kNtKS - 1) / kNtKS);
+  if (nst > 0) {
+    nt_load(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, rb, re, tid, ra);
+    nt_load_e(GT, ldg, HT, ldh, nb, nvalid, k_first, c, rb + rk, re, gv, hv);
+    nt_store(As, tid, ra);
+    nt_store_g(Bs, tid, rb + rk, re, beta, ldg, nb, c, p_lo, p_hi, gv, hv);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const int64_t k1 = rb + (int64_t)(st + 1) * kNtKS;
+    if (st + 1 < nst) {
+      nt_load(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, k1, re, tid, ra);
+      nt_load_e(GT, ldg, HT, ldh, nb, nvalid, k_first, c, k1 + rk, re, gv, hv);
+    }
+    nt_stage(As + buf * kNtBM * kNtSK, Bs + buf * kNtBN * kNtSK, wm, wn, li, g, acc);
+    if (st + 1 < nst) {
+      nt_store(As + (buf ^ 1) * kNtBM * kNtSK, tid, ra);
+      nt_store_g(Bs + (buf ^ 1) * kNtBN * kNtSK, tid, k1 + rk, re, beta, ldg, nb, c, p_lo, p_hi,
+                 gv, hv);
+    }
+    __syncthreads();
+  }
+
+  float* out = part + (int64_t)sp * part_stride;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = a0 + wm + 16 * i + 4 * g + v;
+        const int n = n0 + wn + 16 * j + li;
+        if (a < d && n < SC) {
+          const int64_t o = (int64_t)a * SC + n;
+          out[o] = accumulate ? out[o] + acc[i][j][v] : acc[i][j][v];
+        }
+      }
+}
+
+// dst[j][i] = src[i][j] for an rows x cols row-major source (leading dimension lds) into a
+// destination with leading dimension ldd; entries of dst beyond rows (up to ldd) are zeroed.
+__global__ __launch_bounds__(256) void k_nt_transpose(const float* __restrict__ src, int64_t rows,
+                                                      int64_t cols, int64_t lds,
+                                                      float* __restrict__ dst, int64_t ldd) {
+  __shared__ float tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t i = i0 + q, j = j0 + tx;
+    tile[q][tx] = (i < rows && j < cols) ? src[i * lds + j] : 0.f;
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t j = j0 + q, i = i0 + tx;
+    if (j < cols && i < ldd) dst[j * ldd + i] = tile[tx][q];
+  }
+}
+
+int nt_transpose(const float* src, int64_t rows, int64_t cols, int64_t lds, float* dst,
+                 int64_t ldd, hipStream_t st) {
+  dim3 grid((unsigned)cdiv(ldd, 32), (unsigned)cdiv(cols, 32));
+  k_nt_transpose<<<grid, 256, 0, st>>>(src, rows, cols, lds, dst, ldd);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
+bool g_nt_attr = false;
+
+}  // namespace
+
+// The wide path covers FP32 contexts with d > 128, d % 4 == 0 and c > 128; its transposed
+// copies of X and H are made at creation when this holds.
+bool nt_applies(const Ctx* x) {
+  return x->prec == FIRAL_F32 && x->d > 128 && x->d % 4 == 0 && x->c > kNtBN;
+}
+
+int64_t nt_ld(int64_t rows) { return cdiv(rows, 4) * 4; }
+
+// Column windows per probe of the wide path.
+int nt_windows(int c) { return (int)cdiv(c, kNtBN); }
+
+int nt_prepare_ctx(Ctx* x, hipStream_t st) {
+  FIRAL_CHECK(nt_transpose((const float*)x->X, x->N, x->d, x->d, (float*)x->XTf, x->ldn, st));
+  FIRAL_CHECK(nt_transpose((const float*)x->H, x->N, x->c, x->c, (float*)x->HTf, x->ldn, st));
+  return FIRAL_OK;
+}
+
+int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const float* B,
+                  float* out, int s, Skip skip, hipStream_t st) {
+  const int d = x->d, c = x->c, SC = s * c, nw = nt_windows(c);
+  if (!g_nt_attr) {
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kNtLds));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xtg,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNtLds));
+    g_nt_attr = true;
+  }
+  // V^T: the probe block d x (s c) transposed to (s c) x d
+  float* VT = (float*)x->VTf;
+  FIRAL_CHECK(nt_transpose(B, d, SC, SC, VT, d, st));
+  // buffers: E^T [s c][ldg], beta_part [s][nw][ldg], beta [s][ldg]
+  const int64_t ldg = nt_ld(x->chunk_rows);
+  float* GT = (float*)x->G;
+  float* apart = (float*)x->ntpart;
+  float* beta = apart + (int64_t)s * nw * ldg;
+  float* part = (float*)x->part;
+  const int64_t n_out = (int64_t)d * SC;
+  const int nmt = (int)cdiv(d, kNtBM), nct = (int)cdiv(SC, kNtBN);
+  const int64_t tiles = (int64_t)nmt * nct;
+  const int64_t cap = (int64_t)x->max_splits * x->s_max / s;
+  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(4096, tiles), cap), 256));
+  const int ntc = s * nw;
+  for (int64_t r0 = 0; r0 < n_rows; r0 += x->chunk_rows) {
+    const int64_t R = std::min<int64_t>(x->chunk_rows, n_rows - r0);
+    hipEvent_t e0, e1;
+    FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT, &e0, &e1));
+    hipExtLaunchKernelGGL(k_nt_xv, dim3((unsigned)(cdiv(R, kNtBM) * ntc)), dim3(kNtWG),
+                          (uint32_t)kNtLds, st, e0, e1, 0u, (const float*)x->X + r0 * d, d, R,
+                          (const float*)VT, c, nw, ntc, (const float*)x->HTf + r0, x->ldn,
+                          omega ? omega + r0 : nullptr, GT, ldg, apart, skip);
+    FIRAL_LAUNCHED();
+    k_nt_alpha<<<(unsigned)cdiv((int64_t)s * R, 256), 256, 0, st>>>(apart, nw, s, R, ldg, beta,
+                                                                     skip);
+    FIRAL_LAUNCHED();
+    // splits start on multiples of 32 rows (the stage depth)
+    const int64_t rps = cdiv(cdiv(R, S), kNtKS) * kNtKS;
+    FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT_T, &e0, &e1));
+    hipExtLaunchKernelGGL(k_nt_xtg, dim3((unsigned)(tiles * S)), dim3(kNtWG), (uint32_t)kNtLds,
+                          st, e0, e1, 0u, (const float*)x->XTf + r0, x->ldn, d, (const float*)GT,
+                          ldg, SC, c, (const float*)x->HTf + r0, x->ldn, (const float*)beta,
+                          R, rps, nmt, nct, part, n_out, (int)(r0 > 0), skip);
+    FIRAL_LAUNCHED();
+  }
+  return reduce_parts_launch<float>(part, n_out, n_rows > 0 ? S : 0, shift, B, out, skip, st);
+}
+
+}  // namespace firal

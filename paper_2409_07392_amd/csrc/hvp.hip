@@ -10,7 +10,8 @@
 // X^T G' contraction is split over rows into partial buffers that a final
 // pass (here) sums in a fixed order (no float atomics: results are reproducible).
 // Dispatch: the single-pass fused kernel (hvp_fused.hip) for FP32 / bf16x3 when
-// its tile plan fits, else the row-tiled two-kernel path (tiled.hip).
+// its tile plan fits, else for wide FP32 problems the transposed-operand GEMMs of gemm_nt.hip,
+// else the row-tiled two-kernel path (tiled.hip).
 #include <algorithm>
 
 #include "common.h"
@@ -71,6 +72,8 @@ int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const 
       plan.part_elems <= x->fused_part_elems)
     return hvp_fused_launch(x, plan, omega, n_rows, shift, (const float*)B, (float*)out, s, skip,
                             st);
+  if (x->use_nt && !x->force_tiled)
+    return hvp_nt_launch(x, omega, n_rows, shift, (const float*)B, (float*)out, s, skip, st);
   return hvp_tiled_launch(x, omega, n_rows, shift, B, out, s, skip, st, precise);
 }
 

@@ -602,9 +602,10 @@ __global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst
 // fit in L2 together, else class then row tile.
 // CT is the decision precision: every step from the products to the class term is computed
 // in CT (FP64, or FP32 on the FP32 MFMA as the paper's single-precision implementation does).
-// FP32 operands run four workgroups per CU (128 VGPRs, 56 bytes per lane spilled, still
-// faster than three without spills), FP64 three (168 VGPRs, 92 bytes spilled, rows padded by
-// two values instead of four so that three fit in LDS; faster than two without spills).
+// FP32 operands run four workgroups per CU, FP64 three (rows padded by two values instead of
+// four so that three fit in LDS), both without scratch: the next stage is fetched after the
+// current stage's products (no staging registers live across the MFMAs) and the four k-steps
+// of a stage are unrolled by two (84 VGPRs for FP32, 126 for FP64).
 template <typename T, typename CT>
 __global__ __launch_bounds__(256, sizeof(CT) == 4 ? 4 : 3) void k_round_score(const T* __restrict__ X,
                                                      const T* __restrict__ H, int64_t r0,
@@ -684,9 +685,8 @@ __global__ __launch_bounds__(256, sizeof(CT) == 4 ? 4 : 3) void k_round_score(co
     __syncthreads();
     for (int st = 0; st < nst; ++st) {
       const int buf = st & 1;
-      if (st + 1 < nst) load(st + 1);
       const int k0 = st * TK;
-#pragma unroll
+#pragma unroll 2
       for (int q = 0; q < TK / 4; ++q) {
         CT a[2], bu[2], bv[2];
 #pragma unroll
@@ -704,7 +704,12 @@ __global__ __launch_bounds__(256, sizeof(CT) == 4 ? 4 : 3) void k_round_score(co
             if (k0 < jend[j]) au[i][j] = MF::run(a[i], bu[j], au[i][j]);
           }
       }
-      if (st + 1 < nst) store(buf ^ 1);
+      // the next stage is fetched after this stage's products: no staging registers live
+      // across the MFMAs (the other workgroups on the CU keep it busy meanwhile)
+      if (st + 1 < nst) {
+        load(st + 1);
+        store(buf ^ 1);
+      }
       __syncthreads();
     }
     // this tile's u . v and v . v, summed over the lane's columns, then over the 16 lanes of

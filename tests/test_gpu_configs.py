@@ -14,7 +14,7 @@
   labeled rows and z = 25 x Dirichlet(1) (the full problem's z = 1000 x Dirichlet(1) restricted
   to 5,000 of its 200,000 points sums to about 25): the sampled objective and its adjoint
   gradient (extension 3) against the oracle in FP64 and FP32 at 30 fixed CG iterations per
-  solve, and FP64 central differences (h = 1e-4, each f with the second-order residual
+  solve, and FP64 central differences (step 1e-4 z_i, each f with the second-order residual
   correction) on 64 random coordinates.
 * Batches (extension 2) in FP32 and bf16x3 against the oracle for two uneven problems.
 * A two-round synthetic active-learning loop whose FIRAL selections (Relax with the stop rule,
@@ -196,13 +196,16 @@ def test_configuration_3_objective_and_adjoint(cfg3sub, prec):
 
 
 def test_configuration_3_central_differences_64_coordinates(cfg3sub):
-    # FP64 central differences (h = 1e-4) of f_V on 64 random coordinates against the adjoint
-    # gradient (RelaxObjective's backward).  The weights here cover the d c = 25,600 directions
-    # thinly (z sums to 25 beside 100 labeled rows), so Sigma^-1 H_p V is large and the plain
-    # estimate <U, Y> of f carries an error first-order in the PCG residual, which divided by
-    # 2h swamps the difference.  Each f is therefore evaluated with the residual correction
-    # f = (<U, Y> + <W, V - Sigma U>) / s, U = Sigma^-1 V and W = Sigma^-1 H_p V from PCG (all
-    # library calls), whose error is second order in the residuals (-<e_W, Sigma e_U> / s).
+    # FP64 central differences of f_V on 64 random coordinates against the adjoint gradient
+    # (RelaxObjective's backward), with the step h_i = 1e-4 z_i.  The weights here cover the
+    # d c = 25,600 directions thinly (z sums to 25 beside 100 labeled rows): a step of 1e-4 in
+    # absolute terms (20 times the mean z_i) changes the thinly covered blocks of Sigma by far
+    # more than their size, outside the range where f is linear in z_i, so the step is taken
+    # relative to z_i.  Sigma^-1 H_p V is then large and the plain estimate <U, Y> of f carries
+    # an error first-order in the PCG residual that would swamp the difference, so each f is
+    # evaluated with the residual correction f = (<U, Y> + <W, V - Sigma U>) / s,
+    # U = Sigma^-1 V and W = Sigma^-1 H_p V from PCG (all library calls), whose error is second
+    # order in the residuals (-<e_W, Sigma e_U> / s).
     p, z, V, _, _ = cfg3sub
     ctx = RelaxContext(dev(p.X), dev(p.H), p.n_pool, p.s, "f64")
     Vd = dev(V)
@@ -222,9 +225,9 @@ def test_configuration_3_central_differences_64_coordinates(cfg3sub):
         return (float((U * Y).sum()) + float((W * R).sum())) / p.s
 
     idx = np.random.default_rng(3004).choice(p.n_pool, 64, replace=False)
-    h = 1e-4
     fd = np.empty(64)
     for m, i in enumerate(idx):
+        h = 1e-4 * z[i]   # the step relative to the weight (see the reading on the step)
         zp, zm = z.copy(), z.copy()
         zp[i] += h
         zm[i] -= h

@@ -497,3 +497,52 @@ def test_relax_bf16x3_gradient_error_fixed_iterations():
     assert info["cg_iters"] == (15, 15)
     e = relerr(host(g), ir["g"])
     assert e <= BF3_TOL, e
+
+
+# ------------------------------------------------------------- wide FP32 path
+# d > 128 (a multiple of 4) and c > 128 in an FP32 context: the transposed-operand GEMMs with the
+# row step split between the first kernel's epilogue (alpha per column window) and the second
+# kernel's staging.  Shapes: configuration 4's d and c; d with a 4-deep last stage (132); a
+# one-column last window (c = 129); ragged rows and several chunks (FIRAL_CHUNK_ROWS, rounded
+# down to 32 rows); H_p over the pool rows only (the labeled rows follow in the same chunk).
+NT_SHAPES = [  # n_pool, n_lab, d, c, s, chunk rows
+    (1500, 10, 384, 1000, 2, None),
+    (900, 7, 132, 129, 3, None),
+    (777, 3, 260, 300, 5, "320"),
+    (2050, 14, 136, 257, 1, "100"),
+]
+
+
+@pytest.mark.parametrize("shape", NT_SHAPES)
+def test_wide_fp32_product_matches_oracle(shape, monkeypatch):
+    n, nl, d, c, s, chunk = shape
+    if chunk:
+        monkeypatch.setenv("FIRAL_CHUNK_ROWS", chunk)
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=33, whiten_x=True, probs="maxprob")
+    ctx, X, H = context(p, "f32", s)
+    rng = np.random.default_rng(34)
+    B = rounded(rng.standard_normal((d, s, c)), "f32")
+    om = rng.uniform(0.0, 2.0, p.N)
+    got = host(ctx.hvp(dev(B, torch.float32), omega=dev(om, torch.float64), shift=0.5))
+    assert_close(got, orc.hvp(X, H, om, 0.5, B), TOL["f32"], f"wide hvp {shape}")
+    got = host(ctx.hvp(dev(B, torch.float32), n_rows=n))
+    assert_close(got, orc.hvp(X[:n], H[:n], None, 0.0, B), TOL["f32"], f"wide H_p {shape}")
+    # the same call twice: bitwise identical (fixed-order sums)
+    a = ctx.hvp(dev(B, torch.float32), shift=0.5)
+    b = ctx.hvp(dev(B, torch.float32), shift=0.5)
+    assert torch.equal(a, b)
+
+
+def test_wide_fp32_relax_step_matches_oracle():
+    p = make_small(n=2000, n_lab=9, d=132, c=130, s=3, seed=35, whiten_x=True, probs="maxprob")
+    ctx, X, H = context(p, "f32", p.s)
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(w)
+    info = ctx.relax_step(w, 20.0, 1e-3, 0.4, 7, 1, p.s, 0.0, 12, project=True, g_out=g)
+    assert info["cg_iters"] == (12, 12)
+    wr, ir = orc.relax_iteration(X, H, p.n_pool, np.full(p.n_pool, 1.0 / p.n_pool), 20.0, 1e-3,
+                                 0.4, 7, 1, p.s, 0.0, 12, project=True)
+    e = relerr(host(g), ir["g"])
+    print(f"wide FP32 Relax step at 12 CG iterations: gradient rel err {e:.2e}")
+    assert e <= TOL["f32"], e
+    assert relerr(host(w), wr) <= TOL["f32"]
