@@ -105,6 +105,22 @@ int firal_destroy(firal_ctx ctx);
 int firal_hvp(firal_ctx ctx, const double* omega, int64_t n_rows, double shift,
               const void* B, void* out, int32_t s, void* stream);
 
+/* The product of firal_hvp without a context and without allocating, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops that forbid hipMalloc):
+ *   out_j = sum_{i < n_rows} omega_i H_i v_j + shift * v_j
+ * over the n_rows rows of X (device FP32, n_rows x d row-major) and H (device FP32, n_rows x c),
+ * B and out device FP32 blocks d x s x c (out must not alias B), omega device FP64 [n_rows] or
+ * NULL for all ones.  It runs the fused FP32 kernels of firal_hvp and keeps their per-row-range
+ * partial sums in one fixed 64 MiB device array of the library (each device holds its own until
+ * the process ends), so it covers FP32 with d <= 128 and the shapes whose partial sums fit that
+ * array.  Calls on one device share the array: calls that overlap on a device (two streams, two
+ * host threads) race and must not be issued.  No allocation, no host synchronisation;
+ * asynchronous.  Errors: EINVAL (null pointer, size out of range, partial sums larger than the
+ * array: checked before any device call), ENOTSUP (d > 128, or no single-pass tile plan), EHIP. */
+int firal_hvp_noalloc(const float* X, const float* H, int64_t n_rows, int32_t d, int32_t c,
+                      const double* omega, double shift, const float* B, float* out, int32_t s,
+                      void* stream);
+
 /* Block-diagonal preconditioner (Definition 1, eq. 12):
  *   P_k = shift * I_d + sum_i omega_i h_ik (1 - h_ik) x_i x_i^T,  k = 0..c-1, all rows,
  * factorised in FP64 as P_k = L_k L_k^T.  L (lower, upper part zero) and Pinv = P_k^-1

@@ -24,7 +24,7 @@ EXPORTS = ("firal_create", "firal_destroy", "firal_hvp", "firal_build_precond",
            "firal_batch_next_t", "firal_batch_destroy", "firal_round_create", "firal_round_step",
            "firal_round_scores", "firal_round_result", "firal_round_criterion",
            "firal_round_destroy", "firal_round_eta_sweep", "firal_default_beta0",
-           "firal_relax_solve", "firal_strerror", "firal_last_error")
+           "firal_relax_solve", "firal_hvp_noalloc", "firal_strerror", "firal_last_error")
 
 
 class Info(ctypes.Structure):
@@ -74,6 +74,7 @@ def load() -> ctypes.CDLL:
         "firal_create": [ctypes.POINTER(vp), i64, i64, i32, i32, i32, i32, vp, vp, vp],
         "firal_destroy": [vp],
         "firal_hvp": [vp, vp, i64, dbl, vp, vp, i32, vp],
+        "firal_hvp_noalloc": [vp, vp, i64, i32, i32, vp, dbl, vp, vp, i32, vp],
         "firal_build_precond": [vp, vp, dbl, vp, vp, pinfo, vp],
         "firal_pcg_solve": [vp, vp, dbl, vp, vp, vp, i32, dbl, i32, u32, pinfo, vp],
         "firal_grad_z": [vp, vp, vp, i32, vp, vp],

@@ -87,6 +87,18 @@ def test_calls_reject_null_context():
     assert lib.firal_destroy(None) == _lib.OK
 
 
+def test_noalloc_product_refuses_before_any_device_call():
+    # argument errors and partial sums beyond the fixed device array are found on the host
+    lib = _lib.load()
+    assert lib.firal_hvp_noalloc(None, 1, 10, 8, 3, None, 0.0, 1, 2, 1, None) == _lib.EINVAL
+    assert lib.firal_hvp_noalloc(1, 1, 10, 8, 3, None, 0.0, 1, 1, 1, None) == _lib.EINVAL
+    assert lib.firal_hvp_noalloc(1, 1, 10, 200, 3, None, 0.0, 1, 2, 1, None) == _lib.ENOTSUP
+    # d = 128, c = 128: one probe per tile, so s = 4096 probes need 4096 x 128 x 128 floats
+    rc = lib.firal_hvp_noalloc(1, 1, 100000, 128, 128, None, 0.0, 1, 2, 4096, None)
+    assert rc == _lib.EINVAL
+    assert "fixed device array" in lib.firal_last_error().decode()
+
+
 def test_default_beta0_is_the_entropic_mirror_descent_step():
     # sqrt(2 ln n / T) (host arithmetic only; no device needed)
     import math
