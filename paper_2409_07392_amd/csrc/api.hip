@@ -262,7 +262,7 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   if (x->use_nt) {
     x->ldn = nt_ld(x->N);
     const int64_t ldg = nt_ld(rows), nw = nt_windows(c);
-    ALLOC(x->XTf, x->ldn * d * 4);
+    if (prec == FIRAL_F32) ALLOC(x->XTf, x->ldn * d * 4);
     ALLOC(x->HTf, x->ldn * c * 4);
     ALLOC(x->VTf, blk * 4);
     ALLOC(x->ntpart, ((int64_t)s_max * nw * ldg + (int64_t)s_max * ldg) * 4);

@@ -74,8 +74,10 @@ __device__ __forceinline__ void nt_load(const float* __restrict__ src, int64_t l
   for (int t = 0; t < 4; ++t) {
     const int e = tid + kNtWG * t, rr = e >> 3, kk = 4 * (e & 7);
     const int64_t row = row0 + rr, k = k0 + kk;
-    v[t] = (row < nrow && k < nk) ? *reinterpret_cast<const f4*>(src + row * ld + k)
-                                  : f4{0.f, 0.f, 0.f, 0.f};
+    const bool ok = row < nrow && k < nk;
+    // out-of-range lanes read row 0, k 0 (valid) and keep zero
+    const f4 l = *reinterpret_cast<const f4*>(src + (ok ? row * ld + k : 0));
+    v[t] = ok ? l : f4{0.f, 0.f, 0.f, 0.f};
   }
 }
 __device__ __forceinline__ void nt_store(float* __restrict__ dst, int tid, const f4 (&v)[4]) {
@@ -86,63 +88,15 @@ __device__ __forceinline__ void nt_store(float* __restrict__ dst, int tid, const
   }
 }
 
-// Kernel 1.  Tiles: row tile rt (kNtBM rows of the chunk) x column tile ct of the flat column
-// space of s probes cut into windows of kNtBN columns per probe (nw windows each).
-__global__ __launch_bounds__(kNtWG, 2) void k_nt_xv(
-    const float* __restrict__ X, int d, int64_t R, const float* __restrict__ VT, int c, int nw,
-    int ntc, const float* __restrict__ HT, int64_t ldh, const double* __restrict__ omega,
-    float* __restrict__ GT, int64_t ldg, float* __restrict__ apart, Skip skip) {
-  if (skip_now(skip)) return;
-  extern __shared__ __align__(16) float nt_lds[];
-  float* As = nt_lds;                          // [2][kNtBM][kNtSK]
-  float* Bs = nt_lds + 2 * kNtBM * kNtSK;      // [2][kNtBN][kNtSK]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, g = lane >> 4;
-  // tiles in groups of 8 row tiles: consecutive logical ids take the 8 row tiles of a group for
-  // one column tile, then the next column tile, so that 64 workgroups resident on one XCD share
-  // 8 tiles of X and 8 of V^T in its L2 (the last group may hold fewer row tiles)
-  const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
-  const int64_t nrt = (R + kNtBM - 1) / kNtBM;
-  const int64_t grp = lid / (8 * (int64_t)ntc);
-  const int64_t g0 = grp * 8;
-  const int64_t gsz = nrt - g0 < 8 ? nrt - g0 : 8;
-  const int64_t in = lid - grp * 8 * (int64_t)ntc;
-  const int ct = (int)(in / gsz);
-  const int64_t rt = g0 + (in - (int64_t)ct * gsz);
-  const int p = ct / nw, w = ct - p * nw;
-  const int64_t row0 = rt * kNtBM;
-  const int col0 = w * kNtBN;                              // within the probe
-  const int width = c - col0 < kNtBN ? c - col0 : kNtBN;  // columns of the window
-  const int64_t n0 = (int64_t)p * c + col0;                // first column of V^T
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-
-  f32x4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-  f4 ra[4], rb[4];
-  const int nst = (d + kNtKS - 1) / kNtKS;
-  nt_load(X, d, row0, R, 0, d, tid, ra);
-  nt_load(VT + n0 * d, d, 0, width, 0, d, tid, rb);
-  nt_store(As, tid, ra);
-  nt_store(Bs, tid, rb);
-  __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int buf = st & 1;
-    if (st + 1 < nst) {
-      nt_load(X, d, row0, R, (int64_t)(st + 1) * kNtKS, d, tid, ra);
-      nt_load(VT + n0 * d, d, 0, width, (int64_t)(st + 1) * kNtKS, d, tid, rb);
-    }
-    nt_stage(As + buf * kNtBM * kNtSK, Bs + buf * kNtBN * kNtSK, wm, wn, li, g, acc);
-    if (st + 1 < nst) {
-      nt_store(As + (buf ^ 1) * kNtBM * kNtSK, tid, ra);
-      nt_store(Bs + (buf ^ 1) * kNtBN * kNtSK, tid, rb);
-    }
-    __syncthreads();
-  }
-
+// Epilogue of the first contraction (both forms).
+__device__ __forceinline__ void nt_xv_epilogue(const f32x4 (&acc)[4][4], float* nt_lds, int wave,
+                                               int wm, int wn, int li, int g, int tid,
+                                               int64_t row0, int64_t R, int width, int col0,
+                                               int64_t n0, int p, int w, int nw,
+                                               const float* __restrict__ HT, int64_t ldh,
+                                               const double* __restrict__ omega,
+                                               float* __restrict__ GT, int64_t ldg,
+                                               float* __restrict__ apart) {
   // Epilogue.  Lane (g, li) of block (i, j) holds G[r][n] for r = row0 + wm + 16 i + 4 g + v,
   // n = col0 + wn + 16 j + li (v = 0..3).  (1) E^T = (omega G)^T as 16-byte stores of four rows;
   // (2) per row the sum over this wave's columns of E h, then over the 16 lanes of a column
@@ -196,6 +150,90 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt_xv(
   }
 }
 
+// Epilogue of the second contraction (both forms): the split's partial output block.
+__device__ __forceinline__ void nt_xtg_epilogue(const f32x4 (&acc)[4][4], float* __restrict__ part,
+                                                int sp, int64_t part_stride, int a0, int n0,
+                                                int n_end, int wm, int wn, int li, int g, int d,
+                                                int SC, int accumulate) {
+  float* out = part + (int64_t)sp * part_stride;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int a = a0 + wm + 16 * i + 4 * g + v;
+        const int n = n0 + wn + 16 * j + li;
+        if (a < d && n < n_end) {
+          const int64_t o = (int64_t)a * SC + n;
+          out[o] = accumulate ? out[o] + acc[i][j][v] : acc[i][j][v];
+        }
+      }
+}
+
+// Kernel 1.  Tiles: row tile rt (kNtBM rows of the chunk) x column tile ct: the column windows
+// of kNtBN columns of s probes (nw windows each), tile ct = window (ct / s) of probe (ct % s).
+__global__ __launch_bounds__(kNtWG, 2) void k_nt_xv(
+    const float* __restrict__ X, int d, int64_t R, const float* __restrict__ VT, int c, int nw,
+    int ntc, const float* __restrict__ HT, int64_t ldh, const double* __restrict__ omega,
+    float* __restrict__ GT, int64_t ldg, float* __restrict__ apart, Skip skip) {
+  if (skip_now(skip)) return;
+  extern __shared__ __align__(16) float nt_lds[];
+  float* As = nt_lds;                          // [2][kNtBM][kNtSK]
+  float* Bs = nt_lds + 2 * kNtBM * kNtSK;      // [2][kNtBN][kNtSK]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  // tiles in groups of 8 row tiles: consecutive logical ids take the 8 row tiles of a group for
+  // one column tile, then the next column tile, so that 64 workgroups resident on one XCD share
+  // 8 tiles of X and 8 of V^T in its L2 (the last group may hold fewer row tiles)
+  const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
+  const int64_t nrt = (R + kNtBM - 1) / kNtBM;
+  const int64_t grp = lid / (8 * (int64_t)ntc);
+  const int64_t g0 = grp * 8;
+  const int64_t gsz = nrt - g0 < 8 ? nrt - g0 : 8;
+  const int64_t in = lid - grp * 8 * (int64_t)ntc;
+  const int ct = (int)(in / gsz);
+  const int64_t rt = g0 + (in - (int64_t)ct * gsz);
+  // column tiles with the probe fastest: consecutive tiles share the window's classes (h)
+  const int ns = ntc / nw;
+  const int w = ct / ns, p = ct - w * ns;
+  const int64_t row0 = rt * kNtBM;
+  const int col0 = w * kNtBN;                              // within the probe
+  const int width = c - col0 < kNtBN ? c - col0 : kNtBN;  // columns of the window
+  const int64_t n0 = (int64_t)p * c + col0;                // first column of V^T
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  f4 ra[4], rb[4];
+  const int nst = (d + kNtKS - 1) / kNtKS;
+  nt_load(X, d, row0, R, 0, d, tid, ra);
+  nt_load(VT + n0 * d, d, 0, width, 0, d, tid, rb);
+  nt_store(As, tid, ra);
+  nt_store(Bs, tid, rb);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) {
+      nt_load(X, d, row0, R, (int64_t)(st + 1) * kNtKS, d, tid, ra);
+      nt_load(VT + n0 * d, d, 0, width, (int64_t)(st + 1) * kNtKS, d, tid, rb);
+    }
+    nt_stage(As + buf * kNtBM * kNtSK, Bs + buf * kNtBN * kNtSK, wm, wn, li, g, acc);
+    if (st + 1 < nst) {
+      nt_store(As + (buf ^ 1) * kNtBM * kNtSK, tid, ra);
+      nt_store(Bs + (buf ^ 1) * kNtBN * kNtSK, tid, rb);
+    }
+    __syncthreads();
+  }
+
+  nt_xv_epilogue(acc, nt_lds, wave, wm, wn, li, g, tid, row0, R, width, col0, n0, p, w, nw, HT,
+                 ldh, omega, GT, ldg, apart);
+}
+
 // beta[p][r] = sum_w beta_part[p][w][r] in FP64, fixed order (= omega_r alpha_rp).
 __global__ __launch_bounds__(256) void k_nt_alpha(const float* __restrict__ apart, int nw, int s,
                                                   int64_t R, int64_t ldg,
@@ -210,20 +248,22 @@ __global__ __launch_bounds__(256) void k_nt_alpha(const float* __restrict__ apar
   beta[(int64_t)p * ldg + r] = (float)a;
 }
 
-// E^T and h of four consecutive columns nb .. nb + 3 (nvalid of them valid; the class of nb is
-// k_first) at rows r .. r + 3 (zero when r >= re).
+// E^T and h of four consecutive columns nb .. nb + 3 of one window (nvalid of them valid; the
+// class of nb is k_first) at rows r .. r + 3 (zero when r >= re).  Addresses are clamped into the
+// valid columns and rows (r0 is a valid row) so that no lane forms an address outside them.
 __device__ __forceinline__ void nt_load_e(const float* __restrict__ GT, int64_t ldg,
                                           const float* __restrict__ HT, int64_t ldh, int nb,
-                                          int nvalid, int k_first, int c, int64_t r, int64_t re,
-                                          f4 (&gv)[4], f4 (&hv)[4]) {
+                                          int nvalid, int k_first, int64_t r, int64_t re,
+                                          int64_t r0, f4 (&gv)[4], f4 (&hv)[4]) {
+  const int64_t rr = r < re ? r : r0;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    int k = k_first + t;
-    if (k >= c) k -= c;   // the next probe's first classes
+    const int tt = t < nvalid ? t : 0;
     const bool ok = t < nvalid && r < re;
-    gv[t] = ok ? *reinterpret_cast<const f4*>(GT + (int64_t)(nb + t) * ldg + r)
-               : f4{0.f, 0.f, 0.f, 0.f};
-    hv[t] = ok ? *reinterpret_cast<const f4*>(HT + (int64_t)k * ldh + r) : f4{0.f, 0.f, 0.f, 0.f};
+    const f4 gl = *reinterpret_cast<const f4*>(GT + (int64_t)(nb + tt) * ldg + rr);
+    const f4 hl = *reinterpret_cast<const f4*>(HT + (int64_t)(k_first + tt) * ldh + rr);
+    gv[t] = ok ? gl : f4{0.f, 0.f, 0.f, 0.f};
+    hv[t] = ok ? hl : f4{0.f, 0.f, 0.f, 0.f};
   }
 }
 // G'^T = (E^T - beta[p]) h of the four columns into the LDS tile b[n][k] (rows at or beyond re
@@ -234,8 +274,11 @@ __device__ __forceinline__ void nt_store_g(float* __restrict__ b, int tid, int64
                                            const f4 (&hv)[4]) {
   const bool rok = r < re;   // re is a multiple of 4 except at the end of the rows
   const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-  const f4 b_lo = rok ? *reinterpret_cast<const f4*>(beta + (int64_t)p_lo * ldg + r) : z4;
-  const f4 b_hi = rok ? *reinterpret_cast<const f4*>(beta + (int64_t)p_hi * ldg + r) : z4;
+  const int64_t rr = rok ? r : 0;
+  const f4 bl_ = *reinterpret_cast<const f4*>(beta + (int64_t)p_lo * ldg + rr);
+  const f4 bh_ = *reinterpret_cast<const f4*>(beta + (int64_t)p_hi * ldg + rr);
+  const f4 b_lo = rok ? bl_ : z4;
+  const f4 b_hi = rok ? bh_ : z4;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const f4 bt = (nb + t) / c == p_lo ? b_lo : b_hi;
@@ -246,16 +289,16 @@ __device__ __forceinline__ void nt_store_g(float* __restrict__ b, int tid, int64
   }
 }
 
-// Kernel 2.  Output tiles: a-tile mt (kNtBM values of a) x column tile ct (kNtBN flat columns),
-// split sp of the chunk's rows.  B is staged as G'^T[n][r] = (E^T[n][r] - beta[p][r]) h_rk with
+// Kernel 2.  Output tiles: a-tile mt (kNtBM values of a) x column tile ct (a column window of one
+// probe, as in kernel 1), split sp of the chunk's rows.  B is staged as G'^T[n][r] = (E^T[n][r] - beta[p][r]) h_rk with
 // p = n / c, k = n % c.  Thread tid stages columns n0 + 4 (tid / 8) + t, t = 0..3, at rows
 // 4 (tid % 8) of the stage: E^T and h are fetched before the stage's products, beta (at most two
 // probes among four consecutive columns) after them.
 __global__ __launch_bounds__(kNtWG, 2) void k_nt_xtg(
     const float* __restrict__ XT, int64_t ldx, int d, const float* __restrict__ GT, int64_t ldg,
-    int SC, int c, const float* __restrict__ HT, int64_t ldh, const float* __restrict__ beta,
-    int64_t R, int64_t rows_per_split, int nmt, int nct, float* __restrict__ part,
-    int64_t part_stride, int accumulate, Skip skip) {
+    int SC, int c, int nw, const float* __restrict__ HT, int64_t ldh,
+    const float* __restrict__ beta, int64_t R, int64_t rows_per_split, int nmt, int nct,
+    float* __restrict__ part, int64_t part_stride, int accumulate, Skip skip) {
   if (skip_now(skip)) return;
   extern __shared__ __align__(16) float nt_lds[];
   float* As = nt_lds;
@@ -267,7 +310,13 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt_xtg(
   const int64_t rest = lid / nmt;
   const int ct = (int)(rest % nct);
   const int sp = (int)(rest / nct);
-  const int a0 = mt * kNtBM, n0 = ct * kNtBN;
+  // column tiles are windows of one probe (probe fastest, as in the first contraction)
+  const int ns = nct / nw;
+  const int w = ct / ns, p = ct - w * ns;
+  const int col0w = w * kNtBN;
+  const int width = c - col0w < kNtBN ? c - col0w : kNtBN;
+  const int a0 = mt * kNtBM;
+  const int n0 = p * c + col0w;
   const int64_t rb = (int64_t)sp * rows_per_split;
   const int64_t re = rb + rows_per_split < R ? rb + rows_per_split : R;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -280,18 +329,20 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt_xtg(
 
   // B staging: columns nb + t (t = 0..3) at rows 4 (tid % 8) of the stage; the columns' probes
   // (the first and last of the four may differ), classes and validity are fixed per thread
-  const int nb = n0 + 4 * (tid >> 3);
+  const int jl = 4 * (tid >> 3);               // first of the thread's columns in the window
+  const int nb = n0 + jl;
   const int rk = 4 * (tid & 7);
-  const int nvalid = SC - nb < 4 ? (SC - nb > 0 ? SC - nb : 0) : 4;
-  const int k_first = nb < SC ? nb % c : 0;
-  const int p_lo = nb < SC ? nb / c : 0;
-  const int p_hi = nb + 3 < SC ? (nb + 3) / c : p_lo;
+  const int nvalid = width - jl < 4 ? (width - jl > 0 ? width - jl : 0) : 4;
+  // with no valid column the loads are made from the window's first column (and zeroed)
+  const int nb_c = nvalid > 0 ? nb : n0;
+  const int k_first = nvalid > 0 ? col0w + jl : col0w;
+  const int p_lo = p, p_hi = p;
   f4 ra[4], gv[4], hv[4];
   const int64_t nrows = re > rb ? re - rb : 0;
   const int nst = (int)((nrows + kNtKS - 1) / kNtKS);
   if (nst > 0) {
     nt_load(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, rb, re, tid, ra);
-    nt_load_e(GT, ldg, HT, ldh, nb, nvalid, k_first, c, rb + rk, re, gv, hv);
+    nt_load_e(GT, ldg, HT, ldh, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv);
     nt_store(As, tid, ra);
     nt_store_g(Bs, tid, rb + rk, re, beta, ldg, nb, c, p_lo, p_hi, gv, hv);
   }
@@ -301,7 +352,7 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt_xtg(
     const int64_t k1 = rb + (int64_t)(st + 1) * kNtKS;
     if (st + 1 < nst) {
       nt_load(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, k1, re, tid, ra);
-      nt_load_e(GT, ldg, HT, ldh, nb, nvalid, k_first, c, k1 + rk, re, gv, hv);
+      nt_load_e(GT, ldg, HT, ldh, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv);
     }
     nt_stage(As + buf * kNtBM * kNtSK, Bs + buf * kNtBN * kNtSK, wm, wn, li, g, acc);
     if (st + 1 < nst) {
@@ -312,20 +363,275 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt_xtg(
     __syncthreads();
   }
 
-  float* out = part + (int64_t)sp * part_stride;
+  nt_xtg_epilogue(acc, part, sp, part_stride, a0, n0, n0 + width, wm, wn, li, g, d, SC,
+                  accumulate);
+}
+
+// ------------------------------------------------------------------ bf16x3 form
+// The same two contractions with every product taken as hi*hi + hi*lo + lo*hi of bf16 halves
+// (hi = bf16(x), lo = bf16(x - hi), round to nearest even) on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation.  A stage holds 32 k of each operand as two bf16 planes [row][32] (64 bytes per
+// row, four 16-byte chunks, chunk q of row m stored at chunk q ^ ((m >> 2) & 3) so that the 16
+// lanes of a fragment read fall in distinct banks).  Lane (g, li) reads k = 8 g .. 8 g + 7 of
+// row li: one 16-byte read per plane and operand feeds the three products of a block.
+// Operands: k_nt3_xv takes X from the context's hi/lo planes and V^T from planes made once per
+// call; k_nt3_xtg takes X^T from the context's transposed planes and splits G' = (E - beta) h as
+// it is staged.  The epilogues are those of the FP32 kernels.
+constexpr size_t kNt3Lds = (size_t)2 * 2 * (kNtBM + kNtBN) * 32 * 2;   // 65,536 bytes
+
+__device__ __forceinline__ bf16x8 nt3_zero8() {
+  bf16x8 z;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) z[u] = (__bf16)0.0f;
+  return z;
+}
+
+__device__ __forceinline__ int nt3_off(int plane, int row, int ch) {   // in bf16 elements
+  return (plane * kNtBM + row) * 32 + ((ch ^ ((row >> 2) & 3)) << 3);
+}
+
+// One 32-deep stage of a wave's 4 x 4 blocks from hi/lo LDS planes a[2][128][32], b[2][128][32].
+__device__ __forceinline__ void nt3_stage(const __bf16* __restrict__ a,
+                                          const __bf16* __restrict__ b, int wm, int wn, int li,
+                                          int g, f32x4 (&acc)[4][4]) {
+  bf16x8 ah[4], al[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = wm + 16 * i + li;
+    ah[i] = *reinterpret_cast<const bf16x8*>(a + nt3_off(0, row, g));
+    al[i] = *reinterpret_cast<const bf16x8*>(a + nt3_off(1, row, g));
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = wn + 16 * j + li;
+    const bf16x8 bh = *reinterpret_cast<const bf16x8*>(b + nt3_off(0, row, g));
+    const bf16x8 bl = *reinterpret_cast<const bf16x8*>(b + nt3_off(1, row, g));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i][j] = mfma3(ah[i], al[i], bh, bl, acc[i][j]);
+  }
+}
+
+// A 128 x 32 tile of two row-major bf16 planes (leading dimension ld): 512 16-byte chunks per
+// plane, two per thread: chunk e = tid + 256 t is row e / 4, k 8 (e % 4).  Rows at or beyond
+// nrow and k at or beyond nk read as zero (nk a multiple of 8).
+__device__ __forceinline__ void nt3_load(const __bf16* __restrict__ hi, const __bf16* __restrict__ lo,
+                                         int64_t ld, int64_t nrow, int64_t k0, int64_t nk, int tid,
+                                         bf16x8 (&vh)[2], bf16x8 (&vl)[2]) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int e = tid + kNtWG * t, row = e >> 2, ch = e & 3;
+    const int64_t k = k0 + 8 * ch;
+    const bool ok = row < nrow && k < nk;
+    const int64_t o = ok ? row * ld + k : 0;   // out-of-range lanes read element 0 and keep zero
+    const bf16x8 h = *reinterpret_cast<const bf16x8*>(hi + o);
+    const bf16x8 l = *reinterpret_cast<const bf16x8*>(lo + o);
+    vh[t] = ok ? h : nt3_zero8();
+    vl[t] = ok ? l : nt3_zero8();
+  }
+}
+__device__ __forceinline__ void nt3_store(__bf16* __restrict__ dst, int tid, const bf16x8 (&vh)[2],
+                                          const bf16x8 (&vl)[2]) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int e = tid + kNtWG * t, row = e >> 2, ch = e & 3;
+    *reinterpret_cast<bf16x8*>(dst + nt3_off(0, row, ch)) = vh[t];
+    *reinterpret_cast<bf16x8*>(dst + nt3_off(1, row, ch)) = vl[t];
+  }
+}
+
+__global__ __launch_bounds__(kNtWG, 2) void k_nt3_xv(
+    const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int d, int64_t R,
+    const __bf16* __restrict__ VTh, const __bf16* __restrict__ VTl, int c, int nw, int ntc,
+    const float* __restrict__ HT, int64_t ldh, const double* __restrict__ omega,
+    float* __restrict__ GT, int64_t ldg, float* __restrict__ apart, Skip skip) {
+  if (skip_now(skip)) return;
+  extern __shared__ __align__(16) float nt_lds[];
+  __bf16* As = reinterpret_cast<__bf16*>(nt_lds);      // [2 bufs][2 planes][128][32]
+  __bf16* Bs = As + 2 * 2 * kNtBM * 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
+  const int64_t nrt = (R + kNtBM - 1) / kNtBM;
+  const int64_t grp = lid / (8 * (int64_t)ntc);
+  const int64_t g0 = grp * 8;
+  const int64_t gsz = nrt - g0 < 8 ? nrt - g0 : 8;
+  const int64_t in = lid - grp * 8 * (int64_t)ntc;
+  const int ct = (int)(in / gsz);
+  const int64_t rt = g0 + (in - (int64_t)ct * gsz);
+  // column tiles with the probe fastest: consecutive tiles share the window's classes (h)
+  const int ns = ntc / nw;
+  const int w = ct / ns, p = ct - w * ns;
+  const int64_t row0 = rt * kNtBM;
+  const int col0 = w * kNtBN;
+  const int width = c - col0 < kNtBN ? c - col0 : kNtBN;
+  const int64_t n0 = (int64_t)p * c + col0;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  f32x4 acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  bf16x8 ah[2], al[2], bh[2], bl[2];
+  const __bf16* xh = Xh + row0 * d;
+  const __bf16* xl = Xl + row0 * d;
+  const __bf16* vh = VTh + n0 * d;
+  const __bf16* vl = VTl + n0 * d;
+  const int nst = (d + kNtKS - 1) / kNtKS;
+  constexpr int PL = 2 * kNtBM * 32;   // one buffer of one operand (two planes)
+  nt3_load(xh, xl, d, R - row0, 0, d, tid, ah, al);
+  nt3_load(vh, vl, d, width, 0, d, tid, bh, bl);
+  nt3_store(As, tid, ah, al);
+  nt3_store(Bs, tid, bh, bl);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) {
+      nt3_load(xh, xl, d, R - row0, (int64_t)(st + 1) * kNtKS, d, tid, ah, al);
+      nt3_load(vh, vl, d, width, (int64_t)(st + 1) * kNtKS, d, tid, bh, bl);
+    }
+    nt3_stage(As + buf * PL, Bs + buf * PL, wm, wn, li, g, acc);
+    if (st + 1 < nst) {
+      nt3_store(As + (buf ^ 1) * PL, tid, ah, al);
+      nt3_store(Bs + (buf ^ 1) * PL, tid, bh, bl);
+    }
+    __syncthreads();
+  }
+  nt_xv_epilogue(acc, nt_lds, wave, wm, wn, li, g, tid, row0, R, width, col0, n0, p, w, nw, HT,
+                 ldh, omega, GT, ldg, apart);
+}
+
+// G'^T = (E^T - beta[p]) h of four columns at rows r .. r + 3, split into hi/lo bf16 and stored
+// into the planes of the LDS tile (row 4 (tid / 8) + t, k 4 (tid % 8)).
+__device__ __forceinline__ void nt3_store_g(__bf16* __restrict__ b, int tid, int64_t r, int64_t re,
+                                            const float* __restrict__ beta, int64_t ldg, int nb,
+                                            int c, int p_lo, int p_hi, const f4 (&gv)[4],
+                                            const f4 (&hv)[4]) {
+  const bool rok = r < re;
+  const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+  const int64_t rr = rok ? r : 0;
+  const f4 bl_ = *reinterpret_cast<const f4*>(beta + (int64_t)p_lo * ldg + rr);
+  const f4 bh_ = *reinterpret_cast<const f4*>(beta + (int64_t)p_hi * ldg + rr);
+  const f4 b_lo = rok ? bl_ : z4;
+  const f4 b_hi = rok ? bh_ : z4;
+  const int kq = 4 * (tid & 7);              // k offset of the four rows within the stage
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = a0 + wm + 16 * i + 4 * g + v;
-        const int n = n0 + wn + 16 * j + li;
-        if (a < d && n < SC) {
-          const int64_t o = (int64_t)a * SC + n;
-          out[o] = accumulate ? out[o] + acc[i][j][v] : acc[i][j][v];
-        }
-      }
+  for (int t = 0; t < 4; ++t) {
+    const f4 bt = (nb + t) / c == p_lo ? b_lo : b_hi;
+    bf16x4 h4, l4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float x = r + v < re ? (gv[t][v] - bt[v]) * hv[t][v] : 0.f;
+      const __bf16 h = (__bf16)x;
+      h4[v] = h;
+      l4[v] = (__bf16)(x - (float)h);
+    }
+    const int row = 4 * (tid >> 3) + t;
+    *reinterpret_cast<bf16x4*>(b + nt3_off(0, row, kq >> 3) + (kq & 4)) = h4;
+    *reinterpret_cast<bf16x4*>(b + nt3_off(1, row, kq >> 3) + (kq & 4)) = l4;
+  }
+}
+
+__global__ __launch_bounds__(kNtWG, 2) void k_nt3_xtg(
+    const __bf16* __restrict__ XTh, const __bf16* __restrict__ XTl, int64_t ldx, int d,
+    const float* __restrict__ GT, int64_t ldg, int SC, int c, int nw, const float* __restrict__ HT,
+    int64_t ldh, const float* __restrict__ beta, int64_t R, int64_t rows_per_split, int nmt,
+    int nct, float* __restrict__ part, int64_t part_stride, int accumulate, Skip skip) {
+  if (skip_now(skip)) return;
+  extern __shared__ __align__(16) float nt_lds[];
+  __bf16* As = reinterpret_cast<__bf16*>(nt_lds);
+  __bf16* Bs = As + 2 * 2 * kNtBM * 32;
+  constexpr int PL = 2 * kNtBM * 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
+  const int mt = (int)(lid % nmt);
+  const int64_t rest = lid / nmt;
+  const int ct = (int)(rest % nct);
+  const int sp = (int)(rest / nct);
+  // column tiles are windows of one probe (probe fastest, as in the first contraction)
+  const int ns = nct / nw;
+  const int w = ct / ns, p = ct - w * ns;
+  const int col0w = w * kNtBN;
+  const int width = c - col0w < kNtBN ? c - col0w : kNtBN;
+  const int a0 = mt * kNtBM;
+  const int n0 = p * c + col0w;
+  const int64_t rb = (int64_t)sp * rows_per_split;
+  const int64_t re = rb + rows_per_split < R ? rb + rows_per_split : R;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int jl = 4 * (tid >> 3);               // first of the thread's columns in the window
+  const int nb = n0 + jl;
+  const int rk = 4 * (tid & 7);
+  const int nvalid = width - jl < 4 ? (width - jl > 0 ? width - jl : 0) : 4;
+  // with no valid column the loads are made from the window's first column (and zeroed)
+  const int nb_c = nvalid > 0 ? nb : n0;
+  const int k_first = nvalid > 0 ? col0w + jl : col0w;
+  const int p_lo = p, p_hi = p;
+  bf16x8 ah[2], al[2];
+  f4 gv[4], hv[4];
+  const __bf16* xh = XTh + (int64_t)a0 * ldx;
+  const __bf16* xl = XTl + (int64_t)a0 * ldx;
+  const int64_t nrows = re > rb ? re - rb : 0;
+  const int nst = (int)((nrows + kNtKS - 1) / kNtKS);
+  // X^T rows are read 8 at a time: rows beyond re (a multiple of 8 except at the end of the
+  // pool) come from the padding or the next rows and meet zero in B
+  if (nst > 0) {
+    nt3_load(xh, xl, ldx, d - a0, rb, re, tid, ah, al);
+    nt_load_e(GT, ldg, HT, ldh, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv);
+    nt3_store(As, tid, ah, al);
+    nt3_store_g(Bs, tid, rb + rk, re, beta, ldg, nb, c, p_lo, p_hi, gv, hv);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const int64_t k1 = rb + (int64_t)(st + 1) * kNtKS;
+    if (st + 1 < nst) {
+      nt3_load(xh, xl, ldx, d - a0, k1, re, tid, ah, al);
+      nt_load_e(GT, ldg, HT, ldh, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv);
+    }
+    nt3_stage(As + buf * PL, Bs + buf * PL, wm, wn, li, g, acc);
+    if (st + 1 < nst) {
+      nt3_store(As + (buf ^ 1) * PL, tid, ah, al);
+      nt3_store_g(Bs + (buf ^ 1) * PL, tid, k1 + rk, re, beta, ldg, nb, c, p_lo, p_hi, gv, hv);
+    }
+    __syncthreads();
+  }
+  nt_xtg_epilogue(acc, part, sp, part_stride, a0, n0, n0 + width, wm, wn, li, g, d, SC,
+                  accumulate);
+}
+
+// hi/lo bf16 planes of the transpose of an rows x cols row-major FP32 source: dst[j][i] for the
+// cols x rows destination (leading dimension rows).
+__global__ __launch_bounds__(256) void k_nt3_transpose_split(const float* __restrict__ src,
+                                                             int64_t rows, int64_t cols,
+                                                             __bf16* __restrict__ dh,
+                                                             __bf16* __restrict__ dl) {
+  __shared__ float tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t i = i0 + q, j = j0 + tx;
+    tile[q][tx] = (i < rows && j < cols) ? src[i * cols + j] : 0.f;
+  }
+  __syncthreads();
+  for (int q = ty; q < 32; q += 8) {
+    const int64_t j = j0 + q, i = i0 + tx;
+    if (j < cols && i < rows) {
+      const float v = tile[tx][q];
+      const __bf16 h = (__bf16)v;
+      dh[j * rows + i] = h;
+      dl[j * rows + i] = (__bf16)(v - (float)h);
+    }
+  }
 }
 
 // dst[j][i] = src[i][j] for an rows x cols row-major source (leading dimension lds) into a
@@ -359,10 +665,13 @@ bool g_nt_attr = false;
 
 }  // namespace
 
-// The wide path covers FP32 contexts with d > 128, d % 4 == 0 and c > 128; its transposed
-// copies of X and H are made at creation when this holds.
+// The wide path covers FP32 contexts with d % 4 == 0 and bf16x3 contexts with d % 8 == 0, both
+// with d > 128 and c > 128; its transposed FP32 copies of H (and for FP32 of X; bf16x3 contexts
+// read the transposed hi/lo planes of X) are made at creation when this holds.
 bool nt_applies(const Ctx* x) {
-  return x->prec == FIRAL_F32 && x->d > 128 && x->d % 4 == 0 && x->c > kNtBN;
+  const bool form = (x->prec == FIRAL_F32 && x->d % 4 == 0) ||
+                    (x->prec == FIRAL_BF16X3 && x->d % 8 == 0);
+  return form && x->d > 128 && x->c > kNtBN;
 }
 
 int64_t nt_ld(int64_t rows) { return cdiv(rows, 4) * 4; }
@@ -371,7 +680,8 @@ int64_t nt_ld(int64_t rows) { return cdiv(rows, 4) * 4; }
 int nt_windows(int c) { return (int)cdiv(c, kNtBN); }
 
 int nt_prepare_ctx(Ctx* x, hipStream_t st) {
-  FIRAL_CHECK(nt_transpose((const float*)x->X, x->N, x->d, x->d, (float*)x->XTf, x->ldn, st));
+  if (x->prec == FIRAL_F32)
+    FIRAL_CHECK(nt_transpose((const float*)x->X, x->N, x->d, x->d, (float*)x->XTf, x->ldn, st));
   FIRAL_CHECK(nt_transpose((const float*)x->H, x->N, x->c, x->c, (float*)x->HTf, x->ldn, st));
   return FIRAL_OK;
 }
@@ -384,11 +694,24 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
                                   (int)kNtLds));
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xtg,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNtLds));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xv,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNt3Lds));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNt3Lds));
     g_nt_attr = true;
   }
-  // V^T: the probe block d x (s c) transposed to (s c) x d
+  const bool bf3 = x->prec == FIRAL_BF16X3;
+  // V^T: the probe block d x (s c) transposed to (s c) x d (bf16x3: its hi/lo planes)
   float* VT = (float*)x->VTf;
-  FIRAL_CHECK(nt_transpose(B, d, SC, SC, VT, d, st));
+  __bf16* VTh = (__bf16*)x->VTf;
+  __bf16* VTl = VTh + (int64_t)SC * d;
+  if (bf3) {
+    dim3 grid((unsigned)cdiv(d, 32), (unsigned)cdiv(SC, 32));
+    k_nt3_transpose_split<<<grid, 256, 0, st>>>(B, d, SC, VTh, VTl);
+    FIRAL_LAUNCHED();
+  } else {
+    FIRAL_CHECK(nt_transpose(B, d, SC, SC, VT, d, st));
+  }
   // buffers: E^T [s c][ldg], beta_part [s][nw][ldg], beta [s][ldg]
   const int64_t ldg = nt_ld(x->chunk_rows);
   float* GT = (float*)x->G;
@@ -396,7 +719,7 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
   float* beta = apart + (int64_t)s * nw * ldg;
   float* part = (float*)x->part;
   const int64_t n_out = (int64_t)d * SC;
-  const int nmt = (int)cdiv(d, kNtBM), nct = (int)cdiv(SC, kNtBN);
+  const int nmt = (int)cdiv(d, kNtBM), nct = s * nw;   // column windows of every probe
   const int64_t tiles = (int64_t)nmt * nct;
   const int64_t cap = (int64_t)x->max_splits * x->s_max / s;
   const int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(4096, tiles), cap), 256));
@@ -405,10 +728,18 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
     const int64_t R = std::min<int64_t>(x->chunk_rows, n_rows - r0);
     hipEvent_t e0, e1;
     FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT, &e0, &e1));
-    hipExtLaunchKernelGGL(k_nt_xv, dim3((unsigned)(cdiv(R, kNtBM) * ntc)), dim3(kNtWG),
-                          (uint32_t)kNtLds, st, e0, e1, 0u, (const float*)x->X + r0 * d, d, R,
-                          (const float*)VT, c, nw, ntc, (const float*)x->HTf + r0, x->ldn,
-                          omega ? omega + r0 : nullptr, GT, ldg, apart, skip);
+    const dim3 grid1((unsigned)(cdiv(R, kNtBM) * ntc));
+    if (bf3)
+      hipExtLaunchKernelGGL(k_nt3_xv, grid1, dim3(kNtWG), (uint32_t)kNt3Lds, st, e0, e1, 0u,
+                            (const __bf16*)x->Xhi + r0 * d, (const __bf16*)x->Xlo + r0 * d, d, R,
+                            (const __bf16*)VTh, (const __bf16*)VTl, c, nw, ntc,
+                            (const float*)x->HTf + r0, x->ldn, omega ? omega + r0 : nullptr, GT,
+                            ldg, apart, skip);
+    else
+      hipExtLaunchKernelGGL(k_nt_xv, grid1, dim3(kNtWG), (uint32_t)kNtLds, st, e0, e1, 0u,
+                            (const float*)x->X + r0 * d, d, R, (const float*)VT, c, nw, ntc,
+                            (const float*)x->HTf + r0, x->ldn, omega ? omega + r0 : nullptr, GT,
+                            ldg, apart, skip);
     FIRAL_LAUNCHED();
     k_nt_alpha<<<(unsigned)cdiv((int64_t)s * R, 256), 256, 0, st>>>(apart, nw, s, R, ldg, beta,
                                                                      skip);
@@ -416,10 +747,18 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
     // splits start on multiples of 32 rows (the stage depth)
     const int64_t rps = cdiv(cdiv(R, S), kNtKS) * kNtKS;
     FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT_T, &e0, &e1));
-    hipExtLaunchKernelGGL(k_nt_xtg, dim3((unsigned)(tiles * S)), dim3(kNtWG), (uint32_t)kNtLds,
-                          st, e0, e1, 0u, (const float*)x->XTf + r0, x->ldn, d, (const float*)GT,
-                          ldg, SC, c, (const float*)x->HTf + r0, x->ldn, (const float*)beta,
-                          R, rps, nmt, nct, part, n_out, (int)(r0 > 0), skip);
+    const dim3 grid2((unsigned)(tiles * S));
+    if (bf3)
+      hipExtLaunchKernelGGL(k_nt3_xtg, grid2, dim3(kNtWG), (uint32_t)kNt3Lds, st, e0, e1, 0u,
+                            (const __bf16*)x->XThi + r0, (const __bf16*)x->XTlo + r0, x->ldt, d,
+                            (const float*)GT, ldg, SC, c, nw, (const float*)x->HTf + r0, x->ldn,
+                            (const float*)beta, R, rps, nmt, nct, part, n_out, (int)(r0 > 0),
+                            skip);
+    else
+      hipExtLaunchKernelGGL(k_nt_xtg, grid2, dim3(kNtWG), (uint32_t)kNtLds, st, e0, e1, 0u,
+                            (const float*)x->XTf + r0, x->ldn, d, (const float*)GT, ldg, SC, c,
+                            nw, (const float*)x->HTf + r0, x->ldn, (const float*)beta, R, rps,
+                            nmt, nct, part, n_out, (int)(r0 > 0), skip);
     FIRAL_LAUNCHED();
   }
   return reduce_parts_launch<float>(part, n_out, n_rows > 0 ? S : 0, shift, B, out, skip, st);

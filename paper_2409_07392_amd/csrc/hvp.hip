@@ -72,7 +72,8 @@ int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const 
       plan.part_elems <= x->fused_part_elems)
     return hvp_fused_launch(x, plan, omega, n_rows, shift, (const float*)B, (float*)out, s, skip,
                             st);
-  if (x->use_nt && !x->force_tiled)
+  // the wide path's bf16x3 context has no FP32 X^T: its FP32 products (precise) stay row-tiled
+  if (x->use_nt && !x->force_tiled && !(x->prec == FIRAL_BF16X3 && precise))
     return hvp_nt_launch(x, omega, n_rows, shift, (const float*)B, (float*)out, s, skip, st);
   return hvp_tiled_launch(x, omega, n_rows, shift, B, out, s, skip, st, precise);
 }

@@ -546,3 +546,50 @@ def test_wide_fp32_relax_step_matches_oracle():
     print(f"wide FP32 Relax step at 12 CG iterations: gradient rel err {e:.2e}")
     assert e <= TOL["f32"], e
     assert relerr(host(w), wr) <= TOL["f32"]
+
+
+NT3_SHAPES = [  # n_pool, n_lab, d, c, s, chunk rows: d a multiple of 8 for the bf16x3 form
+    (1500, 10, 384, 1000, 2, None),
+    (900, 7, 136, 129, 3, None),
+    (777, 3, 264, 300, 5, "320"),
+    (2050, 14, 136, 257, 1, "100"),
+]
+
+
+@pytest.mark.parametrize("shape", NT3_SHAPES)
+def test_wide_bf16x3_product_matches_oracle(shape, monkeypatch):
+    # the bf16x3 form of the wide path (X from the context's hi/lo planes in both layouts, V^T
+    # split once per call, G' split while staged) at the bf16x3 bar
+    n, nl, d, c, s, chunk = shape
+    if chunk:
+        monkeypatch.setenv("FIRAL_CHUNK_ROWS", chunk)
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=36, whiten_x=True, probs="maxprob")
+    X = rounded(p.X, "f32")
+    H = rounded(p.H, "f32")
+    ctx = RelaxContext(dev(X, torch.float32), dev(H, torch.float32), p.n_pool, s, "bf16x3")
+    rng = np.random.default_rng(37)
+    B = rounded(rng.standard_normal((d, s, c)), "f32")
+    om = rng.uniform(0.0, 2.0, p.N)
+    got = host(ctx.hvp(dev(B, torch.float32), omega=dev(om, torch.float64), shift=0.5))
+    e = relerr(got, orc.hvp(X, H, om, 0.5, B))
+    assert e <= BF3_TOL, ("hvp", shape, e)
+    got = host(ctx.hvp(dev(B, torch.float32), n_rows=n))
+    e = relerr(got, orc.hvp(X[:n], H[:n], None, 0.0, B))
+    print(f"wide bf16x3 {shape}: H_p rel err {e:.2e}")
+    assert e <= BF3_TOL, ("H_p", shape, e)
+
+
+def test_wide_bf16x3_relax_step_matches_oracle():
+    p = make_small(n=2000, n_lab=9, d=136, c=130, s=3, seed=38, whiten_x=True, probs="maxprob")
+    X = rounded(p.X, "f32")
+    H = rounded(p.H, "f32")
+    ctx = RelaxContext(dev(X, torch.float32), dev(H, torch.float32), p.n_pool, p.s, "bf16x3")
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(w)
+    info = ctx.relax_step(w, 20.0, 1e-3, 0.4, 7, 1, p.s, 0.0, 12, project=True, g_out=g)
+    assert info["cg_iters"] == (12, 12)
+    wr, ir = orc.relax_iteration(X, H, p.n_pool, np.full(p.n_pool, 1.0 / p.n_pool), 20.0, 1e-3,
+                                 0.4, 7, 1, p.s, 0.0, 12, project=True)
+    e = relerr(host(g), ir["g"])
+    print(f"wide bf16x3 Relax step at 12 CG iterations: gradient rel err {e:.2e}")
+    assert e <= BF3_TOL, e
