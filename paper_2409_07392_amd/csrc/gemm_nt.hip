@@ -29,11 +29,15 @@ namespace firal {
 namespace {
 
 constexpr int kNtBM = 128, kNtBN = 128;   // workgroup tile (rows x columns of the output)
-constexpr int kNtKS = 32;                 // k per pipeline stage
-constexpr int kNtSK = kNtKS + 4;          // LDS row stride in floats (16-byte reads spread over
-                                          // all banks: rows 36 floats apart)
+constexpr int kNtKS = 32;                 // k per pipeline stage of the bf16x3 kernels and the
+                                          // row granule of the row splits
 constexpr int kNtWG = 256;                // four waves, 2 x 2, each 64 x 64
-constexpr size_t kNtLds = (size_t)2 * (kNtBM + kNtBN) * kNtSK * 4;   // 73,728 bytes
+// FP32 stage depths and workgroups per CU: the first contraction runs 16-deep stages at three
+// workgroups per CU (measured 4.0 ms a launch against 4.25 ms with 32-deep stages at two); the
+// second, whose staging also applies beta and h, runs faster with 32-deep stages at two
+// (4.69 ms against 5.05 ms with 16-deep stages at three).
+constexpr int kNtKsXv = 16, kNtMinbXv = 3;
+constexpr int kNtKsXtg = 32, kNtMinbXtg = 2;
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -43,18 +47,27 @@ __device__ __forceinline__ int64_t nt_lid(int64_t b, int64_t n) {
   return x * q + (x < r ? x : r) + i;
 }
 
-// One 32-deep stage of a wave's 4 x 4 blocks of 16 x 16 from LDS tiles a[m][k], b[n][k].
+// FP32 stages of KS = 16 or 32 k: LDS rows KS + 4 floats apart (16-byte reads of a fragment
+// spread over all banks); two buffers of 128 + 128 rows.
+template <int KS> constexpr int nt_sk() { return KS + 4; }
+template <int KS> constexpr size_t nt_lds_bytes() {
+  return (size_t)2 * (kNtBM + kNtBN) * nt_sk<KS>() * 4;
+}
+
+// One KS-deep stage of a wave's 4 x 4 blocks of 16 x 16 from LDS tiles a[m][k], b[n][k].
+template <int KS>
 __device__ __forceinline__ void nt_stage(const float* __restrict__ a, const float* __restrict__ b,
                                          int wm, int wn, int li, int g, f32x4 (&acc)[4][4]) {
+  constexpr int SK = nt_sk<KS>();
 #pragma unroll
-  for (int kg = 0; kg < kNtKS / 16; ++kg) {
+  for (int kg = 0; kg < KS / 16; ++kg) {
     f4 av[4], bv[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      av[i] = *reinterpret_cast<const f4*>(a + (wm + 16 * i + li) * kNtSK + 16 * kg + 4 * g);
+      av[i] = *reinterpret_cast<const f4*>(a + (wm + 16 * i + li) * SK + 16 * kg + 4 * g);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      bv[j] = *reinterpret_cast<const f4*>(b + (wn + 16 * j + li) * kNtSK + 16 * kg + 4 * g);
+      bv[j] = *reinterpret_cast<const f4*>(b + (wn + 16 * j + li) * SK + 16 * kg + 4 * g);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -65,14 +78,17 @@ __device__ __forceinline__ void nt_stage(const float* __restrict__ a, const floa
   }
 }
 
-// Tile loads: a 128 x 32 tile of a row-major source (leading dimension ld, k contiguous) as
-// 1024 16-byte vectors, four per thread: vector e = tid + 256 t covers row e / 8, k 4 (e % 8).
-// Rows at or beyond nrow and k at or beyond nk read as zero (nk is a multiple of 4).
+// Tile loads: a 128 x KS tile of a row-major source (leading dimension ld, k contiguous) as
+// 16-byte vectors, KS / 8 per thread: vector e = tid + 256 t covers row e / (KS / 4), k 4 (e %
+// (KS / 4)).  Rows at or beyond nrow and k at or beyond nk read as zero (nk a multiple of 4).
+template <int KS>
 __device__ __forceinline__ void nt_load(const float* __restrict__ src, int64_t ld, int64_t row0,
-                                        int64_t nrow, int64_t k0, int64_t nk, int tid, f4 (&v)[4]) {
+                                        int64_t nrow, int64_t k0, int64_t nk, int tid,
+                                        f4 (&v)[KS / 8]) {
+  constexpr int VR = KS / 4;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int e = tid + kNtWG * t, rr = e >> 3, kk = 4 * (e & 7);
+  for (int t = 0; t < KS / 8; ++t) {
+    const int e = tid + kNtWG * t, rr = e / VR, kk = 4 * (e % VR);
     const int64_t row = row0 + rr, k = k0 + kk;
     const bool ok = row < nrow && k < nk;
     // out-of-range lanes read row 0, k 0 (valid) and keep zero
@@ -80,11 +96,13 @@ __device__ __forceinline__ void nt_load(const float* __restrict__ src, int64_t l
     v[t] = ok ? l : f4{0.f, 0.f, 0.f, 0.f};
   }
 }
-__device__ __forceinline__ void nt_store(float* __restrict__ dst, int tid, const f4 (&v)[4]) {
+template <int KS>
+__device__ __forceinline__ void nt_store(float* __restrict__ dst, int tid, const f4 (&v)[KS / 8]) {
+  constexpr int VR = KS / 4;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int e = tid + kNtWG * t, rr = e >> 3, kk = 4 * (e & 7);
-    *reinterpret_cast<f4*>(dst + rr * kNtSK + kk) = v[t];
+  for (int t = 0; t < KS / 8; ++t) {
+    const int e = tid + kNtWG * t, rr = e / VR, kk = 4 * (e % VR);
+    *reinterpret_cast<f4*>(dst + rr * nt_sk<KS>() + kk) = v[t];
   }
 }
 
@@ -173,14 +191,16 @@ __device__ __forceinline__ void nt_xtg_epilogue(const f32x4 (&acc)[4][4], float*
 
 // Kernel 1.  Tiles: row tile rt (kNtBM rows of the chunk) x column tile ct: the column windows
 // of kNtBN columns of s probes (nw windows each), tile ct = window (ct / s) of probe (ct % s).
-__global__ __launch_bounds__(kNtWG, 2) void k_nt_xv(
+template <int KS, int MINB>
+__global__ __launch_bounds__(kNtWG, MINB) void k_nt_xv(
     const float* __restrict__ X, int d, int64_t R, const float* __restrict__ VT, int c, int nw,
     int ntc, const float* __restrict__ HT, int64_t ldh, const double* __restrict__ omega,
     float* __restrict__ GT, int64_t ldg, float* __restrict__ apart, Skip skip) {
   if (skip_now(skip)) return;
   extern __shared__ __align__(16) float nt_lds[];
-  float* As = nt_lds;                          // [2][kNtBM][kNtSK]
-  float* Bs = nt_lds + 2 * kNtBM * kNtSK;      // [2][kNtBN][kNtSK]
+  constexpr int SK = nt_sk<KS>();
+  float* As = nt_lds;                          // [2][kNtBM][SK]
+  float* Bs = nt_lds + 2 * kNtBM * SK;         // [2][kNtBN][SK]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   // tiles in groups of 8 row tiles: consecutive logical ids take the 8 row tiles of a group for
@@ -209,23 +229,23 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt_xv(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  f4 ra[4], rb[4];
-  const int nst = (d + kNtKS - 1) / kNtKS;
-  nt_load(X, d, row0, R, 0, d, tid, ra);
-  nt_load(VT + n0 * d, d, 0, width, 0, d, tid, rb);
-  nt_store(As, tid, ra);
-  nt_store(Bs, tid, rb);
+  f4 ra[KS / 8], rb[KS / 8];
+  const int nst = (d + KS - 1) / KS;
+  nt_load<KS>(X, d, row0, R, 0, d, tid, ra);
+  nt_load<KS>(VT + n0 * d, d, 0, width, 0, d, tid, rb);
+  nt_store<KS>(As, tid, ra);
+  nt_store<KS>(Bs, tid, rb);
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
     if (st + 1 < nst) {
-      nt_load(X, d, row0, R, (int64_t)(st + 1) * kNtKS, d, tid, ra);
-      nt_load(VT + n0 * d, d, 0, width, (int64_t)(st + 1) * kNtKS, d, tid, rb);
+      nt_load<KS>(X, d, row0, R, (int64_t)(st + 1) * KS, d, tid, ra);
+      nt_load<KS>(VT + n0 * d, d, 0, width, (int64_t)(st + 1) * KS, d, tid, rb);
     }
-    nt_stage(As + buf * kNtBM * kNtSK, Bs + buf * kNtBN * kNtSK, wm, wn, li, g, acc);
+    nt_stage<KS>(As + buf * kNtBM * SK, Bs + buf * kNtBN * SK, wm, wn, li, g, acc);
     if (st + 1 < nst) {
-      nt_store(As + (buf ^ 1) * kNtBM * kNtSK, tid, ra);
-      nt_store(Bs + (buf ^ 1) * kNtBN * kNtSK, tid, rb);
+      nt_store<KS>(As + (buf ^ 1) * kNtBM * SK, tid, ra);
+      nt_store<KS>(Bs + (buf ^ 1) * kNtBN * SK, tid, rb);
     }
     __syncthreads();
   }
@@ -248,16 +268,17 @@ __global__ __launch_bounds__(256) void k_nt_alpha(const float* __restrict__ apar
   beta[(int64_t)p * ldg + r] = (float)a;
 }
 
-// E^T and h of four consecutive columns nb .. nb + 3 of one window (nvalid of them valid; the
-// class of nb is k_first) at rows r .. r + 3 (zero when r >= re).  Addresses are clamped into the
-// valid columns and rows (r0 is a valid row) so that no lane forms an address outside them.
+// E^T and h of CPT consecutive columns nb .. nb + CPT - 1 of one window (nvalid of them valid;
+// the class of nb is k_first) at rows r .. r + 3 (zero when r >= re).  Addresses are clamped into
+// the valid columns and rows (r0 is a valid row) so that no lane forms an address outside them.
+template <int CPT>
 __device__ __forceinline__ void nt_load_e(const float* __restrict__ GT, int64_t ldg,
                                           const float* __restrict__ HT, int64_t ldh, int nb,
                                           int nvalid, int k_first, int64_t r, int64_t re,
-                                          int64_t r0, f4 (&gv)[4], f4 (&hv)[4]) {
+                                          int64_t r0, f4 (&gv)[CPT], f4 (&hv)[CPT]) {
   const int64_t rr = r < re ? r : r0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < CPT; ++t) {
     const int tt = t < nvalid ? t : 0;
     const bool ok = t < nvalid && r < re;
     const f4 gl = *reinterpret_cast<const f4*>(GT + (int64_t)(nb + tt) * ldg + rr);
@@ -266,26 +287,22 @@ __device__ __forceinline__ void nt_load_e(const float* __restrict__ GT, int64_t 
     hv[t] = ok ? hl : f4{0.f, 0.f, 0.f, 0.f};
   }
 }
-// G'^T = (E^T - beta[p]) h of the four columns into the LDS tile b[n][k] (rows at or beyond re
-// stage as zero).
-__device__ __forceinline__ void nt_store_g(float* __restrict__ b, int tid, int64_t r, int64_t re,
-                                           const float* __restrict__ beta, int64_t ldg, int nb,
-                                           int c, int p_lo, int p_hi, const f4 (&gv)[4],
-                                           const f4 (&hv)[4]) {
+// G'^T = (E^T - beta[p]) h of the CPT columns (rows jl .. jl + CPT - 1 of the LDS tile b[n][k],
+// row stride SK) at k offset rk (rows at or beyond re stage as zero).
+template <int CPT, int SK>
+__device__ __forceinline__ void nt_store_g(float* __restrict__ b, int jl, int rk, int64_t r,
+                                           int64_t re, const float* __restrict__ beta,
+                                           int64_t ldg, int p, const f4 (&gv)[CPT],
+                                           const f4 (&hv)[CPT]) {
   const bool rok = r < re;   // re is a multiple of 4 except at the end of the rows
-  const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-  const int64_t rr = rok ? r : 0;
-  const f4 bl_ = *reinterpret_cast<const f4*>(beta + (int64_t)p_lo * ldg + rr);
-  const f4 bh_ = *reinterpret_cast<const f4*>(beta + (int64_t)p_hi * ldg + rr);
-  const f4 b_lo = rok ? bl_ : z4;
-  const f4 b_hi = rok ? bh_ : z4;
+  const f4 bl = *reinterpret_cast<const f4*>(beta + (int64_t)p * ldg + (rok ? r : 0));
+  const f4 bt = rok ? bl : f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const f4 bt = (nb + t) / c == p_lo ? b_lo : b_hi;
+  for (int t = 0; t < CPT; ++t) {
     f4 x;
 #pragma unroll
     for (int v = 0; v < 4; ++v) x[v] = r + v < re ? (gv[t][v] - bt[v]) * hv[t][v] : 0.f;
-    *reinterpret_cast<f4*>(b + (4 * (tid >> 3) + t) * kNtSK + (int)(4 * (tid & 7))) = x;
+    *reinterpret_cast<f4*>(b + (jl + t) * SK + rk) = x;
   }
 }
 
@@ -294,15 +311,19 @@ __device__ __forceinline__ void nt_store_g(float* __restrict__ b, int tid, int64
 // p = n / c, k = n % c.  Thread tid stages columns n0 + 4 (tid / 8) + t, t = 0..3, at rows
 // 4 (tid % 8) of the stage: E^T and h are fetched before the stage's products, beta (at most two
 // probes among four consecutive columns) after them.
-__global__ __launch_bounds__(kNtWG, 2) void k_nt_xtg(
+template <int KS, int MINB>
+__global__ __launch_bounds__(kNtWG, MINB) void k_nt_xtg(
     const float* __restrict__ XT, int64_t ldx, int d, const float* __restrict__ GT, int64_t ldg,
     int SC, int c, int nw, const float* __restrict__ HT, int64_t ldh,
     const float* __restrict__ beta, int64_t R, int64_t rows_per_split, int nmt, int nct,
     float* __restrict__ part, int64_t part_stride, int accumulate, Skip skip) {
   if (skip_now(skip)) return;
   extern __shared__ __align__(16) float nt_lds[];
+  constexpr int SK = nt_sk<KS>();
+  constexpr int VR = KS / 4;          // 16-byte row vectors per stage row
+  constexpr int CPT = KS / 8;         // columns staged per thread (4 rows each)
   float* As = nt_lds;
-  float* Bs = nt_lds + 2 * kNtBM * kNtSK;
+  float* Bs = nt_lds + 2 * kNtBM * SK;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
@@ -327,42 +348,39 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt_xtg(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  // B staging: columns nb + t (t = 0..3) at rows 4 (tid % 8) of the stage; the columns' probes
-  // (the first and last of the four may differ), classes and validity are fixed per thread
-  const int jl = 4 * (tid >> 3);               // first of the thread's columns in the window
+  // B staging: columns nb + t (t < CPT, all of probe p) at rows 4 (tid % VR) .. + 3 of the
+  // stage; their classes and validity are fixed per thread
+  const int jl = CPT * (tid / VR);           // first of the thread's columns in the window
   const int nb = n0 + jl;
-  const int rk = 4 * (tid & 7);
-  const int nvalid = width - jl < 4 ? (width - jl > 0 ? width - jl : 0) : 4;
+  const int rk = 4 * (tid % VR);
+  const int nvalid = width - jl < CPT ? (width - jl > 0 ? width - jl : 0) : CPT;
   // with no valid column the loads are made from the window's first column (and zeroed)
   const int nb_c = nvalid > 0 ? nb : n0;
   const int k_first = nvalid > 0 ? col0w + jl : col0w;
-  const int p_lo = p, p_hi = p;
-  f4 ra[4], gv[4], hv[4];
+  f4 ra[KS / 8], gv[CPT], hv[CPT];
   const int64_t nrows = re > rb ? re - rb : 0;
-  const int nst = (int)((nrows + kNtKS - 1) / kNtKS);
+  const int nst = (int)((nrows + KS - 1) / KS);
   if (nst > 0) {
-    nt_load(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, rb, re, tid, ra);
-    nt_load_e(GT, ldg, HT, ldh, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv);
-    nt_store(As, tid, ra);
-    nt_store_g(Bs, tid, rb + rk, re, beta, ldg, nb, c, p_lo, p_hi, gv, hv);
+    nt_load<KS>(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, rb, re, tid, ra);
+    nt_load_e<CPT>(GT, ldg, HT, ldh, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv);
+    nt_store<KS>(As, tid, ra);
+    nt_store_g<CPT, SK>(Bs, jl, rk, rb + rk, re, beta, ldg, p, gv, hv);
   }
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
-    const int64_t k1 = rb + (int64_t)(st + 1) * kNtKS;
+    const int64_t k1 = rb + (int64_t)(st + 1) * KS;
     if (st + 1 < nst) {
-      nt_load(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, k1, re, tid, ra);
-      nt_load_e(GT, ldg, HT, ldh, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv);
+      nt_load<KS>(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, k1, re, tid, ra);
+      nt_load_e<CPT>(GT, ldg, HT, ldh, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv);
     }
-    nt_stage(As + buf * kNtBM * kNtSK, Bs + buf * kNtBN * kNtSK, wm, wn, li, g, acc);
+    nt_stage<KS>(As + buf * kNtBM * SK, Bs + buf * kNtBN * SK, wm, wn, li, g, acc);
     if (st + 1 < nst) {
-      nt_store(As + (buf ^ 1) * kNtBM * kNtSK, tid, ra);
-      nt_store_g(Bs + (buf ^ 1) * kNtBN * kNtSK, tid, k1 + rk, re, beta, ldg, nb, c, p_lo, p_hi,
-                 gv, hv);
+      nt_store<KS>(As + (buf ^ 1) * kNtBM * SK, tid, ra);
+      nt_store_g<CPT, SK>(Bs + (buf ^ 1) * kNtBN * SK, jl, rk, k1 + rk, re, beta, ldg, p, gv, hv);
     }
     __syncthreads();
   }
-
   nt_xtg_epilogue(acc, part, sp, part_stride, a0, n0, n0 + width, wm, wn, li, g, d, SC,
                   accumulate);
 }
@@ -586,7 +604,7 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt3_xtg(
   // pool) come from the padding or the next rows and meet zero in B
   if (nst > 0) {
     nt3_load(xh, xl, ldx, d - a0, rb, re, tid, ah, al);
-    nt_load_e(GT, ldg, HT, ldh, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv);
+    nt_load_e<4>(GT, ldg, HT, ldh, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv);
     nt3_store(As, tid, ah, al);
     nt3_store_g(Bs, tid, rb + rk, re, beta, ldg, nb, c, p_lo, p_hi, gv, hv);
   }
@@ -596,7 +614,7 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt3_xtg(
     const int64_t k1 = rb + (int64_t)(st + 1) * kNtKS;
     if (st + 1 < nst) {
       nt3_load(xh, xl, ldx, d - a0, k1, re, tid, ah, al);
-      nt_load_e(GT, ldg, HT, ldh, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv);
+      nt_load_e<4>(GT, ldg, HT, ldh, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv);
     }
     nt3_stage(As + buf * PL, Bs + buf * PL, wm, wn, li, g, acc);
     if (st + 1 < nst) {
@@ -690,10 +708,12 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
                   float* out, int s, Skip skip, hipStream_t st) {
   const int d = x->d, c = x->c, SC = s * c, nw = nt_windows(c);
   if (!g_nt_attr) {
-    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)kNtLds));
-    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xtg,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNtLds));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xv<kNtKsXv, kNtMinbXv>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)nt_lds_bytes<kNtKsXv>()));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xtg<kNtKsXtg, kNtMinbXtg>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)nt_lds_bytes<kNtKsXtg>()));
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xv,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNt3Lds));
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg,
@@ -736,7 +756,8 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
                             (const float*)x->HTf + r0, x->ldn, omega ? omega + r0 : nullptr, GT,
                             ldg, apart, skip);
     else
-      hipExtLaunchKernelGGL(k_nt_xv, grid1, dim3(kNtWG), (uint32_t)kNtLds, st, e0, e1, 0u,
+      hipExtLaunchKernelGGL(k_nt_xv<kNtKsXv, kNtMinbXv>, grid1, dim3(kNtWG),
+                            (uint32_t)nt_lds_bytes<kNtKsXv>(), st, e0, e1, 0u,
                             (const float*)x->X + r0 * d, d, R, (const float*)VT, c, nw, ntc,
                             (const float*)x->HTf + r0, x->ldn, omega ? omega + r0 : nullptr, GT,
                             ldg, apart, skip);
@@ -755,10 +776,11 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
                             (const float*)beta, R, rps, nmt, nct, part, n_out, (int)(r0 > 0),
                             skip);
     else
-      hipExtLaunchKernelGGL(k_nt_xtg, grid2, dim3(kNtWG), (uint32_t)kNtLds, st, e0, e1, 0u,
-                            (const float*)x->XTf + r0, x->ldn, d, (const float*)GT, ldg, SC, c,
-                            nw, (const float*)x->HTf + r0, x->ldn, (const float*)beta, R, rps,
-                            nmt, nct, part, n_out, (int)(r0 > 0), skip);
+      hipExtLaunchKernelGGL(k_nt_xtg<kNtKsXtg, kNtMinbXtg>, grid2, dim3(kNtWG),
+                            (uint32_t)nt_lds_bytes<kNtKsXtg>(), st, e0, e1, 0u,
+                            (const float*)x->XTf + r0, x->ldn, d, (const float*)GT, ldg, SC, c, nw,
+                            (const float*)x->HTf + r0, x->ldn, (const float*)beta, R, rps, nmt,
+                            nct, part, n_out, (int)(r0 > 0), skip);
     FIRAL_LAUNCHED();
   }
   return reduce_parts_launch<float>(part, n_out, n_rows > 0 ? S : 0, shift, B, out, skip, st);
