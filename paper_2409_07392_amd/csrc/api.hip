@@ -191,9 +191,11 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   x->esize = prec == FIRAL_F64 ? 8 : 4;
   x->X = X;
   x->H = H;
-  if (hipGetDevice(&x->device) != hipSuccess) {
+  if (hipGetDevice(&x->device) != hipSuccess ||
+      hipDeviceGetAttribute(&x->n_cu, hipDeviceAttributeMultiprocessorCount, x->device) !=
+          hipSuccess) {
     delete x;
-    set_error("hipGetDevice failed");
+    set_error("hipGetDevice / hipDeviceGetAttribute failed");
     return FIRAL_EHIP;
   }
   const int64_t blk = (int64_t)d * s_max * c;        // elements per block

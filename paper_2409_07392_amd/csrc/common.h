@@ -66,6 +66,7 @@ struct Ctx {
   const void* X;
   const void* H;
   int device;
+  int n_cu;             // compute units of the device
 
   // hvp / grad row-chunk intermediates
   int64_t chunk_rows;   // rows per chunk of the (rows x s*c) intermediate

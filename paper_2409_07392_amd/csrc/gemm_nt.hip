@@ -80,33 +80,43 @@ __device__ __forceinline__ void nt_stage(const float* __restrict__ a, const floa
 
 // Tile loads: a 128 x KS tile of a row-major source (leading dimension ld, k contiguous) as
 // 16-byte vectors, KS / 8 per thread: vector e = tid + 256 t covers row e / (KS / 4), k 4 (e %
-// (KS / 4)).  Rows at or beyond nrow and k at or beyond nk read as zero (nk a multiple of 4).
+// (KS / 4)).  Rows at or beyond nrow and k at or beyond nk read row 0, k 0 (a valid address)
+// and are cleared to zero by nt_store through the returned mask (bit t: vector t in range), so
+// that nothing consumes a loaded value before the stage's MFMAs (nk a multiple of 4).
 template <int KS>
-__device__ __forceinline__ void nt_load(const float* __restrict__ src, int64_t ld, int64_t row0,
-                                        int64_t nrow, int64_t k0, int64_t nk, int tid,
-                                        f4 (&v)[KS / 8]) {
+__device__ __forceinline__ unsigned nt_load(const float* __restrict__ src, int64_t ld,
+                                            int64_t row0, int64_t nrow, int64_t k0, int64_t nk,
+                                            int tid, f4 (&v)[KS / 8]) {
   constexpr int VR = KS / 4;
+  unsigned m = 0;
 #pragma unroll
   for (int t = 0; t < KS / 8; ++t) {
     const int e = tid + kNtWG * t, rr = e / VR, kk = 4 * (e % VR);
     const int64_t row = row0 + rr, k = k0 + kk;
     const bool ok = row < nrow && k < nk;
-    // out-of-range lanes read row 0, k 0 (valid) and keep zero
-    const f4 l = *reinterpret_cast<const f4*>(src + (ok ? row * ld + k : 0));
-    v[t] = ok ? l : f4{0.f, 0.f, 0.f, 0.f};
+    v[t] = *reinterpret_cast<const f4*>(src + (ok ? row * ld + k : 0));
+    m |= (unsigned)ok << t;
   }
+  return m;
 }
 template <int KS>
-__device__ __forceinline__ void nt_store(float* __restrict__ dst, int tid, const f4 (&v)[KS / 8]) {
+__device__ __forceinline__ void nt_store(float* __restrict__ dst, int tid, const f4 (&v)[KS / 8],
+                                         unsigned m) {
   constexpr int VR = KS / 4;
 #pragma unroll
   for (int t = 0; t < KS / 8; ++t) {
     const int e = tid + kNtWG * t, rr = e / VR, kk = 4 * (e % VR);
-    *reinterpret_cast<f4*>(dst + rr * nt_sk<KS>() + kk) = v[t];
+    *reinterpret_cast<f4*>(dst + rr * nt_sk<KS>() + kk) =
+        (m >> t) & 1u ? v[t] : f4{0.f, 0.f, 0.f, 0.f};
   }
 }
 
-// Epilogue of the first contraction (both forms).
+// Keeps the compiler's scheduler from moving instructions across this point: the next stage's
+// loads are issued before the stage's MFMAs and consumed only after them.
+__device__ __forceinline__ void nt_order() { __builtin_amdgcn_sched_barrier(0); }
+
+// Epilogue of the first contraction (both forms); OM: omega given (else omega = 1).
+template <bool OM>
 __device__ __forceinline__ void nt_xv_epilogue(const f32x4 (&acc)[4][4], float* nt_lds, int wave,
                                                int wm, int wn, int li, int g, int tid,
                                                int64_t row0, int64_t R, int width, int col0,
@@ -120,45 +130,67 @@ __device__ __forceinline__ void nt_xv_epilogue(const f32x4 (&acc)[4][4], float* 
   // (2) per row the sum over this wave's columns of E h, then over the 16 lanes of a column
   // group, then over the two waves of a row band through LDS, into beta_part[p][w][r].
   float* red = nt_lds;   // [2][kNtBM]: the main buffers are free after the last barrier
+  // two halves of two row blocks each: every load of a half first (omega of the lane's 8 rows,
+  // h of its 8 row quads), at addresses clamped into the valid rows and columns, so that their
+  // latencies overlap
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t r = row0 + wm + 16 * i + 4 * g;   // first of the lane's four rows
-    float om[4];
+  for (int hf = 0; hf < 2; ++hf) {
+    float om[2][4];
+    f4 hq[2][4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) om[v] = r + v < R ? (omega ? (float)omega[r + v] : 1.f) : 0.f;
-    float t[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int ii = 0; ii < 2; ++ii) {
+      const int64_t r = row0 + wm + 16 * (2 * hf + ii) + 4 * g;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int nl = wn + 16 * j + li;              // column within the window
-      if (nl < width && r < R) {
-        const int64_t n = n0 + nl;
-        const f4 e = f4{om[0] * acc[i][j][0], om[1] * acc[i][j][1], om[2] * acc[i][j][2],
-                        om[3] * acc[i][j][3]};
-        // R is a multiple of 4 except at the end of the rows; guard the last vector
-        if (r + 3 < R) {
-          *reinterpret_cast<f4*>(GT + n * ldg + r) = e;
-        } else {
+      for (int v = 0; v < 4; ++v) {
+        const int64_t rv = r + v < R ? r + v : 0;
+        const float o = OM ? (float)omega[rv] : 1.f;
+        om[ii][v] = r + v < R ? o : 0.f;
+      }
 #pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (r + v < R) GT[n * ldg + r + v] = e[v];
-        }
-        const f4 h = *reinterpret_cast<const f4*>(HT + (int64_t)(col0 + nl) * ldh + r);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) t[v] = fmaf(e[v], h[v], t[v]);
+      for (int j = 0; j < 4; ++j) {
+        const int nl = wn + 16 * j + li;
+        const int nc = nl < width ? nl : 0;
+        hq[ii][j] =
+            *reinterpret_cast<const f4*>(HT + (int64_t)(col0 + nc) * ldh + (r < R ? r : 0));
       }
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      float s = t[v];
-      s += __shfl_xor(s, 1, 64);
-      s += __shfl_xor(s, 2, 64);
-      s += __shfl_xor(s, 4, 64);
-      s += __shfl_xor(s, 8, 64);
-      t[v] = s;
-    }
-    if (li == 0) {
+    for (int ii = 0; ii < 2; ++ii) {
+      const int i = 2 * hf + ii;
+      const int64_t r = row0 + wm + 16 * i + 4 * g;   // first of the lane's four rows
+      float t[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int v = 0; v < 4; ++v) red[(wave & 1) * kNtBM + wm + 16 * i + 4 * g + v] = t[v];
+      for (int j = 0; j < 4; ++j) {
+        const int nl = wn + 16 * j + li;              // column within the window
+        const f4 e = f4{om[ii][0] * acc[i][j][0], om[ii][1] * acc[i][j][1],
+                        om[ii][2] * acc[i][j][2], om[ii][3] * acc[i][j][3]};
+        if (nl < width && r < R) {
+          const int64_t n = n0 + nl;
+          // R is a multiple of 4 except at the end of the rows; guard the last vector
+          if (r + 3 < R) {
+            *reinterpret_cast<f4*>(GT + n * ldg + r) = e;
+          } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              if (r + v < R) GT[n * ldg + r + v] = e[v];
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) t[v] = fmaf(e[v], hq[ii][j][v], t[v]);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        float s = t[v];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        s += __shfl_xor(s, 4, 64);
+        s += __shfl_xor(s, 8, 64);
+        t[v] = s;
+      }
+      if (li == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave & 1) * kNtBM + wm + 16 * i + 4 * g + v] = t[v];
+      }
     }
   }
   __syncthreads();
@@ -174,24 +206,47 @@ __device__ __forceinline__ void nt_xtg_epilogue(const f32x4 (&acc)[4][4], float*
                                                 int n_end, int wm, int wn, int li, int g, int d,
                                                 int SC, int accumulate) {
   float* out = part + (int64_t)sp * part_stride;
+  if (accumulate) {
+    // every earlier partial is loaded first (clamped addresses) so that the loads overlap, then
+    // added and stored
+    float prev[4][4][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = a0 + wm + 16 * i + 4 * g + v;
-        const int n = n0 + wn + 16 * j + li;
-        if (a < d && n < n_end) {
-          const int64_t o = (int64_t)a * SC + n;
-          out[o] = accumulate ? out[o] + acc[i][j][v] : acc[i][j][v];
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + wm + 16 * i + 4 * g + v;
+          const int n = n0 + wn + 16 * j + li;
+          prev[i][j][v] = out[a < d && n < n_end ? (int64_t)a * SC + n : 0];
         }
-      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + wm + 16 * i + 4 * g + v;
+          const int n = n0 + wn + 16 * j + li;
+          if (a < d && n < n_end) out[(int64_t)a * SC + n] = prev[i][j][v] + acc[i][j][v];
+        }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + wm + 16 * i + 4 * g + v;
+          const int n = n0 + wn + 16 * j + li;
+          if (a < d && n < n_end) out[(int64_t)a * SC + n] = acc[i][j][v];
+        }
+  }
 }
 
 // Kernel 1.  Tiles: row tile rt (kNtBM rows of the chunk) x column tile ct: the column windows
 // of kNtBN columns of s probes (nw windows each), tile ct = window (ct / s) of probe (ct % s).
-template <int KS, int MINB>
+template <int KS, int MINB, bool OM>
 __global__ __launch_bounds__(kNtWG, MINB) void k_nt_xv(
     const float* __restrict__ X, int d, int64_t R, const float* __restrict__ VT, int c, int nw,
     int ntc, const float* __restrict__ HT, int64_t ldh, const double* __restrict__ omega,
@@ -231,27 +286,27 @@ __global__ __launch_bounds__(kNtWG, MINB) void k_nt_xv(
 
   f4 ra[KS / 8], rb[KS / 8];
   const int nst = (d + KS - 1) / KS;
-  nt_load<KS>(X, d, row0, R, 0, d, tid, ra);
-  nt_load<KS>(VT + n0 * d, d, 0, width, 0, d, tid, rb);
-  nt_store<KS>(As, tid, ra);
-  nt_store<KS>(Bs, tid, rb);
+  unsigned ma = nt_load<KS>(X, d, row0, R, 0, d, tid, ra);
+  unsigned mb = nt_load<KS>(VT + n0 * d, d, 0, width, 0, d, tid, rb);
+  nt_store<KS>(As, tid, ra, ma);
+  nt_store<KS>(Bs, tid, rb, mb);
   __syncthreads();
+  // every pass loads the next stage (past the last stage the loads are masked to zero and their
+  // store lands in the buffer no later stage reads)
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
-    if (st + 1 < nst) {
-      nt_load<KS>(X, d, row0, R, (int64_t)(st + 1) * KS, d, tid, ra);
-      nt_load<KS>(VT + n0 * d, d, 0, width, (int64_t)(st + 1) * KS, d, tid, rb);
-    }
+    ma = nt_load<KS>(X, d, row0, R, (int64_t)(st + 1) * KS, d, tid, ra);
+    mb = nt_load<KS>(VT + n0 * d, d, 0, width, (int64_t)(st + 1) * KS, d, tid, rb);
+    nt_order();
     nt_stage<KS>(As + buf * kNtBM * SK, Bs + buf * kNtBN * SK, wm, wn, li, g, acc);
-    if (st + 1 < nst) {
-      nt_store<KS>(As + (buf ^ 1) * kNtBM * SK, tid, ra);
-      nt_store<KS>(Bs + (buf ^ 1) * kNtBN * SK, tid, rb);
-    }
+    nt_order();
+    nt_store<KS>(As + (buf ^ 1) * kNtBM * SK, tid, ra, ma);
+    nt_store<KS>(Bs + (buf ^ 1) * kNtBN * SK, tid, rb, mb);
     __syncthreads();
   }
 
-  nt_xv_epilogue(acc, nt_lds, wave, wm, wn, li, g, tid, row0, R, width, col0, n0, p, w, nw, HT,
-                 ldh, omega, GT, ldg, apart);
+  nt_xv_epilogue<OM>(acc, nt_lds, wave, wm, wn, li, g, tid, row0, R, width, col0, n0, p, w, nw,
+                     HT, ldh, omega, GT, ldg, apart);
 }
 
 // beta[p][r] = sum_w beta_part[p][w][r] in FP64, fixed order (= omega_r alpha_rp).
@@ -268,40 +323,42 @@ __global__ __launch_bounds__(256) void k_nt_alpha(const float* __restrict__ apar
   beta[(int64_t)p * ldg + r] = (float)a;
 }
 
-// E^T and h of CPT consecutive columns nb .. nb + CPT - 1 of one window (nvalid of them valid;
-// the class of nb is k_first) at rows r .. r + 3 (zero when r >= re).  Addresses are clamped into
-// the valid columns and rows (r0 is a valid row) so that no lane forms an address outside them.
+// E^T and h of CPT consecutive columns nb .. nb + CPT - 1 of one window (the class of nb is
+// k_first) and beta of their probe p, at rows r .. r + 3.  Addresses are clamped into the valid
+// columns and rows (r0 is a valid row), so every value is finite; nt_store_g zeroes the rows
+// beyond re.
 template <int CPT>
 __device__ __forceinline__ void nt_load_e(const float* __restrict__ GT, int64_t ldg,
-                                          const float* __restrict__ HT, int64_t ldh, int nb,
+                                          const float* __restrict__ HT, int64_t ldh,
+                                          const float* __restrict__ beta, int p, int nb,
                                           int nvalid, int k_first, int64_t r, int64_t re,
-                                          int64_t r0, f4 (&gv)[CPT], f4 (&hv)[CPT]) {
+                                          int64_t r0, f4 (&gv)[CPT], f4 (&hv)[CPT], f4& bt) {
   const int64_t rr = r < re ? r : r0;
 #pragma unroll
   for (int t = 0; t < CPT; ++t) {
     const int tt = t < nvalid ? t : 0;
-    const bool ok = t < nvalid && r < re;
-    const f4 gl = *reinterpret_cast<const f4*>(GT + (int64_t)(nb + tt) * ldg + rr);
-    const f4 hl = *reinterpret_cast<const f4*>(HT + (int64_t)(k_first + tt) * ldh + rr);
-    gv[t] = ok ? gl : f4{0.f, 0.f, 0.f, 0.f};
-    hv[t] = ok ? hl : f4{0.f, 0.f, 0.f, 0.f};
+    gv[t] = *reinterpret_cast<const f4*>(GT + (int64_t)(nb + tt) * ldg + rr);
+    hv[t] = *reinterpret_cast<const f4*>(HT + (int64_t)(k_first + tt) * ldh + rr);
   }
+  bt = *reinterpret_cast<const f4*>(beta + (int64_t)p * ldg + rr);
 }
-// G'^T = (E^T - beta[p]) h of the CPT columns (rows jl .. jl + CPT - 1 of the LDS tile b[n][k],
-// row stride SK) at k offset rk (rows at or beyond re stage as zero).
+// G'^T = (E^T - beta) h of the CPT columns (rows jl .. jl + CPT - 1 of the LDS tile b[n][k], row
+// stride SK) at k offset rk; rows at or beyond re stage as zero (re is a multiple of 4 except at
+// the end of the rows).  Columns beyond the window (t >= nvalid) stage the finite values of the
+// clamped loads: they only reach output columns that the epilogue drops.
 template <int CPT, int SK>
 __device__ __forceinline__ void nt_store_g(float* __restrict__ b, int jl, int rk, int64_t r,
-                                           int64_t re, const float* __restrict__ beta,
-                                           int64_t ldg, int p, const f4 (&gv)[CPT],
-                                           const f4 (&hv)[CPT]) {
-  const bool rok = r < re;   // re is a multiple of 4 except at the end of the rows
-  const f4 bl = *reinterpret_cast<const f4*>(beta + (int64_t)p * ldg + (rok ? r : 0));
-  const f4 bt = rok ? bl : f4{0.f, 0.f, 0.f, 0.f};
+                                           int64_t re, const f4 (&gv)[CPT], const f4 (&hv)[CPT],
+                                           const f4& bt) {
+  const bool full = r + 3 < re;
 #pragma unroll
   for (int t = 0; t < CPT; ++t) {
     f4 x;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) x[v] = r + v < re ? (gv[t][v] - bt[v]) * hv[t][v] : 0.f;
+    for (int v = 0; v < 4; ++v) {
+      const float y = (gv[t][v] - bt[v]) * hv[t][v];
+      x[v] = full || r + v < re ? y : 0.f;
+    }
     *reinterpret_cast<f4*>(b + (jl + t) * SK + rk) = x;
   }
 }
@@ -357,28 +414,29 @@ __global__ __launch_bounds__(kNtWG, MINB) void k_nt_xtg(
   // with no valid column the loads are made from the window's first column (and zeroed)
   const int nb_c = nvalid > 0 ? nb : n0;
   const int k_first = nvalid > 0 ? col0w + jl : col0w;
-  f4 ra[KS / 8], gv[CPT], hv[CPT];
+  f4 ra[KS / 8], gv[CPT], hv[CPT], bt;
   const int64_t nrows = re > rb ? re - rb : 0;
   const int nst = (int)((nrows + KS - 1) / KS);
   if (nst > 0) {
-    nt_load<KS>(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, rb, re, tid, ra);
-    nt_load_e<CPT>(GT, ldg, HT, ldh, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv);
-    nt_store<KS>(As, tid, ra);
-    nt_store_g<CPT, SK>(Bs, jl, rk, rb + rk, re, beta, ldg, p, gv, hv);
+    const unsigned ma = nt_load<KS>(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, rb, re, tid, ra);
+    nt_load_e<CPT>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv, bt);
+    nt_store<KS>(As, tid, ra, ma);
+    nt_store_g<CPT, SK>(Bs, jl, rk, rb + rk, re, gv, hv, bt);
   }
   __syncthreads();
+  // every pass loads the next stage (past the last one the rows are out of range: clamped
+  // addresses, staged as zero into the buffer no later stage reads)
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
     const int64_t k1 = rb + (int64_t)(st + 1) * KS;
-    if (st + 1 < nst) {
-      nt_load<KS>(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, k1, re, tid, ra);
-      nt_load_e<CPT>(GT, ldg, HT, ldh, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv);
-    }
+    const unsigned ma = nt_load<KS>(XT + (int64_t)a0 * ldx, ldx, 0, d - a0, k1, re, tid, ra);
+    nt_load_e<CPT>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv,
+                   bt);
+    nt_order();
     nt_stage<KS>(As + buf * kNtBM * SK, Bs + buf * kNtBN * SK, wm, wn, li, g, acc);
-    if (st + 1 < nst) {
-      nt_store<KS>(As + (buf ^ 1) * kNtBM * SK, tid, ra);
-      nt_store_g<CPT, SK>(Bs + (buf ^ 1) * kNtBN * SK, jl, rk, k1 + rk, re, beta, ldg, p, gv, hv);
-    }
+    nt_order();
+    nt_store<KS>(As + (buf ^ 1) * kNtBM * SK, tid, ra, ma);
+    nt_store_g<CPT, SK>(Bs + (buf ^ 1) * kNtBN * SK, jl, rk, k1 + rk, re, gv, hv, bt);
     __syncthreads();
   }
   nt_xtg_epilogue(acc, part, sp, part_stride, a0, n0, n0 + width, wm, wn, li, g, d, SC,
@@ -396,6 +454,7 @@ __global__ __launch_bounds__(kNtWG, MINB) void k_nt_xtg(
 // call; k_nt3_xtg takes X^T from the context's transposed planes and splits G' = (E - beta) h as
 // it is staged.  The epilogues are those of the FP32 kernels.
 constexpr size_t kNt3Lds = (size_t)2 * 2 * (kNtBM + kNtBN) * 32 * 2;   // 65,536 bytes
+constexpr size_t kNt3XvLds = kNt3Lds / 2;   // single-buffered first contraction
 
 __device__ __forceinline__ bf16x8 nt3_zero8() {
   bf16x8 z;
@@ -431,41 +490,48 @@ __device__ __forceinline__ void nt3_stage(const __bf16* __restrict__ a,
 
 // A 128 x 32 tile of two row-major bf16 planes (leading dimension ld): 512 16-byte chunks per
 // plane, two per thread: chunk e = tid + 256 t is row e / 4, k 8 (e % 4).  Rows at or beyond
-// nrow and k at or beyond nk read as zero (nk a multiple of 8).
-__device__ __forceinline__ void nt3_load(const __bf16* __restrict__ hi, const __bf16* __restrict__ lo,
-                                         int64_t ld, int64_t nrow, int64_t k0, int64_t nk, int tid,
-                                         bf16x8 (&vh)[2], bf16x8 (&vl)[2]) {
+// nrow and k at or beyond nk read element 0 (a valid address) and are cleared by nt3_store
+// through the returned mask (nk a multiple of 8).
+__device__ __forceinline__ unsigned nt3_load(const __bf16* __restrict__ hi,
+                                             const __bf16* __restrict__ lo, int64_t ld,
+                                             int64_t nrow, int64_t k0, int64_t nk, int tid,
+                                             bf16x8 (&vh)[2], bf16x8 (&vl)[2]) {
+  unsigned m = 0;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int e = tid + kNtWG * t, row = e >> 2, ch = e & 3;
     const int64_t k = k0 + 8 * ch;
     const bool ok = row < nrow && k < nk;
-    const int64_t o = ok ? row * ld + k : 0;   // out-of-range lanes read element 0 and keep zero
-    const bf16x8 h = *reinterpret_cast<const bf16x8*>(hi + o);
-    const bf16x8 l = *reinterpret_cast<const bf16x8*>(lo + o);
-    vh[t] = ok ? h : nt3_zero8();
-    vl[t] = ok ? l : nt3_zero8();
+    const int64_t o = ok ? row * ld + k : 0;
+    vh[t] = *reinterpret_cast<const bf16x8*>(hi + o);
+    vl[t] = *reinterpret_cast<const bf16x8*>(lo + o);
+    m |= (unsigned)ok << t;
   }
+  return m;
 }
 __device__ __forceinline__ void nt3_store(__bf16* __restrict__ dst, int tid, const bf16x8 (&vh)[2],
-                                          const bf16x8 (&vl)[2]) {
+                                          const bf16x8 (&vl)[2], unsigned m) {
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int e = tid + kNtWG * t, row = e >> 2, ch = e & 3;
-    *reinterpret_cast<bf16x8*>(dst + nt3_off(0, row, ch)) = vh[t];
-    *reinterpret_cast<bf16x8*>(dst + nt3_off(1, row, ch)) = vl[t];
+    const bool ok = (m >> t) & 1u;
+    *reinterpret_cast<bf16x8*>(dst + nt3_off(0, row, ch)) = ok ? vh[t] : nt3_zero8();
+    *reinterpret_cast<bf16x8*>(dst + nt3_off(1, row, ch)) = ok ? vl[t] : nt3_zero8();
   }
 }
 
-__global__ __launch_bounds__(kNtWG, 2) void k_nt3_xv(
+template <bool OM>
+__global__ __launch_bounds__(kNtWG, 3) void k_nt3_xv(
     const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int d, int64_t R,
     const __bf16* __restrict__ VTh, const __bf16* __restrict__ VTl, int c, int nw, int ntc,
     const float* __restrict__ HT, int64_t ldh, const double* __restrict__ omega,
     float* __restrict__ GT, int64_t ldg, float* __restrict__ apart, Skip skip) {
   if (skip_now(skip)) return;
   extern __shared__ __align__(16) float nt_lds[];
-  __bf16* As = reinterpret_cast<__bf16*>(nt_lds);      // [2 bufs][2 planes][128][32]
-  __bf16* Bs = As + 2 * 2 * kNtBM * 32;
+  // one buffer per operand (two planes): 32 KB, three workgroups per CU, whose epilogues (the
+  // E^T stores) overlap the others' main loops better than two double-buffered workgroups'
+  __bf16* As = reinterpret_cast<__bf16*>(nt_lds);      // [2 planes][128][32]
+  __bf16* Bs = As + 2 * kNtBM * 32;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
@@ -497,51 +563,40 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt3_xv(
   const __bf16* vh = VTh + n0 * d;
   const __bf16* vl = VTl + n0 * d;
   const int nst = (d + kNtKS - 1) / kNtKS;
-  constexpr int PL = 2 * kNtBM * 32;   // one buffer of one operand (two planes)
-  nt3_load(xh, xl, d, R - row0, 0, d, tid, ah, al);
-  nt3_load(vh, vl, d, width, 0, d, tid, bh, bl);
-  nt3_store(As, tid, ah, al);
-  nt3_store(Bs, tid, bh, bl);
+  unsigned ma = nt3_load(xh, xl, d, R - row0, 0, d, tid, ah, al);
+  unsigned mb = nt3_load(vh, vl, d, width, 0, d, tid, bh, bl);
+  nt3_store(As, tid, ah, al, ma);
+  nt3_store(Bs, tid, bh, bl, mb);
   __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int buf = st & 1;
-    if (st + 1 < nst) {
-      nt3_load(xh, xl, d, R - row0, (int64_t)(st + 1) * kNtKS, d, tid, ah, al);
-      nt3_load(vh, vl, d, width, (int64_t)(st + 1) * kNtKS, d, tid, bh, bl);
-    }
-    nt3_stage(As + buf * PL, Bs + buf * PL, wm, wn, li, g, acc);
-    if (st + 1 < nst) {
-      nt3_store(As + (buf ^ 1) * PL, tid, ah, al);
-      nt3_store(Bs + (buf ^ 1) * PL, tid, bh, bl);
-    }
+  for (int st = 0; st < nst; ++st) {   // loads of the next stage on every pass, as in FP32
+    ma = nt3_load(xh, xl, d, R - row0, (int64_t)(st + 1) * kNtKS, d, tid, ah, al);
+    mb = nt3_load(vh, vl, d, width, (int64_t)(st + 1) * kNtKS, d, tid, bh, bl);
+    nt_order();
+    nt3_stage(As, Bs, wm, wn, li, g, acc);
+    __syncthreads();   // every wave is done with the buffers
+    nt3_store(As, tid, ah, al, ma);
+    nt3_store(Bs, tid, bh, bl, mb);
     __syncthreads();
   }
-  nt_xv_epilogue(acc, nt_lds, wave, wm, wn, li, g, tid, row0, R, width, col0, n0, p, w, nw, HT,
-                 ldh, omega, GT, ldg, apart);
+  nt_xv_epilogue<OM>(acc, nt_lds, wave, wm, wn, li, g, tid, row0, R, width, col0, n0, p, w, nw,
+                     HT, ldh, omega, GT, ldg, apart);
 }
 
-// G'^T = (E^T - beta[p]) h of four columns at rows r .. r + 3, split into hi/lo bf16 and stored
-// into the planes of the LDS tile (row 4 (tid / 8) + t, k 4 (tid % 8)).
+// G'^T = (E^T - beta[p]) h of four columns at rows r .. r + 3 (rows at or beyond re as zero;
+// columns beyond the window as in nt_store_g), split into hi/lo bf16 and stored into the planes
+// of the LDS tile (row 4 (tid / 8) + t, k 4 (tid % 8)).
 __device__ __forceinline__ void nt3_store_g(__bf16* __restrict__ b, int tid, int64_t r, int64_t re,
-                                            const float* __restrict__ beta, int64_t ldg, int nb,
-                                            int c, int p_lo, int p_hi, const f4 (&gv)[4],
-                                            const f4 (&hv)[4]) {
-  const bool rok = r < re;
-  const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-  const int64_t rr = rok ? r : 0;
-  const f4 bl_ = *reinterpret_cast<const f4*>(beta + (int64_t)p_lo * ldg + rr);
-  const f4 bh_ = *reinterpret_cast<const f4*>(beta + (int64_t)p_hi * ldg + rr);
-  const f4 b_lo = rok ? bl_ : z4;
-  const f4 b_hi = rok ? bh_ : z4;
+                                            const f4 (&gv)[4], const f4 (&hv)[4], const f4& bt) {
+  const bool full = r + 3 < re;
   const int kq = 4 * (tid & 7);              // k offset of the four rows within the stage
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const f4 bt = (nb + t) / c == p_lo ? b_lo : b_hi;
     bf16x4 h4, l4;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float x = r + v < re ? (gv[t][v] - bt[v]) * hv[t][v] : 0.f;
+      const float y = (gv[t][v] - bt[v]) * hv[t][v];
+      const float x = full || r + v < re ? y : 0.f;
       const __bf16 h = (__bf16)x;
       h4[v] = h;
       l4[v] = (__bf16)(x - (float)h);
@@ -593,9 +648,8 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt3_xtg(
   // with no valid column the loads are made from the window's first column (and zeroed)
   const int nb_c = nvalid > 0 ? nb : n0;
   const int k_first = nvalid > 0 ? col0w + jl : col0w;
-  const int p_lo = p, p_hi = p;
   bf16x8 ah[2], al[2];
-  f4 gv[4], hv[4];
+  f4 gv[4], hv[4], bt;
   const __bf16* xh = XTh + (int64_t)a0 * ldx;
   const __bf16* xl = XTl + (int64_t)a0 * ldx;
   const int64_t nrows = re > rb ? re - rb : 0;
@@ -603,24 +657,22 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt3_xtg(
   // X^T rows are read 8 at a time: rows beyond re (a multiple of 8 except at the end of the
   // pool) come from the padding or the next rows and meet zero in B
   if (nst > 0) {
-    nt3_load(xh, xl, ldx, d - a0, rb, re, tid, ah, al);
-    nt_load_e<4>(GT, ldg, HT, ldh, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv);
-    nt3_store(As, tid, ah, al);
-    nt3_store_g(Bs, tid, rb + rk, re, beta, ldg, nb, c, p_lo, p_hi, gv, hv);
+    const unsigned ma = nt3_load(xh, xl, ldx, d - a0, rb, re, tid, ah, al);
+    nt_load_e<4>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv, bt);
+    nt3_store(As, tid, ah, al, ma);
+    nt3_store_g(Bs, tid, rb + rk, re, gv, hv, bt);
   }
   __syncthreads();
-  for (int st = 0; st < nst; ++st) {
+  for (int st = 0; st < nst; ++st) {   // loads of the next stage on every pass, as in FP32
     const int buf = st & 1;
     const int64_t k1 = rb + (int64_t)(st + 1) * kNtKS;
-    if (st + 1 < nst) {
-      nt3_load(xh, xl, ldx, d - a0, k1, re, tid, ah, al);
-      nt_load_e<4>(GT, ldg, HT, ldh, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv);
-    }
+    const unsigned ma = nt3_load(xh, xl, ldx, d - a0, k1, re, tid, ah, al);
+    nt_load_e<4>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv, bt);
+    nt_order();
     nt3_stage(As + buf * PL, Bs + buf * PL, wm, wn, li, g, acc);
-    if (st + 1 < nst) {
-      nt3_store(As + (buf ^ 1) * PL, tid, ah, al);
-      nt3_store_g(Bs + (buf ^ 1) * PL, tid, k1 + rk, re, beta, ldg, nb, c, p_lo, p_hi, gv, hv);
-    }
+    nt_order();
+    nt3_store(As + (buf ^ 1) * PL, tid, ah, al, ma);
+    nt3_store_g(Bs + (buf ^ 1) * PL, tid, k1 + rk, re, gv, hv, bt);
     __syncthreads();
   }
   nt_xtg_epilogue(acc, part, sp, part_stride, a0, n0, n0 + width, wm, wn, li, g, d, SC,
@@ -708,14 +760,16 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
                   float* out, int s, Skip skip, hipStream_t st) {
   const int d = x->d, c = x->c, SC = s * c, nw = nt_windows(c);
   if (!g_nt_attr) {
-    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xv<kNtKsXv, kNtMinbXv>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)nt_lds_bytes<kNtKsXv>()));
+    for (const void* f : {(const void*)k_nt_xv<kNtKsXv, kNtMinbXv, true>,
+                          (const void*)k_nt_xv<kNtKsXv, kNtMinbXv, false>})
+      FIRAL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)nt_lds_bytes<kNtKsXv>()));
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xtg<kNtKsXtg, kNtMinbXtg>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)nt_lds_bytes<kNtKsXtg>()));
-    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xv,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNt3Lds));
+    for (const void* f : {(const void*)k_nt3_xv<true>, (const void*)k_nt3_xv<false>})
+      FIRAL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)kNt3XvLds));
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNt3Lds));
     g_nt_attr = true;
@@ -742,25 +796,33 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
   const int nmt = (int)cdiv(d, kNtBM), nct = s * nw;   // column windows of every probe
   const int64_t tiles = (int64_t)nmt * nct;
   const int64_t cap = (int64_t)x->max_splits * x->s_max / s;
-  const int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(4096, tiles), cap), 256));
+  // split count: the second contraction runs two workgroups per CU, so a grid of tiles * S
+  // workgroups takes ceil(tiles * S / slots) rounds of R / S rows each; take the S with the least
+  // time in rounds (the smallest such S: fewest partial sums), with at least 8 stages per split
+  const int64_t slots = (int64_t)2 * std::max(1, x->n_cu);
+  const int64_t s_hi = std::max<int64_t>(1, std::min<int64_t>({cap, 256, cdiv(x->chunk_rows, 8 * kNtKS)}));
+  int S = 1;
+  for (int64_t t = 2; t <= s_hi; ++t)   // rounds / S, compared as cross products
+    if (cdiv(tiles * t, slots) * S < cdiv(tiles * S, slots) * t) S = (int)t;
   const int ntc = s * nw;
   for (int64_t r0 = 0; r0 < n_rows; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, n_rows - r0);
     hipEvent_t e0, e1;
     FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT, &e0, &e1));
     const dim3 grid1((unsigned)(cdiv(R, kNtBM) * ntc));
+    const double* om = omega ? omega + r0 : nullptr;
     if (bf3)
-      hipExtLaunchKernelGGL(k_nt3_xv, grid1, dim3(kNtWG), (uint32_t)kNt3Lds, st, e0, e1, 0u,
-                            (const __bf16*)x->Xhi + r0 * d, (const __bf16*)x->Xlo + r0 * d, d, R,
-                            (const __bf16*)VTh, (const __bf16*)VTl, c, nw, ntc,
-                            (const float*)x->HTf + r0, x->ldn, omega ? omega + r0 : nullptr, GT,
-                            ldg, apart, skip);
+      hipExtLaunchKernelGGL(omega ? k_nt3_xv<true> : k_nt3_xv<false>, grid1, dim3(kNtWG),
+                            (uint32_t)kNt3XvLds, st, e0, e1, 0u, (const __bf16*)x->Xhi + r0 * d,
+                            (const __bf16*)x->Xlo + r0 * d, d, R, (const __bf16*)VTh,
+                            (const __bf16*)VTl, c, nw, ntc, (const float*)x->HTf + r0, x->ldn, om,
+                            GT, ldg, apart, skip);
     else
-      hipExtLaunchKernelGGL(k_nt_xv<kNtKsXv, kNtMinbXv>, grid1, dim3(kNtWG),
-                            (uint32_t)nt_lds_bytes<kNtKsXv>(), st, e0, e1, 0u,
+      hipExtLaunchKernelGGL(omega ? k_nt_xv<kNtKsXv, kNtMinbXv, true>
+                                  : k_nt_xv<kNtKsXv, kNtMinbXv, false>,
+                            grid1, dim3(kNtWG), (uint32_t)nt_lds_bytes<kNtKsXv>(), st, e0, e1, 0u,
                             (const float*)x->X + r0 * d, d, R, (const float*)VT, c, nw, ntc,
-                            (const float*)x->HTf + r0, x->ldn, omega ? omega + r0 : nullptr, GT,
-                            ldg, apart, skip);
+                            (const float*)x->HTf + r0, x->ldn, om, GT, ldg, apart, skip);
     FIRAL_LAUNCHED();
     k_nt_alpha<<<(unsigned)cdiv((int64_t)s * R, 256), 256, 0, st>>>(apart, nw, s, R, ldg, beta,
                                                                      skip);
