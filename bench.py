@@ -204,6 +204,29 @@ def cpu_baseline_products(p, rows=12820, budget_s=20.0):
                       "rate is per Hessian-product flop, as `value`"}
 
 
+def dirichlet_weights_device(p, seed):
+    """z = b x Dirichlet(1) over the pool, drawn on the GPU (the weights of the Round legs)."""
+    import torch
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(seed)
+    e = -torch.log(torch.rand(p.n_pool, generator=g, device="cuda:0", dtype=torch.float64))
+    return p.b * e / e.sum()
+
+
+def round_legs(p, args, seed):
+    """The Round step from Dirichlet weights, FP32 and FP64 decisions (`--round-rounds`)."""
+    import torch
+    z = dirichlet_weights_device(p, seed)
+    eta = 8.0 * (p.d * p.c) ** 0.5 if args.eta is None else args.eta
+    rounds = {}
+    for fp32 in (True, False):
+        log(f"Round step, {'FP32' if fp32 else 'FP64'} decision")
+        rounds["fp32_decision" if fp32 else "fp64_decision"] = round_large(
+            p, z, eta, args.round_rounds, fp32)
+        torch.cuda.empty_cache()
+    return rounds
+
+
 def headline(args):
     import numpy as np
     import torch
@@ -213,6 +236,10 @@ def headline(args):
     log("drawing configuration 4 on the GPU")
     p = make_problem_device(4, device="cuda:0")
     flops = 4.0 * p.N * p.c * p.d * p.s
+    rounds = round_legs(p, args, 4004) if args.round_rounds > 0 else {}
+    if args.round_only:
+        print(json.dumps({"workload": "configuration 4", "round_step": rounds}), flush=True)
+        return
     legs, grads, main = {}, {}, None
     precs = ["bf16x3"] if args.only_bf16x3 else ["f32"] + ([] if args.no_bf16x3 else ["bf16x3"])
     for prec in precs:
@@ -279,6 +306,8 @@ def headline(args):
                      max(kern[dom]["launches_per_product"], 1),
                      "traffic": read_traffic(traffic_file)},
     }
+    if rounds:
+        res["round_step"] = rounds
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle products on a 1% row sample")
         res["cpu_baseline"] = cpu_baseline_products(p)
@@ -764,18 +793,8 @@ def workload3(args):
     log("drawing configuration 3 on the GPU")
     p = make_problem_device(3, device="cuda:0")
     flops = 4.0 * p.N * p.c * p.d * p.s
-    g = torch.Generator(device="cuda:0")
-    g.manual_seed(3003)
-    e = -torch.log(torch.rand(p.n_pool, generator=g, device="cuda:0", dtype=torch.float64))
-    z = p.b * e / e.sum()
-    eta = 8.0 * (p.d * p.c) ** 0.5 if args.eta is None else args.eta
-    rounds = {}
-    if args.round_rounds > 0:
-        for fp32 in (True, False):
-            log(f"Round step, {'FP32' if fp32 else 'FP64'} decision")
-            rounds["fp32_decision" if fp32 else "fp64_decision"] = round_large(
-                p, z, eta, args.round_rounds, fp32)
-            torch.cuda.empty_cache()
+    z = dirichlet_weights_device(p, 3003)
+    rounds = round_legs(p, args, 3003) if args.round_rounds > 0 else {}
     if args.round_only:
         print(json.dumps({"workload": "configuration 3", "round_step": rounds}))
         return

@@ -166,9 +166,11 @@ __device__ __forceinline__ void nt_xv_epilogue(const f32x4 (&acc)[4][4], float* 
                         om[ii][2] * acc[i][j][2], om[ii][3] * acc[i][j][3]};
         if (nl < width && r < R) {
           const int64_t n = n0 + nl;
-          // R is a multiple of 4 except at the end of the rows; guard the last vector
+          // R is a multiple of 4 except at the end of the rows; guard the last vector.  The
+          // stores are non-temporal: E^T is read back by the second kernel from HBM (a chunk's
+          // E^T is far larger than L2 and the MALL), and should not evict X, V^T and h from L2
           if (r + 3 < R) {
-            *reinterpret_cast<f4*>(GT + n * ldg + r) = e;
+            __builtin_nontemporal_store(e, reinterpret_cast<f4*>(GT + n * ldg + r));
           } else {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
