@@ -218,6 +218,25 @@ def test_complete_hadamard_probes_give_the_exact_gradient(project):
     assert abs(info["f_hat"] - f_ref) < 1e-9 * f_ref
 
 
+def test_configuration_1_gradient_with_the_complete_probe_set():
+    # Configuration 1's shape (n = 2000 + 50, d = 20, c = 5: dc = 100) and its data.  With the
+    # complete set of scaled unit probes sqrt(dc) e_k (s = dc), (1/s) sum_j v_j^T A v_j = Tr(A)
+    # for every A, so the Hutchinson gradient of Algorithm 2 (eq. 11) is the exact gradient of
+    # eq. 6, formed here from the dense dc x dc matrices H_i = Gamma_i (x) x_i x_i^T.
+    from synthdata import make_problem
+    p = make_problem(1)
+    dc = p.d * p.c
+    w = np.full(p.n_pool, 1.0 / p.n_pool)
+    z = p.b * w
+    V = orc.vecs_to_block(math.sqrt(dc) * np.eye(dc), p.d, p.c)
+    _, info = orc.relax_iteration(p.X, p.H, p.n_pool, w, p.b, p.lam, 0.1, 0, 1, dc, 1e-13,
+                                  2000, project=True, V=V)
+    g_ref = dense.exact_gradient(p.X, p.H, p.n_pool, z, p.lam)
+    np.testing.assert_allclose(info["g"], g_ref, rtol=1e-7, atol=1e-9 * np.abs(g_ref).max())
+    f_ref = dense.objective(p.X, p.H, p.n_pool, z, p.lam)
+    assert abs(info["f_hat"] - f_ref) < 1e-9 * f_ref
+
+
 def test_grad_contract_equals_dense_quadratic_forms():
     p = tiny(n=6, n_lab=0, d=3, c=3, s=2)
     rng = np.random.default_rng(12)
