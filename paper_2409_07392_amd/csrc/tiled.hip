@@ -336,21 +336,36 @@ __global__ __launch_bounds__(256, 2) void k_xv(
     return;
   } else {
     // E2: this wave's rows (m = wave + 4 it), lanes over columns; the row operand (h for
-    // kGamma, Gin for kDot) is loaded for every row before any is used.
-    T gv[RPW][NU], xv[RPW][NU];
+    // kGamma, Gin for kDot) and omega are loaded for every row before any is used, at addresses
+    // clamped into the arrays, so that the loads overlap; values outside the tile are masked
+    // where they are used.
+    T gv[RPW][NU], xv[RPW][NU], omv[RPW];
 #pragma unroll
     for (int it = 0; it < RPW; ++it) {
       const int m = wave + 4 * it;
+      const int64_t r = row0 + (m < rows_here ? m : 0);
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
         const int n = lane + 64 * u;
         const bool ok = m < rows_here && n < width;
         if constexpr (MODE == kGamma) {
           const int kk = n - (n / c) * c;
-          xv[it][u] = ok ? H[(row0 + m) * c + kk] : T(0);
+          xv[it][u] = H[ok ? r * c + kk : 0];
         } else {
-          xv[it][u] = ok ? Gin[(row0 + m) * SC + col0 + n] : T(0);
+          xv[it][u] = Gin[ok ? r * SC + col0 + n : 0];
         }
+      }
+    }
+    if constexpr (MODE == kGamma) {
+      if (omega) {
+#pragma unroll
+        for (int it = 0; it < RPW; ++it) {
+          const int m = wave + 4 * it;
+          omv[it] = (T)omega[row0 + (m < rows_here ? m : 0)];
+        }
+      } else {
+#pragma unroll
+        for (int it = 0; it < RPW; ++it) omv[it] = T(1);
       }
     }
 #pragma unroll
@@ -359,8 +374,10 @@ __global__ __launch_bounds__(256, 2) void k_xv(
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
         const int n = lane + 64 * u;
+        const bool ok = m < rows_here && n < width;
         gv[it][u] = Cs[m * SCs + n];
-        Cs[m * SCs + n] = gv[it][u] * xv[it][u];   // each element is touched by one thread
+        // each element is touched by one thread
+        Cs[m * SCs + n] = ok ? gv[it][u] * xv[it][u] : T(0);
       }
     }
     __syncthreads();
@@ -390,7 +407,7 @@ __global__ __launch_bounds__(256, 2) void k_xv(
         const int m = wave + 4 * it;
         if (m < rows_here) {
           const int64_t r = row0 + m;
-          const T om = omega ? (T)omega[r] : T(1);
+          const T om = omv[it];
           T* go = Gout + r * SC + col0;
 #pragma unroll
           for (int u = 0; u < NU; ++u) {
@@ -605,19 +622,41 @@ __global__ __launch_bounds__(256, 2) void k_xtg(
   }
 
   T* out = part + (int64_t)sp * part_stride;
+  if (accumulate) {
+    // every earlier partial is loaded first (clamped addresses) so that the loads overlap
+    T prev[WM][WN][4];
 #pragma unroll
-  for (int i = 0; i < WM; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < WN; ++j)
+      for (int j = 0; j < WN; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int a = a0 + wm + 16 * i + M::row(g, v);
-        const int col = col0 + wn + 16 * j + li;
-        if (a < d && col < SC) {
-          const int64_t o = (int64_t)a * SC + col;
-          out[o] = accumulate ? out[o] + acc[i][j][v] : acc[i][j][v];
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + wm + 16 * i + M::row(g, v);
+          const int col = col0 + wn + 16 * j + li;
+          prev[i][j][v] = out[a < d && col < SC ? (int64_t)a * SC + col : 0];
         }
-      }
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + wm + 16 * i + M::row(g, v);
+          const int col = col0 + wn + 16 * j + li;
+          if (a < d && col < SC) out[(int64_t)a * SC + col] = prev[i][j][v] + acc[i][j][v];
+        }
+  } else {
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+      for (int j = 0; j < WN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + wm + 16 * i + M::row(g, v);
+          const int col = col0 + wn + 16 * j + li;
+          if (a < d && col < SC) out[(int64_t)a * SC + col] = acc[i][j][v];
+        }
+  }
 }
 
 // g_r = -(1/s) sum over column tiles (in order) of the tile's row dot product.
