@@ -23,6 +23,7 @@ namespace firal {
 // WC x (4 / WC) arrangement (classes x pairs), each CMW x PNW blocks of 16 x 16: with few
 // classes (c <= 16) all four waves sit along the pairs.
 constexpr int kSyrkTK = 16;
+__constant__ double kSyrkUnitWeight = 1.0;   // the row weight when none is given
 
 // L is the storage type of X and H (FP32 rows feed the FP64 Gram of the Round step).
 template <typename T, typename L, int CMW, int PNW, int WC>
@@ -76,35 +77,50 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const L* __restrict__ X, const 
     xvalid[i] = xon[i] && col < d;
     xj[i] = xvalid[i] ? col : 0;   // column of X to load (when valid)
   }
-  T ru[EU], rx[NX];
+  // The loads read rows clamped into the split (rb is a row of it whenever there is a stage) and
+  // classes and columns clamped into the arrays; u = w h (1 - h) is formed and the values outside
+  // the tile are zeroed when the stage is stored, so no loaded value is consumed before the
+  // current stage's MFMAs.
+  L rh[EU], rx[NX];   // as stored (converted to T when staged)
+  double rw[EU];
+  const int uc = uvalid ? c0 + ucls : 0;
+  const double* wsrc = omega ? omega : &kSyrkUnitWeight;
   auto load = [&](int kt) {
     const int64_t r0 = rb + (int64_t)kt * kSyrkTK;
 #pragma unroll
     for (int i = 0; i < EU; ++i) {
       const int64_t r = r0 + uk + KU * i;
-      T u = T(0);
-      if (r < re && uvalid) {
-        const T h = (T)H[r * c + c0 + ucls];
-        const T w = omega ? (T)omega[r] : T(1);
-        u = w * h * (T(1) - h);
-      }
-      ru[i] = u;
+      rh[i] = H[(r < re ? r : rb) * c + uc];
+    }
+#pragma unroll
+    for (int i = 0; i < EU; ++i) {   // without weights every row reads the one weight 1
+      const int64_t r = r0 + uk + KU * i;
+      rw[i] = wsrc[omega ? (r < re ? r : rb) : 0];
     }
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
       const int64_t r = r0 + xk[i];
-      rx[i] = (r < re && xvalid[i]) ? (T)X[r * d + xj[i]] : T(0);
+      rx[i] = X[(r < re ? r : rb) * d + xj[i]];
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int buf, int kt) {
+    const int64_t r0 = rb + (int64_t)kt * kSyrkTK;
 #pragma unroll
-    for (int i = 0; i < EU; ++i) Us[buf][uk + KU * i][ucls] = ru[i];
+    for (int i = 0; i < EU; ++i) {
+      const int64_t r = r0 + uk + KU * i;
+      const T h = (T)rh[i];
+      const T u = (T)rw[i] * h * (T(1) - h);
+      Us[buf][uk + KU * i][ucls] = r < re && uvalid ? u : T(0);
+    }
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
-      if (!xon[i]) continue;
+      // every thread stores (threads without an element write the unread pad column of Xa), so
+      // that the compiler keeps each load in the load phase rather than sinking it here
       const int e = tid + 256 * i, j = e % XW;
-      if (j < 16) Xa[buf][xk[i]][j] = rx[i];
-      else Xb[buf][xk[i]][j - 16] = rx[i];
+      const int64_t r = r0 + xk[i];
+      const T v = r < re && xvalid[i] ? (T)rx[i] : T(0);
+      T* dst = !xon[i] ? &Xa[buf][0][16] : (j < 16 ? &Xa[buf][xk[i]][j] : &Xb[buf][xk[i]][j - 16]);
+      *dst = v;
     }
   };
 
@@ -112,7 +128,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const L* __restrict__ X, const 
   const int nk = (int)((nrows + kSyrkTK - 1) / kSyrkTK);
   if (nk > 0) {
     load(0);
-    store(0);
+    store(0, 0);
   }
   __syncthreads();
   // this lane's pairs in the B operand: (a_local, b_local) of column wp + 16 j + li
@@ -125,7 +141,8 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const L* __restrict__ X, const 
   }
   for (int kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
-    if (kt + 1 < nk) load(kt + 1);
+    load(kt + 1);   // past the last stage every row is out of range (stored as zero, never read)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < kSyrkTK / 4; ++q) {
       const int k = 4 * q + g;
@@ -139,7 +156,8 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const L* __restrict__ X, const 
 #pragma unroll
         for (int j = 0; j < PNW; ++j) acc[i][j] = M::run(av[i], bv[j], acc[i][j]);
     }
-    if (kt + 1 < nk) store(buf ^ 1);
+    __builtin_amdgcn_sched_barrier(0);
+    store(buf ^ 1, kt + 1);
     __syncthreads();
   }
 
