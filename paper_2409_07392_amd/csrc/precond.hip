@@ -484,6 +484,114 @@ __global__ __launch_bounds__(256) void k_sweep_blk(const double* __restrict__ P,
     }
 }
 
+// The sweep for blocks too large for registers (d > 256): block kb is copied to Pinv and swept
+// there in global memory, 16 pivots at a time.  With the block partitioned at pivots K as
+// [[K, B^T], [B, D]], sweeping K leaves [[-K^-1, K^-1 B^T], [B K^-1, D - B K^-1 B^T]].  The 16
+// rows of K are staged in LDS twice: as loaded (Bo = [K, B^T], whose columns outside K are B^T)
+// and swept pivot by pivot (Rs, ending as [-K^-1, K^-1 B^T]); then every row outside K is updated
+// from LDS, D[i][j] -= sum_m Bo[m][i] Rs[m][j] and A[i][k] = Rs[k][i] for k in K (the block stays
+// symmetric), four rows by four columns per thread, and the rows of K are written from Rs.
+// Before pivot p is swept, its staged row holds column p of the Schur complement, so the
+// Cholesky factor's column p is that row over sqrt(pivot) (written to P when asked).  After all
+// pivots the block holds -P^-1.  LDS: (33 d + 16) doubles (99 KB at d = 384).
+__global__ __launch_bounds__(256) void k_sweep_glb(double* __restrict__ P, double* __restrict__ Pinv,
+                                                   int d, int32_t* bad, int write_l) {
+  extern __shared__ __align__(16) double sw_lds[];
+  double* Bo = sw_lds;             // [16][d] rows of K as loaded
+  double* Rs = sw_lds + 16 * d;    // [16][d] rows of K as swept
+  double* Rm = sw_lds + 32 * d;    // [d] pivot row before its sweep
+  double* Cp = sw_lds + 33 * d;    // [16] pivot column before its sweep
+  const int kb = blockIdx.x, tid = threadIdx.x;
+  double* L = P + (int64_t)kb * d * d;
+  double* A = Pinv + (int64_t)kb * d * d;
+  for (int64_t e = tid; e < (int64_t)d * d; e += 256) A[e] = L[e];
+  __syncthreads();
+  const int nq = (d + 3) / 4;            // 4 x 4 tiles of the block
+  for (int k0 = 0; k0 < d; k0 += 16) {
+    const int nb = d - k0 < 16 ? d - k0 : 16;
+    for (int e = tid; e < nb * d; e += 256) {
+      const int m = e / d, j = e - m * d;
+      const double v = A[(int64_t)(k0 + m) * d + j];
+      Bo[m * d + j] = v;
+      Rs[m * d + j] = v;
+    }
+    __syncthreads();
+    for (int m = 0; m < nb; ++m) {
+      const int pc = k0 + m;
+      const double piv = Rs[m * d + pc];
+      if (!(piv > 0.0)) {
+        if (tid == 0) atomicMin(bad, kb);
+        return;
+      }
+      const double ip = 1.0 / piv;
+      const double rs = write_l ? 1.0 / sqrt(piv) : 0.0;
+      // the pivot row and column as they stand, so that every staged element can then be
+      // updated in place by the one thread that owns it
+      for (int j = tid; j < d; j += 256) {
+        const double v = Rs[m * d + j];
+        Rm[j] = v;
+        if (write_l && j >= pc) L[(int64_t)j * d + pc] = v * rs;   // factor column pc
+      }
+      if (tid < nb) Cp[tid] = Rs[tid * d + pc];
+      __syncthreads();
+      for (int e = tid; e < nb * d; e += 256) {
+        const int r = e / d, j = e - r * d;
+        double v;
+        if (r == m) v = j == pc ? -ip : Rm[j] * ip;
+        else if (j == pc) v = Cp[r] * ip;
+        else v = Rs[e] - Cp[r] * Rm[j] * ip;
+        Rs[e] = v;
+      }
+      __syncthreads();
+    }
+    // rows outside K: D -= B K^-1 B^T, and the columns of K from Rs; 4 x 4 tiles
+    for (int t = tid; t < nq * nq; t += 256) {
+      const int i0 = 4 * (t / nq), j0 = 4 * (t % nq);
+      double acc[4][4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+      for (int m = 0; m < nb; ++m) {
+        double bi[4], rj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          bi[u] = i0 + u < d ? Bo[m * d + i0 + u] : 0.0;
+          rj[u] = j0 + u < d ? Rs[m * d + j0 + u] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(bi[u], rj[v], acc[u][v]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u;
+        if (i >= d) continue;
+        const bool iin = i >= k0 && i < k0 + nb;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int j = j0 + v;
+          if (j >= d) continue;
+          const bool jin = j >= k0 && j < k0 + nb;
+          double* a = A + (int64_t)i * d + j;
+          if (iin) *a = Rs[(i - k0) * d + j];
+          else if (jin) *a = Rs[(j - k0) * d + i];
+          else *a -= acc[u][v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)d * d; e += 256) {
+    A[e] = -A[e];
+    if (write_l) {
+      const int i = (int)(e / d), j = (int)(e - (int64_t)i * d);
+      if (j > i) L[e] = 0.0;
+    }
+  }
+}
+
 typedef void (*SweepBlkKernel)(const double*, double*, int, int32_t*);
 
 static SweepBlkKernel pick_sweep_blk(int d) {
@@ -545,6 +653,25 @@ SyrkShape syrk_shape(int prec, int c) {
   return SyrkShape{4, 2, pnw};
 }
 
+// Blocks of 256 < d <= kSweepGlbMaxD go to the global-memory sweep (its LDS, (33 d + 16) doubles,
+// fits the 160 KB of a CU up to there); larger ones to the column-at-a-time factor and inverse.
+constexpr int kSweepGlbMaxD = 600;
+static bool g_sweep_glb_attr = false;
+
+static int sweep_glb_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool want_l,
+                            hipStream_t st) {
+  const int lds = (33 * d + 16) * (int)sizeof(double);
+  if (!g_sweep_glb_attr) {
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_sweep_glb,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (33 * kSweepGlbMaxD + 16) * (int)sizeof(double)));
+    g_sweep_glb_attr = true;
+  }
+  k_sweep_glb<<<c, 256, lds, st>>>(P, Pinv, d, bad, want_l ? 1 : 0);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
 template <typename T, int CMW, int WC>
 static void launch_syrk(Ctx* x, const double* omega, int64_t rps, hipStream_t st) {
   constexpr int PNW = sizeof(T) == 4 ? 4 : 2;
@@ -581,6 +708,8 @@ static int precond_t(Ctx* x, const double* omega, double shift, bool want_l, hip
   } else if (sw) {
     sw<<<c, threads, 0, st>>>(x->P, x->Pinv, d, &x->status->bad_block, want_l ? 1 : 0);
     FIRAL_LAUNCHED();
+  } else if (d <= kSweepGlbMaxD) {
+    FIRAL_CHECK(sweep_glb_launch(x->P, x->Pinv, d, c, &x->status->bad_block, want_l, st));
   } else {
     k_chol<<<c, 256, 0, st>>>(x->P, d, &x->status->bad_block);
     FIRAL_LAUNCHED();
@@ -621,6 +750,8 @@ int chol_blocks_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool
   } else if (sw) {
     sw<<<c, threads, 0, st>>>(P, Pinv, d, bad, want_l ? 1 : 0);
     FIRAL_LAUNCHED();
+  } else if (d <= kSweepGlbMaxD) {
+    FIRAL_CHECK(sweep_glb_launch(P, Pinv, d, c, bad, want_l, st));
   } else {
     k_chol<<<c, 256, 0, st>>>(P, d, bad);
     FIRAL_LAUNCHED();

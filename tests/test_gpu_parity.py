@@ -194,9 +194,12 @@ def test_hvp_is_deterministic():
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(2000, 50, 20, 5), (3001, 7, 100, 10), (517, 3, 37, 13),
                                    (700, 4, 130, 3), (900, 2, 200, 2), (800, 1, 300, 2),
+                                   (1000, 2, 384, 2), (1300, 3, 601, 2),
                                    (600, 3, 45, 40), (500, 5, 24, 70), (400, 2, 27, 130)])
 def test_precond_matches_oracle(prec, shape):
-    # class tiles of 32, 64 and 128 (the last ones partial), pair tiles cut by d
+    # class tiles of 32, 64 and 128 (the last ones partial), pair tiles cut by d; the factor
+    # by the sweeps in registers (d <= 256), the global-memory sweep (d = 300, 384) and the
+    # column-at-a-time factor (d = 601)
     n, nl, d, c = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=6)
     ctx, X, H = context(p, prec, 1)
@@ -216,10 +219,12 @@ def test_precond_matches_oracle(prec, shape):
     assert_close(host(Pinv), np.linalg.inv(P), TOL[prec] * max(10.0, 10 * kappa), "block inverse")
 
 
+@pytest.mark.parametrize("d", [6, 300])
 @pytest.mark.parametrize("want_L", [True, False])
-def test_precond_reports_non_spd_block(want_L):
-    # want_L=False: the inverse alone (the blocked sweep for d <= 128)
-    p = make_small(n=200, n_lab=3, d=6, c=4, s=1, seed=7)
+def test_precond_reports_non_spd_block(want_L, d):
+    # want_L=False: the inverse alone (the blocked sweep for d <= 128); d = 300: the
+    # global-memory sweep
+    p = make_small(n=200 if d < 100 else 700, n_lab=3, d=d, c=4, s=1, seed=7)
     H = p.H.copy()
     H[:, 2] = 0.0
     ctx = RelaxContext(dev(p.X, torch.float64), dev(H, torch.float64), p.n_pool, 1, "f64")
@@ -230,10 +235,12 @@ def test_precond_reports_non_spd_block(want_L):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(2000, 50, 20, 5), (3001, 7, 100, 10), (517, 3, 37, 13),
-                                   (777, 5, 128, 3), (600, 3, 45, 40), (300, 2, 1, 3)])
+                                   (777, 5, 128, 3), (600, 3, 45, 40), (300, 2, 1, 3),
+                                   (800, 1, 300, 2), (1300, 3, 520, 2)])
 def test_precond_inverse_alone_matches_oracle(prec, shape):
-    # without the factor, d <= 128 takes the blocked sweep (16-pivot blocks; d = 1, 37, 45:
-    # partial blocks padded with the identity, d = 128: eight full blocks)
+    # without the factor, d <= 128 takes the blocked sweep in registers (16-pivot blocks;
+    # d = 1, 37, 45: partial blocks padded with the identity, d = 128: eight full blocks), and
+    # d = 300, 520 the global-memory sweep (16-pivot panels, the last one partial)
     n, nl, d, c = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=8)
     ctx, X, H = context(p, prec, 1)
