@@ -219,14 +219,16 @@ int firal_profile_begin(firal_ctx ctx, int32_t kernel);
 int firal_profile_end(firal_ctx ctx, double* total_ms, int64_t* launches);
 
 /* Kernel-variant tuner (the tile plan of extension (2); usable on any context).  Times on this
- * context, for s probes, the product kernels (fused single pass where its plan fits, row-tiled)
- * and the PCG step forms (column-local, separate kernels), keeps the faster of each for the
- * context and remembers the choice for the process per bucket (precision, d, c, s, n_pool +
- * n_lab rounded up to a power of two); a bucket already tuned is applied without timing.
- * The context's work blocks and preconditioner are overwritten.  choice (host, may be NULL)
- * gets bit 0 = row-tiled product (and FP32 gradient), bit 1 = separate-kernel PCG, bit 2 =
- * fused product with two column blocks per wave (else one, the next row chunk fetched
- * ahead).  Synchronous. */
+ * context, for s probes, the product's tilings (the fused single pass with one or two 16-column
+ * blocks per wave and a target of 256, 512 or 1024 workgroups, which sets the rows each
+ * workgroup covers, wherever its plan fits; the row-tiled kernels) and the PCG step forms
+ * (column-local, separate kernels), keeps the fastest of each for the context and remembers
+ * the choice for the process per bucket (precision, d, c, s, n_pool + n_lab rounded up to a
+ * power of two); a bucket already tuned is applied without timing.  The context's work blocks
+ * and preconditioner are overwritten.  choice (host, may be NULL) gets bit 0 = row-tiled
+ * product (and FP32 gradient), bit 1 = separate-kernel PCG, bit 2 = fused product with two
+ * column blocks per wave (else one, the next row chunk fetched ahead), bits 3-4 = code k of
+ * the fused workgroup target 256 << k.  Synchronous. */
 int firal_autotune(firal_ctx ctx, int32_t s, int32_t* choice, void* stream);
 
 /* Batch of independent Relax problems (extension (2)): one Relax iteration (Algorithm 2) of

@@ -194,7 +194,8 @@ class RelaxContext:
         """Time the kernel variants on this problem and keep the faster ones (firal_autotune).
 
         Returns the choice bits: 1 = row-tiled product, 2 = separate-kernel PCG, 4 = fused
-        product with two column blocks per wave.  The work blocks and preconditioner of the
+        product with two column blocks per wave, bits 3-4 = code k of the fused product's
+        workgroup target 256 << k.  The work blocks and preconditioner of the
         context are overwritten."""
         s = self.s_max if s is None else int(s)
         ch = _lib.ctypes.c_int32()

@@ -235,19 +235,25 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   // the switch is off unless asked for.
   const char* sw = getenv("FIRAL_BF3_SWITCH");
   x->bf3_switch = sw ? atof(sw) : 0.0;
+  const char* wgs = getenv("FIRAL_FUSED_WGS");
+  x->fused_wgs = wgs ? std::min(std::max(atoi(wgs), 1), kFusedMaxWgs) : 256;
   x->fused_part_elems = 0;
-  const int ncb_set = x->fused_max_ncb;
-  for (int ncb_try = 1; ncb_try <= 2; ++ncb_try) {   // room for either tile width (the tuner)
-    x->fused_max_ncb = ncb_try;
-    for (int s = 1; s <= s_max; ++s) {
-      for (int precise = 0; precise < 2; ++precise) {
-        FusedPlan fp;
-        if (fused_plan(x, s, x->N, &fp, precise != 0))
-          x->fused_part_elems = std::max(x->fused_part_elems, fp.part_elems);
+  const int ncb_set = x->fused_max_ncb, wgs_set = x->fused_wgs;
+  for (int ncb_try = 1; ncb_try <= 2; ++ncb_try) {   // room for every tile shape the tuner tries
+    for (int wgs_try : {wgs_set, kFusedMaxWgs}) {
+      x->fused_max_ncb = ncb_try;
+      x->fused_wgs = wgs_try;
+      for (int s = 1; s <= s_max; ++s) {
+        for (int precise = 0; precise < 2; ++precise) {
+          FusedPlan fp;
+          if (fused_plan(x, s, x->N, &fp, precise != 0))
+            x->fused_part_elems = std::max(x->fused_part_elems, fp.part_elems);
+        }
       }
     }
   }
   x->fused_max_ncb = ncb_set;
+  x->fused_wgs = wgs_set;
 
   const size_t es = x->esize;
   int rc = FIRAL_OK;

@@ -10,10 +10,11 @@
 // nodes, and the iteration index t read from and advanced in device memory, so one graph
 // replayed T times runs iterations t0 .. t0 + T - 1 of every problem.
 //
-// The tuner times, on the problem itself, the candidate product kernels (fused single pass or
-// row-tiled) and PCG step forms (column-local or separate kernels), keeps the fastest of each,
-// and remembers the choice per bucket (precision, d, c, s, n rounded to a power of two) for
-// the process.
+// The tuner times, on the problem itself, the candidate product tilings (the fused single pass
+// with one or two 16-column blocks per wave and 256, 512 or 1024 workgroups, i.e. rows per
+// workgroup, wherever its plan fits; or the row-tiled kernels) and PCG step forms
+// (column-local or separate kernels), keeps the fastest of each, and remembers the choice per
+// bucket (precision, d, c, s, n rounded to a power of two) for the process.
 #include <algorithm>
 #include <cmath>
 #include <map>
@@ -35,7 +36,8 @@ typedef std::tuple<int, int, int, int, int> TuneKey;   // prec, d, c, s, log2 N 
 
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;   // choice bits: 1 = row-tiled product, 2 = separate-kernel
-                                 // PCG, 4 = fused product with two column blocks per wave
+                                 // PCG, 4 = fused product with two column blocks per wave,
+                                 // bits 3-4 = fused workgroup target (256 << code)
 
 TuneKey tune_key(const Ctx* x, int s) {
   const int nb = (int)std::ceil(std::log2((double)std::max<int64_t>(x->N, 1)));
@@ -46,6 +48,7 @@ void apply_choice(Ctx* x, int choice) {
   x->force_tiled = (choice & 1) != 0;
   x->force_multik = (choice & 2) != 0;
   x->fused_max_ncb = (choice & 4) ? 2 : 1;
+  x->fused_wgs = 256 << ((choice >> 3) & 3);
 }
 
 // Milliseconds per call of fn (after one untimed call), events on st.
@@ -88,19 +91,33 @@ int autotune(Ctx* x, int s, hipStream_t st, int* choice_out) {
     }
   }
   FIRAL_CHECK(probes_launch(x, 1, 1, s, x->V, st));
-  // product: fused with one or two column blocks per wave (where its plan fits), row-tiled
-  const int prod_bits[3] = {0, 4, 1};
+  // product: the fused tilings whose plans fit (distinct plans only: the row ranges are capped
+  // by the row chunks), then the row-tiled kernels
+  std::vector<int> cands;
+  std::vector<std::pair<int, int>> plans;   // (column blocks per wave, row ranges)
+  for (int ncb_bit = 0; ncb_bit <= 4; ncb_bit += 4)
+    for (int code = 0; (256 << code) <= kFusedMaxWgs; ++code) {
+      const int bits = ncb_bit | (code << 3);
+      apply_choice(x, bits);
+      FusedPlan fp;
+      if (!fused_plan(x, s, x->N, &fp, false) || fp.part_elems > x->fused_part_elems) continue;
+      const std::pair<int, int> key(fp.ncb, fp.n_splits);
+      if (std::find(plans.begin(), plans.end(), key) != plans.end()) continue;
+      plans.push_back(key);
+      cands.push_back(bits);
+    }
+  cands.push_back(1);
   double best = 0.0;
-  int prod = 0;
-  for (int v = 0; v < 3; ++v) {
-    apply_choice(x, prod_bits[v]);
+  int prod = cands[0];
+  for (size_t v = 0; v < cands.size(); ++v) {
+    apply_choice(x, cands[v]);
     double t = 0.0;
     FIRAL_CHECK(time_ms([&] { return hvp_launch(x, nullptr, x->N, 1e-3, x->V, x->W1, s,
                                                 skip_none(), st); },
                         3, st, &t));
     if (v == 0 || t < best) {
       best = t;
-      prod = prod_bits[v];
+      prod = cands[v];
     }
   }
   apply_choice(x, prod);

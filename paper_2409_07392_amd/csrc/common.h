@@ -80,6 +80,8 @@ struct Ctx {
   int64_t fused_part_elems;
   int fused_max_ncb;    // fused product: column blocks per wave, 2 (wide tiles) or 1 (two
                         // workgroups' registers per CU, next chunk fetched ahead)
+  int fused_wgs;        // fused product: workgroups a launch aims for (row ranges x column
+                        // tiles; 0 = 256); firal_autotune chooses it
   int force_tiled;      // product and FP32 gradient: the row-tiled kernels even where the
                         // fused ones fit
   int force_multik;     // PCG: separate kernels even where the column-local step fits
@@ -159,6 +161,8 @@ inline Ctx* C(firal_ctx p) { return reinterpret_cast<Ctx*>(p); }
 
 // ------------------------------------------------------------ constants
 constexpr int kBlock = 256;
+// largest workgroup target of the fused product (its partial-sum buffer is sized for it)
+constexpr int kFusedMaxWgs = 1024;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -819,7 +819,7 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p, bool precise)
   }
   if (lds_bytes > 156 * 1024) return false;   // the kernel's own static LDS needs a little
   const int64_t chunks = (n_rows + kRC - 1) / kRC;
-  const int target_wgs = 256;
+  const int target_wgs = x->fused_wgs > 0 ? x->fused_wgs : 256;
   int64_t splits = std::max<int64_t>(1, std::min<int64_t>(chunks, target_wgs / n_ct));
   const int64_t rps = ((n_rows + splits - 1) / splits + kRC - 1) / kRC * kRC;
   splits = (n_rows + rps - 1) / rps;
