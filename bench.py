@@ -683,11 +683,17 @@ def batch_workload(args):
         ctx.autotune(p.s)   # the batch's variants (same bucket)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    by_bucket = {}   # (d, c) -> [problems, seconds, rows]: where the sequential time goes
     for p, ctx, w in B:
         beta0 = default_beta0(p.n_pool, p.T)
+        tp = time.perf_counter()
         for t in range(1, iters + 1):
             ctx.relax_step(w, p.b, p.lam, beta0, p.probe_seed, t, p.s, p.tol, max_iter, True)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        e = by_bucket.setdefault("d%d_c%d" % (p.d, p.c), [0, 0.0, 0])
+        e[0] += 1
+        e[1] += time.perf_counter() - tp
+        e[2] += p.n_pool + p.n_lab
     t_seq = time.perf_counter() - t0
     maxdiff = max(float((a[2] - b[2]).abs().max()) for a, b in zip(A, B))
     flops = sum(4.0 * (p.n_pool + p.n_lab) * p.c * p.d * p.s for p in plist)
@@ -703,6 +709,8 @@ def batch_workload(args):
         "max_abs_weight_difference_batched_vs_one_at_a_time": maxdiff,
         "mean_cg_iters_last_iteration": float(sum(a + b for a, b in cg) / (2 * len(cg))),
         "sum_product_gflop_per_iteration_all_problems": flops / 1e9,
+        "one_at_a_time_by_bucket": {k: {"problems": v[0], "seconds": v[1], "rows": v[2]}
+                                    for k, v in sorted(by_bucket.items())},
     }
     batch.close()
     print(json.dumps(res))

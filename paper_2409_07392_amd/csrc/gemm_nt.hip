@@ -4,14 +4,14 @@
 //
 // Per chunk of R rows (rows r0 .. r0 + R):
 //   k_nt_xv     G = X V^T[n][.] (X row-major; V^T: the probe block transposed once per call),
-//               scaled by the row weights and the row's probabilities and stored transposed,
-//               F^T[n][r] = omega_r G[r][n] h_rk (k = n % c); its epilogue also forms, per row
-//               and tile, beta_part[p][w][r] = sum over the tile's columns of F (the tiles of
-//               probe p are its column windows w: c > 128, so a tile never mixes probes)
+//               stored transposed and scaled by the row weights, E^T[n][r] = omega_r G[r][n]; its
+//               epilogue also forms, per row and tile, beta_part[p][w][r] = sum over the tile's
+//               columns of E h (the tiles of probe p are its column windows w: c > 128, so a
+//               tile never mixes probes)
 //   k_nt_alpha  beta[p][r] = sum_w beta_part[p][w][r] (FP64, fixed order) = omega_r alpha_rp
 //   k_nt_xtg    part[sp][a][n] (+)= sum_r X^T[a][r] G'^T[n][r] over the split's rows, with the
-//               row step of Lemma 1, G' = omega (G - alpha) h = F - beta h, formed (one FMA) while
-//               F^T is staged (X^T and H^T: transposed FP32 copies made at context creation)
+//               row step of Lemma 1, G' = omega (G - alpha) h = (E - beta) h, applied while E^T
+//               is staged (X^T and H^T: transposed FP32 copies made at context creation)
 // and the split sums are reduced in a fixed order (hvp.hip).
 //
 // MFMA: v_mfma_f32_16x16x4f32.  Within a 16-deep k group the four instructions q = 0..3 take
@@ -126,8 +126,8 @@ __device__ __forceinline__ void nt_xv_epilogue(const f32x4 (&acc)[4][4], float* 
                                                float* __restrict__ GT, int64_t ldg,
                                                float* __restrict__ apart) {
   // Epilogue.  Lane (g, li) of block (i, j) holds G[r][n] for r = row0 + wm + 16 i + 4 g + v,
-  // n = col0 + wn + 16 j + li (v = 0..3).  (1) F^T = (omega G h)^T as 16-byte stores of four
-  // rows; (2) per row the sum over this wave's columns of F, then over the 16 lanes of a column
+  // n = col0 + wn + 16 j + li (v = 0..3).  (1) E^T = (omega G)^T as 16-byte stores of four rows;
+  // (2) per row the sum over this wave's columns of E h, then over the 16 lanes of a column
   // group, then over the two waves of a row band through LDS, into beta_part[p][w][r].
   float* red = nt_lds;   // [2][kNtBM]: the main buffers are free after the last barrier
   // two halves of two row blocks each: every load of a half first (omega of the lane's 8 rows,
@@ -162,14 +162,13 @@ __device__ __forceinline__ void nt_xv_epilogue(const f32x4 (&acc)[4][4], float* 
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int nl = wn + 16 * j + li;              // column within the window
-        f4 e;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) e[v] = om[ii][v] * acc[i][j][v] * hq[ii][j][v];
+        const f4 e = f4{om[ii][0] * acc[i][j][0], om[ii][1] * acc[i][j][1],
+                        om[ii][2] * acc[i][j][2], om[ii][3] * acc[i][j][3]};
         if (nl < width && r < R) {
           const int64_t n = n0 + nl;
           // R is a multiple of 4 except at the end of the rows; guard the last vector.  The
-          // stores are non-temporal: F^T is read back by the second kernel from HBM (a chunk's
-          // F^T is far larger than L2 and the MALL), and should not evict X, V^T and h from L2
+          // stores are non-temporal: E^T is read back by the second kernel from HBM (a chunk's
+          // E^T is far larger than L2 and the MALL), and should not evict X, V^T and h from L2
           if (r + 3 < R) {
             __builtin_nontemporal_store(e, reinterpret_cast<f4*>(GT + n * ldg + r));
           } else {
@@ -178,7 +177,7 @@ __device__ __forceinline__ void nt_xv_epilogue(const f32x4 (&acc)[4][4], float* 
               if (r + v < R) GT[n * ldg + r + v] = e[v];
           }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) t[v] += e[v];
+          for (int v = 0; v < 4; ++v) t[v] = fmaf(e[v], hq[ii][j][v], t[v]);
         }
       }
 #pragma unroll
@@ -326,7 +325,7 @@ __global__ __launch_bounds__(256) void k_nt_alpha(const float* __restrict__ apar
   beta[(int64_t)p * ldg + r] = (float)a;
 }
 
-// F^T and h of CPT consecutive columns nb .. nb + CPT - 1 of one window (the class of nb is
+// E^T and h of CPT consecutive columns nb .. nb + CPT - 1 of one window (the class of nb is
 // k_first) and beta of their probe p, at rows r .. r + 3.  Addresses are clamped into the valid
 // columns and rows (r0 is a valid row), so every value is finite; nt_store_g zeroes the rows
 // beyond re.
@@ -345,7 +344,7 @@ __device__ __forceinline__ void nt_load_e(const float* __restrict__ GT, int64_t 
   }
   bt = *reinterpret_cast<const f4*>(beta + (int64_t)p * ldg + rr);
 }
-// G'^T = F^T - beta h of the CPT columns (rows jl .. jl + CPT - 1 of the LDS tile b[n][k], row
+// G'^T = (E^T - beta) h of the CPT columns (rows jl .. jl + CPT - 1 of the LDS tile b[n][k], row
 // stride SK) at k offset rk; rows at or beyond re stage as zero (re is a multiple of 4 except at
 // the end of the rows).  Columns beyond the window (t >= nvalid) stage the finite values of the
 // clamped loads: they only reach output columns that the epilogue drops.
@@ -359,7 +358,7 @@ __device__ __forceinline__ void nt_store_g(float* __restrict__ b, int jl, int rk
     f4 x;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float y = fmaf(-bt[v], hv[t][v], gv[t][v]);
+      const float y = (gv[t][v] - bt[v]) * hv[t][v];
       x[v] = full || r + v < re ? y : 0.f;
     }
     *reinterpret_cast<f4*>(b + (jl + t) * SK + rk) = x;
@@ -367,10 +366,10 @@ __device__ __forceinline__ void nt_store_g(float* __restrict__ b, int jl, int rk
 }
 
 // Kernel 2.  Output tiles: a-tile mt (kNtBM values of a) x column tile ct (a column window of one
-// probe p, as in kernel 1), split sp of the chunk's rows.  B is staged as
-// G'^T[n][r] = F^T[n][r] - beta[p][r] h_rk (k = n % c).  Thread tid stages columns
-// n0 + CPT (tid / (KS / 4)) + t, t < CPT, at rows 4 (tid % (KS / 4)) .. + 3 of the stage; F^T, h
-// and beta are fetched before the stage's products and G' is formed and stored after them.
+// probe, as in kernel 1), split sp of the chunk's rows.  B is staged as G'^T[n][r] = (E^T[n][r] - beta[p][r]) h_rk with
+// p = n / c, k = n % c.  Thread tid stages columns n0 + 4 (tid / 8) + t, t = 0..3, at rows
+// 4 (tid % 8) of the stage: E^T and h are fetched before the stage's products, beta (at most two
+// probes among four consecutive columns) after them.
 template <int KS, int MINB>
 __global__ __launch_bounds__(kNtWG, MINB) void k_nt_xtg(
     const float* __restrict__ XT, int64_t ldx, int d, const float* __restrict__ GT, int64_t ldg,
@@ -454,7 +453,7 @@ __global__ __launch_bounds__(kNtWG, MINB) void k_nt_xtg(
 // lanes of a fragment read fall in distinct banks).  Lane (g, li) reads k = 8 g .. 8 g + 7 of
 // row li: one 16-byte read per plane and operand feeds the three products of a block.
 // Operands: k_nt3_xv takes X from the context's hi/lo planes and V^T from planes made once per
-// call; k_nt3_xtg takes X^T from the context's transposed planes and splits G' = F - beta h as
+// call; k_nt3_xtg takes X^T from the context's transposed planes and splits G' = (E - beta) h as
 // it is staged.  The epilogues are those of the FP32 kernels.
 constexpr size_t kNt3Lds = (size_t)2 * 2 * (kNtBM + kNtBN) * 32 * 2;   // 65,536 bytes
 constexpr size_t kNt3XvLds = kNt3Lds / 2;   // single-buffered first contraction
@@ -532,7 +531,7 @@ __global__ __launch_bounds__(kNtWG, 3) void k_nt3_xv(
   if (skip_now(skip)) return;
   extern __shared__ __align__(16) float nt_lds[];
   // one buffer per operand (two planes): 32 KB, three workgroups per CU, whose epilogues (the
-  // F^T stores) overlap the others' main loops better than two double-buffered workgroups'
+  // E^T stores) overlap the others' main loops better than two double-buffered workgroups'
   __bf16* As = reinterpret_cast<__bf16*>(nt_lds);      // [2 planes][128][32]
   __bf16* Bs = As + 2 * kNtBM * 32;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -585,7 +584,7 @@ __global__ __launch_bounds__(kNtWG, 3) void k_nt3_xv(
                      HT, ldh, omega, GT, ldg, apart);
 }
 
-// G'^T = F^T - beta[p] h of four columns at rows r .. r + 3 (rows at or beyond re as zero;
+// G'^T = (E^T - beta[p]) h of four columns at rows r .. r + 3 (rows at or beyond re as zero;
 // columns beyond the window as in nt_store_g), split into hi/lo bf16 and stored into the planes
 // of the LDS tile (row 4 (tid / 8) + t, k 4 (tid % 8)).
 __device__ __forceinline__ void nt3_store_g(__bf16* __restrict__ b, int tid, int64_t r, int64_t re,
@@ -598,7 +597,7 @@ __device__ __forceinline__ void nt3_store_g(__bf16* __restrict__ b, int tid, int
     bf16x4 h4, l4;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const float y = fmaf(-bt[v], hv[t][v], gv[t][v]);
+      const float y = (gv[t][v] - bt[v]) * hv[t][v];
       const float x = full || r + v < re ? y : 0.f;
       const __bf16 h = (__bf16)x;
       h4[v] = h;
@@ -789,7 +788,7 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
   } else {
     FIRAL_CHECK(nt_transpose(B, d, SC, SC, VT, d, st));
   }
-  // buffers: F^T [s c][ldg], beta_part [s][nw][ldg], beta [s][ldg]
+  // buffers: E^T [s c][ldg], beta_part [s][nw][ldg], beta [s][ldg]
   const int64_t ldg = nt_ld(x->chunk_rows);
   float* GT = (float*)x->G;
   float* apart = (float*)x->ntpart;
