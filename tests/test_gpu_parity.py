@@ -194,12 +194,12 @@ def test_hvp_is_deterministic():
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(2000, 50, 20, 5), (3001, 7, 100, 10), (517, 3, 37, 13),
                                    (700, 4, 130, 3), (900, 2, 200, 2), (800, 1, 300, 2),
-                                   (1000, 2, 384, 2), (1300, 3, 601, 2),
+                                   (700, 2, 257, 2), (1000, 2, 384, 2), (1300, 3, 601, 2),
                                    (600, 3, 45, 40), (500, 5, 24, 70), (400, 2, 27, 130)])
 def test_precond_matches_oracle(prec, shape):
     # class tiles of 32, 64 and 128 (the last ones partial), pair tiles cut by d; the factor
-    # by the sweeps in registers (d <= 256), the global-memory sweep (d = 300, 384) and the
-    # column-at-a-time factor (d = 601)
+    # by the sweeps in registers (d <= 256), the global-memory sweep (d = 257: one pivot in its
+    # last panel; 300, 384) and the column-at-a-time factor (d = 601)
     n, nl, d, c = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=6)
     ctx, X, H = context(p, prec, 1)
