@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--study", default="fig1,fig4,fig5",
                     help="--workload studies: comma-separated subset of fig1, fig4, fig5")
     ap.add_argument("--no-round", action="store_true", help="skip the Round-step leg")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="configuration 3: the product legs only (no objective, adjoint or "
+                         "gradient-error runs)")
     ap.add_argument("--round-rounds", type=int, default=0,
                     help="configurations 3/4: Round-step rounds timed per decision precision")
     ap.add_argument("--round-only", action="store_true",
@@ -808,13 +811,19 @@ def workload3(args):
         return
     legs, grads = {}, {}
     n_cg = 20
-    for prec in ("f32", "bf16x3", "f64"):
+    for prec in ("f32", "bf16x3") if args.no_adjoint else ("f32", "bf16x3", "f64"):
         dt = torch.float64 if prec == "f64" else torch.float32
         ctx = RelaxContext(p.X.to(dt).contiguous(), p.H.to(dt).contiguous(), p.n_pool, p.s, prec)
         V = ctx.probes(p.probe_seed, 1, p.s)
         if prec != "f64":
-            log(f"{prec}: products and the objective with its adjoint")
-            leg, _ = product_leg(ctx, p, prec, 20, 2, 3)
+            log(f"{prec}: products" + ("" if args.no_adjoint else " and the objective with its adjoint"))
+            leg, _ = product_leg(ctx, p, prec, args.steps, args.warmup, args.prof_reps)
+            legs[prec] = leg
+            if args.no_adjoint:
+                ctx.close()
+                del ctx
+                torch.cuda.empty_cache()
+                continue
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             f, _, info = ctx.sampled_objective(z, p.lam, V, tol=p.tol, max_iter=1000, project=True)
@@ -822,16 +831,16 @@ def workload3(args):
             leg["objective_and_adjoint_ms"] = (time.perf_counter() - t0) * 1e3
             leg["cg_iters"] = list(info["cg_iters"])
             leg["f"] = f
-            legs[prec] = leg
         log(f"{prec}: adjoint gradient at {n_cg} fixed CG iterations")
         _, gv, _ = ctx.sampled_objective(z, p.lam, V, tol=0.0, max_iter=n_cg, project=True)
         grads[prec] = gv.cpu().numpy()
         ctx.close()
         del ctx
         torch.cuda.empty_cache()
-    ref = np.linalg.norm(grads["f64"])
-    for prec in ("f32", "bf16x3"):
-        legs[prec]["rel_grad_err_vs_f64"] = float(np.linalg.norm(grads[prec] - grads["f64"]) / ref)
+    if not args.no_adjoint:
+        ref = np.linalg.norm(grads["f64"])
+        for prec in ("f32", "bf16x3"):
+            legs[prec]["rel_grad_err_vs_f64"] = float(np.linalg.norm(grads[prec] - grads["f64"]) / ref)
     res = {"metric": METRIC, "workload": "configuration 3",
            "config": {"n_pool": p.n_pool, "n_lab": p.n_lab, "d": p.d, "c": p.c, "s": p.s,
                       "b": p.b, "tol": p.tol, "z": "b x Dirichlet(1), drawn on the GPU",

@@ -272,10 +272,12 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
     const int64_t ldg = nt_ld(rows), nw = nt_windows(c);
     if (prec == FIRAL_F32) ALLOC(x->XTf, x->ldn * d * 4);
     ALLOC(x->HTf, x->ldn * c * 4);
-    ALLOC(x->VTf, blk * 4);
+    if (prec != FIRAL_BF16X3) ALLOC(x->VTf, blk * 4);
     ALLOC(x->ntpart, ((int64_t)s_max * nw * ldg + (int64_t)s_max * ldg) * 4);
   }
   if (prec == FIRAL_BF16X3) {
+    // hi/lo planes of V^T for two probe blocks (the gradient's U and W; products use the first)
+    ALLOC(x->VTf, blk * 8);
     x->ldt = cdiv(x->N, 8) * 8;
     ALLOC(x->Xhi, x->N * d * 2);
     ALLOC(x->Xlo, x->N * d * 2);

@@ -308,6 +308,8 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p, bool precise 
 template <typename T>
 int reduce_parts_launch(const T* part, int64_t n, int P, double shift, const T* B, T* out,
                         Skip skip, hipStream_t st);
+// hi/lo bf16 planes of V^T, (s c) x d, for a probe block B (d x s c, row-major), split once
+int nt3_split_vt(const float* B, int d, int SC, __bf16* VTh, __bf16* VTl, hipStream_t st);
 int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_rows, double shift,
                      const float* B, float* out, int s, Skip skip, hipStream_t st);
 

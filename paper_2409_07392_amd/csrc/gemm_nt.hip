@@ -737,6 +737,13 @@ bool g_nt_attr = false;
 
 }  // namespace
 
+int nt3_split_vt(const float* B, int d, int SC, __bf16* VTh, __bf16* VTl, hipStream_t st) {
+  dim3 grid((unsigned)cdiv(d, 32), (unsigned)cdiv(SC, 32));
+  k_nt3_transpose_split<<<grid, 256, 0, st>>>(B, d, SC, VTh, VTl);
+  FIRAL_LAUNCHED();
+  return FIRAL_OK;
+}
+
 // The wide path covers FP32 contexts with d % 4 == 0 and bf16x3 contexts with d % 8 == 0, both
 // with d > 128 and c > 128; its transposed FP32 copies of H (and for FP32 of X; bf16x3 contexts
 // read the transposed hi/lo planes of X) are made at creation when this holds.
@@ -782,9 +789,7 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
   __bf16* VTh = (__bf16*)x->VTf;
   __bf16* VTl = VTh + (int64_t)SC * d;
   if (bf3) {
-    dim3 grid((unsigned)cdiv(d, 32), (unsigned)cdiv(SC, 32));
-    k_nt3_transpose_split<<<grid, 256, 0, st>>>(B, d, SC, VTh, VTl);
-    FIRAL_LAUNCHED();
+    FIRAL_CHECK(nt3_split_vt(B, d, SC, VTh, VTl, st));
   } else {
     FIRAL_CHECK(nt_transpose(B, d, SC, SC, VT, d, st));
   }

@@ -166,7 +166,8 @@ __device__ __forceinline__ bf16x8 bf16_zero8() {
 template <typename T, int WM, int WN, int MODE, bool BF3>
 __global__ __launch_bounds__(256, 2) void k_xv(
     const T* __restrict__ X, const __bf16* __restrict__ Xh, const __bf16* __restrict__ Xl, int d,
-    int64_t R, const T* __restrict__ B, const T* __restrict__ H, const double* __restrict__ omega,
+    int64_t R, const T* __restrict__ B, const __bf16* __restrict__ Vh,
+    const __bf16* __restrict__ Vl, const T* __restrict__ H, const double* __restrict__ omega,
     ColMap cm, T* __restrict__ Gout, const T* __restrict__ Gin, double* __restrict__ dpart,
     Skip skip) {
   if (skip_now(skip)) return;
@@ -191,13 +192,13 @@ __global__ __launch_bounds__(256, 2) void k_xv(
     for (int j = 0; j < WN; ++j) acc[i][j] = M::zero();
 
   if constexpr (BF3) {
-    // X from its pre-split planes (16-byte chunks of 8 k), B split once while staged
+    // X and B from their pre-split planes (16-byte chunks of 8 k): X's made at context
+    // creation, B's (as V^T, (s c) x d) once per call
     static_assert(TM * 4 == 512 && TN * 4 == 512, "two staging tasks per thread and operand");
     __bf16* Ab = reinterpret_cast<__bf16*>(lds_raw);   // [2 bufs][2 planes][TM][32]
     __bf16* Bb = Ab + 2 * 2 * TM * 32;                 // [2 bufs][2 planes][TN][32]
     const bool xvec = (d & 7) == 0;
-    bf16x8 pah[2], pal[2];
-    float pb[2][8];
+    bf16x8 pah[2], pal[2], pbh[2], pbl[2];
     auto load = [&](int kt) {
       const int k0 = kt * 32;
 #pragma unroll
@@ -224,10 +225,22 @@ __global__ __launch_bounds__(256, 2) void k_xv(
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int n = tid & (TN - 1), ch = (tid / TN) + 2 * i;
+        const int k = k0 + 8 * ch;
+        pbh[i] = bf16_zero8();
+        pbl[i] = bf16_zero8();
+        if (n < width && k < d) {
+          const int64_t o = (int64_t)(col0 + n) * d + k;
+          if (xvec) {
+            pbh[i] = *reinterpret_cast<const bf16x8*>(Vh + o);
+            pbl[i] = *reinterpret_cast<const bf16x8*>(Vl + o);
+          } else {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int k = k0 + 8 * ch + u;
-          pb[i][u] = (k < d && n < width) ? (float)B[(int64_t)k * SC + col0 + n] : 0.0f;
+            for (int u = 0; u < 8; ++u)
+              if (k + u < d) {
+                pbh[i][u] = Vh[o + u];
+                pbl[i][u] = Vl[o + u];
+              }
+          }
         }
       }
     };
@@ -243,10 +256,8 @@ __global__ __launch_bounds__(256, 2) void k_xv(
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const int n = tid & (TN - 1), ch = (tid / TN) + 2 * i;
-        bf16x8 h, l;
-        split8(pb[i], h, l);
-        *reinterpret_cast<bf16x8*>(b + pl_off(0, TN, n, ch)) = h;
-        *reinterpret_cast<bf16x8*>(b + pl_off(1, TN, n, ch)) = l;
+        *reinterpret_cast<bf16x8*>(b + pl_off(0, TN, n, ch)) = pbh[i];
+        *reinterpret_cast<bf16x8*>(b + pl_off(1, TN, n, ch)) = pbl[i];
       }
     };
     const int nk = (d + 31) / 32;
@@ -329,7 +340,7 @@ __global__ __launch_bounds__(256, 2) void k_xv(
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
           const int n = lane + 64 * u;
-          if (n < width) go[n] = Cs[m * SCs + n];
+          if (n < width) __builtin_nontemporal_store(Cs[m * SCs + n], go + n);
         }
       }
     }
@@ -412,7 +423,9 @@ __global__ __launch_bounds__(256, 2) void k_xv(
 #pragma unroll
           for (int u = 0; u < NU; ++u) {
             const int n = lane + 64 * u;
-            if (n < width) go[n] = om * ((gv[it][u] - Al[m * kMaxPP + n / c]) * xv[it][u]);
+            if (n < width)
+              __builtin_nontemporal_store(om * ((gv[it][u] - Al[m * kMaxPP + n / c]) * xv[it][u]),
+                                          go + n);
           }
         }
       }
@@ -728,7 +741,8 @@ XRows<T> chunk_rows_of(const Ctx* x, int64_t r0) {
 // only; the gradient's use of this step is not timed).
 template <typename T, bool BF3>
 int xv_gamma(Ctx* x, bool prof, const ColMap& cm, const XRows<T>& xr, int d, int64_t R,
-             const T* B, const T* Hc, const double* om, T* G, Skip skip, hipStream_t st) {
+             const T* B, const __bf16* Vh, const __bf16* Vl, const T* Hc, const double* om, T* G,
+             Skip skip, hipStream_t st) {
   typedef Shape<T> S_;
   constexpr int TM1 = 32 * S_::WM1;
   const unsigned nwg = (unsigned)(cdiv(R, TM1) * cm.ntiles);
@@ -740,7 +754,7 @@ int xv_gamma(Ctx* x, bool prof, const ColMap& cm, const XRows<T>& xr, int d, int
     static bool attr = false;
     FIRAL_CHECK(set_lds(k, lds, attr));
     hipExtLaunchKernelGGL(k, dim3(nwg), dim3(256), lds, st, e0, e1, 0u, xr.x, xr.xh, xr.xl, d, R,
-                          B, Hc, om, cm, G, (const T*)nullptr, (double*)nullptr, skip);
+                          B, Vh, Vl, Hc, om, cm, G, (const T*)nullptr, (double*)nullptr, skip);
     FIRAL_LAUNCHED();
   } else {
     auto k = k_xv<T, S_::WM1, S_::WN1, kRaw, BF3>;
@@ -748,7 +762,7 @@ int xv_gamma(Ctx* x, bool prof, const ColMap& cm, const XRows<T>& xr, int d, int
     static bool attr = false;
     FIRAL_CHECK(set_lds(k, lds, attr));
     hipExtLaunchKernelGGL(k, dim3(nwg), dim3(256), lds, st, e0, e1, 0u, xr.x, xr.xh, xr.xl, d, R,
-                          B, Hc, om, cm, G, (const T*)nullptr, (double*)nullptr, skip);
+                          B, Vh, Vl, Hc, om, cm, G, (const T*)nullptr, (double*)nullptr, skip);
     FIRAL_LAUNCHED();
     const unsigned nb = (unsigned)cdiv(R * cm.s, 4);
     if (sizeof(T) == 4 && cm.c % 4 == 0 && cm.c <= 1024)
@@ -793,11 +807,19 @@ static int hvp_tiled_t(Ctx* x, const double* omega, int64_t n_rows, double shift
   constexpr size_t lds2 = xtg_lds_bytes<T, S_::WM2, S_::WN2, BF3>();
   static bool attr2 = false;
   FIRAL_CHECK(set_lds(k2, lds2, attr2));
+  // bf16x3: the hi/lo planes of V^T, made once for every chunk
+  __bf16* Vh = nullptr;
+  __bf16* Vl = nullptr;
+  if constexpr (BF3) {
+    Vh = (__bf16*)x->VTf;
+    Vl = Vh + (int64_t)SC * d;
+    if (n_rows > 0) FIRAL_CHECK(nt3_split_vt((const float*)B, d, SC, Vh, Vl, st));
+  }
 
   for (int64_t r0 = 0; r0 < n_rows; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, n_rows - r0);
     const XRows<T> xr = chunk_rows_of<T>(x, r0);
-    FIRAL_CHECK((xv_gamma<T, BF3>(x, true, cm, xr, d, R, B, H + r0 * c,
+    FIRAL_CHECK((xv_gamma<T, BF3>(x, true, cm, xr, d, R, B, Vh, Vl, H + r0 * c,
                                   omega ? omega + r0 : nullptr, G, skip, st)));
     // splits start on a multiple of 32 rows (the bf16x3 kernel reads X^T in 8-row chunks)
     const int64_t rps = cdiv(cdiv(R, S), 32) * 32;
@@ -836,13 +858,27 @@ static int grad_tiled_t(Ctx* x, const T* U, const T* W, int s, double* g, hipStr
   static bool attr = false;
   FIRAL_CHECK(set_lds(kd, lds, attr));
   T* G = (T*)x->G;
+  // bf16x3: hi/lo planes of W^T and U^T, made once for every chunk
+  __bf16 *Wh = nullptr, *Wl = nullptr, *Uh = nullptr, *Ul = nullptr;
+  if constexpr (BF3) {
+    const int64_t SC = (int64_t)s * c;
+    Wh = (__bf16*)x->VTf;
+    Wl = Wh + SC * d;
+    Uh = Wl + SC * d;
+    Ul = Uh + SC * d;
+    if (x->n_pool > 0) {
+      FIRAL_CHECK(nt3_split_vt((const float*)W, d, (int)SC, Wh, Wl, st));
+      FIRAL_CHECK(nt3_split_vt((const float*)U, d, (int)SC, Uh, Ul, st));
+    }
+  }
   for (int64_t r0 = 0; r0 < x->n_pool; r0 += x->chunk_rows) {
     const int64_t R = std::min<int64_t>(x->chunk_rows, x->n_pool - r0);
     const XRows<T> xr = chunk_rows_of<T>(x, r0);
     const T* Hc = (const T*)x->H + r0 * c;
-    FIRAL_CHECK((xv_gamma<T, BF3>(x, false, cm, xr, d, R, W, Hc, nullptr, G, skip_none(), st)));
+    FIRAL_CHECK((xv_gamma<T, BF3>(x, false, cm, xr, d, R, W, Wh, Wl, Hc, nullptr, G, skip_none(),
+                                  st)));
     kd<<<(unsigned)(cdiv(R, TM1) * cm.ntiles), 256, lds, st>>>(
-        xr.x, xr.xh, xr.xl, d, R, U, Hc, nullptr, cm, nullptr, G, x->gpart, skip_none());
+        xr.x, xr.xh, xr.xl, d, R, U, Uh, Ul, Hc, nullptr, cm, nullptr, G, x->gpart, skip_none());
     FIRAL_LAUNCHED();
     k_grad_sum<<<(unsigned)cdiv(R, 256), 256, 0, st>>>(x->gpart, R, cm.ntiles, s, g + r0);
     FIRAL_LAUNCHED();
