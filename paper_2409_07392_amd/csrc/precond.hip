@@ -485,30 +485,32 @@ __global__ __launch_bounds__(256) void k_sweep_blk(const double* __restrict__ P,
 }
 
 // The sweep for blocks too large for registers (d > 256): block kb is copied to Pinv and swept
-// there in global memory, 16 pivots at a time.  With the block partitioned at pivots K as
-// [[K, B^T], [B, D]], sweeping K leaves [[-K^-1, K^-1 B^T], [B K^-1, D - B K^-1 B^T]].  The 16
+// there in global memory, NB pivots at a time.  With the block partitioned at pivots K as
+// [[K, B^T], [B, D]], sweeping K leaves [[-K^-1, K^-1 B^T], [B K^-1, D - B K^-1 B^T]].  The NB
 // rows of K are staged in LDS twice: as loaded (Bo = [K, B^T], whose columns outside K are B^T)
 // and swept pivot by pivot (Rs, ending as [-K^-1, K^-1 B^T]); then every row outside K is updated
 // from LDS, D[i][j] -= sum_m Bo[m][i] Rs[m][j] and A[i][k] = Rs[k][i] for k in K (the block stays
 // symmetric), four rows by four columns per thread, and the rows of K are written from Rs.
 // Before pivot p is swept, its staged row holds column p of the Schur complement, so the
 // Cholesky factor's column p is that row over sqrt(pivot) (written to P when asked).  After all
-// pivots the block holds -P^-1.  LDS: (33 d + 16) doubles (99 KB at d = 384).
+// pivots the block holds -P^-1.  LDS: ((2 NB + 1) d + NB) doubles (NB = 16: 99 KB at d = 384;
+// NB = 8 for larger blocks, at twice the passes over the block).
+template <int NB>
 __global__ __launch_bounds__(256) void k_sweep_glb(double* __restrict__ P, double* __restrict__ Pinv,
                                                    int d, int32_t* bad, int write_l) {
   extern __shared__ __align__(16) double sw_lds[];
-  double* Bo = sw_lds;             // [16][d] rows of K as loaded
-  double* Rs = sw_lds + 16 * d;    // [16][d] rows of K as swept
-  double* Rm = sw_lds + 32 * d;    // [d] pivot row before its sweep
-  double* Cp = sw_lds + 33 * d;    // [16] pivot column before its sweep
+  double* Bo = sw_lds;                  // [NB][d] rows of K as loaded
+  double* Rs = sw_lds + NB * d;         // [NB][d] rows of K as swept
+  double* Rm = sw_lds + 2 * NB * d;     // [d] pivot row before its sweep
+  double* Cp = Rm + d;                  // [NB] pivot column before its sweep
   const int kb = blockIdx.x, tid = threadIdx.x;
   double* L = P + (int64_t)kb * d * d;
   double* A = Pinv + (int64_t)kb * d * d;
   for (int64_t e = tid; e < (int64_t)d * d; e += 256) A[e] = L[e];
   __syncthreads();
   const int nq = (d + 3) / 4;            // 4 x 4 tiles of the block
-  for (int k0 = 0; k0 < d; k0 += 16) {
-    const int nb = d - k0 < 16 ? d - k0 : 16;
+  for (int k0 = 0; k0 < d; k0 += NB) {
+    const int nb = d - k0 < NB ? d - k0 : NB;
     for (int e = tid; e < nb * d; e += 256) {
       const int m = e / d, j = e - m * d;
       const double v = A[(int64_t)(k0 + m) * d + j];
@@ -653,21 +655,29 @@ SyrkShape syrk_shape(int prec, int c) {
   return SyrkShape{4, 2, pnw};
 }
 
-// Blocks of 256 < d <= kSweepGlbMaxD go to the global-memory sweep (its LDS, (33 d + 16) doubles,
-// fits the 160 KB of a CU up to there); larger ones to the column-at-a-time factor and inverse.
-constexpr int kSweepGlbMaxD = 600;
+// Blocks of 256 < d <= kSweepGlbMaxD go to the global-memory sweep: 16-pivot panels up to
+// d = 600, 8-pivot panels up to 1200 (its LDS, ((2 NB + 1) d + NB) doubles, fits the 160 KB of
+// a CU up to there); larger ones to the column-at-a-time factor and inverse.
+constexpr int kSweepGlb16MaxD = 600, kSweepGlbMaxD = 1200;
+template <int NB>
+constexpr int sweep_glb_lds(int d) { return ((2 * NB + 1) * d + NB) * (int)sizeof(double); }
 static bool g_sweep_glb_attr = false;
 
 static int sweep_glb_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool want_l,
                             hipStream_t st) {
-  const int lds = (33 * d + 16) * (int)sizeof(double);
   if (!g_sweep_glb_attr) {
-    FIRAL_HIP(hipFuncSetAttribute((const void*)k_sweep_glb,
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_sweep_glb<16>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (33 * kSweepGlbMaxD + 16) * (int)sizeof(double)));
+                                  sweep_glb_lds<16>(kSweepGlb16MaxD)));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_sweep_glb<8>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  sweep_glb_lds<8>(kSweepGlbMaxD)));
     g_sweep_glb_attr = true;
   }
-  k_sweep_glb<<<c, 256, lds, st>>>(P, Pinv, d, bad, want_l ? 1 : 0);
+  if (d <= kSweepGlb16MaxD)
+    k_sweep_glb<16><<<c, 256, sweep_glb_lds<16>(d), st>>>(P, Pinv, d, bad, want_l ? 1 : 0);
+  else
+    k_sweep_glb<8><<<c, 256, sweep_glb_lds<8>(d), st>>>(P, Pinv, d, bad, want_l ? 1 : 0);
   FIRAL_LAUNCHED();
   return FIRAL_OK;
 }

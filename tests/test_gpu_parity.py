@@ -195,18 +195,23 @@ def test_hvp_is_deterministic():
 @pytest.mark.parametrize("shape", [(2000, 50, 20, 5), (3001, 7, 100, 10), (517, 3, 37, 13),
                                    (700, 4, 130, 3), (900, 2, 200, 2), (800, 1, 300, 2),
                                    (700, 2, 257, 2), (1000, 2, 384, 2), (1300, 3, 601, 2),
+                                   (5000, 2, 1100, 2, 1.0), (6000, 2, 1201, 2, 1.0),
                                    (600, 3, 45, 40), (500, 5, 24, 70), (400, 2, 27, 130)])
 def test_precond_matches_oracle(prec, shape):
     # class tiles of 32, 64 and 128 (the last ones partial), pair tiles cut by d; the factor
-    # by the sweeps in registers (d <= 256), the global-memory sweep (d = 257: one pivot in its
-    # last panel; 300, 384) and the column-at-a-time factor (d = 601)
-    n, nl, d, c = shape
+    # by the sweeps in registers (d <= 256), the global-memory sweep with 16-pivot panels
+    # (d = 257: one pivot in its last panel; 300, 384) and 8-pivot panels (d = 601, 1100), and
+    # the column-at-a-time factor (d = 1201).  Shift 1e-3 unless given: at d > 1000 it leaves
+    # kappa(P_k) near 5e7, past FP32 (kappa u > 1: the FP32 Gram block is not SPD), so those
+    # shapes take shift 1
+    n, nl, d, c, *rest = shape
+    shift = rest[0] if rest else 1e-3
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=6)
     ctx, X, H = context(p, prec, 1)
     om = np.random.default_rng(5).uniform(0.0, 1.0, p.N)
-    L, Pinv, info = ctx.build_precond(dev(om, torch.float64), shift=1e-3)
+    L, Pinv, info = ctx.build_precond(dev(om, torch.float64), shift=shift)
     assert info["bad_block"] == -1
-    P = orc.precond_blocks(X, H, om, 1e-3)
+    P = orc.precond_blocks(X, H, om, shift)
     Lr, bad = orc.precond_factor(P)
     assert bad == -1
     L = host(L)
@@ -236,18 +241,20 @@ def test_precond_reports_non_spd_block(want_L, d):
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("shape", [(2000, 50, 20, 5), (3001, 7, 100, 10), (517, 3, 37, 13),
                                    (777, 5, 128, 3), (600, 3, 45, 40), (300, 2, 1, 3),
-                                   (800, 1, 300, 2), (1300, 3, 520, 2)])
+                                   (800, 1, 300, 2), (1300, 3, 520, 2), (5000, 2, 1100, 2, 1.0)])
 def test_precond_inverse_alone_matches_oracle(prec, shape):
     # without the factor, d <= 128 takes the blocked sweep in registers (16-pivot blocks;
     # d = 1, 37, 45: partial blocks padded with the identity, d = 128: eight full blocks), and
-    # d = 300, 520 the global-memory sweep (16-pivot panels, the last one partial)
-    n, nl, d, c = shape
+    # d = 300, 520 the global-memory sweep (16-pivot panels, the last one partial), d = 1100
+    # its 8-pivot panels (the last one partial; shift 1, as in the test above)
+    n, nl, d, c, *rest = shape
+    shift = rest[0] if rest else 1e-3
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=8)
     ctx, X, H = context(p, prec, 1)
     om = np.random.default_rng(9).uniform(0.0, 1.0, p.N)
-    L, Pinv, info = ctx.build_precond(dev(om, torch.float64), shift=1e-3, want_L=False)
+    L, Pinv, info = ctx.build_precond(dev(om, torch.float64), shift=shift, want_L=False)
     assert L is None and info["bad_block"] == -1
-    P = orc.precond_blocks(X, H, om, 1e-3)
+    P = orc.precond_blocks(X, H, om, shift)
     kappa = max(np.linalg.cond(Pk) for Pk in P)
     assert_close(host(Pinv), np.linalg.inv(P), TOL[prec] * max(10.0, 10 * kappa), "block inverse")
 
