@@ -681,6 +681,167 @@ __global__ __launch_bounds__(kNtWG, 2) void k_nt3_xtg(
                   accumulate);
 }
 
+// The bf16x3 second contraction with one workgroup over all d <= 128 MT output rows: MT row
+// tiles of 128, four waves each (waves 4 m .. 4 m + 3 on row tile m, in the 2 x 2 arrangement
+// of the kernel above), so that each E^T tile is loaded, turned into G' and split into bf16
+// halves once instead of once per row tile.  X^T planes [2][128 MT][32] per buffer; B as above,
+// staged by the first 512 threads, two columns by four rows each (MT = 3: waves 8-11 stage X^T
+// only).  One workgroup per CU (128 KB of LDS at MT = 3).
+template <int PR>
+__device__ __forceinline__ int nt3_offp(int plane, int row, int ch) {   // plane of PR rows
+  return (plane * PR + row) * 32 + ((ch ^ ((row >> 2) & 3)) << 3);
+}
+
+template <int PA>
+__device__ __forceinline__ void nt3_stage_p(const __bf16* __restrict__ a,
+                                            const __bf16* __restrict__ b, int wm, int wn, int li,
+                                            int g, f32x4 (&acc)[4][4]) {
+  bf16x8 ah[4], al[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = wm + 16 * i + li;
+    ah[i] = *reinterpret_cast<const bf16x8*>(a + nt3_offp<PA>(0, row, g));
+    al[i] = *reinterpret_cast<const bf16x8*>(a + nt3_offp<PA>(1, row, g));
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = wn + 16 * j + li;
+    const bf16x8 bh = *reinterpret_cast<const bf16x8*>(b + nt3_off(0, row, g));
+    const bf16x8 bl = *reinterpret_cast<const bf16x8*>(b + nt3_off(1, row, g));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i][j] = mfma3(ah[i], al[i], bh, bl, acc[i][j]);
+  }
+}
+
+// X^T rows 0 .. 128 MT - 1, 32 k of two planes: 512 MT 16-byte chunks per plane, two per
+// thread; rows at or beyond nrow and k at or beyond nk read element 0 and are cleared at the
+// store through the returned mask.
+template <int MT>
+__device__ __forceinline__ unsigned nt3_load_m(const __bf16* __restrict__ hi,
+                                               const __bf16* __restrict__ lo, int64_t ld,
+                                               int64_t nrow, int64_t k0, int64_t nk, int tid,
+                                               bf16x8 (&vh)[2], bf16x8 (&vl)[2]) {
+  unsigned m = 0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int e = tid + 256 * MT * t, row = e >> 2, ch = e & 3;
+    const int64_t k = k0 + 8 * ch;
+    const bool ok = row < nrow && k < nk;
+    const int64_t o = ok ? row * ld + k : 0;
+    vh[t] = *reinterpret_cast<const bf16x8*>(hi + o);
+    vl[t] = *reinterpret_cast<const bf16x8*>(lo + o);
+    m |= (unsigned)ok << t;
+  }
+  return m;
+}
+template <int MT>
+__device__ __forceinline__ void nt3_store_m(__bf16* __restrict__ dst, int tid,
+                                            const bf16x8 (&vh)[2], const bf16x8 (&vl)[2],
+                                            unsigned m) {
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int e = tid + 256 * MT * t, row = e >> 2, ch = e & 3;
+    const bool ok = (m >> t) & 1u;
+    *reinterpret_cast<bf16x8*>(dst + nt3_offp<kNtBM * MT>(0, row, ch)) = ok ? vh[t] : nt3_zero8();
+    *reinterpret_cast<bf16x8*>(dst + nt3_offp<kNtBM * MT>(1, row, ch)) = ok ? vl[t] : nt3_zero8();
+  }
+}
+
+// G'^T = (E^T - beta[p]) h of CPT columns jl .. jl + CPT - 1 at rows r .. r + 3 (k offset rk of
+// the stage), split into hi/lo bf16 planes of the LDS tile; rows at or beyond re as zero.
+template <int CPT>
+__device__ __forceinline__ void nt3_store_gc(__bf16* __restrict__ b, int jl, int rk, int64_t r,
+                                             int64_t re, const f4 (&gv)[CPT], const f4 (&hv)[CPT],
+                                             const f4& bt) {
+  const bool full = r + 3 < re;
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+  for (int t = 0; t < CPT; ++t) {
+    bf16x4 h4, l4;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const float y = (gv[t][v] - bt[v]) * hv[t][v];
+      const float x = full || r + v < re ? y : 0.f;
+      const __bf16 h = (__bf16)x;
+      h4[v] = h;
+      l4[v] = (__bf16)(x - (float)h);
+    }
+    const int row = jl + t;
+    *reinterpret_cast<bf16x4*>(b + nt3_off(0, row, rk >> 3) + (rk & 4)) = h4;
+    *reinterpret_cast<bf16x4*>(b + nt3_off(1, row, rk >> 3) + (rk & 4)) = l4;
+  }
+}
+
+template <int MT>
+constexpr size_t nt3m_lds_bytes() { return (size_t)2 * 2 * (kNtBM * MT + kNtBN) * 32 * 2; }
+
+template <int MT>
+__global__ __launch_bounds__(256 * MT, 1) void k_nt3_xtg_m(
+    const __bf16* __restrict__ XTh, const __bf16* __restrict__ XTl, int64_t ldx, int d,
+    const float* __restrict__ GT, int64_t ldg, int SC, int c, int nw, const float* __restrict__ HT,
+    int64_t ldh, const float* __restrict__ beta, int64_t R, int64_t rows_per_split, int nct,
+    float* __restrict__ part, int64_t part_stride, int accumulate, Skip skip) {
+  if (skip_now(skip)) return;
+  constexpr int TMR = kNtBM * MT;
+  constexpr int PLA = 2 * TMR * 32, PLB = 2 * kNtBN * 32;   // one buffer's two planes
+  extern __shared__ __align__(16) float nt_lds[];
+  __bf16* As = reinterpret_cast<__bf16*>(nt_lds);   // [2 bufs][2 planes][TMR][32]
+  __bf16* Bs = As + 2 * PLA;                         // [2 bufs][2 planes][128][32]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
+  const int ct = (int)(lid % nct);
+  const int sp = (int)(lid / nct);
+  const int ns = nct / nw;
+  const int w = ct / ns, p = ct - w * ns;
+  const int col0w = w * kNtBN;
+  const int width = c - col0w < kNtBN ? c - col0w : kNtBN;
+  const int n0 = p * c + col0w;
+  const int64_t rb = (int64_t)sp * rows_per_split;
+  const int64_t re = rb + rows_per_split < R ? rb + rows_per_split : R;
+  const int q = wave & 3;
+  const int wm = (wave >> 2) * kNtBM + (q >> 1) * 64, wn = (q & 1) * 64;
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const bool bst = tid < 512;                  // this thread stages B (whole waves)
+  const int jl = 2 * ((tid & 511) >> 3);       // its first column in the window
+  const int nb = n0 + jl;
+  const int rk = 4 * (tid & 7);
+  const int nvalid = width - jl < 2 ? (width - jl > 0 ? width - jl : 0) : 2;
+  const int nb_c = nvalid > 0 ? nb : n0;
+  const int k_first = nvalid > 0 ? col0w + jl : col0w;
+  bf16x8 ah[2], al[2];
+  f4 gv[2], hv[2], bt;
+  const int64_t nrows = re > rb ? re - rb : 0;
+  const int nst = (int)((nrows + kNtKS - 1) / kNtKS);
+  if (nst > 0) {
+    const unsigned ma = nt3_load_m<MT>(XTh, XTl, ldx, d, rb, re, tid, ah, al);
+    if (bst) nt_load_e<2>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv, bt);
+    nt3_store_m<MT>(As, tid, ah, al, ma);
+    if (bst) nt3_store_gc<2>(Bs, jl, rk, rb + rk, re, gv, hv, bt);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const int64_t k1 = rb + (int64_t)(st + 1) * kNtKS;
+    const unsigned ma = nt3_load_m<MT>(XTh, XTl, ldx, d, k1, re, tid, ah, al);
+    if (bst) nt_load_e<2>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv, bt);
+    nt_order();
+    nt3_stage_p<TMR>(As + buf * PLA, Bs + buf * PLB, wm, wn, li, g, acc);
+    nt_order();
+    nt3_store_m<MT>(As + (buf ^ 1) * PLA, tid, ah, al, ma);
+    if (bst) nt3_store_gc<2>(Bs + (buf ^ 1) * PLB, jl, rk, k1 + rk, re, gv, hv, bt);
+    __syncthreads();
+  }
+  nt_xtg_epilogue(acc, part, sp, part_stride, 0, n0, n0 + width, wm, wn, li, g, d, SC,
+                  accumulate);
+}
+
 // hi/lo bf16 planes of the transpose of an rows x cols row-major FP32 source: dst[j][i] for the
 // cols x rows destination (leading dimension rows).
 __global__ __launch_bounds__(256) void k_nt3_transpose_split(const float* __restrict__ src,
@@ -781,6 +942,12 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
                                     (int)kNt3XvLds));
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNt3Lds));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg_m<2>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)nt3m_lds_bytes<2>()));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg_m<3>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)nt3m_lds_bytes<3>()));
     g_nt_attr = true;
   }
   const bool bf3 = x->prec == FIRAL_BF16X3;
@@ -801,12 +968,14 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
   float* part = (float*)x->part;
   const int64_t n_out = (int64_t)d * SC;
   const int nmt = (int)cdiv(d, kNtBM), nct = s * nw;   // column windows of every probe
-  const int64_t tiles = (int64_t)nmt * nct;
+  // bf16x3 with d <= 384: one workgroup per column tile covers every output row
+  const int mt_all = bf3 && (nmt == 2 || nmt == 3) ? nmt : 0;
+  const int64_t tiles = mt_all ? (int64_t)nct : (int64_t)nmt * nct;
   const int64_t cap = (int64_t)x->max_splits * x->s_max / s;
   // split count: the second contraction runs two workgroups per CU, so a grid of tiles * S
   // workgroups takes ceil(tiles * S / slots) rounds of R / S rows each; take the S with the least
   // time in rounds (the smallest such S: fewest partial sums), with at least 8 stages per split
-  const int64_t slots = (int64_t)2 * std::max(1, x->n_cu);
+  const int64_t slots = (int64_t)(mt_all ? 1 : 2) * std::max(1, x->n_cu);
   const int64_t s_hi = std::max<int64_t>(1, std::min<int64_t>({cap, 256, cdiv(x->chunk_rows, 8 * kNtKS)}));
   int S = 1;
   for (int64_t t = 2; t <= s_hi; ++t)   // rounds / S, compared as cross products
@@ -838,7 +1007,19 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
     const int64_t rps = cdiv(cdiv(R, S), kNtKS) * kNtKS;
     FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT_T, &e0, &e1));
     const dim3 grid2((unsigned)(tiles * S));
-    if (bf3)
+    if (mt_all == 3)
+      hipExtLaunchKernelGGL(k_nt3_xtg_m<3>, grid2, dim3(3 * kNtWG), (uint32_t)nt3m_lds_bytes<3>(),
+                            st, e0, e1, 0u, (const __bf16*)x->XThi + r0,
+                            (const __bf16*)x->XTlo + r0, x->ldt, d, (const float*)GT, ldg, SC, c,
+                            nw, (const float*)x->HTf + r0, x->ldn, (const float*)beta, R, rps, nct,
+                            part, n_out, (int)(r0 > 0), skip);
+    else if (mt_all == 2)
+      hipExtLaunchKernelGGL(k_nt3_xtg_m<2>, grid2, dim3(2 * kNtWG), (uint32_t)nt3m_lds_bytes<2>(),
+                            st, e0, e1, 0u, (const __bf16*)x->XThi + r0,
+                            (const __bf16*)x->XTlo + r0, x->ldt, d, (const float*)GT, ldg, SC, c,
+                            nw, (const float*)x->HTf + r0, x->ldn, (const float*)beta, R, rps, nct,
+                            part, n_out, (int)(r0 > 0), skip);
+    else if (bf3)
       hipExtLaunchKernelGGL(k_nt3_xtg, grid2, dim3(kNtWG), (uint32_t)kNt3Lds, st, e0, e1, 0u,
                             (const __bf16*)x->XThi + r0, (const __bf16*)x->XTlo + r0, x->ldt, d,
                             (const float*)GT, ldg, SC, c, nw, (const float*)x->HTf + r0, x->ldn,
