@@ -772,6 +772,37 @@ __device__ __forceinline__ void nt3_store_gc(__bf16* __restrict__ b, int jl, int
   }
 }
 
+// The X^T stage of k_nt3_xtg_m loaded straight into LDS (global_load_lds_dwordx4: lane L of a
+// wave writes the 16 bytes at the instruction's LDS base + 16 L).  One instruction fills 16
+// rows of one plane; lane L's slot is row 16 blk + L / 4, physical chunk L % 4, which under the
+// swizzle of nt3_offp holds logical chunk (L % 4) ^ ((row / 4) % 4), so the lane fetches that
+// chunk.  Rows at or beyond nrow and k at or beyond nk fetch element 0 of the plane: such rows
+// of A only meet output rows the epilogue drops or rows of B staged as zero.  Wave w fills
+// blocks w and w + 4 MT of each plane.
+template <int MT>
+__device__ __forceinline__ void nt3_load_lds(const __bf16* __restrict__ hi,
+                                             const __bf16* __restrict__ lo, int64_t ld,
+                                             int64_t nrow, int64_t k0, int64_t nk, int wave,
+                                             int lane, __bf16* __restrict__ dst) {
+  constexpr int TMR = kNtBM * MT;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int blk = wave + 4 * MT * j;
+    const int row = 16 * blk + (lane >> 2);
+    const int ch = (lane & 3) ^ ((row >> 2) & 3);
+    const int64_t k = k0 + 8 * ch;
+    const bool ok = row < nrow && k < nk;
+    const int64_t o = ok ? row * ld + k : 0;
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+      const __bf16* src = (pl == 0 ? hi : lo) + o;
+      __bf16* base = dst + (pl * TMR + 16 * blk) * 32;   // 16 rows of 32 bf16: 1 KB
+      __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src),
+                                       reinterpret_cast<void*>(base), 16, 0, 0);
+    }
+  }
+}
+
 template <int MT>
 constexpr size_t nt3m_lds_bytes() { return (size_t)2 * 2 * (kNtBM * MT + kNtBN) * 32 * 2; }
 
@@ -815,27 +846,29 @@ __global__ __launch_bounds__(256 * MT, 1) void k_nt3_xtg_m(
   const int nvalid = width - jl < 2 ? (width - jl > 0 ? width - jl : 0) : 2;
   const int nb_c = nvalid > 0 ? nb : n0;
   const int k_first = nvalid > 0 ? col0w + jl : col0w;
-  bf16x8 ah[2], al[2];
   f4 gv[2], hv[2], bt;
   const int64_t nrows = re > rb ? re - rb : 0;
   const int nst = (int)((nrows + kNtKS - 1) / kNtKS);
+  // vmcnt(0), no wait on the other counters: the direct-to-LDS loads of X^T have landed
+  constexpr int kWaitVm0 = 0x0F70;
   if (nst > 0) {
-    const unsigned ma = nt3_load_m<MT>(XTh, XTl, ldx, d, rb, re, tid, ah, al);
+    nt3_load_lds<MT>(XTh, XTl, ldx, d, rb, re, wave, lane, As);
     if (bst) nt_load_e<2>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv, bt);
-    nt3_store_m<MT>(As, tid, ah, al, ma);
     if (bst) nt3_store_gc<2>(Bs, jl, rk, rb + rk, re, gv, hv, bt);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
   }
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int buf = st & 1;
     const int64_t k1 = rb + (int64_t)(st + 1) * kNtKS;
-    const unsigned ma = nt3_load_m<MT>(XTh, XTl, ldx, d, k1, re, tid, ah, al);
+    // the other buffer was last read before the previous barrier
+    nt3_load_lds<MT>(XTh, XTl, ldx, d, k1, re, wave, lane, As + (buf ^ 1) * PLA);
     if (bst) nt_load_e<2>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv, bt);
     nt_order();
     nt3_stage_p<TMR>(As + buf * PLA, Bs + buf * PLB, wm, wn, li, g, acc);
     nt_order();
-    nt3_store_m<MT>(As + (buf ^ 1) * PLA, tid, ah, al, ma);
     if (bst) nt3_store_gc<2>(Bs + (buf ^ 1) * PLB, jl, rk, k1 + rk, re, gv, hv, bt);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
     __syncthreads();
   }
   nt_xtg_epilogue(acc, part, sp, part_stride, 0, n0, n0 + width, wm, wn, li, g, d, SC,
