@@ -524,6 +524,7 @@ NT_SHAPES = [  # n_pool, n_lab, d, c, s, chunk rows
     (900, 7, 132, 129, 3, None),
     (777, 3, 260, 300, 5, "320"),
     (2050, 14, 136, 257, 1, "100"),
+    (1100, 6, 520, 140, 2, "400"),    # five 128-row output tiles
 ]
 
 
@@ -563,10 +564,11 @@ def test_wide_fp32_relax_step_matches_oracle():
 
 
 NT3_SHAPES = [  # n_pool, n_lab, d, c, s, chunk rows: d a multiple of 8 for the bf16x3 form
-    (1500, 10, 384, 1000, 2, None),
+    (1500, 10, 384, 1000, 2, None),   # second contraction over all output rows (d <= 384)
     (900, 7, 136, 129, 3, None),
     (777, 3, 264, 300, 5, "320"),
     (2050, 14, 136, 257, 1, "100"),
+    (1100, 6, 520, 140, 2, "400"),    # d > 384: one workgroup per 128-row output tile
 ]
 
 
