@@ -40,6 +40,14 @@ sys.path.insert(0, ROOT)
 METRIC = "Relax iter time + HVP TFLOP/s, FP32 vs bf16x3 at ≤1e-4 rel grad error"
 # TFLOP/s, MI355X dense MFMA; bf16x3 counts the FP32-equivalent products of three bf16 passes
 PEAK = {"f32": 157.3, "f64": 78.6, "bf16x3": 2500.0 / 3}
+HBM_PEAK = 8.0e12   # bytes/s, MI355X HBM3E
+
+
+def hbm_frac(traffic, launch_us):
+    """Measured HBM bytes per launch over the launch time, as a fraction of the HBM peak."""
+    if traffic is None or not launch_us:
+        return None
+    return traffic / (launch_us * 1e-6) / HBM_PEAK
 
 
 def parse():
@@ -307,7 +315,8 @@ def headline(args):
                      "avg_launch_us": kern[dom]["avg_launch_us"],
                      "algorithmic_flop_per_launch": 2.0 * p.N * p.c * p.d * p.s /
                      max(kern[dom]["launches_per_product"], 1),
-                     "traffic": read_traffic(traffic_file)},
+                     "traffic": read_traffic(traffic_file),
+                     "hbm_frac": hbm_frac(read_traffic(traffic_file), kern[dom]["avg_launch_us"])},
     }
     if rounds:
         res["round_step"] = rounds
@@ -783,7 +792,9 @@ def workload2(args):
                      "achieved": main_leg["kern_tflops"], "peak": peak, "unit": "TFLOP/s",
                      "frac": main_leg["kern_tflops"] / peak,
                      "kernel_us": main_leg["t_kern"] * 1e6,
-                     "traffic": read_traffic(tfile) if tfile else None},
+                     "traffic": read_traffic(tfile) if tfile else None,
+                     "hbm_frac": hbm_frac(read_traffic(tfile) if tfile else None,
+                                          main_leg["t_kern"] * 1e6)},
     }
     if rnd is not None:
         res["round_step"] = rnd
