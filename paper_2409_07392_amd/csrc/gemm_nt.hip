@@ -209,29 +209,33 @@ __device__ __forceinline__ void nt_xtg_epilogue(const f32x4 (&acc)[4][4], float*
                                                 int SC, int accumulate) {
   float* out = part + (int64_t)sp * part_stride;
   if (accumulate) {
-    // every earlier partial is loaded first (clamped addresses) so that the loads overlap, then
-    // added and stored
-    float prev[4][4][4];
+    // the earlier partials of two row blocks at a time are loaded first (clamped addresses) so
+    // that the loads overlap, then added and stored
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i0 = 0; i0 < 4; i0 += 2) {
+      float prev[2][4][4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = a0 + wm + 16 * i + 4 * g + v;
-          const int n = n0 + wn + 16 * j + li;
-          prev[i][j][v] = out[a < d && n < n_end ? (int64_t)a * SC + n : 0];
-        }
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+          for (int v = 0; v < 4; ++v) {
+            const int a = a0 + wm + 16 * (i0 + i) + 4 * g + v;
+            const int n = n0 + wn + 16 * j + li;
+            prev[i][j][v] = out[a < d && n < n_end ? (int64_t)a * SC + n : 0];
+          }
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int a = a0 + wm + 16 * i + 4 * g + v;
-          const int n = n0 + wn + 16 * j + li;
-          if (a < d && n < n_end) out[(int64_t)a * SC + n] = prev[i][j][v] + acc[i][j][v];
-        }
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a = a0 + wm + 16 * (i0 + i) + 4 * g + v;
+            const int n = n0 + wn + 16 * j + li;
+            if (a < d && n < n_end)
+              out[(int64_t)a * SC + n] = prev[i][j][v] + acc[i0 + i][j][v];
+          }
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -442,6 +446,128 @@ __global__ __launch_bounds__(kNtWG, MINB) void k_nt_xtg(
     __syncthreads();
   }
   nt_xtg_epilogue(acc, part, sp, part_stride, a0, n0, n0 + width, wm, wn, li, g, d, SC,
+                  accumulate);
+}
+
+// The FP32 second contraction with one workgroup of 4 MT waves over all d <= 128 MT output rows
+// (as k_nt3_xtg_m below), 32-deep stages: each E^T tile is loaded and formed into G' once
+// instead of once per 128-row tile.  The X^T stage goes straight into LDS
+// (global_load_lds_dwordx4) as unpadded rows of 32 floats, eight 16-byte chunks, chunk q of
+// row a stored at q ^ (a & 7): one instruction fills 8 rows and each lane fetches the chunk the
+// swizzle puts in its slot; a fragment read (16 rows, one chunk) then meets distinct banks.
+// B is staged through registers by the first 512 threads, two columns by four rows each.
+template <int MT>
+__device__ __forceinline__ void nt_load_lds32(const float* __restrict__ src, int64_t ld,
+                                              int64_t nrow, int64_t k0, int64_t nk, int wave,
+                                              int lane, float* __restrict__ dst) {
+#pragma unroll 1
+  for (int j = 0; j < 4; ++j) {   // blocks of 8 rows: 4 per wave
+    const int blk = wave + 4 * MT * j;
+    const int row = 8 * blk + (lane >> 3);
+    const int ch = (lane & 7) ^ (row & 7);
+    const int64_t k = k0 + 4 * ch;
+    const bool ok = row < nrow && k < nk;
+    const int64_t o = ok ? row * ld + k : 0;
+    __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + o),
+                                     reinterpret_cast<void*>(dst + 8 * blk * 32), 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void nt_stage_m32(const float* __restrict__ a,
+                                             const float* __restrict__ b, int wm, int wn, int li,
+                                             int g, f32x4 (&acc)[4][4]) {
+  constexpr int SK = nt_sk<32>();
+#pragma unroll
+  for (int kg = 0; kg < 2; ++kg) {
+    f4 av[4], bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wm + 16 * i + li;
+      av[i] = *reinterpret_cast<const f4*>(a + row * 32 + 4 * ((4 * kg + g) ^ (row & 7)));
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      bv[j] = *reinterpret_cast<const f4*>(b + (wn + 16 * j + li) * SK + 16 * kg + 4 * g);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][q], bv[j][q], acc[i][j], 0, 0, 0);
+  }
+}
+
+template <int MT>
+constexpr size_t ntm_lds_bytes() {
+  return (size_t)2 * kNtBM * MT * 32 * 4 + (size_t)2 * kNtBN * nt_sk<32>() * 4;
+}
+
+template <int MT>
+__global__ __launch_bounds__(256 * MT, 1) void k_nt_xtg_m(
+    const float* __restrict__ XT, int64_t ldx, int d, const float* __restrict__ GT, int64_t ldg,
+    int SC, int c, int nw, const float* __restrict__ HT, int64_t ldh,
+    const float* __restrict__ beta, int64_t R, int64_t rows_per_split, int nct,
+    float* __restrict__ part, int64_t part_stride, int accumulate, Skip skip) {
+  if (skip_now(skip)) return;
+  constexpr int KS = 32, SK = nt_sk<KS>(), TMR = kNtBM * MT;
+  constexpr int PA = TMR * 32, PB = kNtBN * SK;   // one buffer of each operand, floats
+  extern __shared__ __align__(16) float nt_lds[];
+  float* As = nt_lds;              // [2][TMR][32], swizzled
+  float* Bs = nt_lds + 2 * PA;     // [2][128][SK]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int64_t lid = nt_lid(blockIdx.x, gridDim.x);
+  const int ct = (int)(lid % nct);
+  const int sp = (int)(lid / nct);
+  const int ns = nct / nw;
+  const int w = ct / ns, p = ct - w * ns;
+  const int col0w = w * kNtBN;
+  const int width = c - col0w < kNtBN ? c - col0w : kNtBN;
+  const int n0 = p * c + col0w;
+  const int64_t rb = (int64_t)sp * rows_per_split;
+  const int64_t re = rb + rows_per_split < R ? rb + rows_per_split : R;
+  const int q = wave & 3;
+  const int wm = (wave >> 2) * kNtBM + (q >> 1) * 64, wn = (q & 1) * 64;
+
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const bool bst = tid < 512;                  // this thread stages B (whole waves)
+  const int jl = 2 * ((tid & 511) >> 3);
+  const int nb = n0 + jl;
+  const int rk = 4 * (tid & 7);
+  const int nvalid = width - jl < 2 ? (width - jl > 0 ? width - jl : 0) : 2;
+  const int nb_c = nvalid > 0 ? nb : n0;
+  const int k_first = nvalid > 0 ? col0w + jl : col0w;
+  f4 gv[2], hv[2], bt;
+  const int64_t nrows = re > rb ? re - rb : 0;
+  const int nst = (int)((nrows + KS - 1) / KS);
+  constexpr int kWaitVm0 = 0x0F70;   // vmcnt(0), no wait on the other counters
+  if (nst > 0) {
+    nt_load_lds32<MT>(XT, ldx, d, rb, re, wave, lane, As);
+    if (bst) nt_load_e<2>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, rb + rk, re, rb, gv, hv, bt);
+    if (bst) nt_store_g<2, SK>(Bs, jl, rk, rb + rk, re, gv, hv, bt);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    const int64_t k1 = rb + (int64_t)(st + 1) * KS;
+    // the other buffer was last read before the previous barrier
+    nt_load_lds32<MT>(XT, ldx, d, k1, re, wave, lane, As + (buf ^ 1) * PA);
+    if (bst) nt_load_e<2>(GT, ldg, HT, ldh, beta, p, nb_c, nvalid, k_first, k1 + rk, re, rb, gv, hv, bt);
+    nt_order();
+    nt_stage_m32(As + buf * PA, Bs + buf * PB, wm, wn, li, g, acc);
+    nt_order();
+    if (bst) nt_store_g<2, SK>(Bs + (buf ^ 1) * PB, jl, rk, k1 + rk, re, gv, hv, bt);
+    __builtin_amdgcn_s_waitcnt(kWaitVm0);
+    __syncthreads();
+  }
+  nt_xtg_epilogue(acc, part, sp, part_stride, 0, n0, n0 + width, wm, wn, li, g, d, SC,
                   accumulate);
 }
 
@@ -978,6 +1104,12 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg_m<2>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)nt3m_lds_bytes<2>()));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xtg_m<2>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)ntm_lds_bytes<2>()));
+    FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt_xtg_m<3>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)ntm_lds_bytes<3>()));
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg_m<3>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)nt3m_lds_bytes<3>()));
@@ -1001,8 +1133,8 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
   float* part = (float*)x->part;
   const int64_t n_out = (int64_t)d * SC;
   const int nmt = (int)cdiv(d, kNtBM), nct = s * nw;   // column windows of every probe
-  // bf16x3 with d <= 384: one workgroup per column tile covers every output row
-  const int mt_all = bf3 && (nmt == 2 || nmt == 3) ? nmt : 0;
+  // d <= 384: one workgroup per column tile covers every output row
+  const int mt_all = nmt == 2 || nmt == 3 ? nmt : 0;
   const int64_t tiles = mt_all ? (int64_t)nct : (int64_t)nmt * nct;
   const int64_t cap = (int64_t)x->max_splits * x->s_max / s;
   // split count: the second contraction runs two workgroups per CU, so a grid of tiles * S
@@ -1040,7 +1172,17 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
     const int64_t rps = cdiv(cdiv(R, S), kNtKS) * kNtKS;
     FIRAL_CHECK(prof_pair(x, FIRAL_PROF_PRODUCT_T, &e0, &e1));
     const dim3 grid2((unsigned)(tiles * S));
-    if (mt_all == 3)
+    if (!bf3 && mt_all == 3)
+      hipExtLaunchKernelGGL(k_nt_xtg_m<3>, grid2, dim3(3 * kNtWG), (uint32_t)ntm_lds_bytes<3>(),
+                            st, e0, e1, 0u, (const float*)x->XTf + r0, x->ldn, d,
+                            (const float*)GT, ldg, SC, c, nw, (const float*)x->HTf + r0, x->ldn,
+                            (const float*)beta, R, rps, nct, part, n_out, (int)(r0 > 0), skip);
+    else if (!bf3 && mt_all == 2)
+      hipExtLaunchKernelGGL(k_nt_xtg_m<2>, grid2, dim3(2 * kNtWG), (uint32_t)ntm_lds_bytes<2>(),
+                            st, e0, e1, 0u, (const float*)x->XTf + r0, x->ldn, d,
+                            (const float*)GT, ldg, SC, c, nw, (const float*)x->HTf + r0, x->ldn,
+                            (const float*)beta, R, rps, nct, part, n_out, (int)(r0 > 0), skip);
+    else if (mt_all == 3)
       hipExtLaunchKernelGGL(k_nt3_xtg_m<3>, grid2, dim3(3 * kNtWG), (uint32_t)nt3m_lds_bytes<3>(),
                             st, e0, e1, 0u, (const __bf16*)x->XThi + r0,
                             (const __bf16*)x->XTlo + r0, x->ldt, d, (const float*)GT, ldg, SC, c,
