@@ -288,8 +288,8 @@ def headline(args):
     pre = "k_nt" if mprec == "f32" else "k_nt3"
     kname = {"product": f"{pre}_xv (first contraction X V^T with the row sums of Lemma 1, "
                         f"{mprec})",
-             "product_t": f"{pre}_xtg (second contraction X^T G'^T with the row step, "
-                          f"{mprec})"}[dom]
+             "product_t": f"{pre}_xtg{'_m<3>' if p.d <= 384 else ''} (second contraction "
+                          f"X^T G'^T with the row step, {mprec})"}[dom]
     traffic_file = {"product": f"{pre}_xv_cfg4_traffic.md",
                     "product_t": f"{pre}_xtg_cfg4_traffic.md"}[dom]
     res = {
