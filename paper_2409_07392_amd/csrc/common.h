@@ -6,6 +6,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <atomic>
 #include <vector>
 
 #include "firal.h"
@@ -165,6 +166,29 @@ constexpr int kBlock = 256;
 constexpr int kFusedMaxWgs = 1024;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// One-time set-up per device: kernel attributes (the dynamic LDS limit above 64 KiB) apply to the
+// device current when they are set, so a process driving contexts on several devices sets them
+// on each.  done() and set() refer to the current device (0 .. 63; any other device is never
+// marked done, so its set-up simply repeats).
+class DeviceOnce {
+ public:
+  bool done() const {
+    const int dev = current();
+    return dev >= 0 && dev < 64 && ((bits_.load() >> dev) & 1u) != 0;
+  }
+  void set() {
+    const int dev = current();
+    if (dev >= 0 && dev < 64) bits_.fetch_or(uint64_t(1) << dev);
+  }
+
+ private:
+  static int current() {
+    int dev = -1;
+    return hipGetDevice(&dev) == hipSuccess ? dev : -1;
+  }
+  std::atomic<uint64_t> bits_{0};
+};
 
 // ------------------------------------------------------------- MFMA
 typedef float f32x4 __attribute__((ext_vector_type(4)));

@@ -1053,7 +1053,7 @@ int nt_transpose(const float* src, int64_t rows, int64_t cols, int64_t lds, floa
   return FIRAL_OK;
 }
 
-bool g_nt_attr = false;
+DeviceOnce g_nt_attr;
 
 }  // namespace
 
@@ -1088,7 +1088,7 @@ int nt_prepare_ctx(Ctx* x, hipStream_t st) {
 int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const float* B,
                   float* out, int s, Skip skip, hipStream_t st) {
   const int d = x->d, c = x->c, SC = s * c, nw = nt_windows(c);
-  if (!g_nt_attr) {
+  if (!g_nt_attr.done()) {
     for (const void* f : {(const void*)k_nt_xv<kNtKsXv, kNtMinbXv, true>,
                           (const void*)k_nt_xv<kNtKsXv, kNtMinbXv, false>})
       FIRAL_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1113,7 +1113,7 @@ int hvp_nt_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, con
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_nt3_xtg_m<3>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)nt3m_lds_bytes<3>()));
-    g_nt_attr = true;
+    g_nt_attr.set();
   }
   const bool bf3 = x->prec == FIRAL_BF16X3;
   // V^T: the probe block d x (s c) transposed to (s c) x d (bf16x3: its hi/lo planes)

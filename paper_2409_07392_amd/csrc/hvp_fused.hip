@@ -844,11 +844,17 @@ bool fused_plan(const Ctx* x, int s, int64_t n_rows, FusedPlan* p, bool precise)
 int hvp_fused_launch(Ctx* x, const FusedPlan& p, const double* omega, int64_t n_rows, double shift,
                      const float* B, float* out, int s, Skip skip, hipStream_t st) {
   FusedKernel k = (FusedKernel)p.kernel;
-  static size_t attr_set[2][17][3] = {};   // largest dynamic LDS size granted per instantiation
-  if (p.lds_bytes > 64 * 1024 && attr_set[p.bf3][p.D16][p.ncb] < p.lds_bytes) {
+  // largest dynamic LDS size granted per device and instantiation (devices 0 .. 15 remembered;
+  // on others the attribute is set on every call)
+  static std::atomic<size_t> attr_set[16][2][17][3] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  std::atomic<size_t>* granted =
+      dev >= 0 && dev < 16 ? &attr_set[dev][p.bf3][p.D16][p.ncb] : nullptr;
+  if (p.lds_bytes > 64 * 1024 && (!granted || granted->load() < p.lds_bytes)) {
     FIRAL_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)p.lds_bytes));
-    attr_set[p.bf3][p.D16][p.ncb] = p.lds_bytes;
+    if (granted) granted->store(p.lds_bytes);
   }
   const int SC = s * x->c;
   const int nwg = (int)(((int64_t)p.n_splits * p.n_ctiles + 7) / 8 * 8);

@@ -770,8 +770,8 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
     // column-local CG: init, then per iteration the product and the three column kernels.
     // The iterate lives in the solution buffer itself when the caller gives one.
     if (Xsol && Xsol != B && Xsol != r && Xsol != p && Xsol != q) xv = Xsol;
-    static bool attr[2] = {false, false};
-    if (!attr[sizeof(T) == 8]) {
+    static DeviceOnce attr[2];
+    if (!attr[sizeof(T) == 8].done()) {
       FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_init<T>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
       FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_alpha<T>,
@@ -782,7 +782,7 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
       FIRAL_HIP(hipFuncSetAttribute((const void*)k_cg_col_apply<kApplyCols>,
                                     hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024));
-      attr[sizeof(T) == 8] = true;
+      attr[sizeof(T) == 8].set();
     }
     double* rd = x->cgd;
     double* zd = x->cgd + (int64_t)d * c * x->s_max;

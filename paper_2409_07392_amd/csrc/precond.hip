@@ -661,18 +661,18 @@ SyrkShape syrk_shape(int prec, int c) {
 constexpr int kSweepGlb16MaxD = 600, kSweepGlbMaxD = 1200;
 template <int NB>
 constexpr int sweep_glb_lds(int d) { return ((2 * NB + 1) * d + NB) * (int)sizeof(double); }
-static bool g_sweep_glb_attr = false;
+static DeviceOnce g_sweep_glb_attr;
 
 static int sweep_glb_launch(double* P, double* Pinv, int d, int c, int32_t* bad, bool want_l,
                             hipStream_t st) {
-  if (!g_sweep_glb_attr) {
+  if (!g_sweep_glb_attr.done()) {
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_sweep_glb<16>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   sweep_glb_lds<16>(kSweepGlb16MaxD)));
     FIRAL_HIP(hipFuncSetAttribute((const void*)k_sweep_glb<8>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   sweep_glb_lds<8>(kSweepGlbMaxD)));
-    g_sweep_glb_attr = true;
+    g_sweep_glb_attr.set();
   }
   if (d <= kSweepGlb16MaxD)
     k_sweep_glb<16><<<c, 256, sweep_glb_lds<16>(d), st>>>(P, Pinv, d, bad, want_l ? 1 : 0);

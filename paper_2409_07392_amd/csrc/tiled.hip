@@ -698,12 +698,13 @@ constexpr size_t xtg_lds_bytes() {
 }
 
 template <typename Kern>
-int set_lds(Kern k, size_t bytes, bool& done) {
-  if (!done && bytes > 48 * 1024) {
+int set_lds(Kern k, size_t bytes, DeviceOnce& once) {
+  if (once.done()) return FIRAL_OK;
+  if (bytes > 48 * 1024) {
     FIRAL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
   }
-  done = true;
+  once.set();
   return FIRAL_OK;
 }
 
@@ -751,7 +752,7 @@ int xv_gamma(Ctx* x, bool prof, const ColMap& cm, const XRows<T>& xr, int d, int
   if (cm.full) {
     auto k = k_xv<T, S_::WM1, S_::WN1, kGamma, BF3>;
     constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kGamma, BF3>();
-    static bool attr = false;
+    static DeviceOnce attr;
     FIRAL_CHECK(set_lds(k, lds, attr));
     hipExtLaunchKernelGGL(k, dim3(nwg), dim3(256), lds, st, e0, e1, 0u, xr.x, xr.xh, xr.xl, d, R,
                           B, Vh, Vl, Hc, om, cm, G, (const T*)nullptr, (double*)nullptr, skip);
@@ -759,7 +760,7 @@ int xv_gamma(Ctx* x, bool prof, const ColMap& cm, const XRows<T>& xr, int d, int
   } else {
     auto k = k_xv<T, S_::WM1, S_::WN1, kRaw, BF3>;
     constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kRaw, BF3>();
-    static bool attr = false;
+    static DeviceOnce attr;
     FIRAL_CHECK(set_lds(k, lds, attr));
     hipExtLaunchKernelGGL(k, dim3(nwg), dim3(256), lds, st, e0, e1, 0u, xr.x, xr.xh, xr.xl, d, R,
                           B, Vh, Vl, Hc, om, cm, G, (const T*)nullptr, (double*)nullptr, skip);
@@ -805,7 +806,7 @@ static int hvp_tiled_t(Ctx* x, const double* omega, int64_t n_rows, double shift
   const int S = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(4096, tiles), cap), 256));
   auto k2 = k_xtg<T, S_::WM2, S_::WN2, BF3>;
   constexpr size_t lds2 = xtg_lds_bytes<T, S_::WM2, S_::WN2, BF3>();
-  static bool attr2 = false;
+  static DeviceOnce attr2;
   FIRAL_CHECK(set_lds(k2, lds2, attr2));
   // bf16x3: the hi/lo planes of V^T, made once for every chunk
   __bf16* Vh = nullptr;
@@ -855,7 +856,7 @@ static int grad_tiled_t(Ctx* x, const T* U, const T* W, int s, double* g, hipStr
   const ColMap cm = colmap_for<T>(c, s);
   auto kd = k_xv<T, S_::WM1, S_::WN1, kDot, BF3>;
   constexpr size_t lds = xv_lds_bytes<T, S_::WM1, S_::WN1, kDot, BF3>();
-  static bool attr = false;
+  static DeviceOnce attr;
   FIRAL_CHECK(set_lds(kd, lds, attr));
   T* G = (T*)x->G;
   // bf16x3: hi/lo planes of W^T and U^T, made once for every chunk
