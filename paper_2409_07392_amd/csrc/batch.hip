@@ -91,9 +91,11 @@ int autotune(Ctx* x, int s, hipStream_t st, int* choice_out) {
     }
   }
   FIRAL_CHECK(probes_launch(x, 1, 1, s, x->V, st));
-  // product: the fused tilings whose plans fit (distinct plans only: the row ranges are capped
-  // by the row chunks), then the row-tiled kernels
-  std::vector<int> cands;
+  // product: the default path (the fused kernel's first tiling where its plan fits, else the
+  // wide or row-tiled kernels the context chose), the other fused tilings whose plans fit
+  // (distinct plans only: the row ranges are capped by the row chunks), then the row-tiled
+  // kernels
+  std::vector<int> cands{0};
   std::vector<std::pair<int, int>> plans;   // (column blocks per wave, row ranges)
   for (int ncb_bit = 0; ncb_bit <= 4; ncb_bit += 4)
     for (int code = 0; (256 << code) <= kFusedMaxWgs; ++code) {
@@ -104,7 +106,7 @@ int autotune(Ctx* x, int s, hipStream_t st, int* choice_out) {
       const std::pair<int, int> key(fp.ncb, fp.n_splits);
       if (std::find(plans.begin(), plans.end(), key) != plans.end()) continue;
       plans.push_back(key);
-      cands.push_back(bits);
+      if (bits != 0) cands.push_back(bits);
     }
   cands.push_back(1);
   double best = 0.0;

@@ -51,6 +51,20 @@ def test_autotune_choice_is_cached_and_keeps_parity():
     assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
 
 
+def test_autotune_on_a_wide_shape_keeps_parity():
+    # d > 128 and c > 128: no fused tiling fits; the tuner times the context's default (wide)
+    # path against the row-tiled kernels and the product keeps the FP32 bar either way
+    p, X, H, dt = problem(3, (1500, 10, 136, 257, 2), "f32")
+    ctx = RelaxContext(dev(X, dt), dev(H, dt), p.n_pool, p.s, "f32")
+    ch = ctx.autotune()
+    assert ch & ~3 == 0   # no fused bits: the default path (0) or the row-tiled one (1)
+    rng = np.random.default_rng(4)
+    B = rng.standard_normal((p.d, p.s, p.c)).astype(np.float32).astype(np.float64)
+    got = ctx.hvp(dev(B, dt), shift=1e-3).cpu().numpy().astype(np.float64)
+    ref = orc.hvp(X, H, None, 1e-3, B)
+    assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16x3"])
 def test_batch_replays_equal_sequential_steps(prec):
     T = 3
