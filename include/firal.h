@@ -126,7 +126,12 @@ int firal_hvp_noalloc(const float* X, const float* H, int64_t n_rows, int32_t d,
  * factorised in FP64 as P_k = L_k L_k^T.  L (lower, upper part zero) and Pinv = P_k^-1
  * are device FP64 arrays c x d x d; either may be NULL.  omega: device FP64
  * [n_pool + n_lab] or NULL for all ones.  Synchronous; info (host, may be NULL)
- * gets bad_block.  Returns ENOTSPD when a block fails. */
+ * gets bad_block.  Returns ENOTSPD when a block fails.  The sums over rows are FP32 (FIRAL_F32,
+ * FIRAL_BF16X3) or FP64.  A FIRAL_BF16X3 context created with FIRAL_BF3_GRAM=1 in the
+ * environment forms them as bf16x3 products instead when c > 64, d is a multiple of 4 and X is
+ * 16-byte aligned (about 1e-5 relative error in P_k: a PCG run to a tolerance reaches the same
+ * solution, iterates taken at a fixed iteration count move by up to that error times the
+ * conditioning). */
 int firal_build_precond(firal_ctx ctx, const double* omega, double shift, double* L,
                         double* Pinv, firal_info* info, void* stream);
 

@@ -178,6 +178,160 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const L* __restrict__ X, const 
       }
 }
 
+// The same Gram GEMM for the split-precision (bf16x3) contexts with c > 64 classes and d a
+// multiple of 4: each 32-row stage feeds one 16x16x32 bf16 MFMA triple (hi hi + hi lo + lo hi)
+// per 16 x 16 block.  u = omega h (1 - h) is formed in FP32 and split into hi/lo bf16 planes
+// when staged (LDS [class][row]); the x values of the tile's 16 a and 16 b columns are staged
+// in FP32 (LDS [column][row]) and each lane forms its pairs' products x_a x_b for its 8 rows and
+// splits them in registers.  Four waves along the pairs (wave w: a columns 4 w .. 4 w + 3 of the
+// tile against all 16 b columns), each over all CMW x 16 classes of the tile, so a pair product
+// is formed once per workgroup and feeds CMW blocks.
+constexpr int kS3TK = 32;            // rows per stage: the bf16 MFMA's k
+constexpr int kS3US = kS3TK + 8;     // LDS row of a class's u plane, bf16 (80 bytes)
+constexpr int kS3XS = kS3TK + 4;     // LDS row of a staged x column, floats
+template <int CMW>
+__global__ __launch_bounds__(256, 2) void k_syrk3(const float* __restrict__ X,
+                                                  const float* __restrict__ H,
+                                                  const double* __restrict__ omega, int64_t N,
+                                                  int d, int c, const int32_t* __restrict__ tiles,
+                                                  int ntiles, int nct, int64_t rows_per_split,
+                                                  float* __restrict__ part) {
+  constexpr int TC = 16 * CMW, NQ = TC / 64;
+  static_assert(TC % 64 == 0, "u staging: 64 classes per quarter of the workgroup");
+  __shared__ __align__(16) __bf16 Uh[2][TC][kS3US];
+  __shared__ __align__(16) __bf16 Ul[2][TC][kS3US];
+  __shared__ __align__(16) float XaT[2][16][kS3XS];
+  __shared__ __align__(16) float XbT[2][16][kS3XS];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int li = lane & 15, g = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t lid = blockIdx.x;
+  const int cls_t = (int)(lid % nct);
+  const int64_t rest = lid / nct;
+  const int pt = (int)(rest % ntiles);
+  const int sp = (int)(rest / ntiles);
+  const int c0 = cls_t * TC;
+  const int a0 = 16 * tiles[2 * pt], b0 = 16 * tiles[2 * pt + 1];
+  const int64_t rb = (int64_t)sp * rows_per_split;
+  const int64_t re = rb + rows_per_split < N ? rb + rows_per_split : N;
+
+  f32x4 acc[CMW][4];
+#pragma unroll
+  for (int i = 0; i < CMW; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  // staging: u of classes (tid % 64) + 64 q for the 8 rows 8 wave .. 8 wave + 7 of the stage
+  // (the row weights are the same for a whole wave); one 4-float x vector per thread: row
+  // tid / 8, columns a0 + 4 (tid % 8) (tid % 8 < 4) or b0 + 4 (tid % 8 - 4)
+  int ucls[NQ];
+  bool uvalid[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    ucls[q] = (tid & 63) + 64 * q;
+    uvalid[q] = c0 + ucls[q] < c;
+  }
+  const int xr = tid >> 3, xp = tid & 7;
+  const int xcol = xp < 4 ? a0 + 4 * xp : b0 + 4 * (xp - 4);
+  const bool xvalid = xcol < d;   // d and the column a multiple of 4: all four in or all out
+  const double* wsrc = omega ? omega : &kSyrkUnitWeight;
+  float rh[NQ][8];
+  double rw[8];
+  f32x4 rx;
+  // loads read rows clamped into the split and columns clamped into the arrays; the values
+  // outside the tile are zeroed when stored
+  auto load = [&](int kt) {
+    const int64_t r0 = rb + (int64_t)kt * kS3TK + 8 * wave;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t r = r0 + e < re ? r0 + e : rb;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) rh[q][e] = H[r * c + (uvalid[q] ? c0 + ucls[q] : 0)];
+      rw[e] = wsrc[omega ? r : 0];
+    }
+    const int64_t r = rb + (int64_t)kt * kS3TK + xr;
+    rx = *reinterpret_cast<const f32x4*>(X + (r < re ? r : rb) * d + (xvalid ? xcol : 0));
+  };
+  auto store = [&](int buf, int kt) {
+    const int64_t r0 = rb + (int64_t)kt * kS3TK + 8 * wave;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      float u[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float h = rh[q][e];
+        u[e] = r0 + e < re && uvalid[q] ? (float)rw[e] * h * (1.f - h) : 0.f;
+      }
+      bf16x8 hi, lo;
+      split8(u, hi, lo);
+      *reinterpret_cast<bf16x8*>(&Uh[buf][ucls[q]][8 * wave]) = hi;
+      *reinterpret_cast<bf16x8*>(&Ul[buf][ucls[q]][8 * wave]) = lo;
+    }
+    const int64_t r = rb + (int64_t)kt * kS3TK + xr;
+    const bool ok = r < re && xvalid;
+    float* dst = xp < 4 ? &XaT[buf][4 * xp][xr] : &XbT[buf][4 * (xp - 4)][xr];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dst[e * kS3XS] = ok ? rx[e] : 0.f;
+  };
+
+  const int64_t nrows = re > rb ? re - rb : 0;
+  const int nk = (int)((nrows + kS3TK - 1) / kS3TK);
+  if (nk > 0) {
+    load(0);
+    store(0, 0);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    load(kt + 1);   // past the last stage every row is out of range (stored as zero, never read)
+    __builtin_amdgcn_sched_barrier(0);
+    // this lane's pairs: (a0 + 4 wave + j, b0 + li), rows 8 g .. 8 g + 7 of the stage
+    const f32x4 xb0 = *reinterpret_cast<const f32x4*>(&XbT[buf][li][8 * g]);
+    const f32x4 xb1 = *reinterpret_cast<const f32x4*>(&XbT[buf][li][8 * g + 4]);
+    bf16x8 bh[4], bl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const f32x4 xa0 = *reinterpret_cast<const f32x4*>(&XaT[buf][4 * wave + j][8 * g]);
+      const f32x4 xa1 = *reinterpret_cast<const f32x4*>(&XaT[buf][4 * wave + j][8 * g + 4]);
+      const float pr[8] = {xa0[0] * xb0[0], xa0[1] * xb0[1], xa0[2] * xb0[2], xa0[3] * xb0[3],
+                           xa1[0] * xb1[0], xa1[1] * xb1[1], xa1[2] * xb1[2], xa1[3] * xb1[3]};
+      split8(pr, bh[j], bl[j]);
+    }
+    // the u planes of class block i + 1 are read while block i's MFMAs run (the scheduler is
+    // kept from hoisting all of them, which would not fit two waves per SIMD)
+    bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Uh[buf][li][8 * g]);
+    bf16x8 al = *reinterpret_cast<const bf16x8*>(&Ul[buf][li][8 * g]);
+#pragma unroll
+    for (int i = 0; i < CMW; ++i) {
+      const int in = i + 1 < CMW ? i + 1 : i;
+      const bf16x8 nh = *reinterpret_cast<const bf16x8*>(&Uh[buf][16 * in + li][8 * g]);
+      const bf16x8 nl = *reinterpret_cast<const bf16x8*>(&Ul[buf][16 * in + li][8 * g]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = mfma3(ah, al, bh[j], bl[j], acc[i][j]);
+      __builtin_amdgcn_sched_barrier(0);
+      ah = nh;
+      al = nl;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    store(buf ^ 1, kt + 1);
+    __syncthreads();
+  }
+
+  float* out = part + (int64_t)sp * c * d * d;
+  const int b = b0 + li;
+#pragma unroll
+  for (int i = 0; i < CMW; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int a = a0 + 4 * wave + j;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = c0 + 16 * i + 4 * g + v;
+        if (k < c && a < d && b < d && b <= a) out[((int64_t)k * d + a) * d + b] = acc[i][j][v];
+      }
+    }
+}
+
 // P[k][a][b] = sum over splits (in order, FP64) of the lower-triangle entry (max, min) +
 // shift [a == b]: P is exactly symmetric.
 template <typename T>
@@ -641,13 +795,18 @@ static SweepKernel pick_sweep(int d, int* threads) {
 __global__ void k_bad_reset(Status* st) { st->bad_block = INT_MAX; }
 
 // Tile shape by c: class blocks per wave (CMW) and waves along the classes (WC); pair tiles
-// of 16 x BR with BR = PNW (4 / WC), PNW = 4 (FP32) or 2 (FP64).
+// of 16 x BR with BR = PNW (4 / WC), PNW = 4 (FP32) or 2 (FP64).  The bf16x3 kernel: CMW = 8,
+// WC = 1 (its four waves along the pairs), pair tiles of 16 x 16.
 struct SyrkShape {
   int cmw, wc, pnw;
   int tc() const { return 16 * cmw * wc; }
   int br() const { return pnw * (4 / wc); }
 };
-SyrkShape syrk_shape(int prec, int c) {
+bool syrk3_applies(int prec, int d, int c, const void* X) {
+  return prec == FIRAL_BF16X3 && c > 64 && d % 4 == 0 && ((uintptr_t)X & 15) == 0;
+}
+SyrkShape syrk_shape(int prec, int c, bool gram3) {
+  if (gram3) return SyrkShape{8, 1, 4};
   const int pnw = prec == FIRAL_F64 ? 2 : 4;
   if (c <= 16) return SyrkShape{1, 1, pnw};
   if (c <= 32) return SyrkShape{1, 2, pnw};
@@ -699,8 +858,14 @@ static int precond_t(Ctx* x, const double* omega, double shift, bool want_l, hip
   const int64_t rps = cdiv(x->N, S);
   k_bad_reset<<<1, 1, 0, st>>>(x->status);
   FIRAL_LAUNCHED();
-  const SyrkShape sh = syrk_shape(x->prec, c);
-  if (sh.wc == 1) launch_syrk<T, 1, 1>(x, omega, rps, st);
+  const SyrkShape sh = syrk_shape(x->prec, c, x->gram3);
+  if (x->gram3) {
+    const int nct = (int)cdiv(c, sh.tc());
+    const int64_t nwg = (int64_t)nct * x->syrk_ntiles * S;
+    k_syrk3<8><<<(unsigned)nwg, 256, 0, st>>>((const float*)x->X, (const float*)x->H, omega,
+                                              x->N, d, c, x->syrk_tiles, x->syrk_ntiles, nct,
+                                              rps, (float*)x->syrk_part);
+  } else if (sh.wc == 1) launch_syrk<T, 1, 1>(x, omega, rps, st);
   else if (sh.cmw == 1) launch_syrk<T, 1, 2>(x, omega, rps, st);
   else if (sh.cmw == 2) launch_syrk<T, 2, 2>(x, omega, rps, st);
   else launch_syrk<T, 4, 2>(x, omega, rps, st);
@@ -731,8 +896,8 @@ static int precond_t(Ctx* x, const double* omega, double shift, bool want_l, hip
 
 // Pair tiles (a-block of 16, b-block of BR) that meet the lower triangle, and the row-split
 // count, for a context (host side, at creation).
-void syrk_plan(int prec, int d, int c, std::vector<int32_t>* tiles, int* splits) {
-  const SyrkShape sh = syrk_shape(prec, c);
+void syrk_plan(int prec, int d, int c, bool gram3, std::vector<int32_t>* tiles, int* splits) {
+  const SyrkShape sh = syrk_shape(prec, c, gram3);
   const int BR = sh.br();
   const int nab = (int)cdiv(d, 16), nbb = (int)cdiv(d, BR);
   tiles->clear();
@@ -788,7 +953,7 @@ template <typename L>
 static int gram64_t(const L* X, const L* H, const double* omega, int64_t N, int d, int c,
                     const int32_t* tiles, int ntiles, int S, double shift, double* part,
                     double* out, hipStream_t st) {
-  const SyrkShape sh = syrk_shape(FIRAL_F64, c);
+  const SyrkShape sh = syrk_shape(FIRAL_F64, c, false);
   if (sh.wc == 1) launch_gram64<L, 1, 1>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);
   else if (sh.cmw == 1) launch_gram64<L, 1, 2>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);
   else if (sh.cmw == 2) launch_gram64<L, 2, 2>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);

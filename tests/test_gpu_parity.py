@@ -470,6 +470,41 @@ def test_hvp_bf16x3(shape, ncb, monkeypatch):
         assert relerr(got, ref) <= BF3_TOL, relerr(got, ref)
 
 
+@pytest.mark.parametrize("gram3", ["0", "1"])
+@pytest.mark.parametrize("shape", [(2000, 50, 20, 70), (3001, 7, 100, 130), (1500, 3, 132, 300),
+                                   (700, 2, 384, 65), (517, 3, 37, 70), (600, 3, 44, 40)])
+def test_precond_bf16x3_matches_oracle(shape, gram3, monkeypatch):
+    # FIRAL_BF3_GRAM=1 with c > 64 and d a multiple of 4: the Gram blocks as bf16x3 products (one
+    # class tile with 64 row splits of 32 rows; two and three class tiles, the last partial;
+    # a-blocks cut by d); d = 37, c = 40 and the default keep the FP32 Gram in the bf16x3
+    # context.  Blocks at the bf16x3 bar, factor and inverse within kappa(P_k) times it
+    monkeypatch.setenv("FIRAL_BF3_GRAM", gram3)
+    n, nl, d, c = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=31)
+    X = rounded(p.X, "f32")
+    H = rounded(p.H, "f32")
+    ctx = RelaxContext(dev(X, torch.float32), dev(H, torch.float32), p.n_pool, 1, "bf16x3")
+    om = np.random.default_rng(32).uniform(0.0, 1.0, p.N)
+    L, Pinv, info = ctx.build_precond(dev(om, torch.float64), shift=1e-3)
+    assert info["bad_block"] == -1
+    P = orc.precond_blocks(X, H, om, 1e-3)
+    Lr, bad = orc.precond_factor(P)
+    assert bad == -1
+    L = host(L)
+    assert np.all(np.triu(L, 1) == 0.0)
+    assert_close(L @ np.transpose(L, (0, 2, 1)), P, BF3_TOL, "blocks L L^T")
+    kappa = max(np.linalg.cond(Pk) for Pk in P)
+    assert_close(L, Lr, BF3_TOL * max(1.0, kappa), "Cholesky factor")
+    assert_close(host(Pinv), np.linalg.inv(P), BF3_TOL * max(10.0, 10 * kappa), "block inverse")
+    # without row weights (omega = 1): the kernel's unit-weight path
+    _, Pinv1, info = ctx.build_precond(None, shift=1e-3, want_L=False)
+    assert info["bad_block"] == -1
+    P1 = orc.precond_blocks(X, H, np.ones(p.N), 1e-3)
+    kappa1 = max(np.linalg.cond(Pk) for Pk in P1)
+    assert_close(host(Pinv1), np.linalg.inv(P1), BF3_TOL * max(10.0, 10 * kappa1),
+                 "block inverse, unit weights")
+
+
 @pytest.mark.parametrize("chunk", [None, "333"])
 @pytest.mark.parametrize("shape", TILED_SHAPES)
 def test_tiled_bf16x3_hvp_and_grad(shape, chunk, monkeypatch):
@@ -608,4 +643,23 @@ def test_wide_bf16x3_relax_step_matches_oracle():
                                  0.4, 7, 1, p.s, 0.0, 12, project=True)
     e = relerr(host(g), ir["g"])
     print(f"wide bf16x3 Relax step at 12 CG iterations: gradient rel err {e:.2e}")
+    assert e <= BF3_TOL, e
+
+
+def test_wide_bf16x3_gram_relax_step_to_tolerance(monkeypatch):
+    # the bf16x3 Gram blocks (FIRAL_BF3_GRAM=1) change the preconditioner by ~1e-5 relative: PCG
+    # run to a tolerance on both sides reaches the same gradient at the bf16x3 bar
+    monkeypatch.setenv("FIRAL_BF3_GRAM", "1")
+    p = make_small(n=2000, n_lab=9, d=136, c=130, s=3, seed=38, whiten_x=True, probs="maxprob")
+    X = rounded(p.X, "f32")
+    H = rounded(p.H, "f32")
+    ctx = RelaxContext(dev(X, torch.float32), dev(H, torch.float32), p.n_pool, p.s, "bf16x3")
+    w = torch.full((p.n_pool,), 1.0 / p.n_pool, dtype=torch.float64, device="cuda")
+    g = torch.empty_like(w)
+    info = ctx.relax_step(w, 20.0, 1e-3, 0.4, 7, 1, p.s, 1e-6, 400, project=True, g_out=g)
+    wr, ir = orc.relax_iteration(X, H, p.n_pool, np.full(p.n_pool, 1.0 / p.n_pool), 20.0, 1e-3,
+                                 0.4, 7, 1, p.s, 1e-6, 400, project=True)
+    e = relerr(host(g), ir["g"])
+    print(f"wide bf16x3 Relax step, bf16x3 Gram, PCG to 1e-6: CG {info['cg_iters']} "
+          f"(oracle {ir.get('cg_iters')}), gradient rel err {e:.2e}")
     assert e <= BF3_TOL, e
