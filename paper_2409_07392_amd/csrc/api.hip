@@ -218,12 +218,11 @@ int firal_create(firal_ctx* out, int64_t n_pool, int64_t n_lab, int32_t d, int32
   x->max_splits = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(4096, tiles), 64));
 
   std::vector<int32_t> syrk_tiles;
-  // BF16X3: the preconditioner's Gram blocks as bf16x3 products when asked for (FIRAL_BF3_GRAM=1;
-  // FP32 otherwise).  Their ~1e-5 relative error does not move a solve run to a tolerance, but it
-  // does move PCG iterates taken at a fixed iteration count
-  const char* g3 = getenv("FIRAL_BF3_GRAM");
-  x->gram3 = g3 && atoi(g3) != 0 && syrk3_applies(prec, d, c, X);
-  syrk_plan(prec, d, c, x->gram3, &syrk_tiles, &x->syrk_splits);
+  // the preconditioner's Gram kernel.  Its bf16x3 form (an opt-in of BF16X3 contexts) leaves
+  // ~1e-5 relative error in the blocks: no change to a solve run to a tolerance, but PCG iterates
+  // taken at a fixed iteration count move with it
+  x->gram_form = gram_form_for(prec, d, c, X);
+  syrk_plan(prec, d, c, x->gram_form, x->n_cu, &syrk_tiles, &x->syrk_splits);
   x->syrk_ntiles = (int)(syrk_tiles.size() / 2);
   x->col_parts = (int)std::max<int64_t>(1, std::min<int64_t>(d, cdiv(256, s_max)));
   x->red_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(n_pool, 256), 1024));

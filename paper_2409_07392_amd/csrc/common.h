@@ -81,7 +81,7 @@ struct Ctx {
   int64_t fused_part_elems;
   int fused_max_ncb;    // fused product: column blocks per wave, 2 (wide tiles) or 1 (two
                         // workgroups' registers per CU, next chunk fetched ahead)
-  bool gram3;           // BF16X3: preconditioner Gram blocks as bf16x3 products (opt-in)
+  int gram_form;        // preconditioner Gram kernel (kGramClassic, kGramWide, kGramWideBf3)
   int fused_wgs;        // fused product: workgroups a launch aims for (row ranges x column
                         // tiles; 0 = 256); firal_autotune chooses it
   int force_tiled;      // product and FP32 gradient: the row-tiled kernels even where the
@@ -346,10 +346,14 @@ int hvp_launch(Ctx* x, const double* omega, int64_t n_rows, double shift, const 
 // Gram blocks, then P^-1 into x->Pinv; the factor L goes to x->P only when want_l (for d <= 256
 // x->P otherwise keeps the Gram blocks)
 int precond_launch(Ctx* x, const double* omega, double shift, hipStream_t st, bool want_l = false);
-// gram3: the Gram blocks as bf16x3 products (a BF16X3 context that asks for it, where
-// syrk3_applies: c > 64, d a multiple of 4, X 16-byte aligned)
-bool syrk3_applies(int prec, int d, int c, const void* X);
-void syrk_plan(int prec, int d, int c, bool gram3, std::vector<int32_t>* tiles, int* splits);
+// Preconditioner Gram kernels: the classic tiling (classes and pairs split between the waves),
+// or, for FP32 storage with c > 64, d a multiple of 4 and X 16-byte aligned, the waves along the
+// pairs (FIRAL_GRAM_WIDE=0 in the environment keeps the classic one), in a BF16X3 context as
+// bf16x3 products when FIRAL_BF3_GRAM=1 (FP32 otherwise).  Chosen once, at context creation.
+constexpr int kGramClassic = 0, kGramWide = 1, kGramWideBf3 = 2;
+int gram_form_for(int prec, int d, int c, const void* X);
+void syrk_plan(int prec, int d, int c, int form, int n_cu, std::vector<int32_t>* tiles,
+               int* splits);
 // FP64 weighted Gram blocks sum_r omega_r h_rk (1 - h_rk) x_r x_r^T + shift I over rows [0, N)
 // of X and H (storage FP32 unless prec is FIRAL_F64; omega null: weight 1) into out
 // (c x d x d); tiles/S from syrk_plan(FIRAL_F64, ...), part holds S x c x d x d doubles.

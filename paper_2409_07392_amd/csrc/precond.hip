@@ -8,6 +8,8 @@
 // slices of rows are reduced afterwards in FP64 in a fixed order.
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -178,30 +180,34 @@ __global__ __launch_bounds__(256, 2) void k_syrk(const L* __restrict__ X, const 
       }
 }
 
-// The same Gram GEMM for the split-precision (bf16x3) contexts with c > 64 classes and d a
-// multiple of 4: each 32-row stage feeds one 16x16x32 bf16 MFMA triple (hi hi + hi lo + lo hi)
-// per 16 x 16 block.  u = omega h (1 - h) is formed in FP32 and split into hi/lo bf16 planes
-// when staged (LDS [class][row]); the x values of the tile's 16 a and 16 b columns are staged
-// in FP32 (LDS [column][row]) and each lane forms its pairs' products x_a x_b for its 8 rows and
-// splits them in registers.  Four waves along the pairs (wave w: a columns 4 w .. 4 w + 3 of the
-// tile against all 16 b columns), each over all CMW x 16 classes of the tile, so a pair product
-// is formed once per workgroup and feeds CMW blocks.
-constexpr int kS3TK = 32;            // rows per stage: the bf16 MFMA's k
-constexpr int kS3US = kS3TK + 8;     // LDS row of a class's u plane, bf16 (80 bytes)
-constexpr int kS3XS = kS3TK + 4;     // LDS row of a staged x column, floats
-template <int CMW>
-__global__ __launch_bounds__(256, 2) void k_syrk3(const float* __restrict__ X,
+// The same Gram GEMM with the four waves along the pairs, for FP32-storage contexts with c > 64
+// classes and d a multiple of 4: a pair tile of 16 a x 16 b columns against 128 classes, wave w
+// taking a columns 4 w .. 4 w + 3 against all 16 b columns and all classes of the tile, so a pair
+// product x_a x_b is formed once per workgroup and feeds CMW class blocks.  Stages of 32 rows;
+// u = omega h (1 - h) is staged as [class][row] and the tile's x values as FP32 [column][row], so
+// each lane reads its rows of a class or a column as 16-byte vectors.
+//   FP32 (BF3 false): v_mfma_f32_16x16x4f32, the 16-row groups of a stage in the k order of the
+//     wide products (lane group g takes rows 4 g + q of the group for instruction q, so one
+//     16-byte read of u or x feeds four instructions).
+//   bf16x3 (BF3 true, the opt-in of bf16x3 contexts): u split into hi/lo bf16 planes when staged;
+//     each lane forms the products for its 8 rows (8 g .. 8 g + 7) in FP32 and splits them in
+//     registers; three 16x16x32 bf16 MFMAs per block (hi hi + hi lo + lo hi).
+constexpr int kSwTK = 32;                        // rows per stage (the bf16 MFMA's k)
+constexpr int kSwXS = kSwTK + 4;                 // LDS row of a staged x column, floats
+template <bool BF3> constexpr int kSwUS = BF3 ? kSwTK + 8 : kSwTK + 4;   // LDS row of u
+template <int CMW, bool BF3>
+__global__ __launch_bounds__(256, 2) void k_syrkw(const float* __restrict__ X,
                                                   const float* __restrict__ H,
                                                   const double* __restrict__ omega, int64_t N,
                                                   int d, int c, const int32_t* __restrict__ tiles,
                                                   int ntiles, int nct, int64_t rows_per_split,
                                                   float* __restrict__ part) {
-  constexpr int TC = 16 * CMW, NQ = TC / 64;
+  constexpr int TC = 16 * CMW, NQ = TC / 64, US = kSwUS<BF3>;
   static_assert(TC % 64 == 0, "u staging: 64 classes per quarter of the workgroup");
-  __shared__ __align__(16) __bf16 Uh[2][TC][kS3US];
-  __shared__ __align__(16) __bf16 Ul[2][TC][kS3US];
-  __shared__ __align__(16) float XaT[2][16][kS3XS];
-  __shared__ __align__(16) float XbT[2][16][kS3XS];
+  typedef typename std::conditional<BF3, __bf16, float>::type UT;
+  __shared__ __align__(16) UT Us[BF3 ? 2 : 1][2][TC][US];   // [hi, lo] or [u]
+  __shared__ __align__(16) float XaT[2][16][kSwXS];
+  __shared__ __align__(16) float XbT[2][16][kSwXS];
   const int tid = threadIdx.x, lane = tid & 63;
   const int li = lane & 15, g = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -241,7 +247,7 @@ __global__ __launch_bounds__(256, 2) void k_syrk3(const float* __restrict__ X,
   // loads read rows clamped into the split and columns clamped into the arrays; the values
   // outside the tile are zeroed when stored
   auto load = [&](int kt) {
-    const int64_t r0 = rb + (int64_t)kt * kS3TK + 8 * wave;
+    const int64_t r0 = rb + (int64_t)kt * kSwTK + 8 * wave;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int64_t r = r0 + e < re ? r0 + e : rb;
@@ -249,11 +255,11 @@ __global__ __launch_bounds__(256, 2) void k_syrk3(const float* __restrict__ X,
       for (int q = 0; q < NQ; ++q) rh[q][e] = H[r * c + (uvalid[q] ? c0 + ucls[q] : 0)];
       rw[e] = wsrc[omega ? r : 0];
     }
-    const int64_t r = rb + (int64_t)kt * kS3TK + xr;
+    const int64_t r = rb + (int64_t)kt * kSwTK + xr;
     rx = *reinterpret_cast<const f32x4*>(X + (r < re ? r : rb) * d + (xvalid ? xcol : 0));
   };
   auto store = [&](int buf, int kt) {
-    const int64_t r0 = rb + (int64_t)kt * kS3TK + 8 * wave;
+    const int64_t r0 = rb + (int64_t)kt * kSwTK + 8 * wave;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       float u[8];
@@ -262,20 +268,26 @@ __global__ __launch_bounds__(256, 2) void k_syrk3(const float* __restrict__ X,
         const float h = rh[q][e];
         u[e] = r0 + e < re && uvalid[q] ? (float)rw[e] * h * (1.f - h) : 0.f;
       }
-      bf16x8 hi, lo;
-      split8(u, hi, lo);
-      *reinterpret_cast<bf16x8*>(&Uh[buf][ucls[q]][8 * wave]) = hi;
-      *reinterpret_cast<bf16x8*>(&Ul[buf][ucls[q]][8 * wave]) = lo;
+      if constexpr (BF3) {
+        bf16x8 hi, lo;
+        split8(u, hi, lo);
+        *reinterpret_cast<bf16x8*>(&Us[0][buf][ucls[q]][8 * wave]) = hi;
+        *reinterpret_cast<bf16x8*>(&Us[1][buf][ucls[q]][8 * wave]) = lo;
+      } else {
+        *reinterpret_cast<f32x4*>(&Us[0][buf][ucls[q]][8 * wave]) = f32x4{u[0], u[1], u[2], u[3]};
+        *reinterpret_cast<f32x4*>(&Us[0][buf][ucls[q]][8 * wave + 4]) =
+            f32x4{u[4], u[5], u[6], u[7]};
+      }
     }
-    const int64_t r = rb + (int64_t)kt * kS3TK + xr;
+    const int64_t r = rb + (int64_t)kt * kSwTK + xr;
     const bool ok = r < re && xvalid;
     float* dst = xp < 4 ? &XaT[buf][4 * xp][xr] : &XbT[buf][4 * (xp - 4)][xr];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) dst[e * kS3XS] = ok ? rx[e] : 0.f;
+    for (int e = 0; e < 4; ++e) dst[e * kSwXS] = ok ? rx[e] : 0.f;
   };
 
   const int64_t nrows = re > rb ? re - rb : 0;
-  const int nk = (int)((nrows + kS3TK - 1) / kS3TK);
+  const int nk = (int)((nrows + kSwTK - 1) / kSwTK);
   if (nk > 0) {
     load(0);
     store(0, 0);
@@ -285,32 +297,59 @@ __global__ __launch_bounds__(256, 2) void k_syrk3(const float* __restrict__ X,
     const int buf = kt & 1;
     load(kt + 1);   // past the last stage every row is out of range (stored as zero, never read)
     __builtin_amdgcn_sched_barrier(0);
-    // this lane's pairs: (a0 + 4 wave + j, b0 + li), rows 8 g .. 8 g + 7 of the stage
-    const f32x4 xb0 = *reinterpret_cast<const f32x4*>(&XbT[buf][li][8 * g]);
-    const f32x4 xb1 = *reinterpret_cast<const f32x4*>(&XbT[buf][li][8 * g + 4]);
-    bf16x8 bh[4], bl[4];
+    // this lane's pairs: (a0 + 4 wave + j, b0 + li).  The u of class block i + 1 is read while
+    // block i's MFMAs run (the scheduler is kept from hoisting all of them, which would not fit
+    // two waves per SIMD)
+    if constexpr (BF3) {
+      const f32x4 xb0 = *reinterpret_cast<const f32x4*>(&XbT[buf][li][8 * g]);
+      const f32x4 xb1 = *reinterpret_cast<const f32x4*>(&XbT[buf][li][8 * g + 4]);
+      bf16x8 bh[4], bl[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const f32x4 xa0 = *reinterpret_cast<const f32x4*>(&XaT[buf][4 * wave + j][8 * g]);
-      const f32x4 xa1 = *reinterpret_cast<const f32x4*>(&XaT[buf][4 * wave + j][8 * g + 4]);
-      const float pr[8] = {xa0[0] * xb0[0], xa0[1] * xb0[1], xa0[2] * xb0[2], xa0[3] * xb0[3],
-                           xa1[0] * xb1[0], xa1[1] * xb1[1], xa1[2] * xb1[2], xa1[3] * xb1[3]};
-      split8(pr, bh[j], bl[j]);
-    }
-    // the u planes of class block i + 1 are read while block i's MFMAs run (the scheduler is
-    // kept from hoisting all of them, which would not fit two waves per SIMD)
-    bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Uh[buf][li][8 * g]);
-    bf16x8 al = *reinterpret_cast<const bf16x8*>(&Ul[buf][li][8 * g]);
+      for (int j = 0; j < 4; ++j) {
+        const f32x4 xa0 = *reinterpret_cast<const f32x4*>(&XaT[buf][4 * wave + j][8 * g]);
+        const f32x4 xa1 = *reinterpret_cast<const f32x4*>(&XaT[buf][4 * wave + j][8 * g + 4]);
+        const float pr[8] = {xa0[0] * xb0[0], xa0[1] * xb0[1], xa0[2] * xb0[2], xa0[3] * xb0[3],
+                             xa1[0] * xb1[0], xa1[1] * xb1[1], xa1[2] * xb1[2], xa1[3] * xb1[3]};
+        split8(pr, bh[j], bl[j]);
+      }
+      bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Us[0][buf][li][8 * g]);
+      bf16x8 al = *reinterpret_cast<const bf16x8*>(&Us[1][buf][li][8 * g]);
 #pragma unroll
-    for (int i = 0; i < CMW; ++i) {
-      const int in = i + 1 < CMW ? i + 1 : i;
-      const bf16x8 nh = *reinterpret_cast<const bf16x8*>(&Uh[buf][16 * in + li][8 * g]);
-      const bf16x8 nl = *reinterpret_cast<const bf16x8*>(&Ul[buf][16 * in + li][8 * g]);
+      for (int i = 0; i < CMW; ++i) {
+        const int in = i + 1 < CMW ? i + 1 : i;
+        const bf16x8 nh = *reinterpret_cast<const bf16x8*>(&Us[0][buf][16 * in + li][8 * g]);
+        const bf16x8 nl = *reinterpret_cast<const bf16x8*>(&Us[1][buf][16 * in + li][8 * g]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = mfma3(ah, al, bh[j], bl[j], acc[i][j]);
-      __builtin_amdgcn_sched_barrier(0);
-      ah = nh;
-      al = nl;
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma3(ah, al, bh[j], bl[j], acc[i][j]);
+        __builtin_amdgcn_sched_barrier(0);
+        ah = nh;
+        al = nl;
+      }
+    } else {
+#pragma unroll
+      for (int kg = 0; kg < kSwTK / 16; ++kg) {
+        const int k0 = 16 * kg + 4 * g;
+        const f32x4 xb = *reinterpret_cast<const f32x4*>(&XbT[buf][li][k0]);
+        f32x4 bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const f32x4 xa = *reinterpret_cast<const f32x4*>(&XaT[buf][4 * wave + j][k0]);
+          bv[j] = f32x4{xa[0] * xb[0], xa[1] * xb[1], xa[2] * xb[2], xa[3] * xb[3]};
+        }
+        f32x4 av = *reinterpret_cast<const f32x4*>(&Us[0][buf][li][k0]);
+#pragma unroll
+        for (int i = 0; i < CMW; ++i) {
+          const int in = i + 1 < CMW ? i + 1 : i;
+          const f32x4 nv = *reinterpret_cast<const f32x4*>(&Us[0][buf][16 * in + li][k0]);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bv[j][q], acc[i][j], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+          av = nv;
+        }
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
     store(buf ^ 1, kt + 1);
@@ -802,11 +841,15 @@ struct SyrkShape {
   int tc() const { return 16 * cmw * wc; }
   int br() const { return pnw * (4 / wc); }
 };
-bool syrk3_applies(int prec, int d, int c, const void* X) {
-  return prec == FIRAL_BF16X3 && c > 64 && d % 4 == 0 && ((uintptr_t)X & 15) == 0;
+int gram_form_for(int prec, int d, int c, const void* X) {
+  if (prec == FIRAL_F64 || c <= 64 || d % 4 != 0 || ((uintptr_t)X & 15) != 0) return kGramClassic;
+  const char* w = getenv("FIRAL_GRAM_WIDE");
+  if (w && atoi(w) == 0) return kGramClassic;
+  const char* g3 = getenv("FIRAL_BF3_GRAM");
+  return prec == FIRAL_BF16X3 && g3 && atoi(g3) != 0 ? kGramWideBf3 : kGramWide;
 }
-SyrkShape syrk_shape(int prec, int c, bool gram3) {
-  if (gram3) return SyrkShape{8, 1, 4};
+SyrkShape syrk_shape(int prec, int c, int form) {
+  if (form != kGramClassic) return SyrkShape{8, 1, 4};
   const int pnw = prec == FIRAL_F64 ? 2 : 4;
   if (c <= 16) return SyrkShape{1, 1, pnw};
   if (c <= 32) return SyrkShape{1, 2, pnw};
@@ -858,13 +901,14 @@ static int precond_t(Ctx* x, const double* omega, double shift, bool want_l, hip
   const int64_t rps = cdiv(x->N, S);
   k_bad_reset<<<1, 1, 0, st>>>(x->status);
   FIRAL_LAUNCHED();
-  const SyrkShape sh = syrk_shape(x->prec, c, x->gram3);
-  if (x->gram3) {
+  const SyrkShape sh = syrk_shape(x->prec, c, x->gram_form);
+  if (x->gram_form != kGramClassic) {
     const int nct = (int)cdiv(c, sh.tc());
     const int64_t nwg = (int64_t)nct * x->syrk_ntiles * S;
-    k_syrk3<8><<<(unsigned)nwg, 256, 0, st>>>((const float*)x->X, (const float*)x->H, omega,
-                                              x->N, d, c, x->syrk_tiles, x->syrk_ntiles, nct,
-                                              rps, (float*)x->syrk_part);
+    auto k = x->gram_form == kGramWideBf3 ? k_syrkw<8, true> : k_syrkw<8, false>;
+    k<<<(unsigned)nwg, 256, 0, st>>>((const float*)x->X, (const float*)x->H, omega, x->N, d, c,
+                                     x->syrk_tiles, x->syrk_ntiles, nct, rps,
+                                     (float*)x->syrk_part);
   } else if (sh.wc == 1) launch_syrk<T, 1, 1>(x, omega, rps, st);
   else if (sh.cmw == 1) launch_syrk<T, 1, 2>(x, omega, rps, st);
   else if (sh.cmw == 2) launch_syrk<T, 2, 2>(x, omega, rps, st);
@@ -895,9 +939,15 @@ static int precond_t(Ctx* x, const double* omega, double shift, bool want_l, hip
 }
 
 // Pair tiles (a-block of 16, b-block of BR) that meet the lower triangle, and the row-split
-// count, for a context (host side, at creation).
-void syrk_plan(int prec, int d, int c, bool gram3, std::vector<int32_t>* tiles, int* splits) {
-  const SyrkShape sh = syrk_shape(prec, c, gram3);
+// count, for a context (host side, at creation).  Grids smaller than the device's workgroup
+// slots (two per CU) are split over the rows up to about 1024 workgroups (partials within
+// 256 MB); larger grids of the wide forms take the split count (up to 8, partials within 4 GiB)
+// with the least time in rounds of slots, ceil(wgs S / slots) / S: at configuration 4, 2400
+// workgroups on 512 slots run 4.69 rounds unsplit (five, the last one two-thirds empty) and
+// 18.75 in four splits (nineteen quarter-length rounds).
+void syrk_plan(int prec, int d, int c, int form, int n_cu, std::vector<int32_t>* tiles,
+               int* splits) {
+  const SyrkShape sh = syrk_shape(prec, c, form);
   const int BR = sh.br();
   const int nab = (int)cdiv(d, 16), nbb = (int)cdiv(d, BR);
   tiles->clear();
@@ -909,7 +959,17 @@ void syrk_plan(int prec, int d, int c, bool gram3, std::vector<int32_t>* tiles, 
   const int64_t nt = (int64_t)tiles->size() / 2;
   const int64_t wgs = nt * cdiv(c, sh.tc());
   const int64_t es = prec == FIRAL_F64 ? 8 : 4;
-  const int64_t mem_cap = std::max<int64_t>(1, ((int64_t)1 << 28) / ((int64_t)c * d * d * es));
+  const int64_t blk = (int64_t)c * d * d * es;
+  const int64_t slots = 2 * (int64_t)std::max(1, n_cu);
+  if (form != kGramClassic && wgs >= slots) {
+    const int64_t cap = std::min<int64_t>(8, std::max<int64_t>(1, ((int64_t)4 << 30) / blk));
+    int S = 1;
+    for (int64_t t = 2; t <= cap; ++t)   // rounds / S, compared as cross products
+      if (cdiv(wgs * t, slots) * S < cdiv(wgs * S, slots) * t) S = (int)t;
+    *splits = S;
+    return;
+  }
+  const int64_t mem_cap = std::max<int64_t>(1, ((int64_t)1 << 28) / blk);
   *splits = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(cdiv(1024, wgs), 64),
                                                         mem_cap));
 }
@@ -953,7 +1013,7 @@ template <typename L>
 static int gram64_t(const L* X, const L* H, const double* omega, int64_t N, int d, int c,
                     const int32_t* tiles, int ntiles, int S, double shift, double* part,
                     double* out, hipStream_t st) {
-  const SyrkShape sh = syrk_shape(FIRAL_F64, c, false);
+  const SyrkShape sh = syrk_shape(FIRAL_F64, c, kGramClassic);
   if (sh.wc == 1) launch_gram64<L, 1, 1>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);
   else if (sh.cmw == 1) launch_gram64<L, 1, 2>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);
   else if (sh.cmw == 2) launch_gram64<L, 2, 2>(X, H, omega, N, d, c, tiles, ntiles, S, part, st);

@@ -1134,7 +1134,7 @@ extern "C" int firal_round_create(firal_round* out, firal_ctx ctx, const double*
   r->R = std::min<int64_t>(cdiv(r->n_pool, 256) * 256, cap);
   r->nparts = cdiv(r->n_pool, 256);
   std::vector<int32_t> tiles;
-  syrk_plan(FIRAL_F64, d, c, false, &tiles, &r->splits);
+  syrk_plan(FIRAL_F64, d, c, kGramClassic, 0, &tiles, &r->splits);
   r->ntiles = (int)(tiles.size() / 2);
   const int64_t dd = (int64_t)d * d;
   const int64_t nw = (int64_t)c * d * 2 * r->ldo;

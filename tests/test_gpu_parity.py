@@ -224,6 +224,31 @@ def test_precond_matches_oracle(prec, shape):
     assert_close(host(Pinv), np.linalg.inv(P), TOL[prec] * max(10.0, 10 * kappa), "block inverse")
 
 
+@pytest.mark.parametrize("wide", ["0", "1"])
+@pytest.mark.parametrize("shape", [(2000, 50, 20, 70), (3001, 7, 100, 130), (1500, 3, 132, 300),
+                                   (700, 2, 384, 65)])
+def test_precond_f32_gram_forms(shape, wide, monkeypatch):
+    # c > 64, d a multiple of 4: the Gram kernel with its waves along the pairs (default) and the
+    # classic tiling (FIRAL_GRAM_WIDE=0), one class tile with 64 row splits of 32 rows, two and
+    # three class tiles with the last partial, a-blocks cut by d; both at the FP32 bar
+    monkeypatch.setenv("FIRAL_GRAM_WIDE", wide)
+    n, nl, d, c = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=33)
+    ctx, X, H = context(p, "f32", 1)
+    om = np.random.default_rng(34).uniform(0.0, 1.0, p.N)
+    L, Pinv, info = ctx.build_precond(dev(om, torch.float64), shift=1e-3)
+    assert info["bad_block"] == -1
+    P = orc.precond_blocks(X, H, om, 1e-3)
+    L = host(L)
+    assert_close(L @ np.transpose(L, (0, 2, 1)), P, TOL["f32"], "blocks L L^T")
+    _, Pinv1, info = ctx.build_precond(None, shift=1e-3, want_L=False)
+    assert info["bad_block"] == -1
+    P1 = orc.precond_blocks(X, H, np.ones(p.N), 1e-3)
+    kappa1 = max(np.linalg.cond(Pk) for Pk in P1)
+    assert_close(host(Pinv1), np.linalg.inv(P1), TOL["f32"] * max(10.0, 10 * kappa1),
+                 "block inverse, unit weights")
+
+
 @pytest.mark.parametrize("d", [6, 300])
 @pytest.mark.parametrize("want_L", [True, False])
 def test_precond_reports_non_spd_block(want_L, d):
