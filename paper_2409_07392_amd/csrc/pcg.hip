@@ -53,72 +53,96 @@ int coldot_launch(Ctx* x, const void* A, const void* B, int s, double* part, Ski
 }
 
 // Y[a,j,:] = R[a,j,:] - mean_k R[a,j,k]  (projection onto the complement of 1_c (x) u).
-// Y may alias R.
+// Y may alias R.  One wave per (a, j) row of c classes: the lanes read the row coalesced,
+// sum in FP64 (lane partials in class order, then the fixed-order wave sum), and write the
+// row after every lane's reads of it have entered the sum.
+constexpr int kRowWaves = 4;   // rows per 256-thread block
+template <typename T>
+__device__ __forceinline__ double row_mean(const T* r, int c, int lane) {
+  double m = 0.0;
+  for (int k = lane; k < c; k += 64) m += (double)r[k];
+  return wave_sum(m) / c;
+}
 template <typename T>
 __global__ __launch_bounds__(256) void k_project(const T* R, T* Y, int d, int s, int c,
                                                  Skip skip) {
   if (skip_now(skip)) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)d * s) return;
-  const T* r = R + idx * c;
-  T* y = Y + idx * c;
-  double m = 0.0;
-  for (int k = 0; k < c; ++k) m += (double)r[k];
-  m /= c;
-  for (int k = 0; k < c; ++k) y[k] = (T)((double)r[k] - m);
+  const int64_t row = (int64_t)blockIdx.x * kRowWaves + (threadIdx.x >> 6);
+  if (row >= (int64_t)d * s) return;
+  const int lane = threadIdx.x & 63;
+  const T* r = R + row * c;
+  T* y = Y + row * c;
+  const double m = row_mean(r, c, lane);
+  for (int k = lane; k < c; k += 64) y[k] = (T)((double)r[k] - m);
 }
 
-// mean[a*s + j] = mean_k R[a,j,k]
+// mean[a*s + j] = mean_k R[a,j,k] (one wave per row, as above)
 template <typename T>
 __global__ __launch_bounds__(256) void k_classmean(const T* __restrict__ R, double* __restrict__ mean,
                                                    int d, int s, int c, Skip skip) {
   if (skip_now(skip)) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)d * s) return;
-  const T* r = R + idx * c;
-  double m = 0.0;
-  for (int k = 0; k < c; ++k) m += (double)r[k];
-  mean[idx] = m / c;
+  const int64_t row = (int64_t)blockIdx.x * kRowWaves + (threadIdx.x >> 6);
+  if (row >= (int64_t)d * s) return;
+  const int lane = threadIdx.x & 63;
+  const double m = row_mean(R + row * c, c, lane);
+  if (lane == 0) mean[row] = m;
 }
 
-// Z[a,j,k] = sum_b Pinv_k[b][a] (R[b,j,k] - mean[b,j]) for the probes j0..j0+JT-1 of one
-// class k per block.  The JT right-hand sides are staged in LDS; Pinv_k is symmetric, so its
-// column is read, and consecutive threads (consecutive a) read consecutive addresses.  The
-// dot product over b is split in four interleaved partial sums (fixed order).
-constexpr int kApplyJT = 4;
-template <typename T>
+// Z[a,j,k] = sum_b Pinv_k[b][a] (R[b,j,k] - mean[b,j]) for the probes j0 .. j0 + jn - 1
+// (jn <= JT) of one class k per block.  The group's right-hand sides are staged in LDS as
+// [b][j] (read as 16-byte broadcasts); each thread takes rows a = tid, tid + 256, ... and
+// streams column a of Pinv_k (P_k is symmetric), consecutive threads reading consecutive
+// addresses, so a group reads each block once: with up to 16 probes in one group (d <= 512),
+// Pinv is read once per apply.  Each XCD takes a contiguous range of blocks (classes), so the
+// classes that share a cache line of R and Z (class is their innermost index) meet in one L2.
+// Each output is one sequential sum over b (fixed order).
+template <int JT> constexpr size_t papply_lds(int d) { return (size_t)d * JT * sizeof(double); }
+template <typename T, int JT>
 __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
                                                 const T* __restrict__ R,
                                                 const double* __restrict__ mean,
                                                 T* __restrict__ Z, int d, int s, int c,
                                                 Skip skip) {
+  static_assert(JT % 2 == 0, "right-hand sides read in pairs");
   if (skip_now(skip)) return;
-  extern __shared__ double rs[];   // [kApplyJT][d]
-  const int k = blockIdx.x;
-  const int j0 = blockIdx.y * kApplyJT;
-  const int jn = min(kApplyJT, s - j0);
+  extern __shared__ __align__(16) double rs[];   // [d][JT]
+  const int64_t nb = gridDim.x, q = nb >> 3, rm = nb & 7;
+  const int64_t x = blockIdx.x & 7, lid = x * q + (x < rm ? x : rm) + (blockIdx.x >> 3);
+  const int ng = (s + JT - 1) / JT;
+  const int k = (int)(lid / ng);
+  const int j0 = (int)(lid - (int64_t)k * ng) * JT;
+  const int jn = min(JT, s - j0);
   const int64_t sc = (int64_t)s * c;
-  for (int e = threadIdx.x; e < jn * d; e += blockDim.x) {
-    const int jj = e / d, b = e - jj * d;
-    double rv = (double)R[b * sc + (int64_t)(j0 + jj) * c + k];
-    if (mean) rv -= mean[(int64_t)b * s + j0 + jj];
-    rs[jj * d + b] = rv;
+#pragma unroll 8
+  for (int e = threadIdx.x; e < d * JT; e += blockDim.x) {
+    const int b = e / JT, jj = e - b * JT;
+    double rv = 0.0;
+    if (jj < jn) {
+      rv = (double)R[b * sc + (int64_t)(j0 + jj) * c + k];
+      if (mean) rv -= mean[(int64_t)b * s + j0 + jj];
+    }
+    rs[e] = rv;
   }
   __syncthreads();
   const double* Pk = Pinv + (int64_t)k * d * d;
-  for (int e = threadIdx.x; e < jn * d; e += blockDim.x) {
-    const int jj = e / d, a = e - jj * d;
-    const double* r = rs + jj * d;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int b = 0;
-    for (; b + 3 < d; b += 4) {
-      s0 += Pk[(int64_t)b * d + a] * r[b];
-      s1 += Pk[(int64_t)(b + 1) * d + a] * r[b + 1];
-      s2 += Pk[(int64_t)(b + 2) * d + a] * r[b + 2];
-      s3 += Pk[(int64_t)(b + 3) * d + a] * r[b + 3];
+  for (int a = threadIdx.x; a < d; a += blockDim.x) {
+    double acc[JT];
+#pragma unroll
+    for (int jj = 0; jj < JT; ++jj) acc[jj] = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < d; ++b) {
+      const double p = Pk[(int64_t)b * d + a];
+      const double* r = rs + b * JT;
+#pragma unroll
+      for (int jj = 0; jj < JT; jj += 2) {
+        const double2 rv = *reinterpret_cast<const double2*>(r + jj);
+        acc[jj] = fma(p, rv.x, acc[jj]);
+        acc[jj + 1] = fma(p, rv.y, acc[jj + 1]);
+      }
     }
-    for (; b < d; ++b) s0 += Pk[(int64_t)b * d + a] * r[b];
-    Z[a * sc + (int64_t)(j0 + jj) * c + k] = (T)((s0 + s1) + (s2 + s3));
+#pragma unroll
+    for (int jj = 0; jj < JT; ++jj)
+      if (jj < jn) Z[a * sc + (int64_t)(j0 + jj) * c + k] = (T)acc[jj];
   }
 }
 
@@ -689,14 +713,25 @@ static int apply_t(Ctx* x, const double* Pinv, const T* r, T* z, int s, bool pro
   const int d = x->d, c = x->c;
   const int64_t nds = (int64_t)d * s;
   if (project) {
-    k_classmean<T><<<(unsigned)cdiv(nds, 256), 256, 0, st>>>(r, x->mean, d, s, c, skip);
+    k_classmean<T><<<(unsigned)cdiv(nds, kRowWaves), 256, 0, st>>>(r, x->mean, d, s, c, skip);
     FIRAL_LAUNCHED();
   }
-  k_papply<T><<<dim3(c, (unsigned)cdiv(s, kApplyJT)), 256, kApplyJT * d * sizeof(double), st>>>(
-      Pinv, r, project ? x->mean : nullptr, z, d, s, c, skip);
+  // probes per group: all 16 of a Relax step's block while their LDS stays within 64 KB
+  const double* mean = project ? x->mean : nullptr;
+  if (d <= 512)
+    k_papply<T, 16><<<(unsigned)(c * cdiv(s, 16)), 256, papply_lds<16>(d), st>>>(Pinv, r, mean, z,
+                                                                             d, s, c, skip);
+  else if (d <= 2048)
+    k_papply<T, 4><<<(unsigned)(c * cdiv(s, 4)), 256, papply_lds<4>(d), st>>>(Pinv, r, mean, z,
+                                                                            d, s, c, skip);
+  else if (d <= 4096)
+    k_papply<T, 2><<<(unsigned)(c * cdiv(s, 2)), 256, papply_lds<2>(d), st>>>(Pinv, r, mean, z,
+                                                                            d, s, c, skip);
+  else
+    return FIRAL_ENOTSUP;
   FIRAL_LAUNCHED();
   if (project) {
-    k_project<T><<<(unsigned)cdiv(nds, 256), 256, 0, st>>>(z, z, d, s, c, skip);
+    k_project<T><<<(unsigned)cdiv(nds, kRowWaves), 256, 0, st>>>(z, z, d, s, c, skip);
     FIRAL_LAUNCHED();
   }
   return FIRAL_OK;
@@ -853,7 +888,8 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
   k_fill<T><<<nb, 256, 0, st>>>(xv, n, T(0));
   FIRAL_LAUNCHED();
   if (project) {
-    k_project<T><<<(unsigned)cdiv((int64_t)d * s, 256), 256, 0, st>>>(B, r, d, s, c, skip_none());
+    k_project<T><<<(unsigned)cdiv((int64_t)d * s, kRowWaves), 256, 0, st>>>(B, r, d, s, c,
+                                                                          skip_none());
     FIRAL_LAUNCHED();
   } else {
     FIRAL_HIP(hipMemcpyAsync(r, B, n * sizeof(T), hipMemcpyDeviceToDevice, st));
@@ -879,7 +915,8 @@ static int pcg_t(Ctx* x, const double* omega, double shift, const double* Pinv, 
       k_cg_update<T><<<nb, 256, 0, st>>>(xv, r, p, q, x->alpha, n, s, c, skip);
       FIRAL_LAUNCHED();
       if (project) {   // keep r in the projected space (removes rounding only)
-        k_project<T><<<(unsigned)cdiv((int64_t)d * s, 256), 256, 0, st>>>(r, r, d, s, c, skip);
+        k_project<T><<<(unsigned)cdiv((int64_t)d * s, kRowWaves), 256, 0, st>>>(r, r, d, s, c,
+                                                                              skip);
         FIRAL_LAUNCHED();
       }
       FIRAL_CHECK(coldot_launch(x, r, r, s, part1, skip, st));
