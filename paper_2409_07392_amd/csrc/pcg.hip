@@ -89,15 +89,19 @@ __global__ __launch_bounds__(256) void k_classmean(const T* __restrict__ R, doub
 }
 
 // Z[a,j,k] = sum_b Pinv_k[b][a] (R[b,j,k] - mean[b,j]) for the probes j0 .. j0 + jn - 1
-// (jn <= JT) of one class k per block.  The group's right-hand sides are staged in LDS as
-// [b][j] (read as 16-byte broadcasts); each thread takes rows a = tid, tid + 256, ... and
-// streams column a of Pinv_k (P_k is symmetric), consecutive threads reading consecutive
-// addresses, so a group reads each block once: with up to 16 probes in one group (d <= 512),
-// Pinv is read once per apply.  Each XCD takes a contiguous range of blocks (classes), so the
-// classes that share a cache line of R and Z (class is their innermost index) meet in one L2.
-// Each output is one sequential sum over b (fixed order).
-template <int JT> constexpr size_t papply_lds(int d) { return (size_t)d * JT * sizeof(double); }
-template <typename T, int JT>
+// (jn <= JT) of one class k per block (PROJ: the class means given).  The group's right-hand
+// sides are staged in LDS as [b][j] (read as 16-byte broadcasts; rows padded with zeros to a
+// multiple of 8); each thread takes rows a = tid, tid + 256, ... and streams column a of Pinv_k
+// (P_k is symmetric) in batches of 8 rows b, the next batch loaded while the current one is
+// used, consecutive threads reading consecutive addresses, so a group reads each block once:
+// with up to 16 probes in one group (d <= 512), Pinv is read once per apply.  Each XCD takes a
+// contiguous range of blocks (classes), so the classes that share a cache line of R and Z (class
+// is their innermost index) meet in one L2.  Each output is one sequential sum over b.
+constexpr int kApplyB = 8;   // rows b per batch
+template <int JT> constexpr size_t papply_lds(int d) {
+  return (size_t)cdiv(d, kApplyB) * kApplyB * JT * sizeof(double);
+}
+template <typename T, int JT, bool PROJ>
 __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
                                                 const T* __restrict__ R,
                                                 const double* __restrict__ mean,
@@ -105,7 +109,7 @@ __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
                                                 Skip skip) {
   static_assert(JT % 2 == 0, "right-hand sides read in pairs");
   if (skip_now(skip)) return;
-  extern __shared__ __align__(16) double rs[];   // [d][JT]
+  extern __shared__ __align__(16) double rs[];   // [dp][JT]
   const int64_t nb = gridDim.x, q = nb >> 3, rm = nb & 7;
   const int64_t x = blockIdx.x & 7, lid = x * q + (x < rm ? x : rm) + (blockIdx.x >> 3);
   const int ng = (s + JT - 1) / JT;
@@ -113,15 +117,25 @@ __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
   const int j0 = (int)(lid - (int64_t)k * ng) * JT;
   const int jn = min(JT, s - j0);
   const int64_t sc = (int64_t)s * c;
-#pragma unroll 8
-  for (int e = threadIdx.x; e < d * JT; e += blockDim.x) {
-    const int b = e / JT, jj = e - b * JT;
-    double rv = 0.0;
-    if (jj < jn) {
-      rv = (double)R[b * sc + (int64_t)(j0 + jj) * c + k];
-      if (mean) rv -= mean[(int64_t)b * s + j0 + jj];
+  const int dp = (d + kApplyB - 1) / kApplyB * kApplyB;
+  // staging in batches of 8 elements per thread: the 8 loads (clamped addresses) are issued
+  // together, then the 8 LDS stores
+  for (int e0 = 0; e0 < dp * JT; e0 += 8 * 256) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + (int)threadIdx.x + 256 * u, b = e / JT, jj = e - b * JT;
+      const bool ok = jj < jn && b < d;
+      const int bc = ok ? b : 0, jc = ok ? jj : 0;
+      v[u] = (double)R[bc * sc + (int64_t)(j0 + jc) * c + k];
+      if constexpr (PROJ) v[u] -= mean[(int64_t)bc * s + j0 + jc];
+      v[u] = ok ? v[u] : 0.0;
     }
-    rs[e] = rv;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + (int)threadIdx.x + 256 * u;
+      if (e < dp * JT) rs[e] = v[u];
+    }
   }
   __syncthreads();
   const double* Pk = Pinv + (int64_t)k * d * d;
@@ -129,21 +143,45 @@ __global__ __launch_bounds__(256) void k_papply(const double* __restrict__ Pinv,
     double acc[JT];
 #pragma unroll
     for (int jj = 0; jj < JT; ++jj) acc[jj] = 0.0;
-#pragma unroll 8
-    for (int b = 0; b < d; ++b) {
-      const double p = Pk[(int64_t)b * d + a];
-      const double* r = rs + b * JT;
+    // rows b >= d of a batch read row d - 1 and are weighted by the zero pad of rs
+    auto fetch = [&](int b0, double (&p)[kApplyB]) {
 #pragma unroll
-      for (int jj = 0; jj < JT; jj += 2) {
-        const double2 rv = *reinterpret_cast<const double2*>(r + jj);
-        acc[jj] = fma(p, rv.x, acc[jj]);
-        acc[jj + 1] = fma(p, rv.y, acc[jj + 1]);
+      for (int u = 0; u < kApplyB; ++u) {
+        const int b = b0 + u < d ? b0 + u : d - 1;
+        p[u] = Pk[(int64_t)b * d + a];
       }
+    };
+    double pc[kApplyB], pn[kApplyB];
+    fetch(0, pc);
+    for (int b0 = 0; b0 < dp; b0 += kApplyB) {
+      fetch(b0 + kApplyB < dp ? b0 + kApplyB : b0, pn);
+#pragma unroll
+      for (int u = 0; u < kApplyB; ++u) {
+        const double* r = rs + (b0 + u) * JT;
+#pragma unroll
+        for (int jj = 0; jj < JT; jj += 2) {
+          const double2 rv = *reinterpret_cast<const double2*>(r + jj);
+          acc[jj] = fma(pc[u], rv.x, acc[jj]);
+          acc[jj + 1] = fma(pc[u], rv.y, acc[jj + 1]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kApplyB; ++u) pc[u] = pn[u];
     }
 #pragma unroll
     for (int jj = 0; jj < JT; ++jj)
       if (jj < jn) Z[a * sc + (int64_t)(j0 + jj) * c + k] = (T)acc[jj];
   }
+}
+
+template <typename T, int JT>
+static void papply_launch(const double* Pinv, const T* r, const double* mean, T* z, int d, int s,
+                          int c, Skip skip, hipStream_t st) {
+  const dim3 grid((unsigned)(c * cdiv(s, JT)));
+  if (mean)
+    k_papply<T, JT, true><<<grid, 256, papply_lds<JT>(d), st>>>(Pinv, r, mean, z, d, s, c, skip);
+  else
+    k_papply<T, JT, false><<<grid, 256, papply_lds<JT>(d), st>>>(Pinv, r, mean, z, d, s, c, skip);
 }
 
 // ------------------------------------------------------------ scalars
@@ -719,14 +757,11 @@ static int apply_t(Ctx* x, const double* Pinv, const T* r, T* z, int s, bool pro
   // probes per group: all 16 of a Relax step's block while their LDS stays within 64 KB
   const double* mean = project ? x->mean : nullptr;
   if (d <= 512)
-    k_papply<T, 16><<<(unsigned)(c * cdiv(s, 16)), 256, papply_lds<16>(d), st>>>(Pinv, r, mean, z,
-                                                                             d, s, c, skip);
+    papply_launch<T, 16>(Pinv, r, mean, z, d, s, c, skip, st);
   else if (d <= 2048)
-    k_papply<T, 4><<<(unsigned)(c * cdiv(s, 4)), 256, papply_lds<4>(d), st>>>(Pinv, r, mean, z,
-                                                                            d, s, c, skip);
+    papply_launch<T, 4>(Pinv, r, mean, z, d, s, c, skip, st);
   else if (d <= 4096)
-    k_papply<T, 2><<<(unsigned)(c * cdiv(s, 2)), 256, papply_lds<2>(d), st>>>(Pinv, r, mean, z,
-                                                                            d, s, c, skip);
+    papply_launch<T, 2>(Pinv, r, mean, z, d, s, c, skip, st);
   else
     return FIRAL_ENOTSUP;
   FIRAL_LAUNCHED();
