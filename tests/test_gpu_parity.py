@@ -357,6 +357,30 @@ def test_pcg_f32_fixed_iterations(unfused, monkeypatch):
     assert e <= TOL["f32"], e
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(1500, 10, 600, 5, 6), (2600, 4, 2100, 2, 3)])
+def test_pcg_apply_groups_large_d(prec, shape):
+    # d c > 2340: the separate-kernel CG step, with the preconditioner applied in groups of 4
+    # probes (512 < d <= 2048; s = 6: a full and a partial group) and of 2 (d > 2048; s = 3).
+    # Shift 1 and small pool weights keep the spectrum of A in [1, ~c x 260] (the blocks' kappa is
+    # at most ~260), so the rounding drift after 8 iterations, about kappa u k < 1e-12, stays
+    # under the FP64 bar
+    n, nl, d, c, s = shape
+    p = make_small(n=n, n_lab=nl, d=d, c=c, s=s, seed=40)
+    ctx, X, H = context(p, prec, s)
+    rng = np.random.default_rng(41)
+    om = np.concatenate([rng.uniform(0, 0.02, p.n_pool), np.ones(p.n_lab)])
+    B = rounded(rng.standard_normal((d, s, c)), prec)
+    _, Pinv, _ = ctx.build_precond(dev(om, torch.float64), shift=1.0)
+    Xs, info = ctx.pcg_solve(dev(B, DT[prec]), Pinv, omega=dev(om, torch.float64), shift=1.0,
+                             tol=0.0, max_iter=8, project=True)
+    assert info["cg_iters"][0] == 8
+    L, _ = orc.precond_factor(orc.precond_blocks(X, H, om, 1.0))
+    xr, it, _ = orc.pcg(X, H, om, 1.0, L, B, 0.0, 8, True)
+    assert it == 8
+    assert_close(host(Xs), xr, TOL[prec], f"pcg iterate after 8 iterations {prec} {shape}")
+
+
 @pytest.mark.parametrize("unfused", ["0", "1"])
 def test_pcg_breakdown_and_not_converged(unfused, monkeypatch):
     monkeypatch.setenv("FIRAL_UNFUSED", unfused)
