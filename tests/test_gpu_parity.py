@@ -229,7 +229,7 @@ def test_precond_matches_oracle(prec, shape):
                                    (700, 2, 384, 65)])
 def test_precond_f32_gram_forms(shape, wide, monkeypatch):
     # c > 64, d a multiple of 4: the Gram kernel with its waves along the pairs (default) and the
-    # classic tiling (FIRAL_GRAM_WIDE=0), one class tile with 64 row splits of 32 rows, two and
+    # classic tiling (FIRAL_GRAM_WIDE=0), one class tile with 64 row splits of 33 rows, two and
     # three class tiles with the last partial, a-blocks cut by d; both at the FP32 bar
     monkeypatch.setenv("FIRAL_GRAM_WIDE", wide)
     n, nl, d, c = shape
@@ -524,7 +524,7 @@ def test_hvp_bf16x3(shape, ncb, monkeypatch):
                                    (700, 2, 384, 65), (517, 3, 37, 70), (600, 3, 44, 40)])
 def test_precond_bf16x3_matches_oracle(shape, gram3, monkeypatch):
     # FIRAL_BF3_GRAM=1 with c > 64 and d a multiple of 4: the Gram blocks as bf16x3 products (one
-    # class tile with 64 row splits of 32 rows; two and three class tiles, the last partial;
+    # class tile with 64 row splits of 33 rows; two and three class tiles, the last partial;
     # a-blocks cut by d); d = 37, c = 40 and the default keep the FP32 Gram in the bf16x3
     # context.  Blocks at the bf16x3 bar, factor and inverse within kappa(P_k) times it
     monkeypatch.setenv("FIRAL_BF3_GRAM", gram3)
