@@ -226,11 +226,13 @@ def test_precond_matches_oracle(prec, shape):
 
 @pytest.mark.parametrize("wide", ["0", "1"])
 @pytest.mark.parametrize("shape", [(2000, 50, 20, 70), (3001, 7, 100, 130), (1500, 3, 132, 300),
-                                   (700, 2, 384, 65)])
+                                   (700, 2, 384, 65), (1500, 3, 384, 200)])
 def test_precond_f32_gram_forms(shape, wide, monkeypatch):
     # c > 64, d a multiple of 4: the Gram kernel with its waves along the pairs (default) and the
     # classic tiling (FIRAL_GRAM_WIDE=0), one class tile with 64 row splits of 33 rows, two and
-    # three class tiles with the last partial, a-blocks cut by d; both at the FP32 bar
+    # three class tiles with the last partial, a-blocks cut by d; d = 384, c = 200: 600
+    # workgroups of the wide form, more than the 512 slots of a 256-CU device, so its row splits
+    # are chosen by rounds (5 there); both at the FP32 bar
     monkeypatch.setenv("FIRAL_GRAM_WIDE", wide)
     n, nl, d, c = shape
     p = make_small(n=n, n_lab=nl, d=d, c=c, s=1, seed=33)
@@ -521,7 +523,8 @@ def test_hvp_bf16x3(shape, ncb, monkeypatch):
 
 @pytest.mark.parametrize("gram3", ["0", "1"])
 @pytest.mark.parametrize("shape", [(2000, 50, 20, 70), (3001, 7, 100, 130), (1500, 3, 132, 300),
-                                   (700, 2, 384, 65), (517, 3, 37, 70), (600, 3, 44, 40)])
+                                   (700, 2, 384, 65), (1500, 3, 384, 200), (517, 3, 37, 70),
+                                   (600, 3, 44, 40)])
 def test_precond_bf16x3_matches_oracle(shape, gram3, monkeypatch):
     # FIRAL_BF3_GRAM=1 with c > 64 and d a multiple of 4: the Gram blocks as bf16x3 products (one
     # class tile with 64 row splits of 33 rows; two and three class tiles, the last partial;
