@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_classmean(const T* __restrict__ R, doub
 // contiguous range of blocks (classes), so the classes that share a cache line of R and Z (class
 // is their innermost index) meet in one L2.  Each output is one sequential sum over b.
 constexpr int kApplyB = 8;   // rows b per batch
-template <int JT> constexpr size_t papply_lds(int d) {
+template <int JT> inline size_t papply_lds(int d) {
   return (size_t)cdiv(d, kApplyB) * kApplyB * JT * sizeof(double);
 }
 template <typename T, int JT, bool PROJ>
